@@ -1,0 +1,128 @@
+"""Execute a program strictly in program order on the CPU (test infrastructure).
+
+Buffers are named 1-D numpy arrays.  Kernel operations name one of the task
+kernels below and pass their arguments positionally; the order of the
+arguments and their meaning is the kernel signature documented with each
+entry of ``KERNELS``.  Copies move bytes; host reads snapshot a buffer; host
+writes overwrite one.  Nothing runs concurrently and nothing is reordered.
+"""
+
+import numpy as np
+
+from . import tasks
+
+
+def _f32(a, n=None):
+    v = a.view(np.float32)
+    return v if n is None else v[:n]
+
+
+def _k_vec_square(p, x):
+    n = p["n"]
+    _f32(x, n)[:] = tasks.vec_square(_f32(x, n))
+
+
+def _k_vec_sum_diff(p, x, y, r):
+    n = p["n"]
+    _f32(r)[0] = tasks.vec_sum_diff(_f32(x, n), _f32(y, n))
+
+
+def _k_bs_call(p, s, c):
+    n = p["n"]
+    _f32(c, n)[:] = tasks.bs_call(_f32(s, n), p["K"], p["r"], p["sigma"], p["T"])
+
+
+def _img(a, p):
+    return _f32(a, p["w"] * p["h"]).reshape(p["h"], p["w"])
+
+
+def _k_gauss_blur(p, src, dst):
+    _img(dst, p)[:] = tasks.gauss_blur(_img(src, p), p["ksize"])
+
+
+def _k_sobel(p, src, dst):
+    _img(dst, p)[:] = tasks.sobel(_img(src, p))
+
+
+def _k_minmax(p, src, m):
+    mx, mn = tasks.minmax(_f32(src, p["n"]))
+    _f32(m)[0] = mx
+    _f32(m)[1] = mn
+
+
+def _k_normalise(p, s, m, out):
+    n = p["n"]
+    _f32(out, n)[:] = tasks.normalise(_f32(s, n), _f32(m)[0], _f32(m)[1])
+
+
+def _k_unsharp_combine(p, img, b3, b7, b15, n3, n7, n15, out):
+    n = p["n"]
+    ins = [_f32(a, n) for a in (img, b3, b7, b15, n3, n7, n15)]
+    _f32(out, n)[:] = tasks.unsharp_combine(*ins)
+
+
+def _k_spmv(p, row_ptr, col, val, x, y):
+    nr, nc, nnz = p["nrows"], p["ncols"], p["nnz"]
+    rp = row_ptr.view(np.int32)[: nr + 1]
+    ci = col.view(np.int32)[:nnz]
+    _f32(y, nr)[:] = tasks.spmv(rp, ci, _f32(val, nnz), _f32(x, nc))
+
+
+def _k_sumsq(p, v, s):
+    s.view(np.float64)[0] = tasks.sumsq(_f32(v, p["n"]))
+
+
+def _k_scale_l2(p, t, s, v):
+    n = p["n"]
+    _f32(v, n)[:] = tasks.scale_l2(_f32(t, n), s.view(np.float64)[0])
+
+
+def _k_spin(p, *bufs):
+    """Delay kernel used by the scheduler tests: no effect on data."""
+
+
+# name -> function(params, *buffers) ; signature (argument order, mode):
+KERNELS = {
+    "vec_square": _k_vec_square,            # x:m
+    "vec_sum_diff": _k_vec_sum_diff,        # x:c y:c r:m  (r float32 at [0])
+    "bs_call": _k_bs_call,                  # S:c C:m
+    "gauss_blur": _k_gauss_blur,            # in:c out:m
+    "sobel": _k_sobel,                      # in:c out:m
+    "minmax": _k_minmax,                    # in:c M:m     (M = [max, min])
+    "normalise": _k_normalise,              # S:c M:c N:m
+    "unsharp_combine": _k_unsharp_combine,  # img B3 B7 B15 N3 N7 N15 :c out:m
+    "spmv": _k_spmv,                        # row_ptr col val x :c  y:m
+    "sumsq": _k_sumsq,                      # v:c s:m      (s float64)
+    "scale_l2": _k_scale_l2,                # t:c s:c v:m
+    "spin": _k_spin,                        # any
+}
+
+
+def execute(ops, buffers):
+    """Run ``ops`` in program order over ``buffers`` (name -> 1-D array of any
+    dtype; modified in place).  Returns the list of host-read snapshots as
+    (position, name, bytes-array copy)."""
+    bytes_of = {k: v.view(np.uint8) for k, v in buffers.items()}
+    reads = []
+    for pos, op in enumerate(ops, start=1):
+        kind = op["kind"]
+        if kind == "kernel":
+            fn = KERNELS[op["kernel"]]
+            fn(op.get("params", {}), *[bytes_of[b] for b, _ in op["args"]])
+        elif kind == "copy":
+            nb = op["bytes"]
+            so, do = op.get("src_off", 0), op.get("dst_off", 0)
+            src = bytes_of[op["src"]][so:so + nb].copy()
+            bytes_of[op["dst"]][do:do + nb] = src
+        elif kind == "host_read":
+            reads.append((pos, op["buf"], bytes_of[op["buf"]].copy()))
+        elif kind == "host_write":
+            data = np.asarray(op["data"]).view(np.uint8).ravel()
+            off = op.get("off", 0)
+            bytes_of[op["buf"]][off:off + data.size] = data
+        elif kind in ("sync", "macro"):
+            if kind == "macro":
+                raise ValueError("macro operations carry no math of their own")
+        else:
+            raise ValueError("unknown op kind %r" % (kind,))
+    return reads

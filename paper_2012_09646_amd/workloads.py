@@ -1,0 +1,250 @@
+"""Seeded synthetic inputs and task programs of the benchmark workloads.
+
+This module is the only code shared by the product path and the CPU oracle.
+It draws random numbers and lays out data; it holds none of the scheduler's
+logic and none of the task kernels' arithmetic.
+
+Random numbers come from numpy's Philox4x32-10 counter-based generator
+(Salmon et al., SC'11), keyed by the workload seed.
+
+A *program* is a list of operations in program order (dicts, see
+``oracle.dag`` and ``runner``) plus a buffer table
+``name -> Buf(nbytes, loc, init)`` where ``loc`` is ``'device'`` or
+``'host'`` (pinned host memory) and ``init`` is a numpy array (or None for
+zero-filled buffers).  Kernel argument order follows the kernel signatures
+declared in ``include/dagrt.h``.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+F32 = np.float32
+
+
+def rng(seed):
+    return np.random.Generator(np.random.Philox(key=int(seed)))
+
+
+def uniform_f32(seed, n, lo=0.0, hi=1.0, stream=0):
+    """n float32 values ~ U[lo, hi) from Philox(seed); ``stream`` selects an
+    independent sub-sequence (jumped generator) for multi-array inputs."""
+    g = np.random.Generator(np.random.Philox(key=int(seed)).jumped(int(stream)))
+    u = g.random(int(n), dtype=np.float32)
+    if lo == 0.0 and hi == 1.0:
+        return u
+    return (F32(lo) + F32(hi - lo) * u).astype(F32)
+
+
+# ---------------------------------------------------------------------------
+# Power-law graph: every source has `deg` distinct out-neighbours (no
+# self-loops); targets follow a Zipf(alpha) rank distribution mapped through a
+# seeded random permutation of vertex ids, so in-degrees are power-law.
+# ---------------------------------------------------------------------------
+def zipf_graph(seed, n, deg=20, alpha=1.5):
+    """Return (src, dst) int64 arrays of n*deg edges."""
+    g = rng(seed)
+    ranks = np.arange(1, n + 1, dtype=np.float64)
+    pmf = ranks ** (-alpha)
+    cdf = np.cumsum(pmf)
+    cdf /= cdf[-1]
+    perm = g.permutation(n).astype(np.int64)
+
+    def draw(k):
+        u = g.random(k)
+        r = np.searchsorted(cdf, u, side="right")
+        return perm[np.minimum(r, n - 1)]
+
+    src = np.repeat(np.arange(n, dtype=np.int64), deg).reshape(n, deg)
+    dst = draw(n * deg).reshape(n, deg)
+    todo = np.arange(n)
+    while todo.size:
+        sub = dst[todo]
+        order = np.argsort(sub, axis=1, kind="stable")
+        s = np.take_along_axis(sub, order, axis=1)
+        dup_sorted = np.zeros_like(s, dtype=bool)
+        dup_sorted[:, 1:] = s[:, 1:] == s[:, :-1]
+        bad = np.zeros_like(dup_sorted)
+        np.put_along_axis(bad, order, dup_sorted, axis=1)
+        bad |= sub == src[todo]
+        rows_bad = bad.any(axis=1)
+        if not rows_bad.any():
+            break
+        todo = todo[rows_bad]
+        bad = bad[rows_bad]
+        sub = sub[rows_bad]
+        sub[bad] = draw(int(bad.sum()))
+        dst[todo] = sub
+    return src.ravel(), dst.ravel()
+
+
+def csr(nrows, rows, cols):
+    """CSR (row_ptr int32, col int32, val float32 = 1) of the 0/1 matrix with
+    ones at (rows, cols); column indices sorted within each row."""
+    ncols = int(cols.max()) + 1 if cols.size else 1
+    key = np.sort(rows.astype(np.int64) * ncols + cols.astype(np.int64))
+    r = key // ncols
+    c = (key - r * ncols).astype(np.int32)
+    counts = np.bincount(r, minlength=nrows)
+    row_ptr = np.zeros(nrows + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] > np.iinfo(np.int32).max:
+        raise ValueError("nnz exceeds int32 indexing")
+    return row_ptr.astype(np.int32), c, np.ones(c.size, dtype=F32)
+
+
+# ---------------------------------------------------------------------------
+# Programs
+# ---------------------------------------------------------------------------
+@dataclass
+class Buf:
+    nbytes: int
+    loc: str = "device"
+    init: object = None     # numpy array (any dtype) or None = zeros
+
+
+@dataclass
+class Program:
+    name: str
+    bufs: dict
+    ops: list
+    outputs: list           # buffer names whose final contents are checked
+
+
+def K(kernel, args, **params):
+    return {"kind": "kernel", "kernel": kernel, "params": params,
+            "args": [tuple(a) for a in args]}
+
+
+def COPY(dst, src, nbytes):
+    return {"kind": "copy", "dst": dst, "src": src, "bytes": int(nbytes)}
+
+
+def HR(buf):
+    return {"kind": "host_read", "buf": buf}
+
+
+def vec_program(n=1 << 20, seed=0):
+    """Vector diamond: x <- x^2, y <- y^2 (independent), r = sum(x - y),
+    host reads r."""
+    x = uniform_f32(seed, n, stream=0)
+    y = uniform_f32(seed, n, stream=1)
+    bufs = {"x": Buf(4 * n, init=x), "y": Buf(4 * n, init=y), "r": Buf(4)}
+    ops = [K("vec_square", [("x", "m")], n=n),
+           K("vec_square", [("y", "m")], n=n),
+           K("vec_sum_diff", [("x", "c"), ("y", "c"), ("r", "m")], n=n),
+           HR("r")]
+    return Program("vec", bufs, ops, ["x", "y", "r"])
+
+
+BS_K, BS_R, BS_SIGMA, BS_T = 25.0, 0.08, 0.3, 1.0
+
+
+def bs_program(n=1 << 22, tasks=10, seed=1):
+    """Black-Scholes fan-out: per task, pinned host spot prices are copied to
+    the device, priced, and the call prices copied back; host reads at the
+    end.  No edges between tasks."""
+    bufs, ops = {}, []
+    for i in range(tasks):
+        bufs["S%d" % i] = Buf(4 * n, "host", uniform_f32(seed, n, 10.0, 50.0, stream=i))
+        bufs["C%d" % i] = Buf(4 * n, "host")
+        bufs["dS%d" % i] = Buf(4 * n)
+        bufs["dC%d" % i] = Buf(4 * n)
+    for i in range(tasks):
+        ops.append(COPY("dS%d" % i, "S%d" % i, 4 * n))
+        ops.append(K("bs_call", [("dS%d" % i, "c"), ("dC%d" % i, "m")],
+                     n=n, K=BS_K, r=BS_R, sigma=BS_SIGMA, T=BS_T))
+        ops.append(COPY("C%d" % i, "dC%d" % i, 4 * n))
+    for i in range(tasks):
+        ops.append(HR("C%d" % i))
+    return Program("bs", bufs, ops, ["C%d" % i for i in range(tasks)])
+
+
+IMG_KSIZES = (3, 7, 15)
+
+
+def img_program(side=2048, seed=2, height=None):
+    """Image pipeline: for k in (3, 7, 15): blur_k -> sobel_k -> minmax_k ->
+    normalise_k, then one unsharp-mask combine of all branches; breadth-first
+    submission order; host reads the output."""
+    w = side
+    h = side if height is None else height
+    n = w * h
+    bufs = {"img": Buf(4 * n, init=uniform_f32(seed, n)), "out": Buf(4 * n)}
+    for k in IMG_KSIZES:
+        for p in ("B", "S", "N"):
+            bufs["%s%d" % (p, k)] = Buf(4 * n)
+        bufs["M%d" % k] = Buf(8)
+    ops = []
+    for k in IMG_KSIZES:
+        ops.append(K("gauss_blur", [("img", "c"), ("B%d" % k, "m")], w=w, h=h, ksize=k))
+    for k in IMG_KSIZES:
+        ops.append(K("sobel", [("B%d" % k, "c"), ("S%d" % k, "m")], w=w, h=h))
+    for k in IMG_KSIZES:
+        ops.append(K("minmax", [("S%d" % k, "c"), ("M%d" % k, "m")], n=n))
+    for k in IMG_KSIZES:
+        ops.append(K("normalise", [("S%d" % k, "c"), ("M%d" % k, "c"), ("N%d" % k, "m")], n=n))
+    ops.append(K("unsharp_combine",
+                 [("img", "c"), ("B3", "c"), ("B7", "c"), ("B15", "c"),
+                  ("N3", "c"), ("N7", "c"), ("N15", "c"), ("out", "m")], n=n))
+    ops.append(HR("out"))
+    outs = ["B%d" % k for k in IMG_KSIZES] + ["S%d" % k for k in IMG_KSIZES] + \
+           ["M%d" % k for k in IMG_KSIZES] + ["N%d" % k for k in IMG_KSIZES] + ["out"]
+    return Program("img", bufs, ops, outs)
+
+
+def hits_graph(n=1 << 20, deg=20, seed=3, alpha=1.5):
+    """CSR of A (rows = sources) and A^T (rows = targets) of the power-law
+    graph: dict with a_ptr, a_col, a_val, at_ptr, at_col, at_val."""
+    src, dst = zipf_graph(seed, n, deg, alpha)
+    a_ptr, a_col, a_val = csr(n, src, dst)
+    at_ptr, at_col, at_val = csr(n, dst, src)
+    return dict(a_ptr=a_ptr, a_col=a_col, a_val=a_val,
+                at_ptr=at_ptr, at_col=at_col, at_val=at_val)
+
+
+def hits_iteration_ops(n, nnz):
+    sp = dict(nrows=n, ncols=n, nnz=nnz)
+    return [
+        K("spmv", [("at_ptr", "c"), ("at_col", "c"), ("at_val", "c"), ("h", "c"), ("at", "m")], **sp),
+        K("spmv", [("a_ptr", "c"), ("a_col", "c"), ("a_val", "c"), ("a", "c"), ("ht", "m")], **sp),
+        K("sumsq", [("at", "c"), ("sa", "m")], n=n),
+        K("sumsq", [("ht", "c"), ("sh", "m")], n=n),
+        K("scale_l2", [("at", "c"), ("sa", "c"), ("a", "m")], n=n),
+        K("scale_l2", [("ht", "c"), ("sh", "c"), ("h", "m")], n=n),
+    ]
+
+
+def hits_program(n=1 << 20, deg=20, iters=10, seed=3, graph=None):
+    """HITS: per iteration auth_tmp = A^T hub, hub_tmp = A auth, their squared
+    norms, and the normalised auth / hub (two chains with cross edges)."""
+    gr = hits_graph(n, deg, seed) if graph is None else graph
+    nnz = int(gr["a_ptr"][-1])
+    bufs = {k: Buf(v.nbytes, init=v) for k, v in gr.items()}
+    ones = np.ones(n, dtype=F32)
+    bufs["a"] = Buf(4 * n, init=ones)
+    bufs["h"] = Buf(4 * n, init=ones.copy())
+    bufs["at"] = Buf(4 * n)
+    bufs["ht"] = Buf(4 * n)
+    bufs["sa"] = Buf(8)
+    bufs["sh"] = Buf(8)
+    ops = []
+    for _ in range(iters):
+        ops.extend(hits_iteration_ops(n, nnz))
+    ops.append(HR("a"))
+    ops.append(HR("h"))
+    return Program("hits", bufs, ops, ["a", "h", "at", "ht", "sa", "sh"])
+
+
+def initial_arrays(prog):
+    """Fresh numpy arrays (uint8 views over the initial contents) for a program."""
+    out = {}
+    for name, b in prog.bufs.items():
+        if b.init is None:
+            out[name] = np.zeros(b.nbytes, dtype=np.uint8)
+        else:
+            arr = np.ascontiguousarray(b.init).view(np.uint8).ravel().copy()
+            if arr.size != b.nbytes:
+                raise ValueError("init size mismatch for %s" % name)
+            out[name] = arr
+    return out

@@ -1,0 +1,59 @@
+"""Parser of tests/golden/dag_cases.txt (program tokens -> oracle ops)."""
+
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KIND = {"RAW": 0, "WAR": 1, "WAW": 2}
+
+
+def parse_ops(tokens):
+    ops = []
+    for tok in tokens:
+        if tok == "SYNC":
+            ops.append({"kind": "sync"})
+            continue
+        m = re.fullmatch(r"(K|HR|HW)\((.*)\)", tok)
+        if not m:
+            raise ValueError(tok)
+        head, body = m.groups()
+        if head == "K":
+            args = [tuple(a.split(":")) for a in body.split(",")]
+            ops.append({"kind": "kernel", "kernel": "spin", "params": {}, "args": args})
+        elif head == "HR":
+            ops.append({"kind": "host_read", "buf": body})
+        else:
+            ops.append({"kind": "host_write", "buf": body})
+    return ops
+
+
+def load_cases():
+    cases = []
+    cur = None
+    with open(os.path.join(HERE, "golden", "dag_cases.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            if line.startswith("case "):
+                parts = line.split()
+                cur = {"name": parts[1], "max_streams": int(parts[2].split("=")[1])}
+                cases.append(cur)
+                continue
+            key, val = line.split(":", 1)
+            toks = val.split()
+            if key == "ops":
+                cur["ops"] = parse_ops(toks)
+            elif key == "edges":
+                edges = set()
+                if toks != ["none"]:
+                    for t in toks:
+                        pair, buf, kind = t.split(":")
+                        s, d = pair.split("-")
+                        edges.add((int(s), int(d), buf, KIND[kind]))
+                cur["edges"] = edges
+            elif key == "streams":
+                cur["streams"] = [None if t == "-" else int(t) for t in toks]
+            elif key == "waits":
+                cur["waits"] = [[] if t == "-" else [int(x) for x in t.split(",")] for t in toks]
+    return cases

@@ -1,0 +1,231 @@
+"""Pins of the oracle's task math against closed forms, invariants, library
+routines and brute force (CPU only)."""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, ndimage, sparse
+
+from oracle import run as orun
+from oracle import tasks as T
+from paper_2012_09646_amd import workloads as W
+
+
+def test_vec_square_is_ieee_single_product():
+    x = W.uniform_f32(11, 4096)
+    x = np.concatenate([x, np.float32([0.0, 1.0, 3.0, 1e-20, 1.5e-45, 3.4e38])])
+    with np.errstate(over="ignore", under="ignore"):
+        ref = x * x                      # numpy float32 multiply, IEEE rounding
+    assert np.array_equal(T.vec_square(x).view(np.uint32), ref.view(np.uint32))
+    assert T.vec_square(np.float32([3.0]))[0] == 9.0
+
+
+def test_vec_sum_diff_closed_forms():
+    n = 4096
+    i = np.arange(n, dtype=np.float32)
+    x = i / np.float32(1024.0)           # exact binary fractions
+    y = np.zeros(n, np.float32)
+    assert T.vec_sum_diff(x, y) == np.float32(n * (n - 1) / 2 / 1024.0)
+    # difference order matters: sum(x - y) = -sum(y - x)
+    assert T.vec_sum_diff(y, x) == -np.float32(n * (n - 1) / 2 / 1024.0)
+    assert T.vec_sum_diff(x, x) == 0.0
+    # cancellation: exact, unlike a float32 running sum
+    x2 = np.float32([1e8, 1.0, -1e8, 1.0])
+    assert T.vec_sum_diff(x2, np.zeros(4, np.float32)) == 2.0
+
+
+def _bs_quadrature(S, K, r, sigma, T_):
+    """Discounted expectation of (S_T - K)^+ under the lognormal law, by
+    numerical integration over the standard normal variable."""
+    mu = math.log(S) + (r - 0.5 * sigma * sigma) * T_
+    sd = sigma * math.sqrt(T_)
+    z0 = (math.log(K) - mu) / sd
+
+    def f(z):
+        return (math.exp(mu + sd * z) - K) * math.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)
+
+    val, _ = integrate.quad(f, z0, z0 + 40.0, epsabs=1e-13, epsrel=1e-12, limit=200)
+    return math.exp(-r * T_) * val
+
+
+@pytest.mark.parametrize("S", [10.0, 17.5, 24.0, 25.0, 31.25, 42.0, 50.0])
+def test_bs_call_matches_lognormal_quadrature(S):
+    K, r, sig, T_ = W.BS_K, W.BS_R, W.BS_SIGMA, W.BS_T
+    got = float(T.bs_call(np.float32([S]), K, r, sig, T_)[0])
+    ref = _bs_quadrature(S, K, r, sig, T_)
+    assert abs(got - ref) <= 2e-7 * max(ref, 1e-3) + 1e-9
+
+
+def test_bs_call_other_parameters_quadrature():
+    for (S, K, r, sig, T_) in [(42.0, 40.0, 0.1, 0.2, 0.5), (100.0, 90.0, 0.01, 0.6, 2.0)]:
+        got = float(T.bs_call(np.float32([S]), K, r, sig, T_)[0])
+        assert abs(got - _bs_quadrature(S, K, r, sig, T_)) < 2e-5
+
+
+def test_bs_call_invariants():
+    S = W.uniform_f32(1, 20000, 10.0, 50.0)
+    K, r, sig, T_ = W.BS_K, W.BS_R, W.BS_SIGMA, W.BS_T
+    C = T.bs_call(S, K, r, sig, T_).astype(np.float64)
+    Sd = S.astype(np.float64)
+    lower = np.maximum(Sd - K * math.exp(-r * T_), 0.0)
+    assert np.all(C >= lower * (1 - 1e-6)) and np.all(C <= Sd)
+    order = np.argsort(S)
+    assert np.all(np.diff(C[order]) >= -1e-6)
+    # vanishing volatility -> intrinsic value of the forward
+    c0 = T.bs_call(np.float32([30.0, 20.0]), K, r, 1e-6, T_)
+    assert abs(c0[0] - (30.0 - K * math.exp(-r * T_))) < 1e-5 and c0[1] < 1e-6
+
+
+def test_gauss_weights():
+    for k in (3, 7, 15):
+        w = T.gauss_weights(k)
+        s = k / 6.0
+        assert w.size == k and abs(w.sum() - 1.0) < 1e-15
+        assert np.allclose(w, w[::-1], rtol=0, atol=0)
+        c = (k - 1) // 2
+        assert abs(w[c + 1] / w[c] - math.exp(-1.0 / (2 * s * s))) < 1e-14
+
+
+@pytest.mark.parametrize("k", [3, 7, 15])
+def test_gauss_blur_vs_separable_library(k):
+    img = W.uniform_f32(5, 37 * 29).reshape(29, 37)
+    w = T.gauss_weights(k)
+    ref = ndimage.correlate1d(img.astype(np.float64), w, axis=1, mode="nearest")
+    ref = ndimage.correlate1d(ref, w, axis=0, mode="nearest")
+    got = T.gauss_blur(img, k)
+    assert np.array_equal(got, ref.astype(np.float32)) or \
+        np.max(np.abs(got - ref) / np.abs(ref)) < 1.2e-7
+
+
+def test_gauss_blur_constant_and_impulse():
+    c = np.full((20, 24), 0.375, np.float32)
+    assert np.all(T.gauss_blur(c, 15) == np.float32(0.375))
+    imp = np.zeros((31, 31), np.float32)
+    imp[15, 15] = 1.0
+    w = T.gauss_weights(7)
+    out = T.gauss_blur(imp, 7)
+    assert np.allclose(out[12:19, 12:19], np.outer(w, w).astype(np.float32), rtol=1e-7, atol=0)
+    assert out[:12].max() == 0.0
+
+
+def test_sobel_vs_library_and_ramps():
+    img = W.uniform_f32(6, 33 * 21).reshape(21, 33)
+    a = img.astype(np.float64)
+    gx = ndimage.correlate(a, T.SOBEL_X, mode="nearest")
+    gy = ndimage.correlate(a, T.SOBEL_X.T, mode="nearest")
+    ref = np.sqrt(gx * gx + gy * gy).astype(np.float32)
+    assert np.array_equal(T.sobel(img), ref)
+    yy, xx = np.mgrid[0:16, 0:16].astype(np.float32)
+    assert np.all(T.sobel(xx)[1:-1, 1:-1] == 8.0)
+    assert np.all(T.sobel(yy)[1:-1, 1:-1] == 8.0)
+    assert np.all(T.sobel(3 * xx + 4 * yy)[1:-1, 1:-1] == 40.0)
+    assert np.all(T.sobel(np.ones((5, 5), np.float32)) == 0.0)
+
+
+def test_minmax_normalise():
+    s = W.uniform_f32(7, 1000) * np.float32(3.0)
+    mx, mn = T.minmax(s)
+    assert mx == max(s.tolist()) and mn == min(s.tolist())
+    nrm = T.normalise(s, mx, mn)
+    assert nrm[np.argmax(s)] == 1.0 and nrm[np.argmin(s)] == 0.0
+    assert np.all((nrm >= 0) & (nrm <= 1))
+    assert np.all(T.normalise(np.full(9, 2.0, np.float32), 2.0, 2.0) == 0.0)
+    assert T.normalise(np.float32([1.5]), 2.0, 1.0)[0] == 0.5
+
+
+def test_unsharp_combine_hand_values():
+    one = lambda v: np.float32([v])
+    out = T.unsharp_combine(one(0.5), one(0.25), one(0.5), one(0.75), one(0.3), one(0.6), one(0.9))
+    assert abs(out[0] - 0.7) < 1e-7
+    # constant image -> unchanged, whatever the edge weight
+    c = one(0.4)
+    for e in (0.0, 0.5, 1.0):
+        assert abs(T.unsharp_combine(c, c, c, c, one(e), one(e), one(e))[0] - 0.4) < 1e-7
+    # clamped to [0, 1]
+    assert T.unsharp_combine(one(1.0), one(0.0), one(0.0), one(0.0), one(1), one(1), one(1))[0] == 1.0
+    assert T.unsharp_combine(one(0.0), one(1.0), one(0.0), one(0.0), one(1), one(1), one(1))[0] == 0.0
+
+
+def test_spmv_vs_library_and_dense():
+    src, dst = W.zipf_graph(9, 300, 5)
+    rp, ci, va = W.csr(300, src, dst)
+    va = W.uniform_f32(9, va.size)
+    x = W.uniform_f32(10, 300)
+    A = sparse.csr_matrix((va.astype(np.float64), ci, rp), shape=(300, 300))
+    ref = (A @ x.astype(np.float64)).astype(np.float32)
+    got = T.spmv(rp, ci, va, x)
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)) < 1.2e-7
+    dense = A.toarray() @ x.astype(np.float64)
+    assert np.allclose(got, dense, rtol=2e-7, atol=0)
+    # empty rows give exact zeros
+    assert np.all(got[np.diff(rp) == 0] == 0.0)
+
+
+def test_sumsq_scale_closed_forms():
+    v = np.arange(1, 1001, dtype=np.float32)
+    assert T.sumsq(v) == 1000 * 1001 * 2001 / 6
+    t = np.float32([3.0, 4.0])
+    assert np.array_equal(T.scale_l2(t, T.sumsq(t)), np.float32([0.6, 0.8]))
+
+
+def test_hits_converges_to_singular_vectors():
+    n = 48
+    src, dst = W.zipf_graph(12, n, 6)
+    g = {}
+    g["a_ptr"], g["a_col"], g["a_val"] = W.csr(n, src, dst)
+    g["at_ptr"], g["at_col"], g["at_val"] = W.csr(n, dst, src)
+    A = np.zeros((n, n))
+    A[src, dst] = 1.0
+    U, S, Vt = np.linalg.svd(A)
+    assert S[0] > 1.05 * S[1]
+    auth, hub = T.hits(g["a_ptr"], g["a_col"], g["a_val"], g["at_ptr"], g["at_col"], g["at_val"], 400)
+    v = np.abs(Vt[0])
+    u = np.abs(U[:, 0])
+    assert np.allclose(auth, v, atol=2e-5) and np.allclose(hub, u, atol=2e-5)
+
+
+def test_hits_even_steps_equal_sequential_hits():
+    # both products read the previous iterate, so two steps of this form equal
+    # one step of the textbook sequential update a <- A^T A a (normalised)
+    n = 40
+    src, dst = W.zipf_graph(13, n, 5)
+    A = np.zeros((n, n))
+    A[src, dst] = 1.0
+    g = W.csr(n, src, dst) + W.csr(n, dst, src)
+    auth, _ = T.hits(*g, 6)
+    a = np.ones(n)
+    for _ in range(3):
+        a = A.T @ (A @ a)
+        a /= np.linalg.norm(a)
+    assert np.allclose(auth, a, rtol=1e-6, atol=1e-7)
+
+
+def test_program_executor_vec_and_img():
+    prog = W.vec_program(n=1000)
+    bufs = W.initial_arrays(prog)
+    x0 = bufs["x"].view(np.float32).copy()
+    y0 = bufs["y"].view(np.float32).copy()
+    reads = orun.execute(prog.ops, bufs)
+    assert np.array_equal(bufs["x"].view(np.float32), x0 * x0)
+    r = reads[0][2].view(np.float32)[0]
+    assert r == T.vec_sum_diff(x0 * x0, y0 * y0)
+    prog = W.img_program(side=24)
+    bufs = W.initial_arrays(prog)
+    orun.execute(prog.ops, bufs)
+    img = prog.bufs["img"].init.reshape(24, 24)
+    b7 = T.gauss_blur(img, 7)
+    assert np.array_equal(bufs["B7"].view(np.float32).reshape(24, 24), b7)
+    s7 = T.sobel(b7)
+    m = bufs["M7"].view(np.float32)
+    assert (m[0], m[1]) == T.minmax(s7)
+
+
+def test_program_executor_copies():
+    prog = W.bs_program(n=64, tasks=3)
+    bufs = W.initial_arrays(prog)
+    orun.execute(prog.ops, bufs)
+    for i in range(3):
+        S = prog.bufs["S%d" % i].init
+        ref = T.bs_call(S, W.BS_K, W.BS_R, W.BS_SIGMA, W.BS_T)
+        assert np.array_equal(bufs["C%d" % i].view(np.float32), ref)
