@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Makespan of the benchmark DAGs on one MI355X: the runtime DAG scheduler
+against synchronous serial execution of the same calls, and against the
+contention-free critical-path bound (paper Sec. V-C and V-E).
+
+Workloads (seeded synthetic inputs, sizes of the benchmark configurations):
+  vec   vector diamond, 2^20 fp32, 3 tasks + host read of r, 5 repeats
+  bs    Black-Scholes fan-out: 10 x (H2D 16 MiB -> price 2^22 -> D2H 16 MiB)
+  img   image pipeline 2048x2048: 3 blur/Sobel/minmax/normalise branches + combine
+  hits  HITS on a 2^20-vertex power-law graph (20 out-links each), 10 iterations,
+        eager DAG and one-iteration graph replay
+
+The headline line is the Black-Scholes fan-out.  Prints ONE JSON line on
+stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DAG makespan speedup vs serial + % critical-path bound; serving p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits"])
+    ap.add_argument("--max-streams", type=int, default=8)
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="GPU_MAX_HW_QUEUES for this process (0 = runtime default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the scheduler space-shares a single device; "
+              "multi-GPU runs are not part of this build (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
+    import numpy as np  # noqa: F401
+
+    from paper_2012_09646_amd import dagrt as D
+    from paper_2012_09646_amd import metrics as M
+    from paper_2012_09646_amd import runner
+    from paper_2012_09646_amd import workloads as W
+
+    def kernel_intervals(ctx, b, nops):
+        iv = []
+        for pos in range(1, nops + 1):
+            inf = ctx.info(b.base + pos)
+            if inf.stream < 0 or inf.t_start_ms < 0:
+                continue
+            kind = "C" if inf.kind in (D.DAG_TASK_KERNEL, D.DAG_TASK_REGION) else "T"
+            iv.append((pos, kind, inf.t_start_ms, inf.t_end_ms))
+        return iv
+
+    def measure(name, prog, steps, warmup, restore=(), region=None):
+        """Timed parallel runs, serial runs, traced runs; returns a summary."""
+        res = {"workload": name, "tasks": sum(1 for o in prog.ops if o["kind"] != "host_read")}
+        pris = {}
+
+        def make(policy, trace):
+            ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace)
+            b = runner.Bound(ctx, prog, read_bytes=4)
+            for dst in restore:
+                if dst not in pris:
+                    pris[dst] = prog.bufs[dst].init
+                h0 = ctx.alloc(prog.bufs[dst].nbytes)
+                ctx.host_write(h0, pris[dst])
+                b.h[dst + "@0"] = h0
+            ctx.sync()
+            return ctx, b
+
+        def reset(ctx, b):
+            if restore:
+                for dst in restore:
+                    ctx.copy(b.h[dst], b.h[dst + "@0"], prog.bufs[dst].nbytes)
+                ctx.sync()
+
+        def timed(ctx, b, n, warm):
+            ts = []
+            for i in range(warm + n):
+                reset(ctx, b)
+                t0 = time.perf_counter()
+                b.run()
+                t1 = time.perf_counter()
+                if i >= warm:
+                    ts.append((t1 - t0) * 1e3)
+            return ts
+
+        ctxP, bP = make(D.DAG_PARALLEL_ASYNC, False)
+        log(name, "parallel")
+        par = timed(ctxP, bP, steps, warmup)
+        st = ctxP.stats()
+        res["makespan_ms"] = statistics.median(par)
+        res["makespan_min_ms"] = min(par)
+        res["host_us_per_task"] = st.submit_host_us / max(st.tasks, 1)
+        res["launch_us_per_task"] = st.launch_host_us / max(st.tasks, 1)
+        res["streams"] = st.streams
+        edges = sorted({(s, d) for s, d, _, _ in bP.edges()})
+        res["edges"] = len(edges)
+        res["event_waits_per_run"] = sum(len(w) for w in bP.waits().values())
+        ctxP.close()
+
+        ctxS, bS = make(D.DAG_SERIAL_SYNC, False)
+        log(name, "serial")
+        ser = timed(ctxS, bS, steps, warmup)
+        res["serial_ms"] = statistics.median(ser)
+        res["speedup"] = res["serial_ms"] / res["makespan_ms"]
+        ctxS.close()
+
+        # isolated task times: serial policy with timing events
+        ctxI, bI = make(D.DAG_SERIAL_SYNC, True)
+        log(name, "isolated")
+        iso = {}
+        for i in range(max(3, min(steps, 10))):
+            reset(ctxI, bI)
+            D.dag_trace_reset(ctxI.h)
+            bI.run()
+            for pos, kind, a, bb in kernel_intervals(ctxI, bI, len(prog.ops)):
+                iso.setdefault(pos, []).append(bb - a)
+        ctxI.close()
+        w = {p: statistics.median(v) for p, v in iso.items()}
+        cp, path = M.critical_path(len(prog.ops), edges, w)
+        res["cp_bound_ms"] = cp
+        res["cp_path"] = [prog.ops[p - 1].get("kernel", prog.ops[p - 1]["kind"]) for p in path]
+        res["cp_frac"] = cp / res["makespan_ms"]
+        h2d = sum(w[p] for p in w if prog.ops[p - 1]["kind"] == "copy" and prog.bufs[prog.ops[p - 1]["src"]].loc == "host")
+        d2h = sum(w[p] for p in w if prog.ops[p - 1]["kind"] == "copy" and prog.bufs[prog.ops[p - 1]["dst"]].loc == "host")
+        hbm = sum(M.algorithmic_bytes(o["kernel"], o["params"]) for o in prog.ops if o["kind"] == "kernel")
+        res["resource_bound_ms"] = max(cp, h2d, d2h, hbm / HBM_PEAK_GBS / 1e6)
+        res["resource_frac"] = res["resource_bound_ms"] / res["makespan_ms"]
+        # per-kernel isolated bandwidth
+        per = {}
+        for p, t in w.items():
+            o = prog.ops[p - 1]
+            if o["kind"] != "kernel":
+                continue
+            k = o["kernel"]
+            by = M.algorithmic_bytes(k, o["params"])
+            e = per.setdefault(k, {"launches": 0, "ms": 0.0, "bytes": 0})
+            e["launches"] += 1
+            e["ms"] += t
+            e["bytes"] += by
+        res["kernels_isolated"] = {k: {"avg_us": 1e3 * e["ms"] / e["launches"],
+                                       "gbs": e["bytes"] / e["ms"] / 1e6} for k, e in per.items()}
+
+        # traced parallel runs: overlap and in-DAG kernel durations
+        ctxT, bT = make(D.DAG_PARALLEL_ASYNC, True)
+        log(name, "traced parallel")
+        ktimes = {}
+        tr = []
+        for i in range(max(3, min(steps, 10))):
+            reset(ctxT, bT)
+            D.dag_trace_reset(ctxT.h)
+            t0 = time.perf_counter()
+            bT.run()
+            tr.append((time.perf_counter() - t0) * 1e3)
+            ivs = kernel_intervals(ctxT, bT, len(prog.ops))
+            for pos, kind, a, bb in ivs:
+                if kind == "C" and prog.ops[pos - 1]["kind"] == "kernel":
+                    k = prog.ops[pos - 1]["kernel"]
+                    ktimes.setdefault(k, []).append((bb - a, M.algorithmic_bytes(k, prog.ops[pos - 1]["params"])))
+        res["overlap"] = M.overlap([(k, a, bb) for _, k, a, bb in ivs])
+        res["traced_makespan_ms"] = statistics.median(tr)
+        res["kernels_in_dag"] = {k: {"launches": len(v), "avg_us": 1e3 * sum(t for t, _ in v) / len(v),
+                                     "gbs": sum(by for _, by in v) / sum(t for t, _ in v) / 1e6}
+                                 for k, v in ktimes.items()}
+        ctxT.close()
+
+        if region is not None:
+            res.update(region())
+        return res, ktimes
+
+    workloads = ["bs", "vec", "img", "hits"] if args.workload == "all" else [args.workload]
+    results = {}
+    kt_bs = None
+    for wl in workloads:
+        if wl == "vec":
+            prog = W.vec_program(n=1 << 20, seed=0)
+            results[wl], _ = measure(wl, prog, 5, args.warmup, restore=("x", "y"))
+        elif wl == "bs":
+            prog = W.bs_program(n=1 << 22, tasks=10, seed=1)
+            results[wl], kt_bs = measure(wl, prog, args.steps, args.warmup)
+            bs_prog = prog
+        elif wl == "img":
+            prog = W.img_program(side=2048, seed=2)
+            results[wl], _ = measure(wl, prog, args.steps, args.warmup)
+        elif wl == "hits":
+            log("hits: generating the graph")
+            prog = W.hits_program(n=1 << 20, deg=20, iters=10, seed=3)
+            results[wl], _ = measure(wl, prog, args.steps, args.warmup, restore=("a", "h"))
+
+    head = results.get("bs") or results[workloads[0]]
+    line = {
+        "metric": METRIC,
+        "value": round(head["speedup"], 4),
+        "unit": "x (serial-sync makespan / DAG makespan)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["makespan_ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "bs_fanout_10x2^22" if "bs" in results else head["workload"],
+                   "max_streams": args.max_streams,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)},
+        "makespan_ms": round(head["makespan_ms"], 4),
+        "serial_ms": round(head["serial_ms"], 4),
+        "cp_bound_ms": round(head["cp_bound_ms"], 4),
+        "cp_frac": round(head["cp_frac"], 4),
+        "resource_bound_ms": round(head["resource_bound_ms"], 4),
+        "resource_frac": round(head["resource_frac"], 4),
+        "overlap": head["overlap"],
+    }
+    if kt_bs:
+        v = kt_bs["bs_call"]
+        avg = sum(t for t, _ in v) / len(v)
+        by = v[0][1]
+        ach = by / avg / 1e6
+        line["roofline"] = {"kernel": "bs_call", "bound": "hbm", "achieved": round(ach, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                            "traffic": None, "avg_us": round(avg * 1e3, 2), "bytes_per_launch": by}
+    line["workloads"] = results
+    if "bs" in results and not args.no_cpu_baseline:
+        from oracle import run as orun
+        log("cpu baseline (oracle, program order)")
+        times = []
+        t_start = time.perf_counter()
+        while True:
+            arrays = W.initial_arrays(bs_prog)
+            t0 = time.perf_counter()
+            orun.execute(bs_prog.ops, arrays)
+            times.append((time.perf_counter() - t0) * 1e3)
+            if time.perf_counter() - t_start > 10.0 or len(times) >= 5:
+                break
+        line["cpu_baseline"] = {"value": round(statistics.median(times), 2), "unit": "ms per DAG run",
+                                "cores": 1, "kind": "oracle",
+                                "sample": "%d full runs of the 10-task Black-Scholes DAG (numpy/scipy, one thread)" % len(times)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,335 @@
+/*
+ * dagrt.h -- C ABI of a runtime DAG scheduler for GPU kernel and copy calls.
+ *
+ * The scheduler receives GPU computations one call at a time, infers the data
+ * dependencies between them from the buffers each call reads and modifies,
+ * and executes them asynchronously: independent calls run concurrently on
+ * separate HIP streams (space-sharing), events are waited on only where a
+ * real read-after-write, write-after-read or write-after-write dependency
+ * crosses streams, and host<->device copies overlap with kernels.  A host
+ * read of a buffer is the point where the host waits.
+ *
+ * Paper: A. Parravicini, A. Delamare, M. Arnaboldi, M. D. Santambrogio,
+ * "DAG-based Scheduling with Resource Sharing for Multi-task Applications in
+ * a Polyglot GPU Runtime" (arXiv:2012.09646).  Each declaration cites the
+ * section that defines the operation:
+ *   Sec. IV-A  computation DAG, dependency sets, read-only arguments, host
+ *              accesses as computational elements
+ *   Sec. IV-B  execution context, one event per computation, activity until
+ *              the host needs a result
+ *   Sec. IV-C  serial/parallel x synchronous/asynchronous policies, stream
+ *              manager (FIFO reuse, first child on the parent's stream)
+ *   Sec. IV-D  argument annotations (read-only vs modifiable)
+ *   Sec. V-D   comparison with graph-based APIs (graph capture here)
+ *   Sec. V-E   contention-free (critical-path) bound
+ *
+ * Conventions
+ *   - Every call returns a dag_status; DAG_OK (0) on success, a negative code
+ *     otherwise.  dag_last_error(ctx) returns a message for the last failure.
+ *   - Argument errors (DAG_E_INVAL, DAG_E_ALIAS, DAG_E_RANGE, ...) leave the
+ *     context usable.  A failing HIP call poisons the context: that call
+ *     returns DAG_E_HIP and every later call except dag_destroy,
+ *     dag_last_error and the introspection calls returns DAG_E_POISONED.
+ *   - A context is used by one host thread at a time (not thread-safe).
+ *   - Pointers are plain host or device addresses; sizes are in bytes unless
+ *     stated.  Nothing in this header refers to a framework type.
+ *   - Task ids are 1-based positions in program order (every submit, host
+ *     access and sync call takes the next id) and are never reused.
+ */
+#ifndef DAGRT_H
+#define DAGRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dag_ctx_s* dag_ctx;
+typedef uint32_t dag_buf;  /* buffer handle; 0 is never a valid handle */
+typedef uint64_t dag_task; /* task id; 0 = none */
+typedef int32_t dag_status;
+
+#define DAG_OK 0
+#define DAG_E_INVAL (-1)       /* bad argument (handle, size, mode, params) */
+#define DAG_E_ALIAS (-2)       /* registration overlaps a registered buffer */
+#define DAG_E_NOMEM (-3)       /* allocation failed */
+#define DAG_E_HIP (-4)         /* a HIP call failed; the context is poisoned */
+#define DAG_E_POISONED (-5)    /* an earlier HIP failure poisoned the context */
+#define DAG_E_BUSY (-6)        /* call not allowed in the current state */
+#define DAG_E_UNSUPPORTED (-7) /* operation not available in this mode */
+#define DAG_E_NOTFOUND (-8)    /* unknown region key / kernel id */
+#define DAG_E_RANGE (-9)       /* size beyond a fixed library limit */
+
+/* Argument access modes (Sec. IV-D): a read-only ("input"/"const") argument
+ * or a modifiable one.  An argument without annotation must be passed as
+ * DAG_MUTABLE; MUTABLE means read-write.  The same buffer passed twice in one
+ * call counts as MUTABLE if either use is. */
+#define DAG_CONST 0u
+#define DAG_MUTABLE 1u
+
+/* Buffer locations: device memory, or page-locked host memory that the copy
+ * engines can read and write asynchronously. */
+#define DAG_DEVICE 0u
+#define DAG_PINNED_HOST 1u
+
+/* Scheduling policies (Sec. IV-C).  SERIAL_SYNC: every call runs on one
+ * stream and the host waits for it before returning (no dependency
+ * computation).  PARALLEL_ASYNC: the DAG scheduler. */
+#define DAG_SERIAL_SYNC 0u
+#define DAG_PARALLEL_ASYNC 1u
+
+/* Dependency kinds on an edge. */
+#define DAG_EDGE_RAW 0u
+#define DAG_EDGE_WAR 1u
+#define DAG_EDGE_WAW 2u
+
+/* Task kinds. */
+#define DAG_TASK_KERNEL 0u
+#define DAG_TASK_COPY 1u
+#define DAG_TASK_HOST_READ 2u
+#define DAG_TASK_HOST_WRITE 3u
+#define DAG_TASK_SYNC 4u
+#define DAG_TASK_REGION 5u  /* one replay of a captured region */
+#define DAG_TASK_RELEASE 6u /* buffer release (waits like a host write) */
+
+/* Upper bound of max_streams. */
+#define DAG_MAX_STREAMS 64u
+
+typedef struct {
+  uint32_t policy;        /* DAG_SERIAL_SYNC or DAG_PARALLEL_ASYNC */
+  uint32_t max_streams;   /* stream pool bound, 1..DAG_MAX_STREAMS (0 = 8) */
+  uint32_t trace;         /* 1 = record timing events around every task */
+  uint32_t dry_run;       /* 1 = schedule only: infer edges, streams and
+                             waits, make no HIP call and touch no memory */
+  int32_t device;         /* HIP device ordinal */
+  uint32_t graph_mode;    /* region replays: 0 = hipGraph, 1 = recorded
+                             multi-stream replay without dependency work */
+  uint64_t scratch_bytes; /* per-stream device scratch for reductions and
+                             SpMV carries (0 = 4 MiB) */
+} dag_config;
+
+/* One argument of a call: a buffer and its access mode. */
+typedef struct {
+  dag_buf buf;
+  uint32_t mode; /* DAG_CONST or DAG_MUTABLE */
+} dag_arg;
+
+/* One dependency edge, labelled with the buffer that causes it (Sec. IV-A;
+ * two calls linked through several buffers give one record per buffer). */
+typedef struct {
+  dag_task src;
+  dag_task dst;
+  dag_buf buf;
+  uint32_t kind; /* DAG_EDGE_* */
+} dag_edge;
+
+typedef struct {
+  uint32_t kind;      /* DAG_TASK_* */
+  int32_t stream;     /* pool stream index, -1 for host accesses / sync */
+  uint32_t vertex;    /* 1 if the task is a DAG vertex (host accesses
+                         without a conflict are not) */
+  uint32_t active;    /* 1 until a host access retires it (Sec. IV-B) */
+  uint32_t nparents;  /* distinct tasks it depends on */
+  uint32_t nwaits;    /* event waits placed for it */
+  uint32_t kernel_id; /* kernel id for kernel tasks, else 0 */
+  uint32_t reserved;
+  double t_start_ms;  /* trace mode: start/end on the device, in ms after the
+                         last dag_trace_reset (or context creation); -1 when
+                         not traced */
+  double t_end_ms;
+} dag_task_info;
+
+typedef struct {
+  uint64_t tasks;        /* ids handed out */
+  uint64_t vertices;     /* tasks that are DAG vertices */
+  uint64_t edges;        /* edge records (per buffer) */
+  uint64_t waits;        /* hipStreamWaitEvent calls placed */
+  uint64_t host_waits;   /* host blocking waits */
+  uint32_t streams;      /* streams created so far */
+  uint32_t active;       /* currently active tasks */
+  double submit_host_us; /* host time spent inside submit calls, excluding
+                            the HIP launch/copy calls themselves */
+  double launch_host_us; /* host time spent in HIP launch/copy/event calls */
+} dag_stats;
+
+/* ---- context ------------------------------------------------------------
+ * The execution context of Sec. IV-B: it tracks every call, owns the DAG,
+ * the stream pool and the events.  cfg may be NULL (defaults).  On success
+ * *out owns HIP streams and device scratch (none in dry-run mode). */
+dag_status dag_create(const dag_config* cfg, dag_ctx* out);
+/* Waits for all outstanding work, then frees everything the context owns
+ * (library-allocated buffers included).  ctx may be NULL. */
+dag_status dag_destroy(dag_ctx ctx);
+/* Message of the last failing call on ctx (static string if ctx is NULL). */
+const char* dag_last_error(dag_ctx ctx);
+const char* dag_status_string(dag_status st);
+
+/* ---- buffers ------------------------------------------------------------
+ * Buffers are the unit of dependency tracking (Sec. IV-A relies on managed
+ * objects to exclude aliasing; here a registration that overlaps a
+ * registered buffer is rejected with DAG_E_ALIAS).  Any sub-range access
+ * counts as an access to the whole buffer. */
+/* Register caller-owned memory [ptr, ptr+bytes) (bytes > 0).  The memory
+ * must stay valid until dag_buffer_release returns. */
+dag_status dag_buffer_register(dag_ctx ctx, void* ptr, size_t bytes, uint32_t loc,
+                               dag_buf* out);
+/* Allocate and register library-owned memory (hipMalloc / hipHostMalloc,
+ * 256-byte aligned, not initialised). */
+dag_status dag_buffer_alloc(dag_ctx ctx, size_t bytes, uint32_t loc, dag_buf* out);
+/* Wait for every active task that uses the buffer (as a host write would),
+ * then drop the handle; library-owned memory is freed. */
+dag_status dag_buffer_release(dag_ctx ctx, dag_buf buf);
+dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
+
+/* ---- kernels --------------------------------------------------------------
+ * Built-in task kernels (hand-written for gfx950).  Arguments are passed in
+ * the order listed; "c" arguments may be DAG_CONST, "m" arguments must be
+ * DAG_MUTABLE (DAG_E_INVAL otherwise).  All kernel arguments must be
+ * DAG_DEVICE buffers large enough for the sizes in params (checked on the
+ * host before launch).  fp32 data, fp64 arithmetic, one rounding to fp32. */
+#define DAG_K_VEC_SQUARE 1u      /* x:m                 x_i <- x_i*x_i (fp32) */
+#define DAG_K_VEC_SUM_DIFF 2u    /* x:c y:c r:m         r[0] = sum(x_i - y_i) */
+#define DAG_K_BS_CALL 3u         /* S:c C:m             Black-Scholes call */
+#define DAG_K_GAUSS_BLUR 4u      /* in:c out:m          Gaussian blur, clamp */
+#define DAG_K_SOBEL 5u           /* in:c out:m          Sobel magnitude */
+#define DAG_K_MINMAX 6u          /* in:c M:m            M = [max, min] */
+#define DAG_K_NORMALISE 7u       /* S:c M:c N:m         (S-min)/(max-min) */
+#define DAG_K_UNSHARP_COMBINE 8u /* img B3 B7 B15 N3 N7 N15:c out:m */
+#define DAG_K_SPMV 9u            /* row_ptr col val x:c y:m   y = A x (CSR) */
+#define DAG_K_SUMSQ 11u          /* v:c s:m             s (fp64) = sum v_i^2 */
+#define DAG_K_SCALE_L2 12u       /* t:c s:c v:m         v_i = t_i / sqrt(s) */
+#define DAG_K_SPIN 13u           /* (any args)          busy-wait, no data */
+#define DAG_K_COPY_F32 14u       /* src:c dst:m         dst_i = src_i */
+#define DAG_K_USER_BASE 1000u    /* ids of dag_kernel_register */
+
+/* Parameter blocks (passed by pointer + size to dag_submit_kernel). */
+typedef struct { uint64_t n; } dag_p_n; /* VEC_SQUARE, VEC_SUM_DIFF, MINMAX,
+                                           NORMALISE, UNSHARP_COMBINE, SUMSQ,
+                                           SCALE_L2, COPY_F32: element count */
+typedef struct {
+  uint64_t n;      /* options priced */
+  double strike;   /* K */
+  double rate;     /* r, continuously compounded */
+  double vol;      /* sigma */
+  double years;    /* T */
+} dag_p_bs;
+typedef struct {
+  uint32_t w, h;  /* image width, height (row-major, w contiguous) */
+  uint32_t ksize; /* GAUSS_BLUR: odd kernel size 1..31, sigma = ksize/6 */
+  uint32_t reserved;
+} dag_p_img;
+typedef struct {
+  uint32_t nrows, ncols; /* y has nrows, x has ncols entries */
+  uint64_t nnz;          /* row_ptr: nrows+1 int32; col: nnz int32; val:
+                            nnz fp32.  row_ptr must be non-decreasing from 0
+                            to nnz and col < ncols (kernels clamp indices
+                            so that malformed input cannot fault) */
+} dag_p_csr;
+typedef struct { uint64_t ns; } dag_p_spin; /* delay in ns (<= 1 s) */
+
+/* Launch configuration of a built-in kernel (used by the autotuner). */
+typedef struct {
+  uint32_t block;    /* threads per workgroup (multiple of 64, <= 1024) */
+  uint32_t grid_cap; /* max workgroups for grid-stride kernels; 0 = none */
+  uint32_t variant;  /* kernel-specific (SpMV items per thread, ...) */
+  uint32_t reserved;
+} dag_launch;
+dag_status dag_kernel_get_launch(dag_ctx ctx, uint32_t kernel_id, dag_launch* out);
+/* Validated against the kernel's supported set (DAG_E_INVAL otherwise). */
+dag_status dag_kernel_set_launch(dag_ctx ctx, uint32_t kernel_id, const dag_launch* cfg);
+
+/* User kernels: fn enqueues its work on the given hipStream_t (passed as
+ * void*) using the device pointers of its arguments, in order; it returns
+ * 0 on success.  The scheduler treats the call like any other. */
+typedef int (*dag_launch_fn)(void* stream, void* const* ptrs, uint32_t nptrs,
+                             const void* params, void* user);
+dag_status dag_kernel_register(dag_ctx ctx, const char* name, dag_launch_fn fn,
+                               void* user, uint32_t* kernel_id);
+
+/* ---- calls ------------------------------------------------------------------
+ * Submit one computational element (Sec. IV-A): the scheduler adds it to the
+ * DAG with an edge from every active task it conflicts with (RAW, WAR, WAW
+ * through the read-only rule of Sec. IV-A), picks a stream (Sec. IV-C),
+ * makes that stream wait on the events of parents on other streams that are
+ * not already ordered before it, enqueues the work and returns without
+ * waiting.  params is copied; nargs <= 16. */
+dag_status dag_submit_kernel(dag_ctx ctx, uint32_t kernel_id, const void* params,
+                             size_t params_bytes, const dag_arg* args, uint32_t nargs,
+                             dag_task* out);
+/* Asynchronous copy of bytes from src+src_off to dst+dst_off: src is read
+ * (DAG_CONST), dst modified (DAG_MUTABLE).  Direction follows the buffer
+ * locations; pinned host memory makes host<->device copies asynchronous. */
+dag_status dag_submit_copy(dag_ctx ctx, dag_buf dst, size_t dst_off, dag_buf src,
+                           size_t src_off, size_t bytes, dag_task* out);
+/* Host read (Sec. IV-A): if an active task writes buf, the host waits for
+ * it, and that task and all its ancestors stop being active (Sec. IV-B);
+ * otherwise the read happens immediately and is not a DAG vertex.  Then
+ * copies bytes at off into host_dst (NULL = wait only).  out (optional)
+ * receives the task id. */
+dag_status dag_host_read(dag_ctx ctx, dag_buf buf, size_t off, void* host_dst,
+                         size_t bytes, dag_task* out);
+/* Host write: waits for the active tasks that read or write buf (WAR/WAW),
+ * retires them with their ancestors, then copies host_src into the buffer. */
+dag_status dag_host_write(dag_ctx ctx, dag_buf buf, size_t off, const void* host_src,
+                          size_t bytes, dag_task* out);
+/* Wait for every submitted task and retire all of them. */
+dag_status dag_sync(dag_ctx ctx);
+
+/* Batched submission: ops are processed in order exactly as the equivalent
+ * sequence of single calls (same ids, edges, streams and waits).  Stops at
+ * the first failing op; *done (optional) = number of ops completed. */
+typedef struct {
+  uint32_t kind;         /* DAG_TASK_KERNEL/COPY/HOST_READ/HOST_WRITE/SYNC */
+  uint32_t kernel_id;    /* KERNEL */
+  const void* params;    /* KERNEL */
+  size_t params_bytes;   /* KERNEL */
+  const dag_arg* args;   /* KERNEL */
+  uint32_t nargs;        /* KERNEL */
+  dag_buf dst;           /* COPY destination; HOST_READ/WRITE buffer */
+  dag_buf src;           /* COPY source */
+  uint32_t reserved;
+  size_t dst_off;        /* COPY / HOST_READ / HOST_WRITE offset in dst */
+  size_t src_off;        /* COPY */
+  size_t bytes;          /* COPY / HOST_READ / HOST_WRITE */
+  void* host;            /* HOST_READ destination / HOST_WRITE source */
+} dag_op;
+dag_status dag_submit_batch(dag_ctx ctx, const dag_op* ops, uint32_t nops,
+                            dag_task* ids, uint32_t* done);
+
+/* ---- recurring DAG shapes (graph capture; Sec. V-D compares the scheduler
+ * with graphs built once and replayed) -----------------------------------------
+ * dag_region_begin(key) ... kernel/copy submissions ... dag_region_end():
+ * the calls run eagerly as usual and are also recorded; region_end builds a
+ * replayable graph of them (intra-region dependencies only) under key.
+ * Host accesses and sync are not allowed inside a region (DAG_E_BUSY).
+ * dag_region_launch(key) replays it as ONE task whose access set is the
+ * union of the region's accesses (MUTABLE wins), with its dependencies on
+ * earlier tasks inferred like any call.  Re-recording an existing key
+ * replaces it. */
+dag_status dag_region_begin(dag_ctx ctx, uint64_t key);
+dag_status dag_region_end(dag_ctx ctx);
+dag_status dag_region_launch(dag_ctx ctx, uint64_t key, dag_task* out);
+/* Number of recorded tasks and distinct streams of a region. */
+dag_status dag_region_info(dag_ctx ctx, uint64_t key, uint32_t* ntasks, uint32_t* nstreams);
+dag_status dag_region_drop(dag_ctx ctx, uint64_t key);
+
+/* ---- introspection ------------------------------------------------------- */
+/* Edge records in order of (dst, src, buf); *n = total count even when it
+ * exceeds cap (then only cap records are written). */
+dag_status dag_edges(dag_ctx ctx, dag_edge* out, size_t cap, size_t* n);
+/* Parents a task waited on through events (ascending ids). */
+dag_status dag_task_waits(dag_ctx ctx, dag_task t, dag_task* out, uint32_t cap, uint32_t* n);
+/* Trace times need the task to have completed; this call waits for it. */
+dag_status dag_task_get_info(dag_ctx ctx, dag_task t, dag_task_info* out);
+dag_status dag_get_stats(dag_ctx ctx, dag_stats* out);
+/* Wait for all work, then restart the trace clock (trace mode only). */
+dag_status dag_trace_reset(dag_ctx ctx);
+/* HIP stream of pool stream index i (as void*), e.g. to time on it. */
+dag_status dag_stream_handle(dag_ctx ctx, uint32_t i, void** stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DAGRT_H */

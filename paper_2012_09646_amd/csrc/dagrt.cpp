@@ -1,0 +1,1033 @@
+// C-ABI of the runtime DAG scheduler: execution context, buffer registry,
+// HIP executor (streams, events, launches, copies, host synchronisation),
+// recurring-region graphs and introspection.  The dependency and stream
+// decisions come from tracker.hpp; the task kernels from kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dagrt.h"
+#include "kernels.hpp"
+#include "tracker.hpp"
+
+namespace dagrt {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double us_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::micro>(Clock::now() - t0).count();
+}
+
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  uint32_t loc = 0;
+  bool owned = false;
+  bool live = false;
+};
+
+struct UserKernel {
+  std::string name;
+  dag_launch_fn fn;
+  void* user;
+};
+
+// One recorded call of a region.
+struct RegionTask {
+  uint32_t kind = 0;  // TK_KERNEL or TK_COPY
+  uint32_t kernel_id = 0;
+  std::vector<char> params;
+  std::vector<void*> ptrs;
+  LaunchCfg cfg{};
+  void* cdst = nullptr;
+  const void* csrc = nullptr;
+  size_t cbytes = 0;
+  hipMemcpyKind ckind = hipMemcpyDefault;
+  uint64_t id = 0;         // task id of the eager run
+  int32_t rstream = 0;     // region-local stream
+  std::vector<uint32_t> rwaits;  // region-local task indices waited on
+  bool waited_on = false;
+};
+
+struct Region {
+  std::vector<RegionTask> tasks;
+  std::vector<Access> accs;  // union of accesses, MUTABLE wins
+  uint32_t nstreams = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* scratch = nullptr;  // nstreams * scratch_bytes (graph mode)
+  std::vector<hipEvent_t> evs;  // replay-mode events (per task)
+};
+
+constexpr uint32_t kMaxArgs = 16;
+
+}  // namespace
+}  // namespace dagrt
+
+using namespace dagrt;
+
+struct dag_ctx_s {
+  dag_config cfg{};
+  bool serial = false;
+  bool dry = false;
+  bool poisoned = false;
+  std::string err;
+  Tracker tr;
+  std::vector<Buffer> bufs;               // slot = handle - 1
+  std::map<uintptr_t, uint32_t> ranges;   // live buffers: base -> slot
+  uintptr_t fake_next = uintptr_t(1) << 44;
+  std::vector<hipStream_t> streams;
+  std::vector<void*> scratch;             // per pool stream
+  hipStream_t io = nullptr;
+  std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion
+  std::vector<hipEvent_t> ev0;            // per task, start (trace mode)
+  std::vector<hipEvent_t> free_ev;
+  hipEvent_t trace_ref = nullptr;
+  std::vector<uint64_t> tmp_wait, tmp_retired;
+  std::vector<Access> tmp_acc;
+  std::vector<UserKernel> user_kernels;
+  LaunchCfg launch_cfg[15]{};
+  // regions
+  std::unordered_map<uint64_t, std::unique_ptr<Region>> regions;
+  bool recording = false;
+  uint64_t rec_key = 0;
+  std::unique_ptr<Region> rec;
+  std::vector<hipStream_t> aux;           // capture / replay streams
+  std::vector<void*> aux_scratch;
+  // stats
+  uint64_t n_waits = 0, n_host_waits = 0;
+  double submit_us = 0.0, launch_us = 0.0;
+
+  explicit dag_ctx_s(uint32_t ms) : tr(ms) {}
+};
+
+namespace {
+
+dag_status fail(dag_ctx c, dag_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+dag_status hip_fail(dag_ctx c, hipError_t e, const char* what) {
+  c->poisoned = true;
+  return fail(c, DAG_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, call)                                  \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
+  } while (0)
+
+#define CHECK_CTX(c)                                                        \
+  do {                                                                      \
+    if (!(c)) return DAG_E_INVAL;                                           \
+    if ((c)->poisoned) return fail((c), DAG_E_POISONED, "context poisoned: %s", (c)->err.c_str()); \
+  } while (0)
+
+Buffer* get_buf(dag_ctx c, dag_buf h) {
+  if (h == 0 || h > c->bufs.size()) return nullptr;
+  Buffer* b = &c->bufs[h - 1];
+  return b->live ? b : nullptr;
+}
+
+dag_status get_event(dag_ctx c, bool timing, hipEvent_t* out) {
+  if (!timing && !c->free_ev.empty()) {
+    *out = c->free_ev.back();
+    c->free_ev.pop_back();
+    return DAG_OK;
+  }
+  HIP_TRY(c, hipEventCreateWithFlags(out, timing ? hipEventDefault : hipEventDisableTiming));
+  return DAG_OK;
+}
+
+void recycle_retired(dag_ctx c) {
+  if (c->cfg.trace || c->dry) return;
+  for (uint64_t t : c->tmp_retired) {
+    if (t < c->ev.size() && c->ev[t]) {
+      c->free_ev.push_back(c->ev[t]);
+      c->ev[t] = nullptr;
+    }
+  }
+}
+
+dag_status ensure_stream(dag_ctx c, int32_t s) {
+  if (c->dry) return DAG_OK;
+  while (static_cast<int32_t>(c->streams.size()) <= s) {
+    hipStream_t st;
+    HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    void* scr = nullptr;
+    HIP_TRY(c, hipMalloc(&scr, c->cfg.scratch_bytes));
+    HIP_TRY(c, hipMemsetAsync(scr, 0, c->cfg.scratch_bytes, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    c->streams.push_back(st);
+    c->scratch.push_back(scr);
+  }
+  return DAG_OK;
+}
+
+void note_event_slot(dag_ctx c, uint64_t id) {
+  if (c->ev.size() <= id) {
+    c->ev.resize(id + 1, nullptr);
+    if (c->cfg.trace) c->ev0.resize(id + 1, nullptr);
+  }
+}
+
+// Enqueue the waits of task id on its stream and (trace) its start event.
+dag_status begin_task(dag_ctx c, uint64_t id, int32_t s) {
+  if (c->dry) return DAG_OK;
+  const TaskRec& t = c->tr.task(id);
+  const uint64_t* w = c->tr.waits(id);
+  for (uint32_t i = 0; i < t.wait_n; ++i) {
+    HIP_TRY(c, hipStreamWaitEvent(c->streams[s], c->ev[w[i]], 0));
+  }
+  c->n_waits += t.wait_n;
+  note_event_slot(c, id);
+  if (c->cfg.trace) {
+    hipEvent_t e0;
+    dag_status st = get_event(c, true, &e0);
+    if (st) return st;
+    c->ev0[id] = e0;
+    HIP_TRY(c, hipEventRecord(e0, c->streams[s]));
+  }
+  return DAG_OK;
+}
+
+dag_status end_task(dag_ctx c, uint64_t id, int32_t s) {
+  if (c->dry) return DAG_OK;
+  hipEvent_t e;
+  dag_status st = get_event(c, c->cfg.trace != 0, &e);
+  if (st) return st;
+  c->ev[id] = e;
+  HIP_TRY(c, hipEventRecord(e, c->streams[s]));
+  if (c->serial) HIP_TRY(c, hipStreamSynchronize(c->streams[s]));
+  return DAG_OK;
+}
+
+// Dedupe (slot, acc) pairs: MUTABLE wins.
+void add_access(std::vector<Access>* v, uint32_t slot, uint8_t acc) {
+  for (Access& a : *v) {
+    if (a.buf == slot) {
+      a.acc = std::max(a.acc, acc);
+      return;
+    }
+  }
+  v->push_back(Access{slot, acc});
+}
+
+dag_status host_wait(dag_ctx c) {
+  if (c->dry) return DAG_OK;
+  for (uint64_t w : c->tmp_wait) {
+    HIP_TRY(c, hipEventSynchronize(c->ev[w]));
+    ++c->n_host_waits;
+  }
+  return DAG_OK;
+}
+
+// -------------------------------------------------------------------------
+// submissions
+// -------------------------------------------------------------------------
+dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pbytes,
+                         const dag_arg* args, uint32_t nargs, dag_task* out) {
+  const auto t0 = Clock::now();
+  const KernelDesc* kd = nullptr;
+  const UserKernel* uk = nullptr;
+  if (kid >= DAG_K_USER_BASE) {
+    const uint32_t u = kid - DAG_K_USER_BASE;
+    if (u >= c->user_kernels.size()) return fail(c, DAG_E_NOTFOUND, "unknown kernel id %u", kid);
+    uk = &c->user_kernels[u];
+  } else {
+    kd = builtin_kernel(kid);
+    if (!kd) return fail(c, DAG_E_NOTFOUND, "unknown kernel id %u", kid);
+    if (pbytes != kd->params_bytes || !params)
+      return fail(c, DAG_E_INVAL, "%s: params must be %zu bytes", kd->name, kd->params_bytes);
+    if (kd->nargs && nargs != kd->nargs)
+      return fail(c, DAG_E_INVAL, "%s takes %u arguments, got %u", kd->name, kd->nargs, nargs);
+  }
+  if (nargs > kMaxArgs) return fail(c, DAG_E_INVAL, "at most %u arguments", kMaxArgs);
+  if (nargs && !args) return fail(c, DAG_E_INVAL, "args is NULL");
+  void* ptrs[kMaxArgs];
+  size_t sizes[kMaxArgs];
+  c->tmp_acc.clear();
+  for (uint32_t i = 0; i < nargs; ++i) {
+    Buffer* b = get_buf(c, args[i].buf);
+    if (!b) return fail(c, DAG_E_INVAL, "argument %u: invalid buffer handle %u", i, args[i].buf);
+    if (args[i].mode > DAG_MUTABLE) return fail(c, DAG_E_INVAL, "argument %u: bad mode", i);
+    if (kd && ((kd->write_mask >> i) & 1u) && args[i].mode != DAG_MUTABLE)
+      return fail(c, DAG_E_INVAL, "%s: argument %u is written and must be DAG_MUTABLE", kd->name, i);
+    if (kd && b->loc != DAG_DEVICE)
+      return fail(c, DAG_E_INVAL, "%s: argument %u must be a device buffer", kd->name, i);
+    ptrs[i] = b->ptr;
+    sizes[i] = b->bytes;
+    add_access(&c->tmp_acc, args[i].buf - 1, args[i].mode == DAG_MUTABLE ? ACC_W : ACC_R);
+  }
+  LaunchCfg cfg{};
+  if (kd) {
+    cfg = c->launch_cfg[kid];
+    if (const char* msg = kd->validate(params, sizes, nargs, cfg, c->cfg.scratch_bytes))
+      return fail(c, DAG_E_INVAL, "%s: %s", kd->name, msg);
+  }
+  int32_t s;
+  bool created;
+  const uint64_t id = c->tr.add_gpu(TK_KERNEL, kid, c->tmp_acc.data(),
+                                    static_cast<uint32_t>(c->tmp_acc.size()), c->serial, &s, &created);
+  if (out) *out = id;
+  dag_status st = ensure_stream(c, s);
+  if (st) return st;
+  c->submit_us += us_since(t0);
+  const auto t1 = Clock::now();
+  st = begin_task(c, id, s);
+  if (st) return st;
+  if (!c->dry) {
+    if (kd) {
+      hipError_t e = kd->launch(c->streams[s], ptrs, params, cfg, c->scratch[s], c->cfg.scratch_bytes);
+      if (e != hipSuccess) return hip_fail(c, e, kd->name);
+    } else {
+      int rc = uk->fn(c->streams[s], ptrs, nargs, params, uk->user);
+      if (rc != 0) {
+        c->poisoned = true;
+        return fail(c, DAG_E_HIP, "user kernel %s returned %d", uk->name.c_str(), rc);
+      }
+    }
+  }
+  st = end_task(c, id, s);
+  c->launch_us += us_since(t1);
+  if (st) return st;
+  if (c->recording) {
+    if (!kd) return fail(c, DAG_E_UNSUPPORTED, "user kernels cannot be recorded in a region");
+    RegionTask rt;
+    rt.kind = TK_KERNEL;
+    rt.kernel_id = kid;
+    rt.params.assign(static_cast<const char*>(params), static_cast<const char*>(params) + pbytes);
+    rt.ptrs.assign(ptrs, ptrs + nargs);
+    rt.cfg = cfg;
+    rt.id = id;
+    c->rec->tasks.push_back(std::move(rt));
+    for (const Access& a : c->tmp_acc) add_access(&c->rec->accs, a.buf, a.acc);
+  }
+  return DAG_OK;
+}
+
+hipMemcpyKind copy_kind(uint32_t dst_loc, uint32_t src_loc) {
+  if (src_loc == DAG_PINNED_HOST)
+    return dst_loc == DAG_PINNED_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
+  return dst_loc == DAG_PINNED_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+}
+
+dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t soff, size_t bytes,
+                       dag_task* out) {
+  const auto t0 = Clock::now();
+  Buffer* bd = get_buf(c, dst);
+  Buffer* bs = get_buf(c, src);
+  if (!bd || !bs) return fail(c, DAG_E_INVAL, "invalid buffer handle");
+  if (bytes == 0) return fail(c, DAG_E_INVAL, "copy of 0 bytes");
+  if (doff > bd->bytes || bytes > bd->bytes - doff) return fail(c, DAG_E_INVAL, "copy overruns dst");
+  if (soff > bs->bytes || bytes > bs->bytes - soff) return fail(c, DAG_E_INVAL, "copy overruns src");
+  if (dst == src) {
+    const size_t lo = std::max(doff, soff), hi = std::min(doff, soff) + bytes;
+    if (lo < hi) return fail(c, DAG_E_INVAL, "overlapping copy within one buffer");
+  }
+  c->tmp_acc.clear();
+  add_access(&c->tmp_acc, src - 1, ACC_R);
+  add_access(&c->tmp_acc, dst - 1, ACC_W);
+  int32_t s;
+  bool created;
+  const uint64_t id = c->tr.add_gpu(TK_COPY, 0, c->tmp_acc.data(),
+                                    static_cast<uint32_t>(c->tmp_acc.size()), c->serial, &s, &created);
+  if (out) *out = id;
+  dag_status st = ensure_stream(c, s);
+  if (st) return st;
+  c->submit_us += us_since(t0);
+  const auto t1 = Clock::now();
+  st = begin_task(c, id, s);
+  if (st) return st;
+  void* dp = static_cast<char*>(bd->ptr) + doff;
+  const void* sp = static_cast<const char*>(bs->ptr) + soff;
+  const hipMemcpyKind kind = copy_kind(bd->loc, bs->loc);
+  if (!c->dry) HIP_TRY(c, hipMemcpyAsync(dp, sp, bytes, kind, c->streams[s]));
+  st = end_task(c, id, s);
+  c->launch_us += us_since(t1);
+  if (st) return st;
+  if (c->recording) {
+    RegionTask rt;
+    rt.kind = TK_COPY;
+    rt.cdst = dp;
+    rt.csrc = sp;
+    rt.cbytes = bytes;
+    rt.ckind = kind;
+    rt.id = id;
+    c->rec->tasks.push_back(std::move(rt));
+    for (const Access& a : c->tmp_acc) add_access(&c->rec->accs, a.buf, a.acc);
+  }
+  return DAG_OK;
+}
+
+dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hdst, const void* hsrc,
+                       size_t bytes, dag_task* out) {
+  if (c->recording) return fail(c, DAG_E_BUSY, "host access inside a region");
+  Buffer* b = get_buf(c, h);
+  if (!b) return fail(c, DAG_E_INVAL, "invalid buffer handle %u", h);
+  if (off > b->bytes || bytes > b->bytes - off) return fail(c, DAG_E_INVAL, "access overruns the buffer");
+  if (bytes && !hdst && !hsrc && kind == TK_HOST_WRITE) return fail(c, DAG_E_INVAL, "host_src is NULL");
+  const uint64_t id = c->tr.add_host(kind, h - 1, kind == TK_HOST_READ ? ACC_R : ACC_W, c->serial,
+                                     &c->tmp_wait);
+  if (out) *out = id;
+  dag_status st = host_wait(c);
+  if (st) return st;
+  c->tmp_retired.clear();
+  c->tr.retire(id, &c->tmp_retired);
+  recycle_retired(c);
+  if (c->dry || bytes == 0) return DAG_OK;
+  char* p = static_cast<char*>(b->ptr) + off;
+  if (kind == TK_HOST_READ && hdst) {
+    if (b->loc == DAG_PINNED_HOST) {
+      if (hdst != p) std::memcpy(hdst, p, bytes);
+    } else {
+      HIP_TRY(c, hipMemcpyAsync(hdst, p, bytes, hipMemcpyDeviceToHost, c->io));
+      HIP_TRY(c, hipStreamSynchronize(c->io));
+    }
+  } else if (kind == TK_HOST_WRITE) {
+    if (b->loc == DAG_PINNED_HOST) {
+      if (hsrc != p) std::memcpy(p, hsrc, bytes);
+    } else {
+      HIP_TRY(c, hipMemcpyAsync(p, hsrc, bytes, hipMemcpyHostToDevice, c->io));
+      HIP_TRY(c, hipStreamSynchronize(c->io));
+    }
+  }
+  return DAG_OK;
+}
+
+dag_status do_sync(dag_ctx c) {
+  if (c->recording) return fail(c, DAG_E_BUSY, "sync inside a region");
+  c->tr.add_sync();
+  if (!c->dry) {
+    for (hipStream_t s : c->streams) HIP_TRY(c, hipStreamSynchronize(s));
+    for (hipStream_t s : c->aux) HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  c->tmp_retired.clear();
+  c->tr.retire_all(&c->tmp_retired);
+  recycle_retired(c);
+  return DAG_OK;
+}
+
+// -------------------------------------------------------------------------
+// regions
+// -------------------------------------------------------------------------
+dag_status ensure_aux(dag_ctx c, uint32_t n) {
+  while (c->aux.size() < n) {
+    hipStream_t st;
+    HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    void* scr = nullptr;
+    HIP_TRY(c, hipMalloc(&scr, c->cfg.scratch_bytes));
+    HIP_TRY(c, hipMemsetAsync(scr, 0, c->cfg.scratch_bytes, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    c->aux.push_back(st);
+    c->aux_scratch.push_back(scr);
+  }
+  return DAG_OK;
+}
+
+// Region-local streams and waits from the eager run's intra-region parents.
+void plan_region(dag_ctx c, Region* r) {
+  std::unordered_map<uint64_t, uint32_t> index;  // task id -> region index
+  std::unordered_map<int32_t, int32_t> smap;     // pool stream -> region stream
+  for (uint32_t k = 0; k < r->tasks.size(); ++k) index[r->tasks[k].id] = k;
+  std::vector<std::vector<uint32_t>> vc;   // region-stream vector clocks
+  std::vector<std::vector<uint32_t>> snap(r->tasks.size());
+  std::vector<uint32_t> pos(r->tasks.size()), npos;
+  for (uint32_t k = 0; k < r->tasks.size(); ++k) {
+    RegionTask& t = r->tasks[k];
+    const TaskRec& tr = c->tr.task(t.id);
+    auto it = smap.find(tr.stream);
+    if (it == smap.end()) it = smap.emplace(tr.stream, static_cast<int32_t>(smap.size())).first;
+    t.rstream = it->second;
+    const uint32_t ns = static_cast<uint32_t>(smap.size());
+    vc.resize(ns);
+    npos.resize(ns, 0);
+    for (auto& v : vc) v.resize(ns, 0);
+    std::vector<uint32_t> cand;  // newest intra-region parent per other region stream
+    const uint64_t* par = c->tr.parents(t.id);
+    for (uint32_t i = 0; i < tr.par_n; ++i) {
+      auto pi = index.find(par[i]);
+      if (pi == index.end()) continue;
+      const uint32_t p = pi->second;
+      if (r->tasks[p].rstream == t.rstream) continue;
+      bool rep = false;
+      for (uint32_t& q : cand)
+        if (r->tasks[q].rstream == r->tasks[p].rstream) {
+          q = std::max(q, p);
+          rep = true;
+        }
+      if (!rep) cand.push_back(p);
+    }
+    std::sort(cand.begin(), cand.end(), [](uint32_t a, uint32_t b) { return a > b; });
+    std::vector<uint32_t>& v = vc[t.rstream];
+    for (uint32_t p : cand) {
+      if (v[r->tasks[p].rstream] >= pos[p]) continue;
+      t.rwaits.push_back(p);
+      r->tasks[p].waited_on = true;
+      for (uint32_t k2 = 0; k2 < snap[p].size(); ++k2) v[k2] = std::max(v[k2], snap[p][k2]);
+    }
+    pos[k] = ++npos[t.rstream];
+    v[t.rstream] = pos[k];
+    snap[k] = v;
+  }
+  r->nstreams = static_cast<uint32_t>(smap.size());
+}
+
+hipError_t launch_region_task(dag_ctx c, const RegionTask& t, hipStream_t s, void* scratch) {
+  if (t.kind == TK_COPY) return hipMemcpyAsync(t.cdst, t.csrc, t.cbytes, t.ckind, s);
+  const KernelDesc* kd = builtin_kernel(t.kernel_id);
+  return kd->launch(s, t.ptrs.data(), t.params.data(), t.cfg, scratch, c->cfg.scratch_bytes);
+}
+
+dag_status build_graph(dag_ctx c, Region* r) {
+  dag_status st = ensure_aux(c, r->nstreams);
+  if (st) return st;
+  HIP_TRY(c, hipMalloc(&r->scratch, c->cfg.scratch_bytes * r->nstreams));
+  HIP_TRY(c, hipMemset(r->scratch, 0, c->cfg.scratch_bytes * r->nstreams));
+  HIP_TRY(c, hipDeviceSynchronize());
+  std::vector<hipEvent_t> evs(r->tasks.size(), nullptr);
+  std::vector<hipEvent_t> forks(r->nstreams, nullptr);
+  for (uint32_t k = 0; k < r->tasks.size(); ++k)
+    if (r->tasks[k].waited_on) HIP_TRY(c, hipEventCreateWithFlags(&evs[k], hipEventDisableTiming));
+  for (uint32_t i = 0; i < r->nstreams; ++i) HIP_TRY(c, hipEventCreateWithFlags(&forks[i], hipEventDisableTiming));
+  hipStream_t s0 = c->aux[0];
+  HIP_TRY(c, hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+  HIP_TRY(c, hipEventRecord(forks[0], s0));
+  for (uint32_t i = 1; i < r->nstreams; ++i) HIP_TRY(c, hipStreamWaitEvent(c->aux[i], forks[0], 0));
+  for (uint32_t k = 0; k < r->tasks.size(); ++k) {
+    const RegionTask& t = r->tasks[k];
+    hipStream_t s = c->aux[t.rstream];
+    for (uint32_t w : t.rwaits) HIP_TRY(c, hipStreamWaitEvent(s, evs[w], 0));
+    hipError_t e = launch_region_task(c, t, s, static_cast<char*>(r->scratch) + c->cfg.scratch_bytes * t.rstream);
+    if (e != hipSuccess) return hip_fail(c, e, "region capture launch");
+    if (t.waited_on) HIP_TRY(c, hipEventRecord(evs[k], s));
+  }
+  for (uint32_t i = 1; i < r->nstreams; ++i) {
+    HIP_TRY(c, hipEventRecord(forks[i], c->aux[i]));
+    HIP_TRY(c, hipStreamWaitEvent(s0, forks[i], 0));
+  }
+  HIP_TRY(c, hipStreamEndCapture(s0, &r->graph));
+  HIP_TRY(c, hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0));
+  for (hipEvent_t e : evs)
+    if (e) HIP_TRY(c, hipEventDestroy(e));
+  for (hipEvent_t e : forks) HIP_TRY(c, hipEventDestroy(e));
+  return DAG_OK;
+}
+
+void free_region(Region* r) {
+  if (r->exec) (void)hipGraphExecDestroy(r->exec);
+  if (r->graph) (void)hipGraphDestroy(r->graph);
+  if (r->scratch) (void)hipFree(r->scratch);
+  for (hipEvent_t e : r->evs)
+    if (e) (void)hipEventDestroy(e);
+  r->exec = nullptr;
+  r->graph = nullptr;
+  r->scratch = nullptr;
+  r->evs.clear();
+}
+
+// Replay without a graph: fork from the macro task's stream onto auxiliary
+// streams, run the recorded calls with their intra-region waits, join back.
+dag_status replay_region(dag_ctx c, Region* r, hipStream_t s, int32_t pool_stream) {
+  dag_status st = ensure_aux(c, r->nstreams);
+  if (st) return st;
+  if (r->evs.empty()) {
+    r->evs.assign(r->tasks.size() + 2 * r->nstreams, nullptr);
+    for (auto& e : r->evs) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  hipEvent_t* fork = &r->evs[r->tasks.size()];
+  hipEvent_t* join = fork + r->nstreams;
+  HIP_TRY(c, hipEventRecord(fork[0], s));
+  for (uint32_t i = 1; i < r->nstreams; ++i) HIP_TRY(c, hipStreamWaitEvent(c->aux[i], fork[0], 0));
+  for (uint32_t k = 0; k < r->tasks.size(); ++k) {
+    const RegionTask& t = r->tasks[k];
+    hipStream_t ts = t.rstream == 0 ? s : c->aux[t.rstream];
+    void* scr = t.rstream == 0 ? c->scratch[pool_stream] : c->aux_scratch[t.rstream];
+    for (uint32_t w : t.rwaits) HIP_TRY(c, hipStreamWaitEvent(ts, r->evs[w], 0));
+    hipError_t e = launch_region_task(c, t, ts, scr);
+    if (e != hipSuccess) return hip_fail(c, e, "region replay launch");
+    if (t.waited_on) HIP_TRY(c, hipEventRecord(r->evs[k], ts));
+  }
+  for (uint32_t i = 1; i < r->nstreams; ++i) {
+    HIP_TRY(c, hipEventRecord(join[i], c->aux[i]));
+    HIP_TRY(c, hipStreamWaitEvent(s, join[i], 0));
+  }
+  return DAG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* dag_status_string(dag_status st) {
+  switch (st) {
+    case DAG_OK: return "ok";
+    case DAG_E_INVAL: return "invalid argument";
+    case DAG_E_ALIAS: return "buffer overlaps a registered buffer";
+    case DAG_E_NOMEM: return "out of memory";
+    case DAG_E_HIP: return "HIP error";
+    case DAG_E_POISONED: return "context poisoned by an earlier HIP error";
+    case DAG_E_BUSY: return "not allowed in the current state";
+    case DAG_E_UNSUPPORTED: return "unsupported";
+    case DAG_E_NOTFOUND: return "not found";
+    case DAG_E_RANGE: return "size beyond a library limit";
+    default: return "unknown status";
+  }
+}
+
+const char* dag_last_error(dag_ctx ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
+  if (!out) return DAG_E_INVAL;
+  *out = nullptr;
+  dag_config c{};
+  c.policy = DAG_PARALLEL_ASYNC;
+  c.max_streams = 8;
+  if (cfg) c = *cfg;
+  if (c.max_streams == 0) c.max_streams = 8;
+  if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1)
+    return DAG_E_INVAL;
+  if (c.scratch_bytes == 0) c.scratch_bytes = 4u << 20;
+  if (c.scratch_bytes < 4096 || c.scratch_bytes > (1ull << 32)) return DAG_E_INVAL;
+  c.scratch_bytes = (c.scratch_bytes + 255) & ~uint64_t(255);
+  dag_ctx x = new (std::nothrow) dag_ctx_s(c.policy == DAG_SERIAL_SYNC ? 1 : c.max_streams);
+  if (!x) return DAG_E_NOMEM;
+  x->cfg = c;
+  x->serial = c.policy == DAG_SERIAL_SYNC;
+  x->dry = c.dry_run != 0;
+  for (uint32_t k = 0; k < 15; ++k) {
+    const KernelDesc* kd = builtin_kernel(k);
+    if (kd) x->launch_cfg[k] = kd->def;
+  }
+  if (!x->dry) {
+    hipError_t e = hipSetDevice(c.device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&x->io, hipStreamNonBlocking);
+    int khz = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device);
+    if (e == hipSuccess) set_wall_clock_khz(static_cast<uint64_t>(khz));
+    if (e == hipSuccess && c.trace) {
+      e = hipEventCreate(&x->trace_ref);
+      if (e == hipSuccess) e = hipEventRecord(x->trace_ref, x->io);
+    }
+    if (e != hipSuccess) {
+      fprintf(stderr, "dag_create: %s\n", hipGetErrorString(e));
+      if (x->io) (void)hipStreamDestroy(x->io);
+      delete x;
+      return DAG_E_HIP;
+    }
+  }
+  *out = x;
+  return DAG_OK;
+}
+
+dag_status dag_destroy(dag_ctx c) {
+  if (!c) return DAG_OK;
+  if (!c->dry) {
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->regions) free_region(kv.second.get());
+    if (c->rec) free_region(c->rec.get());
+    for (hipEvent_t e : c->ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev0)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
+    if (c->trace_ref) (void)hipEventDestroy(c->trace_ref);
+    for (Buffer& b : c->bufs) {
+      if (b.live && b.owned) {
+        if (b.loc == DAG_PINNED_HOST)
+          (void)hipHostFree(b.ptr);
+        else
+          (void)hipFree(b.ptr);
+      }
+    }
+    for (size_t i = 0; i < c->streams.size(); ++i) {
+      (void)hipFree(c->scratch[i]);
+      (void)hipStreamDestroy(c->streams[i]);
+    }
+    for (size_t i = 0; i < c->aux.size(); ++i) {
+      (void)hipFree(c->aux_scratch[i]);
+      (void)hipStreamDestroy(c->aux[i]);
+    }
+    if (c->io) (void)hipStreamDestroy(c->io);
+  }
+  delete c;
+  return DAG_OK;
+}
+
+static dag_status register_range(dag_ctx c, void* ptr, size_t bytes, uint32_t loc, bool owned, dag_buf* out) {
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(ptr);
+  if (lo + bytes < lo) return fail(c, DAG_E_INVAL, "range wraps around");
+  auto it = c->ranges.lower_bound(lo);
+  if (it != c->ranges.end() && it->first < lo + bytes)
+    return fail(c, DAG_E_ALIAS, "range overlaps buffer %u", it->second + 1);
+  if (it != c->ranges.begin()) {
+    auto pv = std::prev(it);
+    const Buffer& b = c->bufs[pv->second];
+    if (pv->first + b.bytes > lo) return fail(c, DAG_E_ALIAS, "range overlaps buffer %u", pv->second + 1);
+  }
+  if (c->bufs.size() >= 0xfffffffeu) return fail(c, DAG_E_RANGE, "too many buffers");
+  Buffer b;
+  b.ptr = ptr;
+  b.bytes = bytes;
+  b.loc = loc;
+  b.owned = owned;
+  b.live = true;
+  c->bufs.push_back(b);
+  const uint32_t slot = static_cast<uint32_t>(c->bufs.size() - 1);
+  c->ranges[lo] = slot;
+  c->tr.ensure_buffer(slot);
+  *out = slot + 1;
+  return DAG_OK;
+}
+
+dag_status dag_buffer_register(dag_ctx c, void* ptr, size_t bytes, uint32_t loc, dag_buf* out) {
+  CHECK_CTX(c);
+  if (!out || !ptr || bytes == 0 || loc > DAG_PINNED_HOST) return fail(c, DAG_E_INVAL, "bad registration");
+  return register_range(c, ptr, bytes, loc, false, out);
+}
+
+dag_status dag_buffer_alloc(dag_ctx c, size_t bytes, uint32_t loc, dag_buf* out) {
+  CHECK_CTX(c);
+  if (!out || bytes == 0 || loc > DAG_PINNED_HOST) return fail(c, DAG_E_INVAL, "bad allocation request");
+  void* p = nullptr;
+  if (c->dry) {
+    p = reinterpret_cast<void*>(c->fake_next);
+    c->fake_next += (bytes + 0xffff) & ~uintptr_t(0xffff);
+  } else {
+    hipError_t e = loc == DAG_PINNED_HOST ? hipHostMalloc(&p, bytes, hipHostMallocDefault) : hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+      (void)hipGetLastError();
+      return fail(c, DAG_E_NOMEM, "allocation of %zu bytes failed", bytes);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "allocation");
+  }
+  dag_status st = register_range(c, p, bytes, loc, true, out);
+  if (st != DAG_OK && !c->dry) {
+    if (loc == DAG_PINNED_HOST)
+      (void)hipHostFree(p);
+    else
+      (void)hipFree(p);
+  }
+  return st;
+}
+
+dag_status dag_buffer_release(dag_ctx c, dag_buf h) {
+  CHECK_CTX(c);
+  if (c->recording) return fail(c, DAG_E_BUSY, "release inside a region");
+  Buffer* b = get_buf(c, h);
+  if (!b) return fail(c, DAG_E_INVAL, "invalid buffer handle %u", h);
+  c->tr.add_host(TK_RELEASE, h - 1, ACC_W, c->serial, &c->tmp_wait);
+  dag_status st = host_wait(c);
+  if (st) return st;
+  c->tmp_retired.clear();
+  c->tr.retire(c->tr.last_id(), &c->tmp_retired);
+  recycle_retired(c);
+  if (b->owned && !c->dry) {
+    hipError_t e = b->loc == DAG_PINNED_HOST ? hipHostFree(b->ptr) : hipFree(b->ptr);
+    if (e != hipSuccess) return hip_fail(c, e, "free");
+  }
+  c->ranges.erase(reinterpret_cast<uintptr_t>(b->ptr));
+  b->live = false;
+  c->tr.reset_buffer(h - 1);
+  return DAG_OK;
+}
+
+dag_status dag_buffer_ptr(dag_ctx c, dag_buf h, void** ptr, size_t* bytes) {
+  if (!c) return DAG_E_INVAL;
+  Buffer* b = get_buf(c, h);
+  if (!b) return fail(c, DAG_E_INVAL, "invalid buffer handle %u", h);
+  if (ptr) *ptr = b->ptr;
+  if (bytes) *bytes = b->bytes;
+  return DAG_OK;
+}
+
+dag_status dag_kernel_get_launch(dag_ctx c, uint32_t kid, dag_launch* out) {
+  if (!c || !out) return DAG_E_INVAL;
+  if (!builtin_kernel(kid)) return fail(c, DAG_E_NOTFOUND, "unknown kernel id %u", kid);
+  const LaunchCfg& l = c->launch_cfg[kid];
+  *out = dag_launch{l.block, l.grid_cap, l.variant, 0};
+  return DAG_OK;
+}
+
+dag_status dag_kernel_set_launch(dag_ctx c, uint32_t kid, const dag_launch* cfg) {
+  CHECK_CTX(c);
+  const KernelDesc* kd = builtin_kernel(kid);
+  if (!kd) return fail(c, DAG_E_NOTFOUND, "unknown kernel id %u", kid);
+  if (!cfg) return fail(c, DAG_E_INVAL, "cfg is NULL");
+  LaunchCfg l{cfg->block, cfg->grid_cap, cfg->variant};
+  if (const char* msg = kd->check_cfg(l)) return fail(c, DAG_E_INVAL, "%s: %s", kd->name, msg);
+  c->launch_cfg[kid] = l;
+  return DAG_OK;
+}
+
+dag_status dag_kernel_register(dag_ctx c, const char* name, dag_launch_fn fn, void* user, uint32_t* kid) {
+  CHECK_CTX(c);
+  if (!fn || !kid) return fail(c, DAG_E_INVAL, "fn and kernel_id are required");
+  c->user_kernels.push_back(UserKernel{name ? name : "user", fn, user});
+  *kid = DAG_K_USER_BASE + static_cast<uint32_t>(c->user_kernels.size() - 1);
+  return DAG_OK;
+}
+
+dag_status dag_submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pbytes,
+                             const dag_arg* args, uint32_t nargs, dag_task* out) {
+  CHECK_CTX(c);
+  return submit_kernel(c, kid, params, pbytes, args, nargs, out);
+}
+
+dag_status dag_submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t soff, size_t bytes,
+                           dag_task* out) {
+  CHECK_CTX(c);
+  return submit_copy(c, dst, doff, src, soff, bytes, out);
+}
+
+dag_status dag_host_read(dag_ctx c, dag_buf h, size_t off, void* dst, size_t bytes, dag_task* out) {
+  CHECK_CTX(c);
+  if (bytes && !dst) return fail(c, DAG_E_INVAL, "host_dst is NULL");
+  return host_access(c, TK_HOST_READ, h, off, dst, nullptr, bytes, out);
+}
+
+dag_status dag_host_write(dag_ctx c, dag_buf h, size_t off, const void* src, size_t bytes, dag_task* out) {
+  CHECK_CTX(c);
+  if (bytes && !src) return fail(c, DAG_E_INVAL, "host_src is NULL");
+  return host_access(c, TK_HOST_WRITE, h, off, nullptr, src, bytes, out);
+}
+
+dag_status dag_sync(dag_ctx c) {
+  CHECK_CTX(c);
+  return do_sync(c);
+}
+
+dag_status dag_submit_batch(dag_ctx c, const dag_op* ops, uint32_t nops, dag_task* ids, uint32_t* done) {
+  if (done) *done = 0;
+  CHECK_CTX(c);
+  if (nops && !ops) return fail(c, DAG_E_INVAL, "ops is NULL");
+  for (uint32_t i = 0; i < nops; ++i) {
+    const dag_op& o = ops[i];
+    dag_task id = 0;
+    dag_status st;
+    switch (o.kind) {
+      case DAG_TASK_KERNEL:
+        st = submit_kernel(c, o.kernel_id, o.params, o.params_bytes, o.args, o.nargs, &id);
+        break;
+      case DAG_TASK_COPY:
+        st = submit_copy(c, o.dst, o.dst_off, o.src, o.src_off, o.bytes, &id);
+        break;
+      case DAG_TASK_HOST_READ:
+        if (o.bytes && !o.host) return fail(c, DAG_E_INVAL, "op %u: host is NULL", i);
+        st = host_access(c, TK_HOST_READ, o.dst, o.dst_off, o.host, nullptr, o.bytes, &id);
+        break;
+      case DAG_TASK_HOST_WRITE:
+        if (o.bytes && !o.host) return fail(c, DAG_E_INVAL, "op %u: host is NULL", i);
+        st = host_access(c, TK_HOST_WRITE, o.dst, o.dst_off, nullptr, o.host, o.bytes, &id);
+        break;
+      case DAG_TASK_SYNC:
+        st = do_sync(c);
+        id = c->tr.last_id();
+        break;
+      default:
+        return fail(c, DAG_E_INVAL, "op %u: bad kind %u", i, o.kind);
+    }
+    if (st) return st;
+    if (ids) ids[i] = id;
+    if (done) *done = i + 1;
+  }
+  return DAG_OK;
+}
+
+dag_status dag_region_begin(dag_ctx c, uint64_t key) {
+  CHECK_CTX(c);
+  if (c->recording) return fail(c, DAG_E_BUSY, "a region is already being recorded");
+  if (c->dry && c->cfg.graph_mode == 0) {
+    // schedule-only contexts record the region but never build a graph
+  }
+  c->recording = true;
+  c->rec_key = key;
+  c->rec.reset(new Region());
+  return DAG_OK;
+}
+
+dag_status dag_region_end(dag_ctx c) {
+  CHECK_CTX(c);
+  if (!c->recording) return fail(c, DAG_E_BUSY, "no region is being recorded");
+  c->recording = false;
+  std::unique_ptr<Region> r = std::move(c->rec);
+  if (r->tasks.empty()) return fail(c, DAG_E_INVAL, "empty region");
+  plan_region(c, r.get());
+  if (!c->dry && c->cfg.graph_mode == 0) {
+    dag_status st = build_graph(c, r.get());
+    if (st) {
+      free_region(r.get());
+      return st;
+    }
+  }
+  auto it = c->regions.find(c->rec_key);
+  if (it != c->regions.end()) {
+    if (!c->dry) (void)hipDeviceSynchronize();
+    free_region(it->second.get());
+    it->second = std::move(r);
+  } else {
+    c->regions.emplace(c->rec_key, std::move(r));
+  }
+  return DAG_OK;
+}
+
+dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
+  CHECK_CTX(c);
+  if (c->recording) return fail(c, DAG_E_BUSY, "region launch while recording");
+  auto it = c->regions.find(key);
+  if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
+  Region* r = it->second.get();
+  const auto t0 = Clock::now();
+  int32_t s;
+  bool created;
+  const uint64_t id = c->tr.add_gpu(TK_REGION, 0, r->accs.data(), static_cast<uint32_t>(r->accs.size()),
+                                    c->serial, &s, &created);
+  if (out) *out = id;
+  dag_status st = ensure_stream(c, s);
+  if (st) return st;
+  c->submit_us += us_since(t0);
+  const auto t1 = Clock::now();
+  st = begin_task(c, id, s);
+  if (st) return st;
+  if (!c->dry) {
+    if (c->cfg.graph_mode == 0) {
+      HIP_TRY(c, hipGraphLaunch(r->exec, c->streams[s]));
+    } else {
+      st = replay_region(c, r, c->streams[s], s);
+      if (st) return st;
+    }
+  }
+  st = end_task(c, id, s);
+  c->launch_us += us_since(t1);
+  return st;
+}
+
+dag_status dag_region_info(dag_ctx c, uint64_t key, uint32_t* ntasks, uint32_t* nstreams) {
+  if (!c) return DAG_E_INVAL;
+  auto it = c->regions.find(key);
+  if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
+  if (ntasks) *ntasks = static_cast<uint32_t>(it->second->tasks.size());
+  if (nstreams) *nstreams = it->second->nstreams;
+  return DAG_OK;
+}
+
+dag_status dag_region_drop(dag_ctx c, uint64_t key) {
+  CHECK_CTX(c);
+  auto it = c->regions.find(key);
+  if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
+  if (!c->dry) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+  }
+  free_region(it->second.get());
+  c->regions.erase(it);
+  return DAG_OK;
+}
+
+dag_status dag_edges(dag_ctx c, dag_edge* out, size_t cap, size_t* n) {
+  if (!c || !n) return DAG_E_INVAL;
+  const std::vector<EdgeRec>& e = c->tr.edges();
+  *n = e.size();
+  if (!out || cap == 0) return DAG_OK;
+  std::vector<EdgeRec> v(e);
+  std::sort(v.begin(), v.end(), [](const EdgeRec& a, const EdgeRec& b) {
+    if (a.dst != b.dst) return a.dst < b.dst;
+    if (a.src != b.src) return a.src < b.src;
+    return a.buf < b.buf;
+  });
+  const size_t m = std::min(cap, v.size());
+  for (size_t i = 0; i < m; ++i) out[i] = dag_edge{v[i].src, v[i].dst, v[i].buf + 1, v[i].kind};
+  return DAG_OK;
+}
+
+dag_status dag_task_waits(dag_ctx c, dag_task t, dag_task* out, uint32_t cap, uint32_t* n) {
+  if (!c || !n) return DAG_E_INVAL;
+  if (t == 0 || t > c->tr.last_id()) return fail(c, DAG_E_INVAL, "unknown task %llu", (unsigned long long)t);
+  const TaskRec& r = c->tr.task(t);
+  *n = r.wait_n;
+  const uint64_t* w = c->tr.waits(t);
+  for (uint32_t i = 0; i < r.wait_n && i < cap && out; ++i) out[i] = w[i];
+  return DAG_OK;
+}
+
+dag_status dag_task_get_info(dag_ctx c, dag_task t, dag_task_info* out) {
+  if (!c || !out) return DAG_E_INVAL;
+  if (t == 0 || t > c->tr.last_id()) return fail(c, DAG_E_INVAL, "unknown task %llu", (unsigned long long)t);
+  const TaskRec& r = c->tr.task(t);
+  out->kind = r.kind;
+  out->stream = r.stream;
+  out->vertex = r.vertex ? 1 : 0;
+  out->active = r.active ? 1 : 0;
+  out->nparents = r.par_n;
+  out->nwaits = r.wait_n;
+  out->kernel_id = r.kernel_id;
+  out->reserved = 0;
+  out->t_start_ms = -1.0;
+  out->t_end_ms = -1.0;
+  if (c->cfg.trace && !c->dry && is_gpu_kind(r.kind) && t < c->ev.size() && c->ev[t] && c->ev0[t]) {
+    float a = 0.f, b = 0.f;
+    hipError_t e = hipEventSynchronize(c->ev[t]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&a, c->trace_ref, c->ev0[t]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, c->trace_ref, c->ev[t]);
+    if (e != hipSuccess) return hip_fail(c, e, "trace event query");
+    out->t_start_ms = a;
+    out->t_end_ms = b;
+  }
+  return DAG_OK;
+}
+
+dag_status dag_get_stats(dag_ctx c, dag_stats* out) {
+  if (!c || !out) return DAG_E_INVAL;
+  out->tasks = c->tr.last_id();
+  uint64_t v = 0;
+  for (uint64_t t = 1; t <= c->tr.last_id(); ++t) v += c->tr.task(t).vertex ? 1 : 0;
+  out->vertices = v;
+  out->edges = c->tr.edges().size();
+  out->waits = c->n_waits;
+  out->host_waits = c->n_host_waits;
+  out->streams = c->tr.num_streams();
+  out->active = static_cast<uint32_t>(c->tr.num_active());
+  out->submit_host_us = c->submit_us;
+  out->launch_host_us = c->launch_us;
+  return DAG_OK;
+}
+
+dag_status dag_trace_reset(dag_ctx c) {
+  CHECK_CTX(c);
+  if (!c->cfg.trace) return fail(c, DAG_E_UNSUPPORTED, "trace is off");
+  if (c->dry) return DAG_OK;
+  HIP_TRY(c, hipDeviceSynchronize());
+  HIP_TRY(c, hipEventRecord(c->trace_ref, c->io));
+  HIP_TRY(c, hipEventSynchronize(c->trace_ref));
+  return DAG_OK;
+}
+
+dag_status dag_stream_handle(dag_ctx c, uint32_t i, void** s) {
+  if (!c || !s) return DAG_E_INVAL;
+  if (i >= c->streams.size()) return fail(c, DAG_E_INVAL, "no stream %u", i);
+  *s = c->streams[i];
+  return DAG_OK;
+}
+
+}  // extern "C"

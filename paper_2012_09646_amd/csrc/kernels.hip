@@ -1,0 +1,985 @@
+// Task kernels of the benchmark workloads, written for gfx950 (CDNA4):
+// wave64, fp32 data in HBM, fp64 arithmetic in registers, one rounding to
+// fp32 on store.  None of them is a dense contraction, so none uses MFMA:
+// they are HBM-bound (coalesced float4 streams, LDS-tiled stencils, a
+// merge-path CSR SpMV) and keep every reduction deterministic (fixed
+// combination order, no floating-point atomics).
+//
+// Benchmarks (paper Sec. V-B): VEC sums the difference of two squared
+// vectors; B&S prices European calls in double precision; IMG combines a
+// sharpened image with blurred copies; HITS repeats SpMV with a matrix and
+// its transpose.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/dagrt.h"
+#include "kernels.hpp"
+
+namespace dagrt {
+namespace {
+
+constexpr int kWave = 64;
+uint64_t g_wall_khz = 100000;  // device constant-rate clock (kHz)
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// ---------------------------------------------------------------------------
+// Wave / workgroup reductions (butterfly: every lane ends with the same value)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Sum over the workgroup (<= 1024 threads); every thread gets the result.
+__device__ double block_sum(double v, double* sh /* 17 entries */) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  v = wave_sum(v);
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    double r = lane < nw ? sh[lane] : 0.0;
+    r = wave_sum(r);
+    if (lane == 0) sh[16] = r;
+  }
+  __syncthreads();
+  const double r = sh[16];
+  __syncthreads();
+  return r;
+}
+
+__device__ void block_minmax(float* mx, float* mn, float* sh /* 34 entries */) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  float a = wave_max(*mx), b = wave_min(*mn);
+  if (lane == 0) {
+    sh[w] = a;
+    sh[16 + w] = b;
+  }
+  __syncthreads();
+  if (w == 0) {
+    a = lane < nw ? sh[lane] : -INFINITY;
+    b = lane < nw ? sh[16 + lane] : INFINITY;
+    a = wave_max(a);
+    b = wave_min(b);
+    if (lane == 0) {
+      sh[32] = a;
+      sh[33] = b;
+    }
+  }
+  __syncthreads();
+  *mx = sh[32];
+  *mn = sh[33];
+  __syncthreads();
+}
+
+// Grid-wide completion: each workgroup publishes its partial, then takes a
+// ticket; the workgroup holding the last ticket combines all partials in
+// index order.  Agent-scope release/acquire makes the partials visible
+// across XCDs (each has its own L2).
+__device__ __forceinline__ void publish_partial(uint64_t* partials, uint64_t bits) {
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&partials[blockIdx.x], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t read_partial(const uint64_t* partials, uint32_t i) {
+  return __hip_atomic_load(const_cast<uint64_t*>(partials) + i, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ bool arrive_last(uint32_t* counter, int* s_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t t =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = (t == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *s_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+__device__ __forceinline__ void reset_counter(uint32_t* counter) {
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t d2u(double d) { return static_cast<uint64_t>(__double_as_longlong(d)); }
+__device__ __forceinline__ double u2d(uint64_t u) { return __longlong_as_double(static_cast<long long>(u)); }
+
+// ---------------------------------------------------------------------------
+// VEC: x <- x*x (one fp32 product, bit-exact with IEEE single precision)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_vec_square(float* __restrict__ x, uint64_t n, int vec) {
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  if (vec) {
+    float4* x4 = reinterpret_cast<float4*>(x);
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      float4 v = x4[i];
+      v.x *= v.x;
+      v.y *= v.y;
+      v.z *= v.z;
+      v.w *= v.w;
+      x4[i] = v;
+    }
+    for (uint64_t i = (n4 << 2) + gid; i < n; i += stride) x[i] *= x[i];
+  } else {
+    for (uint64_t i = gid; i < n; i += stride) x[i] *= x[i];
+  }
+}
+
+// r[0] = fl32(sum_i (x_i - y_i)) with fp64 differences and accumulation.
+__global__ __launch_bounds__(1024) void k_vec_sum_diff(const float* __restrict__ x,
+                                                       const float* __restrict__ y,
+                                                       float* __restrict__ r, uint64_t n, int vec,
+                                                       uint32_t* counter, uint64_t* partials) {
+  __shared__ double sh[17];
+  __shared__ int flag;
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  double acc = 0.0;
+  if (vec) {
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const float4* y4 = reinterpret_cast<const float4*>(y);
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      const float4 a = x4[i], b = y4[i];
+      acc += static_cast<double>(a.x) - static_cast<double>(b.x);
+      acc += static_cast<double>(a.y) - static_cast<double>(b.y);
+      acc += static_cast<double>(a.z) - static_cast<double>(b.z);
+      acc += static_cast<double>(a.w) - static_cast<double>(b.w);
+    }
+    for (uint64_t i = (n4 << 2) + gid; i < n; i += stride)
+      acc += static_cast<double>(x[i]) - static_cast<double>(y[i]);
+  } else {
+    for (uint64_t i = gid; i < n; i += stride)
+      acc += static_cast<double>(x[i]) - static_cast<double>(y[i]);
+  }
+  const double bsum = block_sum(acc, sh);
+  publish_partial(partials, d2u(bsum));
+  if (arrive_last(counter, &flag)) {
+    double t = 0.0;
+    for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) t += u2d(read_partial(partials, i));
+    const double tot = block_sum(t, sh);
+    if (threadIdx.x == 0) r[0] = static_cast<float>(tot);
+    reset_counter(counter);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// B&S: European call, C = S N(d1) - K e^{-rT} N(d2), N(z) = erfc(-z/sqrt2)/2
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bs_price(double s, double strike, double mu_t, double vol_t,
+                                           double disc_strike) {
+  const double d1 = (log(s / strike) + mu_t) / vol_t;
+  const double d2 = d1 - vol_t;
+  const double n1 = 0.5 * erfc(-d1 * M_SQRT1_2);
+  const double n2 = 0.5 * erfc(-d2 * M_SQRT1_2);
+  return s * n1 - disc_strike * n2;
+}
+
+__global__ __launch_bounds__(1024) void k_bs_call(const float* __restrict__ S, float* __restrict__ C,
+                                                  uint64_t n, int vec, double strike, double mu_t,
+                                                  double vol_t, double disc_strike) {
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  if (vec) {
+    const float4* s4 = reinterpret_cast<const float4*>(S);
+    float4* c4 = reinterpret_cast<float4*>(C);
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      const float4 s = s4[i];
+      float4 c;
+      c.x = static_cast<float>(bs_price(s.x, strike, mu_t, vol_t, disc_strike));
+      c.y = static_cast<float>(bs_price(s.y, strike, mu_t, vol_t, disc_strike));
+      c.z = static_cast<float>(bs_price(s.z, strike, mu_t, vol_t, disc_strike));
+      c.w = static_cast<float>(bs_price(s.w, strike, mu_t, vol_t, disc_strike));
+      c4[i] = c;
+    }
+    for (uint64_t i = (n4 << 2) + gid; i < n; i += stride)
+      C[i] = static_cast<float>(bs_price(S[i], strike, mu_t, vol_t, disc_strike));
+  } else {
+    for (uint64_t i = gid; i < n; i += stride)
+      C[i] = static_cast<float>(bs_price(S[i], strike, mu_t, vol_t, disc_strike));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// IMG: LDS-tiled stencils with clamp-to-edge borders.  A workgroup of 256
+// threads (64 x 4) produces a 64 x 16 output tile.
+// ---------------------------------------------------------------------------
+constexpr int kTW = 64;
+constexpr int kTH = 16;
+
+struct GaussW {
+  double w[31];
+};
+
+// Separable Gaussian: stage the input tile with its halo in LDS (fp32, as
+// stored), horizontal pass into an fp64 LDS tile, vertical pass to output.
+template <int R>
+__global__ __launch_bounds__(256) void k_gauss_blur(const float* __restrict__ in,
+                                                    float* __restrict__ out, int w, int h,
+                                                    GaussW wt) {
+  constexpr int K = 2 * R + 1;
+  constexpr int IW = kTW + 2 * R;
+  constexpr int IH = kTH + 2 * R;
+  __shared__ float s_in[IH][IW];
+  __shared__ double s_h[IH][kTW];
+  const int x0 = blockIdx.x * kTW;
+  const int y0 = blockIdx.y * kTH;
+  for (int i = threadIdx.x; i < IH * IW; i += 256) {
+    const int r = i / IW, c = i - r * IW;
+    const int gy = min(max(y0 - R + r, 0), h - 1);
+    const int gx = min(max(x0 - R + c, 0), w - 1);
+    s_in[r][c] = in[static_cast<size_t>(gy) * w + gx];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < IH * kTW; i += 256) {
+    const int r = i / kTW, c = i - r * kTW;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc += wt.w[j] * static_cast<double>(s_in[r][c + j]);
+    s_h[r][c] = acc;
+  }
+  __syncthreads();
+  const int c = threadIdx.x & (kTW - 1);
+  const int gx = x0 + c;
+  for (int r = threadIdx.x / kTW; r < kTH; r += 256 / kTW) {
+    const int gy = y0 + r;
+    if (gx < w && gy < h) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < K; ++i) acc += wt.w[i] * s_h[r + i][c];
+      out[static_cast<size_t>(gy) * w + gx] = static_cast<float>(acc);
+    }
+  }
+}
+
+// Sobel gradient magnitude sqrt(gx^2 + gy^2), gx with [[-1,0,1],[-2,0,2],
+// [-1,0,1]] (correlation), gy with its transpose.
+__global__ __launch_bounds__(256) void k_sobel(const float* __restrict__ in,
+                                               float* __restrict__ out, int w, int h) {
+  constexpr int IW = kTW + 2, IH = kTH + 2;
+  __shared__ float s_in[IH][IW];
+  const int x0 = blockIdx.x * kTW;
+  const int y0 = blockIdx.y * kTH;
+  for (int i = threadIdx.x; i < IH * IW; i += 256) {
+    const int r = i / IW, c = i - r * IW;
+    const int gy = min(max(y0 - 1 + r, 0), h - 1);
+    const int gx = min(max(x0 - 1 + c, 0), w - 1);
+    s_in[r][c] = in[static_cast<size_t>(gy) * w + gx];
+  }
+  __syncthreads();
+  const int c = threadIdx.x & (kTW - 1);
+  const int gx = x0 + c;
+  for (int r = threadIdx.x / kTW; r < kTH; r += 256 / kTW) {
+    const int gy = y0 + r;
+    if (gx < w && gy < h) {
+      const double p00 = s_in[r][c], p01 = s_in[r][c + 1], p02 = s_in[r][c + 2];
+      const double p10 = s_in[r + 1][c], p12 = s_in[r + 1][c + 2];
+      const double p20 = s_in[r + 2][c], p21 = s_in[r + 2][c + 1], p22 = s_in[r + 2][c + 2];
+      const double sx = (p02 - p00) + 2.0 * (p12 - p10) + (p22 - p20);
+      const double sy = (p20 - p00) + 2.0 * (p21 - p01) + (p22 - p02);
+      out[static_cast<size_t>(gy) * w + gx] = static_cast<float>(sqrt(sx * sx + sy * sy));
+    }
+  }
+}
+
+// M = [max, min] of n fp32 values (exact).
+__global__ __launch_bounds__(1024) void k_minmax(const float* __restrict__ a, float* __restrict__ M,
+                                                 uint64_t n, int vec, uint32_t* counter,
+                                                 uint64_t* partials) {
+  __shared__ float sh[34];
+  __shared__ int flag;
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  float mx = -INFINITY, mn = INFINITY;
+  if (vec) {
+    const float4* a4 = reinterpret_cast<const float4*>(a);
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      const float4 v = a4[i];
+      mx = fmaxf(mx, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+      mn = fminf(mn, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+    }
+    for (uint64_t i = (n4 << 2) + gid; i < n; i += stride) {
+      mx = fmaxf(mx, a[i]);
+      mn = fminf(mn, a[i]);
+    }
+  } else {
+    for (uint64_t i = gid; i < n; i += stride) {
+      mx = fmaxf(mx, a[i]);
+      mn = fminf(mn, a[i]);
+    }
+  }
+  block_minmax(&mx, &mn, sh);
+  publish_partial(partials, (static_cast<uint64_t>(__float_as_uint(mx)) << 32) | __float_as_uint(mn));
+  if (arrive_last(counter, &flag)) {
+    float gmx = -INFINITY, gmn = INFINITY;
+    for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
+      const uint64_t u = read_partial(partials, i);
+      gmx = fmaxf(gmx, __uint_as_float(static_cast<uint32_t>(u >> 32)));
+      gmn = fminf(gmn, __uint_as_float(static_cast<uint32_t>(u & 0xffffffffu)));
+    }
+    block_minmax(&gmx, &gmn, sh);
+    if (threadIdx.x == 0) {
+      M[0] = gmx;
+      M[1] = gmn;
+    }
+    reset_counter(counter);
+  }
+}
+
+// N = (S - min) / (max - min) in fp64; all zeros when max == min.
+__device__ __forceinline__ float norm1(float s, double mn, double d) {
+  return d == 0.0 ? 0.0f : static_cast<float>((static_cast<double>(s) - mn) / d);
+}
+__global__ __launch_bounds__(1024) void k_normalise(const float* __restrict__ S,
+                                                    const float* __restrict__ M,
+                                                    float* __restrict__ N, uint64_t n, int vec) {
+  const double mx = M[0], mn = M[1];
+  const double d = mx - mn;
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  if (vec) {
+    const float4* s4 = reinterpret_cast<const float4*>(S);
+    float4* o4 = reinterpret_cast<float4*>(N);
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      const float4 s = s4[i];
+      o4[i] = make_float4(norm1(s.x, mn, d), norm1(s.y, mn, d), norm1(s.z, mn, d), norm1(s.w, mn, d));
+    }
+    for (uint64_t i = (n4 << 2) + gid; i < n; i += stride) N[i] = norm1(S[i], mn, d);
+  } else {
+    for (uint64_t i = gid; i < n; i += stride) N[i] = norm1(S[i], mn, d);
+  }
+}
+
+// Unsharp-mask combine: E = (N3+N7+N15)/3, sharp = 2 img - B3,
+// soft = (B7+B15)/2, out = clamp(E sharp + (1-E) soft, 0, 1).
+__device__ __forceinline__ float combine1(float img, float b3, float b7, float b15, float n3,
+                                          float n7, float n15) {
+  const double e = (static_cast<double>(n3) + static_cast<double>(n7) + static_cast<double>(n15)) / 3.0;
+  const double sharp = 2.0 * static_cast<double>(img) - static_cast<double>(b3);
+  const double soft = 0.5 * (static_cast<double>(b7) + static_cast<double>(b15));
+  const double o = e * sharp + (1.0 - e) * soft;
+  return static_cast<float>(fmin(fmax(o, 0.0), 1.0));
+}
+__global__ __launch_bounds__(1024) void k_unsharp_combine(
+    const float* __restrict__ img, const float* __restrict__ b3, const float* __restrict__ b7,
+    const float* __restrict__ b15, const float* __restrict__ n3, const float* __restrict__ n7,
+    const float* __restrict__ n15, float* __restrict__ out, uint64_t n, int vec) {
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t start = 0;
+  if (vec) {
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      const float4 a = reinterpret_cast<const float4*>(img)[i];
+      const float4 p = reinterpret_cast<const float4*>(b3)[i];
+      const float4 q = reinterpret_cast<const float4*>(b7)[i];
+      const float4 u = reinterpret_cast<const float4*>(b15)[i];
+      const float4 e3 = reinterpret_cast<const float4*>(n3)[i];
+      const float4 e7 = reinterpret_cast<const float4*>(n7)[i];
+      const float4 e15 = reinterpret_cast<const float4*>(n15)[i];
+      reinterpret_cast<float4*>(out)[i] =
+          make_float4(combine1(a.x, p.x, q.x, u.x, e3.x, e7.x, e15.x),
+                      combine1(a.y, p.y, q.y, u.y, e3.y, e7.y, e15.y),
+                      combine1(a.z, p.z, q.z, u.z, e3.z, e7.z, e15.z),
+                      combine1(a.w, p.w, q.w, u.w, e3.w, e7.w, e15.w));
+    }
+    start = n4 << 2;
+  }
+  for (uint64_t i = start + gid; i < n; i += stride)
+    out[i] = combine1(img[i], b3[i], b7[i], b15[i], n3[i], n7[i], n15[i]);
+}
+
+// ---------------------------------------------------------------------------
+// HITS: CSR SpMV (merge-path over row ends and nonzeros, so a row with
+// millions of nonzeros is split evenly across workgroups), sum of squares,
+// L2 scaling.
+// ---------------------------------------------------------------------------
+struct SpmvScratch {
+  int* head_row;      // per tile: row whose sum continues from earlier tiles, or -1
+  int* tail_row;      // per tile: row open at the end of the tile
+  double* head_val;   // per tile: this tile's part of head_row (incl. in-tile carry)
+  double* tail_val;   // per tile: this tile's part of tail_row
+};
+
+__device__ __forceinline__ int clamp_nnz(int v, int nnz) { return min(max(v, 0), nnz); }
+
+template <int IPT>
+__global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col,
+                                                    const float* __restrict__ val,
+                                                    const float* __restrict__ x,
+                                                    float* __restrict__ y, int nrows, int ncols,
+                                                    int nnz, SpmvScratch sc) {
+  constexpr int TILE = 256 * IPT;
+  __shared__ int s_rowend[TILE + 1];
+  __shared__ double s_prod[TILE];
+  __shared__ int s_crow[256];
+  __shared__ double s_cval[256];
+  __shared__ int s_coord[4];
+  __shared__ int s_head_row;
+  __shared__ double s_head_val;
+  const int tid = threadIdx.x;
+  const long long total = static_cast<long long>(nrows) + nnz;
+  if (tid < 2) {
+    const long long diag = min(static_cast<long long>(blockIdx.x + tid) * TILE, total);
+    long long lo = max(0LL, diag - nnz), hi = min(diag, static_cast<long long>(nrows));
+    while (lo < hi) {
+      const long long mid = (lo + hi) >> 1;
+      if (clamp_nnz(row_ptr[mid + 1], nnz) <= diag - mid - 1)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    s_coord[2 * tid] = static_cast<int>(lo);
+    s_coord[2 * tid + 1] = static_cast<int>(diag - lo);
+  }
+  if (tid == 0) s_head_row = -1;
+  __syncthreads();
+  const int xb = s_coord[0], yb = s_coord[1];
+  const int na = max(0, min(s_coord[2] - xb, TILE));
+  const int nb = max(0, min(s_coord[3] - yb, TILE));
+  for (int i = tid; i <= na; i += 256) {
+    const int r = xb + i;
+    s_rowend[i] = r < nrows ? clamp_nnz(row_ptr[r + 1], nnz) : nnz;
+  }
+  for (int i = tid; i < nb; i += 256) {
+    const int k = yb + i;
+    const int c = min(max(col[k], 0), ncols - 1);
+    s_prod[i] = static_cast<double>(val[k]) * static_cast<double>(x[c]);
+  }
+  __syncthreads();
+  // this thread's segment of the merge path inside the tile
+  const int td = min(tid * IPT, na + nb);
+  int lo = max(0, td - nb), hi = min(td, na);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s_rowend[mid] <= yb + td - mid - 1)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int tx = lo, ty = td - lo;
+  const int te = min(td + IPT, na + nb);
+  double acc = 0.0;
+  bool has_head = false;
+  int head_row = 0;
+  double head_acc = 0.0;
+  for (int d = td; d < te; ++d) {
+    if (tx < na && (ty >= nb || s_rowend[tx] <= yb + ty)) {
+      if (!has_head) {
+        has_head = true;
+        head_row = tx;
+        head_acc = acc;
+      } else {
+        y[xb + tx] = static_cast<float>(acc);
+      }
+      acc = 0.0;
+      ++tx;
+    } else {
+      acc += s_prod[ty];
+      ++ty;
+    }
+  }
+  s_crow[tid] = tx;
+  s_cval[tid] = acc;
+  __syncthreads();
+  // segmented inclusive scan of the carries (rows are non-decreasing)
+  for (int off = 1; off < 256; off <<= 1) {
+    const double add = (tid >= off && s_crow[tid - off] == s_crow[tid]) ? s_cval[tid - off] : 0.0;
+    __syncthreads();
+    s_cval[tid] += add;
+    __syncthreads();
+  }
+  if (has_head) {
+    const double cin = (tid > 0 && s_crow[tid - 1] == head_row) ? s_cval[tid - 1] : 0.0;
+    const double v = head_acc + cin;
+    const int grow = xb + head_row;
+    if (head_row == 0 && clamp_nnz(row_ptr[xb], nnz) < yb) {
+      s_head_row = grow;
+      s_head_val = v;
+    } else {
+      y[grow] = static_cast<float>(v);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    sc.head_row[blockIdx.x] = s_head_row;
+    sc.head_val[blockIdx.x] = s_head_row >= 0 ? s_head_val : 0.0;
+    sc.tail_row[blockIdx.x] = xb + na;
+    sc.tail_val[blockIdx.x] = s_cval[255];
+  }
+}
+
+// Rows split across tiles: add the parts of the preceding tiles, in order.
+__global__ __launch_bounds__(256) void k_spmv_fixup(float* __restrict__ y, SpmvScratch sc,
+                                                    int ntiles) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= ntiles) return;
+  const int r = sc.head_row[b];
+  if (r < 0) return;
+  double v = sc.head_val[b];
+  for (int p = b - 1; p >= 0 && sc.tail_row[p] == r; --p) v += sc.tail_val[p];
+  y[r] = static_cast<float>(v);
+}
+
+// s = sum v_i^2 (fp64).
+__global__ __launch_bounds__(1024) void k_sumsq(const float* __restrict__ v, double* __restrict__ s,
+                                                uint64_t n, int vec, uint32_t* counter,
+                                                uint64_t* partials) {
+  __shared__ double sh[17];
+  __shared__ int flag;
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  double acc = 0.0;
+  uint64_t start = 0;
+  if (vec) {
+    const float4* v4 = reinterpret_cast<const float4*>(v);
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      const float4 a = v4[i];
+      const double ax = a.x, ay = a.y, az = a.z, aw = a.w;
+      acc += ax * ax;
+      acc += ay * ay;
+      acc += az * az;
+      acc += aw * aw;
+    }
+    start = n4 << 2;
+  }
+  for (uint64_t i = start + gid; i < n; i += stride) {
+    const double a = v[i];
+    acc += a * a;
+  }
+  const double bsum = block_sum(acc, sh);
+  publish_partial(partials, d2u(bsum));
+  if (arrive_last(counter, &flag)) {
+    double t = 0.0;
+    for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) t += u2d(read_partial(partials, i));
+    const double tot = block_sum(t, sh);
+    if (threadIdx.x == 0) s[0] = tot;
+    reset_counter(counter);
+  }
+}
+
+// v_i = fl32(t_i / sqrt(s)) in fp64.
+__global__ __launch_bounds__(1024) void k_scale_l2(const float* __restrict__ t,
+                                                   const double* __restrict__ s,
+                                                   float* __restrict__ v, uint64_t n, int vec) {
+  const double r = sqrt(s[0]);
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t start = 0;
+  if (vec) {
+    const float4* t4 = reinterpret_cast<const float4*>(t);
+    float4* v4 = reinterpret_cast<float4*>(v);
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride) {
+      const float4 a = t4[i];
+      v4[i] = make_float4(static_cast<float>(a.x / r), static_cast<float>(a.y / r),
+                          static_cast<float>(a.z / r), static_cast<float>(a.w / r));
+    }
+    start = n4 << 2;
+  }
+  for (uint64_t i = start + gid; i < n; i += stride) v[i] = static_cast<float>(t[i] / r);
+}
+
+// ---------------------------------------------------------------------------
+// Utilities: a delay kernel for scheduler tests and a plain copy.
+// ---------------------------------------------------------------------------
+__global__ void k_spin(uint64_t ticks) {
+  if (threadIdx.x == 0) {
+    const uint64_t t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_copy_f32(const float* __restrict__ src,
+                                                   float* __restrict__ dst, uint64_t n, int vec) {
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t start = 0;
+  if (vec) {
+    const uint64_t n4 = n >> 2;
+    for (uint64_t i = gid; i < n4; i += stride)
+      reinterpret_cast<float4*>(dst)[i] = reinterpret_cast<const float4*>(src)[i];
+    start = n4 << 2;
+  }
+  for (uint64_t i = start + gid; i < n; i += stride) dst[i] = src[i];
+}
+
+// ===========================================================================
+// Host side: argument checks and launches
+// ===========================================================================
+const char* cfg_block_any(const LaunchCfg& c) {
+  if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
+  if (c.variant != 0) return "variant must be 0";
+  return nullptr;
+}
+const char* cfg_tile256(const LaunchCfg& c) {
+  if (c.block != 256) return "this kernel runs 256-thread workgroups";
+  if (c.grid_cap != 0 || c.variant != 0) return "grid_cap and variant must be 0";
+  return nullptr;
+}
+const char* cfg_spmv(const LaunchCfg& c) {
+  if (c.block != 256) return "SpMV runs 256-thread workgroups";
+  if (c.grid_cap != 0) return "grid_cap must be 0";
+  if (c.variant != 4 && c.variant != 8 && c.variant != 12 && c.variant != 16)
+    return "SpMV variant (items per thread) must be 4, 8, 12 or 16";
+  return nullptr;
+}
+const char* cfg_spin(const LaunchCfg& c) {
+  if (c.block != 64 || c.grid_cap != 0 || c.variant != 0) return "spin runs one 64-thread workgroup";
+  return nullptr;
+}
+
+uint32_t stream_grid(uint64_t work, const LaunchCfg& c) {
+  uint64_t g = ceil_div(std::max<uint64_t>(work, 1), c.block);
+  if (c.grid_cap) g = std::min<uint64_t>(g, c.grid_cap);
+  return static_cast<uint32_t>(std::max<uint64_t>(std::min<uint64_t>(g, 1u << 30), 1));
+}
+
+uint64_t reduction_capacity(size_t scratch_bytes) {
+  return scratch_bytes > kScratchPartialsOffset ? (scratch_bytes - kScratchPartialsOffset) / 8 : 0;
+}
+
+uint32_t reduction_grid(uint64_t work, const LaunchCfg& c, size_t scratch_bytes) {
+  uint64_t g = stream_grid(work, c);
+  g = std::min<uint64_t>(g, reduction_capacity(scratch_bytes));
+  return static_cast<uint32_t>(std::max<uint64_t>(g, 1));
+}
+
+uint64_t pn(const void* p) { return static_cast<const dag_p_n*>(p)->n; }
+
+bool mul_fits(uint64_t a, uint64_t b, size_t have) {
+  return a <= (~0ull) / b && a * b <= have;
+}
+
+// -- VEC --------------------------------------------------------------------
+const char* v_vec_square(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  return mul_fits(pn(p), 4, sz[0]) ? nullptr : "x smaller than 4*n bytes";
+}
+hipError_t l_vec_square(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const uint64_t n = pn(p);
+  if (n == 0) return hipSuccess;
+  const int vec = aligned16(a[0]);
+  hipLaunchKernelGGL(k_vec_square, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+                     static_cast<float*>(a[0]), n, vec);
+  return hipGetLastError();
+}
+
+const char* v_vec_sum_diff(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t sb) {
+  const uint64_t n = pn(p);
+  if (!mul_fits(n, 4, sz[0]) || !mul_fits(n, 4, sz[1])) return "x or y smaller than 4*n bytes";
+  if (sz[2] < 4) return "r smaller than 4 bytes";
+  if (reduction_capacity(sb) < 1) return "scratch too small";
+  return nullptr;
+}
+hipError_t l_vec_sum_diff(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
+  const uint64_t n = pn(p);
+  const int vec = aligned16(a[0]) && aligned16(a[1]);
+  auto* counter = static_cast<uint32_t*>(scr);
+  auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
+  hipLaunchKernelGGL(k_vec_sum_diff, dim3(reduction_grid(vec ? ceil_div(n, 4) : n, c, sb)), dim3(c.block), 0,
+                     s, static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
+                     static_cast<float*>(a[2]), n, vec, counter, partials);
+  return hipGetLastError();
+}
+
+// -- B&S --------------------------------------------------------------------
+const char* v_bs(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const auto* q = static_cast<const dag_p_bs*>(p);
+  if (!mul_fits(q->n, 4, sz[0]) || !mul_fits(q->n, 4, sz[1])) return "S or C smaller than 4*n bytes";
+  if (!(q->strike > 0) || !(q->vol > 0) || !(q->years > 0)) return "strike, vol and years must be > 0";
+  return nullptr;
+}
+hipError_t l_bs(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const auto* q = static_cast<const dag_p_bs*>(p);
+  if (q->n == 0) return hipSuccess;
+  const double vol_t = q->vol * std::sqrt(q->years);
+  const double mu_t = (q->rate + 0.5 * q->vol * q->vol) * q->years;
+  const double disc = q->strike * std::exp(-q->rate * q->years);
+  const int vec = aligned16(a[0]) && aligned16(a[1]);
+  hipLaunchKernelGGL(k_bs_call, dim3(stream_grid(vec ? ceil_div(q->n, 4) : q->n, c)), dim3(c.block), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<float*>(a[1]), q->n, vec, q->strike,
+                     mu_t, vol_t, disc);
+  return hipGetLastError();
+}
+
+// -- IMG --------------------------------------------------------------------
+const char* v_img2(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const auto* q = static_cast<const dag_p_img*>(p);
+  if (q->w == 0 || q->h == 0) return "empty image";
+  const uint64_t n = static_cast<uint64_t>(q->w) * q->h;
+  if (n > (1ull << 31)) return "image larger than 2^31 pixels";
+  if (!mul_fits(n, 4, sz[0]) || !mul_fits(n, 4, sz[1])) return "image buffers smaller than 4*w*h bytes";
+  return nullptr;
+}
+const char* v_blur(const void* p, const size_t* sz, uint32_t na, const LaunchCfg& c, size_t sb) {
+  const auto* q = static_cast<const dag_p_img*>(p);
+  if (q->ksize < 1 || q->ksize > 31 || q->ksize % 2 == 0) return "ksize must be odd in [1, 31]";
+  return v_img2(p, sz, na, c, sb);
+}
+
+template <int R>
+void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt) {
+  hipLaunchKernelGGL(k_gauss_blur<R>, dim3(ceil_div(w, kTW), ceil_div(h, kTH)), dim3(256), 0, s, in, out, w,
+                     h, wt);
+}
+
+hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg&, void*, size_t) {
+  const auto* q = static_cast<const dag_p_img*>(p);
+  const int k = static_cast<int>(q->ksize), rad = (k - 1) / 2;
+  const double sigma = k / 6.0;
+  GaussW wt{};
+  double sum = 0.0;
+  for (int i = -rad; i <= rad; ++i) {
+    wt.w[i + rad] = std::exp(-(static_cast<double>(i) * i) / (2.0 * sigma * sigma));
+    sum += wt.w[i + rad];
+  }
+  for (int i = 0; i < k; ++i) wt.w[i] /= sum;
+  const auto* in = static_cast<const float*>(a[0]);
+  auto* out = static_cast<float*>(a[1]);
+  const int w = static_cast<int>(q->w), h = static_cast<int>(q->h);
+  switch (rad) {
+    case 0: launch_blur_r<0>(s, in, out, w, h, wt); break;
+    case 1: launch_blur_r<1>(s, in, out, w, h, wt); break;
+    case 2: launch_blur_r<2>(s, in, out, w, h, wt); break;
+    case 3: launch_blur_r<3>(s, in, out, w, h, wt); break;
+    case 4: launch_blur_r<4>(s, in, out, w, h, wt); break;
+    case 5: launch_blur_r<5>(s, in, out, w, h, wt); break;
+    case 6: launch_blur_r<6>(s, in, out, w, h, wt); break;
+    case 7: launch_blur_r<7>(s, in, out, w, h, wt); break;
+    case 8: launch_blur_r<8>(s, in, out, w, h, wt); break;
+    case 9: launch_blur_r<9>(s, in, out, w, h, wt); break;
+    case 10: launch_blur_r<10>(s, in, out, w, h, wt); break;
+    case 11: launch_blur_r<11>(s, in, out, w, h, wt); break;
+    case 12: launch_blur_r<12>(s, in, out, w, h, wt); break;
+    case 13: launch_blur_r<13>(s, in, out, w, h, wt); break;
+    case 14: launch_blur_r<14>(s, in, out, w, h, wt); break;
+    default: launch_blur_r<15>(s, in, out, w, h, wt); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t l_sobel(hipStream_t s, void* const* a, const void* p, const LaunchCfg&, void*, size_t) {
+  const auto* q = static_cast<const dag_p_img*>(p);
+  hipLaunchKernelGGL(k_sobel, dim3(ceil_div(q->w, kTW), ceil_div(q->h, kTH)), dim3(256), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<float*>(a[1]), static_cast<int>(q->w),
+                     static_cast<int>(q->h));
+  return hipGetLastError();
+}
+
+const char* v_minmax(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t sb) {
+  const uint64_t n = pn(p);
+  if (n == 0) return "minmax of an empty array";
+  if (!mul_fits(n, 4, sz[0])) return "input smaller than 4*n bytes";
+  if (sz[1] < 8) return "M smaller than 8 bytes";
+  if (reduction_capacity(sb) < 1) return "scratch too small";
+  return nullptr;
+}
+hipError_t l_minmax(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
+  const uint64_t n = pn(p);
+  const int vec = aligned16(a[0]);
+  hipLaunchKernelGGL(k_minmax, dim3(reduction_grid(vec ? ceil_div(n, 4) : n, c, sb)), dim3(c.block), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<float*>(a[1]), n, vec,
+                     static_cast<uint32_t*>(scr),
+                     reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset));
+  return hipGetLastError();
+}
+
+const char* v_normalise(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const uint64_t n = pn(p);
+  if (!mul_fits(n, 4, sz[0]) || !mul_fits(n, 4, sz[2])) return "S or N smaller than 4*n bytes";
+  if (sz[1] < 8) return "M smaller than 8 bytes";
+  return nullptr;
+}
+hipError_t l_normalise(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const uint64_t n = pn(p);
+  if (n == 0) return hipSuccess;
+  const int vec = aligned16(a[0]) && aligned16(a[2]);
+  hipLaunchKernelGGL(k_normalise, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
+                     static_cast<float*>(a[2]), n, vec);
+  return hipGetLastError();
+}
+
+const char* v_combine(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const uint64_t n = pn(p);
+  for (int i = 0; i < 8; ++i)
+    if (!mul_fits(n, 4, sz[i])) return "a buffer is smaller than 4*n bytes";
+  return nullptr;
+}
+hipError_t l_combine(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const uint64_t n = pn(p);
+  if (n == 0) return hipSuccess;
+  int vec = 1;
+  for (int i = 0; i < 8; ++i) vec &= aligned16(a[i]) ? 1 : 0;
+  hipLaunchKernelGGL(k_unsharp_combine, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
+                     static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
+                     static_cast<const float*>(a[4]), static_cast<const float*>(a[5]),
+                     static_cast<const float*>(a[6]), static_cast<float*>(a[7]), n, vec);
+  return hipGetLastError();
+}
+
+// -- HITS -------------------------------------------------------------------
+uint64_t spmv_tiles(const dag_p_csr* q, uint32_t ipt) {
+  return ceil_div(static_cast<uint64_t>(q->nrows) + q->nnz, 256ull * ipt);
+}
+// Carries live after the reduction ticket counter (which must stay zero).
+size_t spmv_scratch_need(uint64_t tiles) { return kScratchPartialsOffset + tiles * (4 + 4 + 8 + 8); }
+
+const char* v_spmv(const void* p, const size_t* sz, uint32_t, const LaunchCfg& c, size_t sb) {
+  const auto* q = static_cast<const dag_p_csr*>(p);
+  if (q->nrows == 0) return nullptr;
+  if (q->ncols == 0) return "ncols must be > 0";
+  if (q->nnz > 0x7fffffffull - q->nrows) return "nrows + nnz must stay below 2^31";
+  if (!mul_fits(static_cast<uint64_t>(q->nrows) + 1, 4, sz[0])) return "row_ptr smaller than 4*(nrows+1) bytes";
+  if (!mul_fits(q->nnz, 4, sz[1]) || !mul_fits(q->nnz, 4, sz[2])) return "col or val smaller than 4*nnz bytes";
+  if (!mul_fits(q->ncols, 4, sz[3])) return "x smaller than 4*ncols bytes";
+  if (!mul_fits(q->nrows, 4, sz[4])) return "y smaller than 4*nrows bytes";
+  if (spmv_scratch_need(spmv_tiles(q, c.variant)) > sb) return "matrix too large for the per-stream scratch";
+  return nullptr;
+}
+
+template <int IPT>
+void launch_spmv_ipt(hipStream_t s, void* const* a, const dag_p_csr* q, const SpmvScratch& sc, int tiles) {
+  hipLaunchKernelGGL(k_spmv_merge<IPT>, dim3(tiles), dim3(256), 0, s, static_cast<const int*>(a[0]),
+                     static_cast<const int*>(a[1]), static_cast<const float*>(a[2]),
+                     static_cast<const float*>(a[3]), static_cast<float*>(a[4]), static_cast<int>(q->nrows),
+                     static_cast<int>(q->ncols), static_cast<int>(q->nnz), sc);
+}
+
+hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t) {
+  const auto* q = static_cast<const dag_p_csr*>(p);
+  if (q->nrows == 0) return hipSuccess;
+  const int tiles = static_cast<int>(spmv_tiles(q, c.variant));
+  char* base = static_cast<char*>(scr) + kScratchPartialsOffset;
+  SpmvScratch sc;
+  sc.head_val = reinterpret_cast<double*>(base);
+  sc.tail_val = reinterpret_cast<double*>(base + 8ull * tiles);
+  sc.head_row = reinterpret_cast<int*>(base + 16ull * tiles);
+  sc.tail_row = reinterpret_cast<int*>(base + 20ull * tiles);
+  switch (c.variant) {
+    case 4: launch_spmv_ipt<4>(s, a, q, sc, tiles); break;
+    case 12: launch_spmv_ipt<12>(s, a, q, sc, tiles); break;
+    case 16: launch_spmv_ipt<16>(s, a, q, sc, tiles); break;
+    default: launch_spmv_ipt<8>(s, a, q, sc, tiles); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_spmv_fixup, dim3(ceil_div(tiles, 256)), dim3(256), 0, s, static_cast<float*>(a[4]), sc,
+                     tiles);
+  return hipGetLastError();
+}
+
+const char* v_sumsq(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t sb) {
+  if (!mul_fits(pn(p), 4, sz[0])) return "v smaller than 4*n bytes";
+  if (sz[1] < 8) return "s smaller than 8 bytes";
+  if (reduction_capacity(sb) < 1) return "scratch too small";
+  return nullptr;
+}
+hipError_t l_sumsq(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
+  const uint64_t n = pn(p);
+  const int vec = aligned16(a[0]);
+  hipLaunchKernelGGL(k_sumsq, dim3(reduction_grid(vec ? ceil_div(n, 4) : n, c, sb)), dim3(c.block), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<double*>(a[1]), n, vec,
+                     static_cast<uint32_t*>(scr),
+                     reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset));
+  return hipGetLastError();
+}
+
+const char* v_scale(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const uint64_t n = pn(p);
+  if (!mul_fits(n, 4, sz[0]) || !mul_fits(n, 4, sz[2])) return "t or v smaller than 4*n bytes";
+  if (sz[1] < 8) return "s smaller than 8 bytes";
+  return nullptr;
+}
+hipError_t l_scale(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const uint64_t n = pn(p);
+  if (n == 0) return hipSuccess;
+  const int vec = aligned16(a[0]) && aligned16(a[2]);
+  hipLaunchKernelGGL(k_scale_l2, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<const double*>(a[1]),
+                     static_cast<float*>(a[2]), n, vec);
+  return hipGetLastError();
+}
+
+// -- utilities ---------------------------------------------------------------
+const char* v_spin(const void* p, const size_t*, uint32_t, const LaunchCfg&, size_t) {
+  return static_cast<const dag_p_spin*>(p)->ns <= 1000000000ull ? nullptr : "spin longer than 1 s";
+}
+hipError_t l_spin(hipStream_t s, void* const*, const void* p, const LaunchCfg&, void*, size_t) {
+  const uint64_t ns = static_cast<const dag_p_spin*>(p)->ns;
+  const uint64_t ticks = ns * g_wall_khz / 1000000ull;
+  hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, s, ticks);
+  return hipGetLastError();
+}
+
+const char* v_copy(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const uint64_t n = pn(p);
+  if (!mul_fits(n, 4, sz[0]) || !mul_fits(n, 4, sz[1])) return "src or dst smaller than 4*n bytes";
+  return nullptr;
+}
+hipError_t l_copy(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const uint64_t n = pn(p);
+  if (n == 0) return hipSuccess;
+  const int vec = aligned16(a[0]) && aligned16(a[1]);
+  hipLaunchKernelGGL(k_copy_f32, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+                     static_cast<const float*>(a[0]), static_cast<float*>(a[1]), n, vec);
+  return hipGetLastError();
+}
+
+const KernelDesc kTable[] = {
+    /* 0 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
+    /* 1 */ {"vec_square", 1, 0x1, sizeof(dag_p_n), {256, 0, 0}, v_vec_square, l_vec_square, cfg_block_any},
+    /* 2 */ {"vec_sum_diff", 3, 0x4, sizeof(dag_p_n), {256, 1024, 0}, v_vec_sum_diff, l_vec_sum_diff, cfg_block_any},
+    /* 3 */ {"bs_call", 2, 0x2, sizeof(dag_p_bs), {256, 0, 0}, v_bs, l_bs, cfg_block_any},
+    /* 4 */ {"gauss_blur", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_blur, l_blur, cfg_tile256},
+    /* 5 */ {"sobel", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_img2, l_sobel, cfg_tile256},
+    /* 6 */ {"minmax", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_minmax, l_minmax, cfg_block_any},
+    /* 7 */ {"normalise", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_normalise, l_normalise, cfg_block_any},
+    /* 8 */ {"unsharp_combine", 8, 0x80, sizeof(dag_p_n), {256, 0, 0}, v_combine, l_combine, cfg_block_any},
+    /* 9 */ {"spmv", 5, 0x10, sizeof(dag_p_csr), {256, 0, 8}, v_spmv, l_spmv, cfg_spmv},
+    /* 10 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
+    /* 11 */ {"sumsq", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_sumsq, l_sumsq, cfg_block_any},
+    /* 12 */ {"scale_l2", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_scale, l_scale, cfg_block_any},
+    /* 13 */ {"spin", 0, 0x0, sizeof(dag_p_spin), {64, 0, 0}, v_spin, l_spin, cfg_spin},
+    /* 14 */ {"copy_f32", 2, 0x2, sizeof(dag_p_n), {256, 0, 0}, v_copy, l_copy, cfg_block_any},
+};
+
+}  // namespace
+
+const KernelDesc* builtin_kernel(uint32_t id) {
+  if (id >= sizeof(kTable) / sizeof(kTable[0])) return nullptr;
+  return kTable[id].name ? &kTable[id] : nullptr;
+}
+
+void set_wall_clock_khz(uint64_t khz) {
+  if (khz) g_wall_khz = khz;
+}
+
+}  // namespace dagrt

@@ -1,0 +1,42 @@
+// Built-in task kernels: host-side descriptors (argument checks + launch).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dagrt {
+
+struct LaunchCfg {
+  uint32_t block;
+  uint32_t grid_cap;
+  uint32_t variant;
+};
+
+struct KernelDesc {
+  const char* name;
+  uint32_t nargs;       // exact argument count (0 = any number)
+  uint32_t write_mask;  // bit i: argument i is modified by the kernel
+  size_t params_bytes;
+  LaunchCfg def;
+  // nullptr when the call is valid; otherwise a static message.
+  const char* (*validate)(const void* params, const size_t* sizes, uint32_t nargs,
+                          const LaunchCfg& cfg, size_t scratch_bytes);
+  hipError_t (*launch)(hipStream_t s, void* const* ptrs, const void* params,
+                       const LaunchCfg& cfg, void* scratch, size_t scratch_bytes);
+  const char* (*check_cfg)(const LaunchCfg& cfg);
+};
+
+// nullptr for unknown ids.
+const KernelDesc* builtin_kernel(uint32_t id);
+
+// Device wall-clock frequency in kHz (for the spin kernel); set once.
+void set_wall_clock_khz(uint64_t khz);
+
+// Scratch layout shared by the reduction kernels: a 32-bit ticket counter at
+// offset 0 (zero between launches: the last workgroup resets it) and
+// per-workgroup partials from offset 256.
+constexpr size_t kScratchPartialsOffset = 256;
+
+}  // namespace dagrt

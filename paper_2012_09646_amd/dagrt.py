@@ -1,0 +1,448 @@
+"""ctypes binding of the C ABI declared in include/dagrt.h.
+
+Every ``dag_*`` function of the header is exposed under the same name and
+with the same arguments; these wrappers only marshal arguments and turn a
+non-zero status into :class:`DagError`.  :class:`Context` is a small
+convenience layer over the same calls.  All scheduling and all device work
+happen in the native library (``_lib/libdagrt.so``); if it has not been
+built this module raises instead of falling back to anything else.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libdagrt.so")
+
+# ---- constants (mirror include/dagrt.h) --------------------------------------
+DAG_OK = 0
+STATUS = {0: "DAG_OK", -1: "DAG_E_INVAL", -2: "DAG_E_ALIAS", -3: "DAG_E_NOMEM", -4: "DAG_E_HIP",
+          -5: "DAG_E_POISONED", -6: "DAG_E_BUSY", -7: "DAG_E_UNSUPPORTED", -8: "DAG_E_NOTFOUND",
+          -9: "DAG_E_RANGE"}
+DAG_CONST, DAG_MUTABLE = 0, 1
+DAG_DEVICE, DAG_PINNED_HOST = 0, 1
+DAG_SERIAL_SYNC, DAG_PARALLEL_ASYNC = 0, 1
+DAG_EDGE_RAW, DAG_EDGE_WAR, DAG_EDGE_WAW = 0, 1, 2
+(DAG_TASK_KERNEL, DAG_TASK_COPY, DAG_TASK_HOST_READ, DAG_TASK_HOST_WRITE, DAG_TASK_SYNC,
+ DAG_TASK_REGION, DAG_TASK_RELEASE) = range(7)
+DAG_MAX_STREAMS = 64
+DAG_K_USER_BASE = 1000
+
+KERNEL_IDS = {
+    "vec_square": 1, "vec_sum_diff": 2, "bs_call": 3, "gauss_blur": 4, "sobel": 5,
+    "minmax": 6, "normalise": 7, "unsharp_combine": 8, "spmv": 9, "sumsq": 11,
+    "scale_l2": 12, "spin": 13, "copy_f32": 14,
+}
+KERNEL_NAMES = {v: k for k, v in KERNEL_IDS.items()}
+
+
+class dag_config(C.Structure):
+    _fields_ = [("policy", C.c_uint32), ("max_streams", C.c_uint32), ("trace", C.c_uint32),
+                ("dry_run", C.c_uint32), ("device", C.c_int32), ("graph_mode", C.c_uint32),
+                ("scratch_bytes", C.c_uint64)]
+
+
+class dag_arg(C.Structure):
+    _fields_ = [("buf", C.c_uint32), ("mode", C.c_uint32)]
+
+
+class dag_edge(C.Structure):
+    _fields_ = [("src", C.c_uint64), ("dst", C.c_uint64), ("buf", C.c_uint32), ("kind", C.c_uint32)]
+
+
+class dag_task_info(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("stream", C.c_int32), ("vertex", C.c_uint32),
+                ("active", C.c_uint32), ("nparents", C.c_uint32), ("nwaits", C.c_uint32),
+                ("kernel_id", C.c_uint32), ("reserved", C.c_uint32),
+                ("t_start_ms", C.c_double), ("t_end_ms", C.c_double)]
+
+
+class dag_stats(C.Structure):
+    _fields_ = [("tasks", C.c_uint64), ("vertices", C.c_uint64), ("edges", C.c_uint64),
+                ("waits", C.c_uint64), ("host_waits", C.c_uint64), ("streams", C.c_uint32),
+                ("active", C.c_uint32), ("submit_host_us", C.c_double),
+                ("launch_host_us", C.c_double)]
+
+
+class dag_launch(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("grid_cap", C.c_uint32), ("variant", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class dag_op(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("kernel_id", C.c_uint32), ("params", C.c_void_p),
+                ("params_bytes", C.c_size_t), ("args", C.POINTER(dag_arg)), ("nargs", C.c_uint32),
+                ("dst", C.c_uint32), ("src", C.c_uint32), ("reserved", C.c_uint32),
+                ("dst_off", C.c_size_t), ("src_off", C.c_size_t), ("bytes", C.c_size_t),
+                ("host", C.c_void_p)]
+
+
+class dag_p_n(C.Structure):
+    _fields_ = [("n", C.c_uint64)]
+
+
+class dag_p_bs(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("strike", C.c_double), ("rate", C.c_double),
+                ("vol", C.c_double), ("years", C.c_double)]
+
+
+class dag_p_img(C.Structure):
+    _fields_ = [("w", C.c_uint32), ("h", C.c_uint32), ("ksize", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class dag_p_csr(C.Structure):
+    _fields_ = [("nrows", C.c_uint32), ("ncols", C.c_uint32), ("nnz", C.c_uint64)]
+
+
+class dag_p_spin(C.Structure):
+    _fields_ = [("ns", C.c_uint64)]
+
+
+DAG_LAUNCH_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p,
+                            C.c_void_p)
+
+_ctx_t = C.c_void_p
+_st = C.c_int32
+_P = C.POINTER
+_SIGS = {
+    "dag_create": (_st, [_P(dag_config), _P(_ctx_t)]),
+    "dag_destroy": (_st, [_ctx_t]),
+    "dag_last_error": (C.c_char_p, [_ctx_t]),
+    "dag_status_string": (C.c_char_p, [_st]),
+    "dag_buffer_register": (_st, [_ctx_t, C.c_void_p, C.c_size_t, C.c_uint32, _P(C.c_uint32)]),
+    "dag_buffer_alloc": (_st, [_ctx_t, C.c_size_t, C.c_uint32, _P(C.c_uint32)]),
+    "dag_buffer_release": (_st, [_ctx_t, C.c_uint32]),
+    "dag_buffer_ptr": (_st, [_ctx_t, C.c_uint32, _P(C.c_void_p), _P(C.c_size_t)]),
+    "dag_kernel_get_launch": (_st, [_ctx_t, C.c_uint32, _P(dag_launch)]),
+    "dag_kernel_set_launch": (_st, [_ctx_t, C.c_uint32, _P(dag_launch)]),
+    "dag_kernel_register": (_st, [_ctx_t, C.c_char_p, DAG_LAUNCH_FN, C.c_void_p, _P(C.c_uint32)]),
+    "dag_submit_kernel": (_st, [_ctx_t, C.c_uint32, C.c_void_p, C.c_size_t, _P(dag_arg), C.c_uint32,
+                                _P(C.c_uint64)]),
+    "dag_submit_copy": (_st, [_ctx_t, C.c_uint32, C.c_size_t, C.c_uint32, C.c_size_t, C.c_size_t,
+                              _P(C.c_uint64)]),
+    "dag_host_read": (_st, [_ctx_t, C.c_uint32, C.c_size_t, C.c_void_p, C.c_size_t, _P(C.c_uint64)]),
+    "dag_host_write": (_st, [_ctx_t, C.c_uint32, C.c_size_t, C.c_void_p, C.c_size_t, _P(C.c_uint64)]),
+    "dag_sync": (_st, [_ctx_t]),
+    "dag_submit_batch": (_st, [_ctx_t, _P(dag_op), C.c_uint32, _P(C.c_uint64), _P(C.c_uint32)]),
+    "dag_region_begin": (_st, [_ctx_t, C.c_uint64]),
+    "dag_region_end": (_st, [_ctx_t]),
+    "dag_region_launch": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint64)]),
+    "dag_region_info": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint32), _P(C.c_uint32)]),
+    "dag_region_drop": (_st, [_ctx_t, C.c_uint64]),
+    "dag_edges": (_st, [_ctx_t, _P(dag_edge), C.c_size_t, _P(C.c_size_t)]),
+    "dag_task_waits": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint64), C.c_uint32, _P(C.c_uint32)]),
+    "dag_task_get_info": (_st, [_ctx_t, C.c_uint64, _P(dag_task_info)]),
+    "dag_get_stats": (_st, [_ctx_t, _P(dag_stats)]),
+    "dag_trace_reset": (_st, [_ctx_t]),
+    "dag_stream_handle": (_st, [_ctx_t, C.c_uint32, _P(C.c_void_p)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdagrt.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdagrt.so is not built (python -m paper_2012_09646_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DagError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+def _check(ctx, st):
+    if st != DAG_OK:
+        m = lib().dag_last_error(ctx)
+        raise DagError(st, m.decode() if m else "")
+
+
+# ---- raw wrappers, one per C function ------------------------------------------
+def dag_create(cfg=None):
+    h = C.c_void_p()
+    st = lib().dag_create(C.byref(cfg) if cfg is not None else None, C.byref(h))
+    if st != DAG_OK:
+        raise DagError(st, "dag_create failed")
+    return h
+
+
+def dag_destroy(ctx):
+    _check(None, lib().dag_destroy(ctx))
+
+
+def dag_last_error(ctx):
+    return lib().dag_last_error(ctx).decode()
+
+
+def dag_status_string(st):
+    return lib().dag_status_string(st).decode()
+
+
+def dag_buffer_register(ctx, ptr, nbytes, loc):
+    out = C.c_uint32()
+    _check(ctx, lib().dag_buffer_register(ctx, C.c_void_p(ptr), nbytes, loc, C.byref(out)))
+    return out.value
+
+
+def dag_buffer_alloc(ctx, nbytes, loc):
+    out = C.c_uint32()
+    _check(ctx, lib().dag_buffer_alloc(ctx, nbytes, loc, C.byref(out)))
+    return out.value
+
+
+def dag_buffer_release(ctx, buf):
+    _check(ctx, lib().dag_buffer_release(ctx, buf))
+
+
+def dag_buffer_ptr(ctx, buf):
+    p, n = C.c_void_p(), C.c_size_t()
+    _check(ctx, lib().dag_buffer_ptr(ctx, buf, C.byref(p), C.byref(n)))
+    return p.value, n.value
+
+
+def dag_kernel_get_launch(ctx, kid):
+    out = dag_launch()
+    _check(ctx, lib().dag_kernel_get_launch(ctx, kid, C.byref(out)))
+    return out
+
+
+def dag_kernel_set_launch(ctx, kid, cfg):
+    _check(ctx, lib().dag_kernel_set_launch(ctx, kid, C.byref(cfg)))
+
+
+def dag_kernel_register(ctx, name, fn, user=None):
+    kid = C.c_uint32()
+    _check(ctx, lib().dag_kernel_register(ctx, name.encode(), fn, user, C.byref(kid)))
+    return kid.value
+
+
+def _args_array(args):
+    arr = (dag_arg * max(len(args), 1))()
+    for i, (b, m) in enumerate(args):
+        arr[i].buf = b
+        arr[i].mode = m
+    return arr
+
+
+def dag_submit_kernel(ctx, kid, params, args):
+    """params: a ctypes parameter struct (or None); args: [(buf, mode)]."""
+    arr = _args_array(args)
+    out = C.c_uint64()
+    pp = C.byref(params) if params is not None else None
+    pb = C.sizeof(params) if params is not None else 0
+    _check(ctx, lib().dag_submit_kernel(ctx, kid, pp, pb, arr, len(args), C.byref(out)))
+    return out.value
+
+
+def dag_submit_copy(ctx, dst, dst_off, src, src_off, nbytes):
+    out = C.c_uint64()
+    _check(ctx, lib().dag_submit_copy(ctx, dst, dst_off, src, src_off, nbytes, C.byref(out)))
+    return out.value
+
+
+def _host_ptr(arr):
+    if arr is None:
+        return None
+    if not isinstance(arr, np.ndarray) or not arr.flags["C_CONTIGUOUS"]:
+        raise ValueError("host buffer must be a C-contiguous numpy array")
+    return arr.ctypes.data
+
+
+def dag_host_read(ctx, buf, off=0, host_dst=None, nbytes=0):
+    out = C.c_uint64()
+    _check(ctx, lib().dag_host_read(ctx, buf, off, _host_ptr(host_dst), nbytes, C.byref(out)))
+    return out.value
+
+
+def dag_host_write(ctx, buf, off, host_src, nbytes):
+    out = C.c_uint64()
+    _check(ctx, lib().dag_host_write(ctx, buf, off, _host_ptr(host_src), nbytes, C.byref(out)))
+    return out.value
+
+
+def dag_sync(ctx):
+    _check(ctx, lib().dag_sync(ctx))
+
+
+def dag_submit_batch(ctx, ops):
+    """ops: a ctypes array of dag_op (see Batch).  Returns the task ids."""
+    n = len(ops)
+    ids = (C.c_uint64 * max(n, 1))()
+    done = C.c_uint32()
+    _check(ctx, lib().dag_submit_batch(ctx, ops, n, ids, C.byref(done)))
+    return list(ids[:n])
+
+
+def dag_region_begin(ctx, key):
+    _check(ctx, lib().dag_region_begin(ctx, key))
+
+
+def dag_region_end(ctx):
+    _check(ctx, lib().dag_region_end(ctx))
+
+
+def dag_region_launch(ctx, key):
+    out = C.c_uint64()
+    _check(ctx, lib().dag_region_launch(ctx, key, C.byref(out)))
+    return out.value
+
+
+def dag_region_info(ctx, key):
+    a, b = C.c_uint32(), C.c_uint32()
+    _check(ctx, lib().dag_region_info(ctx, key, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def dag_region_drop(ctx, key):
+    _check(ctx, lib().dag_region_drop(ctx, key))
+
+
+def dag_edges(ctx):
+    n = C.c_size_t()
+    _check(ctx, lib().dag_edges(ctx, None, 0, C.byref(n)))
+    arr = (dag_edge * max(n.value, 1))()
+    _check(ctx, lib().dag_edges(ctx, arr, n.value, C.byref(n)))
+    return [(e.src, e.dst, e.buf, e.kind) for e in arr[:n.value]]
+
+
+def dag_task_waits(ctx, t):
+    n = C.c_uint32()
+    _check(ctx, lib().dag_task_waits(ctx, t, None, 0, C.byref(n)))
+    arr = (C.c_uint64 * max(n.value, 1))()
+    _check(ctx, lib().dag_task_waits(ctx, t, arr, n.value, C.byref(n)))
+    return list(arr[:n.value])
+
+
+def dag_task_get_info(ctx, t):
+    out = dag_task_info()
+    _check(ctx, lib().dag_task_get_info(ctx, t, C.byref(out)))
+    return out
+
+
+def dag_get_stats(ctx):
+    out = dag_stats()
+    _check(ctx, lib().dag_get_stats(ctx, C.byref(out)))
+    return out
+
+
+def dag_trace_reset(ctx):
+    _check(ctx, lib().dag_trace_reset(ctx))
+
+
+def dag_stream_handle(ctx, i):
+    out = C.c_void_p()
+    _check(ctx, lib().dag_stream_handle(ctx, i, C.byref(out)))
+    return out.value
+
+
+# ---- parameter blocks ------------------------------------------------------------
+def make_params(kernel, p):
+    """ctypes parameter block of a built-in kernel from a dict of values."""
+    if kernel in ("vec_square", "vec_sum_diff", "minmax", "normalise", "unsharp_combine",
+                  "sumsq", "scale_l2", "copy_f32"):
+        return dag_p_n(int(p["n"]))
+    if kernel == "bs_call":
+        return dag_p_bs(int(p["n"]), float(p["K"]), float(p["r"]), float(p["sigma"]), float(p["T"]))
+    if kernel in ("gauss_blur", "sobel"):
+        return dag_p_img(int(p["w"]), int(p["h"]), int(p.get("ksize", 0)), 0)
+    if kernel == "spmv":
+        return dag_p_csr(int(p["nrows"]), int(p["ncols"]), int(p["nnz"]))
+    if kernel == "spin":
+        return dag_p_spin(int(p.get("ns", 0)))
+    raise KeyError(kernel)
+
+
+class Context:
+    """Convenience wrapper: one execution context with its buffers."""
+
+    def __init__(self, policy=DAG_PARALLEL_ASYNC, max_streams=8, trace=False, dry_run=False,
+                 device=0, graph_mode=0, scratch_bytes=0):
+        self.cfg = dag_config(policy, max_streams, int(bool(trace)), int(bool(dry_run)), device,
+                              graph_mode, scratch_bytes)
+        self.h = dag_create(self.cfg)
+
+    def close(self):
+        if self.h:
+            dag_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # buffers
+    def alloc(self, nbytes, loc=DAG_DEVICE):
+        return dag_buffer_alloc(self.h, int(nbytes), loc)
+
+    def register(self, ptr, nbytes, loc=DAG_DEVICE):
+        return dag_buffer_register(self.h, ptr, int(nbytes), loc)
+
+    def release(self, buf):
+        dag_buffer_release(self.h, buf)
+
+    def ptr(self, buf):
+        return dag_buffer_ptr(self.h, buf)
+
+    # calls
+    def kernel(self, kernel, args, **params):
+        kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else kernel
+        prm = make_params(KERNEL_NAMES.get(kid, ""), params) if kid in KERNEL_NAMES else params.get("params")
+        return dag_submit_kernel(self.h, kid, prm, [(b, DAG_MUTABLE if m in ("m", 1) else DAG_CONST)
+                                                    for b, m in args])
+
+    def copy(self, dst, src, nbytes, dst_off=0, src_off=0):
+        return dag_submit_copy(self.h, dst, dst_off, src, src_off, int(nbytes))
+
+    def host_read(self, buf, out=None, off=0):
+        return dag_host_read(self.h, buf, off, out, 0 if out is None else out.nbytes)
+
+    def host_write(self, buf, data, off=0):
+        data = np.ascontiguousarray(data)
+        return dag_host_write(self.h, buf, off, data, data.nbytes)
+
+    def sync(self):
+        dag_sync(self.h)
+
+    # introspection
+    def edges(self):
+        return dag_edges(self.h)
+
+    def waits(self, t):
+        return dag_task_waits(self.h, t)
+
+    def info(self, t):
+        return dag_task_get_info(self.h, t)
+
+    def stats(self):
+        return dag_get_stats(self.h)
+
+    def set_launch(self, kernel, block, grid_cap=0, variant=0):
+        kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else kernel
+        dag_kernel_set_launch(self.h, kid, dag_launch(block, grid_cap, variant, 0))
+
+    def get_launch(self, kernel):
+        kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else kernel
+        l = dag_kernel_get_launch(self.h, kid)
+        return l.block, l.grid_cap, l.variant

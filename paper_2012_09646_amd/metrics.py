@@ -1,0 +1,127 @@
+"""Measurement helpers over task intervals and the DAG.
+
+critical_path  contention-free bound (paper Sec. V-E): the longest path of
+               the DAG when every task takes its isolated time, i.e. the time
+               it takes alone on the whole GPU (measured under the serial
+               policy).
+overlap        the four overlap figures of Sec. V-F over an execution
+               timeline: CT (share of kernel time overlapping any transfer),
+               TC (share of transfer time overlapping any kernel), CC (share
+               of kernel time overlapping another kernel) and TOT (share of
+               all busy time overlapping any other operation; an interval that
+               overlaps several others is counted once, via the union).
+"""
+
+
+def critical_path(n, edges, weight):
+    """Longest weighted path.  n tasks at positions 1..n, edges (src, dst)
+    with src < dst, weight[pos] >= 0 (missing = 0).  Returns (length, path)."""
+    parents = {}
+    for s, d in edges:
+        parents.setdefault(d, []).append(s)
+    best = [0.0] * (n + 1)
+    prev = [0] * (n + 1)
+    for j in range(1, n + 1):
+        w = float(weight.get(j, 0.0))
+        b, arg = 0.0, 0
+        for p in parents.get(j, ()):
+            if best[p] > b:
+                b, arg = best[p], p
+        best[j] = b + w
+        prev[j] = arg
+    end = max(range(1, n + 1), key=lambda j: best[j]) if n else 0
+    path = []
+    j = end
+    while j:
+        path.append(j)
+        j = prev[j]
+    return (best[end] if n else 0.0), path[::-1]
+
+
+def _union(iv):
+    out = []
+    for a, b in sorted(iv):
+        if b <= a:
+            continue
+        if out and a <= out[-1][1]:
+            out[-1][1] = max(out[-1][1], b)
+        else:
+            out.append([a, b])
+    return out
+
+
+def _covered(a, b, union):
+    """Length of [a, b) covered by a sorted disjoint interval list."""
+    tot = 0.0
+    for x, y in union:
+        lo, hi = max(a, x), min(b, y)
+        if hi > lo:
+            tot += hi - lo
+    return tot
+
+
+def overlap(intervals):
+    """intervals: list of (kind, start, end) with kind 'C' (kernel) or 'T'
+    (transfer).  Returns dict CT, TC, CC, TOT in [0, 1] (None when the
+    denominator is empty)."""
+    ks = [(a, b) for k, a, b in intervals if k == "C"]
+    ts = [(a, b) for k, a, b in intervals if k == "T"]
+    allv = ks + ts
+    uk, ut = _union(ks), _union(ts)
+
+    def frac(num, den):
+        return None if den <= 0 else num / den
+
+    def self_excl(items, idx_pool):
+        num = 0.0
+        for i, (a, b) in enumerate(items):
+            others = _union([iv for j, iv in enumerate(idx_pool) if j != i])
+            num += _covered(a, b, others)
+        return num
+
+    len_k = sum(b - a for a, b in ks)
+    len_t = sum(b - a for a, b in ts)
+    ct = frac(sum(_covered(a, b, ut) for a, b in ks), len_k)
+    tc = frac(sum(_covered(a, b, uk) for a, b in ts), len_t)
+    cc = frac(self_excl(ks, ks), len_k)
+    tot = frac(self_excl(allv, allv), len_k + len_t)
+    return {"CT": ct, "TC": tc, "CC": cc, "TOT": tot}
+
+
+def percentile(values, q):
+    """Nearest-rank percentile (q in (0, 100])."""
+    v = sorted(values)
+    if not v:
+        return None
+    import math
+    k = max(1, int(math.ceil(q / 100.0 * len(v))))
+    return v[k - 1]
+
+
+def algorithmic_bytes(kernel, p):
+    """Compulsory HBM bytes of one launch of a built-in kernel: every input
+    read once, every output written once (CSR SpMV: the matrix, one read of x
+    and one write of y)."""
+    if kernel == "vec_square":
+        return 8 * p["n"]
+    if kernel == "vec_sum_diff":
+        return 8 * p["n"] + 4
+    if kernel == "bs_call":
+        return 8 * p["n"]
+    if kernel in ("gauss_blur", "sobel"):
+        return 8 * p["w"] * p["h"]
+    if kernel == "minmax":
+        return 4 * p["n"] + 8
+    if kernel == "normalise":
+        return 8 * p["n"] + 8
+    if kernel == "unsharp_combine":
+        return 32 * p["n"]
+    if kernel == "spmv":
+        return 4 * (p["nrows"] + 1) + 8 * p["nnz"] + 4 * p["ncols"] + 4 * p["nrows"]
+    if kernel == "sumsq":
+        return 4 * p["n"] + 8
+    if kernel == "scale_l2":
+        return 8 * p["n"] + 8
+    if kernel == "copy_f32":
+        return 8 * p["n"]
+    return 0

@@ -57,3 +57,23 @@ def load_cases():
             elif key == "waits":
                 cur["waits"] = [[] if t == "-" else [int(x) for x in t.split(",")] for t in toks]
     return cases
+
+
+def random_program(rnd, n_ops, n_bufs, host=True):
+    """Random program over n_bufs buffers: kernels with 1-4 args of random
+    modes, interleaved host reads / writes and syncs."""
+    bufs = ["b%d" % i for i in range(n_bufs)]
+    ops = []
+    for _ in range(n_ops):
+        r = rnd.random()
+        if host and r < 0.1:
+            ops.append({"kind": "host_read", "buf": rnd.choice(bufs)})
+        elif host and r < 0.15:
+            ops.append({"kind": "host_write", "buf": rnd.choice(bufs)})
+        elif host and r < 0.17:
+            ops.append({"kind": "sync"})
+        else:
+            k = rnd.randint(1, 4)
+            args = [(rnd.choice(bufs), rnd.choice("cm")) for _ in range(k)]
+            ops.append({"kind": "kernel", "kernel": "spin", "params": {}, "args": args})
+    return ops

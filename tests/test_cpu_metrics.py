@@ -1,0 +1,44 @@
+"""Pins of the measurement helpers on hand-computed cases (CPU only)."""
+
+from paper_2012_09646_amd import metrics as M
+
+
+def test_critical_path_diamond():
+    # VEC diamond: 1 -> 3, 2 -> 3; weights 2, 5, 1 -> path 2,3 = 6
+    length, path = M.critical_path(3, [(1, 3), (2, 3)], {1: 2.0, 2: 5.0, 3: 1.0})
+    assert length == 6.0 and path == [2, 3]
+
+
+def test_critical_path_chain_and_isolated():
+    length, path = M.critical_path(5, [(1, 2), (2, 4)], {1: 1, 2: 1, 3: 10, 4: 1, 5: 0.5})
+    assert length == 10 and path == [3]
+    length, path = M.critical_path(5, [(1, 2), (2, 4), (3, 4)], {1: 1, 2: 1, 3: 10, 4: 1, 5: 0.5})
+    assert length == 11 and path == [3, 4]
+    assert M.critical_path(0, [], {}) == (0.0, [])
+
+
+def test_overlap_hand_values():
+    # kernel [0,10), transfer [5,15), kernel [8,12)
+    iv = [("C", 0, 10), ("T", 5, 15), ("C", 8, 12)]
+    o = M.overlap(iv)
+    # CT: kernel1 overlaps T on [5,10) = 5, kernel2 on [8,12) = 4 -> 9 / 14
+    assert abs(o["CT"] - 9 / 14) < 1e-12
+    # TC: T overlaps union of kernels [0,12) on [5,12) = 7 -> 7/10
+    assert abs(o["TC"] - 0.7) < 1e-12
+    # CC: k1 overlaps k2 on [8,10) = 2; k2 overlaps k1 on [8,10) = 2 -> 4/14
+    assert abs(o["CC"] - 4 / 14) < 1e-12
+    # TOT: k1 vs union(T,k2)=[5,15): 5; T vs union(k1,k2)=[0,12): 7; k2 vs [0,15): 4 -> 16/24
+    assert abs(o["TOT"] - 16 / 24) < 1e-12
+
+
+def test_overlap_serial_timeline_is_zero():
+    iv = [("T", 0, 1), ("C", 1, 2), ("T", 2, 3), ("C", 3.5, 4)]
+    o = M.overlap(iv)
+    assert o == {"CT": 0.0, "TC": 0.0, "CC": 0.0, "TOT": 0.0}
+    assert M.overlap([("C", 0, 1)])["CT"] == 0.0 and M.overlap([("C", 0, 1)])["TC"] is None
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert M.percentile(v, 50) == 50 and M.percentile(v, 99) == 99 and M.percentile(v, 100) == 100
+    assert M.percentile([3, 1, 2], 50) == 2

@@ -1,0 +1,205 @@
+"""The native scheduler in schedule-only mode (no GPU: dry_run makes no HIP
+call) against the oracle: edges, streams and event waits must be identical.
+Also the C-ABI's argument checks and error conventions."""
+
+import random
+
+import numpy as np
+import pytest
+
+import dagcases
+from oracle import dag as odag
+from paper_2012_09646_amd import dagrt as D
+from paper_2012_09646_amd import runner
+from paper_2012_09646_amd import workloads as W
+
+
+def run_dry(ops, max_streams):
+    ctx = D.Context(dry_run=True, max_streams=max_streams)
+    names = sorted({b for op in ops for b in
+                    ([a for a, _ in op["args"]] if op["kind"] in ("kernel", "macro") else
+                     [op["buf"]] if op["kind"] in ("host_read", "host_write") else [])})
+    h = {n: ctx.alloc(256) for n in names}
+    name_of = {v: k for k, v in h.items()}
+    ids = []
+    for op in ops:
+        k = op["kind"]
+        if k in ("kernel", "macro"):
+            ids.append(ctx.kernel("spin", [(h[b], m) for b, m in op["args"]], ns=0))
+        elif k == "host_read":
+            ids.append(D.dag_host_read(ctx.h, h[op["buf"]]))
+        elif k == "host_write":
+            ids.append(D.dag_host_write(ctx.h, h[op["buf"]], 0, None, 0))
+        elif k == "sync":
+            ctx.sync()
+            ids.append(ctx.stats().tasks)
+    assert ids == list(range(1, len(ops) + 1))
+    edges = {(s, d, name_of[b], kd) for s, d, b, kd in ctx.edges()}
+    streams = {}
+    waits = {}
+    for i in ids:
+        inf = ctx.info(i)
+        if inf.stream >= 0:
+            streams[i] = inf.stream
+            waits[i] = ctx.waits(i)
+    return ctx, edges, streams, waits
+
+
+def check_against_oracle(ops, max_streams):
+    g = odag.build_dag(ops)
+    st, wt = odag.replay_streams(ops, g, max_streams)
+    ctx, edges, streams, waits = run_dry(ops, max_streams)
+    assert edges == g.edges
+    assert streams == st
+    assert waits == {k: v for k, v in wt.items()}
+    for i in range(1, len(ops) + 1):
+        inf = ctx.info(i)
+        assert bool(inf.vertex) == g.vertex[i]
+        assert bool(inf.active) == (i not in g.retired_by and ops[i - 1]["kind"] == "kernel")
+    ctx.close()
+
+
+CASES = dagcases.load_cases()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_golden_cases_native(case):
+    check_against_oracle(case["ops"], case["max_streams"])
+
+
+@pytest.mark.parametrize("seed", range(150))
+def test_random_programs_native(seed):
+    rnd = random.Random(1000 + seed)
+    ops = dagcases.random_program(rnd, rnd.randint(3, 45), rnd.randint(1, 6))
+    check_against_oracle(ops, rnd.choice([1, 2, 3, 4, 8, 64]))
+
+
+def test_many_readers_compaction():
+    # long read-only runs with periodic host reads exercise reader-list compaction
+    ops = []
+    for i in range(120):
+        ops.append({"kind": "kernel", "kernel": "spin", "params": {},
+                    "args": [("A", "c"), ("B%d" % (i % 5), "m")]})
+        if i % 17 == 3:
+            ops.append({"kind": "host_read", "buf": "B%d" % (i % 5)})
+    ops.append({"kind": "kernel", "kernel": "spin", "params": {}, "args": [("A", "m")]})
+    check_against_oracle(ops, 8)
+
+
+@pytest.mark.parametrize("maker,pool", [
+    (lambda: W.vec_program(n=64), 8),
+    (lambda: W.bs_program(n=64, tasks=10), 4),
+    (lambda: W.bs_program(n=64, tasks=10), 16),
+    (lambda: W.img_program(side=16), 8),
+    (lambda: W.hits_program(n=64, deg=4, iters=10), 8),
+    (lambda: W.hits_program(n=64, deg=4, iters=3), 1),
+])
+def test_workload_programs_native(maker, pool):
+    prog = maker()
+    g = odag.build_dag(prog.ops)
+    st, wt = odag.replay_streams(prog.ops, g, pool)
+    ctx = D.Context(dry_run=True, max_streams=pool)
+    b = runner.Bound(ctx, prog, upload=False)
+    b.run()
+    assert b.edges() == g.edges
+    assert b.streams() == st
+    assert {k: v for k, v in b.waits().items() if k in st} == wt
+    # the single-call path gives the same DAG as the batched one
+    ctx2 = D.Context(dry_run=True, max_streams=pool)
+    b2 = runner.Bound(ctx2, prog, upload=False)
+    b2.run_calls()
+    assert b2.edges() == g.edges and b2.streams() == st
+    ctx.close()
+    ctx2.close()
+
+
+def test_region_replay_is_one_task_with_union_access():
+    ctx = D.Context(dry_run=True)
+    x, y, z = ctx.alloc(64), ctx.alloc(64), ctx.alloc(64)
+    D.dag_region_begin(ctx.h, 7)
+    t1 = ctx.kernel("spin", [(x, "c"), (y, "m")], ns=0)
+    t2 = ctx.kernel("spin", [(y, "c"), (z, "m")], ns=0)
+    D.dag_region_end(ctx.h)
+    assert D.dag_region_info(ctx.h, 7) == (2, 1)
+    t3 = D.dag_region_launch(ctx.h, 7)
+    t4 = ctx.kernel("spin", [(z, "c")], ns=0)
+    ops = [{"kind": "kernel", "args": [("x", "c"), ("y", "m")]},
+           {"kind": "kernel", "args": [("y", "c"), ("z", "m")]},
+           {"kind": "macro", "args": [("x", "c"), ("y", "m"), ("z", "m")]},
+           {"kind": "kernel", "args": [("z", "c")]}]
+    g = odag.build_dag(ops)
+    name_of = {x: "x", y: "y", z: "z"}
+    assert {(s, d, name_of[b], k) for s, d, b, k in ctx.edges()} == g.edges
+    assert (t1, t2, t3, t4) == (1, 2, 3, 4)
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# argument checks and error conventions
+# ---------------------------------------------------------------------------
+def _status(fn, *a, **k):
+    try:
+        fn(*a, **k)
+    except D.DagError as e:
+        return e.name
+    return "DAG_OK"
+
+
+def test_error_paths():
+    ctx = D.Context(dry_run=True)
+    x = ctx.alloc(4 * 100)
+    r = ctx.alloc(4)
+    p = ctx.alloc(400, D.DAG_PINNED_HOST)
+    # unknown handle, bad mode, written argument passed as const
+    assert _status(ctx.kernel, "vec_square", [(999, "m")], n=100) == "DAG_E_INVAL"
+    assert _status(ctx.kernel, "vec_square", [(x, "c")], n=100) == "DAG_E_INVAL"
+    # buffer too small for n, wrong arity, pinned host argument
+    assert _status(ctx.kernel, "vec_square", [(x, "m")], n=101) == "DAG_E_INVAL"
+    assert _status(ctx.kernel, "vec_sum_diff", [(x, "c"), (x, "c")], n=100) == "DAG_E_INVAL"
+    assert _status(ctx.kernel, "vec_square", [(p, "m")], n=100) == "DAG_E_INVAL"
+    assert _status(D.dag_submit_kernel, ctx.h, 77, None, []) == "DAG_E_NOTFOUND"
+    # copies out of range
+    assert _status(ctx.copy, x, p, 401) == "DAG_E_INVAL"
+    assert _status(ctx.copy, x, x, 8, 0, 4) == "DAG_E_INVAL"
+    # none of the failures consumed a task id
+    t = ctx.kernel("vec_square", [(x, "m")], n=100)
+    assert t == 1
+    # aliasing registrations
+    base, nbytes = ctx.ptr(x)
+    assert _status(ctx.register, base + 16, 8) == "DAG_E_ALIAS"
+    assert _status(ctx.register, base - 8, 16) == "DAG_E_ALIAS"
+    ok = ctx.register(base + nbytes + (1 << 20), 8)
+    assert ok > 0
+    # host access / sync inside a region
+    D.dag_region_begin(ctx.h, 1)
+    assert _status(D.dag_host_read, ctx.h, r) == "DAG_E_BUSY"
+    assert _status(ctx.sync) == "DAG_E_BUSY"
+    assert _status(D.dag_region_begin, ctx.h, 2) == "DAG_E_BUSY"
+    assert _status(D.dag_region_end, ctx.h) == "DAG_E_INVAL"  # empty region
+    assert _status(D.dag_region_launch, ctx.h, 5) == "DAG_E_NOTFOUND"
+    # released handles are invalid
+    ctx.release(x)
+    assert _status(ctx.kernel, "vec_square", [(x, "m")], n=100) == "DAG_E_INVAL"
+    # launch configuration checks
+    assert _status(ctx.set_launch, "vec_square", 96) == "DAG_E_INVAL"
+    assert _status(ctx.set_launch, "spmv", 256, 0, 5) == "DAG_E_INVAL"
+    ctx.set_launch("vec_square", 512, 64)
+    assert ctx.get_launch("vec_square") == (512, 64, 0)
+    ctx.close()
+
+
+def test_bad_config_rejected():
+    with pytest.raises(D.DagError):
+        D.Context(dry_run=True, max_streams=65)
+    with pytest.raises(D.DagError):
+        D.Context(dry_run=True, policy=7)
+
+
+def test_serial_policy_computes_no_dependencies():
+    ctx = D.Context(dry_run=True, policy=D.DAG_SERIAL_SYNC)
+    x = ctx.alloc(64)
+    ctx.kernel("spin", [(x, "m")], ns=0)
+    ctx.kernel("spin", [(x, "m")], ns=0)
+    assert ctx.edges() == []
+    assert ctx.info(1).stream == ctx.info(2).stream == 0
+    ctx.close()

@@ -1,0 +1,103 @@
+"""GPU parity: every workload program run through the C ABI on the MI355X
+equals the CPU oracle (bit-exact for squares and min/max, 1e-5 relative for
+fp32 outputs), with the DAG and the stream assignment identical."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import gpu_util as G
+from oracle import tasks as T
+from paper_2012_09646_amd import dagrt as D
+from paper_2012_09646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def banner(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n", [1, 5, 4096, (1 << 16) + 3, 1 << 20])
+def test_vec(n):
+    banner("vec n=%d" % n)
+    G.check_program(W.vec_program(n=n, seed=n))
+
+
+@pytest.mark.parametrize("n,tasks", [(7, 2), (100003, 3), (1 << 22, 10)])
+def test_bs(n, tasks):
+    banner("bs n=%d tasks=%d" % (n, tasks))
+    G.check_program(W.bs_program(n=n, tasks=tasks, seed=1))
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (5, 3), (100, 77), (333, 130), (2048, 2048)])
+def test_img(w, h):
+    banner("img %dx%d" % (w, h))
+    G.check_program(W.img_program(side=w, height=h, seed=2))
+
+
+@pytest.mark.parametrize("n,deg,iters", [(64, 4, 3), (3000, 20, 10), (1 << 20, 20, 10)])
+def test_hits(n, deg, iters):
+    banner("hits n=%d deg=%d iters=%d" % (n, deg, iters))
+    G.check_program(W.hits_program(n=n, deg=deg, iters=iters, seed=3))
+
+
+def _spmv_program(rp, ci, va, x):
+    n = rp.size - 1
+    bufs = {"rp": W.Buf(rp.nbytes, init=rp), "ci": W.Buf(max(ci.nbytes, 4), init=ci if ci.size else np.zeros(1, np.int32)),
+            "va": W.Buf(max(va.nbytes, 4), init=va if va.size else np.zeros(1, np.float32)),
+            "x": W.Buf(x.nbytes, init=x), "y": W.Buf(4 * n)}
+    ops = [W.K("spmv", [("rp", "c"), ("ci", "c"), ("va", "c"), ("x", "c"), ("y", "m")],
+               nrows=n, ncols=x.size, nnz=int(ci.size))]
+    return W.Program("spmv", bufs, ops, ["y"])
+
+
+@pytest.mark.parametrize("variant", [4, 8, 12, 16])
+def test_spmv_long_rows_and_empty_rows(variant):
+    banner("spmv variant=%d" % variant)
+    n = 50000
+    rng = np.random.default_rng(5)
+    lengths = np.zeros(n, dtype=np.int64)
+    lengths[17] = 40000          # one row spanning many tiles
+    lengths[n - 1] = 9000        # a long last row
+    some = rng.choice(n, 3000, replace=False)
+    lengths[some] = rng.integers(1, 30, some.size)
+    lengths[0] = 0
+    rp = np.zeros(n + 1, np.int32)
+    np.cumsum(lengths, out=rp[1:])
+    ci = rng.integers(0, n, int(rp[-1])).astype(np.int32)
+    va = W.uniform_f32(6, ci.size)
+    x = W.uniform_f32(7, n)
+    prog = _spmv_program(rp, ci, va, x)
+    ref = T.spmv(rp, ci, va, x)
+    ctx = D.Context()
+    ctx.set_launch("spmv", 256, 0, variant)
+    from paper_2012_09646_amd import runner
+    b = runner.Bound(ctx, prog)
+    b.run()
+    y = b.read("y").view(np.float32)
+    ctx.close()
+    assert np.all(y[lengths == 0] == 0.0)
+    bad = np.abs(y.astype(np.float64) - ref) > 1e-5 * np.abs(ref)
+    assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:5])
+
+
+def test_spmv_no_nonzeros():
+    banner("spmv nnz=0")
+    n = 1000
+    rp = np.zeros(n + 1, np.int32)
+    prog = _spmv_program(rp, np.zeros(0, np.int32), np.zeros(0, np.float32), W.uniform_f32(1, n))
+    out = G.check_program(prog)
+    assert np.all(out["y"].view(np.float32) == 0)
+
+
+@pytest.mark.parametrize("policy,pool,batch", [
+    (D.DAG_SERIAL_SYNC, 1, True), (D.DAG_PARALLEL_ASYNC, 1, False),
+    (D.DAG_PARALLEL_ASYNC, 2, True), (D.DAG_PARALLEL_ASYNC, 16, False)])
+def test_policies_agree(policy, pool, batch):
+    banner("policies %d %d %d" % (policy, pool, batch))
+    for prog in (W.img_program(side=200, height=130, seed=9), W.hits_program(n=2000, iters=4, seed=8),
+                 W.bs_program(n=5000, tasks=5)):
+        G.check_program(prog, policy=policy, max_streams=pool, batch=batch)
