@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--max-streams", type=int, default=8)
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="GPU_MAX_HW_QUEUES for this process (0 = runtime default)")
+    ap.add_argument("--copy-streams", type=int, default=0, choices=[0, 1],
+                    help="0: one FIFO stream per copy direction; 1: copies placed like kernels")
+    ap.add_argument("--spin-wait", type=int, default=0, choices=[0, 1],
+                    help="1: host waits spin (hipDeviceScheduleSpin)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
 
@@ -70,13 +74,14 @@ def main():
             iv.append((pos, kind, inf.t_start_ms, inf.t_end_ms))
         return iv
 
-    def measure(name, prog, steps, warmup, restore=(), region=None):
+    def measure(name, prog, steps, warmup, restore=(), per_iter=None):
         """Timed parallel runs, serial runs, traced runs; returns a summary."""
         res = {"workload": name, "tasks": sum(1 for o in prog.ops if o["kind"] != "host_read")}
         pris = {}
 
         def make(policy, trace):
-            ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace)
+            ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,
+                            copy_streams=args.copy_streams, spin_wait=args.spin_wait)
             b = runner.Bound(ctx, prog, read_bytes=4)
             for dst in restore:
                 if dst not in pris:
@@ -118,6 +123,30 @@ def main():
         res["event_waits_per_run"] = sum(len(w) for w in bP.waits().values())
         ctxP.close()
 
+        # the same runs with timing events around every kernel (not copies):
+        # in-DAG kernel durations for the roofline, measured on the kernels' streams
+        ctxK, bK = make(D.DAG_PARALLEL_ASYNC, 2)
+        log(name, "parallel, kernel timing events")
+        ktimes = {}
+        park = []
+        for i in range(warmup + steps):
+            reset(ctxK, bK)
+            t0 = time.perf_counter()
+            bK.run()
+            t1 = time.perf_counter()
+            if i < warmup:
+                continue
+            park.append((t1 - t0) * 1e3)
+            for pos, kind, a, bb in kernel_intervals(ctxK, bK, len(prog.ops)):
+                o = prog.ops[pos - 1]
+                if o["kind"] == "kernel":
+                    ktimes.setdefault(o["kernel"], []).append((bb - a, M.algorithmic_bytes(o["kernel"], o["params"])))
+        res["makespan_kernel_events_ms"] = statistics.median(park)
+        res["kernels_in_dag"] = {k: {"launches": len(v), "avg_us": 1e3 * sum(t for t, _ in v) / len(v),
+                                     "gbs": sum(by for _, by in v) / sum(t for t, _ in v) / 1e6}
+                                 for k, v in ktimes.items()}
+        ctxK.close()
+
         ctxS, bS = make(D.DAG_SERIAL_SYNC, False)
         log(name, "serial")
         ser = timed(ctxS, bS, steps, warmup)
@@ -126,7 +155,7 @@ def main():
         ctxS.close()
 
         # isolated task times: serial policy with timing events
-        ctxI, bI = make(D.DAG_SERIAL_SYNC, True)
+        ctxI, bI = make(D.DAG_SERIAL_SYNC, 1)
         log(name, "isolated")
         iso = {}
         for i in range(max(3, min(steps, 10))):
@@ -161,10 +190,9 @@ def main():
         res["kernels_isolated"] = {k: {"avg_us": 1e3 * e["ms"] / e["launches"],
                                        "gbs": e["bytes"] / e["ms"] / 1e6} for k, e in per.items()}
 
-        # traced parallel runs: overlap and in-DAG kernel durations
-        ctxT, bT = make(D.DAG_PARALLEL_ASYNC, True)
+        # fully traced parallel runs (copies too): overlap figures
+        ctxT, bT = make(D.DAG_PARALLEL_ASYNC, 1)
         log(name, "traced parallel")
-        ktimes = {}
         tr = []
         for i in range(max(3, min(steps, 10))):
             reset(ctxT, bT)
@@ -173,19 +201,41 @@ def main():
             bT.run()
             tr.append((time.perf_counter() - t0) * 1e3)
             ivs = kernel_intervals(ctxT, bT, len(prog.ops))
-            for pos, kind, a, bb in ivs:
-                if kind == "C" and prog.ops[pos - 1]["kind"] == "kernel":
-                    k = prog.ops[pos - 1]["kernel"]
-                    ktimes.setdefault(k, []).append((bb - a, M.algorithmic_bytes(k, prog.ops[pos - 1]["params"])))
         res["overlap"] = M.overlap([(k, a, bb) for _, k, a, bb in ivs])
         res["traced_makespan_ms"] = statistics.median(tr)
-        res["kernels_in_dag"] = {k: {"launches": len(v), "avg_us": 1e3 * sum(t for t, _ in v) / len(v),
-                                     "gbs": sum(by for _, by in v) / sum(t for t, _ in v) / 1e6}
-                                 for k, v in ktimes.items()}
         ctxT.close()
 
-        if region is not None:
-            res.update(region())
+        # graph form: the DAG (or one HITS iteration) recorded once and replayed
+        # as one task per launch; no dependency work or per-task HIP calls
+        for gm, tag in ((0, "graph"), (1, "replay")):
+            ctxG = D.Context(policy=D.DAG_PARALLEL_ASYNC, max_streams=args.max_streams, graph_mode=gm,
+                             copy_streams=args.copy_streams, spin_wait=args.spin_wait)
+            bG = runner.Bound(ctxG, prog, read_bytes=4)
+            for dst in restore:
+                h0 = ctxG.alloc(prog.bufs[dst].nbytes)
+                ctxG.host_write(h0, pris[dst])
+                bG.h[dst + "@0"] = h0
+            reset(ctxG, bG)
+            if per_iter:
+                bG.record(1, 0, per_iter)
+                times = len(prog.ops) // per_iter
+            else:
+                bG.record(1)
+                times = 1
+            ctxG.sync()
+            log(name, tag)
+            gt = []
+            for i in range(warmup + steps):
+                reset(ctxG, bG)
+                t0 = time.perf_counter()
+                bG.replay(1, times)
+                t1 = time.perf_counter()
+                if i >= warmup:
+                    gt.append((t1 - t0) * 1e3)
+            res[tag + "_ms"] = statistics.median(gt)
+            res[tag + "_speedup"] = res["serial_ms"] / res[tag + "_ms"]
+            res[tag + "_cp_frac"] = res["cp_bound_ms"] / res[tag + "_ms"]
+            ctxG.close()
         return res, ktimes
 
     workloads = ["bs", "vec", "img", "hits"] if args.workload == "all" else [args.workload]
@@ -205,7 +255,7 @@ def main():
         elif wl == "hits":
             log("hits: generating the graph")
             prog = W.hits_program(n=1 << 20, deg=20, iters=10, seed=3)
-            results[wl], _ = measure(wl, prog, args.steps, args.warmup, restore=("a", "h"))
+            results[wl], _ = measure(wl, prog, args.steps, args.warmup, restore=("a", "h"), per_iter=6)
 
     head = results.get("bs") or results[workloads[0]]
     line = {
@@ -222,7 +272,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "bs_fanout_10x2^22" if "bs" in results else head["workload"],
-                   "max_streams": args.max_streams,
+                   "max_streams": args.max_streams, "copy_streams": args.copy_streams,
+                   "spin_wait": args.spin_wait,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)},
         "makespan_ms": round(head["makespan_ms"], 4),
         "serial_ms": round(head["serial_ms"], 4),
@@ -231,6 +282,8 @@ def main():
         "resource_bound_ms": round(head["resource_bound_ms"], 4),
         "resource_frac": round(head["resource_frac"], 4),
         "overlap": head["overlap"],
+        "graph_ms": round(head["graph_ms"], 4),
+        "graph_speedup": round(head["graph_speedup"], 4),
     }
     if kt_bs:
         v = kt_bs["bs_call"]

@@ -100,7 +100,8 @@ typedef int32_t dag_status;
 typedef struct {
   uint32_t policy;        /* DAG_SERIAL_SYNC or DAG_PARALLEL_ASYNC */
   uint32_t max_streams;   /* stream pool bound, 1..DAG_MAX_STREAMS (0 = 8) */
-  uint32_t trace;         /* 1 = record timing events around every task */
+  uint32_t trace;         /* 1 = record timing events around every GPU task,
+                             2 = around kernels and region replays only */
   uint32_t dry_run;       /* 1 = schedule only: infer edges, streams and
                              waits, make no HIP call and touch no memory */
   int32_t device;         /* HIP device ordinal */
@@ -108,6 +109,15 @@ typedef struct {
                              multi-stream replay without dependency work */
   uint64_t scratch_bytes; /* per-stream device scratch for reductions and
                              SpMV carries (0 = 4 MiB) */
+  uint32_t copy_streams;  /* 0 = host->device and device->host copies each
+                             run on one FIFO stream of their own, outside
+                             the pool (concurrent copies in one direction
+                             share one link, so issue order finishes them
+                             soonest); 1 = copies are placed by the stream
+                             policy like kernels */
+  uint32_t spin_wait;     /* 1 = host waits spin instead of sleeping (asks
+                             HIP for hipDeviceScheduleSpin; effective only if
+                             no HIP context exists yet in the process) */
 } dag_config;
 
 /* One argument of a call: a buffer and its access mode. */

@@ -71,6 +71,7 @@ struct Region {
 };
 
 constexpr uint32_t kMaxArgs = 16;
+constexpr size_t kStagingBytes = 64 << 10;
 
 }  // namespace
 }  // namespace dagrt
@@ -90,6 +91,8 @@ struct dag_ctx_s {
   std::vector<hipStream_t> streams;
   std::vector<void*> scratch;             // per pool stream
   hipStream_t io = nullptr;
+  void* staging = nullptr;                // pinned, for small host reads
+  hipEvent_t read_ev = nullptr;
   std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion
   std::vector<hipEvent_t> ev0;            // per task, start (trace mode)
   std::vector<hipEvent_t> free_ev;
@@ -189,6 +192,13 @@ void note_event_slot(dag_ctx c, uint64_t id) {
   }
 }
 
+// Trace mode 1 times every GPU task, mode 2 only kernels and region replays.
+bool traced(dag_ctx c, uint64_t id) {
+  if (c->cfg.trace == 0) return false;
+  if (c->cfg.trace == 1) return true;
+  return c->tr.task(id).kind != TK_COPY;
+}
+
 // Enqueue the waits of task id on its stream and (trace) its start event.
 dag_status begin_task(dag_ctx c, uint64_t id, int32_t s) {
   if (c->dry) return DAG_OK;
@@ -199,7 +209,7 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s) {
   }
   c->n_waits += t.wait_n;
   note_event_slot(c, id);
-  if (c->cfg.trace) {
+  if (traced(c, id)) {
     hipEvent_t e0;
     dag_status st = get_event(c, true, &e0);
     if (st) return st;
@@ -212,7 +222,7 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s) {
 dag_status end_task(dag_ctx c, uint64_t id, int32_t s) {
   if (c->dry) return DAG_OK;
   hipEvent_t e;
-  dag_status st = get_event(c, c->cfg.trace != 0, &e);
+  dag_status st = get_event(c, traced(c, id), &e);
   if (st) return st;
   c->ev[id] = e;
   HIP_TRY(c, hipEventRecord(e, c->streams[s]));
@@ -288,9 +298,9 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
   const uint64_t id = c->tr.add_gpu(TK_KERNEL, kid, c->tmp_acc.data(),
                                     static_cast<uint32_t>(c->tmp_acc.size()), c->serial, &s, &created);
   if (out) *out = id;
+  c->submit_us += us_since(t0);
   dag_status st = ensure_stream(c, s);
   if (st) return st;
-  c->submit_us += us_since(t0);
   const auto t1 = Clock::now();
   st = begin_task(c, id, s);
   if (st) return st;
@@ -348,18 +358,23 @@ dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t 
   add_access(&c->tmp_acc, dst - 1, ACC_W);
   int32_t s;
   bool created;
+  const hipMemcpyKind kind = copy_kind(bd->loc, bs->loc);
+  uint8_t lane = 0;
+  if (c->cfg.copy_streams == 0) {
+    if (kind == hipMemcpyHostToDevice) lane = kLaneH2D;
+    if (kind == hipMemcpyDeviceToHost) lane = kLaneD2H;
+  }
   const uint64_t id = c->tr.add_gpu(TK_COPY, 0, c->tmp_acc.data(),
-                                    static_cast<uint32_t>(c->tmp_acc.size()), c->serial, &s, &created);
+                                    static_cast<uint32_t>(c->tmp_acc.size()), c->serial, &s, &created, lane);
   if (out) *out = id;
+  c->submit_us += us_since(t0);
   dag_status st = ensure_stream(c, s);
   if (st) return st;
-  c->submit_us += us_since(t0);
   const auto t1 = Clock::now();
   st = begin_task(c, id, s);
   if (st) return st;
   void* dp = static_cast<char*>(bd->ptr) + doff;
   const void* sp = static_cast<const char*>(bs->ptr) + soff;
-  const hipMemcpyKind kind = copy_kind(bd->loc, bs->loc);
   if (!c->dry) HIP_TRY(c, hipMemcpyAsync(dp, sp, bytes, kind, c->streams[s]));
   st = end_task(c, id, s);
   c->launch_us += us_since(t1);
@@ -388,16 +403,35 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
   const uint64_t id = c->tr.add_host(kind, h - 1, kind == TK_HOST_READ ? ACC_R : ACC_W, c->serial,
                                      &c->tmp_wait);
   if (out) *out = id;
+  char* p = static_cast<char*>(b->ptr) + off;
+  // A read of device memory that waits on its writer: copy on the writer's
+  // stream into pinned staging and wait once (one host<->device round trip).
+  if (!c->dry && kind == TK_HOST_READ && hdst && bytes && bytes <= kStagingBytes &&
+      b->loc == DAG_DEVICE && c->tmp_wait.size() == 1) {
+    hipStream_t ws = c->streams[c->tr.task(c->tmp_wait[0]).stream];
+    HIP_TRY(c, hipMemcpyAsync(c->staging, p, bytes, hipMemcpyDeviceToHost, ws));
+    HIP_TRY(c, hipEventRecord(c->read_ev, ws));
+    HIP_TRY(c, hipEventSynchronize(c->read_ev));
+    ++c->n_host_waits;
+    std::memcpy(hdst, c->staging, bytes);
+    c->tmp_retired.clear();
+    c->tr.retire(id, &c->tmp_retired);
+    recycle_retired(c);
+    return DAG_OK;
+  }
   dag_status st = host_wait(c);
   if (st) return st;
   c->tmp_retired.clear();
   c->tr.retire(id, &c->tmp_retired);
   recycle_retired(c);
   if (c->dry || bytes == 0) return DAG_OK;
-  char* p = static_cast<char*>(b->ptr) + off;
   if (kind == TK_HOST_READ && hdst) {
     if (b->loc == DAG_PINNED_HOST) {
       if (hdst != p) std::memcpy(hdst, p, bytes);
+    } else if (bytes <= kStagingBytes) {
+      HIP_TRY(c, hipMemcpyAsync(c->staging, p, bytes, hipMemcpyDeviceToHost, c->io));
+      HIP_TRY(c, hipStreamSynchronize(c->io));
+      std::memcpy(hdst, c->staging, bytes);
     } else {
       HIP_TRY(c, hipMemcpyAsync(hdst, p, bytes, hipMemcpyDeviceToHost, c->io));
       HIP_TRY(c, hipStreamSynchronize(c->io));
@@ -606,7 +640,8 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   c.max_streams = 8;
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
-  if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1)
+  if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1 ||
+      c.trace > 2 || c.copy_streams > 1)
     return DAG_E_INVAL;
   if (c.scratch_bytes == 0) c.scratch_bytes = 4u << 20;
   if (c.scratch_bytes < 4096 || c.scratch_bytes > (1ull << 32)) return DAG_E_INVAL;
@@ -621,8 +656,14 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
     if (kd) x->launch_cfg[k] = kd->def;
   }
   if (!x->dry) {
+    // Spin instead of sleeping in host waits (only effective if this is the
+    // first HIP use in the process; ignored otherwise).
+    if (c.spin_wait) (void)hipSetDeviceFlags(hipDeviceScheduleSpin);
+    (void)hipGetLastError();
     hipError_t e = hipSetDevice(c.device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&x->io, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipHostMalloc(&x->staging, kStagingBytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&x->read_ev, hipEventDisableTiming);
     int khz = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device);
     if (e == hipSuccess) set_wall_clock_khz(static_cast<uint64_t>(khz));
@@ -633,6 +674,8 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
     if (e != hipSuccess) {
       fprintf(stderr, "dag_create: %s\n", hipGetErrorString(e));
       if (x->io) (void)hipStreamDestroy(x->io);
+      if (x->staging) (void)hipHostFree(x->staging);
+      if (x->read_ev) (void)hipEventDestroy(x->read_ev);
       delete x;
       return DAG_E_HIP;
     }
@@ -670,6 +713,8 @@ dag_status dag_destroy(dag_ctx c) {
       (void)hipStreamDestroy(c->aux[i]);
     }
     if (c->io) (void)hipStreamDestroy(c->io);
+    if (c->staging) (void)hipHostFree(c->staging);
+    if (c->read_ev) (void)hipEventDestroy(c->read_ev);
   }
   delete c;
   return DAG_OK;
@@ -904,9 +949,9 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   const uint64_t id = c->tr.add_gpu(TK_REGION, 0, r->accs.data(), static_cast<uint32_t>(r->accs.size()),
                                     c->serial, &s, &created);
   if (out) *out = id;
+  c->submit_us += us_since(t0);
   dag_status st = ensure_stream(c, s);
   if (st) return st;
-  c->submit_us += us_since(t0);
   const auto t1 = Clock::now();
   st = begin_task(c, id, s);
   if (st) return st;

@@ -146,7 +146,13 @@ __global__ __launch_bounds__(1024) void k_vec_square(float* __restrict__ x, uint
   }
 }
 
+// Two ways to combine the per-workgroup partials, chosen by the launch
+// variant: 0 = a second one-workgroup kernel sums them (the kernel boundary
+// makes them visible); 1 = single pass, the last workgroup to arrive sums
+// them (one agent-scope release per workgroup: each XCD has its own L2).
+
 // r[0] = fl32(sum_i (x_i - y_i)) with fp64 differences and accumulation.
+template <bool kSinglePass>
 __global__ __launch_bounds__(1024) void k_vec_sum_diff(const float* __restrict__ x,
                                                        const float* __restrict__ y,
                                                        float* __restrict__ r, uint64_t n, int vec,
@@ -175,13 +181,24 @@ __global__ __launch_bounds__(1024) void k_vec_sum_diff(const float* __restrict__
   }
   const double bsum = block_sum(acc, sh);
   publish_partial(partials, d2u(bsum));
-  if (arrive_last(counter, &flag)) {
+  if (kSinglePass && arrive_last(counter, &flag)) {
     double t = 0.0;
     for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) t += u2d(read_partial(partials, i));
     const double tot = block_sum(t, sh);
     if (threadIdx.x == 0) r[0] = static_cast<float>(tot);
     reset_counter(counter);
   }
+}
+
+// Second pass: one workgroup sums np fp64 partials in a fixed order.
+template <typename Out>
+__global__ __launch_bounds__(256) void k_finish_sum(const uint64_t* __restrict__ partials, uint32_t np,
+                                                    Out* __restrict__ out) {
+  __shared__ double sh[17];
+  double t = 0.0;
+  for (uint32_t i = threadIdx.x; i < np; i += blockDim.x) t += u2d(partials[i]);
+  const double tot = block_sum(t, sh);
+  if (threadIdx.x == 0) out[0] = static_cast<Out>(tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,6 +322,7 @@ __global__ __launch_bounds__(256) void k_sobel(const float* __restrict__ in,
 }
 
 // M = [max, min] of n fp32 values (exact).
+template <bool kSinglePass>
 __global__ __launch_bounds__(1024) void k_minmax(const float* __restrict__ a, float* __restrict__ M,
                                                  uint64_t n, int vec, uint32_t* counter,
                                                  uint64_t* partials) {
@@ -333,7 +351,7 @@ __global__ __launch_bounds__(1024) void k_minmax(const float* __restrict__ a, fl
   }
   block_minmax(&mx, &mn, sh);
   publish_partial(partials, (static_cast<uint64_t>(__float_as_uint(mx)) << 32) | __float_as_uint(mn));
-  if (arrive_last(counter, &flag)) {
+  if (kSinglePass && arrive_last(counter, &flag)) {
     float gmx = -INFINITY, gmn = INFINITY;
     for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
       const uint64_t u = read_partial(partials, i);
@@ -346,6 +364,22 @@ __global__ __launch_bounds__(1024) void k_minmax(const float* __restrict__ a, fl
       M[1] = gmn;
     }
     reset_counter(counter);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finish_minmax(const uint64_t* __restrict__ partials, uint32_t np,
+                                                       float* __restrict__ M) {
+  __shared__ float sh[34];
+  float gmx = -INFINITY, gmn = INFINITY;
+  for (uint32_t i = threadIdx.x; i < np; i += blockDim.x) {
+    const uint64_t u = partials[i];
+    gmx = fmaxf(gmx, __uint_as_float(static_cast<uint32_t>(u >> 32)));
+    gmn = fminf(gmn, __uint_as_float(static_cast<uint32_t>(u & 0xffffffffu)));
+  }
+  block_minmax(&gmx, &gmn, sh);
+  if (threadIdx.x == 0) {
+    M[0] = gmx;
+    M[1] = gmn;
   }
 }
 
@@ -419,6 +453,7 @@ __global__ __launch_bounds__(1024) void k_unsharp_combine(
 // L2 scaling.
 // ---------------------------------------------------------------------------
 struct SpmvScratch {
+  int* coord;         // per tile boundary b (0..ntiles): rows finished before diagonal b*TILE
   int* head_row;      // per tile: row whose sum continues from earlier tiles, or -1
   int* tail_row;      // per tile: row open at the end of the tile
   double* head_val;   // per tile: this tile's part of head_row (incl. in-tile carry)
@@ -426,6 +461,64 @@ struct SpmvScratch {
 };
 
 __device__ __forceinline__ int clamp_nnz(int v, int nnz) { return min(max(v, 0), nnz); }
+
+// Merge-path split of diagonal `diag` (rows finished before it) by one wave:
+// the smallest x in [max(0, diag - nnz), min(diag, nrows)] whose row end is
+// past diag - x - 1.  64 probes per round shrink the interval 65-fold, so a
+// few dependent global loads replace a long binary-search chain.
+__device__ long long wave_merge_search(const int* __restrict__ row_ptr, int nrows, int nnz,
+                                       long long diag) {
+  const int lane = threadIdx.x & (kWave - 1);
+  long long lo = max(0LL, diag - nnz), hi = min(diag, static_cast<long long>(nrows));
+  while (hi - lo > kWave) {
+    const long long span = hi - lo;
+    const long long x = lo + ((lane + 1) * span) / (kWave + 1);
+    const bool p = clamp_nnz(row_ptr[x + 1], nnz) <= diag - x - 1;
+    const int c = __popcll(__ballot(p));
+    if (c == 0) {
+      hi = lo + span / (kWave + 1);
+    } else {
+      const long long sc1 = lo + (static_cast<long long>(c) * span) / (kWave + 1);
+      const long long nhi = c < kWave ? lo + ((c + 1) * span) / (kWave + 1) : hi;
+      lo = sc1 + 1;
+      hi = nhi;
+    }
+  }
+  const long long x = lo + lane;
+  const bool p = x < hi && clamp_nnz(row_ptr[x + 1], nnz) <= diag - x - 1;
+  return lo + __popcll(__ballot(p));
+}
+
+// Smallest p in [lo, hi) with a[p] >= key (a non-decreasing), or hi; one wave.
+__device__ int wave_lower_bound(const int* __restrict__ a, int lo, int hi, int key) {
+  const int lane = threadIdx.x & (kWave - 1);
+  while (hi - lo > kWave) {
+    const long long span = hi - lo;
+    const int x = static_cast<int>(lo + ((lane + 1) * span) / (kWave + 1));
+    const int c = __popcll(__ballot(a[x] < key));
+    if (c == 0) {
+      hi = static_cast<int>(lo + span / (kWave + 1));
+    } else {
+      const int sc1 = static_cast<int>(lo + (c * span) / (kWave + 1));
+      const int nhi = c < kWave ? static_cast<int>(lo + ((c + 1) * span) / (kWave + 1)) : hi;
+      lo = sc1 + 1;
+      hi = nhi;
+    }
+  }
+  const int x = lo + lane;
+  return lo + __popcll(__ballot(x < hi && a[x] < key));
+}
+
+// Tile boundaries of the merge path, one wave per boundary, all in parallel.
+__global__ __launch_bounds__(256) void k_spmv_partition(const int* __restrict__ row_ptr, int nrows,
+                                                        int nnz, int tile, int ntiles, SpmvScratch sc) {
+  const int b = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (b > ntiles) return;
+  const long long total = static_cast<long long>(nrows) + nnz;
+  const long long diag = min(static_cast<long long>(b) * tile, total);
+  const long long x = wave_merge_search(row_ptr, nrows, nnz, diag);
+  if ((threadIdx.x & (kWave - 1)) == 0) sc.coord[b] = static_cast<int>(x);
+}
 
 template <int IPT>
 __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_ptr,
@@ -439,37 +532,45 @@ __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_
   __shared__ double s_prod[TILE];
   __shared__ int s_crow[256];
   __shared__ double s_cval[256];
-  __shared__ int s_coord[4];
   __shared__ int s_head_row;
   __shared__ double s_head_val;
   const int tid = threadIdx.x;
   const long long total = static_cast<long long>(nrows) + nnz;
-  if (tid < 2) {
-    const long long diag = min(static_cast<long long>(blockIdx.x + tid) * TILE, total);
-    long long lo = max(0LL, diag - nnz), hi = min(diag, static_cast<long long>(nrows));
-    while (lo < hi) {
-      const long long mid = (lo + hi) >> 1;
-      if (clamp_nnz(row_ptr[mid + 1], nnz) <= diag - mid - 1)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    s_coord[2 * tid] = static_cast<int>(lo);
-    s_coord[2 * tid + 1] = static_cast<int>(diag - lo);
-  }
+  const long long d0 = static_cast<long long>(blockIdx.x) * TILE;
+  const long long d1 = min(d0 + TILE, total);
+  const int xb = sc.coord[blockIdx.x];
+  const int xe = sc.coord[blockIdx.x + 1];
+  const int yb = static_cast<int>(d0 - xb);
+  const int ye = static_cast<int>(d1 - xe);
+  const int na = max(0, min(xe - xb, TILE));
+  const int nb = max(0, min(ye - yb, TILE));
   if (tid == 0) s_head_row = -1;
-  __syncthreads();
-  const int xb = s_coord[0], yb = s_coord[1];
-  const int na = max(0, min(s_coord[2] - xb, TILE));
-  const int nb = max(0, min(s_coord[3] - yb, TILE));
-  for (int i = tid; i <= na; i += 256) {
-    const int r = xb + i;
-    s_rowend[i] = r < nrows ? clamp_nnz(row_ptr[r + 1], nnz) : nnz;
+  // Stage the tile with every load of a thread in flight at once: IPT column
+  // indices and values (streamed once, non-temporal, so x stays in L2), then
+  // the IPT gathers of x, then the row ends.
+  int cidx[IPT];
+  float v[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int i = tid + j * 256;
+    cidx[j] = i < nb ? __builtin_nontemporal_load(col + yb + i) : 0;
+    v[j] = i < nb ? __builtin_nontemporal_load(val + yb + i) : 0.0f;
   }
-  for (int i = tid; i < nb; i += 256) {
-    const int k = yb + i;
-    const int c = min(max(col[k], 0), ncols - 1);
-    s_prod[i] = static_cast<double>(val[k]) * static_cast<double>(x[c]);
+  float xv[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) xv[j] = x[min(max(cidx[j], 0), ncols - 1)];
+#pragma unroll
+  for (int j = 0; j < IPT + 1; ++j) {
+    const int i = tid + j * 256;
+    if (i <= na) {
+      const int r = xb + i;
+      s_rowend[i] = r < nrows ? clamp_nnz(row_ptr[r + 1], nnz) : nnz;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int i = tid + j * 256;
+    if (i < nb) s_prod[i] = static_cast<double>(v[j]) * static_cast<double>(xv[j]);
   }
   __syncthreads();
   // this thread's segment of the merge path inside the tile
@@ -534,19 +635,24 @@ __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_
   }
 }
 
-// Rows split across tiles: add the parts of the preceding tiles, in order.
-__global__ __launch_bounds__(256) void k_spmv_fixup(float* __restrict__ y, SpmvScratch sc,
-                                                    int ntiles) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// Rows split across tiles: one wave per tile whose first row started in an
+// earlier tile finds the run of preceding tiles that end inside that row
+// (tile tail rows are non-decreasing) and adds their parts in a fixed order.
+__global__ __launch_bounds__(256) void k_spmv_fixup(float* __restrict__ y, SpmvScratch sc, int ntiles) {
+  const int b = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
   if (b >= ntiles) return;
   const int r = sc.head_row[b];
-  if (r < 0) return;
-  double v = sc.head_val[b];
-  for (int p = b - 1; p >= 0 && sc.tail_row[p] == r; --p) v += sc.tail_val[p];
-  y[r] = static_cast<float>(v);
+  if (r < 0 || b == 0) return;
+  const int p0 = wave_lower_bound(sc.tail_row, 0, b, r);
+  double acc = 0.0;
+  for (int p = p0 + lane; p < b; p += kWave) acc += sc.tail_val[p];
+  acc = wave_sum(acc);
+  if (lane == 0) y[r] = static_cast<float>(sc.head_val[b] + acc);
 }
 
 // s = sum v_i^2 (fp64).
+template <bool kSinglePass>
 __global__ __launch_bounds__(1024) void k_sumsq(const float* __restrict__ v, double* __restrict__ s,
                                                 uint64_t n, int vec, uint32_t* counter,
                                                 uint64_t* partials) {
@@ -575,7 +681,7 @@ __global__ __launch_bounds__(1024) void k_sumsq(const float* __restrict__ v, dou
   }
   const double bsum = block_sum(acc, sh);
   publish_partial(partials, d2u(bsum));
-  if (arrive_last(counter, &flag)) {
+  if (kSinglePass && arrive_last(counter, &flag)) {
     double t = 0.0;
     for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) t += u2d(read_partial(partials, i));
     const double tot = block_sum(t, sh);
@@ -636,6 +742,11 @@ __global__ __launch_bounds__(1024) void k_copy_f32(const float* __restrict__ src
 const char* cfg_block_any(const LaunchCfg& c) {
   if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
   if (c.variant != 0) return "variant must be 0";
+  return nullptr;
+}
+const char* cfg_reduce(const LaunchCfg& c) {
+  if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
+  if (c.variant > 1) return "variant: 0 = two kernels, 1 = single pass";
   return nullptr;
 }
 const char* cfg_tile256(const LaunchCfg& c) {
@@ -702,9 +813,17 @@ hipError_t l_vec_sum_diff(hipStream_t s, void* const* a, const void* p, const La
   const int vec = aligned16(a[0]) && aligned16(a[1]);
   auto* counter = static_cast<uint32_t*>(scr);
   auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
-  hipLaunchKernelGGL(k_vec_sum_diff, dim3(reduction_grid(vec ? ceil_div(n, 4) : n, c, sb)), dim3(c.block), 0,
-                     s, static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
-                     static_cast<float*>(a[2]), n, vec, counter, partials);
+  const uint32_t g = reduction_grid(vec ? ceil_div(n, 4) : n, c, sb);
+  if (c.variant == 1) {
+    hipLaunchKernelGGL(k_vec_sum_diff<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                       static_cast<const float*>(a[1]), static_cast<float*>(a[2]), n, vec, counter, partials);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_vec_sum_diff<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                     static_cast<const float*>(a[1]), static_cast<float*>(a[2]), n, vec, counter, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish_sum<float>, dim3(1), dim3(256), 0, s, partials, g, static_cast<float*>(a[2]));
   return hipGetLastError();
 }
 
@@ -803,10 +922,19 @@ const char* v_minmax(const void* p, const size_t* sz, uint32_t, const LaunchCfg&
 hipError_t l_minmax(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
   const uint64_t n = pn(p);
   const int vec = aligned16(a[0]);
-  hipLaunchKernelGGL(k_minmax, dim3(reduction_grid(vec ? ceil_div(n, 4) : n, c, sb)), dim3(c.block), 0, s,
-                     static_cast<const float*>(a[0]), static_cast<float*>(a[1]), n, vec,
-                     static_cast<uint32_t*>(scr),
-                     reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset));
+  auto* counter = static_cast<uint32_t*>(scr);
+  auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
+  const uint32_t g = reduction_grid(vec ? ceil_div(n, 4) : n, c, sb);
+  if (c.variant == 1) {
+    hipLaunchKernelGGL(k_minmax<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                       static_cast<float*>(a[1]), n, vec, counter, partials);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_minmax<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                     static_cast<float*>(a[1]), n, vec, counter, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish_minmax, dim3(1), dim3(256), 0, s, partials, g, static_cast<float*>(a[1]));
   return hipGetLastError();
 }
 
@@ -849,8 +977,9 @@ hipError_t l_combine(hipStream_t s, void* const* a, const void* p, const LaunchC
 uint64_t spmv_tiles(const dag_p_csr* q, uint32_t ipt) {
   return ceil_div(static_cast<uint64_t>(q->nrows) + q->nnz, 256ull * ipt);
 }
-// Carries live after the reduction ticket counter (which must stay zero).
-size_t spmv_scratch_need(uint64_t tiles) { return kScratchPartialsOffset + tiles * (4 + 4 + 8 + 8); }
+// Carries live after the reduction ticket counter (which must stay zero):
+// head_val, tail_val (fp64), head_row, tail_row, coord (int32, tiles + 1).
+size_t spmv_scratch_need(uint64_t tiles) { return kScratchPartialsOffset + tiles * (8 + 8 + 4 + 4) + 4 * (tiles + 1); }
 
 const char* v_spmv(const void* p, const size_t* sz, uint32_t, const LaunchCfg& c, size_t sb) {
   const auto* q = static_cast<const dag_p_csr*>(p);
@@ -883,16 +1012,23 @@ hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   sc.tail_val = reinterpret_cast<double*>(base + 8ull * tiles);
   sc.head_row = reinterpret_cast<int*>(base + 16ull * tiles);
   sc.tail_row = reinterpret_cast<int*>(base + 20ull * tiles);
+  sc.coord = reinterpret_cast<int*>(base + 24ull * tiles);
+  const int waves_per_wg = 256 / kWave;
+  hipLaunchKernelGGL(k_spmv_partition, dim3(ceil_div(tiles + 1, waves_per_wg)), dim3(256), 0, s,
+                     static_cast<const int*>(a[0]), static_cast<int>(q->nrows), static_cast<int>(q->nnz),
+                     static_cast<int>(256 * c.variant), tiles, sc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   switch (c.variant) {
     case 4: launch_spmv_ipt<4>(s, a, q, sc, tiles); break;
     case 12: launch_spmv_ipt<12>(s, a, q, sc, tiles); break;
     case 16: launch_spmv_ipt<16>(s, a, q, sc, tiles); break;
     default: launch_spmv_ipt<8>(s, a, q, sc, tiles); break;
   }
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spmv_fixup, dim3(ceil_div(tiles, 256)), dim3(256), 0, s, static_cast<float*>(a[4]), sc,
-                     tiles);
+  hipLaunchKernelGGL(k_spmv_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s, static_cast<float*>(a[4]),
+                     sc, tiles);
   return hipGetLastError();
 }
 
@@ -905,10 +1041,19 @@ const char* v_sumsq(const void* p, const size_t* sz, uint32_t, const LaunchCfg&,
 hipError_t l_sumsq(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
   const uint64_t n = pn(p);
   const int vec = aligned16(a[0]);
-  hipLaunchKernelGGL(k_sumsq, dim3(reduction_grid(vec ? ceil_div(n, 4) : n, c, sb)), dim3(c.block), 0, s,
-                     static_cast<const float*>(a[0]), static_cast<double*>(a[1]), n, vec,
-                     static_cast<uint32_t*>(scr),
-                     reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset));
+  auto* counter = static_cast<uint32_t*>(scr);
+  auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
+  const uint32_t g = reduction_grid(vec ? ceil_div(n, 4) : n, c, sb);
+  if (c.variant == 1) {
+    hipLaunchKernelGGL(k_sumsq<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                       static_cast<double*>(a[1]), n, vec, counter, partials);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_sumsq<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                     static_cast<double*>(a[1]), n, vec, counter, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish_sum<double>, dim3(1), dim3(256), 0, s, partials, g, static_cast<double*>(a[1]));
   return hipGetLastError();
 }
 
@@ -956,16 +1101,16 @@ hipError_t l_copy(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
 const KernelDesc kTable[] = {
     /* 0 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
     /* 1 */ {"vec_square", 1, 0x1, sizeof(dag_p_n), {256, 0, 0}, v_vec_square, l_vec_square, cfg_block_any},
-    /* 2 */ {"vec_sum_diff", 3, 0x4, sizeof(dag_p_n), {256, 1024, 0}, v_vec_sum_diff, l_vec_sum_diff, cfg_block_any},
+    /* 2 */ {"vec_sum_diff", 3, 0x4, sizeof(dag_p_n), {256, 1024, 0}, v_vec_sum_diff, l_vec_sum_diff, cfg_reduce},
     /* 3 */ {"bs_call", 2, 0x2, sizeof(dag_p_bs), {256, 0, 0}, v_bs, l_bs, cfg_block_any},
     /* 4 */ {"gauss_blur", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_blur, l_blur, cfg_tile256},
     /* 5 */ {"sobel", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_img2, l_sobel, cfg_tile256},
-    /* 6 */ {"minmax", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_minmax, l_minmax, cfg_block_any},
+    /* 6 */ {"minmax", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_minmax, l_minmax, cfg_reduce},
     /* 7 */ {"normalise", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_normalise, l_normalise, cfg_block_any},
     /* 8 */ {"unsharp_combine", 8, 0x80, sizeof(dag_p_n), {256, 0, 0}, v_combine, l_combine, cfg_block_any},
     /* 9 */ {"spmv", 5, 0x10, sizeof(dag_p_csr), {256, 0, 8}, v_spmv, l_spmv, cfg_spmv},
     /* 10 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
-    /* 11 */ {"sumsq", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_sumsq, l_sumsq, cfg_block_any},
+    /* 11 */ {"sumsq", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_sumsq, l_sumsq, cfg_reduce},
     /* 12 */ {"scale_l2", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_scale, l_scale, cfg_block_any},
     /* 13 */ {"spin", 0, 0x0, sizeof(dag_p_spin), {64, 0, 0}, v_spin, l_spin, cfg_spin},
     /* 14 */ {"copy_f32", 2, 0x2, sizeof(dag_p_n), {256, 0, 0}, v_copy, l_copy, cfg_block_any},

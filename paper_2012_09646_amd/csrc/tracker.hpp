@@ -19,7 +19,11 @@
 // Streams (Sec. IV-C): the first child of a computation goes on its parent's
 // stream; otherwise an empty stream is reused in FIFO order; otherwise a new
 // stream is created while the pool is below its bound, and beyond it the
-// stream whose last task is oldest is reused.  A call waits only on parents
+// stream whose last task is oldest is reused.  Optionally, host<->device
+// copies bypass the pool and go to one FIFO stream per direction (a copy
+// lane): concurrent copies in one direction share the single PCIe link, so
+// running them one after the other in issue order finishes the first ones
+// early and lets their consumers start while later copies still stream.  A call waits only on parents
 // on other streams (Sec. IV-B: one event per computation), and among those
 // only on the newest per stream that is not already ordered before it;
 // per-stream vector clocks decide that in O(#streams).
@@ -44,6 +48,9 @@ enum TaskKind : uint8_t {
   TK_REGION = 5,
   TK_RELEASE = 6,
 };
+
+constexpr uint8_t kLaneH2D = 1;
+constexpr uint8_t kLaneD2H = 2;
 
 inline bool is_gpu_kind(uint8_t k) { return k == TK_KERNEL || k == TK_COPY || k == TK_REGION; }
 
@@ -81,6 +88,7 @@ struct StreamRec {
   uint32_t nactive = 0;
   uint32_t npos = 0;
   bool in_fifo = false;
+  uint8_t lane = 0;  // 0 = pool stream, else the copy lane it serves
   std::vector<uint32_t> vc;  // vc[t]: highest position of stream t ordered before this point
 };
 
@@ -93,6 +101,7 @@ class Tracker {
   uint64_t last_id() const { return tasks_.size() - 1; }
   const TaskRec& task(uint64_t id) const { return tasks_[id]; }
   uint32_t num_streams() const { return static_cast<uint32_t>(streams_.size()); }
+  bool is_lane(int32_t s) const { return s >= 0 && streams_[s].lane != 0; }
   uint64_t num_active() const { return nactive_total_; }
   const std::vector<EdgeRec>& edges() const { return edges_; }
   const uint64_t* parents(uint64_t id) const { return par_pool_.data() + tasks_[id].par_off; }
@@ -123,8 +132,10 @@ class Tracker {
   // stream 0 (the serial policy of Sec. IV-C computes no dependencies).
   // Returns the new id; *stream_out, *new_stream_out and the wait list
   // (waits(id), task(id).wait_n) describe what the executor must do.
+  // lane: 0 = placed by the policy; 1..kMaxLanes = always on that copy lane
+  // (one FIFO stream per copy direction, outside the pool).
   uint64_t add_gpu(uint8_t kind, uint32_t kernel_id, const Access* accs, uint32_t n,
-                   bool serial, int32_t* stream_out, bool* new_stream_out) {
+                   bool serial, int32_t* stream_out, bool* new_stream_out, uint8_t lane = 0) {
     const uint64_t id = tasks_.size();
     tasks_.emplace_back();
     TaskRec& t = tasks_.back();
@@ -144,7 +155,7 @@ class Tracker {
     par_pool_.insert(par_pool_.end(), tmp_par_.begin(), tmp_par_.end());
 
     bool created = false;
-    int32_t s = serial ? pick_serial(&created) : pick_stream(&created);
+    int32_t s = serial ? pick_serial(&created) : lane ? pick_lane(lane, &created) : pick_stream(&created);
     place(id, s);
     *stream_out = s;
     *new_stream_out = created;
@@ -245,10 +256,18 @@ class Tracker {
     }
   }
 
-  int32_t new_stream(bool* created) {
+  int32_t new_stream(bool* created, uint8_t lane = 0) {
     streams_.emplace_back();
+    streams_.back().lane = lane;
+    if (!lane) ++npool_;
     *created = true;
     return static_cast<int32_t>(streams_.size() - 1);
+  }
+
+  int32_t pick_lane(uint8_t lane, bool* created) {
+    *created = false;
+    if (lane_stream_[lane] < 0) lane_stream_[lane] = new_stream(created, lane);
+    return lane_stream_[lane];
   }
 
   int32_t pick_serial(bool* created) {
@@ -264,6 +283,7 @@ class Tracker {
     const uint32_t np = tasks_.back().par_n;
     for (uint32_t i = 0; i < np; ++i) {
       const int32_t s = tasks_[par[i]].stream;
+      if (streams_[s].lane) continue;  // calls never join a copy lane
       if (streams_[s].tail == par[i]) {
         chosen = s;
         break;
@@ -276,11 +296,12 @@ class Tracker {
         fifo_.pop_front();
       }
     }
-    if (chosen < 0 && streams_.size() < max_streams_) chosen = new_stream(created);
+    if (chosen < 0 && npool_ < max_streams_) chosen = new_stream(created);
     if (chosen < 0) {
-      chosen = 0;
-      for (uint32_t s = 1; s < streams_.size(); ++s)
-        if (streams_[s].tail < streams_[chosen].tail) chosen = static_cast<int32_t>(s);
+      for (uint32_t s = 0; s < streams_.size(); ++s) {
+        if (streams_[s].lane) continue;
+        if (chosen < 0 || streams_[s].tail < streams_[chosen].tail) chosen = static_cast<int32_t>(s);
+      }
     }
     streams_[chosen].in_fifo = false;  // lazily dropped from fifo_
     return chosen;
@@ -350,7 +371,7 @@ class Tracker {
       --nactive_total_;
       if (retired) retired->push_back(x);
       StreamRec& st = streams_[t.stream];
-      if (--st.nactive == 0) empties_.push_back(t.stream);
+      if (--st.nactive == 0 && !st.lane) empties_.push_back(t.stream);
       const uint64_t* par = par_pool_.data() + t.par_off;
       stack_.insert(stack_.end(), par, par + t.par_n);
     }
@@ -364,6 +385,8 @@ class Tracker {
   }
 
   uint32_t max_streams_;
+  uint32_t npool_ = 0;
+  int32_t lane_stream_[4] = {-1, -1, -1, -1};
   std::vector<TaskRec> tasks_;
   std::vector<BufTrack> bufs_;
   std::vector<StreamRec> streams_;

@@ -41,7 +41,8 @@ KERNEL_NAMES = {v: k for k, v in KERNEL_IDS.items()}
 class dag_config(C.Structure):
     _fields_ = [("policy", C.c_uint32), ("max_streams", C.c_uint32), ("trace", C.c_uint32),
                 ("dry_run", C.c_uint32), ("device", C.c_int32), ("graph_mode", C.c_uint32),
-                ("scratch_bytes", C.c_uint64)]
+                ("scratch_bytes", C.c_uint64), ("copy_streams", C.c_uint32),
+                ("spin_wait", C.c_uint32)]
 
 
 class dag_arg(C.Structure):
@@ -369,10 +370,10 @@ def make_params(kernel, p):
 class Context:
     """Convenience wrapper: one execution context with its buffers."""
 
-    def __init__(self, policy=DAG_PARALLEL_ASYNC, max_streams=8, trace=False, dry_run=False,
-                 device=0, graph_mode=0, scratch_bytes=0):
-        self.cfg = dag_config(policy, max_streams, int(bool(trace)), int(bool(dry_run)), device,
-                              graph_mode, scratch_bytes)
+    def __init__(self, policy=DAG_PARALLEL_ASYNC, max_streams=8, trace=0, dry_run=False,
+                 device=0, graph_mode=0, scratch_bytes=0, copy_streams=0, spin_wait=0):
+        self.cfg = dag_config(policy, max_streams, int(trace), int(bool(dry_run)), device,
+                              graph_mode, scratch_bytes, copy_streams, int(spin_wait))
         self.h = dag_create(self.cfg)
 
     def close(self):

@@ -112,6 +112,33 @@ class Bound:
         self.base = ids[0] - 1
         return ids
 
+    # ---- recurring shapes: record once, replay as one task -----------------------
+    def _sub(self, idx):
+        arr = (D.dag_op * len(idx))()
+        for j, i in enumerate(idx):
+            arr[j] = self.ops[i]
+        return arr
+
+    def record(self, key, lo=0, hi=None):
+        """Record ops[lo:hi] (kernels and copies only) as region `key`; they
+        also run once, eagerly."""
+        hi = len(self.prog.ops) if hi is None else hi
+        idx = [i for i in range(lo, hi) if self.prog.ops[i]["kind"] in ("kernel", "copy")]
+        D.dag_region_begin(self.ctx.h, key)
+        try:
+            D.dag_submit_batch(self.ctx.h, self._sub(idx))
+        finally:
+            D.dag_region_end(self.ctx.h)
+
+    def replay(self, key, times=1, host_reads=True):
+        """Replay region `key` `times` times, then the program's host reads."""
+        ids = [D.dag_region_launch(self.ctx.h, key) for _ in range(times)]
+        if host_reads:
+            idx = [i for i, o in enumerate(self.prog.ops) if o["kind"] == "host_read"]
+            if idx:
+                ids += D.dag_submit_batch(self.ctx.h, self._sub(idx))
+        return ids
+
     # ---- results relative to the program (positions 1..n) ----------------------
     def edges(self):
         out = set()

@@ -77,3 +77,26 @@ def random_program(rnd, n_ops, n_bufs, host=True):
             args = [(rnd.choice(bufs), rnd.choice("cm")) for _ in range(k)]
             ops.append({"kind": "kernel", "kernel": "spin", "params": {}, "args": args})
     return ops
+
+
+def reach(preds, src, dst):
+    stack, seen = [dst], set()
+    while stack:
+        t = stack.pop()
+        if t == src:
+            return True
+        if t not in seen:
+            seen.add(t)
+            stack.extend(preds.get(t, ()))
+    return False
+
+
+def uncovered_edges(edges, streams, waits):
+    """Edges between GPU tasks that stream order plus event waits do not
+    order (brute-force search over the happens-before graph)."""
+    preds, last = {}, {}
+    for t in sorted(streams):
+        s = streams[t]
+        preds[t] = ([last[s]] if s in last else []) + list(waits.get(t, []))
+        last[s] = t
+    return [(s, d) for (s, d, *_rest) in edges if d in streams and s in streams and not reach(preds, s, d)]

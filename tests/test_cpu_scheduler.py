@@ -15,7 +15,7 @@ from paper_2012_09646_amd import workloads as W
 
 
 def run_dry(ops, max_streams):
-    ctx = D.Context(dry_run=True, max_streams=max_streams)
+    ctx = D.Context(dry_run=True, max_streams=max_streams, copy_streams=1)
     names = sorted({b for op in ops for b in
                     ([a for a, _ in op["args"]] if op["kind"] in ("kernel", "macro") else
                      [op["buf"]] if op["kind"] in ("host_read", "host_write") else [])})
@@ -98,14 +98,14 @@ def test_workload_programs_native(maker, pool):
     prog = maker()
     g = odag.build_dag(prog.ops)
     st, wt = odag.replay_streams(prog.ops, g, pool)
-    ctx = D.Context(dry_run=True, max_streams=pool)
+    ctx = D.Context(dry_run=True, max_streams=pool, copy_streams=1)
     b = runner.Bound(ctx, prog, upload=False)
     b.run()
     assert b.edges() == g.edges
     assert b.streams() == st
     assert {k: v for k, v in b.waits().items() if k in st} == wt
     # the single-call path gives the same DAG as the batched one
-    ctx2 = D.Context(dry_run=True, max_streams=pool)
+    ctx2 = D.Context(dry_run=True, max_streams=pool, copy_streams=1)
     b2 = runner.Bound(ctx2, prog, upload=False)
     b2.run_calls()
     assert b2.edges() == g.edges and b2.streams() == st
@@ -202,4 +202,58 @@ def test_serial_policy_computes_no_dependencies():
     ctx.kernel("spin", [(x, "m")], ns=0)
     assert ctx.edges() == []
     assert ctx.info(1).stream == ctx.info(2).stream == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("pool", [1, 4, 8])
+def test_copy_lanes(pool):
+    """Host<->device copies on one FIFO stream per direction: same edges as
+    the oracle, every edge ordered by stream order + waits, copies of each
+    direction on one lane in issue order, kernels never on a lane."""
+    prog = W.bs_program(n=64, tasks=10)
+    g = odag.build_dag(prog.ops)
+    ctx = D.Context(dry_run=True, max_streams=pool, copy_streams=0)
+    b = runner.Bound(ctx, prog, upload=False)
+    b.run()
+    assert b.edges() == g.edges
+    st = b.streams()
+    wt = b.waits()
+    assert dagcases.uncovered_edges(g.edges, st, wt) == []
+    h2d = [p for p, o in enumerate(prog.ops, 1) if o["kind"] == "copy" and o["src"].startswith("S")]
+    d2h = [p for p, o in enumerate(prog.ops, 1) if o["kind"] == "copy" and o["dst"].startswith("C")]
+    ker = [p for p, o in enumerate(prog.ops, 1) if o["kind"] == "kernel"]
+    assert len({st[p] for p in h2d}) == 1 and len({st[p] for p in d2h}) == 1
+    lanes = {st[h2d[0]], st[d2h[0]]}
+    assert len(lanes) == 2 and not lanes & {st[p] for p in ker}
+    assert len({st[p] for p in ker}) == min(pool, 10)
+    ctx.close()
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_copy_lanes_random(seed):
+    rnd = random.Random(77 + seed)
+    ctx = D.Context(dry_run=True, max_streams=rnd.choice([1, 2, 4]), copy_streams=0)
+    names = ["d%d" % i for i in range(4)] + ["h%d" % i for i in range(3)]
+    h = {n: ctx.alloc(256, D.DAG_PINNED_HOST if n[0] == "h" else D.DAG_DEVICE) for n in names}
+    ops = []
+    for _ in range(rnd.randint(5, 40)):
+        r = rnd.random()
+        if r < 0.3:
+            a, c = rnd.sample(names, 2)
+            ops.append({"kind": "copy", "dst": a, "src": c, "bytes": 16})
+            ctx.copy(h[a], h[c], 16)
+        elif r < 0.4:
+            bname = rnd.choice(names)
+            ops.append({"kind": "host_read", "buf": bname})
+            D.dag_host_read(ctx.h, h[bname])
+        else:
+            args = [(rnd.choice(names[:4]), rnd.choice("cm")) for _ in range(rnd.randint(1, 3))]
+            ops.append({"kind": "kernel", "kernel": "spin", "params": {}, "args": args})
+            ctx.kernel("spin", [(h[x], m) for x, m in args], ns=0)
+    g = odag.build_dag(ops)
+    name_of = {v: k for k, v in h.items()}
+    assert {(s, d, name_of[bb], k) for s, d, bb, k in ctx.edges()} == g.edges
+    st = {i: ctx.info(i).stream for i in range(1, len(ops) + 1) if ctx.info(i).stream >= 0}
+    wt = {i: ctx.waits(i) for i in st}
+    assert dagcases.uncovered_edges(g.edges, st, wt) == []
     ctx.close()

@@ -26,10 +26,10 @@ def test_vec(n):
     G.check_program(W.vec_program(n=n, seed=n))
 
 
-@pytest.mark.parametrize("n,tasks", [(7, 2), (100003, 3), (1 << 22, 10)])
-def test_bs(n, tasks):
-    banner("bs n=%d tasks=%d" % (n, tasks))
-    G.check_program(W.bs_program(n=n, tasks=tasks, seed=1))
+@pytest.mark.parametrize("n,tasks,lanes", [(7, 2, 1), (100003, 3, 0), (1 << 22, 10, 1), (1 << 22, 10, 0)])
+def test_bs(n, tasks, lanes):
+    banner("bs n=%d tasks=%d copy_streams=%d" % (n, tasks, lanes))
+    G.check_program(W.bs_program(n=n, tasks=tasks, seed=1), copy_streams=lanes)
 
 
 @pytest.mark.parametrize("w,h", [(1, 1), (5, 3), (100, 77), (333, 130), (2048, 2048)])
@@ -101,3 +101,47 @@ def test_policies_agree(policy, pool, batch):
     for prog in (W.img_program(side=200, height=130, seed=9), W.hits_program(n=2000, iters=4, seed=8),
                  W.bs_program(n=5000, tasks=5)):
         G.check_program(prog, policy=policy, max_streams=pool, batch=batch)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("block,cap", [(256, 1024), (64, 7), (1024, 0)])
+def test_reduction_variants(variant, block, cap):
+    banner("reductions variant=%d block=%d cap=%d" % (variant, block, cap))
+    for prog in (W.vec_program(n=(1 << 18) + 5, seed=4), W.img_program(side=130, height=97, seed=5),
+                 W.hits_program(n=1500, iters=3, seed=6)):
+        ref = G.oracle_run(prog)
+        ctx = D.Context()
+        for k in ("vec_sum_diff", "minmax", "sumsq"):
+            ctx.set_launch(k, block, cap, variant)
+        from paper_2012_09646_amd import runner
+        b = runner.Bound(ctx, prog)
+        b.run()
+        for name in prog.outputs:
+            G.assert_close(prog, name, b.read(name), ref[name])
+        ctx.close()
+
+
+@pytest.mark.parametrize("graph_mode", [0, 1])
+def test_region_replays(graph_mode):
+    """Recurring shapes replayed as one task (hipGraph or recorded multi-stream
+    replay) give the oracle's results; HITS replays one iteration 9 times."""
+    from paper_2012_09646_amd import runner
+    banner("regions graph_mode=%d" % graph_mode)
+    for prog, per, times in ((W.hits_program(n=5000, iters=10, seed=11), 6, 9),
+                             (W.img_program(side=300, height=200, seed=12), None, 3),
+                             (W.bs_program(n=30001, tasks=4, seed=13), None, 2),
+                             (W.vec_program(n=(1 << 17) + 1, seed=14), None, 1)):
+        ref = G.oracle_run(prog)
+        ctx = D.Context(graph_mode=graph_mode)
+        b = runner.Bound(ctx, prog)
+        if per:  # first iteration eagerly while recording, the rest replayed
+            b.record(1, 0, per)
+            b.replay(1, times)
+        else:    # record (runs once), restore inputs, replay
+            b.record(1)
+            for _ in range(times):
+                b.upload([n for n in prog.bufs if prog.bufs[n].init is not None])
+                b.replay(1)
+        for name in prog.outputs:
+            G.assert_close(prog, name, b.read(name), ref[name])
+        ctx.close()
