@@ -9,6 +9,9 @@ Workloads (seeded synthetic inputs, sizes of the benchmark configurations):
   img   image pipeline 2048x2048: 3 blur/Sobel/minmax/normalise branches + combine
   hits  HITS on a 2^20-vertex power-law graph (20 out-links each), 10 iterations,
         eager DAG and one-iteration graph replay
+  serve open-loop Poisson arrivals (2000/s) of request DAGs drawn uniformly from
+        the four workloads at footprint scale 2^k, k in -4..0, admitted by a 64 GB
+        device-memory budget; p50/p99 latency and req/s, concurrent vs serial
 
 The headline line is the Black-Scholes fan-out.  Prints ONE JSON line on
 stdout; progress goes to stderr.
@@ -37,7 +40,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits"])
+    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "serve"])
+    ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
+    ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"),
+                    help="kernel launch configurations from the autotuner (ignored if missing)")
     ap.add_argument("--max-streams", type=int, default=8)
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="GPU_MAX_HW_QUEUES for this process (0 = runtime default)")
@@ -62,7 +68,14 @@ def main():
     from paper_2012_09646_amd import dagrt as D
     from paper_2012_09646_amd import metrics as M
     from paper_2012_09646_amd import runner
+    from paper_2012_09646_amd import serving
+    from paper_2012_09646_amd import tune
     from paper_2012_09646_amd import workloads as W
+
+    tuned = {}
+    if args.tuned and os.path.exists(args.tuned):
+        tuned = tune.load(args.tuned).get("kernels", {})
+        log("kernel launch configurations from", args.tuned)
 
     def kernel_intervals(ctx, b, nops):
         iv = []
@@ -82,6 +95,7 @@ def main():
         def make(policy, trace):
             ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,
                             copy_streams=args.copy_streams, spin_wait=args.spin_wait)
+            tune.apply_kernels(ctx, tuned)
             b = runner.Bound(ctx, prog, read_bytes=4)
             for dst in restore:
                 if dst not in pris:
@@ -210,6 +224,7 @@ def main():
         for gm, tag in ((0, "graph"), (1, "replay")):
             ctxG = D.Context(policy=D.DAG_PARALLEL_ASYNC, max_streams=args.max_streams, graph_mode=gm,
                              copy_streams=args.copy_streams, spin_wait=args.spin_wait)
+            tune.apply_kernels(ctxG, tuned)
             bG = runner.Bound(ctxG, prog, read_bytes=4)
             for dst in restore:
                 h0 = ctxG.alloc(prog.bufs[dst].nbytes)
@@ -238,8 +253,45 @@ def main():
             ctxG.close()
         return res, ktimes
 
-    workloads = ["bs", "vec", "img", "hits"] if args.workload == "all" else [args.workload]
+    def measure_serving(graphs):
+        """Open-loop serving of the mixed trace, concurrent and serial."""
+        ctx = D.Context(spin_wait=args.spin_wait)
+        tune.apply_kernels(ctx, tuned)
+        kinds = ("vec", "bs", "img", "hits")
+        tmpls = []
+        key = 1000
+        for kind in kinds:
+            for k in W.SERVE_KS:
+                prog = W.serve_program(kind, k, seed=4, graphs=graphs)
+                tmpls.append(serving.ShapeTemplate(ctx, prog, key=key, result_bytes=64))
+                key += 1
+        budget = 64 << 30
+        srv = serving.Server(ctx, budget, host_arena_bytes=8 << 30, lanes=8, bypass=32)
+        foot = []
+        for t in tmpls:
+            sid = srv.add(t)
+            foot.append(srv.footprint(sid))
+        arr, shp = W.poisson_trace(4, args.requests, 2000.0, len(tmpls))
+        log("serving: %d requests, %d shapes" % (len(arr), len(tmpls)))
+        mix, st, _ = srv.run(arr, shp)
+        log("serving: serial baseline")
+        ser, st2, _ = srv.run(arr, shp, mode=D.DAG_SERVE_SERIAL)
+        srv.close()
+        ctx.close()
+        return {
+            "requests": len(arr), "rate_per_s": 2000.0, "shapes": len(tmpls), "budget_bytes": budget,
+            "mean_footprint_mb": float(np.mean([foot[i][0] for i in shp])) / 2 ** 20,
+            "concurrent": {"p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+                           "req_per_s": st.req_per_s, "max_inflight": st.max_inflight,
+                           "max_queued": st.max_queued, "peak_device_gb": st.peak_device_bytes / 2 ** 30},
+            "serial": {"p50_ms": st2.p50_ms, "p99_ms": st2.p99_ms, "mean_ms": st2.mean_ms,
+                       "req_per_s": st2.req_per_s, "max_queued": st2.max_queued},
+            "throughput_gain": st.req_per_s / st2.req_per_s if st2.req_per_s else None,
+        }
+
+    workloads = ["bs", "vec", "img", "hits", "serve"] if args.workload == "all" else [args.workload]
     results = {}
+    graphs = {}
     kt_bs = None
     for wl in workloads:
         if wl == "vec":
@@ -256,7 +308,17 @@ def main():
             log("hits: generating the graph")
             prog = W.hits_program(n=1 << 20, deg=20, iters=10, seed=3)
             results[wl], _ = measure(wl, prog, args.steps, args.warmup, restore=("a", "h"), per_iter=6)
+        elif wl == "serve":
+            results[wl] = measure_serving(graphs)
 
+    if "serve" in results and len(results) == 1:
+        sv = results["serve"]
+        print(json.dumps({"metric": METRIC, "value": round(sv["concurrent"]["p50_ms"], 4), "unit": "ms (p50 latency)",
+                          "n_gpus": 1, "steps": sv["requests"], "warmup": 0, "ms_per_step": None,
+                          "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": "serving_mix_poisson_2000"}, "serving": sv}),
+              flush=True)
+        return
     head = results.get("bs") or results[workloads[0]]
     line = {
         "metric": METRIC,
@@ -293,6 +355,8 @@ def main():
         line["roofline"] = {"kernel": "bs_call", "bound": "hbm", "achieved": round(ach, 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                             "traffic": None, "avg_us": round(avg * 1e3, 2), "bytes_per_launch": by}
+    if "serve" in results:
+        line["serving"] = results.pop("serve")
     line["workloads"] = results
     if "bs" in results and not args.no_cpu_baseline:
         from oracle import run as orun

@@ -250,6 +250,20 @@ dag_status dag_kernel_get_launch(dag_ctx ctx, uint32_t kernel_id, dag_launch* ou
 /* Validated against the kernel's supported set (DAG_E_INVAL otherwise). */
 dag_status dag_kernel_set_launch(dag_ctx ctx, uint32_t kernel_id, const dag_launch* cfg);
 
+/* Autotuning (the paper keeps each kernel's history to guide later
+ * scheduling, Sec. IV-A, and tunes launch parameters for serial execution,
+ * Sec. V-A): time every candidate configuration of a built-in kernel on the
+ * given arguments, alone on the GPU (reps launches back to back between two
+ * timing events, three batches, median), install the fastest as the kernel's
+ * launch configuration and return its index.  us[i] receives candidate i's
+ * time per launch in microseconds (-1 for a candidate the kernel rejects).
+ * This is a host synchronisation point: it first waits for and retires all
+ * tasks.  The launches overwrite the kernel's outputs, so pass scratch
+ * buffers (or data that may be clobbered).  Not available in dry-run mode. */
+dag_status dag_tune_kernel(dag_ctx ctx, uint32_t kernel_id, const void* params, size_t params_bytes,
+                           const dag_arg* args, uint32_t nargs, const dag_launch* candidates,
+                           uint32_t ncand, uint32_t reps, uint32_t* best, double* us);
+
 /* User kernels: fn enqueues its work on the given hipStream_t (passed as
  * void*) using the device pointers of its arguments, in order; it returns
  * 0 on success.  The scheduler treats the call like any other. */
@@ -338,6 +352,97 @@ dag_status dag_get_stats(dag_ctx ctx, dag_stats* out);
 dag_status dag_trace_reset(dag_ctx ctx);
 /* HIP stream of pool stream index i (as void*), e.g. to time on it. */
 dag_status dag_stream_handle(dag_ctx ctx, uint32_t i, void** stream);
+
+/* ---- serving loop ------------------------------------------------------------
+ * Requests are DAGs of recorded shapes (a region recorded with
+ * dag_region_begin/end on template buffers).  They arrive over time (open
+ * loop) and are admitted while the sum of the device footprints of the
+ * requests in flight stays within budget_bytes: each admitted request gets
+ * private copies of its shape's PRIVATE and INIT buffers, sub-allocated from
+ * arenas the server keeps resident (device arena for device buffers, pinned
+ * host arena for pinned ones and for staging device results), replays the
+ * shape's calls in recorded order on one of `lanes` HIP streams (the lane
+ * with the fewest requests in flight), and is retired when its completion
+ * event fires, which frees its memory for queued requests.  Requests in
+ * flight on different lanes run concurrently (space-sharing, Sec. IV-B/C
+ * applied across independent requests).  Requests are queued FIFO; up to
+ * `bypass` queued requests are examined per admission pass, so small requests
+ * can pass a large one that does not fit yet.
+ *
+ * The server uses the context's regions and kernel launch configurations;
+ * while it runs, the context must not record, drop or re-record those
+ * regions, and nothing may modify SHARED buffers.  Not thread-safe. */
+typedef struct dag_server_s* dag_server;
+
+#define DAG_ROLE_SHARED 0u  /* every request uses the template buffer itself;
+                               the region must only read it */
+#define DAG_ROLE_PRIVATE 1u /* each request gets its own, uninitialised */
+#define DAG_ROLE_INIT 2u    /* each request gets its own, first filled from
+                               init_src (same size or larger) */
+
+typedef struct {
+  dag_buf buf;      /* a buffer the shape's region uses */
+  uint32_t role;    /* DAG_ROLE_* */
+  dag_buf init_src; /* DAG_ROLE_INIT: source of the initial contents */
+  uint32_t reserved;
+} dag_shape_buf;
+
+typedef struct {
+  uint64_t budget_bytes;       /* device bytes in flight at most (the
+                                  admission budget); <= device_arena_bytes */
+  uint64_t device_arena_bytes; /* device memory the server allocates */
+  uint64_t host_arena_bytes;   /* pinned host memory the server allocates */
+  uint32_t lanes;              /* HIP streams requests are spread over */
+  uint32_t bypass;             /* queued requests examined per pass (>= 1) */
+} dag_serve_config;
+
+typedef struct {
+  uint32_t shape;      /* from dag_serve_add_shape */
+  uint32_t reserved;
+  uint64_t arrival_ns; /* scheduled arrival after the start of the run;
+                          non-decreasing over the request array */
+  void* result;        /* host memory for result_bytes, or NULL */
+} dag_request;
+
+typedef struct {
+  uint64_t admit_ns; /* enqueued on the GPU (after the start of the run) */
+  uint64_t done_ns;  /* completion observed */
+  uint32_t lane;
+  uint32_t reserved;
+} dag_request_done;
+
+typedef struct {
+  double p50_ms, p99_ms, mean_ms, max_ms; /* latency = done - arrival
+                                             (nearest-rank percentiles) */
+  double req_per_s;          /* n / (last completion - first arrival) */
+  double wall_ms;            /* run start to last completion */
+  uint64_t peak_device_bytes; /* max footprint in flight */
+  uint32_t max_inflight;
+  uint32_t max_queued;
+} dag_serve_stats;
+
+#define DAG_SERVE_CONCURRENT 0u /* continuous admission, lanes in parallel */
+#define DAG_SERVE_SERIAL 1u     /* one request at a time on one lane, the
+                                   host waiting after every call (baseline) */
+
+dag_status dag_serve_create(dag_ctx ctx, const dag_serve_config* cfg, dag_server* out);
+/* Waits for the lanes, frees the arenas. */
+dag_status dag_serve_destroy(dag_server s);
+/* Register a shape: the region recorded under region_key, the role of every
+ * buffer it uses (all must be listed), and the buffer whose first
+ * result_bytes are returned per request (0 = none).  sim_ns is the service
+ * time assumed by schedule-only contexts (dry_run), which simulate the loop
+ * on a virtual clock instead of running it. */
+dag_status dag_serve_add_shape(dag_server s, uint64_t region_key, const dag_shape_buf* bufs,
+                               uint32_t nbufs, dag_buf result_buf, size_t result_bytes,
+                               uint64_t sim_ns, uint32_t* shape_id);
+/* Per-request footprint of a shape (device arena bytes, pinned arena bytes). */
+dag_status dag_serve_shape_info(dag_server s, uint32_t shape, uint64_t* device_bytes,
+                                uint64_t* host_bytes);
+/* Run the whole arrival trace (blocks until every request completed).
+ * done[i] receives the timestamps of reqs[i]; stats may be NULL. */
+dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint32_t mode,
+                         dag_request_done* done, dag_serve_stats* stats);
 
 #ifdef __cplusplus
 }

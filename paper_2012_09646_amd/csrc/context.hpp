@@ -1,0 +1,128 @@
+// Internal: the execution context shared by the C-ABI translation units
+// (dagrt.cpp: scheduler and executor; serve.cpp: serving loop).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dagrt.h"
+#include "kernels.hpp"
+#include "tracker.hpp"
+
+namespace dagrt {
+
+using Clock = std::chrono::steady_clock;
+
+inline double us_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::micro>(Clock::now() - t0).count();
+}
+
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  uint32_t loc = 0;
+  bool owned = false;
+  bool live = false;
+};
+
+struct UserKernel {
+  std::string name;
+  dag_launch_fn fn;
+  void* user;
+};
+
+// One recorded call of a region.
+struct RegionTask {
+  uint32_t kind = 0;  // TK_KERNEL or TK_COPY
+  uint32_t kernel_id = 0;
+  std::vector<char> params;
+  std::vector<void*> ptrs;
+  LaunchCfg cfg{};
+  void* cdst = nullptr;
+  const void* csrc = nullptr;
+  size_t cbytes = 0;
+  hipMemcpyKind ckind = hipMemcpyDefault;
+  uint64_t id = 0;         // task id of the eager run
+  int32_t rstream = 0;     // region-local stream
+  std::vector<uint32_t> rwaits;  // region-local task indices waited on
+  bool waited_on = false;
+};
+
+struct Region {
+  std::vector<RegionTask> tasks;
+  std::vector<Access> accs;  // union of accesses, MUTABLE wins
+  uint32_t nstreams = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* scratch = nullptr;  // nstreams * scratch_bytes (graph mode)
+  std::vector<hipEvent_t> evs;  // replay-mode events (per task)
+};
+
+constexpr uint32_t kMaxArgs = 16;
+constexpr size_t kStagingBytes = 64 << 10;
+
+}  // namespace dagrt
+
+struct dag_ctx_s {
+  dag_config cfg{};
+  bool serial = false;
+  bool dry = false;
+  bool poisoned = false;
+  std::string err;
+  dagrt::Tracker tr;
+  std::vector<dagrt::Buffer> bufs;        // slot = handle - 1
+  std::map<uintptr_t, uint32_t> ranges;   // live buffers: base -> slot
+  uintptr_t fake_next = uintptr_t(1) << 44;
+  std::vector<hipStream_t> streams;
+  std::vector<void*> scratch;             // per pool stream
+  hipStream_t io = nullptr;
+  void* staging = nullptr;                // pinned, for small host reads
+  hipEvent_t read_ev = nullptr;
+  std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion
+  std::vector<hipEvent_t> ev0;            // per task, start (trace mode)
+  std::vector<hipEvent_t> free_ev;
+  hipEvent_t trace_ref = nullptr;
+  std::vector<uint64_t> tmp_wait, tmp_retired;
+  std::vector<dagrt::Access> tmp_acc;
+  std::vector<dagrt::UserKernel> user_kernels;
+  dagrt::LaunchCfg launch_cfg[15]{};
+  // regions
+  std::unordered_map<uint64_t, std::unique_ptr<dagrt::Region>> regions;
+  bool recording = false;
+  uint64_t rec_key = 0;
+  std::unique_ptr<dagrt::Region> rec;
+  std::vector<hipStream_t> aux;           // capture / replay streams
+  std::vector<void*> aux_scratch;
+  // stats
+  uint64_t n_waits = 0, n_host_waits = 0;
+  double submit_us = 0.0, launch_us = 0.0;
+
+  explicit dag_ctx_s(uint32_t ms) : tr(ms) {}
+};
+
+namespace dagrt {
+// Error helpers (dagrt.cpp).
+dag_status fail(dag_ctx c, dag_status st, const char* fmt, ...);
+dag_status hip_fail(dag_ctx c, hipError_t e, const char* what);
+Buffer* get_buf(dag_ctx c, dag_buf h);
+hipError_t launch_region_task(dag_ctx c, const RegionTask& t, hipStream_t s, void* scratch);
+}  // namespace dagrt
+
+#define HIP_TRY(c, call)                                            \
+  do {                                                              \
+    hipError_t e_ = (call);                                         \
+    if (e_ != hipSuccess) return ::dagrt::hip_fail((c), e_, #call); \
+  } while (0)
+
+#define CHECK_CTX(c)                                                                                     \
+  do {                                                                                                   \
+    if (!(c)) return DAG_E_INVAL;                                                                        \
+    if ((c)->poisoned) return ::dagrt::fail((c), DAG_E_POISONED, "context poisoned: %s", (c)->err.c_str()); \
+  } while (0)

@@ -16,106 +16,10 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/dagrt.h"
-#include "kernels.hpp"
-#include "tracker.hpp"
+#include "context.hpp"
+
 
 namespace dagrt {
-namespace {
-
-using Clock = std::chrono::steady_clock;
-
-double us_since(Clock::time_point t0) {
-  return std::chrono::duration<double, std::micro>(Clock::now() - t0).count();
-}
-
-struct Buffer {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-  uint32_t loc = 0;
-  bool owned = false;
-  bool live = false;
-};
-
-struct UserKernel {
-  std::string name;
-  dag_launch_fn fn;
-  void* user;
-};
-
-// One recorded call of a region.
-struct RegionTask {
-  uint32_t kind = 0;  // TK_KERNEL or TK_COPY
-  uint32_t kernel_id = 0;
-  std::vector<char> params;
-  std::vector<void*> ptrs;
-  LaunchCfg cfg{};
-  void* cdst = nullptr;
-  const void* csrc = nullptr;
-  size_t cbytes = 0;
-  hipMemcpyKind ckind = hipMemcpyDefault;
-  uint64_t id = 0;         // task id of the eager run
-  int32_t rstream = 0;     // region-local stream
-  std::vector<uint32_t> rwaits;  // region-local task indices waited on
-  bool waited_on = false;
-};
-
-struct Region {
-  std::vector<RegionTask> tasks;
-  std::vector<Access> accs;  // union of accesses, MUTABLE wins
-  uint32_t nstreams = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  void* scratch = nullptr;  // nstreams * scratch_bytes (graph mode)
-  std::vector<hipEvent_t> evs;  // replay-mode events (per task)
-};
-
-constexpr uint32_t kMaxArgs = 16;
-constexpr size_t kStagingBytes = 64 << 10;
-
-}  // namespace
-}  // namespace dagrt
-
-using namespace dagrt;
-
-struct dag_ctx_s {
-  dag_config cfg{};
-  bool serial = false;
-  bool dry = false;
-  bool poisoned = false;
-  std::string err;
-  Tracker tr;
-  std::vector<Buffer> bufs;               // slot = handle - 1
-  std::map<uintptr_t, uint32_t> ranges;   // live buffers: base -> slot
-  uintptr_t fake_next = uintptr_t(1) << 44;
-  std::vector<hipStream_t> streams;
-  std::vector<void*> scratch;             // per pool stream
-  hipStream_t io = nullptr;
-  void* staging = nullptr;                // pinned, for small host reads
-  hipEvent_t read_ev = nullptr;
-  std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion
-  std::vector<hipEvent_t> ev0;            // per task, start (trace mode)
-  std::vector<hipEvent_t> free_ev;
-  hipEvent_t trace_ref = nullptr;
-  std::vector<uint64_t> tmp_wait, tmp_retired;
-  std::vector<Access> tmp_acc;
-  std::vector<UserKernel> user_kernels;
-  LaunchCfg launch_cfg[15]{};
-  // regions
-  std::unordered_map<uint64_t, std::unique_ptr<Region>> regions;
-  bool recording = false;
-  uint64_t rec_key = 0;
-  std::unique_ptr<Region> rec;
-  std::vector<hipStream_t> aux;           // capture / replay streams
-  std::vector<void*> aux_scratch;
-  // stats
-  uint64_t n_waits = 0, n_host_waits = 0;
-  double submit_us = 0.0, launch_us = 0.0;
-
-  explicit dag_ctx_s(uint32_t ms) : tr(ms) {}
-};
-
-namespace {
 
 dag_status fail(dag_ctx c, dag_status st, const char* fmt, ...) {
   char buf[512];
@@ -132,23 +36,13 @@ dag_status hip_fail(dag_ctx c, hipError_t e, const char* what) {
   return fail(c, DAG_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(c, call)                                  \
-  do {                                                    \
-    hipError_t e_ = (call);                               \
-    if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
-  } while (0)
-
-#define CHECK_CTX(c)                                                        \
-  do {                                                                      \
-    if (!(c)) return DAG_E_INVAL;                                           \
-    if ((c)->poisoned) return fail((c), DAG_E_POISONED, "context poisoned: %s", (c)->err.c_str()); \
-  } while (0)
-
 Buffer* get_buf(dag_ctx c, dag_buf h) {
   if (h == 0 || h > c->bufs.size()) return nullptr;
   Buffer* b = &c->bufs[h - 1];
   return b->live ? b : nullptr;
 }
+
+namespace {
 
 dag_status get_event(dag_ctx c, bool timing, hipEvent_t* out) {
   if (!timing && !c->free_ev.empty()) {
@@ -525,11 +419,15 @@ void plan_region(dag_ctx c, Region* r) {
   r->nstreams = static_cast<uint32_t>(smap.size());
 }
 
+}  // namespace
+
 hipError_t launch_region_task(dag_ctx c, const RegionTask& t, hipStream_t s, void* scratch) {
   if (t.kind == TK_COPY) return hipMemcpyAsync(t.cdst, t.csrc, t.cbytes, t.ckind, s);
   const KernelDesc* kd = builtin_kernel(t.kernel_id);
   return kd->launch(s, t.ptrs.data(), t.params.data(), t.cfg, scratch, c->cfg.scratch_bytes);
 }
+
+namespace {
 
 dag_status build_graph(dag_ctx c, Region* r) {
   dag_status st = ensure_aux(c, r->nstreams);
@@ -608,6 +506,9 @@ dag_status replay_region(dag_ctx c, Region* r, hipStream_t s, int32_t pool_strea
 }
 
 }  // namespace
+}  // namespace dagrt
+
+using namespace dagrt;
 
 // ===========================================================================
 // C ABI
@@ -823,6 +724,72 @@ dag_status dag_kernel_set_launch(dag_ctx c, uint32_t kid, const dag_launch* cfg)
   LaunchCfg l{cfg->block, cfg->grid_cap, cfg->variant};
   if (const char* msg = kd->check_cfg(l)) return fail(c, DAG_E_INVAL, "%s: %s", kd->name, msg);
   c->launch_cfg[kid] = l;
+  return DAG_OK;
+}
+
+dag_status dag_tune_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pbytes, const dag_arg* args,
+                           uint32_t nargs, const dag_launch* cands, uint32_t ncand, uint32_t reps, uint32_t* best,
+                           double* us) {
+  CHECK_CTX(c);
+  if (c->dry) return fail(c, DAG_E_UNSUPPORTED, "tuning needs a GPU");
+  if (c->recording) return fail(c, DAG_E_BUSY, "tuning inside a region");
+  const KernelDesc* kd = builtin_kernel(kid);
+  if (!kd) return fail(c, DAG_E_NOTFOUND, "unknown kernel id %u", kid);
+  if (!cands || ncand == 0 || !best) return fail(c, DAG_E_INVAL, "candidates and best are required");
+  if (reps == 0 || reps > 10000) return fail(c, DAG_E_INVAL, "reps must be in [1, 10000]");
+  if (pbytes != kd->params_bytes || !params) return fail(c, DAG_E_INVAL, "%s: params must be %zu bytes", kd->name, kd->params_bytes);
+  if ((kd->nargs && nargs != kd->nargs) || nargs > kMaxArgs) return fail(c, DAG_E_INVAL, "%s: wrong argument count", kd->name);
+  void* ptrs[kMaxArgs];
+  size_t sizes[kMaxArgs];
+  for (uint32_t i = 0; i < nargs; ++i) {
+    Buffer* b = get_buf(c, args[i].buf);
+    if (!b || b->loc != DAG_DEVICE) return fail(c, DAG_E_INVAL, "argument %u: invalid device buffer", i);
+    ptrs[i] = b->ptr;
+    sizes[i] = b->bytes;
+  }
+  dag_status st = do_sync(c);
+  if (st) return st;
+  st = ensure_stream(c, 0);
+  if (st) return st;
+  hipStream_t s = c->streams[0];
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  double best_us = -1.0;
+  *best = ncand;
+  for (uint32_t k = 0; k < ncand; ++k) {
+    const LaunchCfg cfg{cands[k].block, cands[k].grid_cap, cands[k].variant};
+    if (us) us[k] = -1.0;
+    if (kd->check_cfg(cfg) || kd->validate(params, sizes, nargs, cfg, c->cfg.scratch_bytes)) continue;
+    double batch[3];
+    hipError_t e = hipSuccess;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = kd->launch(s, ptrs, params, cfg, c->scratch[0], c->cfg.scratch_bytes);
+    for (int bt = 0; bt < 3 && e == hipSuccess; ++bt) {
+      e = hipEventRecord(e0, s);
+      for (uint32_t r = 0; r < reps && e == hipSuccess; ++r)
+        e = kd->launch(s, ptrs, params, cfg, c->scratch[0], c->cfg.scratch_bytes);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      batch[bt] = 1e3 * ms / reps;
+    }
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return hip_fail(c, e, "tuning launch");
+    }
+    std::sort(batch, batch + 3);
+    if (us) us[k] = batch[1];
+    if (best_us < 0 || batch[1] < best_us) {
+      best_us = batch[1];
+      *best = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (*best == ncand) return fail(c, DAG_E_INVAL, "%s: no valid candidate", kd->name);
+  c->launch_cfg[kid] = LaunchCfg{cands[*best].block, cands[*best].grid_cap, cands[*best].variant};
   return DAG_OK;
 }
 

@@ -102,6 +102,36 @@ class dag_p_spin(C.Structure):
     _fields_ = [("ns", C.c_uint64)]
 
 
+class dag_shape_buf(C.Structure):
+    _fields_ = [("buf", C.c_uint32), ("role", C.c_uint32), ("init_src", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class dag_serve_config(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("device_arena_bytes", C.c_uint64),
+                ("host_arena_bytes", C.c_uint64), ("lanes", C.c_uint32), ("bypass", C.c_uint32)]
+
+
+class dag_request(C.Structure):
+    _fields_ = [("shape", C.c_uint32), ("reserved", C.c_uint32), ("arrival_ns", C.c_uint64),
+                ("result", C.c_void_p)]
+
+
+class dag_request_done(C.Structure):
+    _fields_ = [("admit_ns", C.c_uint64), ("done_ns", C.c_uint64), ("lane", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class dag_serve_stats(C.Structure):
+    _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("max_ms", C.c_double), ("req_per_s", C.c_double), ("wall_ms", C.c_double),
+                ("peak_device_bytes", C.c_uint64), ("max_inflight", C.c_uint32),
+                ("max_queued", C.c_uint32)]
+
+
+DAG_ROLE_SHARED, DAG_ROLE_PRIVATE, DAG_ROLE_INIT = 0, 1, 2
+DAG_SERVE_CONCURRENT, DAG_SERVE_SERIAL = 0, 1
+
 DAG_LAUNCH_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p,
                             C.c_void_p)
 
@@ -119,6 +149,8 @@ _SIGS = {
     "dag_buffer_ptr": (_st, [_ctx_t, C.c_uint32, _P(C.c_void_p), _P(C.c_size_t)]),
     "dag_kernel_get_launch": (_st, [_ctx_t, C.c_uint32, _P(dag_launch)]),
     "dag_kernel_set_launch": (_st, [_ctx_t, C.c_uint32, _P(dag_launch)]),
+    "dag_tune_kernel": (_st, [_ctx_t, C.c_uint32, C.c_void_p, C.c_size_t, _P(dag_arg), C.c_uint32,
+                              _P(dag_launch), C.c_uint32, C.c_uint32, _P(C.c_uint32), _P(C.c_double)]),
     "dag_kernel_register": (_st, [_ctx_t, C.c_char_p, DAG_LAUNCH_FN, C.c_void_p, _P(C.c_uint32)]),
     "dag_submit_kernel": (_st, [_ctx_t, C.c_uint32, C.c_void_p, C.c_size_t, _P(dag_arg), C.c_uint32,
                                 _P(C.c_uint64)]),
@@ -139,6 +171,13 @@ _SIGS = {
     "dag_get_stats": (_st, [_ctx_t, _P(dag_stats)]),
     "dag_trace_reset": (_st, [_ctx_t]),
     "dag_stream_handle": (_st, [_ctx_t, C.c_uint32, _P(C.c_void_p)]),
+    "dag_serve_create": (_st, [_ctx_t, _P(dag_serve_config), _P(C.c_void_p)]),
+    "dag_serve_destroy": (_st, [C.c_void_p]),
+    "dag_serve_add_shape": (_st, [C.c_void_p, C.c_uint64, _P(dag_shape_buf), C.c_uint32, C.c_uint32,
+                                  C.c_size_t, C.c_uint64, _P(C.c_uint32)]),
+    "dag_serve_shape_info": (_st, [C.c_void_p, C.c_uint32, _P(C.c_uint64), _P(C.c_uint64)]),
+    "dag_serve_run": (_st, [C.c_void_p, _P(dag_request), C.c_uint32, C.c_uint32, _P(dag_request_done),
+                            _P(dag_serve_stats)]),
 }
 
 _lib = None
@@ -223,6 +262,19 @@ def dag_kernel_get_launch(ctx, kid):
 
 def dag_kernel_set_launch(ctx, kid, cfg):
     _check(ctx, lib().dag_kernel_set_launch(ctx, kid, C.byref(cfg)))
+
+
+def dag_tune_kernel(ctx, kid, params, args, candidates, reps=20):
+    """candidates: [(block, grid_cap, variant)].  Returns (best index, [us])."""
+    arr = _args_array(args)
+    cands = (dag_launch * len(candidates))()
+    for i, (b, g, v) in enumerate(candidates):
+        cands[i] = dag_launch(b, g, v, 0)
+    best = C.c_uint32()
+    us = (C.c_double * len(candidates))()
+    _check(ctx, lib().dag_tune_kernel(ctx, kid, C.byref(params), C.sizeof(params), arr, len(args), cands,
+                                      len(candidates), reps, C.byref(best), us))
+    return best.value, list(us)
 
 
 def dag_kernel_register(ctx, name, fn, user=None):
@@ -348,6 +400,45 @@ def dag_stream_handle(ctx, i):
     out = C.c_void_p()
     _check(ctx, lib().dag_stream_handle(ctx, i, C.byref(out)))
     return out.value
+
+
+def dag_serve_create(ctx, cfg):
+    out = C.c_void_p()
+    _check(ctx, lib().dag_serve_create(ctx, C.byref(cfg), C.byref(out)))
+    return out
+
+
+def dag_serve_destroy(srv):
+    lib().dag_serve_destroy(srv)
+
+
+def dag_serve_add_shape(ctx, srv, key, bufs, result_buf, result_bytes, sim_ns=0):
+    """bufs: [(handle, role, init_src)]; returns the shape id.  ctx is used
+    for the error message."""
+    arr = (dag_shape_buf * len(bufs))()
+    for i, (b, role, src) in enumerate(bufs):
+        arr[i].buf, arr[i].role, arr[i].init_src = b, role, src
+    sid = C.c_uint32()
+    _check(ctx, lib().dag_serve_add_shape(srv, key, arr, len(bufs), result_buf, result_bytes, sim_ns,
+                                          C.byref(sid)))
+    return sid.value
+
+
+def dag_serve_shape_info(srv, shape):
+    a, b = C.c_uint64(), C.c_uint64()
+    st = lib().dag_serve_shape_info(srv, shape, C.byref(a), C.byref(b))
+    if st != DAG_OK:
+        raise DagError(st, "dag_serve_shape_info")
+    return a.value, b.value
+
+
+def dag_serve_run(ctx, srv, reqs, mode):
+    """reqs: ctypes array of dag_request.  Returns (done array, stats)."""
+    n = len(reqs)
+    done = (dag_request_done * max(n, 1))()
+    stats = dag_serve_stats()
+    _check(ctx, lib().dag_serve_run(srv, reqs, n, mode, done, C.byref(stats)))
+    return done, stats
 
 
 # ---- parameter blocks ------------------------------------------------------------

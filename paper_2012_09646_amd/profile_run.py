@@ -1,0 +1,50 @@
+"""Launch a workload's DAG a few times plus a plain copy kernel of known size,
+for profiler runs (kernel traces, and hardware-counter passes that need a
+reference kernel to calibrate byte counters against).
+
+Usage (under a profiler):
+  python3 -m paper_2012_09646_amd.profile_run --workload bs --runs 3 --copy-mib 256
+Prints one JSON line describing what was launched.
+"""
+
+import argparse
+import json
+import os
+
+from . import dagrt as D
+from . import runner
+from . import tune
+from . import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="bs", choices=["vec", "bs", "img", "hits"])
+    ap.add_argument("--runs", type=int, default=3)
+    ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--copies", type=int, default=3)
+    ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"))
+    args = ap.parse_args()
+    prog, _ = tune.workload_program(args.workload)
+    ctx = D.Context()
+    if args.tuned and os.path.exists(args.tuned):
+        tune.apply_kernels(ctx, tune.load(args.tuned).get("kernels", {}))
+    b = runner.Bound(ctx, prog, read_bytes=4)
+    for _ in range(args.runs):
+        b.run()
+    ctx.sync()
+    n = args.copy_mib << 18  # fp32 elements
+    src = ctx.alloc(4 * n)
+    dst = ctx.alloc(4 * n)
+    for _ in range(args.copies):
+        ctx.kernel("copy_f32", [(src, "c"), (dst, "m")], n=n)
+    ctx.sync()
+    ctx.close()
+    print(json.dumps({"workload": args.workload, "runs": args.runs, "copy_f32_bytes_read": 4 * n,
+                      "copy_f32_bytes_written": 4 * n, "copies": args.copies}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+"""Autotuner: launch configurations of the task kernels and the scheduler's
+DAG-level knobs.
+
+Kernels are tuned alone on the GPU, as the paper tunes launch parameters for
+serial execution (Sec. V-A): for every kernel a workload uses, each candidate
+(threads per workgroup, grid cap, kernel variant) is timed by
+``dag_tune_kernel`` on the workload's own buffers after one full run of the
+workload (so every input holds realistic data), summed over the kernel's
+occurrences, and the fastest is kept.  The DAG knobs (stream pool size, copy
+placement) are then chosen by the median makespan of whole runs.  Results are
+stored as JSON keyed by GPU architecture, kernel and problem size, and loaded
+with ``apply``.
+
+Usage: python -m paper_2012_09646_amd.tune --workload img --out tuned.json
+"""
+
+import argparse
+import json
+import os
+import statistics
+import time
+
+from . import dagrt as D
+from . import runner
+from . import workloads as W
+
+ARCH = "gfx950"
+BLOCKS = (64, 128, 256, 512, 1024)
+CAPS = (0, 1024, 4096)
+
+
+def candidates(kernel):
+    """Candidate (block, grid_cap, variant) triples of a built-in kernel."""
+    if kernel in ("vec_square", "bs_call", "normalise", "unsharp_combine", "scale_l2", "copy_f32"):
+        return [(b, c, 0) for b in BLOCKS for c in CAPS]
+    if kernel in ("vec_sum_diff", "minmax", "sumsq"):
+        return [(b, c, v) for b in (256, 512, 1024) for c in (256, 512, 1024, 2048) for v in (0, 1)]
+    if kernel == "spmv":
+        return [(256, 0, v) for v in (4, 8, 12, 16)]
+    return []  # fixed-tile kernels (blur, Sobel) and the delay kernel
+
+
+def size_key(op):
+    p = op.get("params", {})
+    return ",".join("%s=%s" % (k, p[k]) for k in sorted(p) if k in ("n", "w", "h", "nrows", "nnz", "ksize"))
+
+
+def tune_kernels(ctx, prog, reps=20, log=None):
+    """Tune every tunable kernel of `prog` in context `ctx`; installs the
+    winners in ctx and returns {kernel: entry}."""
+    b = runner.Bound(ctx, prog, read_bytes=0)
+    b.run()
+    ctx.sync()
+    occ = {}
+    for op in prog.ops:
+        if op["kind"] == "kernel" and candidates(op["kernel"]):
+            occ.setdefault(op["kernel"], []).append(op)
+    out = {}
+    for k, ops in occ.items():
+        cands = candidates(k)
+        total = [0.0] * len(cands)
+        for op in ops:
+            prm = D.make_params(k, op["params"])
+            args = [(b.h[n], D.DAG_MUTABLE if m == "m" else D.DAG_CONST) for n, m in op["args"]]
+            _, us = D.dag_tune_kernel(ctx.h, D.KERNEL_IDS[k], prm, args, cands, reps)
+            total = [t + u if (t >= 0 and u >= 0) else -1.0 for t, u in zip(total, us)]
+        valid = [i for i, t in enumerate(total) if t >= 0]
+        best = min(valid, key=lambda i: total[i])
+        default = ctx.get_launch(k)
+        di = cands.index(default) if default in cands else None
+        ctx.set_launch(k, *cands[best])
+        out[k] = {"block": cands[best][0], "grid_cap": cands[best][1], "variant": cands[best][2],
+                  "us": total[best] / len(ops), "size": size_key(ops[0]), "launches": len(ops),
+                  "default_us": (total[di] / len(ops)) if di is not None and total[di] >= 0 else None}
+        if log:
+            log("tuned %s: %s %.2f us (default %s)" % (k, cands[best], out[k]["us"], out[k]["default_us"]))
+    b.release()
+    return out
+
+
+def tune_dag(prog, kernels, pools=(1, 2, 4, 8, 16), copy_modes=(0, 1), runs=15, restore=(), log=None):
+    """Choose max_streams and copy placement by median makespan."""
+    best = None
+    table = []
+    for cm in copy_modes:
+        if cm == 1 and not any(o["kind"] == "copy" for o in prog.ops):
+            continue
+        for ms in pools:
+            ctx = D.Context(max_streams=ms, copy_streams=cm)
+            apply_kernels(ctx, kernels)
+            b = runner.Bound(ctx, prog, read_bytes=4)
+            pris = {}
+            for dst in restore:
+                pris[dst] = ctx.alloc(prog.bufs[dst].nbytes)
+                ctx.host_write(pris[dst], prog.bufs[dst].init)
+            ts = []
+            for i in range(runs + 2):
+                for dst in restore:
+                    ctx.copy(b.h[dst], pris[dst], prog.bufs[dst].nbytes)
+                ctx.sync()
+                t0 = time.perf_counter()
+                b.run()
+                if i >= 2:
+                    ts.append((time.perf_counter() - t0) * 1e3)
+            ctx.close()
+            m = statistics.median(ts)
+            table.append({"max_streams": ms, "copy_streams": cm, "ms": m})
+            if log:
+                log("dag %s: max_streams=%d copy_streams=%d %.4f ms" % (prog.name, ms, cm, m))
+            if best is None or m < best["ms"]:
+                best = {"max_streams": ms, "copy_streams": cm, "ms": m}
+    return best, table
+
+
+def apply_kernels(ctx, kernels):
+    for k, e in (kernels or {}).items():
+        ctx.set_launch(k, e["block"], e["grid_cap"], e["variant"])
+
+
+def load(path):
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("arch") != ARCH:
+        raise ValueError("tuning file is for %s, not %s" % (data.get("arch"), ARCH))
+    return data
+
+
+def save(path, data):
+    data = dict(data)
+    data["arch"] = ARCH
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def workload_program(name):
+    if name == "vec":
+        return W.vec_program(n=1 << 20, seed=0), ("x", "y")
+    if name == "bs":
+        return W.bs_program(n=1 << 22, tasks=10, seed=1), ()
+    if name == "img":
+        return W.img_program(side=2048, seed=2), ()
+    if name == "hits":
+        return W.hits_program(n=1 << 20, iters=10, seed=3), ("a", "h")
+    raise ValueError(name)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits"])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--dag", action="store_true", help="also tune pool size and copy placement")
+    args = ap.parse_args()
+    log = lambda *a: print("[tune]", *a, flush=True)
+    data = {"kernels": {}, "dag": {}}
+    names = ["vec", "bs", "img", "hits"] if args.workload == "all" else [args.workload]
+    for name in names:
+        prog, restore = workload_program(name)
+        ctx = D.Context()
+        ks = tune_kernels(ctx, prog, args.reps, log)
+        ctx.close()
+        for k, e in ks.items():
+            prev = data["kernels"].get(k)
+            if prev is None or e["launches"] >= prev.get("launches", 0):
+                data["kernels"][k] = e
+        if args.dag:
+            best, table = tune_dag(prog, data["kernels"], restore=restore, log=log)
+            data["dag"][name] = dict(best, table=table)
+    save(args.out, data)
+    log("wrote", args.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,6 +109,7 @@ class Program:
     bufs: dict
     ops: list
     outputs: list           # buffer names whose final contents are checked
+    result: str = ""        # the buffer a serving request returns
 
 
 def K(kernel, args, **params):
@@ -134,7 +135,7 @@ def vec_program(n=1 << 20, seed=0):
            K("vec_square", [("y", "m")], n=n),
            K("vec_sum_diff", [("x", "c"), ("y", "c"), ("r", "m")], n=n),
            HR("r")]
-    return Program("vec", bufs, ops, ["x", "y", "r"])
+    return Program("vec", bufs, ops, ["x", "y", "r"], "r")
 
 
 BS_K, BS_R, BS_SIGMA, BS_T = 25.0, 0.08, 0.3, 1.0
@@ -157,7 +158,7 @@ def bs_program(n=1 << 22, tasks=10, seed=1):
         ops.append(COPY("C%d" % i, "dC%d" % i, 4 * n))
     for i in range(tasks):
         ops.append(HR("C%d" % i))
-    return Program("bs", bufs, ops, ["C%d" % i for i in range(tasks)])
+    return Program("bs", bufs, ops, ["C%d" % i for i in range(tasks)], "C0")
 
 
 IMG_KSIZES = (3, 7, 15)
@@ -190,7 +191,7 @@ def img_program(side=2048, seed=2, height=None):
     ops.append(HR("out"))
     outs = ["B%d" % k for k in IMG_KSIZES] + ["S%d" % k for k in IMG_KSIZES] + \
            ["M%d" % k for k in IMG_KSIZES] + ["N%d" % k for k in IMG_KSIZES] + ["out"]
-    return Program("img", bufs, ops, outs)
+    return Program("img", bufs, ops, outs, "out")
 
 
 def hits_graph(n=1 << 20, deg=20, seed=3, alpha=1.5):
@@ -233,7 +234,7 @@ def hits_program(n=1 << 20, deg=20, iters=10, seed=3, graph=None):
         ops.extend(hits_iteration_ops(n, nnz))
     ops.append(HR("a"))
     ops.append(HR("h"))
-    return Program("hits", bufs, ops, ["a", "h", "at", "ht", "sa", "sh"])
+    return Program("hits", bufs, ops, ["a", "h", "at", "ht", "sa", "sh"], "a")
 
 
 def initial_arrays(prog):
@@ -248,3 +249,43 @@ def initial_arrays(prog):
                 raise ValueError("init size mismatch for %s" % name)
             out[name] = arr
     return out
+
+
+# ---------------------------------------------------------------------------
+# Serving mix: request shapes and arrival traces
+# ---------------------------------------------------------------------------
+SERVE_KS = (-4, -3, -2, -1, 0)
+
+
+def img_side(k):
+    """Image side for size scale 2^k (pixels scale with 2^k), rounded to 32."""
+    return int(round(2048 * 2.0 ** (k / 2.0) / 32.0)) * 32
+
+
+def serve_program(kind, k, seed=4, graphs=None):
+    """Program of one request shape: workload `kind` at footprint scale 2^k."""
+    if kind == "vec":
+        return vec_program(n=1 << (20 + k), seed=seed)
+    if kind == "bs":
+        return bs_program(n=1 << (22 + k), tasks=10, seed=seed)
+    if kind == "img":
+        return img_program(side=img_side(k), seed=seed)
+    if kind == "hits":
+        n = 1 << (20 + k)
+        g = graphs.get(n) if graphs is not None else None
+        if g is None:
+            g = hits_graph(n, 20, seed)
+            if graphs is not None:
+                graphs[n] = g
+        return hits_program(n=n, iters=10, graph=g)
+    raise ValueError(kind)
+
+
+def poisson_trace(seed, n, rate_per_s, nshapes):
+    """Open-loop arrivals: exponential inter-arrival times at `rate_per_s`,
+    shapes uniform over range(nshapes).  Returns (arrival_ns int64, shape int32)."""
+    g = rng(seed)
+    gaps = g.exponential(1e9 / rate_per_s, size=n)
+    arrival = np.cumsum(gaps).astype(np.int64)
+    shape = g.integers(0, nshapes, size=n).astype(np.int32)
+    return arrival, shape

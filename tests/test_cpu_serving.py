@@ -1,0 +1,115 @@
+"""The serving loop's admission logic, simulated on a virtual clock by a
+schedule-only context (no GPU): budget, bypass, lanes, serial mode."""
+
+import numpy as np
+import pytest
+
+from paper_2012_09646_amd import dagrt as D
+from paper_2012_09646_amd import serving
+from paper_2012_09646_amd import workloads as W
+
+
+def make(budget, lanes=4, bypass=32):
+    ctx = D.Context(dry_run=True)
+    small = serving.ShapeTemplate(ctx, W.vec_program(n=1 << 10), key=1)
+    big = serving.ShapeTemplate(ctx, W.img_program(side=256), key=2)
+    srv = serving.Server(ctx, budget, host_arena_bytes=1 << 20, lanes=lanes, bypass=bypass)
+    s0 = srv.add(small, sim_ns=10_000)
+    s1 = srv.add(big, sim_ns=100_000)
+    return ctx, srv, s0, s1
+
+
+def test_roles_and_footprints():
+    ctx, srv, s0, s1 = make(1 << 30)
+    t = srv.shapes[0]
+    roles = {t.bound.name_of[h]: r for h, r, _ in t.roles}
+    assert roles == {"x": D.DAG_ROLE_INIT, "y": D.DAG_ROLE_INIT, "r": D.DAG_ROLE_PRIVATE}
+    dev, host = srv.footprint(s0)
+    assert dev == 2 * 4096 + 256 and host == 256   # x, y, r (256-aligned) + staged result
+    roles1 = {srv.shapes[1].bound.name_of[h]: r for h, r, _ in srv.shapes[1].roles}
+    assert roles1["img"] == D.DAG_ROLE_SHARED and roles1["out"] == D.DAG_ROLE_PRIVATE
+    srv.close()
+    ctx.close()
+
+
+def test_budget_binds_and_everything_completes():
+    ctx, srv, s0, s1 = make(1 << 30)
+    big = srv.footprint(s1)[0]
+    srv.close()
+    ctx.close()
+    ctx, srv, s0, s1 = make(2 * big + 1000, lanes=8)
+    arr, shp = W.poisson_trace(7, 400, 50_000, 2)
+    out, st, _ = srv.run(arr, shp)
+    assert st.peak_device_bytes <= 2 * big + 1000
+    assert st.max_queued > 0 and st.max_inflight >= 2
+    assert np.all(out["admit_ns"] >= arr) and np.all(out["done_ns"] > out["admit_ns"])
+    lat = np.sort((out["done_ns"] - arr) / 1e6)
+    assert abs(st.p50_ms - lat[int(np.ceil(0.5 * len(lat))) - 1]) < 1e-9
+    assert abs(st.p99_ms - lat[int(np.ceil(0.99 * len(lat))) - 1]) < 1e-9
+    srv.close()
+    ctx.close()
+
+
+def test_small_requests_bypass_a_big_one_that_does_not_fit():
+    ctx, srv, s0, s1 = make(1 << 30)
+    big = srv.footprint(s1)[0]
+    small = srv.footprint(s0)[0]
+    srv.close()
+    ctx.close()
+    # budget fits one big request plus a few small ones, not two big ones
+    ctx, srv, s0, s1 = make(big + 4 * small, lanes=4)
+    arr = np.array([0, 1, 2, 3, 4], dtype=np.int64)
+    shp = np.array([s1, s1, s0, s0, s0], dtype=np.int32)
+    out, st, _ = srv.run(arr, shp)
+    # the second big request waits for the first; the small ones do not wait for it
+    assert out["admit_ns"][1] >= out["done_ns"][0]
+    assert np.all(out["admit_ns"][2:] < out["done_ns"][0])
+    srv.close()
+    # without bypass the small ones queue behind the second big request
+    ctx2, srv2, a0, a1 = make(big + 4 * small, lanes=4, bypass=1)
+    out2, _, _ = srv2.run(arr, np.array([a1, a1, a0, a0, a0], dtype=np.int32))
+    assert np.all(out2["admit_ns"][2:] >= out2["admit_ns"][1])
+    srv2.close()
+    ctx.close()
+    ctx2.close()
+
+
+def test_serial_mode_runs_one_at_a_time():
+    ctx, srv, s0, s1 = make(1 << 30)
+    arr, shp = W.poisson_trace(3, 60, 100_000, 2)
+    out, st, _ = srv.run(arr, shp, mode=D.DAG_SERVE_SERIAL)
+    order = np.argsort(out["admit_ns"], kind="stable")
+    assert np.all(out["admit_ns"][order][1:] >= out["done_ns"][order][:-1])
+    assert st.max_inflight == 1 and np.all(out["lane"] == 0)
+    srv.close()
+    ctx.close()
+
+
+def test_lanes_share_load():
+    ctx, srv, s0, s1 = make(1 << 30, lanes=4)
+    arr = np.zeros(40, dtype=np.int64)
+    shp = np.zeros(40, dtype=np.int32)
+    out, st, _ = srv.run(arr, shp)
+    assert sorted(np.bincount(out["lane"], minlength=4).tolist()) == [10, 10, 10, 10]
+    assert st.max_inflight == 40
+    srv.close()
+    ctx.close()
+
+
+def test_shape_validation():
+    ctx = D.Context(dry_run=True)
+    t = serving.ShapeTemplate(ctx, W.vec_program(n=256), key=3)
+    srv = serving.Server(ctx, 1 << 20, host_arena_bytes=1 << 16, lanes=2)
+    with pytest.raises(D.DagError):   # a buffer the region modifies declared shared
+        D.dag_serve_add_shape(ctx.h, srv.h, 3, [(h, D.DAG_ROLE_SHARED, 0) for h, _, _ in t.roles],
+                              t.bound.h["r"], 4, 0)
+    with pytest.raises(D.DagError):   # a buffer of the region missing
+        D.dag_serve_add_shape(ctx.h, srv.h, 3, t.roles[:1], 0, 0, 0)
+    with pytest.raises(D.DagError):   # unknown region
+        D.dag_serve_add_shape(ctx.h, srv.h, 99, t.roles, 0, 0, 0)
+    small = serving.Server(ctx, 1024, host_arena_bytes=1 << 16, lanes=1)
+    with pytest.raises(D.DagError):   # footprint beyond the budget
+        small.add(t)
+    small.close()
+    srv.close()
+    ctx.close()

@@ -1,0 +1,39 @@
+"""Autotuner host logic: candidate sets are valid launch configurations,
+the JSON round trip, and applying a tuning table to a context."""
+
+import pytest
+
+from paper_2012_09646_amd import dagrt as D
+from paper_2012_09646_amd import tune
+
+
+@pytest.mark.parametrize("kernel", sorted(D.KERNEL_IDS))
+def test_candidates_accepted_by_the_library(kernel):
+    ctx = D.Context(dry_run=True)
+    for c in tune.candidates(kernel):
+        ctx.set_launch(kernel, *c)
+        assert ctx.get_launch(kernel) == c
+    ctx.close()
+
+
+def test_json_round_trip_and_apply(tmp_path):
+    data = {"kernels": {"bs_call": {"block": 512, "grid_cap": 1024, "variant": 0, "us": 40.0},
+                        "spmv": {"block": 256, "grid_cap": 0, "variant": 16, "us": 30.0}},
+            "dag": {"bs": {"max_streams": 4, "copy_streams": 0, "ms": 3.9}}}
+    p = str(tmp_path / "t.json")
+    tune.save(p, data)
+    back = tune.load(p)
+    assert back["arch"] == "gfx950" and back["kernels"] == data["kernels"]
+    ctx = D.Context(dry_run=True)
+    tune.apply_kernels(ctx, back["kernels"])
+    assert ctx.get_launch("bs_call") == (512, 1024, 0) and ctx.get_launch("spmv") == (256, 0, 16)
+    ctx.close()
+
+
+def test_tune_kernel_needs_a_gpu():
+    ctx = D.Context(dry_run=True)
+    x = ctx.alloc(4096)
+    with pytest.raises(D.DagError) as e:
+        D.dag_tune_kernel(ctx.h, 1, D.dag_p_n(1024), [(x, D.DAG_MUTABLE)], [(256, 0, 0)])
+    assert e.value.name == "DAG_E_UNSUPPORTED"
+    ctx.close()
