@@ -31,6 +31,9 @@
  *     returns DAG_E_HIP and every later call except dag_destroy,
  *     dag_last_error and the introspection calls returns DAG_E_POISONED.
  *   - A context is used by one host thread at a time (not thread-safe).
+ *   - Testing hook: if the environment variable DAGRT_FAULT_LAUNCH=N is set
+ *     when a context is created, its N-th kernel launch fails with DAG_E_HIP
+ *     (without launching anything) and poisons the context.
  *   - Pointers are plain host or device addresses; sizes are in bytes unless
  *     stated.  Nothing in this header refers to a framework type.
  *   - Task ids are 1-based positions in program order (every submit, host

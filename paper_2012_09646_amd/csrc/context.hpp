@@ -100,6 +100,9 @@ struct dag_ctx_s {
   std::unique_ptr<dagrt::Region> rec;
   std::vector<hipStream_t> aux;           // capture / replay streams
   std::vector<void*> aux_scratch;
+  // failure injection (tests): the fault_at-th kernel launch reports an error
+  // instead of launching; 0 = off
+  uint64_t fault_at = 0, n_launches = 0;
   // stats
   uint64_t n_waits = 0, n_host_waits = 0;
   double submit_us = 0.0, launch_us = 0.0;

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -198,6 +199,8 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
   const auto t1 = Clock::now();
   st = begin_task(c, id, s);
   if (st) return st;
+  if (c->fault_at && ++c->n_launches == c->fault_at)
+    return hip_fail(c, hipErrorLaunchFailure, "injected launch failure (DAGRT_FAULT_LAUNCH)");
   if (!c->dry) {
     if (kd) {
       hipError_t e = kd->launch(c->streams[s], ptrs, params, cfg, c->scratch[s], c->cfg.scratch_bytes);
@@ -552,6 +555,7 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   x->cfg = c;
   x->serial = c.policy == DAG_SERIAL_SYNC;
   x->dry = c.dry_run != 0;
+  if (const char* f = std::getenv("DAGRT_FAULT_LAUNCH")) x->fault_at = std::strtoull(f, nullptr, 10);
   for (uint32_t k = 0; k < 15; ++k) {
     const KernelDesc* kd = builtin_kernel(k);
     if (kd) x->launch_cfg[k] = kd->def;

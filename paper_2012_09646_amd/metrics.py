@@ -125,3 +125,38 @@ def algorithmic_bytes(kernel, p):
     if kernel == "copy_f32":
         return 8 * p["n"]
     return 0
+
+
+def rocprof_intervals(kernel_csv, copy_csv=None, name_filter=None):
+    """(kind, start_ns, end_ns, name) from rocprofv3 --kernel-trace /
+    --memory-copy-trace CSV files; kind 'C' for kernels, 'T' for copies
+    between host and device (device-to-device copies count as kernels)."""
+    import csv
+    out = []
+    with open(kernel_csv) as f:
+        for r in csv.DictReader(f):
+            if name_filter and not name_filter(r["Kernel_Name"]):
+                continue
+            out.append(("C", int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    if copy_csv:
+        with open(copy_csv) as f:
+            for r in csv.DictReader(f):
+                d = r["Direction"]
+                kind = "T" if ("HOST_TO_DEVICE" in d or "DEVICE_TO_HOST" in d) else "C"
+                out.append((kind, int(r["Start_Timestamp"]), int(r["End_Timestamp"]), d))
+    out.sort(key=lambda e: e[1])
+    return out
+
+
+def split_runs(intervals, gap_ns):
+    """Split a sorted timeline into runs separated by idle gaps > gap_ns."""
+    runs, cur, end = [], [], None
+    for e in intervals:
+        if cur and e[1] - end > gap_ns:
+            runs.append(cur)
+            cur = []
+        cur.append(e)
+        end = e[2] if end is None or not cur[:-1] else max(end, e[2])
+    if cur:
+        runs.append(cur)
+    return runs

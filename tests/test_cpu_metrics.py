@@ -42,3 +42,18 @@ def test_percentile_nearest_rank():
     v = list(range(1, 101))
     assert M.percentile(v, 50) == 50 and M.percentile(v, 99) == 99 and M.percentile(v, 100) == 100
     assert M.percentile([3, 1, 2], 50) == 2
+
+
+def test_rocprof_intervals_and_runs(tmp_path):
+    k = tmp_path / "k.csv"
+    c = tmp_path / "c.csv"
+    k.write_text('"Kernel_Name","Start_Timestamp","End_Timestamp"\n"a",100,200\n"b",150,260\n"a",10000,10100\n')
+    c.write_text('"Direction","Start_Timestamp","End_Timestamp"\n'
+                 '"MEMORY_COPY_HOST_TO_DEVICE",50,120\n"MEMORY_COPY_DEVICE_TO_DEVICE",300,310\n')
+    iv = M.rocprof_intervals(str(k), str(c))
+    assert [(x[0], x[1]) for x in iv] == [("T", 50), ("C", 100), ("C", 150), ("C", 300), ("C", 10000)]
+    runs = M.split_runs(iv, 1000)
+    assert [len(r) for r in runs] == [4, 1]
+    o = M.overlap([(x[0], x[1], x[2]) for x in runs[0]])
+    # T [50,120) overlaps kernels on [100,120) = 20 of 70
+    assert abs(o["TC"] - 20 / 70) < 1e-12

@@ -257,3 +257,29 @@ def test_copy_lanes_random(seed):
     wt = {i: ctx.waits(i) for i in st}
     assert dagcases.uncovered_edges(g.edges, st, wt) == []
     ctx.close()
+
+
+def test_injected_launch_failure_poisons_the_context(monkeypatch):
+    monkeypatch.setenv("DAGRT_FAULT_LAUNCH", "3")
+    ctx = D.Context(dry_run=True)
+    monkeypatch.delenv("DAGRT_FAULT_LAUNCH")
+    x = ctx.alloc(64)
+    ctx.kernel("spin", [(x, "m")], ns=0)
+    ctx.kernel("spin", [(x, "m")], ns=0)
+    with pytest.raises(D.DagError) as e:
+        ctx.kernel("spin", [(x, "m")], ns=0)
+    assert e.value.name == "DAG_E_HIP" and "injected" in str(e.value)
+    for call in (lambda: ctx.kernel("spin", [(x, "m")], ns=0), ctx.sync, lambda: ctx.alloc(64),
+                 lambda: D.dag_host_read(ctx.h, x)):
+        with pytest.raises(D.DagError) as e:
+            call()
+        assert e.value.name == "DAG_E_POISONED"
+    # introspection still works on a poisoned context
+    assert len(ctx.edges()) == 2 and ctx.stats().tasks == 3
+    ctx.close()
+    # a fresh context is unaffected
+    ctx2 = D.Context(dry_run=True)
+    y = ctx2.alloc(64)
+    for _ in range(4):
+        ctx2.kernel("spin", [(y, "m")], ns=0)
+    ctx2.close()
