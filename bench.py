@@ -49,6 +49,8 @@ def parse():
                     help="GPU_MAX_HW_QUEUES for this process (0 = runtime default)")
     ap.add_argument("--copy-streams", type=int, default=0, choices=[0, 1],
                     help="0: one FIFO stream per copy direction; 1: copies placed like kernels")
+    ap.add_argument("--copy-lanes", type=int, default=0,
+                    help="streams per copy direction (0 = from the tuning file, else 1)")
     ap.add_argument("--spin-wait", type=int, default=0, choices=[0, 1],
                     help="1: host waits spin (hipDeviceScheduleSpin)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -73,9 +75,14 @@ def main():
     from paper_2012_09646_amd import workloads as W
 
     tuned = {}
+    tuned_dag = {}
     if args.tuned and os.path.exists(args.tuned):
-        tuned = tune.load(args.tuned).get("kernels", {})
+        tdata = tune.load(args.tuned)
+        tuned = tdata.get("kernels", {})
+        tuned_dag = tdata.get("dag", {})
         log("kernel launch configurations from", args.tuned)
+    if not args.copy_lanes:
+        args.copy_lanes = int(tuned_dag.get("bs", {}).get("copy_lanes", 1))
 
     def kernel_intervals(ctx, b, nops):
         iv = []
@@ -94,7 +101,8 @@ def main():
 
         def make(policy, trace):
             ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,
-                            copy_streams=args.copy_streams, spin_wait=args.spin_wait)
+                            copy_streams=args.copy_streams, spin_wait=args.spin_wait,
+                            copy_lanes=args.copy_lanes)
             tune.apply_kernels(ctx, tuned)
             b = runner.Bound(ctx, prog, read_bytes=4)
             for dst in restore:
@@ -223,7 +231,8 @@ def main():
         # as one task per launch; no dependency work or per-task HIP calls
         for gm, tag in ((0, "graph"), (1, "replay")):
             ctxG = D.Context(policy=D.DAG_PARALLEL_ASYNC, max_streams=args.max_streams, graph_mode=gm,
-                             copy_streams=args.copy_streams, spin_wait=args.spin_wait)
+                             copy_streams=args.copy_streams, spin_wait=args.spin_wait,
+                             copy_lanes=args.copy_lanes)
             tune.apply_kernels(ctxG, tuned)
             bG = runner.Bound(ctxG, prog, read_bytes=4)
             for dst in restore:
@@ -335,6 +344,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bs_fanout_10x2^22" if "bs" in results else head["workload"],
                    "max_streams": args.max_streams, "copy_streams": args.copy_streams,
+                   "copy_lanes": args.copy_lanes,
                    "spin_wait": args.spin_wait,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)},
         "makespan_ms": round(head["makespan_ms"], 4),

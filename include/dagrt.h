@@ -121,6 +121,11 @@ typedef struct {
   uint32_t spin_wait;     /* 1 = host waits spin instead of sleeping (asks
                              HIP for hipDeviceScheduleSpin; effective only if
                              no HIP context exists yet in the process) */
+  uint32_t copy_lanes;    /* copy_streams = 0: FIFO streams per copy
+                             direction, copies rotating over them (0 = 1,
+                             at most 4); more than one hides per-copy gaps
+                             at the price of later first completions */
+  uint32_t reserved;
 } dag_config;
 
 /* One argument of a call: a buffer and its access mode. */

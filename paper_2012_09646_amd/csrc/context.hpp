@@ -107,7 +107,7 @@ struct dag_ctx_s {
   uint64_t n_waits = 0, n_host_waits = 0;
   double submit_us = 0.0, launch_us = 0.0;
 
-  explicit dag_ctx_s(uint32_t ms) : tr(ms) {}
+  dag_ctx_s(uint32_t ms, uint32_t lanes) : tr(ms, lanes) {}
 };
 
 namespace dagrt {

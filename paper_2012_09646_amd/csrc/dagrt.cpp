@@ -545,12 +545,12 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
   if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1 ||
-      c.trace > 2 || c.copy_streams > 1)
+      c.trace > 2 || c.copy_streams > 1 || c.copy_lanes > 4)
     return DAG_E_INVAL;
   if (c.scratch_bytes == 0) c.scratch_bytes = 4u << 20;
   if (c.scratch_bytes < 4096 || c.scratch_bytes > (1ull << 32)) return DAG_E_INVAL;
   c.scratch_bytes = (c.scratch_bytes + 255) & ~uint64_t(255);
-  dag_ctx x = new (std::nothrow) dag_ctx_s(c.policy == DAG_SERIAL_SYNC ? 1 : c.max_streams);
+  dag_ctx x = new (std::nothrow) dag_ctx_s(c.policy == DAG_SERIAL_SYNC ? 1 : c.max_streams, c.copy_lanes);
   if (!x) return DAG_E_NOMEM;
   x->cfg = c;
   x->serial = c.policy == DAG_SERIAL_SYNC;

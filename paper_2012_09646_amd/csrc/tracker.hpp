@@ -49,8 +49,9 @@ enum TaskKind : uint8_t {
   TK_RELEASE = 6,
 };
 
-constexpr uint8_t kLaneH2D = 1;
+constexpr uint8_t kLaneH2D = 1;  // copy directions with lanes of their own
 constexpr uint8_t kLaneD2H = 2;
+constexpr uint32_t kMaxLanesPerDir = 4;
 
 inline bool is_gpu_kind(uint8_t k) { return k == TK_KERNEL || k == TK_COPY || k == TK_REGION; }
 
@@ -94,7 +95,8 @@ struct StreamRec {
 
 class Tracker {
  public:
-  explicit Tracker(uint32_t max_streams) : max_streams_(max_streams) {
+  explicit Tracker(uint32_t max_streams, uint32_t lanes_per_dir = 1)
+      : max_streams_(max_streams), lanes_per_dir_(std::max<uint32_t>(1, std::min<uint32_t>(lanes_per_dir, kMaxLanesPerDir))) {
     tasks_.emplace_back();  // id 0 = none
   }
 
@@ -132,8 +134,8 @@ class Tracker {
   // stream 0 (the serial policy of Sec. IV-C computes no dependencies).
   // Returns the new id; *stream_out, *new_stream_out and the wait list
   // (waits(id), task(id).wait_n) describe what the executor must do.
-  // lane: 0 = placed by the policy; 1..kMaxLanes = always on that copy lane
-  // (one FIFO stream per copy direction, outside the pool).
+  // lane: 0 = placed by the policy; kLaneH2D / kLaneD2H = on that copy
+  // direction's lanes (FIFO streams outside the pool).
   uint64_t add_gpu(uint8_t kind, uint32_t kernel_id, const Access* accs, uint32_t n,
                    bool serial, int32_t* stream_out, bool* new_stream_out, uint8_t lane = 0) {
     const uint64_t id = tasks_.size();
@@ -264,10 +266,13 @@ class Tracker {
     return static_cast<int32_t>(streams_.size() - 1);
   }
 
-  int32_t pick_lane(uint8_t lane, bool* created) {
+  // Copies of one direction rotate over that direction's lanes.
+  int32_t pick_lane(uint8_t dir, bool* created) {
     *created = false;
-    if (lane_stream_[lane] < 0) lane_stream_[lane] = new_stream(created, lane);
-    return lane_stream_[lane];
+    const uint32_t k = lane_next_[dir]++ % lanes_per_dir_;
+    int32_t& ls = lane_stream_[dir * kMaxLanesPerDir + k];
+    if (ls < 0) ls = new_stream(created, dir);
+    return ls;
   }
 
   int32_t pick_serial(bool* created) {
@@ -385,8 +390,10 @@ class Tracker {
   }
 
   uint32_t max_streams_;
+  uint32_t lanes_per_dir_;
   uint32_t npool_ = 0;
-  int32_t lane_stream_[4] = {-1, -1, -1, -1};
+  int32_t lane_stream_[3 * kMaxLanesPerDir] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  uint32_t lane_next_[3] = {0, 0, 0};
   std::vector<TaskRec> tasks_;
   std::vector<BufTrack> bufs_;
   std::vector<StreamRec> streams_;

@@ -34,7 +34,7 @@ def candidates(kernel):
     if kernel in ("vec_square", "bs_call", "normalise", "unsharp_combine", "scale_l2", "copy_f32"):
         return [(b, c, 0) for b in BLOCKS for c in CAPS]
     if kernel in ("vec_sum_diff", "minmax", "sumsq"):
-        return [(b, c, v) for b in (256, 512, 1024) for c in (256, 512, 1024, 2048) for v in (0, 1)]
+        return [(b, c, v) for b in (256, 512, 1024) for c in (64, 128, 256, 512, 1024, 2048) for v in (0, 1)]
     if kernel == "spmv":
         return [(256, 0, v) for v in (4, 8, 12, 16)]
     return []  # fixed-tile kernels (blur, Sobel) and the delay kernel
@@ -78,15 +78,18 @@ def tune_kernels(ctx, prog, reps=20, log=None):
     return out
 
 
-def tune_dag(prog, kernels, pools=(1, 2, 4, 8, 16), copy_modes=(0, 1), runs=15, restore=(), log=None):
-    """Choose max_streams and copy placement by median makespan."""
+def tune_dag(prog, kernels, pools=(1, 2, 4, 8, 16), copy_modes=((0, 1), (0, 2), (0, 3), (1, 1)), runs=15,
+             restore=(), log=None):
+    """Choose max_streams and copy placement (copy_streams, lanes per
+    direction) by median makespan."""
     best = None
     table = []
-    for cm in copy_modes:
-        if cm == 1 and not any(o["kind"] == "copy" for o in prog.ops):
+    has_copies = any(o["kind"] == "copy" for o in prog.ops)
+    for cm, lanes in copy_modes:
+        if (cm == 1 or lanes > 1) and not has_copies:
             continue
         for ms in pools:
-            ctx = D.Context(max_streams=ms, copy_streams=cm)
+            ctx = D.Context(max_streams=ms, copy_streams=cm, copy_lanes=lanes)
             apply_kernels(ctx, kernels)
             b = runner.Bound(ctx, prog, read_bytes=4)
             pris = {}
@@ -104,11 +107,11 @@ def tune_dag(prog, kernels, pools=(1, 2, 4, 8, 16), copy_modes=(0, 1), runs=15, 
                     ts.append((time.perf_counter() - t0) * 1e3)
             ctx.close()
             m = statistics.median(ts)
-            table.append({"max_streams": ms, "copy_streams": cm, "ms": m})
+            table.append({"max_streams": ms, "copy_streams": cm, "copy_lanes": lanes, "ms": m})
             if log:
-                log("dag %s: max_streams=%d copy_streams=%d %.4f ms" % (prog.name, ms, cm, m))
+                log("dag %s: max_streams=%d copy_streams=%d lanes=%d %.4f ms" % (prog.name, ms, cm, lanes, m))
             if best is None or m < best["ms"]:
-                best = {"max_streams": ms, "copy_streams": cm, "ms": m}
+                best = {"max_streams": ms, "copy_streams": cm, "copy_lanes": lanes, "ms": m}
     return best, table
 
 

@@ -205,6 +205,25 @@ def test_serial_policy_computes_no_dependencies():
     ctx.close()
 
 
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_copy_lanes_rotate(lanes):
+    prog = W.bs_program(n=64, tasks=10)
+    g = odag.build_dag(prog.ops)
+    ctx = D.Context(dry_run=True, max_streams=8, copy_streams=0, copy_lanes=lanes)
+    b = runner.Bound(ctx, prog, upload=False)
+    b.run()
+    assert b.edges() == g.edges
+    st, wt = b.streams(), b.waits()
+    assert dagcases.uncovered_edges(g.edges, st, wt) == []
+    h2d = [p for p, o in enumerate(prog.ops, 1) if o["kind"] == "copy" and o["src"].startswith("S")]
+    d2h = [p for p, o in enumerate(prog.ops, 1) if o["kind"] == "copy" and o["dst"].startswith("C")]
+    for copies in (h2d, d2h):
+        seq = [st[p] for p in copies]
+        assert len(set(seq)) == lanes and all(seq[i] == seq[i % lanes] for i in range(len(seq)))
+    assert not set(st[p] for p in h2d) & set(st[p] for p in d2h)
+    ctx.close()
+
+
 @pytest.mark.parametrize("pool", [1, 4, 8])
 def test_copy_lanes(pool):
     """Host<->device copies on one FIFO stream per direction: same edges as
