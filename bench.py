@@ -29,6 +29,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DAG makespan speedup vs serial + % critical-path bound; serving p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # vector fp64: 256 CUs x 128 flop/clk (4 SIMDs x 16 lanes x FMA) x 2.4 GHz
+# fp64 work of one Black-Scholes price as executed on gfx950, from the SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64
+# counters of the bs_call kernel (127 FMA + 61 ADD + 22 MUL + 7 TRANS per element, FMA = 2 flops)
+BS_FLOPS_PER_ELEMENT = 2 * 127 + 61 + 22 + 7
+# HBM bytes per bs_call launch from FETCH_SIZE / WRITE_SIZE, each divided by what the counter reads for a
+# 256 MiB copy kernel (FETCH_SIZE 0.500x, WRITE_SIZE 1.000x of the true bytes): 16.18 MiB in + 16.00 MiB out
+TRAFFIC_BS_BYTES = int((8286.7 / 0.50004 + 16384.0 / 1.0) * 1024)
 
 
 def log(*a):
@@ -44,7 +51,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"),
                     help="kernel launch configurations from the autotuner (ignored if missing)")
-    ap.add_argument("--max-streams", type=int, default=8)
+    ap.add_argument("--max-streams", type=int, default=0,
+                    help="stream pool bound (0 = per workload from the tuning file, else 8)")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="GPU_MAX_HW_QUEUES for this process (0 = runtime default)")
     ap.add_argument("--copy-streams", type=int, default=0, choices=[0, 1],
@@ -83,6 +91,10 @@ def main():
         log("kernel launch configurations from", args.tuned)
     if not args.copy_lanes:
         args.copy_lanes = int(tuned_dag.get("bs", {}).get("copy_lanes", 1))
+    fixed_pool = args.max_streams
+
+    def pool_for(name):
+        return fixed_pool or int(tuned_dag.get(name, {}).get("max_streams", 8))
 
     def kernel_intervals(ctx, b, nops):
         iv = []
@@ -98,6 +110,8 @@ def main():
         """Timed parallel runs, serial runs, traced runs; returns a summary."""
         res = {"workload": name, "tasks": sum(1 for o in prog.ops if o["kind"] != "host_read")}
         pris = {}
+        args.max_streams = pool_for(name)
+        res["max_streams"] = args.max_streams
 
         def make(policy, trace):
             ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,
@@ -359,12 +373,15 @@ def main():
     }
     if kt_bs:
         v = kt_bs["bs_call"]
-        avg = sum(t for t, _ in v) / len(v)
+        avg = sum(t for t, _ in v) / len(v)          # ms per launch, timing events on its stream
         by = v[0][1]
-        ach = by / avg / 1e6
-        line["roofline"] = {"kernel": "bs_call", "bound": "hbm", "achieved": round(ach, 1),
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                            "traffic": None, "avg_us": round(avg * 1e3, 2), "bytes_per_launch": by}
+        fl = BS_FLOPS_PER_ELEMENT * (by // 8)
+        ach = fl / avg / 1e9                          # TFLOP/s
+        line["roofline"] = {"kernel": "bs_call", "bound": "alu", "achieved": round(ach, 2),
+                            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                            "traffic": TRAFFIC_BS_BYTES, "avg_us": round(avg * 1e3, 2), "flops_per_launch": fl,
+                            "bytes_per_launch": by, "hbm_gbs": round(by / avg / 1e6, 1),
+                            "launches": len(v)}
     if "serve" in results:
         line["serving"] = results.pop("serve")
     line["workloads"] = results

@@ -215,7 +215,10 @@ dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
 #define DAG_K_MINMAX 6u          /* in:c M:m            M = [max, min] */
 #define DAG_K_NORMALISE 7u       /* S:c M:c N:m         (S-min)/(max-min) */
 #define DAG_K_UNSHARP_COMBINE 8u /* img B3 B7 B15 N3 N7 N15:c out:m */
-#define DAG_K_SPMV 9u            /* row_ptr col val x:c y:m   y = A x (CSR) */
+#define DAG_K_SPMV 9u            /* row_ptr col val x:c y:m   y = A x (CSR),
+                                    merge-path: any row lengths */
+#define DAG_K_SPMV_ROWS 10u      /* row_ptr col val x:c y:m   y = A x (CSR),
+                                    lanes per row: for short rows only */
 #define DAG_K_SUMSQ 11u          /* v:c s:m             s (fp64) = sum v_i^2 */
 #define DAG_K_SCALE_L2 12u       /* t:c s:c v:m         v_i = t_i / sqrt(s) */
 #define DAG_K_SPIN 13u           /* (any args)          busy-wait, no data */

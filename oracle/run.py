@@ -92,6 +92,7 @@ KERNELS = {
     "normalise": _k_normalise,              # S:c M:c N:m
     "unsharp_combine": _k_unsharp_combine,  # img B3 B7 B15 N3 N7 N15 :c out:m
     "spmv": _k_spmv,                        # row_ptr col val x :c  y:m
+    "spmv_rows": _k_spmv,                   # same product (an implementation choice of the caller)
     "sumsq": _k_sumsq,                      # v:c s:m      (s float64)
     "scale_l2": _k_scale_l2,                # t:c s:c v:m
     "spin": _k_spin,                        # any

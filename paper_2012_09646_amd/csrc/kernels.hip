@@ -565,15 +565,15 @@ __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_
   const int nb = max(0, min(ye - yb, TILE));
   if (tid == 0) s_head_row = -1;
   // Stage the tile with every load of a thread in flight at once: IPT column
-  // indices and values (streamed once, non-temporal, so x stays in L2), then
-  // the IPT gathers of x, then the row ends.
+  // indices and values, then the IPT gathers of x, then the row ends.
+  // (Plain loads: non-temporal hints measured slower on gfx950.)
   int cidx[IPT];
   float v[IPT];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const int i = tid + j * 256;
-    cidx[j] = i < nb ? __builtin_nontemporal_load(col + yb + i) : 0;
-    v[j] = i < nb ? __builtin_nontemporal_load(val + yb + i) : 0.0f;
+    cidx[j] = i < nb ? col[yb + i] : 0;
+    v[j] = i < nb ? val[yb + i] : 0.0f;
   }
   float xv[IPT];
 #pragma unroll
@@ -668,6 +668,28 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(float* __restrict__ y, SpmvS
   for (int p = p0 + lane; p < b; p += kWave) acc += sc.tail_val[p];
   acc = wave_sum(acc);
   if (lane == 0) y[r] = static_cast<float>(sc.head_val[b] + acc);
+}
+
+// CSR SpMV for matrices with short rows: L lanes per row stride over the row
+// (the matrix read once, coalesced within the row), fp64 partial sums
+// combined by an xor butterfly inside each group of L lanes.  No search and
+// no LDS; a row of length m costs m / L iterations, so it is meant for
+// bounded row lengths (e.g. a fixed out-degree).
+template <int L>
+__global__ __launch_bounds__(256) void k_spmv_rows(const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                                   const float* __restrict__ val, const float* __restrict__ x,
+                                                   float* __restrict__ y, int nrows, int ncols, int nnz) {
+  const int lane = threadIdx.x & (L - 1);
+  const long long stride = static_cast<long long>(gridDim.x) * (256 / L);
+  for (long long r = (static_cast<long long>(blockIdx.x) * 256 + threadIdx.x) / L; r < nrows; r += stride) {
+    const int b = clamp_nnz(row_ptr[r], nnz), e = clamp_nnz(row_ptr[r + 1], nnz);
+    double acc = 0.0;
+    for (int k = b + lane; k < e; k += L)
+      acc += static_cast<double>(val[k]) * static_cast<double>(x[min(max(col[k], 0), ncols - 1)]);
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if (lane == 0) y[r] = static_cast<float>(acc);
+  }
 }
 
 // s = sum v_i^2 (fp64).
@@ -1051,6 +1073,47 @@ hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   return hipGetLastError();
 }
 
+const char* cfg_spmv_rows(const LaunchCfg& c) {
+  if (c.block != 256) return "SpMV runs 256-thread workgroups";
+  if (c.variant != 4 && c.variant != 8 && c.variant != 16 && c.variant != 32)
+    return "spmv_rows variant (lanes per row) must be 4, 8, 16 or 32";
+  return nullptr;
+}
+
+const char* v_spmv_rows(const void* p, const size_t* sz, uint32_t na, const LaunchCfg& c, size_t sb) {
+  const auto* q = static_cast<const dag_p_csr*>(p);
+  if (q->nrows == 0) return nullptr;
+  if (q->ncols == 0) return "ncols must be > 0";
+  if (q->nnz > 0x7fffffffull) return "nnz must stay below 2^31";
+  if (!mul_fits(static_cast<uint64_t>(q->nrows) + 1, 4, sz[0])) return "row_ptr smaller than 4*(nrows+1) bytes";
+  if (!mul_fits(q->nnz, 4, sz[1]) || !mul_fits(q->nnz, 4, sz[2])) return "col or val smaller than 4*nnz bytes";
+  if (!mul_fits(q->ncols, 4, sz[3])) return "x smaller than 4*ncols bytes";
+  if (!mul_fits(q->nrows, 4, sz[4])) return "y smaller than 4*nrows bytes";
+  return nullptr;
+}
+
+template <int L>
+void launch_spmv_rows_l(hipStream_t s, void* const* a, const dag_p_csr* q, uint32_t cap) {
+  uint64_t g = ceil_div(static_cast<uint64_t>(q->nrows) * L, 256);
+  if (cap) g = std::min<uint64_t>(g, cap);
+  hipLaunchKernelGGL(k_spmv_rows<L>, dim3(static_cast<uint32_t>(std::max<uint64_t>(g, 1))), dim3(256), 0, s,
+                     static_cast<const int*>(a[0]), static_cast<const int*>(a[1]), static_cast<const float*>(a[2]),
+                     static_cast<const float*>(a[3]), static_cast<float*>(a[4]), static_cast<int>(q->nrows),
+                     static_cast<int>(q->ncols), static_cast<int>(q->nnz));
+}
+
+hipError_t l_spmv_rows(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const auto* q = static_cast<const dag_p_csr*>(p);
+  if (q->nrows == 0) return hipSuccess;
+  switch (c.variant) {
+    case 4: launch_spmv_rows_l<4>(s, a, q, c.grid_cap); break;
+    case 16: launch_spmv_rows_l<16>(s, a, q, c.grid_cap); break;
+    case 32: launch_spmv_rows_l<32>(s, a, q, c.grid_cap); break;
+    default: launch_spmv_rows_l<8>(s, a, q, c.grid_cap); break;
+  }
+  return hipGetLastError();
+}
+
 const char* v_sumsq(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t sb) {
   if (!mul_fits(pn(p), 4, sz[0])) return "v smaller than 4*n bytes";
   if (sz[1] < 8) return "s smaller than 8 bytes";
@@ -1128,7 +1191,7 @@ const KernelDesc kTable[] = {
     /* 7 */ {"normalise", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_normalise, l_normalise, cfg_block_any},
     /* 8 */ {"unsharp_combine", 8, 0x80, sizeof(dag_p_n), {256, 0, 0}, v_combine, l_combine, cfg_block_any},
     /* 9 */ {"spmv", 5, 0x10, sizeof(dag_p_csr), {256, 0, 8}, v_spmv, l_spmv, cfg_spmv},
-    /* 10 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
+    /* 10 */ {"spmv_rows", 5, 0x10, sizeof(dag_p_csr), {256, 0, 8}, v_spmv_rows, l_spmv_rows, cfg_spmv_rows},
     /* 11 */ {"sumsq", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_sumsq, l_sumsq, cfg_reduce},
     /* 12 */ {"scale_l2", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_scale, l_scale, cfg_block_any},
     /* 13 */ {"spin", 0, 0x0, sizeof(dag_p_spin), {64, 0, 0}, v_spin, l_spin, cfg_spin},

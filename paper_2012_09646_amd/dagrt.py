@@ -32,7 +32,7 @@ DAG_K_USER_BASE = 1000
 
 KERNEL_IDS = {
     "vec_square": 1, "vec_sum_diff": 2, "bs_call": 3, "gauss_blur": 4, "sobel": 5,
-    "minmax": 6, "normalise": 7, "unsharp_combine": 8, "spmv": 9, "sumsq": 11,
+    "minmax": 6, "normalise": 7, "unsharp_combine": 8, "spmv": 9, "spmv_rows": 10, "sumsq": 11,
     "scale_l2": 12, "spin": 13, "copy_f32": 14,
 }
 KERNEL_NAMES = {v: k for k, v in KERNEL_IDS.items()}
@@ -451,7 +451,7 @@ def make_params(kernel, p):
         return dag_p_bs(int(p["n"]), float(p["K"]), float(p["r"]), float(p["sigma"]), float(p["T"]))
     if kernel in ("gauss_blur", "sobel"):
         return dag_p_img(int(p["w"]), int(p["h"]), int(p.get("ksize", 0)), 0)
-    if kernel == "spmv":
+    if kernel in ("spmv", "spmv_rows"):
         return dag_p_csr(int(p["nrows"]), int(p["ncols"]), int(p["nnz"]))
     if kernel == "spin":
         return dag_p_spin(int(p.get("ns", 0)))

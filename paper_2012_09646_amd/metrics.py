@@ -116,7 +116,7 @@ def algorithmic_bytes(kernel, p):
         return 8 * p["n"] + 8
     if kernel == "unsharp_combine":
         return 32 * p["n"]
-    if kernel == "spmv":
+    if kernel in ("spmv", "spmv_rows"):
         return 4 * (p["nrows"] + 1) + 8 * p["nnz"] + 4 * p["ncols"] + 4 * p["nrows"]
     if kernel == "sumsq":
         return 4 * p["n"] + 8

@@ -25,10 +25,11 @@ def main():
     ap.add_argument("--runs", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--copies", type=int, default=3)
+    ap.add_argument("--serial", action="store_true", help="serial policy: every call alone on the GPU")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"))
     args = ap.parse_args()
     prog, _ = tune.workload_program(args.workload)
-    ctx = D.Context()
+    ctx = D.Context(policy=D.DAG_SERIAL_SYNC if args.serial else D.DAG_PARALLEL_ASYNC)
     if args.tuned and os.path.exists(args.tuned):
         tune.apply_kernels(ctx, tune.load(args.tuned).get("kernels", {}))
     b = runner.Bound(ctx, prog, read_bytes=4)

@@ -37,6 +37,8 @@ def candidates(kernel):
         return [(b, c, v) for b in (256, 512, 1024) for c in (64, 128, 256, 512, 1024, 2048) for v in (0, 1)]
     if kernel == "spmv":
         return [(256, 0, v) for v in (4, 8, 12, 16)]
+    if kernel == "spmv_rows":
+        return [(256, c, v) for v in (4, 8, 16, 32) for c in (0, 2048, 8192)]
     return []  # fixed-tile kernels (blur, Sobel) and the delay kernel
 
 
@@ -58,6 +60,7 @@ def tune_kernels(ctx, prog, reps=20, log=None):
     out = {}
     for k, ops in occ.items():
         cands = candidates(k)
+        default = ctx.get_launch(k)  # before tuning installs a winner
         total = [0.0] * len(cands)
         for op in ops:
             prm = D.make_params(k, op["params"])
@@ -66,7 +69,6 @@ def tune_kernels(ctx, prog, reps=20, log=None):
             total = [t + u if (t >= 0 and u >= 0) else -1.0 for t, u in zip(total, us)]
         valid = [i for i, t in enumerate(total) if t >= 0]
         best = min(valid, key=lambda i: total[i])
-        default = ctx.get_launch(k)
         di = cands.index(default) if default in cands else None
         ctx.set_launch(k, *cands[best])
         out[k] = {"block": cands[best][0], "grid_cap": cands[best][1], "variant": cands[best][2],

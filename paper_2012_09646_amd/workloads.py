@@ -205,10 +205,12 @@ def hits_graph(n=1 << 20, deg=20, seed=3, alpha=1.5):
 
 
 def hits_iteration_ops(n, nnz):
+    """A has a fixed out-degree, so its product uses the short-row SpMV;
+    A^T has power-law rows and uses the merge-path SpMV."""
     sp = dict(nrows=n, ncols=n, nnz=nnz)
     return [
         K("spmv", [("at_ptr", "c"), ("at_col", "c"), ("at_val", "c"), ("h", "c"), ("at", "m")], **sp),
-        K("spmv", [("a_ptr", "c"), ("a_col", "c"), ("a_val", "c"), ("a", "c"), ("ht", "m")], **sp),
+        K("spmv_rows", [("a_ptr", "c"), ("a_col", "c"), ("a_val", "c"), ("a", "c"), ("ht", "m")], **sp),
         K("sumsq", [("at", "c"), ("sa", "m")], n=n),
         K("sumsq", [("ht", "c"), ("sh", "m")], n=n),
         K("scale_l2", [("at", "c"), ("sa", "c"), ("a", "m")], n=n),
