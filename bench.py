@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "serve"])
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
+    ap.add_argument("--serve-lanes", type=int, default=8, help="serving: HIP streams requests spread over")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"),
                     help="kernel launch configurations from the autotuner (ignored if missing)")
     ap.add_argument("--max-streams", type=int, default=0,
@@ -289,12 +291,12 @@ def main():
                 tmpls.append(serving.ShapeTemplate(ctx, prog, key=key, result_bytes=64))
                 key += 1
         budget = 64 << 30
-        srv = serving.Server(ctx, budget, host_arena_bytes=8 << 30, lanes=8, bypass=32)
+        srv = serving.Server(ctx, budget, host_arena_bytes=8 << 30, lanes=args.serve_lanes, bypass=32)
         foot = []
         for t in tmpls:
             sid = srv.add(t)
             foot.append(srv.footprint(sid))
-        arr, shp = W.poisson_trace(4, args.requests, 2000.0, len(tmpls))
+        arr, shp = W.poisson_trace(4, args.requests, args.rate, len(tmpls))
         log("serving: %d requests, %d shapes" % (len(arr), len(tmpls)))
         mix, st, _ = srv.run(arr, shp)
         log("serving: serial baseline")
@@ -302,7 +304,8 @@ def main():
         srv.close()
         ctx.close()
         return {
-            "requests": len(arr), "rate_per_s": 2000.0, "shapes": len(tmpls), "budget_bytes": budget,
+            "requests": len(arr), "rate_per_s": args.rate, "shapes": len(tmpls), "budget_bytes": budget,
+            "lanes": args.serve_lanes,
             "mean_footprint_mb": float(np.mean([foot[i][0] for i in shp])) / 2 ** 20,
             "concurrent": {"p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
                            "req_per_s": st.req_per_s, "max_inflight": st.max_inflight,
@@ -357,7 +360,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "bs_fanout_10x2^22" if "bs" in results else head["workload"],
-                   "max_streams": args.max_streams, "copy_streams": args.copy_streams,
+                   "max_streams": head["max_streams"], "copy_streams": args.copy_streams,
                    "copy_lanes": args.copy_lanes,
                    "spin_wait": args.spin_wait,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)},

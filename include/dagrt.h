@@ -103,8 +103,10 @@ typedef int32_t dag_status;
 typedef struct {
   uint32_t policy;        /* DAG_SERIAL_SYNC or DAG_PARALLEL_ASYNC */
   uint32_t max_streams;   /* stream pool bound, 1..DAG_MAX_STREAMS (0 = 8) */
-  uint32_t trace;         /* 1 = record timing events around every GPU task,
-                             2 = around kernels and region replays only */
+  uint32_t trace;         /* 1 = timing events for every GPU task, 2 = for
+                             kernels and region replays only; built-in
+                             kernels are timed by events attached to their
+                             dispatch packets, other tasks by markers */
   uint32_t dry_run;       /* 1 = schedule only: infer edges, streams and
                              waits, make no HIP call and touch no memory */
   int32_t device;         /* HIP device ordinal */

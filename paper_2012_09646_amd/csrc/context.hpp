@@ -87,6 +87,7 @@ struct dag_ctx_s {
   hipEvent_t read_ev = nullptr;
   std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion
   std::vector<hipEvent_t> ev0;            // per task, start (trace mode)
+  std::vector<hipEvent_t> ev1;            // per task, kernel end (trace mode 2, built-in kernels)
   std::vector<hipEvent_t> free_ev;
   hipEvent_t trace_ref = nullptr;
   std::vector<uint64_t> tmp_wait, tmp_retired;

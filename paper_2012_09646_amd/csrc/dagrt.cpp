@@ -83,7 +83,10 @@ dag_status ensure_stream(dag_ctx c, int32_t s) {
 void note_event_slot(dag_ctx c, uint64_t id) {
   if (c->ev.size() <= id) {
     c->ev.resize(id + 1, nullptr);
-    if (c->cfg.trace) c->ev0.resize(id + 1, nullptr);
+    if (c->cfg.trace) {
+      c->ev0.resize(id + 1, nullptr);
+      c->ev1.resize(id + 1, nullptr);
+    }
   }
 }
 
@@ -95,7 +98,9 @@ bool traced(dag_ctx c, uint64_t id) {
 }
 
 // Enqueue the waits of task id on its stream and (trace) its start event.
-dag_status begin_task(dag_ctx c, uint64_t id, int32_t s) {
+// With dispatch_timed, the start (and kernel-end) events are attached to the
+// task's kernel dispatches instead of being recorded as separate markers.
+dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = false) {
   if (c->dry) return DAG_OK;
   const TaskRec& t = c->tr.task(id);
   const uint64_t* w = c->tr.waits(id);
@@ -109,7 +114,15 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s) {
     dag_status st = get_event(c, true, &e0);
     if (st) return st;
     c->ev0[id] = e0;
-    HIP_TRY(c, hipEventRecord(e0, c->streams[s]));
+    if (dispatch_timed) {
+      hipEvent_t e1;
+      st = get_event(c, true, &e1);
+      if (st) return st;
+      c->ev1[id] = e1;
+      set_launch_events(e0, e1);
+    } else {
+      HIP_TRY(c, hipEventRecord(e0, c->streams[s]));
+    }
   }
   return DAG_OK;
 }
@@ -197,13 +210,17 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
   dag_status st = ensure_stream(c, s);
   if (st) return st;
   const auto t1 = Clock::now();
-  st = begin_task(c, id, s);
+  const bool dispatch_timed = kd && c->cfg.trace != 0;
+  st = begin_task(c, id, s, dispatch_timed);
   if (st) return st;
-  if (c->fault_at && ++c->n_launches == c->fault_at)
+  if (c->fault_at && ++c->n_launches == c->fault_at) {
+    set_launch_events(nullptr, nullptr);
     return hip_fail(c, hipErrorLaunchFailure, "injected launch failure (DAGRT_FAULT_LAUNCH)");
+  }
   if (!c->dry) {
     if (kd) {
       hipError_t e = kd->launch(c->streams[s], ptrs, params, cfg, c->scratch[s], c->cfg.scratch_bytes);
+      set_launch_events(nullptr, nullptr);
       if (e != hipSuccess) return hip_fail(c, e, kd->name);
     } else {
       int rc = uk->fn(c->streams[s], ptrs, nargs, params, uk->user);
@@ -598,6 +615,8 @@ dag_status dag_destroy(dag_ctx c) {
     for (hipEvent_t e : c->ev)
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev0)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev1)
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
     if (c->trace_ref) (void)hipEventDestroy(c->trace_ref);
@@ -1003,9 +1022,10 @@ dag_status dag_task_get_info(dag_ctx c, dag_task t, dag_task_info* out) {
   out->t_end_ms = -1.0;
   if (c->cfg.trace && !c->dry && is_gpu_kind(r.kind) && t < c->ev.size() && c->ev[t] && c->ev0[t]) {
     float a = 0.f, b = 0.f;
+    hipEvent_t end = (t < c->ev1.size() && c->ev1[t]) ? c->ev1[t] : c->ev[t];
     hipError_t e = hipEventSynchronize(c->ev[t]);
     if (e == hipSuccess) e = hipEventElapsedTime(&a, c->trace_ref, c->ev0[t]);
-    if (e == hipSuccess) e = hipEventElapsedTime(&b, c->trace_ref, c->ev[t]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, c->trace_ref, end);
     if (e != hipSuccess) return hip_fail(c, e, "trace event query");
     out->t_start_ms = a;
     out->t_end_ms = b;

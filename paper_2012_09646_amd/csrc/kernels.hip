@@ -9,6 +9,7 @@
 // vectors; B&S prices European calls in double precision; IMG combines a
 // sharpened image with blurred copies; HITS repeats SpMV with a matrix and
 // its transpose.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +21,23 @@
 
 namespace dagrt {
 namespace {
+
+// Timing of a task's kernels: when set, the first dispatch of the task takes
+// the start event and every dispatch the stop event (the last one wins), both
+// attached to the dispatch packets themselves.
+thread_local hipEvent_t tl_start = nullptr;
+thread_local hipEvent_t tl_stop = nullptr;
+
+#define DAGRT_LAUNCH(kern, grid, block, shmem, stream, ...)                                       \
+  do {                                                                                            \
+    if (tl_stop) {                                                                                \
+      hipEvent_t st_ = tl_start;                                                                  \
+      tl_start = nullptr;                                                                         \
+      hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, st_, tl_stop, 0, __VA_ARGS__);      \
+    } else {                                                                                      \
+      hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                          \
+    }                                                                                             \
+  } while (0)
 
 constexpr int kWave = 64;
 uint64_t g_wall_khz = 100000;  // device constant-rate clock (kHz)
@@ -549,8 +567,10 @@ __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_
   constexpr int TILE = 256 * IPT;
   __shared__ int s_rowend[TILE + 1];
   __shared__ double s_prod[TILE];
-  __shared__ int s_crow[256];
-  __shared__ double s_cval[256];
+  __shared__ float s_out[TILE];  // rows finished in this tile, written out coalesced
+  __shared__ int s_wrow[256 / kWave];
+  __shared__ double s_wsum[256 / kWave];
+  __shared__ int s_wall[256 / kWave];
   __shared__ int s_head_row;
   __shared__ double s_head_val;
   const int tid = threadIdx.x;
@@ -615,7 +635,7 @@ __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_
         head_row = tx;
         head_acc = acc;
       } else {
-        y[xb + tx] = static_cast<float>(acc);
+        s_out[tx] = static_cast<float>(acc);
       }
       acc = 0.0;
       ++tx;
@@ -624,33 +644,62 @@ __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_
       ++ty;
     }
   }
-  s_crow[tid] = tx;
-  s_cval[tid] = acc;
-  __syncthreads();
-  // segmented inclusive scan of the carries (rows are non-decreasing)
-  for (int off = 1; off < 256; off <<= 1) {
-    const double add = (tid >= off && s_crow[tid - off] == s_crow[tid]) ? s_cval[tid - off] : 0.0;
-    __syncthreads();
-    s_cval[tid] += add;
-    __syncthreads();
+  // Carries: thread t ends inside row `crow` with partial sum `cval`.  A
+  // segmented inclusive scan over threads (rows are non-decreasing, so equal
+  // rows are contiguous) gives each thread the sum of the run of same-row
+  // carries ending at it: shuffles inside each wave, then one pass over the
+  // (at most 3) preceding waves' trailing runs.
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const int crow = tx;
+  double cval = acc;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double vu = __shfl_up(cval, off, kWave);
+    const int ru = __shfl_up(crow, off, kWave);
+    if (lane >= off && ru == crow) cval += vu;
   }
+  const double prev_v = __shfl_up(cval, 1, kWave);
+  const int prev_r = __shfl_up(crow, 1, kWave);
+  const int row0 = __shfl(crow, 0, kWave);
+  if (lane == kWave - 1) {
+    s_wrow[wv] = crow;
+    s_wsum[wv] = cval;
+    s_wall[wv] = row0 == crow ? 1 : 0;
+  }
+  __syncthreads();
+  // sum of the trailing same-row runs of the waves before this one
+  auto from_prev_waves = [&](int row) {
+    double c = 0.0;
+    for (int w2 = wv - 1; w2 >= 0; --w2) {
+      if (s_wrow[w2] != row) break;
+      c += s_wsum[w2];
+      if (!s_wall[w2]) break;
+    }
+    return c;
+  };
   if (has_head) {
-    const double cin = (tid > 0 && s_crow[tid - 1] == head_row) ? s_cval[tid - 1] : 0.0;
+    double cin = (lane > 0 && prev_r == head_row) ? prev_v : 0.0;
+    if (lane == 0 || row0 == head_row) cin += from_prev_waves(head_row);
     const double v = head_acc + cin;
     const int grow = xb + head_row;
     if (head_row == 0 && clamp_nnz(row_ptr[xb], nnz) < yb) {
       s_head_row = grow;
       s_head_val = v;
     } else {
-      y[grow] = static_cast<float>(v);
+      s_out[head_row] = static_cast<float>(v);
     }
   }
+  double tail = 0.0;
+  if (tid == 255) tail = cval + (row0 == crow ? from_prev_waves(crow) : 0.0);
   __syncthreads();
-  if (tid == 0) {
+  // rows [xb, xb + na) end in this tile; the first one is written by the
+  // fix-up kernel instead when it started in an earlier tile
+  for (int i = (s_head_row >= 0 ? 1 : 0) + tid; i < na; i += 256) y[xb + i] = s_out[i];
+  if (tid == 255) {
     sc.head_row[blockIdx.x] = s_head_row;
     sc.head_val[blockIdx.x] = s_head_row >= 0 ? s_head_val : 0.0;
     sc.tail_row[blockIdx.x] = xb + na;
-    sc.tail_val[blockIdx.x] = s_cval[255];
+    sc.tail_val[blockIdx.x] = tail;
   }
 }
 
@@ -837,7 +886,7 @@ hipError_t l_vec_square(hipStream_t s, void* const* a, const void* p, const Laun
   const uint64_t n = pn(p);
   if (n == 0) return hipSuccess;
   const int vec = aligned16(a[0]);
-  hipLaunchKernelGGL(k_vec_square, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+  DAGRT_LAUNCH(k_vec_square, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
                      static_cast<float*>(a[0]), n, vec);
   return hipGetLastError();
 }
@@ -856,15 +905,15 @@ hipError_t l_vec_sum_diff(hipStream_t s, void* const* a, const void* p, const La
   auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
   const uint32_t g = reduction_grid(vec ? ceil_div(n, 4) : n, c, sb);
   if (c.variant == 1) {
-    hipLaunchKernelGGL(k_vec_sum_diff<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+    DAGRT_LAUNCH(k_vec_sum_diff<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
                        static_cast<const float*>(a[1]), static_cast<float*>(a[2]), n, vec, counter, partials);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_vec_sum_diff<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+  DAGRT_LAUNCH(k_vec_sum_diff<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
                      static_cast<const float*>(a[1]), static_cast<float*>(a[2]), n, vec, counter, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish_sum<float>, dim3(1), dim3(256), 0, s, partials, g, static_cast<float*>(a[2]));
+  DAGRT_LAUNCH(k_finish_sum<float>, dim3(1), dim3(256), 0, s, partials, g, static_cast<float*>(a[2]));
   return hipGetLastError();
 }
 
@@ -882,7 +931,7 @@ hipError_t l_bs(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c
   const double mu_t = (q->rate + 0.5 * q->vol * q->vol) * q->years;
   const double disc = q->strike * std::exp(-q->rate * q->years);
   const int vec = aligned16(a[0]) && aligned16(a[1]);
-  hipLaunchKernelGGL(k_bs_call, dim3(stream_grid(vec ? ceil_div(q->n, 4) : q->n, c)), dim3(c.block), 0, s,
+  DAGRT_LAUNCH(k_bs_call, dim3(stream_grid(vec ? ceil_div(q->n, 4) : q->n, c)), dim3(c.block), 0, s,
                      static_cast<const float*>(a[0]), static_cast<float*>(a[1]), q->n, vec, q->strike,
                      mu_t, vol_t, disc);
   return hipGetLastError();
@@ -905,7 +954,7 @@ const char* v_blur(const void* p, const size_t* sz, uint32_t na, const LaunchCfg
 
 template <int R>
 void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt) {
-  hipLaunchKernelGGL(k_gauss_blur<R>, dim3(ceil_div(w, kTW), ceil_div(h, kTH)), dim3(256), 0, s, in, out, w,
+  DAGRT_LAUNCH(k_gauss_blur<R>, dim3(ceil_div(w, kTW), ceil_div(h, kTH)), dim3(256), 0, s, in, out, w,
                      h, wt);
 }
 
@@ -946,7 +995,7 @@ hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
 
 hipError_t l_sobel(hipStream_t s, void* const* a, const void* p, const LaunchCfg&, void*, size_t) {
   const auto* q = static_cast<const dag_p_img*>(p);
-  hipLaunchKernelGGL(k_sobel, dim3(ceil_div(q->w, kTW), ceil_div(q->h, kTH)), dim3(256), 0, s,
+  DAGRT_LAUNCH(k_sobel, dim3(ceil_div(q->w, kTW), ceil_div(q->h, kTH)), dim3(256), 0, s,
                      static_cast<const float*>(a[0]), static_cast<float*>(a[1]), static_cast<int>(q->w),
                      static_cast<int>(q->h));
   return hipGetLastError();
@@ -967,15 +1016,15 @@ hipError_t l_minmax(hipStream_t s, void* const* a, const void* p, const LaunchCf
   auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
   const uint32_t g = reduction_grid(vec ? ceil_div(n, 4) : n, c, sb);
   if (c.variant == 1) {
-    hipLaunchKernelGGL(k_minmax<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+    DAGRT_LAUNCH(k_minmax<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
                        static_cast<float*>(a[1]), n, vec, counter, partials);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_minmax<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+  DAGRT_LAUNCH(k_minmax<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
                      static_cast<float*>(a[1]), n, vec, counter, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish_minmax, dim3(1), dim3(256), 0, s, partials, g, static_cast<float*>(a[1]));
+  DAGRT_LAUNCH(k_finish_minmax, dim3(1), dim3(256), 0, s, partials, g, static_cast<float*>(a[1]));
   return hipGetLastError();
 }
 
@@ -989,7 +1038,7 @@ hipError_t l_normalise(hipStream_t s, void* const* a, const void* p, const Launc
   const uint64_t n = pn(p);
   if (n == 0) return hipSuccess;
   const int vec = aligned16(a[0]) && aligned16(a[2]);
-  hipLaunchKernelGGL(k_normalise, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+  DAGRT_LAUNCH(k_normalise, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
                      static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
                      static_cast<float*>(a[2]), n, vec);
   return hipGetLastError();
@@ -1006,7 +1055,7 @@ hipError_t l_combine(hipStream_t s, void* const* a, const void* p, const LaunchC
   if (n == 0) return hipSuccess;
   int vec = 1;
   for (int i = 0; i < 8; ++i) vec &= aligned16(a[i]) ? 1 : 0;
-  hipLaunchKernelGGL(k_unsharp_combine, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+  DAGRT_LAUNCH(k_unsharp_combine, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
                      static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
                      static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
                      static_cast<const float*>(a[4]), static_cast<const float*>(a[5]),
@@ -1037,7 +1086,7 @@ const char* v_spmv(const void* p, const size_t* sz, uint32_t, const LaunchCfg& c
 
 template <int IPT>
 void launch_spmv_ipt(hipStream_t s, void* const* a, const dag_p_csr* q, const SpmvScratch& sc, int tiles) {
-  hipLaunchKernelGGL(k_spmv_merge<IPT>, dim3(tiles), dim3(256), 0, s, static_cast<const int*>(a[0]),
+  DAGRT_LAUNCH(k_spmv_merge<IPT>, dim3(tiles), dim3(256), 0, s, static_cast<const int*>(a[0]),
                      static_cast<const int*>(a[1]), static_cast<const float*>(a[2]),
                      static_cast<const float*>(a[3]), static_cast<float*>(a[4]), static_cast<int>(q->nrows),
                      static_cast<int>(q->ncols), static_cast<int>(q->nnz), sc);
@@ -1055,7 +1104,7 @@ hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   sc.tail_row = reinterpret_cast<int*>(base + 20ull * tiles);
   sc.coord = reinterpret_cast<int*>(base + 24ull * tiles);
   const int waves_per_wg = 256 / kWave;
-  hipLaunchKernelGGL(k_spmv_partition, dim3(ceil_div(tiles + 1, waves_per_wg)), dim3(256), 0, s,
+  DAGRT_LAUNCH(k_spmv_partition, dim3(ceil_div(tiles + 1, waves_per_wg)), dim3(256), 0, s,
                      static_cast<const int*>(a[0]), static_cast<int>(q->nrows), static_cast<int>(q->nnz),
                      static_cast<int>(256 * c.variant), tiles, sc);
   hipError_t e = hipGetLastError();
@@ -1068,7 +1117,7 @@ hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spmv_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s, static_cast<float*>(a[4]),
+  DAGRT_LAUNCH(k_spmv_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s, static_cast<float*>(a[4]),
                      sc, tiles);
   return hipGetLastError();
 }
@@ -1096,7 +1145,7 @@ template <int L>
 void launch_spmv_rows_l(hipStream_t s, void* const* a, const dag_p_csr* q, uint32_t cap) {
   uint64_t g = ceil_div(static_cast<uint64_t>(q->nrows) * L, 256);
   if (cap) g = std::min<uint64_t>(g, cap);
-  hipLaunchKernelGGL(k_spmv_rows<L>, dim3(static_cast<uint32_t>(std::max<uint64_t>(g, 1))), dim3(256), 0, s,
+  DAGRT_LAUNCH(k_spmv_rows<L>, dim3(static_cast<uint32_t>(std::max<uint64_t>(g, 1))), dim3(256), 0, s,
                      static_cast<const int*>(a[0]), static_cast<const int*>(a[1]), static_cast<const float*>(a[2]),
                      static_cast<const float*>(a[3]), static_cast<float*>(a[4]), static_cast<int>(q->nrows),
                      static_cast<int>(q->ncols), static_cast<int>(q->nnz));
@@ -1127,15 +1176,15 @@ hipError_t l_sumsq(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
   const uint32_t g = reduction_grid(vec ? ceil_div(n, 4) : n, c, sb);
   if (c.variant == 1) {
-    hipLaunchKernelGGL(k_sumsq<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+    DAGRT_LAUNCH(k_sumsq<true>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
                        static_cast<double*>(a[1]), n, vec, counter, partials);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_sumsq<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+  DAGRT_LAUNCH(k_sumsq<false>, dim3(g), dim3(c.block), 0, s, static_cast<const float*>(a[0]),
                      static_cast<double*>(a[1]), n, vec, counter, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish_sum<double>, dim3(1), dim3(256), 0, s, partials, g, static_cast<double*>(a[1]));
+  DAGRT_LAUNCH(k_finish_sum<double>, dim3(1), dim3(256), 0, s, partials, g, static_cast<double*>(a[1]));
   return hipGetLastError();
 }
 
@@ -1149,7 +1198,7 @@ hipError_t l_scale(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   const uint64_t n = pn(p);
   if (n == 0) return hipSuccess;
   const int vec = aligned16(a[0]) && aligned16(a[2]);
-  hipLaunchKernelGGL(k_scale_l2, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+  DAGRT_LAUNCH(k_scale_l2, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
                      static_cast<const float*>(a[0]), static_cast<const double*>(a[1]),
                      static_cast<float*>(a[2]), n, vec);
   return hipGetLastError();
@@ -1162,7 +1211,7 @@ const char* v_spin(const void* p, const size_t*, uint32_t, const LaunchCfg&, siz
 hipError_t l_spin(hipStream_t s, void* const*, const void* p, const LaunchCfg&, void*, size_t) {
   const uint64_t ns = static_cast<const dag_p_spin*>(p)->ns;
   const uint64_t ticks = ns * g_wall_khz / 1000000ull;
-  hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, s, ticks);
+  DAGRT_LAUNCH(k_spin, dim3(1), dim3(64), 0, s, ticks);
   return hipGetLastError();
 }
 
@@ -1175,7 +1224,7 @@ hipError_t l_copy(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   const uint64_t n = pn(p);
   if (n == 0) return hipSuccess;
   const int vec = aligned16(a[0]) && aligned16(a[1]);
-  hipLaunchKernelGGL(k_copy_f32, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
+  DAGRT_LAUNCH(k_copy_f32, dim3(stream_grid(vec ? ceil_div(n, 4) : n, c)), dim3(c.block), 0, s,
                      static_cast<const float*>(a[0]), static_cast<float*>(a[1]), n, vec);
   return hipGetLastError();
 }
@@ -1203,6 +1252,11 @@ const KernelDesc kTable[] = {
 const KernelDesc* builtin_kernel(uint32_t id) {
   if (id >= sizeof(kTable) / sizeof(kTable[0])) return nullptr;
   return kTable[id].name ? &kTable[id] : nullptr;
+}
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  tl_start = start;
+  tl_stop = stop;
 }
 
 void set_wall_clock_khz(uint64_t khz) {

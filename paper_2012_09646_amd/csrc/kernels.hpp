@@ -31,6 +31,10 @@ struct KernelDesc {
 // nullptr for unknown ids.
 const KernelDesc* builtin_kernel(uint32_t id);
 
+// Timing events for the next built-in launch call (both null = none): the
+// first kernel dispatch takes `start`, every dispatch `stop`.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 // Device wall-clock frequency in kHz (for the spin kernel); set once.
 void set_wall_clock_khz(uint64_t khz);
 
