@@ -127,7 +127,12 @@ typedef struct {
                              direction, copies rotating over them (0 = 1,
                              at most 4); more than one hides per-copy gaps
                              at the price of later first completions */
-  uint32_t reserved;
+  uint32_t own_queues;    /* must be 0: streams come from the runtime's
+                             shared pool of GPU_MAX_HW_QUEUES hardware
+                             queues (two streams on one queue run in each
+                             other's order).  1 (a hardware queue per
+                             stream, via CU-masked streams) is refused with
+                             DAG_E_UNSUPPORTED: it hung in testing */
 } dag_config;
 
 /* One argument of a call: a buffer and its access mode. */
@@ -172,6 +177,10 @@ typedef struct {
   double submit_host_us; /* host time spent inside submit calls, excluding
                             the HIP launch/copy calls themselves */
   double launch_host_us; /* host time spent in HIP launch/copy/event calls */
+  uint64_t spmv_plans;   /* merge-path SpMV partitions computed; an SpMV
+                            whose row-pointer buffer was not written since
+                            its partition was computed (same sizes) reuses
+                            it */
 } dag_stats;
 
 /* ---- context ------------------------------------------------------------

@@ -30,6 +30,16 @@ struct Buffer {
   uint32_t loc = 0;
   bool owned = false;
   bool live = false;
+  // Tile partition of a CSR matrix whose row pointers are this buffer (the
+  // merge-path SpMV's first step), kept until the buffer is next written.
+  int* plan = nullptr;
+  uint64_t plan_cap = 0;  // ints allocated
+  bool plan_valid = false;
+  bool plan_ready = false;  // plan_ev known to have completed
+  uint32_t plan_variant = 0;
+  uint64_t plan_nrows = 0, plan_nnz = 0;
+  int32_t plan_stream = -1;  // pool stream the partition ran on
+  hipEvent_t plan_ev = nullptr;
 };
 
 struct UserKernel {
@@ -78,6 +88,7 @@ struct dag_ctx_s {
   std::string err;
   dagrt::Tracker tr;
   std::vector<dagrt::Buffer> bufs;        // slot = handle - 1
+  std::vector<void*> dead_plans;          // SpMV partitions replaced while possibly in use
   std::map<uintptr_t, uint32_t> ranges;   // live buffers: base -> slot
   uintptr_t fake_next = uintptr_t(1) << 44;
   std::vector<hipStream_t> streams;
@@ -105,7 +116,7 @@ struct dag_ctx_s {
   // instead of launching; 0 = off
   uint64_t fault_at = 0, n_launches = 0;
   // stats
-  uint64_t n_waits = 0, n_host_waits = 0;
+  uint64_t n_waits = 0, n_host_waits = 0, n_plans = 0;
   double submit_us = 0.0, launch_us = 0.0;
 
   dag_ctx_s(uint32_t ms, uint32_t lanes) : tr(ms, lanes) {}
@@ -114,6 +125,8 @@ struct dag_ctx_s {
 namespace dagrt {
 // Error helpers (dagrt.cpp).
 dag_status fail(dag_ctx c, dag_status st, const char* fmt, ...);
+// A new non-blocking stream of the context, default priority.
+hipError_t new_stream(dag_ctx c, hipStream_t* st);
 dag_status hip_fail(dag_ctx c, hipError_t e, const char* what);
 Buffer* get_buf(dag_ctx c, dag_buf h);
 hipError_t launch_region_task(dag_ctx c, const RegionTask& t, hipStream_t s, void* scratch);

@@ -65,11 +65,17 @@ void recycle_retired(dag_ctx c) {
   }
 }
 
+}  // namespace
+
+hipError_t new_stream(dag_ctx, hipStream_t* st) { return hipStreamCreateWithFlags(st, hipStreamNonBlocking); }
+
+namespace {
+
 dag_status ensure_stream(dag_ctx c, int32_t s) {
   if (c->dry) return DAG_OK;
   while (static_cast<int32_t>(c->streams.size()) <= s) {
     hipStream_t st;
-    HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HIP_TRY(c, new_stream(c, &st));
     void* scr = nullptr;
     HIP_TRY(c, hipMalloc(&scr, c->cfg.scratch_bytes));
     HIP_TRY(c, hipMemsetAsync(scr, 0, c->cfg.scratch_bytes, st));
@@ -158,6 +164,77 @@ dag_status host_wait(dag_ctx c) {
   return DAG_OK;
 }
 
+// A write to a buffer invalidates the SpMV partition derived from it.
+void note_written(dag_ctx c, const std::vector<Access>& accs) {
+  for (const Access& a : accs)
+    if (a.acc == ACC_W) c->bufs[a.buf].plan_valid = false;
+}
+
+void free_plan(Buffer* b) {
+  if (b->plan) (void)hipFree(b->plan);
+  if (b->plan_ev) (void)hipEventDestroy(b->plan_ev);
+  b->plan = nullptr;
+  b->plan_ev = nullptr;
+  b->plan_cap = 0;
+  b->plan_valid = false;
+}
+
+// Merge-path SpMV whose tile partition is kept with the row-pointer buffer
+// rp: the partition kernel runs only when rp was written since it last ran
+// (or the sizes or tile size changed).  Every SpMV reads rp, so a later write
+// of rp is ordered after all of them (WAR) and the next partition after that
+// write (RAW): rewriting the partition in place is race-free.  A partition of
+// other sizes may still be read by SpMVs in flight, so its memory is only
+// freed at the next full synchronisation.
+hipError_t spmv_with_plan(dag_ctx c, Buffer* rp, int32_t s, void* const* ptrs, const void* params,
+                          const LaunchCfg& cfg) {
+  const auto* q = static_cast<const dag_p_csr*>(params);
+  const uint64_t need = spmv_plan_ints(params, cfg);
+  if (need == 0) return hipSuccess;
+  hipStream_t st = c->streams[s];
+  const bool same_sizes = rp->plan_variant == cfg.variant && rp->plan_nrows == q->nrows && rp->plan_nnz == q->nnz;
+  if (!(rp->plan_valid && same_sizes)) {
+    if (rp->plan && (!same_sizes || rp->plan_cap < need)) {
+      c->dead_plans.push_back(rp->plan);
+      rp->plan = nullptr;
+      rp->plan_cap = 0;
+    }
+    hipError_t e = hipSuccess;
+    if (!rp->plan) {
+      e = hipMalloc(reinterpret_cast<void**>(&rp->plan), need * sizeof(int));
+      if (e != hipSuccess) return e;
+      rp->plan_cap = need;
+    }
+    if (!rp->plan_ev) {
+      e = hipEventCreateWithFlags(&rp->plan_ev, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    e = spmv_plan(st, static_cast<const int*>(ptrs[0]), params, cfg, rp->plan);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(rp->plan_ev, st);
+    if (e != hipSuccess) return e;
+    ++c->n_plans;
+    rp->plan_valid = true;
+    rp->plan_ready = false;
+    rp->plan_stream = s;
+    rp->plan_variant = cfg.variant;
+    rp->plan_nrows = q->nrows;
+    rp->plan_nnz = q->nnz;
+  } else if (s != rp->plan_stream && !rp->plan_ready) {
+    // the partition was computed on another stream: wait for it once it is
+    // not known to be complete
+    const hipError_t qe = hipEventQuery(rp->plan_ev);
+    if (qe == hipSuccess) {
+      rp->plan_ready = true;
+    } else {
+      (void)hipGetLastError();  // not-ready is not an error of this call
+      hipError_t e = hipStreamWaitEvent(st, rp->plan_ev, 0);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return spmv_planned(st, ptrs, params, cfg, rp->plan, c->scratch[s]);
+}
+
 // -------------------------------------------------------------------------
 // submissions
 // -------------------------------------------------------------------------
@@ -219,7 +296,9 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
   }
   if (!c->dry) {
     if (kd) {
-      hipError_t e = kd->launch(c->streams[s], ptrs, params, cfg, c->scratch[s], c->cfg.scratch_bytes);
+      hipError_t e = (kid == DAG_K_SPMV && !c->recording)
+                         ? spmv_with_plan(c, get_buf(c, args[0].buf), s, ptrs, params, cfg)
+                         : kd->launch(c->streams[s], ptrs, params, cfg, c->scratch[s], c->cfg.scratch_bytes);
       set_launch_events(nullptr, nullptr);
       if (e != hipSuccess) return hip_fail(c, e, kd->name);
     } else {
@@ -230,6 +309,7 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
       }
     }
   }
+  note_written(c, c->tmp_acc);
   st = end_task(c, id, s);
   c->launch_us += us_since(t1);
   if (st) return st;
@@ -290,6 +370,7 @@ dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t 
   void* dp = static_cast<char*>(bd->ptr) + doff;
   const void* sp = static_cast<const char*>(bs->ptr) + soff;
   if (!c->dry) HIP_TRY(c, hipMemcpyAsync(dp, sp, bytes, kind, c->streams[s]));
+  note_written(c, c->tmp_acc);
   st = end_task(c, id, s);
   c->launch_us += us_since(t1);
   if (st) return st;
@@ -317,6 +398,7 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
   const uint64_t id = c->tr.add_host(kind, h - 1, kind == TK_HOST_READ ? ACC_R : ACC_W, c->serial,
                                      &c->tmp_wait);
   if (out) *out = id;
+  if (kind == TK_HOST_WRITE) b->plan_valid = false;
   char* p = static_cast<char*>(b->ptr) + off;
   // A read of device memory that waits on its writer: copy on the writer's
   // stream into pinned staging and wait once (one host<->device round trip).
@@ -367,6 +449,8 @@ dag_status do_sync(dag_ctx c) {
   if (!c->dry) {
     for (hipStream_t s : c->streams) HIP_TRY(c, hipStreamSynchronize(s));
     for (hipStream_t s : c->aux) HIP_TRY(c, hipStreamSynchronize(s));
+    for (void* p : c->dead_plans) HIP_TRY(c, hipFree(p));
+    c->dead_plans.clear();
   }
   c->tmp_retired.clear();
   c->tr.retire_all(&c->tmp_retired);
@@ -380,7 +464,7 @@ dag_status do_sync(dag_ctx c) {
 dag_status ensure_aux(dag_ctx c, uint32_t n) {
   while (c->aux.size() < n) {
     hipStream_t st;
-    HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HIP_TRY(c, new_stream(c, &st));
     void* scr = nullptr;
     HIP_TRY(c, hipMalloc(&scr, c->cfg.scratch_bytes));
     HIP_TRY(c, hipMemsetAsync(scr, 0, c->cfg.scratch_bytes, st));
@@ -562,8 +646,11 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
   if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1 ||
-      c.trace > 2 || c.copy_streams > 1 || c.copy_lanes > 4)
+      c.trace > 2 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1)
     return DAG_E_INVAL;
+  // One hardware queue per stream (CU-masked streams) hung in testing with no
+  // cause found in this library, so the mode is refused.
+  if (c.own_queues) return DAG_E_UNSUPPORTED;
   if (c.scratch_bytes == 0) c.scratch_bytes = 4u << 20;
   if (c.scratch_bytes < 4096 || c.scratch_bytes > (1ull << 32)) return DAG_E_INVAL;
   c.scratch_bytes = (c.scratch_bytes + 255) & ~uint64_t(255);
@@ -620,7 +707,9 @@ dag_status dag_destroy(dag_ctx c) {
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
     if (c->trace_ref) (void)hipEventDestroy(c->trace_ref);
+    for (void* p : c->dead_plans) (void)hipFree(p);
     for (Buffer& b : c->bufs) {
+      free_plan(&b);
       if (b.live && b.owned) {
         if (b.loc == DAG_PINNED_HOST)
           (void)hipHostFree(b.ptr);
@@ -712,6 +801,7 @@ dag_status dag_buffer_release(dag_ctx c, dag_buf h) {
   c->tmp_retired.clear();
   c->tr.retire(c->tr.last_id(), &c->tmp_retired);
   recycle_retired(c);
+  if (!c->dry) free_plan(b);  // every SpMV that read it has completed
   if (b->owned && !c->dry) {
     hipError_t e = b->loc == DAG_PINNED_HOST ? hipHostFree(b->ptr) : hipFree(b->ptr);
     if (e != hipSuccess) return hip_fail(c, e, "free");
@@ -939,6 +1029,7 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   const uint64_t id = c->tr.add_gpu(TK_REGION, 0, r->accs.data(), static_cast<uint32_t>(r->accs.size()),
                                     c->serial, &s, &created);
   if (out) *out = id;
+  note_written(c, r->accs);
   c->submit_us += us_since(t0);
   dag_status st = ensure_stream(c, s);
   if (st) return st;
@@ -1046,6 +1137,7 @@ dag_status dag_get_stats(dag_ctx c, dag_stats* out) {
   out->active = static_cast<uint32_t>(c->tr.num_active());
   out->submit_host_us = c->submit_us;
   out->launch_host_us = c->launch_us;
+  out->spmv_plans = c->n_plans;
   return DAG_OK;
 }
 

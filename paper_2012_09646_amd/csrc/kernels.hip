@@ -231,9 +231,61 @@ __device__ __forceinline__ double bs_price(double s, double strike, double mu_t,
   return s * n1 - disc_strike * n2;
 }
 
+// Per-launch constants of the call price.
+struct BsConst {
+  double strike, mu_t, vol_t, disc_strike;  // K, (r + vol^2/2) T, vol sqrt(T), K e^{-rT}
+  double inv_strike, inv_vol_t, growth;     // 1/K, 1/(vol sqrt(T)), e^{rT}/K
+};
+
+#include "erfcx_poly.inc"
+
+// erfcx(a) = exp(a^2) erfc(a) for a >= 0 from one polynomial in
+// y = 2t - 1, t = K/(K + a) (coefficients fitted offline to 1.8e-15).
+__device__ __forceinline__ double erfcx_pos(double a) {
+  // t by the hardware reciprocal and two Newton steps (error below 1 ulp of
+  // the fit's accuracy; the divisor is >= K, so no denormal or zero cases)
+  const double x = kErfcxK + a;
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  const double t = kErfcxK * r;
+  const double y = 2.0 * t - 1.0;
+  double g = kErfcxC[kErfcxDegree];
+#pragma unroll
+  for (int k = kErfcxDegree - 1; k >= 0; --k) g = fma(g, y, kErfcxC[k]);
+  return t * g;
+}
+
+// Same price with one exponential per option: N(d) = h or 1 - h with
+// h = exp(-d^2/2) erfcx(|d|/sqrt2)/2, and exp(-d2^2/2) = exp(-d1^2/2) S e^{rT}/K
+// (d1^2 - d2^2 = 2 (ln(S/K) + rT)).  Where exp(-d1^2/2) underflows the second
+// exponential is computed directly.
+__device__ __forceinline__ double bs_price_fast(double s, const BsConst& k) {
+  const double d1 = (log(s * k.inv_strike) + k.mu_t) * k.inv_vol_t;
+  const double d2 = d1 - k.vol_t;
+  const double e1 = exp(-0.5 * d1 * d1);
+  double e2 = e1 * s * k.growth;
+  if (e1 == 0.0) e2 = exp(-0.5 * d2 * d2);
+  const double h1 = 0.5 * e1 * erfcx_pos(fabs(d1) * M_SQRT1_2);
+  const double h2 = 0.5 * e2 * erfcx_pos(fabs(d2) * M_SQRT1_2);
+  const double n1 = d1 < 0.0 ? h1 : 1.0 - h1;
+  const double n2 = d2 < 0.0 ? h2 : 1.0 - h2;
+  return s * n1 - k.disc_strike * n2;
+}
+
+// variant 0: the library's erfc; variant 1: bs_price_fast.
+template <int V>
+__device__ __forceinline__ float bs_one(float s, const BsConst& k) {
+  if constexpr (V == 0) {
+    return static_cast<float>(bs_price(s, k.strike, k.mu_t, k.vol_t, k.disc_strike));
+  } else {
+    return static_cast<float>(bs_price_fast(s, k));
+  }
+}
+
+template <int V>
 __global__ __launch_bounds__(1024) void k_bs_call(const float* __restrict__ S, float* __restrict__ C,
-                                                  uint64_t n, int vec, double strike, double mu_t,
-                                                  double vol_t, double disc_strike) {
+                                                  uint64_t n, int vec, BsConst k) {
   const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   if (vec) {
@@ -243,17 +295,15 @@ __global__ __launch_bounds__(1024) void k_bs_call(const float* __restrict__ S, f
     for (uint64_t i = gid; i < n4; i += stride) {
       const float4 s = s4[i];
       float4 c;
-      c.x = static_cast<float>(bs_price(s.x, strike, mu_t, vol_t, disc_strike));
-      c.y = static_cast<float>(bs_price(s.y, strike, mu_t, vol_t, disc_strike));
-      c.z = static_cast<float>(bs_price(s.z, strike, mu_t, vol_t, disc_strike));
-      c.w = static_cast<float>(bs_price(s.w, strike, mu_t, vol_t, disc_strike));
+      c.x = bs_one<V>(s.x, k);
+      c.y = bs_one<V>(s.y, k);
+      c.z = bs_one<V>(s.z, k);
+      c.w = bs_one<V>(s.w, k);
       c4[i] = c;
     }
-    for (uint64_t i = (n4 << 2) + gid; i < n; i += stride)
-      C[i] = static_cast<float>(bs_price(S[i], strike, mu_t, vol_t, disc_strike));
+    for (uint64_t i = (n4 << 2) + gid; i < n; i += stride) C[i] = bs_one<V>(S[i], k);
   } else {
-    for (uint64_t i = gid; i < n; i += stride)
-      C[i] = static_cast<float>(bs_price(S[i], strike, mu_t, vol_t, disc_strike));
+    for (uint64_t i = gid; i < n; i += stride) C[i] = bs_one<V>(S[i], k);
   }
 }
 
@@ -834,6 +884,11 @@ const char* cfg_block_any(const LaunchCfg& c) {
   if (c.variant != 0) return "variant must be 0";
   return nullptr;
 }
+const char* cfg_bs(const LaunchCfg& c) {
+  if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
+  if (c.variant > 1) return "variant: 0 = library erfc, 1 = one exponential and one polynomial per CDF";
+  return nullptr;
+}
 const char* cfg_reduce(const LaunchCfg& c) {
   if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
   if (c.variant > 1) return "variant: 0 = two kernels, 1 = single pass";
@@ -927,13 +982,23 @@ const char* v_bs(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, si
 hipError_t l_bs(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const auto* q = static_cast<const dag_p_bs*>(p);
   if (q->n == 0) return hipSuccess;
-  const double vol_t = q->vol * std::sqrt(q->years);
-  const double mu_t = (q->rate + 0.5 * q->vol * q->vol) * q->years;
-  const double disc = q->strike * std::exp(-q->rate * q->years);
+  BsConst k;
+  k.strike = q->strike;
+  k.vol_t = q->vol * std::sqrt(q->years);
+  k.mu_t = (q->rate + 0.5 * q->vol * q->vol) * q->years;
+  k.disc_strike = q->strike * std::exp(-q->rate * q->years);
+  k.inv_strike = 1.0 / q->strike;
+  k.inv_vol_t = 1.0 / k.vol_t;
+  k.growth = std::exp(q->rate * q->years) / q->strike;
   const int vec = aligned16(a[0]) && aligned16(a[1]);
-  DAGRT_LAUNCH(k_bs_call, dim3(stream_grid(vec ? ceil_div(q->n, 4) : q->n, c)), dim3(c.block), 0, s,
-                     static_cast<const float*>(a[0]), static_cast<float*>(a[1]), q->n, vec, q->strike,
-                     mu_t, vol_t, disc);
+  const dim3 grid(stream_grid(vec ? ceil_div(q->n, 4) : q->n, c));
+  if (c.variant == 1) {
+    DAGRT_LAUNCH(k_bs_call<1>, grid, dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                 static_cast<float*>(a[1]), q->n, vec, k);
+  } else {
+    DAGRT_LAUNCH(k_bs_call<0>, grid, dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                 static_cast<float*>(a[1]), q->n, vec, k);
+  }
   return hipGetLastError();
 }
 
@@ -1092,10 +1157,7 @@ void launch_spmv_ipt(hipStream_t s, void* const* a, const dag_p_csr* q, const Sp
                      static_cast<int>(q->ncols), static_cast<int>(q->nnz), sc);
 }
 
-hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t) {
-  const auto* q = static_cast<const dag_p_csr*>(p);
-  if (q->nrows == 0) return hipSuccess;
-  const int tiles = static_cast<int>(spmv_tiles(q, c.variant));
+SpmvScratch spmv_carries(void* scr, int tiles) {
   char* base = static_cast<char*>(scr) + kScratchPartialsOffset;
   SpmvScratch sc;
   sc.head_val = reinterpret_cast<double*>(base);
@@ -1103,23 +1165,44 @@ hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   sc.head_row = reinterpret_cast<int*>(base + 16ull * tiles);
   sc.tail_row = reinterpret_cast<int*>(base + 20ull * tiles);
   sc.coord = reinterpret_cast<int*>(base + 24ull * tiles);
+  return sc;
+}
+
+hipError_t spmv_partition_into(hipStream_t s, const int* row_ptr, const dag_p_csr* q, uint32_t ipt, int tiles,
+                               int* coord) {
+  SpmvScratch sc{};
+  sc.coord = coord;
   const int waves_per_wg = 256 / kWave;
-  DAGRT_LAUNCH(k_spmv_partition, dim3(ceil_div(tiles + 1, waves_per_wg)), dim3(256), 0, s,
-                     static_cast<const int*>(a[0]), static_cast<int>(q->nrows), static_cast<int>(q->nnz),
-                     static_cast<int>(256 * c.variant), tiles, sc);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  switch (c.variant) {
+  DAGRT_LAUNCH(k_spmv_partition, dim3(ceil_div(tiles + 1, waves_per_wg)), dim3(256), 0, s, row_ptr,
+               static_cast<int>(q->nrows), static_cast<int>(q->nnz), static_cast<int>(256 * ipt), tiles, sc);
+  return hipGetLastError();
+}
+
+// Merge and fix-up over the tile boundaries in sc.coord.
+hipError_t spmv_merge_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, uint32_t ipt, int tiles,
+                            const SpmvScratch& sc) {
+  switch (ipt) {
     case 4: launch_spmv_ipt<4>(s, a, q, sc, tiles); break;
     case 12: launch_spmv_ipt<12>(s, a, q, sc, tiles); break;
     case 16: launch_spmv_ipt<16>(s, a, q, sc, tiles); break;
     default: launch_spmv_ipt<8>(s, a, q, sc, tiles); break;
   }
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const int waves_per_wg = 256 / kWave;
   DAGRT_LAUNCH(k_spmv_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s, static_cast<float*>(a[4]),
-                     sc, tiles);
+               sc, tiles);
   return hipGetLastError();
+}
+
+hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t) {
+  const auto* q = static_cast<const dag_p_csr*>(p);
+  if (q->nrows == 0) return hipSuccess;
+  const int tiles = static_cast<int>(spmv_tiles(q, c.variant));
+  const SpmvScratch sc = spmv_carries(scr, tiles);
+  hipError_t e = spmv_partition_into(s, static_cast<const int*>(a[0]), q, c.variant, tiles, sc.coord);
+  if (e != hipSuccess) return e;
+  return spmv_merge_fixup(s, a, q, c.variant, tiles, sc);
 }
 
 const char* cfg_spmv_rows(const LaunchCfg& c) {
@@ -1233,7 +1316,7 @@ const KernelDesc kTable[] = {
     /* 0 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
     /* 1 */ {"vec_square", 1, 0x1, sizeof(dag_p_n), {256, 0, 0}, v_vec_square, l_vec_square, cfg_block_any},
     /* 2 */ {"vec_sum_diff", 3, 0x4, sizeof(dag_p_n), {256, 1024, 0}, v_vec_sum_diff, l_vec_sum_diff, cfg_reduce},
-    /* 3 */ {"bs_call", 2, 0x2, sizeof(dag_p_bs), {256, 0, 0}, v_bs, l_bs, cfg_block_any},
+    /* 3 */ {"bs_call", 2, 0x2, sizeof(dag_p_bs), {256, 0, 0}, v_bs, l_bs, cfg_bs},
     /* 4 */ {"gauss_blur", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_blur, l_blur, cfg_tile256},
     /* 5 */ {"sobel", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_img2, l_sobel, cfg_tile256},
     /* 6 */ {"minmax", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_minmax, l_minmax, cfg_reduce},
@@ -1252,6 +1335,27 @@ const KernelDesc kTable[] = {
 const KernelDesc* builtin_kernel(uint32_t id) {
   if (id >= sizeof(kTable) / sizeof(kTable[0])) return nullptr;
   return kTable[id].name ? &kTable[id] : nullptr;
+}
+
+uint64_t spmv_plan_ints(const void* params, const LaunchCfg& cfg) {
+  const auto* q = static_cast<const dag_p_csr*>(params);
+  return q->nrows == 0 ? 0 : spmv_tiles(q, cfg.variant) + 1;
+}
+
+hipError_t spmv_plan(hipStream_t s, const int* row_ptr, const void* params, const LaunchCfg& cfg, int* coord) {
+  const auto* q = static_cast<const dag_p_csr*>(params);
+  if (q->nrows == 0) return hipSuccess;
+  return spmv_partition_into(s, row_ptr, q, cfg.variant, static_cast<int>(spmv_tiles(q, cfg.variant)), coord);
+}
+
+hipError_t spmv_planned(hipStream_t s, void* const* ptrs, const void* params, const LaunchCfg& cfg,
+                        const int* coord, void* scratch) {
+  const auto* q = static_cast<const dag_p_csr*>(params);
+  if (q->nrows == 0) return hipSuccess;
+  const int tiles = static_cast<int>(spmv_tiles(q, cfg.variant));
+  SpmvScratch sc = spmv_carries(scratch, tiles);
+  sc.coord = const_cast<int*>(coord);
+  return spmv_merge_fixup(s, ptrs, q, cfg.variant, tiles, sc);
 }
 
 void set_launch_events(hipEvent_t start, hipEvent_t stop) {

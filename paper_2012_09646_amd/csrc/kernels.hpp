@@ -35,6 +35,16 @@ const KernelDesc* builtin_kernel(uint32_t id);
 // first kernel dispatch takes `start`, every dispatch `stop`.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
+// Merge-path SpMV (kernel 9) in two parts, for callers that keep a matrix's
+// tile partition while its row pointers stay unchanged: the partition needs
+// spmv_plan_ints() ints of device memory and depends only on row_ptr, nrows,
+// nnz and the launch variant; spmv_planned() runs the SpMV proper with it.
+// Arguments as for the kernel's launch; the call must have been validated.
+uint64_t spmv_plan_ints(const void* params, const LaunchCfg& cfg);
+hipError_t spmv_plan(hipStream_t s, const int* row_ptr, const void* params, const LaunchCfg& cfg, int* coord);
+hipError_t spmv_planned(hipStream_t s, void* const* ptrs, const void* params, const LaunchCfg& cfg,
+                        const int* coord, void* scratch);
+
 // Device wall-clock frequency in kHz (for the spin kernel); set once.
 void set_wall_clock_khz(uint64_t khz);
 

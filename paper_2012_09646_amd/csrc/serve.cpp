@@ -221,7 +221,7 @@ dag_status dag_serve_create(dag_ctx c, const dag_serve_config* cfg, dag_server* 
     for (uint32_t i = 0; e == hipSuccess && i < cfg->lanes; ++i) {
       hipStream_t st;
       void* scr = nullptr;
-      e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      e = new_stream(c, &st);
       if (e == hipSuccess) s->lanes.push_back(st);
       if (e == hipSuccess) e = hipMalloc(&scr, c->cfg.scratch_bytes);
       if (e == hipSuccess) s->lane_scratch.push_back(scr);

@@ -42,7 +42,7 @@ class dag_config(C.Structure):
     _fields_ = [("policy", C.c_uint32), ("max_streams", C.c_uint32), ("trace", C.c_uint32),
                 ("dry_run", C.c_uint32), ("device", C.c_int32), ("graph_mode", C.c_uint32),
                 ("scratch_bytes", C.c_uint64), ("copy_streams", C.c_uint32),
-                ("spin_wait", C.c_uint32), ("copy_lanes", C.c_uint32), ("reserved", C.c_uint32)]
+                ("spin_wait", C.c_uint32), ("copy_lanes", C.c_uint32), ("own_queues", C.c_uint32)]
 
 
 class dag_arg(C.Structure):
@@ -64,7 +64,7 @@ class dag_stats(C.Structure):
     _fields_ = [("tasks", C.c_uint64), ("vertices", C.c_uint64), ("edges", C.c_uint64),
                 ("waits", C.c_uint64), ("host_waits", C.c_uint64), ("streams", C.c_uint32),
                 ("active", C.c_uint32), ("submit_host_us", C.c_double),
-                ("launch_host_us", C.c_double)]
+                ("launch_host_us", C.c_double), ("spmv_plans", C.c_uint64)]
 
 
 class dag_launch(C.Structure):
@@ -462,9 +462,11 @@ class Context:
     """Convenience wrapper: one execution context with its buffers."""
 
     def __init__(self, policy=DAG_PARALLEL_ASYNC, max_streams=8, trace=0, dry_run=False,
-                 device=0, graph_mode=0, scratch_bytes=0, copy_streams=0, spin_wait=0, copy_lanes=1):
+                 device=0, graph_mode=0, scratch_bytes=0, copy_streams=0, spin_wait=0, copy_lanes=1,
+                 own_queues=0):
         self.cfg = dag_config(policy, max_streams, int(trace), int(bool(dry_run)), device,
-                              graph_mode, scratch_bytes, copy_streams, int(spin_wait), int(copy_lanes), 0)
+                              graph_mode, scratch_bytes, copy_streams, int(spin_wait), int(copy_lanes),
+                              int(own_queues))
         self.h = dag_create(self.cfg)
 
     def close(self):

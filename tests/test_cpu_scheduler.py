@@ -193,6 +193,13 @@ def test_bad_config_rejected():
         D.Context(dry_run=True, max_streams=65)
     with pytest.raises(D.DagError):
         D.Context(dry_run=True, policy=7)
+    with pytest.raises(D.DagError):
+        D.Context(dry_run=True, own_queues=2)
+    with pytest.raises(D.DagError) as e:
+        D.Context(dry_run=True, own_queues=1)
+    assert e.value.name == "DAG_E_UNSUPPORTED"
+    with pytest.raises(D.DagError):
+        D.Context(dry_run=True, copy_lanes=5)
 
 
 def test_serial_policy_computes_no_dependencies():

@@ -32,6 +32,34 @@ def test_bs(n, tasks, lanes):
     G.check_program(W.bs_program(n=n, tasks=tasks, seed=1), copy_streams=lanes)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("r,sigma,years", [(0.08, 0.3, 1.0), (0.0, 1.5, 4.0), (0.2, 0.05, 0.1), (0.03, 3.0, 30.0)])
+def test_bs_variants_wide_range(variant, r, sigma, years):
+    """Both call-price variants against the oracle over spot prices from deep
+    out of the money to deep in the money (log-uniform over 1e-3 .. 1e4 with
+    strike 25), at several rates, volatilities and maturities."""
+    banner("bs variant=%d r=%g sigma=%g T=%g" % (variant, r, sigma, years))
+    n = 300001
+    spots = np.exp(np.linspace(np.log(1e-3), np.log(1e4), n)).astype(np.float32)
+    spots[:4] = [25.0, 24.999998, 25.000002, 1e-3]
+    prog = W.Program("bs1", {"S": W.Buf(4 * n, init=spots), "C": W.Buf(4 * n)},
+                     [W.K("bs_call", [("S", "c"), ("C", "m")], n=n, K=25.0, r=r, sigma=sigma, T=years)], ["C"])
+    ref = G.oracle_run(prog)["C"].view(np.float32).astype(np.float64)
+    from paper_2012_09646_amd import runner
+    ctx = D.Context()
+    try:
+        ctx.set_launch("bs_call", 256, 0, variant)
+        b = runner.Bound(ctx, prog)
+        b.run()
+        got = b.read("C").view(np.float32).astype(np.float64)
+    finally:
+        ctx.close()
+    big = np.abs(ref) >= 1e-30
+    bad = np.abs(got - ref) > 1e-5 * np.abs(ref)
+    assert not (bad & big).any(), (np.nonzero(bad & big)[0][:5], got[bad & big][:5], ref[bad & big][:5])
+    assert np.all(np.abs(got[~big] - ref[~big]) <= 1e-30)
+
+
 @pytest.mark.parametrize("w,h", [(1, 1), (5, 3), (100, 77), (333, 130), (2048, 2048)])
 def test_img(w, h):
     banner("img %dx%d" % (w, h))
@@ -84,6 +112,60 @@ def test_spmv_long_rows_and_empty_rows(variant):
     assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:5])
 
 
+def _random_csr(seed, n, long_row):
+    rng = np.random.default_rng(seed)
+    lengths = rng.integers(0, 40, n)
+    lengths[long_row] = 5000
+    rp = np.zeros(n + 1, np.int32)
+    np.cumsum(lengths, out=rp[1:])
+    ci = rng.integers(0, n, int(rp[-1])).astype(np.int32)
+    return rp, ci, W.uniform_f32(seed + 100, ci.size)
+
+
+@pytest.mark.parametrize("variant", [4, 16])
+def test_spmv_partition_reuse(variant):
+    """The merge-path partition kept with the row-pointer buffer: reused by an
+    SpMV on another stream, recomputed after the row pointers are rewritten
+    and when the same buffer is used with other sizes."""
+    banner("spmv partition reuse variant=%d" % variant)
+    n = 3000
+    rpa, cia, vaa = _random_csr(21, n, 7)
+    rpb, cib, vab = _random_csr(22, n, 2999)
+    cap = max(cia.size, cib.size)
+    bufs = {"rp": W.Buf(rpa.nbytes, init=rpa), "ci": W.Buf(4 * cap, init=np.resize(cia, cap)),
+            "va": W.Buf(4 * cap, init=np.resize(vaa, cap)),
+            "rpb": W.Buf(rpb.nbytes, init=rpb), "cib": W.Buf(cib.nbytes, init=cib), "vab": W.Buf(vab.nbytes, init=vab),
+            "x": W.Buf(4 * n, init=W.uniform_f32(31, n)), "x2": W.Buf(4 * n, init=W.uniform_f32(32, n))}
+    for i in range(1, 6):
+        bufs["y%d" % i] = W.Buf(4 * n)
+    mat = [("rp", "c"), ("ci", "c"), ("va", "c")]
+    half = n // 2
+    ops = [W.K("spmv", mat + [("x", "c"), ("y1", "m")], nrows=n, ncols=n, nnz=int(cia.size)),
+           W.K("spmv", mat + [("x2", "c"), ("y2", "m")], nrows=n, ncols=n, nnz=int(cia.size)),
+           W.COPY("rp", "rpb", rpb.nbytes), W.COPY("ci", "cib", cib.nbytes), W.COPY("va", "vab", vab.nbytes),
+           W.K("spmv", mat + [("x", "c"), ("y3", "m")], nrows=n, ncols=n, nnz=int(cib.size)),
+           W.K("spmv", mat + [("x2", "c"), ("y4", "m")], nrows=half, ncols=n, nnz=int(rpb[half])),
+           W.K("spmv", mat + [("x2", "c"), ("y5", "m")], nrows=n, ncols=n, nnz=int(cib.size))]
+    prog = W.Program("spmv_reuse", bufs, ops, ["y1", "y2", "y3", "y4", "y5"])
+    ref = G.oracle_run(prog)
+    from paper_2012_09646_amd import runner
+    ctx = D.Context()
+    try:
+        ctx.set_launch("spmv", 256, 0, variant)
+        for rep in range(2):  # the second run on fresh buffers of the same context
+            b = runner.Bound(ctx, prog)
+            b.run()
+            st = b.streams()
+            assert st[1] != st[2]  # the second SpMV uses a partition made on another stream
+            for name in prog.outputs:
+                G.assert_close(prog, name, b.read(name), ref[name])
+            # computed by SpMVs 1, 6 (rp rewritten), 7 and 8 (other sizes); reused by 2
+            assert ctx.stats().spmv_plans == 4 * (rep + 1)
+            b.release()
+    finally:
+        ctx.close()
+
+
 def test_spmv_no_nonzeros():
     banner("spmv nnz=0")
     n = 1000
@@ -101,6 +183,16 @@ def test_policies_agree(policy, pool, batch):
     for prog in (W.img_program(side=200, height=130, seed=9), W.hits_program(n=2000, iters=4, seed=8),
                  W.bs_program(n=5000, tasks=5)):
         G.check_program(prog, policy=policy, max_streams=pool, batch=batch)
+
+
+@pytest.mark.skip(reason="one hardware queue per stream (CU-masked streams) hung on the MI355X with "
+                         "copy_streams=0 and no cause was found in the library; the mode is refused")
+@pytest.mark.parametrize("copy_streams", [0, 1])
+def test_own_queues(copy_streams):
+    banner("own hardware queue per stream, copy_streams=%d" % copy_streams)
+    for prog in (W.img_program(side=300, height=200, seed=11), W.hits_program(n=5000, iters=3, seed=12),
+                 W.bs_program(n=70001, tasks=6, seed=13)):
+        G.check_program(prog, max_streams=6, own_queues=1, copy_streams=copy_streams)
 
 
 @pytest.mark.parametrize("variant", [0, 1])
