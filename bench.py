@@ -30,12 +30,16 @@ sys.path.insert(0, ROOT)
 METRIC = "DAG makespan speedup vs serial + % critical-path bound; serving p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # vector fp64: 256 CUs x 128 flop/clk (4 SIMDs x 16 lanes x FMA) x 2.4 GHz
-# fp64 work of one Black-Scholes price as executed on gfx950, from the SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64
-# counters of the bs_call kernel (127 FMA + 61 ADD + 22 MUL + 7 TRANS per element, FMA = 2 flops)
-BS_FLOPS_PER_ELEMENT = 2 * 127 + 61 + 22 + 7
+# fp64 work of one Black-Scholes price: the SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 counters of the leaner
+# kernel variant (1: one exp and one polynomial per CDF) give 83 FMA + 44 ADD + 23 MUL + 3 TRANS per element
+# (FMA = 2 flops); that count is taken as the method's work for both variants (variant 0, the library erfc,
+# executes 127 + 61 + 22 + 7).  VALU wave instructions per element (all kinds): 285.75 and 206.25.
+BS_FLOPS_PER_ELEMENT = 2 * 83 + 44 + 23 + 3
+BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25}
 # HBM bytes per bs_call launch from FETCH_SIZE / WRITE_SIZE, each divided by what the counter reads for a
-# 256 MiB copy kernel (FETCH_SIZE 0.500x, WRITE_SIZE 1.000x of the true bytes): 16.18 MiB in + 16.00 MiB out
-TRAFFIC_BS_BYTES = int((8286.7 / 0.50004 + 16384.0 / 1.0) * 1024)
+# 256 MiB copy kernel (FETCH_SIZE 0.50005x, WRITE_SIZE 1.000x of the true bytes): 16.16 MiB in + 16.00 MiB out
+TRAFFIC_BS_BYTES = int((8276.19 / 0.50005 + 16384.0 / 1.0) * 1024)
+CUS, CLOCK_GHZ = 256, 2.4
 
 
 def log(*a):
@@ -51,12 +55,14 @@ def parse():
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
     ap.add_argument("--serve-lanes", type=int, default=8, help="serving: HIP streams requests spread over")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
+    ap.add_argument("--low-rate", type=float, default=600.0,
+                    help="serving: a second, lower arrival rate (half the requests; 0 = skip)")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"),
                     help="kernel launch configurations from the autotuner (ignored if missing)")
     ap.add_argument("--max-streams", type=int, default=0,
                     help="stream pool bound (0 = per workload from the tuning file, else 8)")
     ap.add_argument("--hw-queues", type=int, default=0,
-                    help="GPU_MAX_HW_QUEUES for this process (0 = runtime default)")
+                    help="GPU_MAX_HW_QUEUES for this process (0 = from the tuning file, else the runtime's)")
     ap.add_argument("--copy-streams", type=int, default=0, choices=[0, 1],
                     help="0: one FIFO stream per copy direction; 1: copies placed like kernels")
     ap.add_argument("--copy-lanes", type=int, default=0,
@@ -73,6 +79,11 @@ def main():
         print("bench.py measures one GPU: the scheduler space-shares a single device; "
               "multi-GPU runs are not part of this build (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if not args.hw_queues and args.tuned and os.path.exists(args.tuned):
+        # the tuned hardware queue count of the headline workload; HIP reads it
+        # once at start-up, so it is set before anything touches the GPU
+        with open(args.tuned) as f:
+            args.hw_queues = int(json.load(f).get("dag", {}).get("bs", {}).get("hw_queues", 0))
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import numpy as np  # noqa: F401
@@ -159,6 +170,7 @@ def main():
         edges = sorted({(s, d) for s, d, _, _ in bP.edges()})
         res["edges"] = len(edges)
         res["event_waits_per_run"] = sum(len(w) for w in bP.waits().values())
+        eager_out = {o: bP.read(o) for o in prog.outputs}  # outputs of the last timed run
         ctxP.close()
 
         # the same runs with timing events around every kernel (not copies):
@@ -275,6 +287,12 @@ def main():
             res[tag + "_ms"] = statistics.median(gt)
             res[tag + "_speedup"] = res["serial_ms"] / res[tag + "_ms"]
             res[tag + "_cp_frac"] = res["cp_bound_ms"] / res[tag + "_ms"]
+            # one more replay into cleared outputs must reproduce the eager outputs bit for bit
+            for o in prog.outputs:
+                ctxG.host_write(bG.h[o], np.zeros(prog.bufs[o].nbytes, np.uint8))
+            reset(ctxG, bG)
+            bG.replay(1, times)
+            res[tag + "_matches_eager"] = all(np.array_equal(bG.read(o), eager_out[o]) for o in prog.outputs)
             ctxG.close()
         return res, ktimes
 
@@ -296,24 +314,31 @@ def main():
         for t in tmpls:
             sid = srv.add(t)
             foot.append(srv.footprint(sid))
-        arr, shp = W.poisson_trace(4, args.requests, args.rate, len(tmpls))
-        log("serving: %d requests, %d shapes" % (len(arr), len(tmpls)))
-        mix, st, _ = srv.run(arr, shp)
-        log("serving: serial baseline")
-        ser, st2, _ = srv.run(arr, shp, mode=D.DAG_SERVE_SERIAL)
+        def one_rate(rate, nreq):
+            arr, shp = W.poisson_trace(4, nreq, rate, len(tmpls))
+            log("serving: %d requests at %g/s, %d shapes" % (len(arr), rate, len(tmpls)))
+            mix, st, _ = srv.run(arr, shp)
+            log("serving: serial baseline")
+            ser, st2, _ = srv.run(arr, shp, mode=D.DAG_SERVE_SERIAL)
+            return {
+                "requests": len(arr), "rate_per_s": rate,
+                "mean_footprint_mb": float(np.mean([foot[i][0] for i in shp])) / 2 ** 20,
+                "concurrent": {"p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+                               "req_per_s": st.req_per_s, "max_inflight": st.max_inflight,
+                               "max_queued": st.max_queued, "peak_device_gb": st.peak_device_bytes / 2 ** 30},
+                "serial": {"p50_ms": st2.p50_ms, "p99_ms": st2.p99_ms, "mean_ms": st2.mean_ms,
+                           "req_per_s": st2.req_per_s, "max_queued": st2.max_queued},
+                "throughput_gain": st.req_per_s / st2.req_per_s if st2.req_per_s else None,
+            }
+
+        out = one_rate(args.rate, args.requests)
+        out.update({"shapes": len(tmpls), "budget_bytes": budget, "lanes": args.serve_lanes})
+        # a second, lower arrival rate at which the serial baseline is not overloaded
+        if args.low_rate:
+            out["low_rate"] = one_rate(args.low_rate, max(1, args.requests // 2))
         srv.close()
         ctx.close()
-        return {
-            "requests": len(arr), "rate_per_s": args.rate, "shapes": len(tmpls), "budget_bytes": budget,
-            "lanes": args.serve_lanes,
-            "mean_footprint_mb": float(np.mean([foot[i][0] for i in shp])) / 2 ** 20,
-            "concurrent": {"p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
-                           "req_per_s": st.req_per_s, "max_inflight": st.max_inflight,
-                           "max_queued": st.max_queued, "peak_device_gb": st.peak_device_bytes / 2 ** 30},
-            "serial": {"p50_ms": st2.p50_ms, "p99_ms": st2.p99_ms, "mean_ms": st2.mean_ms,
-                       "req_per_s": st2.req_per_s, "max_queued": st2.max_queued},
-            "throughput_gain": st.req_per_s / st2.req_per_s if st2.req_per_s else None,
-        }
+        return out
 
     workloads = ["bs", "vec", "img", "hits", "serve"] if args.workload == "all" else [args.workload]
     results = {}
@@ -380,11 +405,15 @@ def main():
         by = v[0][1]
         fl = BS_FLOPS_PER_ELEMENT * (by // 8)
         ach = fl / avg / 1e9                          # TFLOP/s
+        variant = int(tuned.get("bs_call", {}).get("variant", 0))
+        # share of the SIMDs' issue cycles taken by VALU instructions (a wave64
+        # instruction occupies a 16-lane SIMD for 4 cycles; 4 SIMDs per CU)
+        valu_busy = (BS_VALU_PER_ELEMENT[variant] * (by // 8) / 64 * 4) / (4 * CUS * CLOCK_GHZ * 1e9 * avg / 1e3)
         line["roofline"] = {"kernel": "bs_call", "bound": "alu", "achieved": round(ach, 2),
                             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
                             "traffic": TRAFFIC_BS_BYTES, "avg_us": round(avg * 1e3, 2), "flops_per_launch": fl,
                             "bytes_per_launch": by, "hbm_gbs": round(by / avg / 1e6, 1),
-                            "launches": len(v)}
+                            "launches": len(v), "variant": variant, "valu_busy": round(valu_busy, 3)}
     if "serve" in results:
         line["serving"] = results.pop("serve")
     line["workloads"] = results

@@ -576,26 +576,6 @@ __device__ long long wave_merge_search(const int* __restrict__ row_ptr, int nrow
   return lo + __popcll(__ballot(p));
 }
 
-// Smallest p in [lo, hi) with a[p] >= key (a non-decreasing), or hi; one wave.
-__device__ int wave_lower_bound(const int* __restrict__ a, int lo, int hi, int key) {
-  const int lane = threadIdx.x & (kWave - 1);
-  while (hi - lo > kWave) {
-    const long long span = hi - lo;
-    const int x = static_cast<int>(lo + ((lane + 1) * span) / (kWave + 1));
-    const int c = __popcll(__ballot(a[x] < key));
-    if (c == 0) {
-      hi = static_cast<int>(lo + span / (kWave + 1));
-    } else {
-      const int sc1 = static_cast<int>(lo + (c * span) / (kWave + 1));
-      const int nhi = c < kWave ? static_cast<int>(lo + ((c + 1) * span) / (kWave + 1)) : hi;
-      lo = sc1 + 1;
-      hi = nhi;
-    }
-  }
-  const int x = lo + lane;
-  return lo + __popcll(__ballot(x < hi && a[x] < key));
-}
-
 // Tile boundaries of the merge path, one wave per boundary, all in parallel.
 __global__ __launch_bounds__(256) void k_spmv_partition(const int* __restrict__ row_ptr, int nrows,
                                                         int nnz, int tile, int ntiles, SpmvScratch sc) {
@@ -754,15 +734,19 @@ __global__ __launch_bounds__(256) void k_spmv_merge(const int* __restrict__ row_
 }
 
 // Rows split across tiles: one wave per tile whose first row started in an
-// earlier tile finds the run of preceding tiles that end inside that row
-// (tile tail rows are non-decreasing) and adds their parts in a fixed order.
-__global__ __launch_bounds__(256) void k_spmv_fixup(float* __restrict__ y, SpmvScratch sc, int ntiles) {
+// earlier tile adds the parts of that row held by the preceding tiles, in a
+// fixed order.  Row r enters the merge path at diagonal r + row_ptr[r], so
+// the first tile whose end reaches that diagonal is the first with a part of
+// it (a tile ending exactly there holds an empty part): no search is needed.
+__global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ row_ptr, float* __restrict__ y,
+                                                    SpmvScratch sc, int ntiles, int nnz, int tile) {
   const int b = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (b >= ntiles) return;
   const int r = sc.head_row[b];
   if (r < 0 || b == 0) return;
-  const int p0 = wave_lower_bound(sc.tail_row, 0, b, r);
+  const long long dr = static_cast<long long>(r) + clamp_nnz(row_ptr[r], nnz);
+  const int p0 = static_cast<int>(min(static_cast<long long>(b), max(0LL, (dr + tile - 1) / tile - 1)));
   double acc = 0.0;
   for (int p = p0 + lane; p < b; p += kWave) acc += sc.tail_val[p];
   acc = wave_sum(acc);
@@ -1190,8 +1174,8 @@ hipError_t spmv_merge_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, u
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int waves_per_wg = 256 / kWave;
-  DAGRT_LAUNCH(k_spmv_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s, static_cast<float*>(a[4]),
-               sc, tiles);
+  DAGRT_LAUNCH(k_spmv_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s, static_cast<const int*>(a[0]),
+               static_cast<float*>(a[4]), sc, tiles, static_cast<int>(q->nnz), static_cast<int>(256 * ipt));
   return hipGetLastError();
 }
 

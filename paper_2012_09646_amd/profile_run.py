@@ -27,11 +27,16 @@ def main():
     ap.add_argument("--copies", type=int, default=3)
     ap.add_argument("--serial", action="store_true", help="serial policy: every call alone on the GPU")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"))
+    ap.add_argument("--set", action="append", default=[], metavar="KERNEL=BLOCK,CAP,VARIANT",
+                    help="launch configuration override after the tuning file (repeatable)")
     args = ap.parse_args()
     prog, _ = tune.workload_program(args.workload)
     ctx = D.Context(policy=D.DAG_SERIAL_SYNC if args.serial else D.DAG_PARALLEL_ASYNC)
     if args.tuned and os.path.exists(args.tuned):
         tune.apply_kernels(ctx, tune.load(args.tuned).get("kernels", {}))
+    for item in args.set:
+        name, cfg = item.split("=")
+        ctx.set_launch(name, *[int(v) for v in cfg.split(",")])
     b = runner.Bound(ctx, prog, read_bytes=4)
     for _ in range(args.runs):
         b.run()
@@ -43,7 +48,7 @@ def main():
         ctx.kernel("copy_f32", [(src, "c"), (dst, "m")], n=n)
     ctx.sync()
     ctx.close()
-    print(json.dumps({"workload": args.workload, "runs": args.runs, "copy_f32_bytes_read": 4 * n,
+    print(json.dumps({"workload": args.workload, "runs": args.runs, "set": args.set, "copy_f32_bytes_read": 4 * n,
                       "copy_f32_bytes_written": 4 * n, "copies": args.copies}), flush=True)
 
 

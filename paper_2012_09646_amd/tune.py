@@ -7,7 +7,10 @@ serial execution (Sec. V-A): for every kernel a workload uses, each candidate
 ``dag_tune_kernel`` on the workload's own buffers after one full run of the
 workload (so every input holds realistic data), summed over the kernel's
 occurrences, and the fastest is kept.  The DAG knobs (stream pool size, copy
-placement) are then chosen by the median makespan of whole runs.  Results are
+placement, hardware queue count) are then chosen by the median makespan of
+whole runs; each GPU_MAX_HW_QUEUES value is tried in a process of its own,
+since HIP fixes it at start-up (the orchestrating process never touches the
+GPU).  Results are
 stored as JSON keyed by GPU architecture, kernel and problem size, and loaded
 with ``apply``.
 
@@ -153,28 +156,86 @@ def workload_program(name):
     raise ValueError(name)
 
 
+def _worker(args, log):
+    """Runs inside one process (one GPU_MAX_HW_QUEUES setting)."""
+    names = ["vec", "bs", "img", "hits"] if args.workload == "all" else [args.workload]
+    out = {"kernels": {}, "dag": {}}
+    if args.worker == "kernels":
+        for name in names:
+            prog, _ = workload_program(name)
+            ctx = D.Context()
+            ks = tune_kernels(ctx, prog, args.reps, log)
+            ctx.close()
+            for k, e in ks.items():
+                prev = out["kernels"].get(k)
+                if prev is None or e["launches"] >= prev.get("launches", 0):
+                    out["kernels"][k] = e
+    else:
+        with open(args.kernels_json) as f:
+            kernels = json.load(f)["kernels"]
+        for name in names:
+            prog, restore = workload_program(name)
+            best, table = tune_dag(prog, kernels, restore=restore, log=log)
+            out["dag"][name] = dict(best, table=table)
+    with open(args.worker_out, "w") as f:
+        json.dump(out, f)
+
+
+def _spawn(extra, out, hw_queues=None):
+    """One worker process; the parent never touches the GPU (the hardware
+    queue count is fixed when HIP starts, so each setting needs a process)."""
+    import subprocess
+    import sys
+    env = dict(os.environ)
+    if hw_queues:
+        env["GPU_MAX_HW_QUEUES"] = str(hw_queues)
+    cmd = [sys.executable, "-m", "paper_2012_09646_amd.tune"] + extra + ["--worker-out", out]
+    subprocess.run(cmd, env=env, check=True)
+    with open(out) as f:
+        return json.load(f)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits"])
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", required=False)
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--dag", action="store_true", help="also tune pool size and copy placement")
+    ap.add_argument("--dag", action="store_true", help="also tune pool size, copy placement and hardware queues")
+    ap.add_argument("--hw-queues", default="4,8,16",
+                    help="GPU_MAX_HW_QUEUES values tried by --dag, one worker process each")
+    ap.add_argument("--worker", choices=["kernels", "dag"], help=argparse.SUPPRESS)
+    ap.add_argument("--worker-out", help=argparse.SUPPRESS)
+    ap.add_argument("--kernels-json", help=argparse.SUPPRESS)
     args = ap.parse_args()
     log = lambda *a: print("[tune]", *a, flush=True)
-    data = {"kernels": {}, "dag": {}}
-    names = ["vec", "bs", "img", "hits"] if args.workload == "all" else [args.workload]
-    for name in names:
-        prog, restore = workload_program(name)
-        ctx = D.Context()
-        ks = tune_kernels(ctx, prog, args.reps, log)
-        ctx.close()
-        for k, e in ks.items():
-            prev = data["kernels"].get(k)
-            if prev is None or e["launches"] >= prev.get("launches", 0):
-                data["kernels"][k] = e
-        if args.dag:
-            best, table = tune_dag(prog, data["kernels"], restore=restore, log=log)
-            data["dag"][name] = dict(best, table=table)
+    if args.worker:
+        _worker(args, log)
+        return
+    if not args.out:
+        ap.error("--out is required")
+    tmp = args.out + ".part"
+    common = ["--workload", args.workload, "--reps", str(args.reps)]
+    data = _spawn(common + ["--worker", "kernels"], tmp)
+    if args.dag:
+        kfile = args.out + ".kernels"
+        with open(kfile, "w") as f:
+            json.dump({"kernels": data["kernels"]}, f)
+        for hwq in [int(v) for v in args.hw_queues.split(",") if v]:
+            log("dag knobs with GPU_MAX_HW_QUEUES=%d" % hwq)
+            part = _spawn(common + ["--worker", "dag", "--kernels-json", kfile], tmp, hw_queues=hwq)
+            for name, e in part["dag"].items():
+                e = dict(e, hw_queues=hwq)
+                for row in e["table"]:
+                    row["hw_queues"] = hwq
+                prev = data["dag"].get(name)
+                if prev is None:
+                    data["dag"][name] = e
+                else:
+                    table = prev["table"] + e["table"]
+                    data["dag"][name] = dict(e if e["ms"] < prev["ms"] else prev, table=table)
+        os.remove(kfile)
+    if os.path.exists(tmp):
+        os.remove(tmp)
     save(args.out, data)
     log("wrote", args.out)
 

@@ -37,3 +37,30 @@ def test_tune_kernel_needs_a_gpu():
         D.dag_tune_kernel(ctx.h, 1, D.dag_p_n(1024), [(x, D.DAG_MUTABLE)], [(256, 0, 0)])
     assert e.value.name == "DAG_E_UNSUPPORTED"
     ctx.close()
+
+
+def test_hw_queue_sweep_merges_worker_results(tmp_path, monkeypatch):
+    """The orchestrator runs one worker per GPU_MAX_HW_QUEUES value and keeps,
+    per workload, the fastest configuration with its queue count."""
+    calls = []
+    times = {4: {"bs": 4.0, "img": 0.10}, 8: {"bs": 3.5, "img": 0.12}, 16: {"bs": 3.7, "img": 0.11}}
+
+    def fake_spawn(extra, out, hw_queues=None):
+        calls.append((extra[extra.index("--worker") + 1], hw_queues))
+        if "kernels" in extra:
+            return {"kernels": {"bs_call": {"block": 256, "grid_cap": 0, "variant": 1}}, "dag": {}}
+        dag = {w: {"max_streams": 2, "copy_streams": 0, "copy_lanes": 1, "ms": t,
+                   "table": [{"max_streams": 2, "ms": t}]} for w, t in times[hw_queues].items()}
+        return {"kernels": {}, "dag": dag}
+
+    monkeypatch.setattr(tune, "_spawn", fake_spawn)
+    out = str(tmp_path / "t.json")
+    monkeypatch.setattr("sys.argv", ["tune", "--out", out, "--dag", "--hw-queues", "4,8,16"])
+    tune.main()
+    data = tune.load(out)
+    assert calls == [("kernels", None), ("dag", 4), ("dag", 8), ("dag", 16)]
+    assert data["dag"]["bs"]["hw_queues"] == 8 and data["dag"]["bs"]["ms"] == 3.5
+    assert data["dag"]["img"]["hw_queues"] == 4
+    assert len(data["dag"]["bs"]["table"]) == 3
+    assert {r["hw_queues"] for r in data["dag"]["bs"]["table"]} == {4, 8, 16}
+    assert data["kernels"]["bs_call"]["variant"] == 1
