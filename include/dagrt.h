@@ -281,7 +281,10 @@ dag_status dag_kernel_set_launch(dag_ctx ctx, uint32_t kernel_id, const dag_laun
  * time per launch in microseconds (-1 for a candidate the kernel rejects).
  * This is a host synchronisation point: it first waits for and retires all
  * tasks.  The launches overwrite the kernel's outputs, so pass scratch
- * buffers (or data that may be clobbered).  Not available in dry-run mode. */
+ * buffers (or data that may be clobbered).  The merge-path SpMV is timed as
+ * dag_submit_kernel runs it: with the tile partition kept with its row-pointer
+ * buffer (built by two untimed warm-up launches per candidate).  Not
+ * available in dry-run mode. */
 dag_status dag_tune_kernel(dag_ctx ctx, uint32_t kernel_id, const void* params, size_t params_bytes,
                            const dag_arg* args, uint32_t nargs, const dag_launch* candidates,
                            uint32_t ncand, uint32_t reps, uint32_t* best, double* us);

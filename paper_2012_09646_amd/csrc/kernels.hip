@@ -318,19 +318,37 @@ struct GaussW {
   double w[31];
 };
 
+// Tile of this workgroup (1-D grid).  xcd_map = 0: tile = block id, row-major.
+// xcd_map = 1: the dispatcher hands workgroups to the 8 XCDs round-robin by
+// id, so block b runs on XCD b % 8; giving each XCD one contiguous run of
+// row-major tiles keeps a tile and its left, right, upper and lower
+// neighbours, whose halos overlap it, on one XCD and so in one L2.  Returns
+// false for the padding blocks of the last run (uniform per workgroup).
+__device__ __forceinline__ bool tile_of(int tiles_x, int ntiles, int xcd_map, int* x0, int* y0) {
+  int t = blockIdx.x;
+  if (xcd_map) {
+    const int per = (ntiles + 7) / 8;
+    t = static_cast<int>(blockIdx.x % 8) * per + static_cast<int>(blockIdx.x / 8);
+    if (t >= ntiles) return false;
+  }
+  *x0 = (t % tiles_x) * kTW;
+  *y0 = (t / tiles_x) * kTH;
+  return true;
+}
+
 // Separable Gaussian: stage the input tile with its halo in LDS (fp32, as
 // stored), horizontal pass into an fp64 LDS tile, vertical pass to output.
 template <int R>
 __global__ __launch_bounds__(256) void k_gauss_blur(const float* __restrict__ in,
                                                     float* __restrict__ out, int w, int h,
-                                                    GaussW wt) {
+                                                    GaussW wt, int tiles_x, int ntiles, int xcd_map) {
   constexpr int K = 2 * R + 1;
   constexpr int IW = kTW + 2 * R;
   constexpr int IH = kTH + 2 * R;
   __shared__ float s_in[IH][IW];
   __shared__ double s_h[IH][kTW];
-  const int x0 = blockIdx.x * kTW;
-  const int y0 = blockIdx.y * kTH;
+  int x0, y0;
+  if (!tile_of(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
   for (int i = threadIdx.x; i < IH * IW; i += 256) {
     const int r = i / IW, c = i - r * IW;
     const int gy = min(max(y0 - R + r, 0), h - 1);
@@ -375,11 +393,12 @@ __global__ __launch_bounds__(256) void k_gauss_blur(const float* __restrict__ in
 // Sobel gradient magnitude sqrt(gx^2 + gy^2), gx with [[-1,0,1],[-2,0,2],
 // [-1,0,1]] (correlation), gy with its transpose.
 __global__ __launch_bounds__(256) void k_sobel(const float* __restrict__ in,
-                                               float* __restrict__ out, int w, int h) {
+                                               float* __restrict__ out, int w, int h, int tiles_x,
+                                               int ntiles, int xcd_map) {
   constexpr int IW = kTW + 2, IH = kTH + 2;
   __shared__ float s_in[IH][IW];
-  const int x0 = blockIdx.x * kTW;
-  const int y0 = blockIdx.y * kTH;
+  int x0, y0;
+  if (!tile_of(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
   for (int i = threadIdx.x; i < IH * IW; i += 256) {
     const int r = i / IW, c = i - r * IW;
     const int gy = min(max(y0 - 1 + r, 0), h - 1);
@@ -880,7 +899,8 @@ const char* cfg_reduce(const LaunchCfg& c) {
 }
 const char* cfg_tile256(const LaunchCfg& c) {
   if (c.block != 256) return "this kernel runs 256-thread workgroups";
-  if (c.grid_cap != 0 || c.variant != 0) return "grid_cap and variant must be 0";
+  if (c.grid_cap != 0) return "grid_cap must be 0";
+  if (c.variant > 1) return "variant: 0 = row-major tiles, 1 = one contiguous run of tiles per XCD";
   return nullptr;
 }
 const char* cfg_spmv(const LaunchCfg& c) {
@@ -1002,13 +1022,15 @@ const char* v_blur(const void* p, const size_t* sz, uint32_t na, const LaunchCfg
 }
 
 template <int R>
-void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt) {
-  DAGRT_LAUNCH(k_gauss_blur<R>, dim3(ceil_div(w, kTW), ceil_div(h, kTH)), dim3(256), 0, s, in, out, w,
-                     h, wt);
+void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt, int xcd_map) {
+  const int tx = static_cast<int>(ceil_div(w, kTW)), nt = tx * static_cast<int>(ceil_div(h, kTH));
+  const int grid = xcd_map ? 8 * ((nt + 7) / 8) : nt;
+  DAGRT_LAUNCH(k_gauss_blur<R>, dim3(grid), dim3(256), 0, s, in, out, w, h, wt, tx, nt, xcd_map);
 }
 
-hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg&, void*, size_t) {
+hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const auto* q = static_cast<const dag_p_img*>(p);
+  const int xm = static_cast<int>(c.variant);
   const int k = static_cast<int>(q->ksize), rad = (k - 1) / 2;
   const double sigma = k / 6.0;
   GaussW wt{};
@@ -1022,31 +1044,33 @@ hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   auto* out = static_cast<float*>(a[1]);
   const int w = static_cast<int>(q->w), h = static_cast<int>(q->h);
   switch (rad) {
-    case 0: launch_blur_r<0>(s, in, out, w, h, wt); break;
-    case 1: launch_blur_r<1>(s, in, out, w, h, wt); break;
-    case 2: launch_blur_r<2>(s, in, out, w, h, wt); break;
-    case 3: launch_blur_r<3>(s, in, out, w, h, wt); break;
-    case 4: launch_blur_r<4>(s, in, out, w, h, wt); break;
-    case 5: launch_blur_r<5>(s, in, out, w, h, wt); break;
-    case 6: launch_blur_r<6>(s, in, out, w, h, wt); break;
-    case 7: launch_blur_r<7>(s, in, out, w, h, wt); break;
-    case 8: launch_blur_r<8>(s, in, out, w, h, wt); break;
-    case 9: launch_blur_r<9>(s, in, out, w, h, wt); break;
-    case 10: launch_blur_r<10>(s, in, out, w, h, wt); break;
-    case 11: launch_blur_r<11>(s, in, out, w, h, wt); break;
-    case 12: launch_blur_r<12>(s, in, out, w, h, wt); break;
-    case 13: launch_blur_r<13>(s, in, out, w, h, wt); break;
-    case 14: launch_blur_r<14>(s, in, out, w, h, wt); break;
-    default: launch_blur_r<15>(s, in, out, w, h, wt); break;
+    case 0: launch_blur_r<0>(s, in, out, w, h, wt, xm); break;
+    case 1: launch_blur_r<1>(s, in, out, w, h, wt, xm); break;
+    case 2: launch_blur_r<2>(s, in, out, w, h, wt, xm); break;
+    case 3: launch_blur_r<3>(s, in, out, w, h, wt, xm); break;
+    case 4: launch_blur_r<4>(s, in, out, w, h, wt, xm); break;
+    case 5: launch_blur_r<5>(s, in, out, w, h, wt, xm); break;
+    case 6: launch_blur_r<6>(s, in, out, w, h, wt, xm); break;
+    case 7: launch_blur_r<7>(s, in, out, w, h, wt, xm); break;
+    case 8: launch_blur_r<8>(s, in, out, w, h, wt, xm); break;
+    case 9: launch_blur_r<9>(s, in, out, w, h, wt, xm); break;
+    case 10: launch_blur_r<10>(s, in, out, w, h, wt, xm); break;
+    case 11: launch_blur_r<11>(s, in, out, w, h, wt, xm); break;
+    case 12: launch_blur_r<12>(s, in, out, w, h, wt, xm); break;
+    case 13: launch_blur_r<13>(s, in, out, w, h, wt, xm); break;
+    case 14: launch_blur_r<14>(s, in, out, w, h, wt, xm); break;
+    default: launch_blur_r<15>(s, in, out, w, h, wt, xm); break;
   }
   return hipGetLastError();
 }
 
-hipError_t l_sobel(hipStream_t s, void* const* a, const void* p, const LaunchCfg&, void*, size_t) {
+hipError_t l_sobel(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const auto* q = static_cast<const dag_p_img*>(p);
-  DAGRT_LAUNCH(k_sobel, dim3(ceil_div(q->w, kTW), ceil_div(q->h, kTH)), dim3(256), 0, s,
-                     static_cast<const float*>(a[0]), static_cast<float*>(a[1]), static_cast<int>(q->w),
-                     static_cast<int>(q->h));
+  const int tx = static_cast<int>(ceil_div(q->w, kTW)), nt = tx * static_cast<int>(ceil_div(q->h, kTH));
+  const int xm = static_cast<int>(c.variant);
+  const int grid = xm ? 8 * ((nt + 7) / 8) : nt;
+  DAGRT_LAUNCH(k_sobel, dim3(grid), dim3(256), 0, s, static_cast<const float*>(a[0]), static_cast<float*>(a[1]),
+               static_cast<int>(q->w), static_cast<int>(q->h), tx, nt, xm);
   return hipGetLastError();
 }
 
@@ -1301,8 +1325,8 @@ const KernelDesc kTable[] = {
     /* 1 */ {"vec_square", 1, 0x1, sizeof(dag_p_n), {256, 0, 0}, v_vec_square, l_vec_square, cfg_block_any},
     /* 2 */ {"vec_sum_diff", 3, 0x4, sizeof(dag_p_n), {256, 1024, 0}, v_vec_sum_diff, l_vec_sum_diff, cfg_reduce},
     /* 3 */ {"bs_call", 2, 0x2, sizeof(dag_p_bs), {256, 0, 0}, v_bs, l_bs, cfg_bs},
-    /* 4 */ {"gauss_blur", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_blur, l_blur, cfg_tile256},
-    /* 5 */ {"sobel", 2, 0x2, sizeof(dag_p_img), {256, 0, 0}, v_img2, l_sobel, cfg_tile256},
+    /* 4 */ {"gauss_blur", 2, 0x2, sizeof(dag_p_img), {256, 0, 1}, v_blur, l_blur, cfg_tile256},
+    /* 5 */ {"sobel", 2, 0x2, sizeof(dag_p_img), {256, 0, 1}, v_img2, l_sobel, cfg_tile256},
     /* 6 */ {"minmax", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_minmax, l_minmax, cfg_reduce},
     /* 7 */ {"normalise", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_normalise, l_normalise, cfg_block_any},
     /* 8 */ {"unsharp_combine", 8, 0x80, sizeof(dag_p_n), {256, 0, 0}, v_combine, l_combine, cfg_block_any},

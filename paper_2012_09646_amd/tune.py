@@ -44,7 +44,9 @@ def candidates(kernel):
         return [(256, 0, v) for v in (4, 8, 12, 16)]
     if kernel == "spmv_rows":
         return [(256, c, v) for v in (4, 8, 16, 32) for c in (0, 2048, 8192)]
-    return []  # fixed-tile kernels (blur, Sobel) and the delay kernel
+    if kernel in ("gauss_blur", "sobel"):
+        return [(256, 0, v) for v in (0, 1)]  # tile order: row-major or one run per XCD
+    return []  # the delay kernel
 
 
 def size_key(op):

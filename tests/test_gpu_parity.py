@@ -66,6 +66,27 @@ def test_img(w, h):
     G.check_program(W.img_program(side=w, height=h, seed=2))
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("w,h", [(1, 1), (70, 19), (333, 130), (2048, 2048), (2000, 1000)])
+def test_img_tile_orders(w, h, variant):
+    """Blur and Sobel with row-major tiles (0) and with one contiguous run of
+    tiles per XCD (1): tile counts below 8, not a multiple of 8, full image."""
+    banner("img tile order %d %dx%d" % (variant, w, h))
+    from paper_2012_09646_amd import runner
+    prog = W.img_program(side=w, height=h, seed=21)
+    ref = G.oracle_run(prog)
+    ctx = D.Context()
+    try:
+        ctx.set_launch("gauss_blur", 256, 0, variant)
+        ctx.set_launch("sobel", 256, 0, variant)
+        b = runner.Bound(ctx, prog)
+        b.run()
+        for name in prog.outputs:
+            G.assert_close(prog, name, b.read(name), ref[name])
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("n,deg,iters", [(64, 4, 3), (3000, 20, 10), (1 << 20, 20, 10)])
 def test_hits(n, deg, iters):
     banner("hits n=%d deg=%d iters=%d" % (n, deg, iters))
