@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "serve"])
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
     ap.add_argument("--serve-lanes", type=int, default=8, help="serving: HIP streams requests spread over")
+    ap.add_argument("--serve-copy-lanes", type=int, default=1, choices=[0, 1],
+                    help="serving: 1 = host<->device copies of all requests on one stream per direction")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
     ap.add_argument("--low-rate", type=float, default=600.0,
                     help="serving: a second, lower arrival rate (half the requests; 0 = skip)")
@@ -328,7 +330,8 @@ def main():
                 tmpls.append(serving.ShapeTemplate(ctx, prog, key=key, result_bytes=64))
                 key += 1
         budget = 64 << 30
-        srv = serving.Server(ctx, budget, host_arena_bytes=8 << 30, lanes=args.serve_lanes, bypass=32)
+        srv = serving.Server(ctx, budget, host_arena_bytes=8 << 30, lanes=args.serve_lanes, bypass=32,
+                             copy_lanes=args.serve_copy_lanes)
         foot = []
         for t in tmpls:
             sid = srv.add(t)
@@ -351,7 +354,8 @@ def main():
             }
 
         out = one_rate(args.rate, args.requests)
-        out.update({"shapes": len(tmpls), "budget_bytes": budget, "lanes": args.serve_lanes})
+        out.update({"shapes": len(tmpls), "budget_bytes": budget, "lanes": args.serve_lanes,
+                    "copy_lanes": args.serve_copy_lanes})
         # a second, lower arrival rate at which the serial baseline is not overloaded
         if args.low_rate:
             out["low_rate"] = one_rate(args.low_rate, max(1, args.requests // 2))

@@ -61,7 +61,8 @@ struct RegionTask {
   hipMemcpyKind ckind = hipMemcpyDefault;
   uint64_t id = 0;         // task id of the eager run
   int32_t rstream = 0;     // region-local stream
-  std::vector<uint32_t> rwaits;  // region-local task indices waited on
+  std::vector<uint32_t> rwaits;    // region-local task indices waited on
+  std::vector<uint32_t> rparents;  // every intra-region parent (region-local indices)
   bool waited_on = false;
 };
 

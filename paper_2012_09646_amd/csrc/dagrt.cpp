@@ -499,6 +499,7 @@ void plan_region(dag_ctx c, Region* r) {
       auto pi = index.find(par[i]);
       if (pi == index.end()) continue;
       const uint32_t p = pi->second;
+      t.rparents.push_back(p);
       if (r->tasks[p].rstream == t.rstream) continue;
       bool rep = false;
       for (uint32_t& q : cand)

@@ -87,10 +87,21 @@ struct ShapeTask {
   PtrRef cdst, csrc;         // copy ends
 };
 
+// Where a request's call runs when copies have lanes of their own.
+enum : uint8_t { kOnLane = 0, kOnH2D = 1, kOnD2H = 2 };
+
 struct Shape {
   Region* region;
   std::vector<ShapeBuf> bufs;
   std::vector<ShapeTask> tasks;
+  // copy-lane plan: per call its stream class, the calls it waits for on
+  // other streams (newest recorded parent per stream), whether a later call
+  // or the request's final join waits for it, and the last call per class
+  std::vector<uint8_t> cls;
+  std::vector<std::vector<uint32_t>> waits;
+  std::vector<uint8_t> needs_ev;
+  int32_t last_of[3] = {-1, -1, -1};
+  bool has_init = false;
   int32_t result_buf;
   size_t result_bytes;
   uint64_t dev_bytes = 0, host_bytes = 0;  // per-request block sizes
@@ -104,6 +115,7 @@ struct Flight {
   hipEvent_t ev;
   uint64_t dev_off, host_off;
   uint64_t sim_done;  // schedule-only contexts
+  std::vector<hipEvent_t> evs;  // copy-lane mode: events of the request's calls
 };
 
 }  // namespace
@@ -120,6 +132,7 @@ struct dag_server_s {
   std::vector<Shape> shapes;
   std::vector<hipStream_t> lanes;
   std::vector<void*> lane_scratch;
+  hipStream_t copy_st[3] = {nullptr, nullptr, nullptr};  // [kOnH2D], [kOnD2H]
   std::vector<hipEvent_t> free_ev;
 };
 
@@ -150,9 +163,25 @@ hipMemcpyKind kind_of(uint32_t dst_loc, uint32_t src_loc) {
   return dst_loc == DAG_PINNED_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
 }
 
-// Enqueue one request on lane stream `st`; serial = wait after every call.
+hipError_t launch_task(dag_server s, const Shape& sh, const ShapeTask& t, uint64_t dev_off, uint64_t host_off,
+                       hipStream_t st, void* scratch) {
+  if (t.t->kind == TK_COPY)
+    return hipMemcpyAsync(resolve(s, sh, t.cdst, dev_off, host_off), resolve(s, sh, t.csrc, dev_off, host_off),
+                          t.t->cbytes, t.t->ckind, st);
+  void* ptrs[kMaxArgs];
+  for (size_t i = 0; i < t.refs.size(); ++i) ptrs[i] = resolve(s, sh, t.refs[i], dev_off, host_off);
+  const KernelDesc* kd = builtin_kernel(t.t->kernel_id);
+  return kd->launch(st, ptrs, t.t->params.data(), t.t->cfg, scratch, s->ctx->cfg.scratch_bytes);
+}
+
+// Enqueue one request: its INIT copies and kernels on lane stream `st`, its
+// host<->device copies on the server's copy streams when those exist (not in
+// serial mode), with event waits for the request's own recorded
+// dependencies; the lane then joins the copy streams, so an event recorded on
+// the lane afterwards marks the whole request.  serial = wait after every
+// call.  Events used are appended to *evs (recycled when the request retires).
 dag_status launch_request(dag_server s, const Shape& sh, uint64_t dev_off, uint64_t host_off, hipStream_t st,
-                          void* scratch, bool serial) {
+                          void* scratch, bool serial, std::vector<hipEvent_t>* evs) {
   dag_ctx c = s->ctx;
   for (const ShapeBuf& b : sh.bufs) {
     if (b.role != DAG_ROLE_INIT) continue;
@@ -161,19 +190,42 @@ dag_status launch_request(dag_server s, const Shape& sh, uint64_t dev_off, uint6
     HIP_TRY(c, hipMemcpyAsync(dst, b.init_src, b.bytes, kind_of(b.loc, b.init_loc), st));
     if (serial) HIP_TRY(c, hipStreamSynchronize(st));
   }
-  void* ptrs[kMaxArgs];
-  for (const ShapeTask& t : sh.tasks) {
-    hipError_t e;
-    if (t.t->kind == TK_COPY) {
-      e = hipMemcpyAsync(resolve(s, sh, t.cdst, dev_off, host_off), resolve(s, sh, t.csrc, dev_off, host_off),
-                         t.t->cbytes, t.t->ckind, st);
-    } else {
-      for (size_t i = 0; i < t.refs.size(); ++i) ptrs[i] = resolve(s, sh, t.refs[i], dev_off, host_off);
-      const KernelDesc* kd = builtin_kernel(t.t->kernel_id);
-      e = kd->launch(st, ptrs, t.t->params.data(), t.t->cfg, scratch, c->cfg.scratch_bytes);
+  const bool split = !serial && s->copy_st[kOnH2D] != nullptr;
+  if (!split) {
+    for (const ShapeTask& t : sh.tasks) {
+      hipError_t e = launch_task(s, sh, t, dev_off, host_off, st, scratch);
+      if (e != hipSuccess) return hip_fail(c, e, "serving launch");
+      if (serial) HIP_TRY(c, hipStreamSynchronize(st));
     }
-    if (e != hipSuccess) return hip_fail(c, e, "serving launch");
-    if (serial) HIP_TRY(c, hipStreamSynchronize(st));
+  } else {
+    hipEvent_t init_ev = nullptr;
+    if (sh.has_init) {
+      dag_status e = ev_get(s, &init_ev);
+      if (e) return e;
+      evs->push_back(init_ev);
+      HIP_TRY(c, hipEventRecord(init_ev, st));
+    }
+    bool init_seen[3] = {true, false, false};
+    std::vector<hipEvent_t> tev(sh.tasks.size(), nullptr);
+    for (size_t k = 0; k < sh.tasks.size(); ++k) {
+      const uint8_t cl = sh.cls[k];
+      hipStream_t ts = cl == kOnLane ? st : s->copy_st[cl];
+      if (init_ev && !init_seen[cl]) {
+        HIP_TRY(c, hipStreamWaitEvent(ts, init_ev, 0));
+        init_seen[cl] = true;
+      }
+      for (uint32_t w : sh.waits[k]) HIP_TRY(c, hipStreamWaitEvent(ts, tev[w], 0));
+      hipError_t e = launch_task(s, sh, sh.tasks[k], dev_off, host_off, ts, scratch);
+      if (e != hipSuccess) return hip_fail(c, e, "serving launch");
+      if (sh.needs_ev[k]) {
+        dag_status es = ev_get(s, &tev[k]);
+        if (es) return es;
+        evs->push_back(tev[k]);
+        HIP_TRY(c, hipEventRecord(tev[k], ts));
+      }
+    }
+    for (int cl = kOnH2D; cl <= kOnD2H; ++cl)
+      if (sh.last_of[cl] >= 0) HIP_TRY(c, hipStreamWaitEvent(st, tev[sh.last_of[cl]], 0));
   }
   if (sh.result_buf >= 0 && sh.result_bytes && sh.bufs[sh.result_buf].loc == DAG_DEVICE) {
     PtrRef r{sh.result_buf, 0, nullptr};
@@ -183,6 +235,32 @@ dag_status launch_request(dag_server s, const Shape& sh, uint64_t dev_off, uint6
     if (serial) HIP_TRY(c, hipStreamSynchronize(st));
   }
   return DAG_OK;
+}
+
+// The copy-lane plan of a shape (see Shape).
+void plan_copy_lanes(Shape* sh) {
+  const size_t n = sh->tasks.size();
+  sh->cls.assign(n, kOnLane);
+  sh->waits.assign(n, {});
+  sh->needs_ev.assign(n, 0);
+  for (size_t k = 0; k < n; ++k) {
+    const RegionTask& t = *sh->tasks[k].t;
+    if (t.kind == TK_COPY && t.ckind == hipMemcpyHostToDevice) sh->cls[k] = kOnH2D;
+    if (t.kind == TK_COPY && t.ckind == hipMemcpyDeviceToHost) sh->cls[k] = kOnD2H;
+    int32_t newest[3] = {-1, -1, -1};
+    for (uint32_t p : t.rparents)
+      if (sh->cls[p] != sh->cls[k]) newest[sh->cls[p]] = std::max<int32_t>(newest[sh->cls[p]], static_cast<int32_t>(p));
+    for (int cl = 0; cl < 3; ++cl) {
+      if (newest[cl] < 0) continue;
+      sh->waits[k].push_back(static_cast<uint32_t>(newest[cl]));
+      sh->needs_ev[newest[cl]] = 1;
+    }
+    sh->last_of[sh->cls[k]] = static_cast<int32_t>(k);
+  }
+  for (int cl = kOnH2D; cl <= kOnD2H; ++cl)
+    if (sh->last_of[cl] >= 0) sh->needs_ev[sh->last_of[cl]] = 1;
+  for (const ShapeBuf& b : sh->bufs)
+    if (b.role == DAG_ROLE_INIT) sh->has_init = true;
 }
 
 void copy_result(const dag_server_s* s, const Shape& sh, uint64_t dev_off, uint64_t host_off, void* out) {
@@ -206,6 +284,7 @@ dag_status dag_serve_create(dag_ctx c, const dag_serve_config* cfg, dag_server* 
   CHECK_CTX(c);
   if (!cfg || !out) return fail(c, DAG_E_INVAL, "cfg and out are required");
   if (cfg->lanes == 0 || cfg->lanes > DAG_MAX_STREAMS) return fail(c, DAG_E_INVAL, "lanes must be 1..64");
+  if (cfg->copy_lanes > 1 || cfg->reserved) return fail(c, DAG_E_INVAL, "copy_lanes must be 0 or 1, reserved 0");
   if (cfg->budget_bytes == 0 || cfg->budget_bytes > cfg->device_arena_bytes)
     return fail(c, DAG_E_INVAL, "budget must be in (0, device_arena_bytes]");
   auto* s = new (std::nothrow) dag_server_s();
@@ -218,6 +297,8 @@ dag_status dag_serve_create(dag_ctx c, const dag_serve_config* cfg, dag_server* 
     hipError_t e = hipMalloc(&s->dev_base, cfg->device_arena_bytes);
     if (e == hipSuccess && cfg->host_arena_bytes)
       e = hipHostMalloc(&s->host_base, cfg->host_arena_bytes, hipHostMallocDefault);
+    for (int cl = kOnH2D; e == hipSuccess && cfg->copy_lanes && cl <= kOnD2H; ++cl)
+      e = new_stream(c, &s->copy_st[cl]);
     for (uint32_t i = 0; e == hipSuccess && i < cfg->lanes; ++i) {
       hipStream_t st;
       void* scr = nullptr;
@@ -247,7 +328,11 @@ dag_status dag_serve_destroy(dag_server s) {
   if (!s->ctx->dry) {
     for (hipStream_t st : s->lanes)
       if (st) (void)hipStreamSynchronize(st);
+    for (hipStream_t st : s->copy_st)
+      if (st) (void)hipStreamSynchronize(st);
     for (hipStream_t st : s->lanes)
+      if (st) (void)hipStreamDestroy(st);
+    for (hipStream_t st : s->copy_st)
       if (st) (void)hipStreamDestroy(st);
     for (void* p : s->lane_scratch)
       if (p) (void)hipFree(p);
@@ -327,6 +412,7 @@ dag_status dag_serve_add_shape(dag_server s, uint64_t key, const dag_shape_buf* 
     }
     sh.tasks.push_back(std::move(st));
   }
+  plan_copy_lanes(&sh);
   if (sh.dev_bytes > s->cfg.budget_bytes) return fail(c, DAG_E_RANGE, "shape needs more than the budget");
   if (sh.host_bytes > s->cfg.host_arena_bytes) return fail(c, DAG_E_RANGE, "shape needs more than the host arena");
   s->shapes.push_back(std::move(sh));
@@ -377,6 +463,7 @@ dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint
     if (sh.host_bytes) s->host.release(f.host_off, sh.host_bytes);
     used -= sh.dev_bytes;
     if (f.ev) s->free_ev.push_back(f.ev);
+    for (hipEvent_t e : f.evs) s->free_ev.push_back(e);
     --inflight;
     ++ndone;
   };
@@ -432,13 +519,13 @@ dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint
         const uint64_t start = std::max(now, lane_free[lane]);
         lane_free[lane] = f.sim_done = start + sh.sim_ns;
       } else {
-        dag_status st = launch_request(s, sh, doff, hoff, s->lanes[lane], s->lane_scratch[lane], serial);
+        dag_status st = launch_request(s, sh, doff, hoff, s->lanes[lane], s->lane_scratch[lane], serial, &f.evs);
         if (st) return st;
         st = ev_get(s, &f.ev);
         if (st) return st;
         HIP_TRY(c, hipEventRecord(f.ev, s->lanes[lane]));
       }
-      flights[lane].push_back(f);
+      flights[lane].push_back(std::move(f));
       used += sh.dev_bytes;
       peak = std::max(peak, used);
       ++inflight;

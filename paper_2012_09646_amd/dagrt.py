@@ -109,7 +109,8 @@ class dag_shape_buf(C.Structure):
 
 class dag_serve_config(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("device_arena_bytes", C.c_uint64),
-                ("host_arena_bytes", C.c_uint64), ("lanes", C.c_uint32), ("bypass", C.c_uint32)]
+                ("host_arena_bytes", C.c_uint64), ("lanes", C.c_uint32), ("bypass", C.c_uint32),
+                ("copy_lanes", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class dag_request(C.Structure):

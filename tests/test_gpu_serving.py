@@ -26,9 +26,9 @@ def expected(prog, tmpl):
     return ref[tmpl.result][:tmpl.result_bytes]
 
 
-@pytest.mark.parametrize("budget_mult,lanes", [(100, 4), (2, 8)])
-def test_alone_vs_mix_and_oracle(budget_mult, lanes):
-    print("[gpu] serving budget x%d lanes %d" % (budget_mult, lanes), flush=True)
+@pytest.mark.parametrize("budget_mult,lanes,copy_lanes", [(100, 4, 1), (2, 8, 1), (100, 4, 0)])
+def test_alone_vs_mix_and_oracle(budget_mult, lanes, copy_lanes):
+    print("[gpu] serving budget x%d lanes %d copy lanes %d" % (budget_mult, lanes, copy_lanes), flush=True)
     ctx = D.Context()
     progs = shapes()
     tmpls = [serving.ShapeTemplate(ctx, p, key=100 + i) for i, p in enumerate(progs)]
@@ -38,7 +38,7 @@ def test_alone_vs_mix_and_oracle(budget_mult, lanes):
     biggest = max(probe.footprint(i)[0] for i in range(len(tmpls)))
     probe.close()
     srv = serving.Server(ctx, budget_mult * biggest, device_arena_bytes=budget_mult * biggest + (1 << 20),
-                         host_arena_bytes=1 << 28, lanes=lanes)
+                         host_arena_bytes=1 << 28, lanes=lanes, copy_lanes=copy_lanes)
     for t in tmpls:
         srv.add(t)
     arr, shp = W.poisson_trace(31, 150, 20_000, len(tmpls))
