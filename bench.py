@@ -54,8 +54,8 @@ def parse():
     ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "serve"])
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
     ap.add_argument("--serve-lanes", type=int, default=8, help="serving: HIP streams requests spread over")
-    ap.add_argument("--serve-copy-lanes", type=int, default=1, choices=[0, 1],
-                    help="serving: 1 = host<->device copies of all requests on one stream per direction")
+    ap.add_argument("--serve-copy-lanes", type=int, default=1, choices=[0, 1, 2, 3, 4],
+                    help="serving: N = host<->device copies of all requests on N streams per direction")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
     ap.add_argument("--low-rate", type=float, default=600.0,
                     help="serving: a second, lower arrival rate (half the requests; 0 = skip)")

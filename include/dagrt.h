@@ -419,11 +419,12 @@ typedef struct {
   uint64_t host_arena_bytes;   /* pinned host memory the server allocates */
   uint32_t lanes;              /* HIP streams requests are spread over */
   uint32_t bypass;             /* queued requests examined per pass (>= 1) */
-  uint32_t copy_lanes;         /* concurrent mode: 1 = the host<->device
-                                  copies of all requests run on one FIFO
-                                  stream per direction (kernels stay on the
-                                  request's lane, with event waits on the
-                                  request's own recorded dependencies);
+  uint32_t copy_lanes;         /* concurrent mode, 0..4: N >= 1 = the
+                                  host<->device copies of all requests run on
+                                  N FIFO streams per direction, request i
+                                  using stream i mod N of each (kernels stay
+                                  on the request's lane, with event waits on
+                                  the request's own recorded dependencies);
                                   0 = a request runs wholly on its lane */
   uint32_t reserved;
 } dag_serve_config;

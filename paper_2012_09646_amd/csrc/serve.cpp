@@ -132,7 +132,8 @@ struct dag_server_s {
   std::vector<Shape> shapes;
   std::vector<hipStream_t> lanes;
   std::vector<void*> lane_scratch;
-  hipStream_t copy_st[3] = {nullptr, nullptr, nullptr};  // [kOnH2D], [kOnD2H]
+  std::vector<hipStream_t> copy_st[3];  // [kOnH2D], [kOnD2H]: copy lanes per direction
+  uint64_t launched = 0;                // requests launched (rotates the copy lanes)
   std::vector<hipEvent_t> free_ev;
 };
 
@@ -190,7 +191,9 @@ dag_status launch_request(dag_server s, const Shape& sh, uint64_t dev_off, uint6
     HIP_TRY(c, hipMemcpyAsync(dst, b.init_src, b.bytes, kind_of(b.loc, b.init_loc), st));
     if (serial) HIP_TRY(c, hipStreamSynchronize(st));
   }
-  const bool split = !serial && s->copy_st[kOnH2D] != nullptr;
+  const bool split = !serial && !s->copy_st[kOnH2D].empty();
+  const size_t cl_ix = split ? s->launched % s->copy_st[kOnH2D].size() : 0;
+  ++s->launched;
   if (!split) {
     for (const ShapeTask& t : sh.tasks) {
       hipError_t e = launch_task(s, sh, t, dev_off, host_off, st, scratch);
@@ -209,7 +212,7 @@ dag_status launch_request(dag_server s, const Shape& sh, uint64_t dev_off, uint6
     std::vector<hipEvent_t> tev(sh.tasks.size(), nullptr);
     for (size_t k = 0; k < sh.tasks.size(); ++k) {
       const uint8_t cl = sh.cls[k];
-      hipStream_t ts = cl == kOnLane ? st : s->copy_st[cl];
+      hipStream_t ts = cl == kOnLane ? st : s->copy_st[cl][cl_ix];
       if (init_ev && !init_seen[cl]) {
         HIP_TRY(c, hipStreamWaitEvent(ts, init_ev, 0));
         init_seen[cl] = true;
@@ -284,7 +287,7 @@ dag_status dag_serve_create(dag_ctx c, const dag_serve_config* cfg, dag_server* 
   CHECK_CTX(c);
   if (!cfg || !out) return fail(c, DAG_E_INVAL, "cfg and out are required");
   if (cfg->lanes == 0 || cfg->lanes > DAG_MAX_STREAMS) return fail(c, DAG_E_INVAL, "lanes must be 1..64");
-  if (cfg->copy_lanes > 1 || cfg->reserved) return fail(c, DAG_E_INVAL, "copy_lanes must be 0 or 1, reserved 0");
+  if (cfg->copy_lanes > 4 || cfg->reserved) return fail(c, DAG_E_INVAL, "copy_lanes must be 0..4, reserved 0");
   if (cfg->budget_bytes == 0 || cfg->budget_bytes > cfg->device_arena_bytes)
     return fail(c, DAG_E_INVAL, "budget must be in (0, device_arena_bytes]");
   auto* s = new (std::nothrow) dag_server_s();
@@ -297,8 +300,12 @@ dag_status dag_serve_create(dag_ctx c, const dag_serve_config* cfg, dag_server* 
     hipError_t e = hipMalloc(&s->dev_base, cfg->device_arena_bytes);
     if (e == hipSuccess && cfg->host_arena_bytes)
       e = hipHostMalloc(&s->host_base, cfg->host_arena_bytes, hipHostMallocDefault);
-    for (int cl = kOnH2D; e == hipSuccess && cfg->copy_lanes && cl <= kOnD2H; ++cl)
-      e = new_stream(c, &s->copy_st[cl]);
+    for (int cl = kOnH2D; cl <= kOnD2H; ++cl)
+      for (uint32_t i = 0; e == hipSuccess && i < cfg->copy_lanes; ++i) {
+        hipStream_t cs;
+        e = new_stream(c, &cs);
+        if (e == hipSuccess) s->copy_st[cl].push_back(cs);
+      }
     for (uint32_t i = 0; e == hipSuccess && i < cfg->lanes; ++i) {
       hipStream_t st;
       void* scr = nullptr;
@@ -328,12 +335,12 @@ dag_status dag_serve_destroy(dag_server s) {
   if (!s->ctx->dry) {
     for (hipStream_t st : s->lanes)
       if (st) (void)hipStreamSynchronize(st);
-    for (hipStream_t st : s->copy_st)
-      if (st) (void)hipStreamSynchronize(st);
+    for (auto& v : s->copy_st)
+      for (hipStream_t st : v) (void)hipStreamSynchronize(st);
     for (hipStream_t st : s->lanes)
       if (st) (void)hipStreamDestroy(st);
-    for (hipStream_t st : s->copy_st)
-      if (st) (void)hipStreamDestroy(st);
+    for (auto& v : s->copy_st)
+      for (hipStream_t st : v) (void)hipStreamDestroy(st);
     for (void* p : s->lane_scratch)
       if (p) (void)hipFree(p);
     for (hipEvent_t e : s->free_ev) (void)hipEventDestroy(e);

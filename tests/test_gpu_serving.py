@@ -26,7 +26,7 @@ def expected(prog, tmpl):
     return ref[tmpl.result][:tmpl.result_bytes]
 
 
-@pytest.mark.parametrize("budget_mult,lanes,copy_lanes", [(100, 4, 1), (2, 8, 1), (100, 4, 0)])
+@pytest.mark.parametrize("budget_mult,lanes,copy_lanes", [(100, 4, 1), (2, 8, 2), (100, 4, 0)])
 def test_alone_vs_mix_and_oracle(budget_mult, lanes, copy_lanes):
     print("[gpu] serving budget x%d lanes %d copy lanes %d" % (budget_mult, lanes, copy_lanes), flush=True)
     ctx = D.Context()
