@@ -106,7 +106,13 @@ typedef struct {
   uint32_t trace;         /* 1 = timing events for every GPU task, 2 = for
                              kernels and region replays only; built-in
                              kernels are timed by events attached to their
-                             dispatch packets, other tasks by markers */
+                             dispatch packets, other tasks by markers.
+                             3 = markers around every GPU task, each task
+                             first held behind a 50 us delay kernel on a
+                             side stream so its start marker and its work
+                             are queued together (without it a marker on an
+                             idle stream also times the host's launch
+                             latency); meant for the serial policy */
   uint32_t dry_run;       /* 1 = schedule only: infer edges, streams and
                              waits, make no HIP call and touch no memory */
   int32_t device;         /* HIP device ordinal */

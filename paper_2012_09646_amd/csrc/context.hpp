@@ -116,6 +116,7 @@ struct dag_ctx_s {
   // failure injection (tests): the fault_at-th kernel launch reports an error
   // instead of launching; 0 = off
   uint64_t fault_at = 0, n_launches = 0;
+  hipEvent_t gate_ev = nullptr;  // trace mode 3
   // stats
   uint64_t n_waits = 0, n_host_waits = 0, n_plans = 0;
   double submit_us = 0.0, launch_us = 0.0;

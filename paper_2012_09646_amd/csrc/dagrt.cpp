@@ -96,11 +96,27 @@ void note_event_slot(dag_ctx c, uint64_t id) {
   }
 }
 
-// Trace mode 1 times every GPU task, mode 2 only kernels and region replays.
+// Trace modes 1 and 3 time every GPU task, mode 2 only kernels and region
+// replays.
 bool traced(dag_ctx c, uint64_t id) {
   if (c->cfg.trace == 0) return false;
-  if (c->cfg.trace == 1) return true;
+  if (c->cfg.trace != 2) return true;
   return c->tr.task(id).kind != TK_COPY;
+}
+
+// Trace mode 3: hold the task's stream behind a short delay kernel on the
+// side stream, so that the task's start marker and its work are both queued
+// before the GPU reaches them.  Otherwise, on an idle stream, the marker is
+// stamped at once and the host's launch latency counts as task time.
+constexpr uint64_t kGateNs = 50000;
+
+dag_status gate_stream(dag_ctx c, int32_t s) {
+  const KernelDesc* kd = builtin_kernel(DAG_K_SPIN);
+  const dag_p_spin sp{kGateNs};
+  HIP_TRY(c, kd->launch(c->io, nullptr, &sp, kd->def, nullptr, 0));
+  HIP_TRY(c, hipEventRecord(c->gate_ev, c->io));
+  HIP_TRY(c, hipStreamWaitEvent(c->streams[s], c->gate_ev, 0));
+  return DAG_OK;
 }
 
 // Enqueue the waits of task id on its stream and (trace) its start event.
@@ -115,6 +131,10 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
   }
   c->n_waits += t.wait_n;
   note_event_slot(c, id);
+  if (c->cfg.trace == 3) {
+    dag_status st = gate_stream(c, s);
+    if (st) return st;
+  }
   if (traced(c, id)) {
     hipEvent_t e0;
     dag_status st = get_event(c, true, &e0);
@@ -287,7 +307,7 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
   dag_status st = ensure_stream(c, s);
   if (st) return st;
   const auto t1 = Clock::now();
-  const bool dispatch_timed = kd && c->cfg.trace != 0;
+  const bool dispatch_timed = kd && (c->cfg.trace == 1 || c->cfg.trace == 2);
   st = begin_task(c, id, s, dispatch_timed);
   if (st) return st;
   if (c->fault_at && ++c->n_launches == c->fault_at) {
@@ -561,6 +581,16 @@ dag_status build_graph(dag_ctx c, Region* r) {
     HIP_TRY(c, hipEventRecord(forks[i], c->aux[i]));
     HIP_TRY(c, hipStreamWaitEvent(s0, forks[i], 0));
   }
+  // One sink node that depends on every branch (a zero-length delay kernel):
+  // graphs with several leaf nodes were seen to signal completion on the
+  // launch stream before all branches had finished (a host read then saw a
+  // device-to-host copy's destination unwritten).
+  if (r->nstreams > 1) {
+    const KernelDesc* spin = builtin_kernel(DAG_K_SPIN);
+    const dag_p_spin zero{0};
+    hipError_t e = spin->launch(s0, nullptr, &zero, spin->def, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(c, e, "region capture sink");
+  }
   HIP_TRY(c, hipStreamEndCapture(s0, &r->graph));
   HIP_TRY(c, hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0));
   for (hipEvent_t e : evs)
@@ -647,7 +677,7 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
   if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1 ||
-      c.trace > 2 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1)
+      c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1)
     return DAG_E_INVAL;
   // One hardware queue per stream (CU-masked streams) hung in testing with no
   // cause found in this library, so the mode is refused.
@@ -677,6 +707,7 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
     int khz = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device);
     if (e == hipSuccess) set_wall_clock_khz(static_cast<uint64_t>(khz));
+    if (e == hipSuccess && c.trace == 3) e = hipEventCreateWithFlags(&x->gate_ev, hipEventDisableTiming);
     if (e == hipSuccess && c.trace) {
       e = hipEventCreate(&x->trace_ref);
       if (e == hipSuccess) e = hipEventRecord(x->trace_ref, x->io);
@@ -708,6 +739,7 @@ dag_status dag_destroy(dag_ctx c) {
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
     if (c->trace_ref) (void)hipEventDestroy(c->trace_ref);
+    if (c->gate_ev) (void)hipEventDestroy(c->gate_ev);
     for (void* p : c->dead_plans) (void)hipFree(p);
     for (Buffer& b : c->bufs) {
       free_plan(&b);

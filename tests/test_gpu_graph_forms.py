@@ -20,6 +20,6 @@ def test_replay_results_ready_at_host_read(hw_queues, graph_mode, pool):
     print("[gpu] graph form check hwq=%d graph_mode=%d pool=%d" % (hw_queues, graph_mode, pool), flush=True)
     env = dict(os.environ, GPU_MAX_HW_QUEUES=str(hw_queues))
     r = subprocess.run([sys.executable, os.path.join(HERE, "graph_form_check.py"), str(graph_mode), str(pool),
-                        str(1 << 22), "10", "3"], env=env, capture_output=True, text=True, timeout=240)
+                        str(1 << 22), "10", "8"], env=env, capture_output=True, text=True, timeout=240)
     print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
     assert r.returncode == 0

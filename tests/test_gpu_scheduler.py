@@ -38,6 +38,30 @@ def test_edges_are_honoured_in_time(copy_streams):
         ctx.close()
 
 
+def test_gated_timing_in_the_serial_policy():
+    """Trace mode 3 under the serial policy: tasks are timed one after the
+    other (each starts after the previous one ends), every duration is
+    positive and the outputs equal the oracle's."""
+    print("[gpu] gated timing", flush=True)
+    for prog in (W.img_program(side=300, height=200, seed=44), W.bs_program(n=1 << 16, tasks=3, seed=45)):
+        ref = G.oracle_run(prog)
+        ctx = D.Context(policy=D.DAG_SERIAL_SYNC, trace=3)
+        b = runner.Bound(ctx, prog)
+        D.dag_trace_reset(ctx.h)
+        b.run()
+        iv = []
+        for p in range(1, len(prog.ops) + 1):
+            inf = ctx.info(b.base + p)
+            if inf.stream >= 0:
+                assert inf.t_end_ms > inf.t_start_ms >= 0.0, (prog.name, p)
+                iv.append((inf.t_start_ms, inf.t_end_ms))
+        for (a0, a1), (b0, b1) in zip(iv, iv[1:]):
+            assert a1 <= b0 + 1e-6
+        for name in prog.outputs:
+            G.assert_close(prog, name, b.read(name), ref[name])
+        ctx.close()
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_delay_injection_keeps_results(seed):
     """Spin kernels of random length at random places (with random buffer
