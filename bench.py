@@ -69,6 +69,8 @@ def parse():
                     help="0: one FIFO stream per copy direction; 1: copies placed like kernels")
     ap.add_argument("--copy-lanes", type=int, default=0,
                     help="streams per copy direction (0 = from the tuning file, else 1)")
+    ap.add_argument("--copy-engine", type=int, default=-1, choices=[-1, 0, 1],
+                    help="host<->device copies: 0 = SDMA, 1 = CU copy kernel (-1 = from the tuning file, else 0)")
     ap.add_argument("--spin-wait", type=int, default=0, choices=[0, 1],
                     help="1: host waits spin (hipDeviceScheduleSpin)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -106,6 +108,8 @@ def main():
         log("kernel launch configurations from", args.tuned)
     if not args.copy_lanes:
         args.copy_lanes = int(tuned_dag.get("bs", {}).get("copy_lanes", 1))
+    if args.copy_engine < 0:
+        args.copy_engine = int(tuned_dag.get("bs", {}).get("copy_engine", 0))
     fixed_pool = args.max_streams
 
     def pool_for(name):
@@ -131,7 +135,7 @@ def main():
         def make(policy, trace):
             ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,
                             copy_streams=args.copy_streams, spin_wait=args.spin_wait,
-                            copy_lanes=args.copy_lanes)
+                            copy_lanes=args.copy_lanes, copy_engine=args.copy_engine)
             tune.apply_kernels(ctx, tuned)
             b = runner.Bound(ctx, prog, read_bytes=4)
             for dst in restore:
@@ -293,10 +297,15 @@ def main():
 
         # graph form: the DAG (or one HITS iteration) recorded once and replayed
         # as one task per launch; no dependency work or per-task HIP calls
-        for gm, tag in ((0, "graph"), (1, "replay")):
+        forms = [(0, "graph", args.copy_engine), (1, "replay", args.copy_engine)]
+        if any(o["kind"] == "copy" for o in prog.ops):
+            # the graph with its host<->device copies as copy kernels on the CUs
+            # (kernel nodes) instead of memcpy nodes
+            forms.append((0, "graph_kernel_copies", 1))
+        for gm, tag, engine in forms:
             ctxG = D.Context(policy=D.DAG_PARALLEL_ASYNC, max_streams=args.max_streams, graph_mode=gm,
                              copy_streams=args.copy_streams, spin_wait=args.spin_wait,
-                             copy_lanes=args.copy_lanes)
+                             copy_lanes=args.copy_lanes, copy_engine=engine)
             tune.apply_kernels(ctxG, tuned)
             bG = runner.Bound(ctxG, prog, read_bytes=4)
             for dst in restore:
@@ -334,7 +343,7 @@ def main():
 
     def measure_serving(graphs):
         """Open-loop serving of the mixed trace, concurrent and serial."""
-        ctx = D.Context(spin_wait=args.spin_wait)
+        ctx = D.Context(spin_wait=args.spin_wait, copy_engine=args.copy_engine)
         tune.apply_kernels(ctx, tuned)
         kinds = ("vec", "bs", "img", "hits")
         tmpls = []
@@ -425,7 +434,7 @@ def main():
         "config": {"workload": "bs_fanout_10x2^22" if "bs" in results else head["workload"],
                    "max_streams": head["max_streams"], "copy_streams": args.copy_streams,
                    "copy_lanes": args.copy_lanes,
-                   "spin_wait": args.spin_wait,
+                   "spin_wait": args.spin_wait, "copy_engine": args.copy_engine,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)},
         "makespan_ms": round(head["makespan_ms"], 4),
         "serial_ms": round(head["serial_ms"], 4),
@@ -436,7 +445,12 @@ def main():
         "overlap": head["overlap"],
         "graph_ms": round(head["graph_ms"], 4),
         "graph_speedup": round(head["graph_speedup"], 4),
+        "replay_ms": round(head["replay_ms"], 4),
+        "replay_speedup": round(head["replay_speedup"], 4),
     }
+    if "graph_kernel_copies_ms" in head:
+        line["graph_kernel_copies_ms"] = round(head["graph_kernel_copies_ms"], 4)
+        line["graph_kernel_copies_speedup"] = round(head["graph_kernel_copies_speedup"], 4)
     if "bs" in results:
         # the kernel alone on the GPU, launched back to back on its stream
         # between two events (per-launch median of three batches of 20)

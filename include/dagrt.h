@@ -139,6 +139,13 @@ typedef struct {
                              other's order).  1 (a hardware queue per
                              stream, via CU-masked streams) is refused with
                              DAG_E_UNSUPPORTED: it hung in testing */
+  uint32_t copy_engine;   /* host<->device copies: 0 = the SDMA engines
+                             (hipMemcpyAsync); 1 = a copy kernel on 128
+                             workgroups of the CUs reading or writing the
+                             page-locked host memory over PCIe (the two
+                             directions then overlap; device-to-device
+                             copies always use HIP) */
+  uint32_t reserved;
 } dag_config;
 
 /* One argument of a call: a buffer and its access mode. */

@@ -127,6 +127,10 @@ struct dag_ctx_s {
 namespace dagrt {
 // Error helpers (dagrt.cpp).
 dag_status fail(dag_ctx c, dag_status st, const char* fmt, ...);
+// An asynchronous copy as the context is configured to run it: host<->device
+// copies by the SDMA engines (hipMemcpyAsync) or, with cfg.copy_engine = 1,
+// by a copy kernel on the CUs; device-to-device copies always by HIP.
+hipError_t copy_async(dag_ctx c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s);
 // A new non-blocking stream of the context, default priority.
 hipError_t new_stream(dag_ctx c, hipStream_t* st);
 dag_status hip_fail(dag_ctx c, hipError_t e, const char* what);

@@ -69,6 +69,12 @@ void recycle_retired(dag_ctx c) {
 
 hipError_t new_stream(dag_ctx, hipStream_t* st) { return hipStreamCreateWithFlags(st, hipStreamNonBlocking); }
 
+hipError_t copy_async(dag_ctx c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+  if (c->cfg.copy_engine == 1 && (kind == hipMemcpyHostToDevice || kind == hipMemcpyDeviceToHost))
+    return copy_by_kernel(s, dst, src, bytes);
+  return hipMemcpyAsync(dst, src, bytes, kind, s);
+}
+
 namespace {
 
 dag_status ensure_stream(dag_ctx c, int32_t s) {
@@ -389,7 +395,7 @@ dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t 
   if (st) return st;
   void* dp = static_cast<char*>(bd->ptr) + doff;
   const void* sp = static_cast<const char*>(bs->ptr) + soff;
-  if (!c->dry) HIP_TRY(c, hipMemcpyAsync(dp, sp, bytes, kind, c->streams[s]));
+  if (!c->dry) HIP_TRY(c, copy_async(c, dp, sp, bytes, kind, c->streams[s]));
   note_written(c, c->tmp_acc);
   st = end_task(c, id, s);
   c->launch_us += us_since(t1);
@@ -547,7 +553,7 @@ void plan_region(dag_ctx c, Region* r) {
 }  // namespace
 
 hipError_t launch_region_task(dag_ctx c, const RegionTask& t, hipStream_t s, void* scratch) {
-  if (t.kind == TK_COPY) return hipMemcpyAsync(t.cdst, t.csrc, t.cbytes, t.ckind, s);
+  if (t.kind == TK_COPY) return copy_async(c, t.cdst, t.csrc, t.cbytes, t.ckind, s);
   const KernelDesc* kd = builtin_kernel(t.kernel_id);
   return kd->launch(s, t.ptrs.data(), t.params.data(), t.cfg, scratch, c->cfg.scratch_bytes);
 }
@@ -677,7 +683,7 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
   if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1 ||
-      c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1)
+      c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1 || c.copy_engine > 1 || c.reserved)
     return DAG_E_INVAL;
   // One hardware queue per stream (CU-masked streams) hung in testing with no
   // cause found in this library, so the mode is refused.

@@ -865,6 +865,23 @@ __global__ void k_spin(uint64_t ticks) {
   }
 }
 
+// Host<->device copy by the CUs (pinned host memory is read or written over
+// PCIe by the kernel itself): 16-byte words when both ends are 16-byte
+// aligned, then the tail bytes.
+__global__ __launch_bounds__(256) void k_copy_bytes(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst,
+                                                    uint64_t n) {
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 == 0) {
+    const uint64_t n16 = n / 16;
+    for (uint64_t i = gid; i < n16; i += stride)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    done = n16 * 16;
+  }
+  for (uint64_t i = done + gid; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ __launch_bounds__(1024) void k_copy_f32(const float* __restrict__ src,
                                                    float* __restrict__ dst, uint64_t n, int vec) {
   const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
@@ -1364,6 +1381,14 @@ hipError_t spmv_planned(hipStream_t s, void* const* ptrs, const void* params, co
   SpmvScratch sc = spmv_carries(scratch, tiles);
   sc.coord = const_cast<int*>(coord);
   return spmv_merge_fixup(s, ptrs, q, cfg.variant, tiles, sc);
+}
+
+hipError_t copy_by_kernel(hipStream_t s, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return hipSuccess;
+  constexpr uint32_t kCopyWorkgroups = 128;  // enough requests in flight to fill the link
+  hipLaunchKernelGGL(k_copy_bytes, dim3(kCopyWorkgroups), dim3(256), 0, s, static_cast<const uint8_t*>(src),
+                     static_cast<uint8_t*>(dst), static_cast<uint64_t>(bytes));
+  return hipGetLastError();
 }
 
 void set_launch_events(hipEvent_t start, hipEvent_t stop) {

@@ -45,6 +45,10 @@ hipError_t spmv_plan(hipStream_t s, const int* row_ptr, const void* params, cons
 hipError_t spmv_planned(hipStream_t s, void* const* ptrs, const void* params, const LaunchCfg& cfg,
                         const int* coord, void* scratch);
 
+// Host<->device copy of `bytes` by a copy kernel on 128 workgroups (both
+// pointers device-accessible; pinned host memory is).
+hipError_t copy_by_kernel(hipStream_t s, void* dst, const void* src, size_t bytes);
+
 // Device wall-clock frequency in kHz (for the spin kernel); set once.
 void set_wall_clock_khz(uint64_t khz);
 

@@ -167,8 +167,8 @@ hipMemcpyKind kind_of(uint32_t dst_loc, uint32_t src_loc) {
 hipError_t launch_task(dag_server s, const Shape& sh, const ShapeTask& t, uint64_t dev_off, uint64_t host_off,
                        hipStream_t st, void* scratch) {
   if (t.t->kind == TK_COPY)
-    return hipMemcpyAsync(resolve(s, sh, t.cdst, dev_off, host_off), resolve(s, sh, t.csrc, dev_off, host_off),
-                          t.t->cbytes, t.t->ckind, st);
+    return copy_async(s->ctx, resolve(s, sh, t.cdst, dev_off, host_off), resolve(s, sh, t.csrc, dev_off, host_off),
+                      t.t->cbytes, t.t->ckind, st);
   void* ptrs[kMaxArgs];
   for (size_t i = 0; i < t.refs.size(); ++i) ptrs[i] = resolve(s, sh, t.refs[i], dev_off, host_off);
   const KernelDesc* kd = builtin_kernel(t.t->kernel_id);

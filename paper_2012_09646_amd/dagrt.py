@@ -42,7 +42,8 @@ class dag_config(C.Structure):
     _fields_ = [("policy", C.c_uint32), ("max_streams", C.c_uint32), ("trace", C.c_uint32),
                 ("dry_run", C.c_uint32), ("device", C.c_int32), ("graph_mode", C.c_uint32),
                 ("scratch_bytes", C.c_uint64), ("copy_streams", C.c_uint32),
-                ("spin_wait", C.c_uint32), ("copy_lanes", C.c_uint32), ("own_queues", C.c_uint32)]
+                ("spin_wait", C.c_uint32), ("copy_lanes", C.c_uint32), ("own_queues", C.c_uint32),
+                ("copy_engine", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class dag_arg(C.Structure):
@@ -464,10 +465,10 @@ class Context:
 
     def __init__(self, policy=DAG_PARALLEL_ASYNC, max_streams=8, trace=0, dry_run=False,
                  device=0, graph_mode=0, scratch_bytes=0, copy_streams=0, spin_wait=0, copy_lanes=1,
-                 own_queues=0):
+                 own_queues=0, copy_engine=0):
         self.cfg = dag_config(policy, max_streams, int(trace), int(bool(dry_run)), device,
                               graph_mode, scratch_bytes, copy_streams, int(spin_wait), int(copy_lanes),
-                              int(own_queues))
+                              int(own_queues), int(copy_engine), 0)
         self.h = dag_create(self.cfg)
 
     def close(self):

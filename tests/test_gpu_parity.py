@@ -32,6 +32,37 @@ def test_bs(n, tasks, lanes):
     G.check_program(W.bs_program(n=n, tasks=tasks, seed=1), copy_streams=lanes)
 
 
+@pytest.mark.parametrize("n,tasks,copy_streams", [(7, 2, 0), (100003, 3, 1), (1 << 22, 10, 0)])
+def test_bs_copy_kernel(n, tasks, copy_streams):
+    """Host<->device copies by the CU copy kernel instead of the SDMA engines
+    (odd sizes take the tail path)."""
+    banner("bs copy kernel n=%d tasks=%d copy_streams=%d" % (n, tasks, copy_streams))
+    G.check_program(W.bs_program(n=n, tasks=tasks, seed=5), copy_streams=copy_streams, copy_engine=1)
+
+
+@pytest.mark.parametrize("graph_mode", [0, 1])
+def test_region_replays_copy_kernel(graph_mode):
+    """A recorded Black-Scholes region whose copies run as copy kernels, results
+    cleared before each replay."""
+    from paper_2012_09646_amd import runner
+    banner("regions with copy kernels graph_mode=%d" % graph_mode)
+    prog = W.bs_program(n=(1 << 20) + 3, tasks=5, seed=14)
+    ref = G.oracle_run(prog)
+    ctx = D.Context(graph_mode=graph_mode, copy_engine=1, max_streams=2)
+    try:
+        b = runner.Bound(ctx, prog)
+        b.record(1)
+        ctx.sync()
+        for _ in range(3):
+            for name in prog.outputs:
+                ctx.host_write(b.h[name], np.zeros(prog.bufs[name].nbytes, np.uint8))
+            b.replay(1)
+            for name in prog.outputs:
+                G.assert_close(prog, name, b.read(name), ref[name])
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("r,sigma,years", [(0.08, 0.3, 1.0), (0.0, 1.5, 4.0), (0.2, 0.05, 0.1), (0.03, 3.0, 30.0)])
 def test_bs_variants_wide_range(variant, r, sigma, years):
