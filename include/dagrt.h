@@ -117,7 +117,11 @@ typedef struct {
                              waits, make no HIP call and touch no memory */
   int32_t device;         /* HIP device ordinal */
   uint32_t graph_mode;    /* region replays: 0 = hipGraph, 1 = recorded
-                             multi-stream replay without dependency work */
+                             multi-stream replay without dependency work,
+                             2 = hipGraph unless the region has host<->device
+                             copies (which a graph runs as blit kernels on
+                             the CUs rather than on the SDMA engines), then
+                             recorded replay */
   uint64_t scratch_bytes; /* per-stream device scratch for reductions and
                              SpMV carries (0 = 4 MiB) */
   uint32_t copy_streams;  /* 0 = host->device and device->host copies each
@@ -373,6 +377,22 @@ dag_status dag_submit_batch(dag_ctx ctx, const dag_op* ops, uint32_t nops,
 dag_status dag_region_begin(dag_ctx ctx, uint64_t key);
 dag_status dag_region_end(dag_ctx ctx);
 dag_status dag_region_launch(dag_ctx ctx, uint64_t key, dag_task* out);
+/* Recurring shapes replayed automatically.  The program brackets the
+ * region's calls with dag_region_run_begin(key) / dag_region_run_end every
+ * time it runs them.  The first time (no recording under key) the calls run
+ * eagerly and are recorded, as between dag_region_begin/end.  Later, each
+ * call is only compared with the recording (kernel id, parameter bytes,
+ * launch configuration, argument handles and modes; copy ends, offsets and
+ * size) and nothing is enqueued; the submit calls return task id 0.  If every
+ * recorded call matched, dag_region_run_end launches the recording as one
+ * task (as dag_region_launch; *out = its id, *replayed = 1).  At the first
+ * call that differs, or at the end when only a prefix matched, the calls so
+ * far are submitted eagerly, the rest of the region runs eagerly, and the new
+ * sequence replaces the recording at dag_region_run_end (*out = 0,
+ * *replayed = 0).  Host accesses, sync and release are refused inside
+ * (DAG_E_BUSY).  out and replayed may be NULL. */
+dag_status dag_region_run_begin(dag_ctx ctx, uint64_t key);
+dag_status dag_region_run_end(dag_ctx ctx, dag_task* out, uint32_t* replayed);
 /* Number of recorded tasks and distinct streams of a region. */
 dag_status dag_region_info(dag_ctx ctx, uint64_t key, uint32_t* ntasks, uint32_t* nstreams);
 dag_status dag_region_drop(dag_ctx ctx, uint64_t key);

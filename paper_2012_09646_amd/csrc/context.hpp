@@ -60,6 +60,9 @@ struct RegionTask {
   size_t cbytes = 0;
   hipMemcpyKind ckind = hipMemcpyDefault;
   uint64_t id = 0;         // task id of the eager run
+  std::vector<dag_arg> args;  // kernel arguments as submitted (handles, modes)
+  dag_buf cdst_h = 0, csrc_h = 0;  // copy ends as submitted
+  size_t cdst_off = 0, csrc_off = 0;
   int32_t rstream = 0;     // region-local stream
   std::vector<uint32_t> rwaits;    // region-local task indices waited on
   std::vector<uint32_t> rparents;  // every intra-region parent (region-local indices)
@@ -110,6 +113,12 @@ struct dag_ctx_s {
   std::unordered_map<uint64_t, std::unique_ptr<dagrt::Region>> regions;
   bool recording = false;
   uint64_t rec_key = 0;
+  // dag_region_run_*: calls compared with the recording of match_key instead
+  // of being run; match_pos calls have matched so far
+  bool matching = false;
+  uint64_t match_key = 0;
+  size_t match_pos = 0;
+  bool in_region() const { return recording || matching; }
   std::unique_ptr<dagrt::Region> rec;
   std::vector<hipStream_t> aux;           // capture / replay streams
   std::vector<void*> aux_scratch;

@@ -264,8 +264,42 @@ hipError_t spmv_with_plan(dag_ctx c, Buffer* rp, int32_t s, void* const* ptrs, c
 // -------------------------------------------------------------------------
 // submissions
 // -------------------------------------------------------------------------
+dag_status diverge(dag_ctx c);
+
+// Matching mode: does the next recorded call equal this kernel call?
+bool matches_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pbytes, const dag_arg* args,
+                    uint32_t nargs) {
+  const Region* r = c->regions.at(c->match_key).get();
+  if (c->match_pos >= r->tasks.size()) return false;
+  const RegionTask& t = r->tasks[c->match_pos];
+  if (t.kind != TK_KERNEL || t.kernel_id != kid || kid >= DAG_K_USER_BASE) return false;
+  if (t.params.size() != pbytes || (pbytes && std::memcmp(t.params.data(), params, pbytes) != 0)) return false;
+  if (t.args.size() != nargs || (nargs && !args)) return false;
+  for (uint32_t i = 0; i < nargs; ++i)
+    if (t.args[i].buf != args[i].buf || t.args[i].mode != args[i].mode || !get_buf(c, args[i].buf)) return false;
+  const LaunchCfg& now = c->launch_cfg[kid];
+  return now.block == t.cfg.block && now.grid_cap == t.cfg.grid_cap && now.variant == t.cfg.variant;
+}
+
+bool matches_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t soff, size_t bytes) {
+  const Region* r = c->regions.at(c->match_key).get();
+  if (c->match_pos >= r->tasks.size()) return false;
+  const RegionTask& t = r->tasks[c->match_pos];
+  return t.kind == TK_COPY && t.cdst_h == dst && t.cdst_off == doff && t.csrc_h == src && t.csrc_off == soff &&
+         t.cbytes == bytes && get_buf(c, dst) && get_buf(c, src);
+}
+
 dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pbytes,
                          const dag_arg* args, uint32_t nargs, dag_task* out) {
+  if (c->matching) {
+    if (matches_kernel(c, kid, params, pbytes, args, nargs)) {
+      ++c->match_pos;
+      if (out) *out = 0;
+      return DAG_OK;
+    }
+    dag_status st = diverge(c);
+    if (st) return st;
+  }
   const auto t0 = Clock::now();
   const KernelDesc* kd = nullptr;
   const UserKernel* uk = nullptr;
@@ -346,6 +380,7 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
     rt.kernel_id = kid;
     rt.params.assign(static_cast<const char*>(params), static_cast<const char*>(params) + pbytes);
     rt.ptrs.assign(ptrs, ptrs + nargs);
+    rt.args.assign(args, args + nargs);
     rt.cfg = cfg;
     rt.id = id;
     c->rec->tasks.push_back(std::move(rt));
@@ -362,6 +397,15 @@ hipMemcpyKind copy_kind(uint32_t dst_loc, uint32_t src_loc) {
 
 dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t soff, size_t bytes,
                        dag_task* out) {
+  if (c->matching) {
+    if (matches_copy(c, dst, doff, src, soff, bytes)) {
+      ++c->match_pos;
+      if (out) *out = 0;
+      return DAG_OK;
+    }
+    dag_status st = diverge(c);
+    if (st) return st;
+  }
   const auto t0 = Clock::now();
   Buffer* bd = get_buf(c, dst);
   Buffer* bs = get_buf(c, src);
@@ -407,6 +451,10 @@ dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t 
     rt.csrc = sp;
     rt.cbytes = bytes;
     rt.ckind = kind;
+    rt.cdst_h = dst;
+    rt.csrc_h = src;
+    rt.cdst_off = doff;
+    rt.csrc_off = soff;
     rt.id = id;
     c->rec->tasks.push_back(std::move(rt));
     for (const Access& a : c->tmp_acc) add_access(&c->rec->accs, a.buf, a.acc);
@@ -414,9 +462,30 @@ dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t 
   return DAG_OK;
 }
 
+// Matching mode ends without a replay: start a fresh recording under the same
+// key and run the calls that matched so far eagerly (from the old recording,
+// which stays in place until the new one replaces it at the region's end).
+dag_status diverge(dag_ctx c) {
+  const Region* old = c->regions.at(c->match_key).get();
+  const size_t n = c->match_pos;
+  c->matching = false;
+  c->recording = true;
+  c->rec_key = c->match_key;
+  c->rec.reset(new Region());
+  for (size_t k = 0; k < n; ++k) {
+    const RegionTask& t = old->tasks[k];
+    dag_status st = t.kind == TK_KERNEL
+                        ? submit_kernel(c, t.kernel_id, t.params.data(), t.params.size(), t.args.data(),
+                                        static_cast<uint32_t>(t.args.size()), nullptr)
+                        : submit_copy(c, t.cdst_h, t.cdst_off, t.csrc_h, t.csrc_off, t.cbytes, nullptr);
+    if (st) return st;
+  }
+  return DAG_OK;
+}
+
 dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hdst, const void* hsrc,
                        size_t bytes, dag_task* out) {
-  if (c->recording) return fail(c, DAG_E_BUSY, "host access inside a region");
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "host access inside a region");
   Buffer* b = get_buf(c, h);
   if (!b) return fail(c, DAG_E_INVAL, "invalid buffer handle %u", h);
   if (off > b->bytes || bytes > b->bytes - off) return fail(c, DAG_E_INVAL, "access overruns the buffer");
@@ -470,7 +539,7 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
 }
 
 dag_status do_sync(dag_ctx c) {
-  if (c->recording) return fail(c, DAG_E_BUSY, "sync inside a region");
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "sync inside a region");
   c->tr.add_sync();
   if (!c->dry) {
     for (hipStream_t s : c->streams) HIP_TRY(c, hipStreamSynchronize(s));
@@ -682,7 +751,7 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   c.max_streams = 8;
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
-  if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 1 ||
+  if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 2 ||
       c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1 || c.copy_engine > 1 || c.reserved)
     return DAG_E_INVAL;
   // One hardware queue per stream (CU-masked streams) hung in testing with no
@@ -831,7 +900,7 @@ dag_status dag_buffer_alloc(dag_ctx c, size_t bytes, uint32_t loc, dag_buf* out)
 
 dag_status dag_buffer_release(dag_ctx c, dag_buf h) {
   CHECK_CTX(c);
-  if (c->recording) return fail(c, DAG_E_BUSY, "release inside a region");
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "release inside a region");
   Buffer* b = get_buf(c, h);
   if (!b) return fail(c, DAG_E_INVAL, "invalid buffer handle %u", h);
   c->tr.add_host(TK_RELEASE, h - 1, ACC_W, c->serial, &c->tmp_wait);
@@ -884,7 +953,7 @@ dag_status dag_tune_kernel(dag_ctx c, uint32_t kid, const void* params, size_t p
                            double* us) {
   CHECK_CTX(c);
   if (c->dry) return fail(c, DAG_E_UNSUPPORTED, "tuning needs a GPU");
-  if (c->recording) return fail(c, DAG_E_BUSY, "tuning inside a region");
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "tuning inside a region");
   const KernelDesc* kd = builtin_kernel(kid);
   if (!kd) return fail(c, DAG_E_NOTFOUND, "unknown kernel id %u", kid);
   if (!cands || ncand == 0 || !best) return fail(c, DAG_E_INVAL, "candidates and best are required");
@@ -1026,7 +1095,7 @@ dag_status dag_submit_batch(dag_ctx c, const dag_op* ops, uint32_t nops, dag_tas
 
 dag_status dag_region_begin(dag_ctx c, uint64_t key) {
   CHECK_CTX(c);
-  if (c->recording) return fail(c, DAG_E_BUSY, "a region is already being recorded");
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "a region is already being recorded");
   if (c->dry && c->cfg.graph_mode == 0) {
     // schedule-only contexts record the region but never build a graph
   }
@@ -1043,7 +1112,14 @@ dag_status dag_region_end(dag_ctx c) {
   std::unique_ptr<Region> r = std::move(c->rec);
   if (r->tasks.empty()) return fail(c, DAG_E_INVAL, "empty region");
   plan_region(c, r.get());
-  if (!c->dry && c->cfg.graph_mode == 0) {
+  bool host_copies = false;
+  for (const RegionTask& t : r->tasks)
+    if (t.kind == TK_COPY && (t.ckind == hipMemcpyHostToDevice || t.ckind == hipMemcpyDeviceToHost))
+      host_copies = true;
+  // mode 2 keeps regions with host<->device copies as recorded replays: in a
+  // hipGraph their copies become blit kernels on the CUs instead of SDMA copies
+  const bool as_graph = c->cfg.graph_mode == 0 || (c->cfg.graph_mode == 2 && !host_copies);
+  if (!c->dry && as_graph) {
     dag_status st = build_graph(c, r.get());
     if (st) {
       free_region(r.get());
@@ -1063,7 +1139,7 @@ dag_status dag_region_end(dag_ctx c) {
 
 dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   CHECK_CTX(c);
-  if (c->recording) return fail(c, DAG_E_BUSY, "region launch while recording");
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "region launch while recording");
   auto it = c->regions.find(key);
   if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
   Region* r = it->second.get();
@@ -1081,7 +1157,7 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   st = begin_task(c, id, s);
   if (st) return st;
   if (!c->dry) {
-    if (c->cfg.graph_mode == 0) {
+    if (r->exec) {
       HIP_TRY(c, hipGraphLaunch(r->exec, c->streams[s]));
     } else {
       st = replay_region(c, r, c->streams[s], s);
@@ -1102,8 +1178,37 @@ dag_status dag_region_info(dag_ctx c, uint64_t key, uint32_t* ntasks, uint32_t* 
   return DAG_OK;
 }
 
+dag_status dag_region_run_begin(dag_ctx c, uint64_t key) {
+  CHECK_CTX(c);
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "a region is already open");
+  if (c->regions.find(key) == c->regions.end()) return dag_region_begin(c, key);
+  c->matching = true;
+  c->match_key = key;
+  c->match_pos = 0;
+  return DAG_OK;
+}
+
+dag_status dag_region_run_end(dag_ctx c, dag_task* out, uint32_t* replayed) {
+  CHECK_CTX(c);
+  if (out) *out = 0;
+  if (replayed) *replayed = 0;
+  if (c->matching) {
+    const Region* r = c->regions.at(c->match_key).get();
+    if (c->match_pos == r->tasks.size()) {
+      c->matching = false;
+      if (replayed) *replayed = 1;
+      return dag_region_launch(c, c->match_key, out);
+    }
+    dag_status st = diverge(c);  // only a prefix matched: run it and record anew
+    if (st) return st;
+  }
+  if (!c->recording) return fail(c, DAG_E_BUSY, "no region is open");
+  return dag_region_end(c);
+}
+
 dag_status dag_region_drop(dag_ctx c, uint64_t key) {
   CHECK_CTX(c);
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "region drop inside a region");
   auto it = c->regions.find(key);
   if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
   if (!c->dry) {

@@ -167,6 +167,8 @@ _SIGS = {
     "dag_region_launch": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint64)]),
     "dag_region_info": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint32), _P(C.c_uint32)]),
     "dag_region_drop": (_st, [_ctx_t, C.c_uint64]),
+    "dag_region_run_begin": (_st, [_ctx_t, C.c_uint64]),
+    "dag_region_run_end": (_st, [_ctx_t, _P(C.c_uint64), _P(C.c_uint32)]),
     "dag_edges": (_st, [_ctx_t, _P(dag_edge), C.c_size_t, _P(C.c_size_t)]),
     "dag_task_waits": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint64), C.c_uint32, _P(C.c_uint32)]),
     "dag_task_get_info": (_st, [_ctx_t, C.c_uint64, _P(dag_task_info)]),
@@ -354,6 +356,18 @@ def dag_region_launch(ctx, key):
     out = C.c_uint64()
     _check(ctx, lib().dag_region_launch(ctx, key, C.byref(out)))
     return out.value
+
+
+def dag_region_run_begin(ctx, key):
+    _check(ctx, lib().dag_region_run_begin(ctx, key))
+
+
+def dag_region_run_end(ctx):
+    """Returns (task id or 0, replayed)."""
+    out = C.c_uint64()
+    rep = C.c_uint32()
+    _check(ctx, lib().dag_region_run_end(ctx, C.byref(out), C.byref(rep)))
+    return out.value, bool(rep.value)
 
 
 def dag_region_info(ctx, key):

@@ -130,6 +130,23 @@ class Bound:
         finally:
             D.dag_region_end(self.ctx.h)
 
+    def run_recurring(self, key, per, host_reads=True):
+        """Run the program's kernel/copy calls in chunks of `per` (one
+        iteration each), every chunk bracketed by dag_region_run_begin/end:
+        the first chunk is recorded, identical later chunks replay it.
+        Returns [(task id, replayed)] per chunk."""
+        idx = [i for i, o in enumerate(self.prog.ops) if o["kind"] in ("kernel", "copy")]
+        out = []
+        for c0 in range(0, len(idx), per):
+            D.dag_region_run_begin(self.ctx.h, key)
+            D.dag_submit_batch(self.ctx.h, self._sub(idx[c0:c0 + per]))
+            out.append(D.dag_region_run_end(self.ctx.h))
+        if host_reads:
+            hr = [i for i, o in enumerate(self.prog.ops) if o["kind"] == "host_read"]
+            if hr:
+                D.dag_submit_batch(self.ctx.h, self._sub(hr))
+        return out
+
     def replay(self, key, times=1, host_reads=True):
         """Replay region `key` `times` times, then the program's host reads."""
         ids = [D.dag_region_launch(self.ctx.h, key) for _ in range(times)]

@@ -188,6 +188,63 @@ def test_error_paths():
     ctx.close()
 
 
+def test_recurring_region_replays_when_every_call_matches():
+    """dag_region_run_*: the first HITS iteration is recorded, the next ones
+    are replayed as one task each, chained through the vectors they write."""
+    prog = W.hits_program(n=300, deg=5, iters=4, seed=7)
+    ctx = D.Context(dry_run=True)
+    b = runner.Bound(ctx, prog)
+    before = ctx.stats().tasks  # the uploads
+    res = b.run_recurring(1, 6)
+    assert [r for _, r in res] == [False, True, True, True]
+    assert res[0][0] == 0 and all(t > 0 for t, _ in res[1:])
+    assert D.dag_region_info(ctx.h, 1)[0] == 6
+    # one eager iteration, three replays, two host reads
+    assert ctx.stats().tasks - before == 6 + 3 + 2
+    # each replay depends on the previous one (both read and write a and h)
+    edges = {(s, d) for s, d, _, _ in ctx.edges()}
+    for prev, cur in zip(res[1:], res[2:]):
+        assert (prev[0], cur[0]) in edges
+    ctx.close()
+
+
+def test_recurring_region_rerecords_on_a_difference():
+    prog = W.hits_program(n=300, deg=5, iters=2, seed=7)
+    ctx = D.Context(dry_run=True)
+    b = runner.Bound(ctx, prog)
+    b.run_recurring(1, 6, host_reads=False)
+    before = ctx.stats().tasks
+    # a different launch configuration of sumsq makes the third call differ
+    ctx.set_launch("sumsq", 512, 256, 0)
+    D.dag_region_run_begin(ctx.h, 1)
+    ids = D.dag_submit_batch(ctx.h, b._sub(list(range(6))))
+    t, rep = D.dag_region_run_end(ctx.h)
+    assert not rep and t == 0
+    assert ids[:2] == [0, 0] and all(i > 0 for i in ids[2:])  # matched prefix, then eager
+    # the first two calls were run eagerly once the third differed: six new tasks in all
+    assert ctx.stats().tasks - before == 6
+    # the new sequence replays next time
+    D.dag_region_run_begin(ctx.h, 1)
+    D.dag_submit_batch(ctx.h, b._sub(list(range(6))))
+    t, rep = D.dag_region_run_end(ctx.h)
+    assert rep and t > 0
+    # only a prefix: recorded anew with four calls
+    D.dag_region_run_begin(ctx.h, 1)
+    D.dag_submit_batch(ctx.h, b._sub(list(range(4))))
+    t, rep = D.dag_region_run_end(ctx.h)
+    assert not rep and D.dag_region_info(ctx.h, 1)[0] == 4
+    # host access, sync, region launch and drop are refused inside
+    D.dag_region_run_begin(ctx.h, 1)
+    assert _status(ctx.sync) == "DAG_E_BUSY"
+    assert _status(D.dag_region_launch, ctx.h, 1) == "DAG_E_BUSY"
+    assert _status(D.dag_region_drop, ctx.h, 1) == "DAG_E_BUSY"
+    assert _status(D.dag_region_run_begin, ctx.h, 2) == "DAG_E_BUSY"
+    D.dag_submit_batch(ctx.h, b._sub(list(range(4))))
+    assert D.dag_region_run_end(ctx.h)[1]
+    assert _status(D.dag_region_run_end, ctx.h) == "DAG_E_BUSY"
+    ctx.close()
+
+
 def test_bad_config_rejected():
     with pytest.raises(D.DagError):
         D.Context(dry_run=True, max_streams=65)

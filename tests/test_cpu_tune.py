@@ -64,3 +64,20 @@ def test_hw_queue_sweep_merges_worker_results(tmp_path, monkeypatch):
     assert len(data["dag"]["bs"]["table"]) == 3
     assert {r["hw_queues"] for r in data["dag"]["bs"]["table"]} == {4, 8, 16}
     assert data["kernels"]["bs_call"]["variant"] == 1
+
+
+def test_dag_choice_prefers_configurations_that_fit_the_queues(tmp_path, monkeypatch):
+    def fake_spawn(extra, out, hw_queues=None):
+        if "kernels" in extra:
+            return {"kernels": {}, "dag": {}}
+        # 4 queues: the fastest configuration needs 6 streams; 8 queues: it fits but is slower
+        e = {4: {"max_streams": 4, "ms": 3.0, "fits": False, "table": [{"ms": 3.0}, {"ms": 3.5}]},
+             8: {"max_streams": 1, "ms": 3.4, "fits": True, "table": [{"ms": 3.4}]}}[hw_queues]
+        return {"kernels": {}, "dag": {"bs": e}}
+
+    monkeypatch.setattr(tune, "_spawn", fake_spawn)
+    out = str(tmp_path / "t.json")
+    monkeypatch.setattr("sys.argv", ["tune", "--out", out, "--dag", "--hw-queues", "4,8", "--workload", "bs"])
+    tune.main()
+    d = tune.load(out)["dag"]["bs"]
+    assert d["hw_queues"] == 8 and d["max_streams"] == 1

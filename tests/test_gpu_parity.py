@@ -40,6 +40,34 @@ def test_bs_copy_kernel(n, tasks, copy_streams):
     G.check_program(W.bs_program(n=n, tasks=tasks, seed=5), copy_streams=copy_streams, copy_engine=1)
 
 
+@pytest.mark.parametrize("graph_mode", [0, 1, 2])
+def test_recurring_region_runs(graph_mode):
+    """HITS with every iteration bracketed by dag_region_run_begin/end: the
+    first iteration is recorded, the other nine replay it; a launch
+    configuration changed half-way makes one iteration run eagerly and
+    re-record. The results equal the oracle's either way."""
+    from paper_2012_09646_amd import runner
+    banner("recurring regions graph_mode=%d" % graph_mode)
+    prog = W.hits_program(n=20000, iters=10, seed=15)
+    ref = G.oracle_run(prog)
+    ctx = D.Context(graph_mode=graph_mode)
+    try:
+        b = runner.Bound(ctx, prog)
+        idx = [i for i, o in enumerate(prog.ops) if o["kind"] == "kernel"]
+        reps = []
+        for it in range(10):
+            if it == 5:
+                ctx.set_launch("scale_l2", 128, 1024, 0)  # differs from the default
+            D.dag_region_run_begin(ctx.h, 3)
+            D.dag_submit_batch(ctx.h, b._sub(idx[6 * it:6 * it + 6]))
+            reps.append(D.dag_region_run_end(ctx.h)[1])
+        assert reps == [False, True, True, True, True, False, True, True, True, True]
+        for name in prog.outputs:
+            G.assert_close(prog, name, b.read(name), ref[name])
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("graph_mode", [0, 1])
 def test_region_replays_copy_kernel(graph_mode):
     """A recorded Black-Scholes region whose copies run as copy kernels, results
@@ -265,7 +293,7 @@ def test_reduction_variants(variant, block, cap):
         ctx.close()
 
 
-@pytest.mark.parametrize("graph_mode", [0, 1])
+@pytest.mark.parametrize("graph_mode", [0, 1, 2])
 def test_region_replays(graph_mode):
     """Recurring shapes replayed as one task (hipGraph or recorded multi-stream
     replay) give the oracle's results; HITS replays one iteration 9 times."""
