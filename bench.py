@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "serve"])
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
-    ap.add_argument("--serve-lanes", type=int, default=8, help="serving: HIP streams requests spread over")
+    ap.add_argument("--serve-lanes", type=int, default=2,
+                    help="serving: kernel lanes (HIP streams) requests spread over; 2 measured best at 4 and 8 queues")
     ap.add_argument("--serve-copy-lanes", type=int, default=1, choices=[0, 1, 2, 3, 4],
                     help="serving: N = host<->device copies of all requests on N streams per direction")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
