@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
     ap.add_argument("--serve-lanes", type=int, default=2,
                     help="serving: kernel lanes (HIP streams) requests spread over; 2 measured best at 4 and 8 queues")
+    ap.add_argument("--serve-copy-engine", type=int, default=0, choices=[-1, 0, 1, 2, 3],
+                    help="serving: copy engine (as --copy-engine; -1 = the same as the DAGs); SDMA measured "
+                         "best for the mix in a process of its own")
     ap.add_argument("--serve-copy-lanes", type=int, default=1, choices=[0, 1, 2, 3, 4],
                     help="serving: N = host<->device copies of all requests on N streams per direction")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
@@ -70,12 +73,47 @@ def parse():
                     help="0: one FIFO stream per copy direction; 1: copies placed like kernels")
     ap.add_argument("--copy-lanes", type=int, default=0,
                     help="streams per copy direction (0 = from the tuning file, else 1)")
-    ap.add_argument("--copy-engine", type=int, default=-1, choices=[-1, 0, 1],
-                    help="host<->device copies: 0 = SDMA, 1 = CU copy kernel (-1 = from the tuning file, else 0)")
+    ap.add_argument("--copy-engine", type=int, default=2, choices=[0, 1, 2, 3],
+                    help="host<->device copies: 0 = SDMA, 1 = CU copy kernel, 2 = H2D SDMA + D2H kernel "
+                         "(default: with SDMA both ways, some processes ran the two directions on one engine "
+                         "and the fan-out at serial speed), 3 = H2D kernel + D2H SDMA")
     ap.add_argument("--spin-wait", type=int, default=0, choices=[0, 1],
                     help="1: host waits spin (hipDeviceScheduleSpin)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
+
+
+def orchestrate(args):
+    """--workload all: every workload measured in a fresh child process, one
+    after the other (this process never touches the GPU).  A process's copy
+    engines and hardware queues are bound when it first uses them, and a
+    measurement was seen to depend on what ran earlier in the same process;
+    fresh processes make each figure independent of the others."""
+    import subprocess
+    fwd = ["--steps", str(args.steps), "--warmup", str(args.warmup), "--tuned", args.tuned,
+           "--max-streams", str(args.max_streams), "--copy-streams", str(args.copy_streams),
+           "--copy-lanes", str(args.copy_lanes), "--copy-engine", str(args.copy_engine),
+           "--spin-wait", str(args.spin_wait), "--requests", str(args.requests), "--rate", str(args.rate),
+           "--low-rate", str(args.low_rate), "--serve-lanes", str(args.serve_lanes),
+           "--serve-copy-lanes", str(args.serve_copy_lanes), "--serve-copy-engine", str(args.serve_copy_engine)]
+    if args.hw_queues:
+        fwd += ["--hw-queues", str(args.hw_queues)]
+    lines = {}
+    for wl in ("bs", "vec", "img", "hits", "serve"):
+        extra = [] if wl == "bs" and not args.no_cpu_baseline else ["--no-cpu-baseline"]
+        log("child process: --workload %s" % wl)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", wl] + fwd + extra,
+                           stdout=subprocess.PIPE, text=True)
+        if r.returncode != 0:
+            log("workload %s failed with status %d" % (wl, r.returncode))
+            sys.exit(r.returncode)
+        lines[wl] = json.loads(r.stdout.strip().splitlines()[-1])
+    line = lines["bs"]
+    for wl in ("vec", "img", "hits"):
+        line["workloads"][wl] = lines[wl]["workloads"][wl]
+    line["serving"] = lines["serve"]["serving"]
+    line["config"]["processes"] = "one per workload"
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -91,6 +129,9 @@ def main():
             args.hw_queues = int(json.load(f).get("dag", {}).get("bs", {}).get("hw_queues", 0))
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
+    if args.workload == "all":
+        orchestrate(args)
+        return
     import numpy as np  # noqa: F401
 
     from paper_2012_09646_amd import dagrt as D
@@ -109,8 +150,6 @@ def main():
         log("kernel launch configurations from", args.tuned)
     if not args.copy_lanes:
         args.copy_lanes = int(tuned_dag.get("bs", {}).get("copy_lanes", 1))
-    if args.copy_engine < 0:
-        args.copy_engine = int(tuned_dag.get("bs", {}).get("copy_engine", 0))
     fixed_pool = args.max_streams
 
     def pool_for(name):
@@ -353,7 +392,8 @@ def main():
 
     def measure_serving(graphs):
         """Open-loop serving of the mixed trace, concurrent and serial."""
-        ctx = D.Context(spin_wait=args.spin_wait, copy_engine=args.copy_engine)
+        ctx = D.Context(spin_wait=args.spin_wait,
+                        copy_engine=args.copy_engine if args.serve_copy_engine < 0 else args.serve_copy_engine)
         tune.apply_kernels(ctx, tuned)
         kinds = ("vec", "bs", "img", "hits")
         tmpls = []
@@ -389,7 +429,8 @@ def main():
 
         out = one_rate(args.rate, args.requests)
         out.update({"shapes": len(tmpls), "budget_bytes": budget, "lanes": args.serve_lanes,
-                    "copy_lanes": args.serve_copy_lanes})
+                    "copy_lanes": args.serve_copy_lanes,
+                    "copy_engine": args.copy_engine if args.serve_copy_engine < 0 else args.serve_copy_engine})
         # a second, lower arrival rate at which the serial baseline is not overloaded
         if args.low_rate:
             out["low_rate"] = one_rate(args.low_rate, max(1, args.requests // 2))

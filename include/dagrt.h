@@ -146,9 +146,11 @@ typedef struct {
   uint32_t copy_engine;   /* host<->device copies: 0 = the SDMA engines
                              (hipMemcpyAsync); 1 = a copy kernel on 128
                              workgroups of the CUs reading or writing the
-                             page-locked host memory over PCIe (the two
-                             directions then overlap; device-to-device
-                             copies always use HIP) */
+                             page-locked host memory over PCIe; 2 = host->
+                             device by SDMA, device->host by the copy
+                             kernel; 3 = the reverse.  With 2 and 3 the two
+                             directions never share an SDMA engine.
+                             Device-to-device copies always use HIP. */
   uint32_t reserved;
 } dag_config;
 

@@ -70,8 +70,10 @@ void recycle_retired(dag_ctx c) {
 hipError_t new_stream(dag_ctx, hipStream_t* st) { return hipStreamCreateWithFlags(st, hipStreamNonBlocking); }
 
 hipError_t copy_async(dag_ctx c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
-  if (c->cfg.copy_engine == 1 && (kind == hipMemcpyHostToDevice || kind == hipMemcpyDeviceToHost))
-    return copy_by_kernel(s, dst, src, bytes);
+  const uint32_t e = c->cfg.copy_engine;
+  const bool by_kernel = (kind == hipMemcpyHostToDevice && (e == 1 || e == 3)) ||
+                         (kind == hipMemcpyDeviceToHost && (e == 1 || e == 2));
+  if (by_kernel) return copy_by_kernel(s, dst, src, bytes);
   return hipMemcpyAsync(dst, src, bytes, kind, s);
 }
 
@@ -752,7 +754,7 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
   if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 2 ||
-      c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1 || c.copy_engine > 1 || c.reserved)
+      c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1 || c.copy_engine > 3 || c.reserved)
     return DAG_E_INVAL;
   // One hardware queue per stream (CU-masked streams) hung in testing with no
   // cause found in this library, so the mode is refused.
