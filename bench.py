@@ -30,12 +30,13 @@ sys.path.insert(0, ROOT)
 METRIC = "DAG makespan speedup vs serial + % critical-path bound; serving p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # vector fp64: 256 CUs x 128 flop/clk (4 SIMDs x 16 lanes x FMA) x 2.4 GHz
-# fp64 work of one Black-Scholes price: the SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 counters of the leaner
-# kernel variant (1: one exp and one polynomial per CDF) give 83 FMA + 44 ADD + 23 MUL + 3 TRANS per element
-# (FMA = 2 flops); that count is taken as the method's work for both variants (variant 0, the library erfc,
-# executes 127 + 61 + 22 + 7).  VALU wave instructions per element (all kinds): 285.75 and 206.25.
-BS_FLOPS_PER_ELEMENT = 2 * 83 + 44 + 23 + 3
-BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25}
+# fp64 work of one Black-Scholes price: the SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 counters of the leanest kernel
+# variant (2: own exp and log, one polynomial per CDF) give 86 FMA + 5 ADD + 19 MUL + 3 TRANS per element
+# (FMA = 2 flops); that count is taken as the method's work for every variant (variant 1 executes
+# 83 + 44 + 23 + 3, variant 0, the library erfc, 127 + 61 + 22 + 7).  VALU wave-lane instructions per element
+# (all kinds) per variant:
+BS_FLOPS_PER_ELEMENT = 2 * 86 + 5 + 19 + 3
+BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25, 2: 156.25}
 # HBM bytes per bs_call launch from FETCH_SIZE / WRITE_SIZE, each divided by what the counter reads for a
 # 256 MiB copy kernel (FETCH_SIZE 0.50005x, WRITE_SIZE 1.000x of the true bytes): 16.16 MiB in + 16.00 MiB out
 TRAFFIC_BS_BYTES = int((8276.19 / 0.50005 + 16384.0 / 1.0) * 1024)

@@ -273,13 +273,80 @@ __device__ __forceinline__ double bs_price_fast(double s, const BsConst& k) {
   return s * n1 - k.disc_strike * n2;
 }
 
-// variant 0: the library's erfc; variant 1: bs_price_fast.
+// ln 2 split so that k * kLn2Hi is exact for |k| < 2^21 (its low 21 mantissa
+// bits are zero); kLn2Lo is the rest.
+constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
+constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+
+// e^x for x <= 0 without special-case handling: x = k ln2 + r, |r| <= ln2/2,
+// e^r by its Taylor series to r^13 (next term below 5e-18), scaled by 2^k.
+// Below -746 the result is 0 (clamped so k stays a small integer).
+__device__ __forceinline__ double exp_nonpos(double x) {
+  x = fmax(x, -746.0);
+  const double kd = rint(x * 0x1.71547652b82fep+0);  // x log2(e)
+  double r = fma(-kd, kLn2Hi, x);
+  r = fma(-kd, kLn2Lo, r);
+  constexpr double c[14] = {0x1.0p+0, 0x1.0p+0, 0x1.0p-1, 0x1.5555555555555p-3, 0x1.5555555555555p-5,
+                            0x1.1111111111111p-7, 0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13,
+                            0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19, 0x1.27e4fb7789f5cp-22,
+                            0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};  // 1/n!
+  double p = c[13];
+#pragma unroll
+  for (int i = 12; i >= 0; --i) p = fma(p, r, c[i]);
+  return ldexp(p, static_cast<int>(kd));
+}
+
+// ln y for finite y > 0 in the normal range: y = m 2^e with m in
+// [sqrt(1/2), sqrt(2)); ln m = 2 atanh(u), u = (m - 1)/(m + 1), |u| <= 0.172,
+// by its series to u^19 (next term below 5e-18); u by the hardware
+// reciprocal and two Newton steps.
+__device__ __forceinline__ double log_pos(double y) {
+  int e;
+  double m = frexp(y, &e);  // m in [0.5, 1)
+  if (m < M_SQRT1_2) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = m - 1.0;  // exact
+  const double x = 2.0 + f;
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  const double u = f * r, u2 = u * u;
+  constexpr double c[10] = {0x1.0p+0, 0x1.5555555555555p-2, 0x1.999999999999ap-3, 0x1.2492492492492p-3,
+                            0x1.c71c71c71c71cp-4, 0x1.745d1745d1746p-4, 0x1.3b13b13b13b14p-4,
+                            0x1.1111111111111p-4, 0x1.e1e1e1e1e1e1ep-5, 0x1.af286bca1af28p-5};  // 1/(2n+1)
+  double q = c[9];
+#pragma unroll
+  for (int i = 8; i >= 0; --i) q = fma(q, u2, c[i]);
+  const double ed = static_cast<double>(e);
+  return fma(ed, kLn2Hi, fma(ed, kLn2Lo, 2.0 * u * q));
+}
+
+// bs_price_fast with the exponential and logarithm above (inputs there are
+// finite: S > 0 is a normal float, the exponent is -d^2/2 <= 0).
+__device__ __forceinline__ double bs_price_own(double s, const BsConst& k) {
+  const double d1 = (log_pos(s * k.inv_strike) + k.mu_t) * k.inv_vol_t;
+  const double d2 = d1 - k.vol_t;
+  const double e1 = exp_nonpos(-0.5 * d1 * d1);
+  double e2 = e1 * s * k.growth;
+  if (e1 == 0.0) e2 = exp_nonpos(-0.5 * d2 * d2);
+  const double h1 = 0.5 * e1 * erfcx_pos(fabs(d1) * M_SQRT1_2);
+  const double h2 = 0.5 * e2 * erfcx_pos(fabs(d2) * M_SQRT1_2);
+  const double n1 = d1 < 0.0 ? h1 : 1.0 - h1;
+  const double n2 = d2 < 0.0 ? h2 : 1.0 - h2;
+  return s * n1 - k.disc_strike * n2;
+}
+
+// variant 0: the library's erfc; 1: bs_price_fast; 2: bs_price_own.
 template <int V>
 __device__ __forceinline__ float bs_one(float s, const BsConst& k) {
   if constexpr (V == 0) {
     return static_cast<float>(bs_price(s, k.strike, k.mu_t, k.vol_t, k.disc_strike));
-  } else {
+  } else if constexpr (V == 1) {
     return static_cast<float>(bs_price_fast(s, k));
+  } else {
+    return static_cast<float>(bs_price_own(s, k));
   }
 }
 
@@ -906,7 +973,8 @@ const char* cfg_block_any(const LaunchCfg& c) {
 }
 const char* cfg_bs(const LaunchCfg& c) {
   if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
-  if (c.variant > 1) return "variant: 0 = library erfc, 1 = one exponential and one polynomial per CDF";
+  if (c.variant > 2)
+    return "variant: 0 = library erfc, 1 = one exponential and one polynomial per CDF, 2 = 1 with own log/exp";
   return nullptr;
 }
 const char* cfg_reduce(const LaunchCfg& c) {
@@ -1015,6 +1083,9 @@ hipError_t l_bs(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c
   const dim3 grid(stream_grid(vec ? ceil_div(q->n, 4) : q->n, c));
   if (c.variant == 1) {
     DAGRT_LAUNCH(k_bs_call<1>, grid, dim3(c.block), 0, s, static_cast<const float*>(a[0]),
+                 static_cast<float*>(a[1]), q->n, vec, k);
+  } else if (c.variant == 2) {
+    DAGRT_LAUNCH(k_bs_call<2>, grid, dim3(c.block), 0, s, static_cast<const float*>(a[0]),
                  static_cast<float*>(a[1]), q->n, vec, k);
   } else {
     DAGRT_LAUNCH(k_bs_call<0>, grid, dim3(c.block), 0, s, static_cast<const float*>(a[0]),

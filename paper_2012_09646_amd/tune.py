@@ -37,7 +37,7 @@ def candidates(kernel):
     if kernel in ("vec_square", "normalise", "unsharp_combine", "scale_l2", "copy_f32"):
         return [(b, c, 0) for b in BLOCKS for c in CAPS]
     if kernel == "bs_call":
-        return [(b, c, v) for b in BLOCKS for c in CAPS for v in (0, 1)]
+        return [(b, c, v) for b in BLOCKS for c in CAPS for v in (0, 1, 2)]
     if kernel in ("vec_sum_diff", "minmax", "sumsq"):
         return [(b, c, v) for b in (256, 512, 1024) for c in (64, 128, 256, 512, 1024, 2048) for v in (0, 1)]
     if kernel == "spmv":

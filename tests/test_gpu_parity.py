@@ -91,7 +91,7 @@ def test_region_replays_copy_kernel(graph_mode):
         ctx.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("r,sigma,years", [(0.08, 0.3, 1.0), (0.0, 1.5, 4.0), (0.2, 0.05, 0.1), (0.03, 3.0, 30.0)])
 def test_bs_variants_wide_range(variant, r, sigma, years):
     """Both call-price variants against the oracle over spot prices from deep
