@@ -37,9 +37,9 @@ FP64_PEAK_TFLOPS = 78.6   # vector fp64: 256 CUs x 128 flop/clk (4 SIMDs x 16 la
 # (all kinds) per variant:
 BS_FLOPS_PER_ELEMENT = 2 * 86 + 5 + 19 + 3
 BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25, 2: 156.25}
-# HBM bytes per bs_call launch from FETCH_SIZE / WRITE_SIZE, each divided by what the counter reads for a
-# 256 MiB copy kernel (FETCH_SIZE 0.50005x, WRITE_SIZE 1.000x of the true bytes): 16.16 MiB in + 16.00 MiB out
-TRAFFIC_BS_BYTES = int((8276.19 / 0.50005 + 16384.0 / 1.0) * 1024)
+# HBM bytes per bs_call launch (variant 2) from FETCH_SIZE / WRITE_SIZE, each divided by what the counter reads
+# for a 256 MiB copy kernel (FETCH_SIZE 0.50006x, WRITE_SIZE 1.000x of the true bytes): 16.14 MiB in + 16.00 MiB out
+TRAFFIC_BS_BYTES = int((8262.91 / 0.50006 + 16384.0 / 1.0) * 1024)
 CUS, CLOCK_GHZ = 256, 2.4
 
 
