@@ -193,3 +193,64 @@ def hits(a_ptr, a_col, a_val, at_ptr, at_col, at_val, iters):
         auth = scale_l2(at, sumsq(at))
         hub = scale_l2(ht, sumsq(ht))
     return auth, hub
+
+
+# --------------------------------------------------------------------------
+# ML ensemble (Sec. V-B, "Machine Learning Ensemble"): a categorical naive
+# Bayes classifier and a ridge classifier on standardised features score the
+# same input rows; each row of scores is softmax-normalised, the two
+# probability rows are averaged and the class with the largest average is
+# the prediction.  X is an (n, F) float32 matrix whose entries are category
+# codes 0..V-1 (read as integers by naive Bayes, as numbers by ridge).
+# --------------------------------------------------------------------------
+def softmax_rows(S):
+    """P[r, c] = exp(S[r, c] - m_r) / sum_c' exp(S[r, c'] - m_r) with
+    m_r = max_c S[r, c] (the shift leaves P unchanged and keeps exp finite);
+    float64 in, float64 out."""
+    S = np.asarray(S, dtype=F64)
+    E = np.exp(S - S.max(axis=1, keepdims=True))
+    return E / E.sum(axis=1, keepdims=True)
+
+
+def nb_log_joint(X, log_theta, log_prior):
+    """Joint log-likelihood of categorical naive Bayes, float64:
+    J[r, c] = log pi_c + sum_f log theta[c, f, X[r, f]].
+
+    log_theta has shape (C, F, V): log P(feature f = v | class c);
+    log_prior has shape (C,): log P(class c)."""
+    codes = np.asarray(X, dtype=F32).astype(np.int64)
+    lt = np.asarray(log_theta, dtype=F32).astype(F64)
+    C, F, _ = lt.shape
+    J = np.tile(np.asarray(log_prior, dtype=F32).astype(F64), (codes.shape[0], 1))
+    for f in range(F):
+        J += lt[:, f, codes[:, f]].T
+    return J
+
+
+def nb_predict_proba(X, log_theta, log_prior):
+    """Class posteriors of categorical naive Bayes: softmax of the joint
+    log-likelihood over classes, rounded to float32, shape (n, C)."""
+    return softmax_rows(nb_log_joint(X, log_theta, log_prior)).astype(F32)
+
+
+def ridge_scores(X, mean, scale, W, b):
+    """Decision scores of a linear (ridge) classifier on standardised
+    features, float64: S = ((X - mean) / scale) W^T + b, W of shape (C, F)."""
+    Z = (np.asarray(X, dtype=F32).astype(F64) - np.asarray(mean, dtype=F32).astype(F64)) \
+        / np.asarray(scale, dtype=F32).astype(F64)
+    return Z @ np.asarray(W, dtype=F32).astype(F64).T + np.asarray(b, dtype=F32).astype(F64)
+
+
+def ridge_predict_proba(X, mean, scale, W, b):
+    """Softmax of the ridge scores over classes, rounded to float32."""
+    return softmax_rows(ridge_scores(X, mean, scale, W, b)).astype(F32)
+
+
+def ensemble_argmax(p_nb, p_rr):
+    """Average of the two probability rows and the predicted class.
+
+    avg = (p_nb + p_rr) / 2 is exact in float64 for float32 inputs; the label
+    is the first index of the largest float64 average (lowest class index on
+    ties), the average is returned rounded to float32."""
+    avg = (np.asarray(p_nb, dtype=F32).astype(F64) + np.asarray(p_rr, dtype=F32).astype(F64)) / 2.0
+    return avg.astype(F32), np.argmax(avg, axis=1).astype(np.int32)

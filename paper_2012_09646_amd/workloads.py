@@ -239,6 +239,57 @@ def hits_program(n=1 << 20, deg=20, iters=10, seed=3, graph=None):
     return Program("hits", bufs, ops, ["a", "h", "at", "ht", "sa", "sh"], "a")
 
 
+ML_FEATURES, ML_CLASSES, ML_CATEGORIES = 200, 10, 16
+
+
+def ml_inputs(seed, n, features=ML_FEATURES, classes=ML_CLASSES, categories=ML_CATEGORIES):
+    """Synthetic data and random-initialised model parameters of the ML
+    ensemble (nothing is trained; the paper uses random data):
+
+    X          (n, F) float32 category codes, uniform over 0..V-1
+    log_theta  (C, F, V) float32 log P(feature f = v | class c): each
+               (c, f) row is a random distribution with weights U[0.5, 1)
+    log_prior  (C,) float32 log class priors, weights U[0.5, 1)
+    mean, scale (F,) float32 standardisation of the ridge branch, near the
+               mean and standard deviation of a uniform code
+    W          (C, F) float32 ridge coefficients U[-0.25, 0.25)
+    b          (C,) float32 ridge intercepts U[-0.1, 0.1)
+    """
+    g = np.random.Generator(np.random.Philox(key=int(seed)))
+    F, C, V = int(features), int(classes), int(categories)
+    X = g.integers(0, V, size=(int(n), F)).astype(F32)
+    wt = g.uniform(0.5, 1.0, size=(C, F, V))
+    log_theta = np.log(wt / wt.sum(axis=2, keepdims=True)).astype(F32)
+    wp = g.uniform(0.5, 1.0, size=C)
+    log_prior = np.log(wp / wp.sum()).astype(F32)
+    mu = (V - 1) / 2.0
+    sd = np.sqrt((V * V - 1) / 12.0)
+    mean = (mu + g.uniform(-0.5, 0.5, size=F)).astype(F32)
+    scale = (sd * g.uniform(0.9, 1.1, size=F)).astype(F32)
+    W = g.uniform(-0.25, 0.25, size=(C, F)).astype(F32)
+    b = g.uniform(-0.1, 0.1, size=C).astype(F32)
+    return dict(X=X, log_theta=log_theta, log_prior=log_prior, mean=mean, scale=scale, W=W, b=b)
+
+
+def ml_program(n=1 << 20, seed=5, features=ML_FEATURES, classes=ML_CLASSES, categories=ML_CATEGORIES):
+    """ML ensemble: naive Bayes posteriors and ridge posteriors of the same
+    rows (independent branches sharing the read-only X), then their average
+    and argmax; host reads the labels."""
+    d = ml_inputs(seed, n, features, classes, categories)
+    C = int(classes)
+    bufs = {k: Buf(v.nbytes, init=v) for k, v in d.items()}
+    for name in ("Pnb", "Prr", "Pavg"):
+        bufs[name] = Buf(4 * int(n) * C)
+    bufs["label"] = Buf(4 * int(n))
+    sz = dict(n=int(n), features=int(features), classes=C, categories=int(categories))
+    ops = [K("nb_proba", [("X", "c"), ("log_theta", "c"), ("log_prior", "c"), ("Pnb", "m")], **sz),
+           K("ridge_proba", [("X", "c"), ("mean", "c"), ("scale", "c"), ("W", "c"), ("b", "c"), ("Prr", "m")],
+             **sz),
+           K("ensemble", [("Pnb", "c"), ("Prr", "c"), ("Pavg", "m"), ("label", "m")], **sz),
+           HR("label")]
+    return Program("ml", bufs, ops, ["Pnb", "Prr", "Pavg", "label"], "label")
+
+
 def initial_arrays(prog):
     """Fresh numpy arrays (uint8 views over the initial contents) for a program."""
     out = {}

@@ -229,3 +229,122 @@ def test_program_executor_copies():
         S = prog.bufs["S%d" % i].init
         ref = T.bs_call(S, W.BS_K, W.BS_R, W.BS_SIGMA, W.BS_T)
         assert np.array_equal(bufs["C%d" % i].view(np.float32), ref)
+
+
+# --------------------------------------------------------------------------
+# ML ensemble
+# --------------------------------------------------------------------------
+def test_softmax_rows_against_scipy_and_invariants():
+    from scipy import special
+    g = np.random.default_rng(7)
+    S = g.normal(size=(50, 10)) * 5 - 560.0          # naive-Bayes-like magnitudes
+    P = T.softmax_rows(S)
+    assert np.allclose(P, special.softmax(S, axis=1), rtol=1e-13, atol=0)
+    assert np.allclose(P.sum(axis=1), 1.0, rtol=0, atol=1e-15 * 10)
+    assert np.allclose(T.softmax_rows(S + 123.25), P, rtol=1e-12, atol=0)   # shift invariance
+    assert np.array_equal(T.softmax_rows(np.full((3, 4), -7.0)), np.full((3, 4), 0.25))
+    # two classes: the logistic function of the score difference
+    d = g.normal(size=20)
+    two = T.softmax_rows(np.stack([d, np.zeros(20)], axis=1))
+    assert np.allclose(two[:, 0], 1.0 / (1.0 + np.exp(-d)), rtol=1e-14, atol=0)
+
+
+def _fitted_categorical_nb(F, V, C, seed):
+    """A categorical naive Bayes model fitted by scikit-learn on random data,
+    its parameters rounded to float32 (the in-memory type of the workload)
+    and written back so that both sides use identical values."""
+    from sklearn.naive_bayes import CategoricalNB
+    g = np.random.default_rng(seed)
+    Xtr = g.integers(0, V, size=(400, F))
+    Xtr[:V, :] = np.arange(V)[:, None]               # every category seen
+    ytr = g.integers(0, C, size=400)
+    ytr[:C] = np.arange(C)
+    m = CategoricalNB(alpha=1.0).fit(Xtr, ytr)
+    lt = np.stack([m.feature_log_prob_[f] for f in range(F)], axis=1).astype(np.float32)   # (C, F, V)
+    lp = m.class_log_prior_.astype(np.float32)
+    m.feature_log_prob_ = [lt[:, f, :].astype(np.float64) for f in range(F)]
+    m.class_log_prior_ = lp.astype(np.float64)
+    return m, lt, lp
+
+
+def test_nb_posteriors_match_scikit_learn_categorical_nb():
+    F, V, C = 12, 5, 4
+    m, lt, lp = _fitted_categorical_nb(F, V, C, 3)
+    Xte = np.random.default_rng(4).integers(0, V, size=(300, F))
+    ref = m.predict_proba(Xte)
+    got = T.nb_predict_proba(Xte.astype(np.float32), lt, lp)
+    assert np.allclose(got, ref.astype(np.float32), rtol=2e-7, atol=0)
+    J = T.nb_log_joint(Xte.astype(np.float32), lt, lp)
+    assert np.array_equal(np.argmax(J, axis=1), m.predict(Xte))
+
+
+def test_nb_posteriors_by_brute_force_products():
+    """P(c | x) = pi_c prod_f theta[c, f, x_f] / sum over classes, with the
+    probabilities themselves (no logarithms), in pure Python."""
+    d = W.ml_inputs(21, 7, features=6, classes=3, categories=4)
+    got = T.nb_predict_proba(d["X"], d["log_theta"], d["log_prior"])
+    for r in range(7):
+        joint = []
+        for c in range(3):
+            p = math.exp(float(d["log_prior"][c]))
+            for f in range(6):
+                p *= math.exp(float(d["log_theta"][c, f, int(d["X"][r, f])]))
+            joint.append(p)
+        tot = sum(joint)
+        for c in range(3):
+            assert abs(float(got[r, c]) - joint[c] / tot) <= 1e-6 * joint[c] / tot
+
+
+def test_ridge_scores_match_scikit_learn_pipeline():
+    from sklearn.linear_model import RidgeClassifier
+    from sklearn.pipeline import make_pipeline
+    from sklearn.preprocessing import StandardScaler
+    g = np.random.default_rng(5)
+    F, C = 15, 4
+    Xtr = g.integers(0, 16, size=(500, F)).astype(np.float64)
+    ytr = g.integers(0, C, size=500)
+    pipe = make_pipeline(StandardScaler(), RidgeClassifier(alpha=1.0)).fit(Xtr, ytr)
+    sc, clf = pipe[0], pipe[1]
+    mean, scale = sc.mean_.astype(np.float32), sc.scale_.astype(np.float32)
+    Wc, b = clf.coef_.astype(np.float32), clf.intercept_.astype(np.float32)
+    sc.mean_, sc.scale_ = mean.astype(np.float64), scale.astype(np.float64)
+    clf.coef_, clf.intercept_ = Wc.astype(np.float64), b.astype(np.float64)
+    Xte = g.integers(0, 16, size=(200, F)).astype(np.float32)
+    ref = pipe.decision_function(Xte.astype(np.float64))
+    got = T.ridge_scores(Xte, mean, scale, Wc, b)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+    assert np.array_equal(np.argmax(got, axis=1), pipe.predict(Xte))
+    # a zero coefficient matrix gives the softmax of the intercepts in every row
+    P0 = T.ridge_predict_proba(Xte, mean, scale, np.zeros_like(Wc), b)
+    e = np.exp(b.astype(np.float64) - b.max())
+    assert np.allclose(P0, (e / e.sum()).astype(np.float32)[None, :], rtol=1e-7, atol=0)
+
+
+def test_ensemble_average_and_lowest_index_ties():
+    p_nb = np.float32([[0.25, 0.75, 0.0], [0.5, 0.25, 0.25], [0.2, 0.3, 0.5]])
+    p_rr = np.float32([[0.75, 0.25, 0.0], [0.0, 0.25, 0.75], [0.6, 0.3, 0.1]])
+    avg, lab = T.ensemble_argmax(p_nb, p_rr)
+    assert np.array_equal(avg, np.float32([[0.5, 0.5, 0.0], [0.25, 0.25, 0.5], [0.4, 0.3, 0.3]]))
+    assert lab.tolist() == [0, 2, 0]                 # row 0: tie between 0 and 1 -> 0
+    # the decision is taken on the exact float64 average, not on its float32 rounding
+    a = np.float32(1.0) - np.float32(2.0 ** -24)     # largest float32 below 1
+    nb = np.float32([[a, np.float32(1.0)]])
+    rr = np.float32([[np.float32(1.0), a]])
+    avg, lab = T.ensemble_argmax(nb, rr)
+    assert lab[0] == 0 and avg[0, 0] == avg[0, 1]
+    nb2 = np.float32([[a, 1.0]])
+    rr2 = np.float32([[a, 1.0]])
+    assert T.ensemble_argmax(nb2, rr2)[1][0] == 1
+
+
+def test_ml_program_runs_in_program_order():
+    prog = W.ml_program(n=257, seed=5, features=20, classes=10, categories=16)
+    arrays = W.initial_arrays(prog)
+    orun.execute(prog.ops, arrays)
+    d = W.ml_inputs(5, 257, 20, 10, 16)
+    pnb = T.nb_predict_proba(d["X"], d["log_theta"], d["log_prior"])
+    prr = T.ridge_predict_proba(d["X"], d["mean"], d["scale"], d["W"], d["b"])
+    avg, lab = T.ensemble_argmax(pnb, prr)
+    assert np.array_equal(arrays["Pnb"].view(np.float32).reshape(257, 10), pnb)
+    assert np.array_equal(arrays["label"].view(np.int32), lab)
+    assert np.allclose(arrays["Pavg"].view(np.float32).reshape(257, 10).sum(axis=1), 1.0, atol=1e-6)
