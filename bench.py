@@ -52,15 +52,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "serve"])
+    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "ml", "serve"])
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
-    ap.add_argument("--serve-lanes", type=int, default=2,
-                    help="serving: kernel lanes (HIP streams) requests spread over; 2 measured best at 4 and 8 queues")
+    ap.add_argument("--serve-lanes", type=int, default=3,
+                    help="serving: lanes (HIP streams) requests spread over")
     ap.add_argument("--serve-copy-engine", type=int, default=0, choices=[-1, 0, 1, 2, 3],
                     help="serving: copy engine (as --copy-engine; -1 = the same as the DAGs); SDMA measured "
                          "best for the mix in a process of its own")
     ap.add_argument("--serve-copy-lanes", type=int, default=1, choices=[0, 1, 2, 3, 4],
                     help="serving: N = host<->device copies of all requests on N streams per direction")
+    ap.add_argument("--serve-transfer-lanes", type=int, default=1,
+                    help="serving: N >= 1 = requests that copy between host and device use the first N lanes "
+                         "only, all others the remaining lanes (0 = any lane); 3 lanes with 1 for transfers "
+                         "sustained the 2000/s mix (p50 1.7 ms) where 2 shared lanes saturated at ~1890/s")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
     ap.add_argument("--low-rate", type=float, default=600.0,
                     help="serving: a second, lower arrival rate (half the requests; 0 = skip)")
@@ -96,11 +100,12 @@ def orchestrate(args):
            "--copy-lanes", str(args.copy_lanes), "--copy-engine", str(args.copy_engine),
            "--spin-wait", str(args.spin_wait), "--requests", str(args.requests), "--rate", str(args.rate),
            "--low-rate", str(args.low_rate), "--serve-lanes", str(args.serve_lanes),
-           "--serve-copy-lanes", str(args.serve_copy_lanes), "--serve-copy-engine", str(args.serve_copy_engine)]
+           "--serve-copy-lanes", str(args.serve_copy_lanes), "--serve-copy-engine", str(args.serve_copy_engine),
+           "--serve-transfer-lanes", str(args.serve_transfer_lanes)]
     if args.hw_queues:
         fwd += ["--hw-queues", str(args.hw_queues)]
     lines = {}
-    for wl in ("bs", "vec", "img", "hits", "serve"):
+    for wl in ("bs", "vec", "img", "hits", "ml", "serve"):
         extra = [] if wl == "bs" and not args.no_cpu_baseline else ["--no-cpu-baseline"]
         log("child process: --workload %s" % wl)
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", wl] + fwd + extra,
@@ -110,7 +115,7 @@ def orchestrate(args):
             sys.exit(r.returncode)
         lines[wl] = json.loads(r.stdout.strip().splitlines()[-1])
     line = lines["bs"]
-    for wl in ("vec", "img", "hits"):
+    for wl in ("vec", "img", "hits", "ml"):
         line["workloads"][wl] = lines[wl]["workloads"][wl]
     line["serving"] = lines["serve"]["serving"]
     line["config"]["processes"] = "one per workload"
@@ -406,7 +411,7 @@ def main():
                 key += 1
         budget = 64 << 30
         srv = serving.Server(ctx, budget, host_arena_bytes=8 << 30, lanes=args.serve_lanes, bypass=32,
-                             copy_lanes=args.serve_copy_lanes)
+                             copy_lanes=args.serve_copy_lanes, transfer_lanes=args.serve_transfer_lanes)
         foot = []
         for t in tmpls:
             sid = srv.add(t)
@@ -430,7 +435,7 @@ def main():
 
         out = one_rate(args.rate, args.requests)
         out.update({"shapes": len(tmpls), "budget_bytes": budget, "lanes": args.serve_lanes,
-                    "copy_lanes": args.serve_copy_lanes,
+                    "copy_lanes": args.serve_copy_lanes, "transfer_lanes": args.serve_transfer_lanes,
                     "copy_engine": args.copy_engine if args.serve_copy_engine < 0 else args.serve_copy_engine})
         # a second, lower arrival rate at which the serial baseline is not overloaded
         if args.low_rate:
@@ -439,7 +444,7 @@ def main():
         ctx.close()
         return out
 
-    workloads = ["bs", "vec", "img", "hits", "serve"] if args.workload == "all" else [args.workload]
+    workloads = ["bs", "vec", "img", "hits", "ml", "serve"] if args.workload == "all" else [args.workload]
     results = {}
     graphs = {}
     kt_bs = None
@@ -458,6 +463,9 @@ def main():
             log("hits: generating the graph")
             prog = W.hits_program(n=1 << 20, deg=20, iters=10, seed=3)
             results[wl], _ = measure(wl, prog, args.steps, args.warmup, restore=("a", "h"), per_iter=6)
+        elif wl == "ml":
+            prog = W.ml_program(n=1 << 20, seed=5)
+            results[wl], _ = measure(wl, prog, args.steps, args.warmup)
         elif wl == "serve":
             results[wl] = measure_serving(graphs)
 

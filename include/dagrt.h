@@ -253,6 +253,20 @@ dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
 #define DAG_K_SCALE_L2 12u       /* t:c s:c v:m         v_i = t_i / sqrt(s) */
 #define DAG_K_SPIN 13u           /* (any args)          busy-wait, no data */
 #define DAG_K_COPY_F32 14u       /* src:c dst:m         dst_i = src_i */
+/* ML ensemble (Sec. V-B): X is n x F row-major fp32 holding category codes
+ * 0..V-1; P* are n x C row-major fp32 probabilities. */
+#define DAG_K_NB_PROBA 15u       /* X lt lp:c P:m       categorical naive Bayes:
+                                    P[r] = softmax_c(lp[c] + sum_f lt[c][f][X[r][f]]),
+                                    lt = log P(x_f = v | c) as C x F x V,
+                                    lp = log P(c); codes are truncated and
+                                    clamped to [0, V-1]; C*F*V <= 32768 */
+#define DAG_K_RIDGE_PROBA 16u    /* X mean scale W b:c P:m  ridge classifier:
+                                    P[r] = softmax_c(sum_f (X[r][f] - mean_f) /
+                                    scale_f * W[c][f] + b[c]), W is C x F;
+                                    F*(C+1) <= 8192 */
+#define DAG_K_ENSEMBLE 17u       /* Pnb Prr:c avg:m label:m  avg = (Pnb + Prr)/2,
+                                    label[r] (int32) = first index of the
+                                    largest average (lowest class on ties) */
 #define DAG_K_USER_BASE 1000u    /* ids of dag_kernel_register */
 
 /* Parameter blocks (passed by pointer + size to dag_submit_kernel). */
@@ -279,6 +293,13 @@ typedef struct {
                             so that malformed input cannot fault) */
 } dag_p_csr;
 typedef struct { uint64_t ns; } dag_p_spin; /* delay in ns (<= 1 s) */
+typedef struct {
+  uint64_t n;          /* rows */
+  uint32_t features;   /* F >= 1 */
+  uint32_t classes;    /* C, 1..16 */
+  uint32_t categories; /* V >= 1 (naive Bayes codes; unused by the others) */
+  uint32_t reserved;   /* 0 */
+} dag_p_ml;            /* NB_PROBA, RIDGE_PROBA, ENSEMBLE */
 
 /* Launch configuration of a built-in kernel (used by the autotuner). */
 typedef struct {
@@ -422,7 +443,8 @@ dag_status dag_stream_handle(dag_ctx ctx, uint32_t i, void** stream);
  * arenas the server keeps resident (device arena for device buffers, pinned
  * host arena for pinned ones and for staging device results), replays the
  * shape's calls in recorded order on one of `lanes` HIP streams (the lane
- * with the fewest requests in flight), and is retired when its completion
+ * with the fewest requests in flight among those its class may use, see
+ * transfer_lanes), and is retired when its completion
  * event fires, which frees its memory for queued requests.  Requests in
  * flight on different lanes run concurrently (space-sharing, Sec. IV-B/C
  * applied across independent requests).  Requests are queued FIFO; up to
@@ -461,7 +483,13 @@ typedef struct {
                                   on the request's lane, with event waits on
                                   the request's own recorded dependencies);
                                   0 = a request runs wholly on its lane */
-  uint32_t reserved;
+  uint32_t transfer_lanes;     /* concurrent mode: N >= 1 = requests whose
+                                  shape copies between host and device use
+                                  lanes 0..N-1 only and all other requests
+                                  lanes N..lanes-1 only (lanes > N), so that
+                                  requests bound by the host link never hold
+                                  up compute-bound ones queued on the same
+                                  lane; 0 = any request may use any lane */
 } dag_serve_config;
 
 typedef struct {

@@ -108,7 +108,7 @@ struct dag_ctx_s {
   std::vector<uint64_t> tmp_wait, tmp_retired;
   std::vector<dagrt::Access> tmp_acc;
   std::vector<dagrt::UserKernel> user_kernels;
-  dagrt::LaunchCfg launch_cfg[15]{};
+  dagrt::LaunchCfg launch_cfg[dagrt::kNumBuiltin]{};  // indexed by built-in kernel id
   // regions
   std::unordered_map<uint64_t, std::unique_ptr<dagrt::Region>> regions;
   bool recording = false;

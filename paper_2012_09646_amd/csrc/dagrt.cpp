@@ -768,7 +768,7 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   x->serial = c.policy == DAG_SERIAL_SYNC;
   x->dry = c.dry_run != 0;
   if (const char* f = std::getenv("DAGRT_FAULT_LAUNCH")) x->fault_at = std::strtoull(f, nullptr, 10);
-  for (uint32_t k = 0; k < 15; ++k) {
+  for (uint32_t k = 0; k < kNumBuiltin; ++k) {
     const KernelDesc* kd = builtin_kernel(k);
     if (kd) x->launch_cfg[k] = kd->def;
   }

@@ -1,14 +1,18 @@
 // Task kernels of the benchmark workloads, written for gfx950 (CDNA4):
 // wave64, fp32 data in HBM, fp64 arithmetic in registers, one rounding to
-// fp32 on store.  None of them is a dense contraction, so none uses MFMA:
-// they are HBM-bound (coalesced float4 streams, LDS-tiled stencils, a
-// merge-path CSR SpMV) and keep every reduction deterministic (fixed
-// combination order, no floating-point atomics).
+// fp32 on store.  They are HBM-bound (coalesced float4 streams, LDS-tiled
+// stencils, a merge-path CSR SpMV) and keep every reduction deterministic
+// (fixed combination order, no floating-point atomics).  The one dense
+// contraction, the ridge classifier's X W^T with C <= 16 classes, uses
+// fp64 FMAs on the vector ALUs rather than MFMA: at C = 10 it does 5 flops
+// per byte of X (below the fp64 ridge point of ~10 flops/byte), gfx950's
+// fp64 MFMA peak is no higher than its fp64 vector peak, and a 16-wide MFMA
+// tile would waste 6 of 16 columns.
 //
 // Benchmarks (paper Sec. V-B): VEC sums the difference of two squared
 // vectors; B&S prices European calls in double precision; IMG combines a
 // sharpened image with blurred copies; HITS repeats SpMV with a matrix and
-// its transpose.
+// its transpose; ML averages the posteriors of two classifiers.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -923,6 +927,186 @@ __global__ __launch_bounds__(1024) void k_scale_l2(const float* __restrict__ t,
 }
 
 // ---------------------------------------------------------------------------
+// ML ensemble (Sec. V-B): categorical naive Bayes and a ridge classifier
+// score the same rows of X (n x F row-major fp32 category codes); each row of
+// C scores becomes probabilities by a softmax; the two probability rows are
+// averaged and reduced to the index of the largest average.
+//
+// One thread per row.  A lane reads its own row 16 features (64 bytes) at a
+// time, four 16-byte loads in flight, so the cache lines one load brings in
+// are consumed by the same lane's next loads.  The per-class model data sit
+// in LDS in feature-major order, so the C values one feature contributes are
+// adjacent.
+// ---------------------------------------------------------------------------
+constexpr int kMlMaxClasses = 16;
+constexpr int kMlBatch = 4;                // 16-byte loads in flight per lane
+constexpr uint32_t kNbTable = 32768;       // C*F*V fp32 entries of the naive Bayes table (128 KB)
+constexpr uint32_t kRidgeLdsBytes = 65536; // F*(C+1) fp64: weights / scale, then means
+
+// P = softmax(s) rounded to fp32: the largest score is subtracted before exp.
+template <int C>
+__device__ __forceinline__ void softmax_store(double (&s)[C], float* __restrict__ out) {
+  double m = s[0];
+#pragma unroll
+  for (int c = 1; c < C; ++c) m = fmax(m, s[c]);
+  double tot = 0.0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    s[c] = exp(s[c] - m);
+    tot += s[c];
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) out[c] = static_cast<float>(s[c] / tot);
+}
+
+// acc[c] += log theta[c][f][code(x)] for one feature; t points at feature f's
+// block of the LDS table ([v][c], C values per code).  Codes are truncated and
+// clamped to [0, V-1] so that no input can address outside the table.
+template <int C>
+__device__ __forceinline__ void nb_add(double (&acc)[C], const float* __restrict__ t, float vmax, float x) {
+  const int v = static_cast<int>(fminf(fmaxf(x, 0.0f), vmax));
+  const float* e = t + v * C;
+  if constexpr (C % 2 == 0) {
+#pragma unroll
+    for (int c = 0; c < C; c += 2) {
+      const float2 p = *reinterpret_cast<const float2*>(e + c);
+      acc[c] += static_cast<double>(p.x);
+      acc[c + 1] += static_cast<double>(p.y);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += static_cast<double>(e[c]);
+  }
+}
+
+template <int C>
+__global__ __launch_bounds__(1024) void k_nb_proba(const float* __restrict__ X, const float* __restrict__ lt,
+                                                   const float* __restrict__ lp, float* __restrict__ P,
+                                                   uint64_t n, uint32_t F, uint32_t V, int vec) {
+  __shared__ __align__(16) float s_tab[kNbTable];  // [f][v][c]
+  const uint32_t fv_n = F * V;
+  for (uint32_t i = threadIdx.x; i < C * fv_n; i += blockDim.x) {
+    const uint32_t c = i / fv_n;
+    s_tab[(i - c * fv_n) * C + c] = lt[i];  // lt is [c][f][v]
+  }
+  __syncthreads();
+  double prior[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) prior[c] = static_cast<double>(lp[c]);
+  const float vmax = static_cast<float>(V - 1);
+  const uint32_t tstride = V * C;  // table floats per feature
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < n; r += stride) {
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = prior[c];
+    const float* row = X + r * F;
+    if (vec) {
+      for (uint32_t f0 = 0; f0 < F; f0 += 4 * kMlBatch) {
+        const uint32_t nq = min(static_cast<uint32_t>(kMlBatch), (F - f0) / 4);
+        float4 q[kMlBatch];
+#pragma unroll
+        for (int j = 0; j < kMlBatch; ++j)
+          if (j < static_cast<int>(nq)) q[j] = reinterpret_cast<const float4*>(row + f0)[j];
+#pragma unroll
+        for (int j = 0; j < kMlBatch; ++j) {
+          if (j < static_cast<int>(nq)) {
+            const float* t = s_tab + (f0 + 4 * j) * tstride;
+            nb_add<C>(acc, t, vmax, q[j].x);
+            nb_add<C>(acc, t + tstride, vmax, q[j].y);
+            nb_add<C>(acc, t + 2 * tstride, vmax, q[j].z);
+            nb_add<C>(acc, t + 3 * tstride, vmax, q[j].w);
+          }
+        }
+      }
+    } else {
+      for (uint32_t f = 0; f < F; ++f) nb_add<C>(acc, s_tab + f * tstride, vmax, row[f]);
+    }
+    softmax_store<C>(acc, P + r * C);
+  }
+}
+
+// acc[c] += (x - mean_f) * (W[c][f] / scale_f) for one feature (w = that
+// feature's C weights in LDS).
+template <int C>
+__device__ __forceinline__ void ridge_add(double (&acc)[C], const double* __restrict__ w, double d) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = fma(d, w[c], acc[c]);
+}
+
+template <int C>
+__global__ __launch_bounds__(1024) void k_ridge_proba(const float* __restrict__ X, const float* __restrict__ mean,
+                                                      const float* __restrict__ scale, const float* __restrict__ W,
+                                                      const float* __restrict__ b, float* __restrict__ P,
+                                                      uint64_t n, uint32_t F, int vec) {
+  extern __shared__ __align__(16) double s_w[];  // [f][c] weights / scale, then F means
+  double* s_mu = s_w + F * C;
+  for (uint32_t i = threadIdx.x; i < C * F; i += blockDim.x) {
+    const uint32_t c = i / F, f = i - c * F;  // W is [c][f]
+    s_w[f * C + c] = static_cast<double>(W[i]) / static_cast<double>(scale[f]);
+  }
+  for (uint32_t f = threadIdx.x; f < F; f += blockDim.x) s_mu[f] = static_cast<double>(mean[f]);
+  __syncthreads();
+  double bias[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) bias[c] = static_cast<double>(b[c]);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < n; r += stride) {
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = bias[c];
+    const float* row = X + r * F;
+    if (vec) {
+      for (uint32_t f0 = 0; f0 < F; f0 += 4 * kMlBatch) {
+        const uint32_t nq = min(static_cast<uint32_t>(kMlBatch), (F - f0) / 4);
+        float4 q[kMlBatch];
+#pragma unroll
+        for (int j = 0; j < kMlBatch; ++j)
+          if (j < static_cast<int>(nq)) q[j] = reinterpret_cast<const float4*>(row + f0)[j];
+#pragma unroll
+        for (int j = 0; j < kMlBatch; ++j) {
+          if (j < static_cast<int>(nq)) {
+            const uint32_t f = f0 + 4 * j;
+            ridge_add<C>(acc, s_w + f * C, static_cast<double>(q[j].x) - s_mu[f]);
+            ridge_add<C>(acc, s_w + (f + 1) * C, static_cast<double>(q[j].y) - s_mu[f + 1]);
+            ridge_add<C>(acc, s_w + (f + 2) * C, static_cast<double>(q[j].z) - s_mu[f + 2]);
+            ridge_add<C>(acc, s_w + (f + 3) * C, static_cast<double>(q[j].w) - s_mu[f + 3]);
+          }
+        }
+      }
+    } else {
+      for (uint32_t f = 0; f < F; ++f) ridge_add<C>(acc, s_w + f * C, static_cast<double>(row[f]) - s_mu[f]);
+    }
+    softmax_store<C>(acc, P + r * C);
+  }
+}
+
+// avg = (a + b) / 2, exact in fp64, stored rounded to fp32; label = first
+// index of the largest fp64 average (lowest class on ties).
+template <int C>
+__global__ __launch_bounds__(1024) void k_ensemble(const float* __restrict__ pa, const float* __restrict__ pb,
+                                                   float* __restrict__ avg, int* __restrict__ label, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < n; r += stride) {
+    const float* a = pa + r * C;
+    const float* b = pb + r * C;
+    float* o = avg + r * C;
+    double best = -INFINITY;
+    int arg = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const double m = (static_cast<double>(a[c]) + static_cast<double>(b[c])) * 0.5;
+      o[c] = static_cast<float>(m);
+      if (m > best) {
+        best = m;
+        arg = c;
+      }
+    }
+    label[r] = arg;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Utilities: a delay kernel for scheduler tests and a plain copy.
 // ---------------------------------------------------------------------------
 __global__ void k_spin(uint64_t ticks) {
@@ -1408,6 +1592,119 @@ hipError_t l_copy(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   return hipGetLastError();
 }
 
+// -- ML ensemble -------------------------------------------------------------
+#define DAGRT_ML_CLASSES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+const dag_p_ml* pml(const void* p) { return static_cast<const dag_p_ml*>(p); }
+
+const char* ml_common(const dag_p_ml* q) {
+  if (q->classes < 1 || q->classes > static_cast<uint32_t>(kMlMaxClasses)) return "classes must be in 1..16";
+  if (q->features < 1) return "features must be >= 1";
+  if (q->reserved) return "reserved must be 0";
+  return nullptr;
+}
+
+const char* cfg_ml(const LaunchCfg& c) {
+  if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
+  if (c.variant != 0) return "variant must be 0";
+  return nullptr;
+}
+
+const char* v_nb(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const dag_p_ml* q = pml(p);
+  if (const char* e = ml_common(q)) return e;
+  if (q->categories < 1) return "categories must be >= 1";
+  const uint64_t cfv = static_cast<uint64_t>(q->classes) * q->features * q->categories;
+  if (cfv > kNbTable) return "classes * features * categories must be <= 32768 (the LDS table)";
+  if (!mul_fits(q->n, 4ull * q->features, sz[0])) return "X smaller than 4*n*features bytes";
+  if (sz[1] < 4 * cfv) return "log_theta smaller than 4*classes*features*categories bytes";
+  if (sz[2] < 4ull * q->classes) return "log_prior smaller than 4*classes bytes";
+  if (!mul_fits(q->n, 4ull * q->classes, sz[3])) return "P smaller than 4*n*classes bytes";
+  return nullptr;
+}
+hipError_t l_nb(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const dag_p_ml* q = pml(p);
+  if (q->n == 0) return hipSuccess;
+  const int vec = q->features % 4 == 0 && aligned16(a[0]);
+  const dim3 g(stream_grid(q->n, c)), b(c.block);
+  const auto* X = static_cast<const float*>(a[0]);
+  const auto* lt = static_cast<const float*>(a[1]);
+  const auto* lp = static_cast<const float*>(a[2]);
+  auto* P = static_cast<float*>(a[3]);
+  switch (q->classes) {
+#define DAGRT_NB_CASE(K) \
+  case K: DAGRT_LAUNCH(k_nb_proba<K>, g, b, 0, s, X, lt, lp, P, q->n, q->features, q->categories, vec); break;
+    DAGRT_ML_CLASSES(DAGRT_NB_CASE)
+#undef DAGRT_NB_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+uint64_t ridge_lds_bytes(const dag_p_ml* q) { return 8ull * q->features * (q->classes + 1ull); }
+
+const char* v_ridge(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const dag_p_ml* q = pml(p);
+  if (const char* e = ml_common(q)) return e;
+  if (ridge_lds_bytes(q) > kRidgeLdsBytes) return "features * (classes + 1) must be <= 8192 (the LDS weights)";
+  const uint64_t F = q->features, C = q->classes;
+  if (!mul_fits(q->n, 4 * F, sz[0])) return "X smaller than 4*n*features bytes";
+  if (sz[1] < 4 * F || sz[2] < 4 * F) return "mean or scale smaller than 4*features bytes";
+  if (sz[3] < 4 * F * C) return "W smaller than 4*classes*features bytes";
+  if (sz[4] < 4 * C) return "b smaller than 4*classes bytes";
+  if (!mul_fits(q->n, 4 * C, sz[5])) return "P smaller than 4*n*classes bytes";
+  return nullptr;
+}
+hipError_t l_ridge(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const dag_p_ml* q = pml(p);
+  if (q->n == 0) return hipSuccess;
+  const int vec = q->features % 4 == 0 && aligned16(a[0]);
+  const dim3 g(stream_grid(q->n, c)), b(c.block);
+  const size_t shm = ridge_lds_bytes(q);
+  const auto* X = static_cast<const float*>(a[0]);
+  const auto* mean = static_cast<const float*>(a[1]);
+  const auto* scale = static_cast<const float*>(a[2]);
+  const auto* W = static_cast<const float*>(a[3]);
+  const auto* bias = static_cast<const float*>(a[4]);
+  auto* P = static_cast<float*>(a[5]);
+  switch (q->classes) {
+#define DAGRT_RIDGE_CASE(K) \
+  case K: DAGRT_LAUNCH(k_ridge_proba<K>, g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features, vec); break;
+    DAGRT_ML_CLASSES(DAGRT_RIDGE_CASE)
+#undef DAGRT_RIDGE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+const char* v_ensemble(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const dag_p_ml* q = pml(p);
+  if (const char* e = ml_common(q)) return e;
+  const uint64_t C = q->classes;
+  if (!mul_fits(q->n, 4 * C, sz[0]) || !mul_fits(q->n, 4 * C, sz[1]) || !mul_fits(q->n, 4 * C, sz[2]))
+    return "Pnb, Prr or avg smaller than 4*n*classes bytes";
+  if (!mul_fits(q->n, 4, sz[3])) return "label smaller than 4*n bytes";
+  return nullptr;
+}
+hipError_t l_ensemble(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const dag_p_ml* q = pml(p);
+  if (q->n == 0) return hipSuccess;
+  const dim3 g(stream_grid(q->n, c)), b(c.block);
+  const auto* pa = static_cast<const float*>(a[0]);
+  const auto* pb = static_cast<const float*>(a[1]);
+  auto* avg = static_cast<float*>(a[2]);
+  auto* label = static_cast<int*>(a[3]);
+  switch (q->classes) {
+#define DAGRT_ENS_CASE(K) \
+  case K: DAGRT_LAUNCH(k_ensemble<K>, g, b, 0, s, pa, pb, avg, label, q->n); break;
+    DAGRT_ML_CLASSES(DAGRT_ENS_CASE)
+#undef DAGRT_ENS_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 const KernelDesc kTable[] = {
     /* 0 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
     /* 1 */ {"vec_square", 1, 0x1, sizeof(dag_p_n), {256, 0, 0}, v_vec_square, l_vec_square, cfg_block_any},
@@ -1424,7 +1721,12 @@ const KernelDesc kTable[] = {
     /* 12 */ {"scale_l2", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_scale, l_scale, cfg_block_any},
     /* 13 */ {"spin", 0, 0x0, sizeof(dag_p_spin), {64, 0, 0}, v_spin, l_spin, cfg_spin},
     /* 14 */ {"copy_f32", 2, 0x2, sizeof(dag_p_n), {256, 0, 0}, v_copy, l_copy, cfg_block_any},
+    /* 15 */ {"nb_proba", 4, 0x8, sizeof(dag_p_ml), {1024, 256, 0}, v_nb, l_nb, cfg_ml},
+    /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ml},
+    /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml},
 };
+
+static_assert(sizeof(kTable) / sizeof(kTable[0]) == kNumBuiltin, "kernel table and kNumBuiltin disagree");
 
 }  // namespace
 

@@ -28,7 +28,8 @@ struct KernelDesc {
   const char* (*check_cfg)(const LaunchCfg& cfg);
 };
 
-// nullptr for unknown ids.
+// Built-in kernel ids are 1..kNumBuiltin-1; nullptr for unknown ids.
+constexpr uint32_t kNumBuiltin = 18;
 const KernelDesc* builtin_kernel(uint32_t id);
 
 // Timing events for the next built-in launch call (both null = none): the

@@ -102,6 +102,7 @@ struct Shape {
   std::vector<uint8_t> needs_ev;
   int32_t last_of[3] = {-1, -1, -1};
   bool has_init = false;
+  bool host_io = false;  // the recorded calls copy between host and device
   int32_t result_buf;
   size_t result_bytes;
   uint64_t dev_bytes = 0, host_bytes = 0;  // per-request block sizes
@@ -264,6 +265,8 @@ void plan_copy_lanes(Shape* sh) {
     if (sh->last_of[cl] >= 0) sh->needs_ev[sh->last_of[cl]] = 1;
   for (const ShapeBuf& b : sh->bufs)
     if (b.role == DAG_ROLE_INIT) sh->has_init = true;
+  for (size_t k = 0; k < n; ++k)
+    if (sh->cls[k] != kOnLane) sh->host_io = true;
 }
 
 void copy_result(const dag_server_s* s, const Shape& sh, uint64_t dev_off, uint64_t host_off, void* out) {
@@ -287,7 +290,9 @@ dag_status dag_serve_create(dag_ctx c, const dag_serve_config* cfg, dag_server* 
   CHECK_CTX(c);
   if (!cfg || !out) return fail(c, DAG_E_INVAL, "cfg and out are required");
   if (cfg->lanes == 0 || cfg->lanes > DAG_MAX_STREAMS) return fail(c, DAG_E_INVAL, "lanes must be 1..64");
-  if (cfg->copy_lanes > 4 || cfg->reserved) return fail(c, DAG_E_INVAL, "copy_lanes must be 0..4, reserved 0");
+  if (cfg->copy_lanes > 4) return fail(c, DAG_E_INVAL, "copy_lanes must be 0..4");
+  if (cfg->transfer_lanes && cfg->transfer_lanes >= cfg->lanes)
+    return fail(c, DAG_E_INVAL, "transfer_lanes must be 0 or less than lanes");
   if (cfg->budget_bytes == 0 || cfg->budget_bytes > cfg->device_arena_bytes)
     return fail(c, DAG_E_INVAL, "budget must be in (0, device_arena_bytes]");
   auto* s = new (std::nothrow) dag_server_s();
@@ -515,8 +520,16 @@ dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint
         continue;
       }
       // the lane with the fewest requests in flight (lowest index on ties)
-      uint32_t lane = 0;
-      for (uint32_t l = 1; l < nl; ++l)
+      // among the lanes of the request's class
+      uint32_t lo = 0, hi = nl;
+      if (!serial && s->cfg.transfer_lanes) {
+        if (sh.host_io)
+          hi = s->cfg.transfer_lanes;
+        else
+          lo = s->cfg.transfer_lanes;
+      }
+      uint32_t lane = lo;
+      for (uint32_t l = lo + 1; l < hi; ++l)
         if (flights[l].size() < flights[lane].size()) lane = l;
       Flight f{r, lane, nullptr, doff, hoff, 0};
       done[r].admit_ns = now;

@@ -34,6 +34,7 @@ KERNEL_IDS = {
     "vec_square": 1, "vec_sum_diff": 2, "bs_call": 3, "gauss_blur": 4, "sobel": 5,
     "minmax": 6, "normalise": 7, "unsharp_combine": 8, "spmv": 9, "spmv_rows": 10, "sumsq": 11,
     "scale_l2": 12, "spin": 13, "copy_f32": 14,
+    "nb_proba": 15, "ridge_proba": 16, "ensemble": 17,
 }
 KERNEL_NAMES = {v: k for k, v in KERNEL_IDS.items()}
 
@@ -103,6 +104,11 @@ class dag_p_spin(C.Structure):
     _fields_ = [("ns", C.c_uint64)]
 
 
+class dag_p_ml(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("features", C.c_uint32), ("classes", C.c_uint32),
+                ("categories", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 class dag_shape_buf(C.Structure):
     _fields_ = [("buf", C.c_uint32), ("role", C.c_uint32), ("init_src", C.c_uint32),
                 ("reserved", C.c_uint32)]
@@ -111,7 +117,7 @@ class dag_shape_buf(C.Structure):
 class dag_serve_config(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("device_arena_bytes", C.c_uint64),
                 ("host_arena_bytes", C.c_uint64), ("lanes", C.c_uint32), ("bypass", C.c_uint32),
-                ("copy_lanes", C.c_uint32), ("reserved", C.c_uint32)]
+                ("copy_lanes", C.c_uint32), ("transfer_lanes", C.c_uint32)]
 
 
 class dag_request(C.Structure):
@@ -471,6 +477,8 @@ def make_params(kernel, p):
         return dag_p_csr(int(p["nrows"]), int(p["ncols"]), int(p["nnz"]))
     if kernel == "spin":
         return dag_p_spin(int(p.get("ns", 0)))
+    if kernel in ("nb_proba", "ridge_proba", "ensemble"):
+        return dag_p_ml(int(p["n"]), int(p["features"]), int(p["classes"]), int(p.get("categories", 1)), 0)
     raise KeyError(kernel)
 
 

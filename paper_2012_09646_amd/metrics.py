@@ -124,6 +124,15 @@ def algorithmic_bytes(kernel, p):
         return 8 * p["n"] + 8
     if kernel == "copy_f32":
         return 8 * p["n"]
+    if kernel == "nb_proba":
+        n, F, C, V = p["n"], p["features"], p["classes"], p["categories"]
+        return 4 * n * F + 4 * C * F * V + 4 * C + 4 * n * C
+    if kernel == "ridge_proba":
+        n, F, C = p["n"], p["features"], p["classes"]
+        return 4 * n * F + 4 * (2 * F + C * F + C) + 4 * n * C
+    if kernel == "ensemble":
+        n, C = p["n"], p["classes"]
+        return 12 * n * C + 4 * n
     return 0
 
 

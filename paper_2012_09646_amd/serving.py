@@ -57,10 +57,10 @@ class ShapeTemplate:
 
 class Server:
     def __init__(self, ctx, budget_bytes, device_arena_bytes=None, host_arena_bytes=1 << 30,
-                 lanes=8, bypass=32, copy_lanes=1):
+                 lanes=8, bypass=32, copy_lanes=1, transfer_lanes=0):
         self.ctx = ctx
         cfg = D.dag_serve_config(int(budget_bytes), int(device_arena_bytes or budget_bytes),
-                                 int(host_arena_bytes), lanes, bypass, int(copy_lanes), 0)
+                                 int(host_arena_bytes), lanes, bypass, int(copy_lanes), int(transfer_lanes))
         self.h = D.dag_serve_create(ctx.h, cfg)
         self.shapes = []
 

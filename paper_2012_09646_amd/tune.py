@@ -46,6 +46,11 @@ def candidates(kernel):
         return [(256, c, v) for v in (4, 8, 16, 32) for c in (0, 2048, 8192)]
     if kernel in ("gauss_blur", "sobel"):
         return [(256, 0, v) for v in (0, 1)]  # tile order: row-major or one run per XCD
+    if kernel == "nb_proba":
+        # one workgroup per CU fits beside the 128 KB table: its size sets the waves per CU
+        return [(b, c, 0) for b in (256, 512, 1024) for c in (0, 256, 512, 1024)]
+    if kernel in ("ridge_proba", "ensemble"):
+        return [(b, c, 0) for b in BLOCKS for c in CAPS]
     return []  # the delay kernel
 
 
@@ -164,12 +169,14 @@ def workload_program(name):
         return W.img_program(side=2048, seed=2), ()
     if name == "hits":
         return W.hits_program(n=1 << 20, iters=10, seed=3), ("a", "h")
+    if name == "ml":
+        return W.ml_program(n=1 << 20, seed=5), ()
     raise ValueError(name)
 
 
 def _worker(args, log):
     """Runs inside one process (one GPU_MAX_HW_QUEUES setting)."""
-    names = ["vec", "bs", "img", "hits"] if args.workload == "all" else [args.workload]
+    names = ["vec", "bs", "img", "hits", "ml"] if args.workload == "all" else [args.workload]
     out = {"kernels": {}, "dag": {}}
     if args.worker == "kernels":
         for name in names:
@@ -209,7 +216,7 @@ def _spawn(extra, out, hw_queues=None):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits"])
+    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "ml"])
     ap.add_argument("--out", required=False)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--dag", action="store_true", help="also tune pool size, copy placement and hardware queues")

@@ -263,7 +263,7 @@ def ml_inputs(seed, n, features=ML_FEATURES, classes=ML_CLASSES, categories=ML_C
     wp = g.uniform(0.5, 1.0, size=C)
     log_prior = np.log(wp / wp.sum()).astype(F32)
     mu = (V - 1) / 2.0
-    sd = np.sqrt((V * V - 1) / 12.0)
+    sd = np.sqrt((V * V - 1) / 12.0) if V > 1 else 1.0
     mean = (mu + g.uniform(-0.5, 0.5, size=F)).astype(F32)
     scale = (sd * g.uniform(0.9, 1.1, size=F)).astype(F32)
     W = g.uniform(-0.25, 0.25, size=(C, F)).astype(F32)

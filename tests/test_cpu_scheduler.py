@@ -366,3 +366,43 @@ def test_injected_launch_failure_poisons_the_context(monkeypatch):
     for _ in range(4):
         ctx2.kernel("spin", [(y, "m")], ns=0)
     ctx2.close()
+
+
+def test_ml_kernel_argument_checks():
+    """The ML kernels' sizes are validated on the host: class count 1..16,
+    the naive Bayes table within its LDS capacity, the ridge weights within
+    theirs, every buffer large enough, reserved zero."""
+    ctx = D.Context(dry_run=True)
+    big = ctx.alloc(1 << 22)
+    b2 = ctx.alloc(1 << 22)
+    out = ctx.alloc(1 << 22)
+    lab = ctx.alloc(1 << 22)
+
+    def nb(**p):
+        q = dict(n=1000, features=200, classes=10, categories=16)
+        q.update(p)
+        return _status(ctx.kernel, "nb_proba", [(big, "c"), (b2, "c"), (b2, "c"), (out, "m")], **q)
+
+    def ridge(**p):
+        q = dict(n=1000, features=200, classes=10)
+        q.update(p)
+        return _status(ctx.kernel, "ridge_proba", [(big, "c"), (b2, "c"), (b2, "c"), (b2, "c"), (b2, "c"),
+                                                   (out, "m")], **q)
+
+    assert nb() == "DAG_OK" and ridge() == "DAG_OK"
+    assert nb(classes=0) == "DAG_E_INVAL" and nb(classes=17) == "DAG_E_INVAL"
+    assert nb(features=0) == "DAG_E_INVAL" and nb(categories=0) == "DAG_E_INVAL"
+    assert nb(features=128, classes=16, categories=16) == "DAG_OK"          # 32768 table entries
+    assert nb(features=129, classes=16, categories=16) == "DAG_E_INVAL"
+    assert nb(n=6000) == "DAG_E_INVAL"                                       # X too small
+    assert ridge(features=744, classes=10) == "DAG_OK"                       # 744 * 11 = 8184 <= 8192
+    assert ridge(features=745, classes=10) == "DAG_E_INVAL"
+    assert ridge(classes=17) == "DAG_E_INVAL" and ridge(n=6000) == "DAG_E_INVAL"
+    assert _status(ctx.kernel, "ensemble", [(big, "c"), (b2, "c"), (out, "m"), (lab, "m")],
+                   n=1000, features=1, classes=10) == "DAG_OK"
+    assert _status(ctx.kernel, "ensemble", [(big, "c"), (b2, "c"), (out, "m"), (lab, "m")],
+                   n=1 << 20, features=1, classes=10) == "DAG_E_INVAL"
+    # written arguments passed as const are rejected
+    assert _status(ctx.kernel, "ensemble", [(big, "c"), (b2, "c"), (out, "c"), (lab, "m")],
+                   n=10, features=1, classes=10) == "DAG_E_INVAL"
+    ctx.close()

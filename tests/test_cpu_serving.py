@@ -113,3 +113,31 @@ def test_shape_validation():
     small.close()
     srv.close()
     ctx.close()
+
+
+def test_transfer_lanes_separate_link_bound_requests():
+    """With transfer_lanes = 1, requests whose shape copies between host and
+    device (the Black-Scholes fan-out) use lane 0 only and all others lanes
+    1.. only; without it any lane takes any request."""
+    ctx = D.Context(dry_run=True)
+    comp = serving.ShapeTemplate(ctx, W.vec_program(n=1 << 10), key=11)
+    link = serving.ShapeTemplate(ctx, W.bs_program(n=1 << 10, tasks=2), key=12)
+    arr = np.zeros(32, dtype=np.int64)
+    shp = np.array([i % 4 == 0 for i in range(32)], dtype=np.int32)   # every fourth request copies
+    srv = serving.Server(ctx, 1 << 30, host_arena_bytes=1 << 24, lanes=3, transfer_lanes=1)
+    a, b = srv.add(comp, sim_ns=10_000), srv.add(link, sim_ns=50_000)
+    assert (a, b) == (0, 1)
+    out, st, _ = srv.run(arr, shp)
+    assert np.all(out["lane"][shp == 1] == 0)
+    assert set(out["lane"][shp == 0].tolist()) == {1, 2}
+    srv.close()
+    srv = serving.Server(ctx, 1 << 30, host_arena_bytes=1 << 24, lanes=3, transfer_lanes=0)
+    srv.add(comp, sim_ns=10_000)
+    srv.add(link, sim_ns=50_000)
+    out, _, _ = srv.run(arr, shp)
+    assert set(out["lane"][shp == 1].tolist()) == {0, 1, 2}
+    srv.close()
+    for bad in (3, 4):
+        with pytest.raises(D.DagError):
+            serving.Server(ctx, 1 << 30, host_arena_bytes=1 << 24, lanes=3, transfer_lanes=bad)
+    ctx.close()

@@ -1,0 +1,146 @@
+"""GPU parity of the ML ensemble workload: the naive Bayes and ridge
+posteriors and their average within 1e-5 relative of the oracle; the
+ensemble kernel bit-exact (average and label) when it reads the oracle's
+posteriors; the labels of the whole pipeline equal to the oracle's except at
+a near-tie, where the chosen class must be within the tolerance of the best."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import gpu_util as G
+from oracle import dag as odag
+from paper_2012_09646_amd import dagrt as D
+from paper_2012_09646_amd import runner
+from paper_2012_09646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def banner(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def run(prog, launch=None):
+    ctx = D.Context()
+    try:
+        for k, cfg in (launch or {}).items():
+            ctx.set_launch(k, *cfg)
+        b = runner.Bound(ctx, prog)
+        b.run()
+        outs = {name: b.read(name) for name in prog.outputs}
+        edges = b.edges()
+    finally:
+        ctx.close()
+    return outs, edges
+
+
+def check_labels(lab_g, lab_o, avg_o, C):
+    """Labels equal the oracle's; where they differ the oracle's average of
+    the chosen class must be within 2e-5 of the row's largest (a near-tie
+    that rounding may break either way)."""
+    lab_g = lab_g.view(np.int32)
+    lab_o = lab_o.view(np.int32)
+    avg = avg_o.view(np.float32).reshape(-1, C).astype(np.float64)
+    assert np.all((lab_g >= 0) & (lab_g < C))
+    diff = np.nonzero(lab_g != lab_o)[0]
+    for r in diff:
+        assert avg[r, lab_g[r]] >= avg[r].max() * (1 - 2e-5), "row %d: label %d vs %d" % (r, lab_g[r], lab_o[r])
+    return diff.size
+
+
+@pytest.mark.parametrize("n,F,C,V", [(3000, 200, 10, 16), (1, 200, 10, 16), (777, 13, 3, 5),
+                                     (1000, 128, 16, 16), (500, 1, 1, 1), (2049, 64, 7, 9)])
+def test_ml_pipeline(n, F, C, V):
+    banner("ml n=%d F=%d C=%d V=%d" % (n, F, C, V))
+    prog = W.ml_program(n=n, seed=n + F, features=F, classes=C, categories=V)
+    ref = G.oracle_run(prog)
+    outs, edges = run(prog)
+    assert edges == odag.build_dag(prog.ops).edges
+    for name in ("Pnb", "Prr", "Pavg"):
+        G.assert_close(prog, name, outs[name], ref[name])
+    check_labels(outs["label"], ref["label"], ref["Pavg"], C)
+
+
+@pytest.mark.parametrize("launch", [
+    {"nb_proba": (256, 3, 0), "ridge_proba": (1024, 2, 0), "ensemble": (64, 5, 0)},
+    {"nb_proba": (64, 0, 0), "ridge_proba": (64, 0, 0), "ensemble": (1024, 0, 0)},
+    {"nb_proba": (512, 1, 0), "ridge_proba": (128, 1, 0), "ensemble": (128, 1, 0)},
+])
+def test_ml_launch_configurations(launch):
+    """Grid-stride loops that wrap several times, single workgroups, small
+    and large workgroups: same results."""
+    banner("ml launch %s" % launch)
+    prog = W.ml_program(n=5003, seed=9, features=200, classes=10, categories=16)
+    ref = G.oracle_run(prog)
+    outs, _ = run(prog, launch)
+    for name in ("Pnb", "Prr", "Pavg"):
+        G.assert_close(prog, name, outs[name], ref[name])
+    check_labels(outs["label"], ref["label"], ref["Pavg"], 10)
+
+
+@pytest.mark.parametrize("n,C,tied", [(4099, 10, False), (4099, 10, True), (333, 1, True), (1000, 16, True)])
+def test_ensemble_bit_exact_on_the_oracles_posteriors(n, C, tied):
+    """The ensemble kernel alone, reading the same float32 inputs as the
+    oracle: average and label bit-exact; with values drawn from a small set
+    most rows hold ties, which must go to the lowest class index."""
+    banner("ensemble n=%d C=%d tied=%d" % (n, C, tied))
+    g = np.random.default_rng(n + C)
+    if tied:
+        a = g.choice(np.float32([0.0, 0.25, 0.5, 1.0]), size=(n, C)).astype(np.float32)
+        b = g.choice(np.float32([0.0, 0.25, 0.5, 1.0]), size=(n, C)).astype(np.float32)
+    else:
+        a = g.random((n, C), dtype=np.float32)
+        b = g.random((n, C), dtype=np.float32)
+    bufs = {"Pnb": W.Buf(a.nbytes, init=a), "Prr": W.Buf(b.nbytes, init=b),
+            "Pavg": W.Buf(4 * n * C), "label": W.Buf(4 * n)}
+    ops = [W.K("ensemble", [("Pnb", "c"), ("Prr", "c"), ("Pavg", "m"), ("label", "m")],
+               n=n, features=1, classes=C, categories=1), W.HR("label")]
+    prog = W.Program("ens", bufs, ops, ["Pavg", "label"], "label")
+    ref = G.oracle_run(prog)
+    outs, _ = run(prog)
+    assert np.array_equal(outs["Pavg"], ref["Pavg"])
+    assert np.array_equal(outs["label"], ref["label"])
+    if tied and C > 1:
+        assert np.any(ref["label"].view(np.int32) > 0)
+
+
+def test_ml_full_size_sampled():
+    """The benchmark's shape (2^20 rows, 200 features, 10 classes, 16
+    categories) in the default launch configuration: 4096 sampled rows
+    against the oracle computed for those rows alone (rows are independent)."""
+    from oracle import tasks as T
+    n = 1 << 20
+    banner("ml full size n=%d" % n)
+    prog = W.ml_program(n=n, seed=5)
+    outs, _ = run(prog)
+    d = {k: prog.bufs[k].init for k in ("X", "log_theta", "log_prior", "mean", "scale", "W", "b")}
+    rows = np.sort(np.random.default_rng(1).choice(n, 4096, replace=False))
+    rows[0], rows[-1] = 0, n - 1
+    X = d["X"][rows]
+    pnb = T.nb_predict_proba(X, d["log_theta"], d["log_prior"])
+    prr = T.ridge_predict_proba(X, d["mean"], d["scale"], d["W"], d["b"])
+    avg, lab = T.ensemble_argmax(pnb, prr)
+    g_nb = outs["Pnb"].view(np.float32).reshape(n, 10)[rows]
+    g_rr = outs["Prr"].view(np.float32).reshape(n, 10)[rows]
+    g_avg = outs["Pavg"].view(np.float32).reshape(n, 10)[rows]
+    for g, o in ((g_nb, pnb), (g_rr, prr), (g_avg, avg)):
+        assert np.all(np.abs(g.astype(np.float64) - o) <= 1e-5 * np.abs(o.astype(np.float64)))
+    check_labels(np.ascontiguousarray(outs["label"].view(np.int32)[rows]), lab, avg, 10)
+
+
+def test_ml_zero_rows():
+    """n = 0: nothing is launched, the call succeeds."""
+    banner("ml zero rows")
+    ctx = D.Context()
+    try:
+        bufs = [ctx.alloc(4096) for _ in range(7)]
+        ctx.kernel("nb_proba", [(bufs[0], "c"), (bufs[1], "c"), (bufs[2], "c"), (bufs[3], "m")],
+                   n=0, features=4, classes=2, categories=2)
+        ctx.kernel("ridge_proba", [(bufs[0], "c"), (bufs[1], "c"), (bufs[2], "c"), (bufs[4], "c"),
+                                   (bufs[5], "c"), (bufs[6], "m")], n=0, features=20, classes=10)
+        ctx.sync()
+    finally:
+        ctx.close()
