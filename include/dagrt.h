@@ -253,15 +253,16 @@ dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
 #define DAG_K_SCALE_L2 12u       /* t:c s:c v:m         v_i = t_i / sqrt(s) */
 #define DAG_K_SPIN 13u           /* (any args)          busy-wait, no data */
 #define DAG_K_COPY_F32 14u       /* src:c dst:m         dst_i = src_i */
-/* ML ensemble (Sec. V-B): X is n x F row-major fp32 holding category codes
- * 0..V-1; P* are n x C row-major fp32 probabilities. */
+/* ML ensemble (Sec. V-B): X holds n rows of F fp32 category codes 0..V-1,
+ * stored feature-major (feature f of row r at X[f*n + r]); P* are n x C
+ * row-major fp32 probabilities. */
 #define DAG_K_NB_PROBA 15u       /* X lt lp:c P:m       categorical naive Bayes:
-                                    P[r] = softmax_c(lp[c] + sum_f lt[c][f][X[r][f]]),
+                                    P[r] = softmax_c(lp[c] + sum_f lt[c][f][X[f*n+r]]),
                                     lt = log P(x_f = v | c) as C x F x V,
                                     lp = log P(c); codes are truncated and
                                     clamped to [0, V-1]; C*F*V <= 32768 */
 #define DAG_K_RIDGE_PROBA 16u    /* X mean scale W b:c P:m  ridge classifier:
-                                    P[r] = softmax_c(sum_f (X[r][f] - mean_f) /
+                                    P[r] = softmax_c(sum_f (X[f*n+r] - mean_f) /
                                     scale_f * W[c][f] + b[c]), W is C x F;
                                     F*(C+1) <= 8192 */
 #define DAG_K_ENSEMBLE 17u       /* Pnb Prr:c avg:m label:m  avg = (Pnb + Prr)/2,

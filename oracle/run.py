@@ -81,16 +81,21 @@ def _ml(p):
     return p["n"], p["features"], p["classes"], p["categories"]
 
 
+def _rows(X, n, F):
+    """The n x F matrix of a feature-major buffer (feature f of row r at f*n + r)."""
+    return _f32(X, n * F).reshape(F, n).T
+
+
 def _k_nb_proba(p, X, lt, lp, P):
     n, F, C, V = _ml(p)
     _f32(P, n * C).reshape(n, C)[:] = tasks.nb_predict_proba(
-        _f32(X, n * F).reshape(n, F), _f32(lt, C * F * V).reshape(C, F, V), _f32(lp, C))
+        _rows(X, n, F), _f32(lt, C * F * V).reshape(C, F, V), _f32(lp, C))
 
 
 def _k_ridge_proba(p, X, mean, scale, W, b, P):
     n, F, C, _ = _ml(p)
     _f32(P, n * C).reshape(n, C)[:] = tasks.ridge_predict_proba(
-        _f32(X, n * F).reshape(n, F), _f32(mean, F), _f32(scale, F), _f32(W, C * F).reshape(C, F), _f32(b, C))
+        _rows(X, n, F), _f32(mean, F), _f32(scale, F), _f32(W, C * F).reshape(C, F), _f32(b, C))
 
 
 def _k_ensemble(p, p_nb, p_rr, avg, label):
@@ -119,7 +124,7 @@ KERNELS = {
     "sumsq": _k_sumsq,                      # v:c s:m      (s float64)
     "scale_l2": _k_scale_l2,                # t:c s:c v:m
     "spin": _k_spin,                        # any
-    "nb_proba": _k_nb_proba,                # X lt lp :c P:m      (n x C posteriors)
+    "nb_proba": _k_nb_proba,                # X lt lp :c P:m      (X feature-major; n x C posteriors)
     "ridge_proba": _k_ridge_proba,          # X mean scale W b :c P:m
     "ensemble": _k_ensemble,                # Pnb Prr :c avg:m label:m (int32)
 }

@@ -928,18 +928,18 @@ __global__ __launch_bounds__(1024) void k_scale_l2(const float* __restrict__ t,
 
 // ---------------------------------------------------------------------------
 // ML ensemble (Sec. V-B): categorical naive Bayes and a ridge classifier
-// score the same rows of X (n x F row-major fp32 category codes); each row of
-// C scores becomes probabilities by a softmax; the two probability rows are
-// averaged and reduced to the index of the largest average.
+// score the same rows of X (n rows x F features of fp32 category codes);
+// each row of C scores becomes probabilities by a softmax; the two
+// probability rows are averaged and reduced to the index of the largest
+// average.
 //
-// One thread per row.  A lane reads its own row 16 features (64 bytes) at a
-// time, four 16-byte loads in flight, so the cache lines one load brings in
-// are consumed by the same lane's next loads.  The per-class model data sit
-// in LDS in feature-major order, so the C values one feature contributes are
-// adjacent.
+// X is stored feature-major (feature f of row r at X[f*n + r]) and a thread
+// owns one row, so the 64 lanes of a wave read 256 contiguous bytes per
+// feature and the per-feature model data are the same for the whole wave.
+// kMlUnroll loads are issued before they are used.
 // ---------------------------------------------------------------------------
 constexpr int kMlMaxClasses = 16;
-constexpr int kMlBatch = 4;                // 16-byte loads in flight per lane
+constexpr int kMlUnroll = 8;               // features loaded ahead per lane
 constexpr uint32_t kNbTable = 32768;       // C*F*V fp32 entries of the naive Bayes table (128 KB)
 constexpr uint32_t kRidgeLdsBytes = 65536; // F*(C+1) fp64: weights / scale, then means
 
@@ -979,10 +979,14 @@ __device__ __forceinline__ void nb_add(double (&acc)[C], const float* __restrict
   }
 }
 
-template <int C>
+// R rows per thread: a workgroup covers R * blockDim consecutive rows, row
+// j * blockDim + tid of the tile going to thread tid, so every load of a wave
+// still reads 256 contiguous bytes and each thread has R * kMlUnroll loads in
+// flight.
+template <int C, int R>
 __global__ __launch_bounds__(1024) void k_nb_proba(const float* __restrict__ X, const float* __restrict__ lt,
                                                    const float* __restrict__ lp, float* __restrict__ P,
-                                                   uint64_t n, uint32_t F, uint32_t V, int vec) {
+                                                   uint64_t n, uint32_t F, uint32_t V) {
   __shared__ __align__(16) float s_tab[kNbTable];  // [f][v][c]
   const uint32_t fv_n = F * V;
   for (uint32_t i = threadIdx.x; i < C * fv_n; i += blockDim.x) {
@@ -995,50 +999,53 @@ __global__ __launch_bounds__(1024) void k_nb_proba(const float* __restrict__ X, 
   for (int c = 0; c < C; ++c) prior[c] = static_cast<double>(lp[c]);
   const float vmax = static_cast<float>(V - 1);
   const uint32_t tstride = V * C;  // table floats per feature
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < n; r += stride) {
-    double acc[C];
+  const uint64_t tile = static_cast<uint64_t>(blockDim.x) * R;
+  for (uint64_t base = blockIdx.x * tile; base < n; base += gridDim.x * tile) {
+    // rows past the end read the last row (in bounds, no branches) and are not stored
+    uint64_t row[R];
+    const float* xr[R];
+    double acc[R][C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = prior[c];
-    const float* row = X + r * F;
-    if (vec) {
-      for (uint32_t f0 = 0; f0 < F; f0 += 4 * kMlBatch) {
-        const uint32_t nq = min(static_cast<uint32_t>(kMlBatch), (F - f0) / 4);
-        float4 q[kMlBatch];
+    for (int j = 0; j < R; ++j) {
+      row[j] = base + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
+      xr[j] = X + (row[j] < n ? row[j] : n - 1);
 #pragma unroll
-        for (int j = 0; j < kMlBatch; ++j)
-          if (j < static_cast<int>(nq)) q[j] = reinterpret_cast<const float4*>(row + f0)[j];
-#pragma unroll
-        for (int j = 0; j < kMlBatch; ++j) {
-          if (j < static_cast<int>(nq)) {
-            const float* t = s_tab + (f0 + 4 * j) * tstride;
-            nb_add<C>(acc, t, vmax, q[j].x);
-            nb_add<C>(acc, t + tstride, vmax, q[j].y);
-            nb_add<C>(acc, t + 2 * tstride, vmax, q[j].z);
-            nb_add<C>(acc, t + 3 * tstride, vmax, q[j].w);
-          }
-        }
-      }
-    } else {
-      for (uint32_t f = 0; f < F; ++f) nb_add<C>(acc, s_tab + f * tstride, vmax, row[f]);
+      for (int c = 0; c < C; ++c) acc[j][c] = prior[c];
     }
-    softmax_store<C>(acc, P + r * C);
+    uint32_t f = 0;
+    for (; f + kMlUnroll <= F; f += kMlUnroll) {
+      float x[kMlUnroll][R];
+#pragma unroll
+      for (int u = 0; u < kMlUnroll; ++u)
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[u][j] = xr[j][static_cast<uint64_t>(f + u) * n];
+#pragma unroll
+      for (int u = 0; u < kMlUnroll; ++u)
+#pragma unroll
+        for (int j = 0; j < R; ++j) nb_add<C>(acc[j], s_tab + (f + u) * tstride, vmax, x[u][j]);
+    }
+    for (; f < F; ++f)
+#pragma unroll
+      for (int j = 0; j < R; ++j) nb_add<C>(acc[j], s_tab + f * tstride, vmax, xr[j][static_cast<uint64_t>(f) * n]);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (row[j] < n) softmax_store<C>(acc[j], P + row[j] * C);
   }
 }
 
 // acc[c] += (x - mean_f) * (W[c][f] / scale_f) for one feature (w = that
-// feature's C weights in LDS).
+// feature's C weights in LDS, the same address for every lane).
 template <int C>
 __device__ __forceinline__ void ridge_add(double (&acc)[C], const double* __restrict__ w, double d) {
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = fma(d, w[c], acc[c]);
 }
 
-template <int C>
-__global__ __launch_bounds__(1024) void k_ridge_proba(const float* __restrict__ X, const float* __restrict__ mean,
+template <int C, int R>
+__global__ __launch_bounds__(512) void k_ridge_proba(const float* __restrict__ X, const float* __restrict__ mean,
                                                       const float* __restrict__ scale, const float* __restrict__ W,
                                                       const float* __restrict__ b, float* __restrict__ P,
-                                                      uint64_t n, uint32_t F, int vec) {
+                                                      uint64_t n, uint32_t F) {
   extern __shared__ __align__(16) double s_w[];  // [f][c] weights / scale, then F means
   double* s_mu = s_w + F * C;
   for (uint32_t i = threadIdx.x; i < C * F; i += blockDim.x) {
@@ -1050,34 +1057,99 @@ __global__ __launch_bounds__(1024) void k_ridge_proba(const float* __restrict__ 
   double bias[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) bias[c] = static_cast<double>(b[c]);
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < n; r += stride) {
-    double acc[C];
+  const uint64_t tile = static_cast<uint64_t>(blockDim.x) * R;
+  for (uint64_t base = blockIdx.x * tile; base < n; base += gridDim.x * tile) {
+    // rows past the end read the last row (in bounds, no branches) and are not stored
+    uint64_t row[R];
+    const float* xr[R];
+    double acc[R][C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = bias[c];
-    const float* row = X + r * F;
-    if (vec) {
-      for (uint32_t f0 = 0; f0 < F; f0 += 4 * kMlBatch) {
-        const uint32_t nq = min(static_cast<uint32_t>(kMlBatch), (F - f0) / 4);
-        float4 q[kMlBatch];
+    for (int j = 0; j < R; ++j) {
+      row[j] = base + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
+      xr[j] = X + (row[j] < n ? row[j] : n - 1);
 #pragma unroll
-        for (int j = 0; j < kMlBatch; ++j)
-          if (j < static_cast<int>(nq)) q[j] = reinterpret_cast<const float4*>(row + f0)[j];
-#pragma unroll
-        for (int j = 0; j < kMlBatch; ++j) {
-          if (j < static_cast<int>(nq)) {
-            const uint32_t f = f0 + 4 * j;
-            ridge_add<C>(acc, s_w + f * C, static_cast<double>(q[j].x) - s_mu[f]);
-            ridge_add<C>(acc, s_w + (f + 1) * C, static_cast<double>(q[j].y) - s_mu[f + 1]);
-            ridge_add<C>(acc, s_w + (f + 2) * C, static_cast<double>(q[j].z) - s_mu[f + 2]);
-            ridge_add<C>(acc, s_w + (f + 3) * C, static_cast<double>(q[j].w) - s_mu[f + 3]);
-          }
-        }
-      }
-    } else {
-      for (uint32_t f = 0; f < F; ++f) ridge_add<C>(acc, s_w + f * C, static_cast<double>(row[f]) - s_mu[f]);
+      for (int c = 0; c < C; ++c) acc[j][c] = bias[c];
     }
-    softmax_store<C>(acc, P + r * C);
+    uint32_t f = 0;
+    for (; f + kMlUnroll <= F; f += kMlUnroll) {
+      float x[kMlUnroll][R];
+#pragma unroll
+      for (int u = 0; u < kMlUnroll; ++u)
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[u][j] = xr[j][static_cast<uint64_t>(f + u) * n];
+#pragma unroll
+      for (int u = 0; u < kMlUnroll; ++u) {
+        const double mu = s_mu[f + u];
+#pragma unroll
+        for (int j = 0; j < R; ++j) ridge_add<C>(acc[j], s_w + (f + u) * C, static_cast<double>(x[u][j]) - mu);
+      }
+    }
+    for (; f < F; ++f)
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        ridge_add<C>(acc[j], s_w + f * C, static_cast<double>(xr[j][static_cast<uint64_t>(f) * n]) - s_mu[f]);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (row[j] < n) softmax_store<C>(acc[j], P + row[j] * C);
+  }
+}
+
+// Four consecutive rows per thread with 16-byte loads (n a multiple of 4,
+// X 16-byte aligned): a wave reads 1 KB contiguous per feature, twice the
+// bytes in flight of two single rows, and the weights read from LDS serve
+// four rows.
+template <int C>
+__global__ __launch_bounds__(256) void k_ridge_proba4(const float* __restrict__ X, const float* __restrict__ mean,
+                                                      const float* __restrict__ scale, const float* __restrict__ W,
+                                                      const float* __restrict__ b, float* __restrict__ P,
+                                                      uint64_t n, uint32_t F) {
+  extern __shared__ __align__(16) double s_w[];  // [f][c] weights / scale, then F means
+  double* s_mu = s_w + F * C;
+  for (uint32_t i = threadIdx.x; i < C * F; i += blockDim.x) {
+    const uint32_t c = i / F, f = i - c * F;  // W is [c][f]
+    s_w[f * C + c] = static_cast<double>(W[i]) / static_cast<double>(scale[f]);
+  }
+  for (uint32_t f = threadIdx.x; f < F; f += blockDim.x) s_mu[f] = static_cast<double>(mean[f]);
+  __syncthreads();
+  double bias[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) bias[c] = static_cast<double>(b[c]);
+  const uint64_t groups = n / 4;  // float4 columns per feature
+  const float4* X4 = reinterpret_cast<const float4*>(X);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t g = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; g < groups; g += stride) {
+    double acc[4][C];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[j][c] = bias[c];
+    const float4* col = X4 + g;
+    uint32_t f = 0;
+    for (; f + kMlUnroll <= F; f += kMlUnroll) {
+      float4 x[kMlUnroll];
+#pragma unroll
+      for (int u = 0; u < kMlUnroll; ++u) x[u] = col[static_cast<uint64_t>(f + u) * groups];
+#pragma unroll
+      for (int u = 0; u < kMlUnroll; ++u) {
+        const double mu = s_mu[f + u];
+        const double* w = s_w + (f + u) * C;
+        ridge_add<C>(acc[0], w, static_cast<double>(x[u].x) - mu);
+        ridge_add<C>(acc[1], w, static_cast<double>(x[u].y) - mu);
+        ridge_add<C>(acc[2], w, static_cast<double>(x[u].z) - mu);
+        ridge_add<C>(acc[3], w, static_cast<double>(x[u].w) - mu);
+      }
+    }
+    for (; f < F; ++f) {
+      const float4 x = col[static_cast<uint64_t>(f) * groups];
+      const double mu = s_mu[f];
+      const double* w = s_w + f * C;
+      ridge_add<C>(acc[0], w, static_cast<double>(x.x) - mu);
+      ridge_add<C>(acc[1], w, static_cast<double>(x.y) - mu);
+      ridge_add<C>(acc[2], w, static_cast<double>(x.z) - mu);
+      ridge_add<C>(acc[3], w, static_cast<double>(x.w) - mu);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) softmax_store<C>(acc[j], P + (4 * g + j) * C);
   }
 }
 
@@ -1607,6 +1679,18 @@ const char* ml_common(const dag_p_ml* q) {
 
 const char* cfg_ml(const LaunchCfg& c) {
   if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
+  if (c.variant > 2) return "variant: rows per thread, 0 or 1 = one, 2 = two";
+  return nullptr;
+}
+const char* cfg_ridge(const LaunchCfg& c) {
+  if (c.variant > 2 && c.variant != 4) return "variant: rows per thread, 0 or 1 = one, 2 = two, 4 = four";
+  const uint32_t top = c.variant == 4 ? 256 : 512;
+  if (c.block < 64 || c.block > top || c.block % 64)
+    return "block must be a multiple of 64 in [64, 512] ([64, 256] for variant 4)";
+  return nullptr;
+}
+const char* cfg_ml_one(const LaunchCfg& c) {
+  if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
   if (c.variant != 0) return "variant must be 0";
   return nullptr;
 }
@@ -1617,7 +1701,7 @@ const char* v_nb(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, si
   if (q->categories < 1) return "categories must be >= 1";
   const uint64_t cfv = static_cast<uint64_t>(q->classes) * q->features * q->categories;
   if (cfv > kNbTable) return "classes * features * categories must be <= 32768 (the LDS table)";
-  if (!mul_fits(q->n, 4ull * q->features, sz[0])) return "X smaller than 4*n*features bytes";
+  if (!mul_fits(q->n, 4ull * q->features, sz[0])) return "X smaller than 4*features*n bytes";
   if (sz[1] < 4 * cfv) return "log_theta smaller than 4*classes*features*categories bytes";
   if (sz[2] < 4ull * q->classes) return "log_prior smaller than 4*classes bytes";
   if (!mul_fits(q->n, 4ull * q->classes, sz[3])) return "P smaller than 4*n*classes bytes";
@@ -1626,15 +1710,22 @@ const char* v_nb(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, si
 hipError_t l_nb(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const dag_p_ml* q = pml(p);
   if (q->n == 0) return hipSuccess;
-  const int vec = q->features % 4 == 0 && aligned16(a[0]);
-  const dim3 g(stream_grid(q->n, c)), b(c.block);
+  // two rows per thread within the register budget of 1024-thread workgroups
+  const bool two = c.variant == 2 && q->classes <= 11;
+  const dim3 g(stream_grid(ceil_div(q->n, two ? 2 : 1), c)), b(c.block);
   const auto* X = static_cast<const float*>(a[0]);
   const auto* lt = static_cast<const float*>(a[1]);
   const auto* lp = static_cast<const float*>(a[2]);
   auto* P = static_cast<float*>(a[3]);
   switch (q->classes) {
-#define DAGRT_NB_CASE(K) \
-  case K: DAGRT_LAUNCH(k_nb_proba<K>, g, b, 0, s, X, lt, lp, P, q->n, q->features, q->categories, vec); break;
+#define DAGRT_NB_CASE(K)                                                                                   \
+  case K:                                                                                                  \
+    if (two)                                                                                               \
+      DAGRT_LAUNCH((k_nb_proba<K, (K <= 11 ? 2 : 1)>), g, b, 0, s, X, lt, lp, P, q->n, q->features,       \
+                   q->categories);                                                                         \
+    else                                                                                                   \
+      DAGRT_LAUNCH((k_nb_proba<K, 1>), g, b, 0, s, X, lt, lp, P, q->n, q->features, q->categories);        \
+    break;
     DAGRT_ML_CLASSES(DAGRT_NB_CASE)
 #undef DAGRT_NB_CASE
     default: return hipErrorInvalidValue;
@@ -1659,8 +1750,10 @@ const char* v_ridge(const void* p, const size_t* sz, uint32_t, const LaunchCfg&,
 hipError_t l_ridge(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const dag_p_ml* q = pml(p);
   if (q->n == 0) return hipSuccess;
-  const int vec = q->features % 4 == 0 && aligned16(a[0]);
-  const dim3 g(stream_grid(q->n, c)), b(c.block);
+  // four rows per thread need 16-byte aligned float4 columns (n % 4 == 0), else one row
+  const bool four = c.variant == 4 && q->n % 4 == 0 && aligned16(a[0]);
+  const bool two = c.variant == 2;
+  const dim3 g(stream_grid(four ? q->n / 4 : ceil_div(q->n, two ? 2 : 1), c)), b(c.block);
   const size_t shm = ridge_lds_bytes(q);
   const auto* X = static_cast<const float*>(a[0]);
   const auto* mean = static_cast<const float*>(a[1]);
@@ -1669,8 +1762,15 @@ hipError_t l_ridge(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   const auto* bias = static_cast<const float*>(a[4]);
   auto* P = static_cast<float*>(a[5]);
   switch (q->classes) {
-#define DAGRT_RIDGE_CASE(K) \
-  case K: DAGRT_LAUNCH(k_ridge_proba<K>, g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features, vec); break;
+#define DAGRT_RIDGE_CASE(K)                                                                                \
+  case K:                                                                                                  \
+    if (four)                                                                                              \
+      DAGRT_LAUNCH((k_ridge_proba4<K>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);      \
+    else if (two)                                                                                          \
+      DAGRT_LAUNCH((k_ridge_proba<K, 2>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);    \
+    else                                                                                                   \
+      DAGRT_LAUNCH((k_ridge_proba<K, 1>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);    \
+    break;
     DAGRT_ML_CLASSES(DAGRT_RIDGE_CASE)
 #undef DAGRT_RIDGE_CASE
     default: return hipErrorInvalidValue;
@@ -1722,8 +1822,8 @@ const KernelDesc kTable[] = {
     /* 13 */ {"spin", 0, 0x0, sizeof(dag_p_spin), {64, 0, 0}, v_spin, l_spin, cfg_spin},
     /* 14 */ {"copy_f32", 2, 0x2, sizeof(dag_p_n), {256, 0, 0}, v_copy, l_copy, cfg_block_any},
     /* 15 */ {"nb_proba", 4, 0x8, sizeof(dag_p_ml), {1024, 256, 0}, v_nb, l_nb, cfg_ml},
-    /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ml},
-    /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml},
+    /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ridge},
+    /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml_one},
 };
 
 static_assert(sizeof(kTable) / sizeof(kTable[0]) == kNumBuiltin, "kernel table and kNumBuiltin disagree");

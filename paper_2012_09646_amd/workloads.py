@@ -273,9 +273,11 @@ def ml_inputs(seed, n, features=ML_FEATURES, classes=ML_CLASSES, categories=ML_C
 
 def ml_program(n=1 << 20, seed=5, features=ML_FEATURES, classes=ML_CLASSES, categories=ML_CATEGORIES):
     """ML ensemble: naive Bayes posteriors and ridge posteriors of the same
-    rows (independent branches sharing the read-only X), then their average
-    and argmax; host reads the labels."""
+    rows (independent branches sharing the read-only X, stored feature-major
+    so that the threads of a wave, one row each, read consecutive words),
+    then their average and argmax; host reads the labels."""
     d = ml_inputs(seed, n, features, classes, categories)
+    d["X"] = np.ascontiguousarray(d["X"].T)   # stored feature-major: feature f of row r at f*n + r
     C = int(classes)
     bufs = {k: Buf(v.nbytes, init=v) for k, v in d.items()}
     for name in ("Pnb", "Prr", "Pavg"):

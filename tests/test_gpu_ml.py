@@ -64,21 +64,31 @@ def test_ml_pipeline(n, F, C, V):
     check_labels(outs["label"], ref["label"], ref["Pavg"], C)
 
 
+@pytest.mark.parametrize("C", [10, 16])
 @pytest.mark.parametrize("launch", [
-    {"nb_proba": (256, 3, 0), "ridge_proba": (1024, 2, 0), "ensemble": (64, 5, 0)},
+    {"nb_proba": (256, 3, 0), "ridge_proba": (512, 2, 0), "ensemble": (64, 5, 0)},
     {"nb_proba": (64, 0, 0), "ridge_proba": (64, 0, 0), "ensemble": (1024, 0, 0)},
     {"nb_proba": (512, 1, 0), "ridge_proba": (128, 1, 0), "ensemble": (128, 1, 0)},
+    {"nb_proba": (1024, 256, 2), "ridge_proba": (512, 1024, 2), "ensemble": (256, 0, 0)},
+    {"nb_proba": (256, 3, 2), "ridge_proba": (64, 3, 2), "ensemble": (256, 0, 0)},
+    {"nb_proba": (64, 0, 2), "ridge_proba": (256, 0, 2), "ensemble": (256, 0, 0)},
+    {"nb_proba": (1024, 256, 2), "ridge_proba": (256, 1024, 4), "ensemble": (256, 0, 0)},
+    {"nb_proba": (1024, 256, 2), "ridge_proba": (64, 3, 4), "ensemble": (256, 0, 0)},
 ])
-def test_ml_launch_configurations(launch):
+def test_ml_launch_configurations(launch, C):
     """Grid-stride loops that wrap several times, single workgroups, small
-    and large workgroups: same results."""
-    banner("ml launch %s" % launch)
-    prog = W.ml_program(n=5003, seed=9, features=200, classes=10, categories=16)
+    and large workgroups, one or two rows per thread (with an odd row count,
+    so the second row of the last thread is out of range): same results."""
+    banner("ml launch %s C=%d" % (launch, C))
+    F = 200 if C == 10 else 127
+    # 5004 rows: a multiple of 4, so the four-row variant runs (5003 would fall back to one row)
+    prog = W.ml_program(n=5004 if launch["ridge_proba"][2] == 4 else 5003, seed=9, features=F, classes=C,
+                        categories=16)
     ref = G.oracle_run(prog)
     outs, _ = run(prog, launch)
     for name in ("Pnb", "Prr", "Pavg"):
         G.assert_close(prog, name, outs[name], ref[name])
-    check_labels(outs["label"], ref["label"], ref["Pavg"], 10)
+    check_labels(outs["label"], ref["label"], ref["Pavg"], C)
 
 
 @pytest.mark.parametrize("n,C,tied", [(4099, 10, False), (4099, 10, True), (333, 1, True), (1000, 16, True)])
@@ -119,7 +129,7 @@ def test_ml_full_size_sampled():
     d = {k: prog.bufs[k].init for k in ("X", "log_theta", "log_prior", "mean", "scale", "W", "b")}
     rows = np.sort(np.random.default_rng(1).choice(n, 4096, replace=False))
     rows[0], rows[-1] = 0, n - 1
-    X = d["X"][rows]
+    X = d["X"][:, rows].T                        # stored feature-major
     pnb = T.nb_predict_proba(X, d["log_theta"], d["log_prior"])
     prr = T.ridge_predict_proba(X, d["mean"], d["scale"], d["W"], d["b"])
     avg, lab = T.ensemble_argmax(pnb, prr)
