@@ -177,12 +177,16 @@ def main():
         pris = {}
         args.max_streams = pool_for(name)
         res["max_streams"] = args.max_streams
+        res["kernel_overrides"] = tuned_dag.get(name, {}).get("kernels", {})
 
         def make(policy, trace):
             ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,
                             copy_streams=args.copy_streams, spin_wait=args.spin_wait,
                             copy_lanes=args.copy_lanes, copy_engine=args.copy_engine)
             tune.apply_kernels(ctx, tuned)
+            # near-tie kernel configurations the tuner chose for this DAG's makespan
+            for k, cfg in tuned_dag.get(name, {}).get("kernels", {}).items():
+                ctx.set_launch(k, *cfg)
             b = runner.Bound(ctx, prog, read_bytes=4)
             for dst in restore:
                 if dst not in pris:

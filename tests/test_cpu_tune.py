@@ -5,6 +5,7 @@ import pytest
 
 from paper_2012_09646_amd import dagrt as D
 from paper_2012_09646_amd import tune
+from paper_2012_09646_amd import workloads as W
 
 
 @pytest.mark.parametrize("kernel", sorted(D.KERNEL_IDS))
@@ -81,3 +82,26 @@ def test_dag_choice_prefers_configurations_that_fit_the_queues(tmp_path, monkeyp
     tune.main()
     d = tune.load(out)["dag"]["bs"]
     assert d["hw_queues"] == 8 and d["max_streams"] == 1
+
+
+def test_near_ties_are_broken_by_makespan():
+    """A kernel configuration within 3 % of the fastest alone is kept for a
+    DAG when it shortens the makespan by more than 1 %; one that does not is
+    left out."""
+    prog = W.ml_program(n=64, seed=1, features=8, classes=3, categories=4)
+    kernels = {"nb_proba": {"block": 1024, "grid_cap": 256, "variant": 2,
+                            "near": [[1024, 256, 0, 101.0], [512, 256, 0, 102.0]]},
+               "ridge_proba": {"block": 256, "grid_cap": 0, "variant": 4, "near": [[256, 0, 0, 100.5]]}}
+    best = {"max_streams": 2, "copy_streams": 0, "copy_lanes": 1, "ms": 0.50}
+    seen = []
+
+    def fake(prog_, kern, over, ms, cm, lanes, restore, runs):
+        seen.append(dict(over))
+        if over.get("nb_proba") == (1024, 256, 0):
+            return (0.40 if "ridge_proba" not in over else 0.399), 2
+        return 0.52, 2
+
+    over, ms = tune.break_ties(prog, kernels, best, measure=fake)
+    assert over == {"nb_proba": [1024, 256, 0]} and ms == 0.40
+    assert {"nb_proba": (512, 256, 0)} in seen                      # every near tie was tried
+    assert {"nb_proba": (1024, 256, 0), "ridge_proba": (256, 0, 0)} in seen
