@@ -9,7 +9,7 @@ workload (so every input holds realistic data), summed over the kernel's
 occurrences, and the fastest is kept.  The DAG knobs (stream pool size, copy
 placement, hardware queue count) are then chosen by the median makespan of
 whole runs, and kernel configurations within 3 % of the fastest alone are
-retried inside the DAG (the fastest alone can take every CU's registers and
+retried inside the DAG, kept only when they shorten it by more than 3 % (the fastest alone can take every CU's registers and
 leave nothing for a kernel that could run beside it).  Each
 GPU_MAX_HW_QUEUES value is tried in a process of its own, since HIP fixes it
 at start-up (the orchestrating process never touches the GPU).  Results are
@@ -159,23 +159,30 @@ def makespan(prog, kernels, overrides, ms, cm, lanes, restore=(), runs=15):
     return statistics.median(ts), streams
 
 
-def break_ties(prog, kernels, best, restore=(), runs=15, log=None, measure=None):
+def break_ties(prog, kernels, best, restore=(), runs=15, rounds=3, log=None, measure=None):
     """For every kernel of `prog` with near-tie configurations, try each in
     the DAG (one kernel at a time, the others at their current choice) with
-    the chosen pool and copy placement; keep one if the makespan drops by
-    more than 1 %.  Returns ({kernel: [block, cap, variant]}, makespan)."""
+    the chosen pool and copy placement.  The current choice and the trial are
+    measured alternately, `rounds` times each (makespans of separate contexts
+    vary by several per cent), and the trial is kept if its median over the
+    rounds is more than 3 % below the current one's.  Returns
+    ({kernel: [block, cap, variant]}, makespan)."""
     measure = measure or makespan
     used = sorted({o["kernel"] for o in prog.ops if o["kind"] == "kernel"})
+    cfg = (best["max_streams"], best["copy_streams"], best["copy_lanes"])
     chosen = {}
     cur = best["ms"]
     for k in used:
         for alt in (kernels.get(k) or {}).get("near", []):
             trial = dict(chosen, **{k: tuple(alt[:3])})
-            m, _ = measure(prog, kernels, trial, best["max_streams"], best["copy_streams"], best["copy_lanes"],
-                           restore, runs)
+            mb, mt = [], []
+            for _ in range(rounds):
+                mb.append(measure(prog, kernels, chosen, *cfg, restore, runs)[0])
+                mt.append(measure(prog, kernels, trial, *cfg, restore, runs)[0])
+            base, m = statistics.median(mb), statistics.median(mt)
             if log:
-                log("dag %s: %s=%s %.4f ms (now %.4f)" % (prog.name, k, tuple(alt[:3]), m, cur))
-            if m < cur * 0.99:
+                log("dag %s: %s=%s %.4f ms against %.4f" % (prog.name, k, tuple(alt[:3]), m, base))
+            if m < base * 0.97:
                 chosen, cur = trial, m
     return {k: list(v) for k, v in chosen.items()}, cur
 

@@ -86,8 +86,8 @@ def test_dag_choice_prefers_configurations_that_fit_the_queues(tmp_path, monkeyp
 
 def test_near_ties_are_broken_by_makespan():
     """A kernel configuration within 3 % of the fastest alone is kept for a
-    DAG when it shortens the makespan by more than 1 %; one that does not is
-    left out."""
+    DAG when it shortens the makespan by more than 3 % against the current
+    choice measured in the same rounds; one that does not is left out."""
     prog = W.ml_program(n=64, seed=1, features=8, classes=3, categories=4)
     kernels = {"nb_proba": {"block": 1024, "grid_cap": 256, "variant": 2,
                             "near": [[1024, 256, 0, 101.0], [512, 256, 0, 102.0]]},
@@ -98,7 +98,7 @@ def test_near_ties_are_broken_by_makespan():
     def fake(prog_, kern, over, ms, cm, lanes, restore, runs):
         seen.append(dict(over))
         if over.get("nb_proba") == (1024, 256, 0):
-            return (0.40 if "ridge_proba" not in over else 0.399), 2
+            return (0.40 if "ridge_proba" not in over else 0.395), 2   # the second gain is below 3 %
         return 0.52, 2
 
     over, ms = tune.break_ties(prog, kernels, best, measure=fake)
