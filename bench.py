@@ -66,6 +66,9 @@ def parse():
                          "only, all others the remaining lanes (0 = any lane); 3 lanes with 1 for transfers "
                          "sustained the 2000/s mix (p50 1.7 ms) where 2 shared lanes saturated at ~1890/s")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate per second")
+    ap.add_argument("--capacity-rate", type=float, default=4000.0,
+                    help="serving: an overload rate (half the requests, concurrent mode only) whose throughput "
+                         "is the loop's capacity (0 = skip)")
     ap.add_argument("--low-rate", type=float, default=600.0,
                     help="serving: a second, lower arrival rate (half the requests; 0 = skip)")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"),
@@ -99,7 +102,8 @@ def orchestrate(args):
            "--max-streams", str(args.max_streams), "--copy-streams", str(args.copy_streams),
            "--copy-lanes", str(args.copy_lanes), "--copy-engine", str(args.copy_engine),
            "--spin-wait", str(args.spin_wait), "--requests", str(args.requests), "--rate", str(args.rate),
-           "--low-rate", str(args.low_rate), "--serve-lanes", str(args.serve_lanes),
+           "--low-rate", str(args.low_rate), "--capacity-rate", str(args.capacity_rate),
+           "--serve-lanes", str(args.serve_lanes),
            "--serve-copy-lanes", str(args.serve_copy_lanes), "--serve-copy-engine", str(args.serve_copy_engine),
            "--serve-transfer-lanes", str(args.serve_transfer_lanes)]
     if args.hw_queues:
@@ -141,6 +145,7 @@ def main():
     import numpy as np  # noqa: F401
 
     from paper_2012_09646_amd import dagrt as D
+    from paper_2012_09646_amd import handwritten
     from paper_2012_09646_amd import metrics as M
     from paper_2012_09646_amd import runner
     from paper_2012_09646_amd import serving
@@ -356,6 +361,10 @@ def main():
         # dag_region_run_begin/end: recorded once, then replayed when every call
         # matches (graph mode 2: a hipGraph unless the region copies to or from the host)
         forms.append((2, "recurring", args.copy_engine))
+        # hand-written schedules (streams and waits chosen by hand, checked
+        # against the inferred edges): multi-stream replay and hipGraph, the
+        # paper's hand-optimized baselines
+        forms += [(1, "hand", args.copy_engine), (0, "hand_graph", args.copy_engine)]
         for gm, tag, engine in forms:
             ctxG = D.Context(policy=D.DAG_PARALLEL_ASYNC, max_streams=args.max_streams, graph_mode=gm,
                              copy_streams=args.copy_streams, spin_wait=args.spin_wait,
@@ -378,6 +387,8 @@ def main():
             else:
                 bG.record(1)
                 go = lambda: bG.replay(1, 1)
+            if tag.startswith("hand"):
+                handwritten.install(ctxG, 1, prog)
             ctxG.sync()
             log(name, tag)
             gt = []
@@ -420,10 +431,14 @@ def main():
         for t in tmpls:
             sid = srv.add(t)
             foot.append(srv.footprint(sid))
-        def one_rate(rate, nreq):
+        def one_rate(rate, nreq, serial=True):
             arr, shp = W.poisson_trace(4, nreq, rate, len(tmpls))
             log("serving: %d requests at %g/s, %d shapes" % (len(arr), rate, len(tmpls)))
             mix, st, _ = srv.run(arr, shp)
+            if not serial:
+                return {"requests": len(arr), "rate_per_s": rate,
+                        "concurrent": {"p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "req_per_s": st.req_per_s,
+                                       "max_inflight": st.max_inflight, "max_queued": st.max_queued}}
             log("serving: serial baseline")
             ser, st2, _ = srv.run(arr, shp, mode=D.DAG_SERVE_SERIAL)
             return {
@@ -444,6 +459,9 @@ def main():
         # a second, lower arrival rate at which the serial baseline is not overloaded
         if args.low_rate:
             out["low_rate"] = one_rate(args.low_rate, max(1, args.requests // 2))
+        # an arrival rate past what the loop can serve: its throughput there is the capacity
+        if args.capacity_rate:
+            out["capacity"] = one_rate(args.capacity_rate, max(1, args.requests // 2), serial=False)
         srv.close()
         ctx.close()
         return out
@@ -513,6 +531,12 @@ def main():
         "replay_speedup": round(head["replay_speedup"], 4),
         "recurring_ms": round(head["recurring_ms"], 4),
         "recurring_speedup": round(head["recurring_speedup"], 4),
+        # hand-written streams and waits (multi-stream replay, hipGraph); the
+        # scheduler's makespan relative to them (> 1: the scheduler is slower)
+        "hand_ms": round(head["hand_ms"], 4),
+        "hand_graph_ms": round(head["hand_graph_ms"], 4),
+        "vs_hand": round(head["makespan_ms"] / head["hand_ms"], 4),
+        "vs_hand_graph": round(head["makespan_ms"] / head["hand_graph_ms"], 4),
     }
     if "graph_kernel_copies_ms" in head:
         line["graph_kernel_copies_ms"] = round(head["graph_kernel_copies_ms"], 4)

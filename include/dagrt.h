@@ -417,6 +417,23 @@ dag_status dag_region_launch(dag_ctx ctx, uint64_t key, dag_task* out);
  * (DAG_E_BUSY).  out and replayed may be NULL. */
 dag_status dag_region_run_begin(dag_ctx ctx, uint64_t key);
 dag_status dag_region_run_end(dag_ctx ctx, dag_task* out, uint32_t* replayed);
+/* Hand-written schedules (the paper compares its scheduler with
+ * hand-optimized multi-stream code and CUDA Graphs, Sec. V-D): replace the
+ * stream assignment and event waits of a recorded region with the caller's.
+ * sched[k] belongs to the region's k-th recorded call: its stream (0..63)
+ * and the earlier calls (indices < k) it waits for through events; calls on
+ * one stream run in recording order.  The schedule must order every
+ * dependency the region's calls have among themselves (checked against the
+ * inferred edges: DAG_E_INVAL names the first call that is not ordered after
+ * one of its parents).  The region is then rebuilt as the context's graph
+ * mode says (hipGraph or multi-stream replay) and launched with
+ * dag_region_launch as before.  n must equal the region's call count. */
+typedef struct {
+  uint32_t stream;
+  uint32_t nwaits;
+  const uint32_t* waits;
+} dag_sched;
+dag_status dag_region_set_schedule(dag_ctx ctx, uint64_t key, const dag_sched* sched, uint32_t n);
 /* Number of recorded tasks and distinct streams of a region. */
 dag_status dag_region_info(dag_ctx ctx, uint64_t key, uint32_t* ntasks, uint32_t* nstreams);
 dag_status dag_region_drop(dag_ctx ctx, uint64_t key);

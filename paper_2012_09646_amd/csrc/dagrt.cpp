@@ -1107,13 +1107,8 @@ dag_status dag_region_begin(dag_ctx c, uint64_t key) {
   return DAG_OK;
 }
 
-dag_status dag_region_end(dag_ctx c) {
-  CHECK_CTX(c);
-  if (!c->recording) return fail(c, DAG_E_BUSY, "no region is being recorded");
-  c->recording = false;
-  std::unique_ptr<Region> r = std::move(c->rec);
-  if (r->tasks.empty()) return fail(c, DAG_E_INVAL, "empty region");
-  plan_region(c, r.get());
+// Build the hipGraph of a planned region when the graph mode asks for one.
+static dag_status finish_region(dag_ctx c, Region* r) {
   bool host_copies = false;
   for (const RegionTask& t : r->tasks)
     if (t.kind == TK_COPY && (t.ckind == hipMemcpyHostToDevice || t.ckind == hipMemcpyDeviceToHost))
@@ -1122,12 +1117,23 @@ dag_status dag_region_end(dag_ctx c) {
   // hipGraph their copies become blit kernels on the CUs instead of SDMA copies
   const bool as_graph = c->cfg.graph_mode == 0 || (c->cfg.graph_mode == 2 && !host_copies);
   if (!c->dry && as_graph) {
-    dag_status st = build_graph(c, r.get());
+    dag_status st = build_graph(c, r);
     if (st) {
-      free_region(r.get());
+      free_region(r);
       return st;
     }
   }
+  return DAG_OK;
+}
+
+dag_status dag_region_end(dag_ctx c) {
+  CHECK_CTX(c);
+  if (!c->recording) return fail(c, DAG_E_BUSY, "no region is being recorded");
+  c->recording = false;
+  std::unique_ptr<Region> r = std::move(c->rec);
+  if (r->tasks.empty()) return fail(c, DAG_E_INVAL, "empty region");
+  plan_region(c, r.get());
+  if (dag_status st = finish_region(c, r.get())) return st;
   auto it = c->regions.find(c->rec_key);
   if (it != c->regions.end()) {
     if (!c->dry) (void)hipDeviceSynchronize();
@@ -1169,6 +1175,56 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   st = end_task(c, id, s);
   c->launch_us += us_since(t1);
   return st;
+}
+
+dag_status dag_region_set_schedule(dag_ctx c, uint64_t key, const dag_sched* sched, uint32_t n) {
+  CHECK_CTX(c);
+  if (c->in_region()) return fail(c, DAG_E_BUSY, "schedule change while a region is open");
+  auto it = c->regions.find(key);
+  if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
+  Region* r = it->second.get();
+  if (!sched || n != r->tasks.size())
+    return fail(c, DAG_E_INVAL, "the schedule needs one entry per recorded call (%zu)", r->tasks.size());
+  // vector clocks of the hand-written order: snap[k][s] = the last position
+  // on stream s that call k is ordered after (same stream or event waits)
+  uint32_t ns = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (sched[k].stream >= DAG_MAX_STREAMS) return fail(c, DAG_E_INVAL, "call %u: stream must be < 64", k);
+    if (sched[k].nwaits && !sched[k].waits) return fail(c, DAG_E_INVAL, "call %u: waits is NULL", k);
+    for (uint32_t i = 0; i < sched[k].nwaits; ++i)
+      if (sched[k].waits[i] >= k) return fail(c, DAG_E_INVAL, "call %u: waits must name earlier calls", k);
+    ns = std::max(ns, sched[k].stream + 1);
+  }
+  std::vector<std::vector<uint32_t>> snap(n, std::vector<uint32_t>(ns, 0));
+  std::vector<std::vector<uint32_t>> vc(ns, std::vector<uint32_t>(ns, 0));
+  std::vector<uint32_t> pos(n), npos(ns, 0);
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t sk = sched[k].stream;
+    std::vector<uint32_t> v = vc[sk];
+    for (uint32_t i = 0; i < sched[k].nwaits; ++i) {
+      const std::vector<uint32_t>& w = snap[sched[k].waits[i]];
+      for (uint32_t q = 0; q < ns; ++q) v[q] = std::max(v[q], w[q]);
+    }
+    pos[k] = ++npos[sk];
+    v[sk] = pos[k];
+    for (uint32_t p : r->tasks[k].rparents)
+      if (v[sched[p].stream] < pos[p])
+        return fail(c, DAG_E_INVAL, "call %u is not ordered after call %u, which it depends on", k, p);
+    snap[k] = v;
+    vc[sk] = std::move(v);
+  }
+  if (!c->dry) HIP_TRY(c, hipDeviceSynchronize());  // the region may be in flight
+  free_region(r);
+  for (uint32_t k = 0; k < n; ++k) {
+    RegionTask& t = r->tasks[k];
+    t.rstream = static_cast<int32_t>(sched[k].stream);
+    t.rwaits.assign(sched[k].waits, sched[k].waits + sched[k].nwaits);
+    t.waited_on = false;
+  }
+  for (uint32_t k = 0; k < n; ++k)
+    for (uint32_t w : r->tasks[k].rwaits) r->tasks[w].waited_on = true;
+  r->nstreams = ns;
+  return finish_region(c, r);
 }
 
 dag_status dag_region_info(dag_ctx c, uint64_t key, uint32_t* ntasks, uint32_t* nstreams) {

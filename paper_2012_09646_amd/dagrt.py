@@ -104,6 +104,10 @@ class dag_p_spin(C.Structure):
     _fields_ = [("ns", C.c_uint64)]
 
 
+class dag_sched(C.Structure):
+    _fields_ = [("stream", C.c_uint32), ("nwaits", C.c_uint32), ("waits", C.POINTER(C.c_uint32))]
+
+
 class dag_p_ml(C.Structure):
     _fields_ = [("n", C.c_uint64), ("features", C.c_uint32), ("classes", C.c_uint32),
                 ("categories", C.c_uint32), ("reserved", C.c_uint32)]
@@ -172,6 +176,7 @@ _SIGS = {
     "dag_region_end": (_st, [_ctx_t]),
     "dag_region_launch": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint64)]),
     "dag_region_info": (_st, [_ctx_t, C.c_uint64, _P(C.c_uint32), _P(C.c_uint32)]),
+    "dag_region_set_schedule": (_st, [_ctx_t, C.c_uint64, _P(dag_sched), C.c_uint32]),
     "dag_region_drop": (_st, [_ctx_t, C.c_uint64]),
     "dag_region_run_begin": (_st, [_ctx_t, C.c_uint64]),
     "dag_region_run_end": (_st, [_ctx_t, _P(C.c_uint64), _P(C.c_uint32)]),
@@ -380,6 +385,19 @@ def dag_region_info(ctx, key):
     a, b = C.c_uint32(), C.c_uint32()
     _check(ctx, lib().dag_region_info(ctx, key, C.byref(a), C.byref(b)))
     return a.value, b.value
+
+
+def dag_region_set_schedule(ctx, key, sched):
+    """sched: one (stream, [earlier call indices waited for]) per recorded call."""
+    arr = (dag_sched * max(len(sched), 1))()
+    keep = []
+    for k, (stream, waits) in enumerate(sched):
+        w = (C.c_uint32 * max(len(waits), 1))(*waits)
+        keep.append(w)
+        arr[k].stream = int(stream)
+        arr[k].nwaits = len(waits)
+        arr[k].waits = C.cast(w, _P(C.c_uint32))
+    _check(ctx, lib().dag_region_set_schedule(ctx, key, arr, len(sched)))
 
 
 def dag_region_drop(ctx, key):

@@ -406,3 +406,45 @@ def test_ml_kernel_argument_checks():
     assert _status(ctx.kernel, "ensemble", [(big, "c"), (b2, "c"), (out, "c"), (lab, "m")],
                    n=10, features=1, classes=10) == "DAG_E_INVAL"
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["vec", "bs", "img", "hits", "ml"])
+def test_hand_written_schedules_order_every_dependency(name):
+    """Each workload's hand-written schedule passes the library's check
+    against the inferred dependencies (schedule-only context)."""
+    from paper_2012_09646_amd import handwritten as H
+    small = {"vec": lambda: W.vec_program(n=1024), "bs": lambda: W.bs_program(n=1024, tasks=10),
+             "img": lambda: W.img_program(side=64), "hits": lambda: W.hits_program(n=256, deg=4, iters=3),
+             "ml": lambda: W.ml_program(n=100, features=8, classes=3, categories=4)}
+    prog = small[name]()
+    ctx = D.Context(dry_run=True)
+    b = runner.Bound(ctx, prog)
+    if name == "hits":
+        b.record(7, 0, H.HITS_CALLS_PER_ITERATION)
+    else:
+        b.record(7)
+    H.install(ctx, 7, prog)
+    n, ns = D.dag_region_info(ctx.h, 7)
+    assert ns == max(s for s, _ in H.schedule(prog)) + 1
+    ctx.close()
+
+
+def test_hand_written_schedule_missing_a_wait_is_refused():
+    ctx = D.Context(dry_run=True)
+    prog = W.vec_program(n=1024)
+    b = runner.Bound(ctx, prog)
+    b.record(3)
+    with pytest.raises(D.DagError) as e:        # the sum on stream 0 without waiting for y^2 on stream 1
+        D.dag_region_set_schedule(ctx.h, 3, [(0, []), (1, []), (0, [])])
+    assert e.value.name == "DAG_E_INVAL" and "call 2" in str(e.value)
+    with pytest.raises(D.DagError):              # a wait on a later call
+        D.dag_region_set_schedule(ctx.h, 3, [(0, [1]), (1, []), (0, [1])])
+    with pytest.raises(D.DagError):              # wrong length
+        D.dag_region_set_schedule(ctx.h, 3, [(0, []), (1, [])])
+    with pytest.raises(D.DagError):              # stream out of range
+        D.dag_region_set_schedule(ctx.h, 3, [(0, []), (64, []), (0, [1])])
+    D.dag_region_set_schedule(ctx.h, 3, [(0, []), (0, []), (0, [])])   # one stream: program order suffices
+    assert D.dag_region_info(ctx.h, 3) == (3, 1)
+    D.dag_region_set_schedule(ctx.h, 3, [(0, []), (1, []), (2, [0, 1])])
+    assert D.dag_region_info(ctx.h, 3) == (3, 3)
+    ctx.close()

@@ -317,3 +317,38 @@ def test_region_replays(graph_mode):
         for name in prog.outputs:
             G.assert_close(prog, name, b.read(name), ref[name])
         ctx.close()
+
+
+@pytest.mark.parametrize("graph_mode", [0, 1])
+@pytest.mark.parametrize("name", ["vec", "bs", "img", "hits", "ml"])
+def test_hand_written_schedules(name, graph_mode):
+    """Each workload's region with its hand-written streams and waits (as a
+    hipGraph or a multi-stream replay) reproduces the oracle's outputs; the
+    recording run itself is undone by restoring the initial contents first."""
+    from paper_2012_09646_amd import handwritten as H
+    from paper_2012_09646_amd import runner
+    banner("hand-written schedule %s graph_mode=%d" % (name, graph_mode))
+    progs = {"vec": lambda: W.vec_program(n=(1 << 16) + 3, seed=21),
+             "bs": lambda: W.bs_program(n=100003, tasks=10, seed=22),
+             "img": lambda: W.img_program(side=333, seed=23),
+             "hits": lambda: W.hits_program(n=3000, deg=20, iters=10, seed=24),
+             "ml": lambda: W.ml_program(n=5003, seed=25, features=200, classes=10, categories=16)}
+    prog = progs[name]()
+    ref = G.oracle_run(prog)
+    ctx = D.Context(graph_mode=graph_mode)
+    try:
+        b = runner.Bound(ctx, prog)
+        if name == "hits":
+            b.record(1, 0, H.HITS_CALLS_PER_ITERATION)
+            times = 10
+        else:
+            b.record(1)
+            times = 1
+        H.install(ctx, 1, prog)
+        ctx.sync()
+        b.upload()             # back to the initial contents, outputs cleared
+        b.replay(1, times)
+        for o in prog.outputs:
+            G.assert_close(prog, o, b.read(o), ref[o])
+    finally:
+        ctx.close()
