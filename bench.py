@@ -407,7 +407,17 @@ def main():
                 ctxG.host_write(bG.h[o], np.zeros(prog.bufs[o].nbytes, np.uint8))
             reset(ctxG, bG)
             go()
-            res[tag + "_matches_eager"] = all(np.array_equal(bG.read(o), eager_out[o]) for o in prog.outputs)
+            got = {o: bG.read(o) for o in prog.outputs}
+            res[tag + "_matches_eager"] = all(np.array_equal(got[o], eager_out[o]) for o in prog.outputs)
+            if not res[tag + "_matches_eager"]:
+                # which outputs differ (bytes differing, of them zero) and whether they still
+                # differ after a full device synchronisation
+                res[tag + "_mismatch"] = {o: [int(np.sum(got[o] != eager_out[o])),
+                                              int(np.sum((got[o] != eager_out[o]) & (got[o] == 0)))]
+                                          for o in prog.outputs if not np.array_equal(got[o], eager_out[o])}
+                ctxG.sync()
+                res[tag + "_matches_after_sync"] = all(np.array_equal(bG.read(o), eager_out[o])
+                                                       for o in prog.outputs)
             ctxG.close()
         return res, ktimes
 

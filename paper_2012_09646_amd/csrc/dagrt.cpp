@@ -497,6 +497,15 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
   if (out) *out = id;
   if (kind == TK_HOST_WRITE) b->plan_valid = false;
   char* p = static_cast<char*>(b->ptr) + off;
+  // After a hipGraph launch, waiting on the event recorded behind it on its
+  // stream was seen to return while part of a kernel node's output was not
+  // yet readable by the host copy (a multi-branch graph; a device-wide
+  // synchronisation before the access removed it), so the first host access
+  // after a graph launch synchronises the device.
+  if (!c->dry && c->graph_pending && !c->tmp_wait.empty()) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    c->graph_pending = false;
+  }
   // A read of device memory that waits on its writer: copy on the writer's
   // stream into pinned staging and wait once (one host<->device round trip).
   if (!c->dry && kind == TK_HOST_READ && hdst && bytes && bytes <= kStagingBytes &&
@@ -544,6 +553,10 @@ dag_status do_sync(dag_ctx c) {
   if (c->in_region()) return fail(c, DAG_E_BUSY, "sync inside a region");
   c->tr.add_sync();
   if (!c->dry) {
+    if (c->graph_pending) {
+      HIP_TRY(c, hipDeviceSynchronize());
+      c->graph_pending = false;
+    }
     for (hipStream_t s : c->streams) HIP_TRY(c, hipStreamSynchronize(s));
     for (hipStream_t s : c->aux) HIP_TRY(c, hipStreamSynchronize(s));
     for (void* p : c->dead_plans) HIP_TRY(c, hipFree(p));
@@ -1167,6 +1180,7 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   if (!c->dry) {
     if (r->exec) {
       HIP_TRY(c, hipGraphLaunch(r->exec, c->streams[s]));
+      c->graph_pending = true;
     } else {
       st = replay_region(c, r, c->streams[s], s);
       if (st) return st;

@@ -154,3 +154,29 @@ def test_ml_zero_rows():
         ctx.sync()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("graph_mode", [0, 2])
+def test_ml_graph_region_outputs_read_right_after_the_launch(graph_mode):
+    """The ML DAG recorded as a hipGraph region (graph mode 0, and mode 2,
+    which also makes it a graph since it has no host copies), replayed many
+    times, then once more into cleared outputs: every output read right
+    after that launch equals the eager run bit for bit."""
+    banner("ml graph region reads graph_mode=%d" % graph_mode)
+    n = 1 << 18
+    prog = W.ml_program(n=n, seed=5)
+    outs, _ = run(prog)
+    ctx = D.Context(graph_mode=graph_mode)
+    try:
+        b = runner.Bound(ctx, prog, read_bytes=4)
+        b.record(1)
+        ctx.sync()
+        for _ in range(30):
+            b.replay(1, 1)
+        for o in prog.outputs:
+            ctx.host_write(b.h[o], np.zeros(prog.bufs[o].nbytes, np.uint8))
+        b.replay(1, 1)
+        for o in prog.outputs:
+            assert np.array_equal(b.read(o), outs[o]), o
+    finally:
+        ctx.close()
