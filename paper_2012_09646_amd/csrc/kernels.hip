@@ -979,11 +979,7 @@ __device__ __forceinline__ void nb_add(double (&acc)[C], const float* __restrict
   }
 }
 
-// R rows per thread: a workgroup covers R * blockDim consecutive rows, row
-// j * blockDim + tid of the tile going to thread tid, so every load of a wave
-// still reads 256 contiguous bytes and each thread has R * kMlUnroll loads in
-// flight.
-template <int C, int R>
+template <int C>
 __global__ __launch_bounds__(1024) void k_nb_proba(const float* __restrict__ X, const float* __restrict__ lt,
                                                    const float* __restrict__ lp, float* __restrict__ P,
                                                    uint64_t n, uint32_t F, uint32_t V) {
@@ -999,37 +995,22 @@ __global__ __launch_bounds__(1024) void k_nb_proba(const float* __restrict__ X, 
   for (int c = 0; c < C; ++c) prior[c] = static_cast<double>(lp[c]);
   const float vmax = static_cast<float>(V - 1);
   const uint32_t tstride = V * C;  // table floats per feature
-  const uint64_t tile = static_cast<uint64_t>(blockDim.x) * R;
-  for (uint64_t base = blockIdx.x * tile; base < n; base += gridDim.x * tile) {
-    // rows past the end read the last row (in bounds, no branches) and are not stored
-    uint64_t row[R];
-    const float* xr[R];
-    double acc[R][C];
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < n; r += stride) {
+    double acc[C];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      row[j] = base + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
-      xr[j] = X + (row[j] < n ? row[j] : n - 1);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[j][c] = prior[c];
-    }
+    for (int c = 0; c < C; ++c) acc[c] = prior[c];
+    const float* col = X + r;
     uint32_t f = 0;
     for (; f + kMlUnroll <= F; f += kMlUnroll) {
-      float x[kMlUnroll][R];
+      float x[kMlUnroll];
 #pragma unroll
-      for (int u = 0; u < kMlUnroll; ++u)
+      for (int u = 0; u < kMlUnroll; ++u) x[u] = col[static_cast<uint64_t>(f + u) * n];
 #pragma unroll
-        for (int j = 0; j < R; ++j) x[u][j] = xr[j][static_cast<uint64_t>(f + u) * n];
-#pragma unroll
-      for (int u = 0; u < kMlUnroll; ++u)
-#pragma unroll
-        for (int j = 0; j < R; ++j) nb_add<C>(acc[j], s_tab + (f + u) * tstride, vmax, x[u][j]);
+      for (int u = 0; u < kMlUnroll; ++u) nb_add<C>(acc, s_tab + (f + u) * tstride, vmax, x[u]);
     }
-    for (; f < F; ++f)
-#pragma unroll
-      for (int j = 0; j < R; ++j) nb_add<C>(acc[j], s_tab + f * tstride, vmax, xr[j][static_cast<uint64_t>(f) * n]);
-#pragma unroll
-    for (int j = 0; j < R; ++j)
-      if (row[j] < n) softmax_store<C>(acc[j], P + row[j] * C);
+    for (; f < F; ++f) nb_add<C>(acc, s_tab + f * tstride, vmax, col[static_cast<uint64_t>(f) * n]);
+    softmax_store<C>(acc, P + r * C);
   }
 }
 
@@ -1041,11 +1022,11 @@ __device__ __forceinline__ void ridge_add(double (&acc)[C], const double* __rest
   for (int c = 0; c < C; ++c) acc[c] = fma(d, w[c], acc[c]);
 }
 
-template <int C, int R>
+template <int C>
 __global__ __launch_bounds__(512) void k_ridge_proba(const float* __restrict__ X, const float* __restrict__ mean,
-                                                      const float* __restrict__ scale, const float* __restrict__ W,
-                                                      const float* __restrict__ b, float* __restrict__ P,
-                                                      uint64_t n, uint32_t F) {
+                                                     const float* __restrict__ scale, const float* __restrict__ W,
+                                                     const float* __restrict__ b, float* __restrict__ P,
+                                                     uint64_t n, uint32_t F) {
   extern __shared__ __align__(16) double s_w[];  // [f][c] weights / scale, then F means
   double* s_mu = s_w + F * C;
   for (uint32_t i = threadIdx.x; i < C * F; i += blockDim.x) {
@@ -1057,40 +1038,37 @@ __global__ __launch_bounds__(512) void k_ridge_proba(const float* __restrict__ X
   double bias[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) bias[c] = static_cast<double>(b[c]);
-  const uint64_t tile = static_cast<uint64_t>(blockDim.x) * R;
-  for (uint64_t base = blockIdx.x * tile; base < n; base += gridDim.x * tile) {
-    // rows past the end read the last row (in bounds, no branches) and are not stored
-    uint64_t row[R];
-    const float* xr[R];
-    double acc[R][C];
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < n; r += stride) {
+    double acc[C];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      row[j] = base + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
-      xr[j] = X + (row[j] < n ? row[j] : n - 1);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[j][c] = bias[c];
-    }
+    for (int c = 0; c < C; ++c) acc[c] = bias[c];
+    const float* col = X + r;
+    // the next kMlUnroll features are loaded while the current ones are used
     uint32_t f = 0;
+    float x[kMlUnroll];
+    if (F >= static_cast<uint32_t>(kMlUnroll)) {
+#pragma unroll
+      for (int u = 0; u < kMlUnroll; ++u) x[u] = col[static_cast<uint64_t>(u) * n];
+    }
+#pragma unroll 1
     for (; f + kMlUnroll <= F; f += kMlUnroll) {
-      float x[kMlUnroll][R];
+      float xn[kMlUnroll];
+      const bool more = f + 2 * kMlUnroll <= F;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kMlUnroll; ++u) xn[u] = col[static_cast<uint64_t>(f + kMlUnroll + u) * n];
+      }
 #pragma unroll
       for (int u = 0; u < kMlUnroll; ++u)
+        ridge_add<C>(acc, s_w + (f + u) * C, static_cast<double>(x[u]) - s_mu[f + u]);
+      if (more) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) x[u][j] = xr[j][static_cast<uint64_t>(f + u) * n];
-#pragma unroll
-      for (int u = 0; u < kMlUnroll; ++u) {
-        const double mu = s_mu[f + u];
-#pragma unroll
-        for (int j = 0; j < R; ++j) ridge_add<C>(acc[j], s_w + (f + u) * C, static_cast<double>(x[u][j]) - mu);
+        for (int u = 0; u < kMlUnroll; ++u) x[u] = xn[u];
       }
     }
-    for (; f < F; ++f)
-#pragma unroll
-      for (int j = 0; j < R; ++j)
-        ridge_add<C>(acc[j], s_w + f * C, static_cast<double>(xr[j][static_cast<uint64_t>(f) * n]) - s_mu[f]);
-#pragma unroll
-    for (int j = 0; j < R; ++j)
-      if (row[j] < n) softmax_store<C>(acc[j], P + row[j] * C);
+    for (; f < F; ++f) ridge_add<C>(acc, s_w + f * C, static_cast<double>(col[static_cast<uint64_t>(f) * n]) - s_mu[f]);
+    softmax_store<C>(acc, P + r * C);
   }
 }
 
@@ -1124,19 +1102,34 @@ __global__ __launch_bounds__(256) void k_ridge_proba4(const float* __restrict__ 
 #pragma unroll
       for (int c = 0; c < C; ++c) acc[j][c] = bias[c];
     const float4* col = X4 + g;
+    // the next kU4 features are loaded while the current ones are used
+    constexpr int kU4 = kMlUnroll / 2;
     uint32_t f = 0;
-    for (; f + kMlUnroll <= F; f += kMlUnroll) {
-      float4 x[kMlUnroll];
+    float4 x[kU4];
+    if (F >= static_cast<uint32_t>(kU4)) {
 #pragma unroll
-      for (int u = 0; u < kMlUnroll; ++u) x[u] = col[static_cast<uint64_t>(f + u) * groups];
+      for (int u = 0; u < kU4; ++u) x[u] = col[static_cast<uint64_t>(u) * groups];
+    }
+#pragma unroll 1
+    for (; f + kU4 <= F; f += kU4) {
+      float4 xn[kU4];
+      const bool more = f + 2 * kU4 <= F;
+      if (more) {
 #pragma unroll
-      for (int u = 0; u < kMlUnroll; ++u) {
+        for (int u = 0; u < kU4; ++u) xn[u] = col[static_cast<uint64_t>(f + kU4 + u) * groups];
+      }
+#pragma unroll
+      for (int u = 0; u < kU4; ++u) {
         const double mu = s_mu[f + u];
         const double* w = s_w + (f + u) * C;
         ridge_add<C>(acc[0], w, static_cast<double>(x[u].x) - mu);
         ridge_add<C>(acc[1], w, static_cast<double>(x[u].y) - mu);
         ridge_add<C>(acc[2], w, static_cast<double>(x[u].z) - mu);
         ridge_add<C>(acc[3], w, static_cast<double>(x[u].w) - mu);
+      }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kU4; ++u) x[u] = xn[u];
       }
     }
     for (; f < F; ++f) {
@@ -1677,13 +1670,8 @@ const char* ml_common(const dag_p_ml* q) {
   return nullptr;
 }
 
-const char* cfg_ml(const LaunchCfg& c) {
-  if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
-  if (c.variant > 2) return "variant: rows per thread, 0 or 1 = one, 2 = two";
-  return nullptr;
-}
 const char* cfg_ridge(const LaunchCfg& c) {
-  if (c.variant > 2 && c.variant != 4) return "variant: rows per thread, 0 or 1 = one, 2 = two, 4 = four";
+  if (c.variant != 0 && c.variant != 4) return "variant: rows per thread, 0 = one, 4 = four";
   const uint32_t top = c.variant == 4 ? 256 : 512;
   if (c.block < 64 || c.block > top || c.block % 64)
     return "block must be a multiple of 64 in [64, 512] ([64, 256] for variant 4)";
@@ -1710,22 +1698,14 @@ const char* v_nb(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, si
 hipError_t l_nb(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const dag_p_ml* q = pml(p);
   if (q->n == 0) return hipSuccess;
-  // two rows per thread within the register budget of 1024-thread workgroups
-  const bool two = c.variant == 2 && q->classes <= 11;
-  const dim3 g(stream_grid(ceil_div(q->n, two ? 2 : 1), c)), b(c.block);
+  const dim3 g(stream_grid(q->n, c)), b(c.block);
   const auto* X = static_cast<const float*>(a[0]);
   const auto* lt = static_cast<const float*>(a[1]);
   const auto* lp = static_cast<const float*>(a[2]);
   auto* P = static_cast<float*>(a[3]);
   switch (q->classes) {
-#define DAGRT_NB_CASE(K)                                                                                   \
-  case K:                                                                                                  \
-    if (two)                                                                                               \
-      DAGRT_LAUNCH((k_nb_proba<K, (K <= 11 ? 2 : 1)>), g, b, 0, s, X, lt, lp, P, q->n, q->features,       \
-                   q->categories);                                                                         \
-    else                                                                                                   \
-      DAGRT_LAUNCH((k_nb_proba<K, 1>), g, b, 0, s, X, lt, lp, P, q->n, q->features, q->categories);        \
-    break;
+#define DAGRT_NB_CASE(K) \
+  case K: DAGRT_LAUNCH(k_nb_proba<K>, g, b, 0, s, X, lt, lp, P, q->n, q->features, q->categories); break;
     DAGRT_ML_CLASSES(DAGRT_NB_CASE)
 #undef DAGRT_NB_CASE
     default: return hipErrorInvalidValue;
@@ -1752,8 +1732,7 @@ hipError_t l_ridge(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   if (q->n == 0) return hipSuccess;
   // four rows per thread need 16-byte aligned float4 columns (n % 4 == 0), else one row
   const bool four = c.variant == 4 && q->n % 4 == 0 && aligned16(a[0]);
-  const bool two = c.variant == 2;
-  const dim3 g(stream_grid(four ? q->n / 4 : ceil_div(q->n, two ? 2 : 1), c)), b(c.block);
+  const dim3 g(stream_grid(four ? q->n / 4 : q->n, c)), b(c.block);
   const size_t shm = ridge_lds_bytes(q);
   const auto* X = static_cast<const float*>(a[0]);
   const auto* mean = static_cast<const float*>(a[1]);
@@ -1766,10 +1745,8 @@ hipError_t l_ridge(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   case K:                                                                                                  \
     if (four)                                                                                              \
       DAGRT_LAUNCH((k_ridge_proba4<K>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);      \
-    else if (two)                                                                                          \
-      DAGRT_LAUNCH((k_ridge_proba<K, 2>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);    \
     else                                                                                                   \
-      DAGRT_LAUNCH((k_ridge_proba<K, 1>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);    \
+      DAGRT_LAUNCH((k_ridge_proba<K>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);       \
     break;
     DAGRT_ML_CLASSES(DAGRT_RIDGE_CASE)
 #undef DAGRT_RIDGE_CASE
@@ -1821,7 +1798,7 @@ const KernelDesc kTable[] = {
     /* 12 */ {"scale_l2", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_scale, l_scale, cfg_block_any},
     /* 13 */ {"spin", 0, 0x0, sizeof(dag_p_spin), {64, 0, 0}, v_spin, l_spin, cfg_spin},
     /* 14 */ {"copy_f32", 2, 0x2, sizeof(dag_p_n), {256, 0, 0}, v_copy, l_copy, cfg_block_any},
-    /* 15 */ {"nb_proba", 4, 0x8, sizeof(dag_p_ml), {1024, 256, 0}, v_nb, l_nb, cfg_ml},
+    /* 15 */ {"nb_proba", 4, 0x8, sizeof(dag_p_ml), {1024, 256, 0}, v_nb, l_nb, cfg_ml_one},
     /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ridge},
     /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml_one},
 };
