@@ -41,6 +41,7 @@ BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25, 2: 156.25}
 # for a 256 MiB copy kernel (FETCH_SIZE 0.50006x, WRITE_SIZE 1.000x of the true bytes): 16.14 MiB in + 16.00 MiB out
 TRAFFIC_BS_BYTES = int((8262.91 / 0.50006 + 16384.0 / 1.0) * 1024)
 CUS, CLOCK_GHZ = 256, 2.4
+SERVE_HW_QUEUES = 8
 
 
 def log(*a):
@@ -132,11 +133,15 @@ def main():
         print("bench.py measures one GPU: the scheduler space-shares a single device; "
               "multi-GPU runs are not part of this build (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if not args.hw_queues and args.tuned and os.path.exists(args.tuned):
-        # the tuned hardware queue count of the headline workload; HIP reads it
-        # once at start-up, so it is set before anything touches the GPU
-        with open(args.tuned) as f:
-            args.hw_queues = int(json.load(f).get("dag", {}).get("bs", {}).get("hw_queues", 0))
+    if not args.hw_queues and args.tuned and os.path.exists(args.tuned) and args.workload != "all":
+        # the workload's tuned hardware queue count (the serving loop: 8, which
+        # its 3 lanes and 2 copy streams fit); HIP reads it once at start-up, so
+        # it is set before anything touches the GPU
+        if args.workload == "serve":
+            args.hw_queues = SERVE_HW_QUEUES
+        else:
+            with open(args.tuned) as f:
+                args.hw_queues = int(json.load(f).get("dag", {}).get(args.workload, {}).get("hw_queues", 0))
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.workload == "all":
@@ -183,6 +188,7 @@ def main():
         args.max_streams = pool_for(name)
         res["max_streams"] = args.max_streams
         res["kernel_overrides"] = tuned_dag.get(name, {}).get("kernels", {})
+        res["hw_queues"] = int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)
 
         def make(policy, trace):
             ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,

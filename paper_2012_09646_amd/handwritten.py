@@ -24,9 +24,13 @@ def schedule(prog):
         # x^2 and y^2 on two streams, the sum after both on the first
         return [(0, []), (1, []), (0, [1])]
     if prog.name == "bs":
-        # every stock's copy in, pricing and copy out on a stream of its own
+        # the three-stage pipeline: copies in on stream 1, pricing on stream 0,
+        # copies out on stream 2, each stage waiting for the stock's previous one
         n = sum(1 for o in prog.ops if o["kind"] in ("kernel", "copy"))
-        return [(i // 3, []) for i in range(n)]
+        out = []
+        for i in range(0, n, 3):
+            out += [(1, []), (0, [i]), (2, [i + 1])]
+        return out
     if prog.name == "img":
         # branch k (blur, Sobel, min/max, normalise) on stream k; the combine on
         # stream 0 after the other two branches' normalisation

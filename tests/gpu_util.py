@@ -31,9 +31,15 @@ def gpu_run(prog, policy=D.DAG_PARALLEL_ASYNC, max_streams=8, batch=True, trace=
     return ctx, b, outs
 
 
-def kind_of(prog, name):
-    """How a buffer is compared: 'exact' (bit-exact), 'f32', 'f64'."""
+def kind_of(prog, name, _seen=None):
+    """How a buffer is compared: 'exact' (bit-exact), 'f32', 'f64'.  A copy's
+    destination is compared like its source (the Black-Scholes prices reach
+    host memory by a copy)."""
     for op in prog.ops:
+        if op["kind"] == "copy" and op["dst"] == name:
+            seen = (_seen or set()) | {name}
+            if op["src"] not in seen:
+                return kind_of(prog, op["src"], seen)
         if op["kind"] != "kernel":
             continue
         for i, (b, m) in enumerate(op["args"]):

@@ -1,0 +1,81 @@
+"""Parity at the benchmark sizes in the launch configurations and DAG settings
+bench.py times: the tuning table's kernel configurations, its stream pool per
+workload, the mixed copy engine of the DAG runs.  Outputs against the oracle
+(sampled rows for the ML ensemble, whose rows are independent)."""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gpu_util as G
+from oracle import dag as odag
+from oracle import tasks as T
+from paper_2012_09646_amd import dagrt as D
+from paper_2012_09646_amd import runner, tune
+from paper_2012_09646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNED = os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json")
+
+
+def bench_context(name):
+    with open(TUNED) as f:
+        t = json.load(f)
+    pool = int(t.get("dag", {}).get(name, {}).get("max_streams", 8))
+    ctx = D.Context(max_streams=pool, copy_engine=2)
+    tune.apply_kernels(ctx, t["kernels"])
+    for k, cfg in t.get("dag", {}).get(name, {}).get("kernels", {}).items():
+        ctx.set_launch(k, *cfg)
+    return ctx
+
+
+@pytest.mark.parametrize("name", ["vec", "bs", "img", "hits"])
+def test_benchmark_dag_in_the_bench_configuration(name):
+    print("[gpu] bench configuration %s" % name, flush=True)
+    sys.stdout.flush()
+    prog = {"vec": lambda: W.vec_program(n=1 << 20, seed=0),
+            "bs": lambda: W.bs_program(n=1 << 22, tasks=10, seed=1),
+            "img": lambda: W.img_program(side=2048, seed=2),
+            "hits": lambda: W.hits_program(n=1 << 20, deg=20, iters=10, seed=3)}[name]()
+    ref = G.oracle_run(prog)
+    ctx = bench_context(name)
+    try:
+        b = runner.Bound(ctx, prog)
+        b.run()
+        assert b.edges() == odag.build_dag(prog.ops).edges
+        for o in prog.outputs:
+            G.assert_close(prog, o, b.read(o), ref[o])
+    finally:
+        ctx.close()
+
+
+def test_ml_in_the_bench_configuration():
+    print("[gpu] bench configuration ml", flush=True)
+    n = 1 << 20
+    prog = W.ml_program(n=n, seed=5)
+    ctx = bench_context("ml")
+    try:
+        b = runner.Bound(ctx, prog)
+        b.run()
+        outs = {o: b.read(o) for o in prog.outputs}
+    finally:
+        ctx.close()
+    d = {k: prog.bufs[k].init for k in ("X", "log_theta", "log_prior", "mean", "scale", "W", "b")}
+    rows = np.sort(np.random.default_rng(2).choice(n, 4096, replace=False))
+    rows[0], rows[-1] = 0, n - 1
+    X = d["X"][:, rows].T
+    pnb = T.nb_predict_proba(X, d["log_theta"], d["log_prior"])
+    prr = T.ridge_predict_proba(X, d["mean"], d["scale"], d["W"], d["b"])
+    avg, lab = T.ensemble_argmax(pnb, prr)
+    for name, o in (("Pnb", pnb), ("Prr", prr), ("Pavg", avg)):
+        g = outs[name].view(np.float32).reshape(n, 10)[rows].astype(np.float64)
+        assert np.all(np.abs(g - o) <= 1e-5 * np.abs(o.astype(np.float64))), name
+    got = outs["label"].view(np.int32)[rows]
+    a64 = avg.astype(np.float64)
+    for r in np.nonzero(got != lab)[0]:
+        assert a64[r, got[r]] >= a64[r].max() * (1 - 2e-5)
