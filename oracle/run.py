@@ -105,6 +105,23 @@ def _k_ensemble(p, p_nb, p_rr, avg, label):
     label.view(np.int32)[:n] = lab
 
 
+def _k_conv3x3_relu_pool(p, x, w, b, y):
+    cin, cout, h, wd = p["cin"], p["cout"], p["h"], p["w"]
+    _f32(y, cout * (h // 2) * (wd // 2))[:] = tasks.conv3x3_relu_pool(
+        _f32(x, cin * h * wd).reshape(cin, h, wd), _f32(w, cout * cin * 9).reshape(cout, cin, 3, 3),
+        _f32(b, cout)).ravel()
+
+
+def _k_dense(p, x, w, b, y):
+    n, m = p["n"], p["m"]
+    _f32(y, m)[:] = tasks.dense(_f32(x, n), _f32(w, m * n).reshape(m, n), _f32(b, m))
+
+
+def _k_siamese_combine(p, e1, e2, w, b, out):
+    m = p["m"]
+    _f32(out)[0] = tasks.siamese_combine(_f32(e1, m), _f32(e2, m), _f32(w, 2 * m), _f32(b)[0])
+
+
 def _k_spin(p, *bufs):
     """Delay kernel used by the scheduler tests: no effect on data."""
 
@@ -127,6 +144,9 @@ KERNELS = {
     "nb_proba": _k_nb_proba,                # X lt lp :c P:m      (X feature-major; n x C posteriors)
     "ridge_proba": _k_ridge_proba,          # X mean scale W b :c P:m
     "ensemble": _k_ensemble,                # Pnb Prr :c avg:m label:m (int32)
+    "conv3x3_relu_pool": _k_conv3x3_relu_pool,  # x w b :c y:m      (channel-major)
+    "dense": _k_dense,                      # x W b :c y:m        (y = W x + b)
+    "siamese_combine": _k_siamese_combine,  # e1 e2 w b :c p:m    (p = sigmoid(w.[e1;e2] + b))
 }
 
 

@@ -254,3 +254,50 @@ def ensemble_argmax(p_nb, p_rr):
     ties), the average is returned rounded to float32."""
     avg = (np.asarray(p_nb, dtype=F32).astype(F64) + np.asarray(p_rr, dtype=F32).astype(F64)) / 2.0
     return avg.astype(F32), np.argmax(avg, axis=1).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# DL (Sec. V-B, "Deep Learning"): a convolutional network projects two input
+# images to low-dimensional embeddings and a dense layer combines them.
+# Layers (the paper names only the structure): 3x3 convolution with zero
+# padding (cross-correlation, as in deep-learning frameworks), bias, ReLU and
+# 2x2 max pooling; a dense embedding layer; a dense combining layer with a
+# sigmoid.  Tensors are channel-major (C, H, W) float32.
+# --------------------------------------------------------------------------
+def conv3x3_relu_pool(x, w, b):
+    """y[o] = maxpool2x2(relu(b[o] + sum_c corr3x3(x[c], w[o, c]))), float64 in
+    registers, rounded once to float32.  x: (C_in, H, W) with H, W even;
+    w: (C_out, C_in, 3, 3); b: (C_out,).  Returns (C_out, H/2, W/2)."""
+    x = np.asarray(x, dtype=F32).astype(F64)
+    w = np.asarray(w, dtype=F32).astype(F64)
+    b = np.asarray(b, dtype=F32).astype(F64)
+    cin, h, wd = x.shape
+    cout = w.shape[0]
+    xp = np.zeros((cin, h + 2, wd + 2))
+    xp[:, 1:h + 1, 1:wd + 1] = x
+    z = np.empty((cout, h, wd))
+    for o in range(cout):
+        acc = np.full((h, wd), b[o])
+        for c in range(cin):
+            for dy in range(3):
+                for dx in range(3):
+                    acc += w[o, c, dy, dx] * xp[c, dy:dy + h, dx:dx + wd]
+        z[o] = acc
+    z = np.maximum(z, 0.0)
+    pooled = z.reshape(cout, h // 2, 2, wd // 2, 2).max(axis=(2, 4))
+    return pooled.astype(F32)
+
+
+def dense(x, w, b):
+    """y = W x + b for a flattened input, float64, rounded to float32;
+    W: (M, N), x: (N,), b: (M,)."""
+    x = np.asarray(x, dtype=F32).astype(F64).ravel()
+    w = np.asarray(w, dtype=F32).astype(F64)
+    return (w @ x + np.asarray(b, dtype=F32).astype(F64)).astype(F32)
+
+
+def siamese_combine(e1, e2, w, b):
+    """p = sigmoid(w . [e1; e2] + b) as a float32 scalar (float64 inside)."""
+    z = np.concatenate([np.asarray(e1, dtype=F32).astype(F64), np.asarray(e2, dtype=F32).astype(F64)])
+    s = float(np.dot(np.asarray(w, dtype=F32).astype(F64), z)) + float(np.float32(b))
+    return F32(1.0 / (1.0 + math.exp(-s)))

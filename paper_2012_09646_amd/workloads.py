@@ -292,6 +292,60 @@ def ml_program(n=1 << 20, seed=5, features=ML_FEATURES, classes=ML_CLASSES, cate
     return Program("ml", bufs, ops, ["Pnb", "Prr", "Pavg", "label"], "label")
 
 
+DL_CHANNELS = (16, 32)    # output channels of the two convolution layers
+DL_EMBED = 16             # embedding size
+
+
+def dl_inputs(seed, side=1024, channels=DL_CHANNELS, embed=DL_EMBED):
+    """Two input images (1 channel, side x side, U[0,1)) and random-initialised
+    weights of the network (nothing is trained): He-uniform convolution and
+    dense weights, small uniform biases."""
+    g = np.random.Generator(np.random.Philox(key=int(seed)))
+    c1, c2 = int(channels[0]), int(channels[1])
+    s = int(side)
+
+    def he(shape, fan_in):
+        a = np.sqrt(6.0 / fan_in)
+        return g.uniform(-a, a, size=shape).astype(F32)
+
+    d = {"img1": g.random((1, s, s), dtype=np.float32), "img2": g.random((1, s, s), dtype=np.float32),
+         "w1": he((c1, 1, 3, 3), 9), "b1": g.uniform(-0.05, 0.05, size=c1).astype(F32),
+         "w2": he((c2, c1, 3, 3), 9 * c1), "b2": g.uniform(-0.05, 0.05, size=c2).astype(F32)}
+    n = c2 * (s // 4) * (s // 4)
+    d["we"] = he((int(embed), n), n)
+    d["be"] = g.uniform(-0.05, 0.05, size=int(embed)).astype(F32)
+    d["wc"] = he((2 * int(embed),), 2 * int(embed))
+    d["bc"] = g.uniform(-0.05, 0.05, size=1).astype(F32)
+    return d
+
+
+def dl_program(side=1024, seed=6, channels=DL_CHANNELS, embed=DL_EMBED):
+    """Siamese CNN: each image through conv(3x3)+ReLU+pool twice and a dense
+    embedding (the two branches share the read-only weights), then one dense
+    layer with a sigmoid combines the embeddings; host reads the output."""
+    d = dl_inputs(seed, side, channels, embed)
+    s, c1, c2, m = int(side), int(channels[0]), int(channels[1]), int(embed)
+    bufs = {k: Buf(v.nbytes, init=v) for k, v in d.items()}
+    for i in (1, 2):
+        bufs["a%d" % i] = Buf(4 * c1 * (s // 2) * (s // 2))
+        bufs["f%d" % i] = Buf(4 * c2 * (s // 4) * (s // 4))
+        bufs["e%d" % i] = Buf(4 * m)
+    bufs["p"] = Buf(4)
+    n = c2 * (s // 4) * (s // 4)
+    ops = []
+    for i in (1, 2):
+        ops.append(K("conv3x3_relu_pool", [("img%d" % i, "c"), ("w1", "c"), ("b1", "c"), ("a%d" % i, "m")],
+                     cin=1, cout=c1, h=s, w=s))
+    for i in (1, 2):
+        ops.append(K("conv3x3_relu_pool", [("a%d" % i, "c"), ("w2", "c"), ("b2", "c"), ("f%d" % i, "m")],
+                     cin=c1, cout=c2, h=s // 2, w=s // 2))
+    for i in (1, 2):
+        ops.append(K("dense", [("f%d" % i, "c"), ("we", "c"), ("be", "c"), ("e%d" % i, "m")], n=n, m=m))
+    ops.append(K("siamese_combine", [("e1", "c"), ("e2", "c"), ("wc", "c"), ("bc", "c"), ("p", "m")], m=m))
+    ops.append(HR("p"))
+    return Program("dl", bufs, ops, ["a1", "a2", "f1", "f2", "e1", "e2", "p"], "p")
+
+
 def initial_arrays(prog):
     """Fresh numpy arrays (uint8 views over the initial contents) for a program."""
     out = {}

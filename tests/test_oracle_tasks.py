@@ -348,3 +348,94 @@ def test_ml_program_runs_in_program_order():
     assert np.array_equal(arrays["Pnb"].view(np.float32).reshape(257, 10), pnb)
     assert np.array_equal(arrays["label"].view(np.int32), lab)
     assert np.allclose(arrays["Pavg"].view(np.float32).reshape(257, 10).sum(axis=1), 1.0, atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# DL (Siamese CNN)
+# --------------------------------------------------------------------------
+def test_conv_relu_pool_against_pytorch_cpu():
+    import torch
+    F = torch.nn.functional
+    g = np.random.default_rng(8)
+    for cin, cout, h, w in ((1, 4, 8, 10), (3, 5, 6, 6), (8, 2, 12, 4)):
+        x = g.random((cin, h, w), dtype=np.float32)
+        wt = (g.random((cout, cin, 3, 3), dtype=np.float32) - 0.5)
+        b = (g.random(cout, dtype=np.float32) - 0.5) * 0.1
+        ref = F.max_pool2d(torch.relu(F.conv2d(torch.tensor(x, dtype=torch.float64)[None],
+                                                torch.tensor(wt, dtype=torch.float64),
+                                                torch.tensor(b, dtype=torch.float64), padding=1)), 2)[0]
+        got = T.conv3x3_relu_pool(x, wt, b)
+        assert got.shape == (cout, h // 2, w // 2)
+        assert np.array_equal(got, ref.numpy().astype(np.float32))
+
+
+def test_conv_relu_pool_brute_force():
+    g = np.random.default_rng(9)
+    cin, cout, h, w = 2, 2, 4, 6
+    x = g.random((cin, h, w), dtype=np.float32)
+    wt = g.random((cout, cin, 3, 3), dtype=np.float32) - 0.5
+    b = np.float32([0.01, -0.02])
+    got = T.conv3x3_relu_pool(x, wt, b)
+    for o in range(cout):
+        for py in range(h // 2):
+            for px in range(w // 2):
+                best = 0.0
+                for yy in (2 * py, 2 * py + 1):
+                    for xx in (2 * px, 2 * px + 1):
+                        s = float(b[o])
+                        for c in range(cin):
+                            for dy in range(3):
+                                for dx in range(3):
+                                    iy, ix = yy + dy - 1, xx + dx - 1
+                                    if 0 <= iy < h and 0 <= ix < w:
+                                        s += float(wt[o, c, dy, dx]) * float(x[c, iy, ix])
+                        best = max(best, s)
+                assert abs(float(got[o, py, px]) - best) <= 1e-7 * max(abs(best), 1e-30)
+
+
+def test_conv_relu_pool_special_cases():
+    g = np.random.default_rng(10)
+    x = g.random((2, 6, 8), dtype=np.float32) - 0.5
+    ident = np.zeros((2, 2, 3, 3), np.float32)
+    ident[0, 0, 1, 1] = 1.0                      # output 0 copies input channel 0
+    ident[1, 1, 1, 1] = -1.0                     # output 1 negates input channel 1
+    got = T.conv3x3_relu_pool(x, ident, np.zeros(2, np.float32))
+    pooled = lambda a: np.maximum(a, 0).reshape(3, 2, 4, 2).max(axis=(1, 3))
+    assert np.array_equal(got[0], pooled(x[0]))
+    assert np.array_equal(got[1], pooled(-x[1]))
+    zero = T.conv3x3_relu_pool(x, np.zeros((3, 2, 3, 3), np.float32), np.float32([0.25, -1.0, 0.0]))
+    assert np.all(zero[0] == np.float32(0.25)) and np.all(zero[1] == 0) and np.all(zero[2] == 0)
+
+
+def test_dense_and_combine_closed_forms():
+    g = np.random.default_rng(11)
+    x = g.random(50, dtype=np.float32)
+    y = T.dense(x, np.ones((3, 50), np.float32), np.float32([0.0, 1.0, -2.0]))
+    s = math.fsum(float(v) for v in x)
+    assert np.allclose(y.astype(np.float64), [s, s + 1, s - 2], rtol=1e-7, atol=0)
+    w = g.random((4, 7), dtype=np.float32) - 0.5
+    x7 = g.random(7, dtype=np.float32)
+    yb = T.dense(x7, w, np.zeros(4, np.float32))
+    for j in range(4):
+        ref = sum(float(w[j, i]) * float(x7[i]) for i in range(7))
+        assert abs(float(yb[j]) - ref) <= 1e-7 * abs(ref)
+    e1, e2 = g.random(5, dtype=np.float32), g.random(5, dtype=np.float32)
+    assert T.siamese_combine(e1, e2, np.zeros(10, np.float32), np.float32(0.3)) == np.float32(1 / (1 + math.exp(-0.3)))
+    u = g.random(5, dtype=np.float32)
+    assert T.siamese_combine(e1, e1, np.concatenate([u, -u]), np.float32(0.0)) == np.float32(0.5)
+    assert T.siamese_combine(e1, e2, np.float32([1] * 10), np.float32(-40.0)) < 1e-6
+
+
+def test_dl_program_runs_in_program_order():
+    prog = W.dl_program(side=16, seed=3, channels=(4, 6), embed=5)
+    arrays = W.initial_arrays(prog)
+    orun.execute(prog.ops, arrays)
+    d = W.dl_inputs(3, 16, (4, 6), 5)
+    a1 = T.conv3x3_relu_pool(d["img1"], d["w1"], d["b1"])
+    f1 = T.conv3x3_relu_pool(a1, d["w2"], d["b2"])
+    e1 = T.dense(f1.ravel(), d["we"], d["be"])
+    a2 = T.conv3x3_relu_pool(d["img2"], d["w1"], d["b1"])
+    e2 = T.dense(T.conv3x3_relu_pool(a2, d["w2"], d["b2"]).ravel(), d["we"], d["be"])
+    assert np.array_equal(arrays["e1"].view(np.float32), e1)
+    assert arrays["p"].view(np.float32)[0] == T.siamese_combine(e1, e2, d["wc"], d["bc"][0])
+    assert f1.shape == (6, 4, 4)
