@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "ml", "serve"])
+    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "ml", "dl", "serve"])
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests in the trace")
     ap.add_argument("--serve-lanes", type=int, default=3,
                     help="serving: lanes (HIP streams) requests spread over")
@@ -111,7 +111,7 @@ def orchestrate(args):
     if args.hw_queues:
         fwd += ["--hw-queues", str(args.hw_queues)]
     lines = {}
-    for wl in ("bs", "vec", "img", "hits", "ml", "serve"):
+    for wl in ("bs", "vec", "img", "hits", "ml", "dl", "serve"):
         extra = [] if wl == "bs" and not args.no_cpu_baseline else ["--no-cpu-baseline"]
         log("child process: --workload %s" % wl)
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", wl] + fwd + extra,
@@ -121,7 +121,7 @@ def orchestrate(args):
             sys.exit(r.returncode)
         lines[wl] = json.loads(r.stdout.strip().splitlines()[-1])
     line = lines["bs"]
-    for wl in ("vec", "img", "hits", "ml"):
+    for wl in ("vec", "img", "hits", "ml", "dl"):
         line["workloads"][wl] = lines[wl]["workloads"][wl]
     line["serving"] = lines["serve"]["serving"]
     line["config"]["processes"] = "one per workload"
@@ -483,7 +483,7 @@ def main():
         ctx.close()
         return out
 
-    workloads = ["bs", "vec", "img", "hits", "ml", "serve"] if args.workload == "all" else [args.workload]
+    workloads = ["bs", "vec", "img", "hits", "ml", "dl", "serve"] if args.workload == "all" else [args.workload]
     results = {}
     graphs = {}
     kt_bs = None
@@ -504,6 +504,9 @@ def main():
             results[wl], _ = measure(wl, prog, args.steps, args.warmup, restore=("a", "h"), per_iter=6)
         elif wl == "ml":
             prog = W.ml_program(n=1 << 20, seed=5)
+            results[wl], _ = measure(wl, prog, args.steps, args.warmup)
+        elif wl == "dl":
+            prog = W.dl_program(side=1024, seed=6)
             results[wl], _ = measure(wl, prog, args.steps, args.warmup)
         elif wl == "serve":
             results[wl] = measure_serving(graphs)

@@ -268,6 +268,19 @@ dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
 #define DAG_K_ENSEMBLE 17u       /* Pnb Prr:c avg:m label:m  avg = (Pnb + Prr)/2,
                                     label[r] (int32) = first index of the
                                     largest average (lowest class on ties) */
+/* DL (Sec. V-B, a Siamese convolutional network); tensors channel-major
+ * (C, H, W) fp32. */
+#define DAG_K_CONV3X3_RELU_POOL 18u /* x w b:c y:m   y[o] = maxpool2x2(relu(b[o] +
+                                    sum_c corr3x3(x[c], w[o][c]))), zero
+                                    padding; x: cin x h x w, w: cout x cin x
+                                    3 x 3, y: cout x h/2 x w/2 (h, w even) */
+#define DAG_K_DENSE 19u          /* x W b:c y:m         y[j] = sum_i W[i][j] x[i] + b[j],
+                                    W: n x m row-major (input-major: the m
+                                    weights of input i adjacent), m <= 16
+                                    (uses the stream's scratch for
+                                    per-workgroup partials) */
+#define DAG_K_SIAMESE_COMBINE 20u /* e1 e2 w b:c p:m     p[0] = sigmoid(w . [e1; e2]
+                                    + b[0]), e1, e2: m <= 32, w: 2m */
 #define DAG_K_USER_BASE 1000u    /* ids of dag_kernel_register */
 
 /* Parameter blocks (passed by pointer + size to dag_submit_kernel). */
@@ -301,6 +314,9 @@ typedef struct {
   uint32_t categories; /* V >= 1 (naive Bayes codes; unused by the others) */
   uint32_t reserved;   /* 0 */
 } dag_p_ml;            /* NB_PROBA, RIDGE_PROBA, ENSEMBLE */
+typedef struct { uint32_t cin, cout, h, w; } dag_p_conv;       /* CONV3X3_RELU_POOL: input h x w */
+typedef struct { uint64_t n; uint32_t m, reserved; } dag_p_dense; /* DENSE: n inputs, m outputs */
+typedef struct { uint32_t m, reserved; } dag_p_combine;        /* SIAMESE_COMBINE: embedding size */
 
 /* Launch configuration of a built-in kernel (used by the autotuner). */
 typedef struct {

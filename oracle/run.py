@@ -113,8 +113,9 @@ def _k_conv3x3_relu_pool(p, x, w, b, y):
 
 
 def _k_dense(p, x, w, b, y):
+    """W is stored input-major (n x m); the layer's matrix is its transpose."""
     n, m = p["n"], p["m"]
-    _f32(y, m)[:] = tasks.dense(_f32(x, n), _f32(w, m * n).reshape(m, n), _f32(b, m))
+    _f32(y, m)[:] = tasks.dense(_f32(x, n), _f32(w, m * n).reshape(n, m).T, _f32(b, m))
 
 
 def _k_siamese_combine(p, e1, e2, w, b, out):
@@ -145,7 +146,7 @@ KERNELS = {
     "ridge_proba": _k_ridge_proba,          # X mean scale W b :c P:m
     "ensemble": _k_ensemble,                # Pnb Prr :c avg:m label:m (int32)
     "conv3x3_relu_pool": _k_conv3x3_relu_pool,  # x w b :c y:m      (channel-major)
-    "dense": _k_dense,                      # x W b :c y:m        (y = W x + b)
+    "dense": _k_dense,                      # x W b :c y:m        (y = W x + b, W stored n x m)
     "siamese_combine": _k_siamese_combine,  # e1 e2 w b :c p:m    (p = sigmoid(w.[e1;e2] + b))
 }
 

@@ -1172,6 +1172,177 @@ __global__ __launch_bounds__(1024) void k_ensemble(const float* __restrict__ pa,
 }
 
 // ---------------------------------------------------------------------------
+// DL (Sec. V-B): a Siamese convolutional network.  Tensors are channel-major
+// (C, H, W) fp32; arithmetic in fp64, one rounding to fp32 per output.
+//
+// 3x3 convolution (zero padding) + bias + ReLU + 2x2 max pooling in one
+// kernel: a 256-thread workgroup owns a 16 x 16 tile of pooled outputs (a
+// 32 x 32 tile of convolution outputs) for OC output channels.  Per input
+// channel the 34 x 34 input tile and the OC x 9 weights (as fp64) are staged
+// in LDS once and serve all OC channels; each thread keeps its 4 convolution
+// outputs per channel in fp64 registers, and ReLU then max equals max then
+// ReLU (ReLU is monotone).
+// ---------------------------------------------------------------------------
+constexpr int kConvTile = 16;  // pooled outputs per tile side
+
+template <int OC>
+__global__ __launch_bounds__(256) void k_conv3x3_relu_pool(const float* __restrict__ x, const float* __restrict__ w,
+                                                           const float* __restrict__ bias, float* __restrict__ y,
+                                                           uint32_t cin, uint32_t h, uint32_t wd,
+                                                           uint32_t tiles_x) {
+  constexpr int kIn = 2 * kConvTile + 2;  // 34 input rows / columns per tile
+  __shared__ float s_in[kIn][kIn + 1];
+  __shared__ double s_w[OC * 9];          // this input channel's weights of the OC output channels
+  const uint32_t ph = h / 2, pw = wd / 2;
+  const uint32_t ty0 = (blockIdx.x / tiles_x) * kConvTile, tx0 = (blockIdx.x % tiles_x) * kConvTile;
+  const uint32_t o0 = blockIdx.y * OC;
+  const uint32_t tx = threadIdx.x % kConvTile, ty = threadIdx.x / kConvTile;
+  const int gy0 = 2 * static_cast<int>(ty0) - 1, gx0 = 2 * static_cast<int>(tx0) - 1;
+  double acc[OC][4];
+#pragma unroll
+  for (int k = 0; k < OC; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[k][q] = static_cast<double>(bias[o0 + k]);
+  for (uint32_t c = 0; c < cin; ++c) {
+    const float* xc = x + static_cast<uint64_t>(c) * h * wd;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kIn * kIn; i += blockDim.x) {
+      const int r = static_cast<int>(i / kIn), q = static_cast<int>(i % kIn);
+      const int gy = gy0 + r, gx = gx0 + q;
+      s_in[r][q] = (gy >= 0 && gy < static_cast<int>(h) && gx >= 0 && gx < static_cast<int>(wd))
+                       ? xc[static_cast<uint64_t>(gy) * wd + gx]
+                       : 0.0f;
+    }
+    for (uint32_t i = threadIdx.x; i < OC * 9; i += blockDim.x)
+      s_w[i] = static_cast<double>(w[(static_cast<uint64_t>(o0 + i / 9) * cin + c) * 9 + i % 9]);
+    __syncthreads();
+    double p[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) p[a][d] = static_cast<double>(s_in[2 * ty + a][2 * tx + d]);
+#pragma unroll
+    for (int k = 0; k < OC; ++k) {
+      double wv[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) wv[t] = s_w[k * 9 + t];
+#pragma unroll
+      for (int qy = 0; qy < 2; ++qy)
+#pragma unroll
+        for (int qx = 0; qx < 2; ++qx) {
+          double sacc = acc[k][qy * 2 + qx];
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) sacc = fma(wv[dy * 3 + dx], p[qy + dy][qx + dx], sacc);
+          acc[k][qy * 2 + qx] = sacc;
+        }
+    }
+  }
+  const uint32_t py = ty0 + ty, px = tx0 + tx;
+  if (py < ph && px < pw) {
+#pragma unroll
+    for (int k = 0; k < OC; ++k) {
+      const double m = fmax(fmax(acc[k][0], acc[k][1]), fmax(acc[k][2], acc[k][3]));
+      y[(static_cast<uint64_t>(o0 + k) * ph + py) * pw + px] = static_cast<float>(fmax(m, 0.0));
+    }
+  }
+}
+
+// y = W x + b for M <= 16 outputs of a long input: every workgroup sums its
+// grid-stride share of the inputs for all M outputs (fp64), reduces them in
+// a fixed order and publishes M partials; the last workgroup to finish adds
+// the partials in workgroup order and the bias.
+constexpr int kDenseMaxOut = 16;
+
+// W is stored input-major (n x M: the M weights of input i are adjacent), so
+// a wave streams 64 consecutive inputs' weights, M * 256 contiguous bytes,
+// with 16-byte loads when M is a multiple of 4 and W is 16-byte aligned
+// (vec).  M is a template parameter: the loads of a row are issued without
+// branches between them.
+template <int M>
+__global__ __launch_bounds__(1024) void k_dense(const float* __restrict__ x, const float* __restrict__ W,
+                                                const float* __restrict__ bias, float* __restrict__ y, uint64_t n,
+                                                int vec, uint32_t* counter, uint64_t* partials) {
+  __shared__ double sh[16 * kDenseMaxOut];
+  __shared__ int flag;
+  const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  double acc[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) acc[j] = 0.0;
+  if constexpr (M % 4 == 0) {
+    if (vec) {
+      for (uint64_t i = gid; i < n; i += stride) {
+        const double xi = static_cast<double>(x[i]);
+        const float4* wr = reinterpret_cast<const float4*>(W + i * M);
+        float4 v[M / 4];
+#pragma unroll
+        for (int q = 0; q < M / 4; ++q) v[q] = wr[q];
+#pragma unroll
+        for (int q = 0; q < M / 4; ++q) {
+          acc[4 * q] = fma(static_cast<double>(v[q].x), xi, acc[4 * q]);
+          acc[4 * q + 1] = fma(static_cast<double>(v[q].y), xi, acc[4 * q + 1]);
+          acc[4 * q + 2] = fma(static_cast<double>(v[q].z), xi, acc[4 * q + 2]);
+          acc[4 * q + 3] = fma(static_cast<double>(v[q].w), xi, acc[4 * q + 3]);
+        }
+      }
+    }
+  }
+  if (M % 4 != 0 || !vec) {
+    for (uint64_t i = gid; i < n; i += stride) {
+      const double xi = static_cast<double>(x[i]);
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc[j] = fma(static_cast<double>(W[i * M + j]), xi, acc[j]);
+    }
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv_ = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double t = wave_sum(acc[j]);
+    if (lane == 0) sh[wv_ * kDenseMaxOut + j] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < M) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += sh[q * kDenseMaxOut + threadIdx.x];
+    __hip_atomic_store(&partials[static_cast<uint64_t>(blockIdx.x) * kDenseMaxOut + threadIdx.x], d2u(t),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+  if (arrive_last(counter, &flag)) {
+    // all threads fetch the partials (agent-scope loads, each a trip past the
+    // L2) 16 workgroups' worth at a time into LDS; M threads then add them in
+    // workgroup order
+    double t = 0.0;
+    for (uint32_t q0 = 0; q0 < gridDim.x; q0 += 16) {
+      const uint32_t cnt = min(16u, gridDim.x - q0);
+      for (uint32_t i = threadIdx.x; i < cnt * kDenseMaxOut; i += blockDim.x)
+        sh[i] = u2d(read_partial(partials, q0 * kDenseMaxOut + i));
+      __syncthreads();
+      if (threadIdx.x < M)
+        for (uint32_t q = 0; q < cnt; ++q) t += sh[q * kDenseMaxOut + threadIdx.x];
+      __syncthreads();
+    }
+    if (threadIdx.x < M) y[threadIdx.x] = static_cast<float>(t + static_cast<double>(bias[threadIdx.x]));
+    reset_counter(counter);
+  }
+}
+
+// p = sigmoid(w . [e1; e2] + b), 2m <= 64: one wave, a fixed butterfly sum.
+__global__ __launch_bounds__(64) void k_siamese_combine(const float* __restrict__ e1, const float* __restrict__ e2,
+                                                        const float* __restrict__ w, const float* __restrict__ b,
+                                                        float* __restrict__ p, uint32_t m) {
+  const uint32_t k = threadIdx.x;
+  double t = 0.0;
+  if (k < 2 * m) t = static_cast<double>(w[k]) * static_cast<double>(k < m ? e1[k] : e2[k - m]);
+  const double s = wave_sum(t) + static_cast<double>(b[0]);
+  if (k == 0) p[0] = static_cast<float>(1.0 / (1.0 + exp(-s)));
+}
+
+// ---------------------------------------------------------------------------
 // Utilities: a delay kernel for scheduler tests and a plain copy.
 // ---------------------------------------------------------------------------
 __global__ void k_spin(uint64_t ticks) {
@@ -1782,6 +1953,110 @@ hipError_t l_ensemble(hipStream_t s, void* const* a, const void* p, const Launch
   return hipGetLastError();
 }
 
+// -- DL ---------------------------------------------------------------------------
+const char* cfg_conv(const LaunchCfg& c) {
+  if (c.block != 256) return "this kernel runs 256-thread workgroups (16 x 16 pooled outputs)";
+  if (c.grid_cap != 0 || c.variant != 0) return "grid_cap and variant must be 0";
+  return nullptr;
+}
+const dag_p_conv* pconv(const void* p) { return static_cast<const dag_p_conv*>(p); }
+uint32_t conv_oc(uint32_t cout) { return cout % 8 == 0 ? 8 : (cout % 4 == 0 ? 4 : 1); }
+
+const char* v_conv(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const dag_p_conv* q = pconv(p);
+  if (q->cin < 1 || q->cin > 4096 || q->cout < 1 || q->cout > 4096) return "cin and cout must be in 1..4096";
+  if (q->h < 2 || q->w < 2 || q->h % 2 || q->w % 2 || q->h > 65536 || q->w > 65536)
+    return "h and w must be even, in 2..65536";
+  const uint64_t hw = static_cast<uint64_t>(q->h) * q->w;
+  if (sz[0] < 4 * q->cin * hw) return "x smaller than 4*cin*h*w bytes";
+  if (sz[1] < 36ull * q->cout * q->cin) return "w smaller than 4*cout*cin*9 bytes";
+  if (sz[2] < 4ull * q->cout) return "b smaller than 4*cout bytes";
+  if (sz[3] < 4 * q->cout * (hw / 4)) return "y smaller than 4*cout*(h/2)*(w/2) bytes";
+  const uint64_t tiles = ceil_div(q->h / 2, kConvTile) * ceil_div(q->w / 2, kConvTile);
+  if (tiles > (1u << 30) || q->cout / conv_oc(q->cout) > 65535) return "grid too large";
+  return nullptr;
+}
+hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+  const dag_p_conv* q = pconv(p);
+  const uint32_t tiles_x = static_cast<uint32_t>(ceil_div(q->w / 2, kConvTile));
+  const uint32_t tiles_y = static_cast<uint32_t>(ceil_div(q->h / 2, kConvTile));
+  const uint32_t oc = conv_oc(q->cout);
+  const dim3 g(tiles_x * tiles_y, q->cout / oc), b(c.block);
+  const auto* x = static_cast<const float*>(a[0]);
+  const auto* w = static_cast<const float*>(a[1]);
+  const auto* bias = static_cast<const float*>(a[2]);
+  auto* y = static_cast<float*>(a[3]);
+  if (oc == 8)
+    DAGRT_LAUNCH(k_conv3x3_relu_pool<8>, g, b, 0, s, x, w, bias, y, q->cin, q->h, q->w, tiles_x);
+  else if (oc == 4)
+    DAGRT_LAUNCH(k_conv3x3_relu_pool<4>, g, b, 0, s, x, w, bias, y, q->cin, q->h, q->w, tiles_x);
+  else
+    DAGRT_LAUNCH(k_conv3x3_relu_pool<1>, g, b, 0, s, x, w, bias, y, q->cin, q->h, q->w, tiles_x);
+  return hipGetLastError();
+}
+
+const char* cfg_dense(const LaunchCfg& c) {
+  if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
+  if (c.variant != 0) return "variant must be 0";
+  return nullptr;
+}
+const dag_p_dense* pdense(const void* p) { return static_cast<const dag_p_dense*>(p); }
+uint32_t dense_grid(const dag_p_dense* q, const LaunchCfg& c, size_t sb) {
+  uint64_t g = stream_grid(q->n, c);
+  g = std::min<uint64_t>(g, reduction_capacity(sb) / kDenseMaxOut);
+  return static_cast<uint32_t>(std::max<uint64_t>(g, 1));
+}
+const char* v_dense(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t sb) {
+  const dag_p_dense* q = pdense(p);
+  if (q->m < 1 || q->m > static_cast<uint32_t>(kDenseMaxOut)) return "m must be in 1..16";
+  if (q->reserved) return "reserved must be 0";
+  if (!mul_fits(q->n, 4, sz[0])) return "x smaller than 4*n bytes";
+  if (!mul_fits(q->n, 4ull * q->m, sz[1])) return "W smaller than 4*n*m bytes";
+  if (sz[2] < 4ull * q->m || sz[3] < 4ull * q->m) return "b or y smaller than 4*m bytes";
+  if (reduction_capacity(sb) < static_cast<uint64_t>(kDenseMaxOut)) return "scratch too small";
+  return nullptr;
+}
+hipError_t l_dense(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
+  const dag_p_dense* q = pdense(p);
+  auto* counter = static_cast<uint32_t*>(scr);
+  auto* partials = reinterpret_cast<uint64_t*>(static_cast<char*>(scr) + kScratchPartialsOffset);
+  const int vec = aligned16(a[1]);
+  const dim3 g(dense_grid(q, c, sb)), b(c.block);
+  const auto* x = static_cast<const float*>(a[0]);
+  const auto* W = static_cast<const float*>(a[1]);
+  const auto* bias = static_cast<const float*>(a[2]);
+  auto* y = static_cast<float*>(a[3]);
+  switch (q->m) {
+#define DAGRT_DENSE_CASE(K) \
+  case K: DAGRT_LAUNCH(k_dense<K>, g, b, 0, s, x, W, bias, y, q->n, vec, counter, partials); break;
+    DAGRT_ML_CLASSES(DAGRT_DENSE_CASE)
+#undef DAGRT_DENSE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+const char* cfg_combine(const LaunchCfg& c) {
+  if (c.block != 64 || c.grid_cap != 0 || c.variant != 0) return "this kernel runs one 64-thread workgroup";
+  return nullptr;
+}
+const char* v_combine2(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, size_t) {
+  const auto* q = static_cast<const dag_p_combine*>(p);
+  if (q->m < 1 || q->m > 32) return "m must be in 1..32";
+  if (q->reserved) return "reserved must be 0";
+  if (sz[0] < 4ull * q->m || sz[1] < 4ull * q->m) return "e1 or e2 smaller than 4*m bytes";
+  if (sz[2] < 8ull * q->m) return "w smaller than 8*m bytes";
+  if (sz[3] < 4 || sz[4] < 4) return "b or p smaller than 4 bytes";
+  return nullptr;
+}
+hipError_t l_combine2(hipStream_t s, void* const* a, const void* p, const LaunchCfg&, void*, size_t) {
+  const auto* q = static_cast<const dag_p_combine*>(p);
+  DAGRT_LAUNCH(k_siamese_combine, dim3(1), dim3(64), 0, s, static_cast<const float*>(a[0]),
+               static_cast<const float*>(a[1]), static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
+               static_cast<float*>(a[4]), q->m);
+  return hipGetLastError();
+}
+
 const KernelDesc kTable[] = {
     /* 0 */ {nullptr, 0, 0, 0, {0, 0, 0}, nullptr, nullptr, nullptr},
     /* 1 */ {"vec_square", 1, 0x1, sizeof(dag_p_n), {256, 0, 0}, v_vec_square, l_vec_square, cfg_block_any},
@@ -1801,6 +2076,9 @@ const KernelDesc kTable[] = {
     /* 15 */ {"nb_proba", 4, 0x8, sizeof(dag_p_ml), {1024, 256, 0}, v_nb, l_nb, cfg_ml_one},
     /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ridge},
     /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml_one},
+    /* 18 */ {"conv3x3_relu_pool", 4, 0x8, sizeof(dag_p_conv), {256, 0, 0}, v_conv, l_conv, cfg_conv},
+    /* 19 */ {"dense", 4, 0x8, sizeof(dag_p_dense), {256, 1024, 0}, v_dense, l_dense, cfg_dense},
+    /* 20 */ {"siamese_combine", 5, 0x10, sizeof(dag_p_combine), {64, 0, 0}, v_combine2, l_combine2, cfg_combine},
 };
 
 static_assert(sizeof(kTable) / sizeof(kTable[0]) == kNumBuiltin, "kernel table and kNumBuiltin disagree");

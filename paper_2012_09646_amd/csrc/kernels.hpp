@@ -29,7 +29,7 @@ struct KernelDesc {
 };
 
 // Built-in kernel ids are 1..kNumBuiltin-1; nullptr for unknown ids.
-constexpr uint32_t kNumBuiltin = 18;
+constexpr uint32_t kNumBuiltin = 21;
 const KernelDesc* builtin_kernel(uint32_t id);
 
 // Timing events for the next built-in launch call (both null = none): the

@@ -35,6 +35,7 @@ KERNEL_IDS = {
     "minmax": 6, "normalise": 7, "unsharp_combine": 8, "spmv": 9, "spmv_rows": 10, "sumsq": 11,
     "scale_l2": 12, "spin": 13, "copy_f32": 14,
     "nb_proba": 15, "ridge_proba": 16, "ensemble": 17,
+    "conv3x3_relu_pool": 18, "dense": 19, "siamese_combine": 20,
 }
 KERNEL_NAMES = {v: k for k, v in KERNEL_IDS.items()}
 
@@ -106,6 +107,18 @@ class dag_p_spin(C.Structure):
 
 class dag_sched(C.Structure):
     _fields_ = [("stream", C.c_uint32), ("nwaits", C.c_uint32), ("waits", C.POINTER(C.c_uint32))]
+
+
+class dag_p_conv(C.Structure):
+    _fields_ = [("cin", C.c_uint32), ("cout", C.c_uint32), ("h", C.c_uint32), ("w", C.c_uint32)]
+
+
+class dag_p_dense(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("m", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class dag_p_combine(C.Structure):
+    _fields_ = [("m", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class dag_p_ml(C.Structure):
@@ -495,6 +508,12 @@ def make_params(kernel, p):
         return dag_p_csr(int(p["nrows"]), int(p["ncols"]), int(p["nnz"]))
     if kernel == "spin":
         return dag_p_spin(int(p.get("ns", 0)))
+    if kernel == "conv3x3_relu_pool":
+        return dag_p_conv(int(p["cin"]), int(p["cout"]), int(p["h"]), int(p["w"]))
+    if kernel == "dense":
+        return dag_p_dense(int(p["n"]), int(p["m"]), 0)
+    if kernel == "siamese_combine":
+        return dag_p_combine(int(p["m"]), 0)
     if kernel in ("nb_proba", "ridge_proba", "ensemble"):
         return dag_p_ml(int(p["n"]), int(p["features"]), int(p["classes"]), int(p.get("categories", 1)), 0)
     raise KeyError(kernel)

@@ -43,6 +43,10 @@ def schedule(prog):
     if prog.name == "ml":
         # naive Bayes and ridge on two streams, the ensemble after both
         return [(0, []), (1, []), (0, [1])]
+    if prog.name == "dl":
+        # image 1's layers on stream 0, image 2's on stream 1 (calls in the order
+        # conv1 x2, conv2 x2, dense x2), the combination after both embeddings
+        return [(0, []), (1, []), (0, []), (1, []), (0, []), (1, []), (0, [5])]
     raise ValueError("no hand-written schedule for %s" % prog.name)
 
 

@@ -133,6 +133,13 @@ def algorithmic_bytes(kernel, p):
     if kernel == "ensemble":
         n, C = p["n"], p["classes"]
         return 12 * n * C + 4 * n
+    if kernel == "conv3x3_relu_pool":
+        cin, cout, h, w = p["cin"], p["cout"], p["h"], p["w"]
+        return 4 * cin * h * w + 36 * cout * cin + 4 * cout + cout * h * w
+    if kernel == "dense":
+        return 4 * p["n"] * (p["m"] + 1) + 8 * p["m"]
+    if kernel == "siamese_combine":
+        return 16 * p["m"] + 8
     return 0
 
 

@@ -57,6 +57,10 @@ def candidates(kernel):
         return [(b, c, v) for b in (64, 128, 256, 512) for c in CAPS for v in (0, 4) if v != 4 or b <= 256]
     if kernel == "ensemble":
         return [(b, c, 0) for b in BLOCKS for c in CAPS]
+    if kernel == "dense":
+        return [(b, c, 0) for b in (256, 512, 1024) for c in (256, 512, 1024, 2048)]
+    if kernel == "conv3x3_relu_pool":
+        return [(256, 0, 0)]
     return []  # the delay kernel
 
 
@@ -219,12 +223,14 @@ def workload_program(name):
         return W.hits_program(n=1 << 20, iters=10, seed=3), ("a", "h")
     if name == "ml":
         return W.ml_program(n=1 << 20, seed=5), ()
+    if name == "dl":
+        return W.dl_program(side=1024, seed=6), ()
     raise ValueError(name)
 
 
 def _worker(args, log):
     """Runs inside one process (one GPU_MAX_HW_QUEUES setting)."""
-    names = ["vec", "bs", "img", "hits", "ml"] if args.workload == "all" else [args.workload]
+    names = ["vec", "bs", "img", "hits", "ml", "dl"] if args.workload == "all" else [args.workload]
     out = {"kernels": {}, "dag": {}}
     if args.worker == "kernels":
         for name in names:
@@ -267,7 +273,7 @@ def _spawn(extra, out, hw_queues=None):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "ml"])
+    ap.add_argument("--workload", default="all", choices=["all", "vec", "bs", "img", "hits", "ml", "dl"])
     ap.add_argument("--out", required=False)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--dag", action="store_true", help="also tune pool size, copy placement and hardware queues")

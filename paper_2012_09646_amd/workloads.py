@@ -312,7 +312,7 @@ def dl_inputs(seed, side=1024, channels=DL_CHANNELS, embed=DL_EMBED):
          "w1": he((c1, 1, 3, 3), 9), "b1": g.uniform(-0.05, 0.05, size=c1).astype(F32),
          "w2": he((c2, c1, 3, 3), 9 * c1), "b2": g.uniform(-0.05, 0.05, size=c2).astype(F32)}
     n = c2 * (s // 4) * (s // 4)
-    d["we"] = he((int(embed), n), n)
+    d["we"] = he((n, int(embed)), n)     # stored input-major: the weights of input i adjacent
     d["be"] = g.uniform(-0.05, 0.05, size=int(embed)).astype(F32)
     d["wc"] = he((2 * int(embed),), 2 * int(embed))
     d["bc"] = g.uniform(-0.05, 0.05, size=1).astype(F32)

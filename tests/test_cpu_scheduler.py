@@ -408,14 +408,15 @@ def test_ml_kernel_argument_checks():
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["vec", "bs", "img", "hits", "ml"])
+@pytest.mark.parametrize("name", ["vec", "bs", "img", "hits", "ml", "dl"])
 def test_hand_written_schedules_order_every_dependency(name):
     """Each workload's hand-written schedule passes the library's check
     against the inferred dependencies (schedule-only context)."""
     from paper_2012_09646_amd import handwritten as H
     small = {"vec": lambda: W.vec_program(n=1024), "bs": lambda: W.bs_program(n=1024, tasks=10),
              "img": lambda: W.img_program(side=64), "hits": lambda: W.hits_program(n=256, deg=4, iters=3),
-             "ml": lambda: W.ml_program(n=100, features=8, classes=3, categories=4)}
+             "ml": lambda: W.ml_program(n=100, features=8, classes=3, categories=4),
+             "dl": lambda: W.dl_program(side=16, channels=(4, 4), embed=3)}
     prog = small[name]()
     ctx = D.Context(dry_run=True)
     b = runner.Bound(ctx, prog)
@@ -447,4 +448,30 @@ def test_hand_written_schedule_missing_a_wait_is_refused():
     assert D.dag_region_info(ctx.h, 3) == (3, 1)
     D.dag_region_set_schedule(ctx.h, 3, [(0, []), (1, []), (2, [0, 1])])
     assert D.dag_region_info(ctx.h, 3) == (3, 3)
+    ctx.close()
+
+
+def test_dl_kernel_argument_checks():
+    ctx = D.Context(dry_run=True)
+    big = ctx.alloc(1 << 22)
+    out = ctx.alloc(1 << 22)
+
+    def conv(**p):
+        q = dict(cin=2, cout=8, h=64, w=64)
+        q.update(p)
+        return _status(ctx.kernel, "conv3x3_relu_pool", [(big, "c"), (big, "c"), (big, "c"), (out, "m")], **q)
+
+    assert conv() == "DAG_OK"
+    assert conv(h=63) == "DAG_E_INVAL" and conv(w=0) == "DAG_E_INVAL" and conv(cin=0) == "DAG_E_INVAL"
+    assert conv(cin=64, cout=64, h=512, w=512) == "DAG_E_INVAL"          # x and y too small
+    assert _status(ctx.kernel, "dense", [(big, "c"), (big, "c"), (big, "c"), (out, "m")], n=1000, m=16) == "DAG_OK"
+    assert _status(ctx.kernel, "dense", [(big, "c"), (big, "c"), (big, "c"), (out, "m")], n=1000, m=17) == "DAG_E_INVAL"
+    assert _status(ctx.kernel, "dense", [(big, "c"), (big, "c"), (big, "c"), (out, "m")],
+                   n=1 << 20, m=16) == "DAG_E_INVAL"                     # W too small
+    assert _status(ctx.kernel, "siamese_combine", [(big, "c"), (big, "c"), (big, "c"), (big, "c"), (out, "m")],
+                   m=32) == "DAG_OK"
+    assert _status(ctx.kernel, "siamese_combine", [(big, "c"), (big, "c"), (big, "c"), (big, "c"), (out, "m")],
+                   m=33) == "DAG_E_INVAL"
+    assert _status(ctx.set_launch, "conv3x3_relu_pool", 128) == "DAG_E_INVAL"
+    assert _status(ctx.set_launch, "siamese_combine", 128) == "DAG_E_INVAL"
     ctx.close()

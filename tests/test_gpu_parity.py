@@ -320,7 +320,7 @@ def test_region_replays(graph_mode):
 
 
 @pytest.mark.parametrize("graph_mode", [0, 1])
-@pytest.mark.parametrize("name", ["vec", "bs", "img", "hits", "ml"])
+@pytest.mark.parametrize("name", ["vec", "bs", "img", "hits", "ml", "dl"])
 def test_hand_written_schedules(name, graph_mode):
     """Each workload's region with its hand-written streams and waits (as a
     hipGraph or a multi-stream replay) reproduces the oracle's outputs; the
@@ -332,7 +332,8 @@ def test_hand_written_schedules(name, graph_mode):
              "bs": lambda: W.bs_program(n=100003, tasks=10, seed=22),
              "img": lambda: W.img_program(side=333, seed=23),
              "hits": lambda: W.hits_program(n=3000, deg=20, iters=10, seed=24),
-             "ml": lambda: W.ml_program(n=5003, seed=25, features=200, classes=10, categories=16)}
+             "ml": lambda: W.ml_program(n=5003, seed=25, features=200, classes=10, categories=16),
+             "dl": lambda: W.dl_program(side=100, seed=26)}
     prog = progs[name]()
     ref = G.oracle_run(prog)
     ctx = D.Context(graph_mode=graph_mode)

@@ -433,9 +433,9 @@ def test_dl_program_runs_in_program_order():
     d = W.dl_inputs(3, 16, (4, 6), 5)
     a1 = T.conv3x3_relu_pool(d["img1"], d["w1"], d["b1"])
     f1 = T.conv3x3_relu_pool(a1, d["w2"], d["b2"])
-    e1 = T.dense(f1.ravel(), d["we"], d["be"])
+    e1 = T.dense(f1.ravel(), d["we"].T, d["be"])
     a2 = T.conv3x3_relu_pool(d["img2"], d["w1"], d["b1"])
-    e2 = T.dense(T.conv3x3_relu_pool(a2, d["w2"], d["b2"]).ravel(), d["we"], d["be"])
+    e2 = T.dense(T.conv3x3_relu_pool(a2, d["w2"], d["b2"]).ravel(), d["we"].T, d["be"])
     assert np.array_equal(arrays["e1"].view(np.float32), e1)
     assert arrays["p"].view(np.float32)[0] == T.siamese_combine(e1, e2, d["wc"], d["bc"][0])
     assert f1.shape == (6, 4, 4)
