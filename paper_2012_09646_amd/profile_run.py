@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="bs", choices=["vec", "bs", "img", "hits", "ml"])
+    ap.add_argument("--workload", default="bs", choices=["vec", "bs", "img", "hits", "ml", "dl"])
     ap.add_argument("--runs", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--copies", type=int, default=3)
