@@ -1249,11 +1249,188 @@ __global__ __launch_bounds__(256) void k_conv3x3_relu_pool(const float* __restri
   }
 }
 
+// The same convolution with the input channels pipelined: the next
+// channel's input tile and weights are fetched into registers while the
+// current channel is computed from one half of a double-buffered LDS tile,
+// then stored into the other half, so each channel costs one barrier and the
+// global-load latency hides behind the FMAs.  The tile is kept flat (row
+// stride 34) so that thread t always stages elements t + 256 j; their image
+// offsets are computed once (out-of-image elements read offset 0 and store
+// zero).  Results equal the unpipelined kernel's bit for bit (same FMA order).
+//
+// SW (scalar weights): the weights come from an fp64 copy laid out
+// [input channel][output channel][9] and are read with uniform (scalar)
+// loads straight into the FMAs' scalar operand, instead of being broadcast
+// from LDS: a 16-byte broadcast read still returns 1 KB per wave, and 72 of
+// them per channel nearly saturate the CU's LDS bandwidth.
+template <int OC, bool SW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_conv3x3_relu_pool_pipe(
+    const float* __restrict__ x, const float* __restrict__ w, const double* __restrict__ w64,
+    const float* __restrict__ bias, float* __restrict__ y, uint32_t cin, uint32_t cout, uint32_t h, uint32_t wd,
+    uint32_t tiles_x) {
+  constexpr int kIn = 2 * kConvTile + 2;        // 34 input rows / columns per tile
+  constexpr int kEl = kIn * kIn;                // 1156 tile elements
+  constexpr int kSlots = (kEl + 255) / 256;     // 5 staged elements per thread
+  // every thread stores all its slots and one weight (threads past the
+  // 72 weights store into a spare slot), so the stores need no branch
+  constexpr int kW = (OC * 9 + 2) & ~1;         // weights + spare slot, even for 16-byte reads
+  __shared__ float s_in[2][kSlots * 256];
+  __shared__ __align__(16) double s_w[2][SW ? 2 : kW];
+  const uint32_t ph = h / 2, pw = wd / 2;
+  const uint32_t ty0 = (blockIdx.x / tiles_x) * kConvTile, tx0 = (blockIdx.x % tiles_x) * kConvTile;
+  const uint32_t o0 = blockIdx.y * OC;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t tx = tid % kConvTile, ty = tid / kConvTile;
+  const int gy0 = 2 * static_cast<int>(ty0) - 1, gx0 = 2 * static_cast<int>(tx0) - 1;
+  uint32_t off[kSlots];
+  uint32_t valid = 0;
+#pragma unroll
+  for (int j = 0; j < kSlots; ++j) {
+    const int i = static_cast<int>(tid) + 256 * j;
+    const int gy = gy0 + i / kIn, gx = gx0 + i % kIn;
+    const bool in = i < kEl && gy >= 0 && gy < static_cast<int>(h) && gx >= 0 && gx < static_cast<int>(wd);
+    off[j] = in ? static_cast<uint32_t>(gy) * wd + static_cast<uint32_t>(gx) : 0u;
+    valid |= in ? (1u << j) : 0u;
+  }
+  const bool wl = tid < OC * 9;  // this thread stages one weight per channel
+  const uint64_t w0 = wl ? static_cast<uint64_t>(o0 + tid / 9) * cin * 9 + tid % 9 : 0;
+  const uint64_t plane = static_cast<uint64_t>(h) * wd;
+  float v[kSlots];
+  float wr = 0.0f;
+  auto fetch = [&](uint32_t c) {
+    const float* xc = x + c * plane;
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) v[j] = xc[off[j]];
+    if constexpr (!SW) wr = w[w0 + 9ull * c];
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) s_in[b][tid + 256 * j] = (valid >> j) & 1u ? v[j] : 0.0f;
+    if constexpr (!SW) s_w[b][wl ? tid : kW - 1] = static_cast<double>(wr);
+  };
+  double acc[OC][4];
+#pragma unroll
+  for (int k = 0; k < OC; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[k][q] = static_cast<double>(bias[o0 + k]);
+  auto compute = [&](int b, uint32_t c) {
+    double p[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) p[a][d] = static_cast<double>(s_in[b][(2 * ty + a) * kIn + 2 * tx + d]);
+#pragma unroll
+    for (int k = 0; k < OC; ++k) {
+      double wv[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        wv[t] = SW ? w64[(static_cast<uint64_t>(c) * cout + o0 + k) * 9 + t] : s_w[b][k * 9 + t];
+#pragma unroll
+      for (int qy = 0; qy < 2; ++qy)
+#pragma unroll
+        for (int qx = 0; qx < 2; ++qx) {
+          double sacc = acc[k][qy * 2 + qx];
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) sacc = fma(wv[dy * 3 + dx], p[qy + dy][qx + dx], sacc);
+          acc[k][qy * 2 + qx] = sacc;
+        }
+    }
+  };
+  // channel c is computed from buffer c % 2 while channel c + 1 is fetched;
+  // unrolled by two so that the buffer offsets are constants
+  fetch(0);
+  put(0);
+  __syncthreads();
+  // (past the last channel the last one is fetched again, unused)
+  const uint32_t last = cin - 1;
+  for (uint32_t c = 0; c < cin; c += 2) {
+    fetch(min(c + 1, last));
+    compute(0, c);
+    put(1);
+    __syncthreads();
+    if (c + 1 == cin) break;
+    fetch(min(c + 2, last));
+    compute(1, c + 1);
+    put(0);
+    __syncthreads();
+  }
+  const uint32_t py = ty0 + ty, px = tx0 + tx;
+  if (py < ph && px < pw) {
+#pragma unroll
+    for (int k = 0; k < OC; ++k) {
+      const double m = fmax(fmax(acc[k][0], acc[k][1]), fmax(acc[k][2], acc[k][3]));
+      y[(static_cast<uint64_t>(o0 + k) * ph + py) * pw + px] = static_cast<float>(fmax(m, 0.0));
+    }
+  }
+}
+
+// fp64 copy of convolution weights for the scalar-weight variant:
+// w64[(c * cout + o) * 9 + t] = w[(o * cin + c) * 9 + t] (exact conversion).
+__global__ __launch_bounds__(256) void k_conv_weights_f64(const float* __restrict__ w, double* __restrict__ w64,
+                                                          uint32_t cin, uint32_t cout) {
+  const uint64_t n = static_cast<uint64_t>(cin) * cout * 9;
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += 256ull * gridDim.x) {
+    const uint64_t t = i % 9, oc = i / 9;
+    const uint64_t o = oc % cout, c = oc / cout;
+    w64[i] = static_cast<double>(w[(o * cin + c) * 9 + t]);
+  }
+}
+
 // y = W x + b for M <= 16 outputs of a long input: every workgroup sums its
 // grid-stride share of the inputs for all M outputs (fp64), reduces them in
 // a fixed order and publishes M partials; the last workgroup to finish adds
 // the partials in workgroup order and the bias.
 constexpr int kDenseMaxOut = 16;
+
+// Second half of the dense layer: sh[w * 16 + j] holds wave w's sum for
+// output j.  The block adds its waves in order and publishes M partials; the
+// last block to arrive adds all partials in block order, plus the bias.
+template <int M>
+__device__ void dense_finish(double* sh, int* flag, const float* __restrict__ bias, float* __restrict__ y,
+                             uint32_t* counter, uint64_t* partials) {
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();
+  if (threadIdx.x < M) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += sh[q * kDenseMaxOut + threadIdx.x];
+    __hip_atomic_store(&partials[static_cast<uint64_t>(blockIdx.x) * kDenseMaxOut + threadIdx.x], d2u(t),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+  if (arrive_last(counter, flag)) {
+    // thread t adds, in block order, the partials of output t % 16 over one
+    // contiguous range of blocks (range t / 16), eight agent-scope loads in
+    // flight at a time (each is a trip past the L2, so loading them one
+    // after another would cost a full latency apiece); the ranges are then
+    // added in order
+    const uint32_t j = threadIdx.x % kDenseMaxOut, r = threadIdx.x / kDenseMaxOut;
+    const uint32_t nr = blockDim.x / kDenseMaxOut;
+    const uint32_t per = (gridDim.x + nr - 1) / nr;
+    const uint32_t q1 = min((r + 1) * per, gridDim.x);
+    uint32_t q = min(r * per, gridDim.x);
+    double t = 0.0;
+    if (j < static_cast<uint32_t>(M)) {
+      for (; q + 8 <= q1; q += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = read_partial(partials, (q + u) * kDenseMaxOut + j);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t += u2d(v[u]);
+      }
+      for (; q < q1; ++q) t += u2d(read_partial(partials, q * kDenseMaxOut + j));
+    }
+    sh[r * kDenseMaxOut + j] = t;
+    __syncthreads();
+    if (threadIdx.x < M) {
+      double sum = 0.0;
+      for (uint32_t k = 0; k < nr; ++k) sum += sh[k * kDenseMaxOut + threadIdx.x];
+      y[threadIdx.x] = static_cast<float>(sum + static_cast<double>(bias[threadIdx.x]));
+    }
+    reset_counter(counter);
+  }
+}
 
 // W is stored input-major (n x M: the M weights of input i are adjacent), so
 // a wave streams 64 consecutive inputs' weights, M * 256 contiguous bytes,
@@ -1264,7 +1441,7 @@ template <int M>
 __global__ __launch_bounds__(1024) void k_dense(const float* __restrict__ x, const float* __restrict__ W,
                                                 const float* __restrict__ bias, float* __restrict__ y, uint64_t n,
                                                 int vec, uint32_t* counter, uint64_t* partials) {
-  __shared__ double sh[16 * kDenseMaxOut];
+  __shared__ double sh[1024];  // 16 waves x 16 outputs, then 64 ranges x 16 outputs
   __shared__ int flag;
   const uint64_t gid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
@@ -1298,37 +1475,82 @@ __global__ __launch_bounds__(1024) void k_dense(const float* __restrict__ x, con
   }
   const int lane = threadIdx.x & (kWave - 1);
   const int wv_ = threadIdx.x / kWave;
-  const int nw = (blockDim.x + kWave - 1) / kWave;
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const double t = wave_sum(acc[j]);
     if (lane == 0) sh[wv_ * kDenseMaxOut + j] = t;
   }
-  __syncthreads();
-  if (threadIdx.x < M) {
-    double t = 0.0;
-    for (int q = 0; q < nw; ++q) t += sh[q * kDenseMaxOut + threadIdx.x];
-    __hip_atomic_store(&partials[static_cast<uint64_t>(blockIdx.x) * kDenseMaxOut + threadIdx.x], d2u(t),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+  dense_finish<M>(sh, &flag, bias, y, counter, partials);
+}
+
+// Variants 1 and 2, for M in {4, 8, 16} and 16-byte aligned W: a wave takes 64
+// inputs at a time (a chunk) and reads their weights, M * 256 bytes, as M / 4
+// fully contiguous 1 KB loads; lane l then always holds the four outputs
+// 4l % M .. 4l % M + 3, of inputs (256 q + 4 l) / M of the chunk.  U (2 or
+// 4) chunks are loaded before any is used.  At the end the lanes holding the
+// same outputs are added by a fixed butterfly (masks M/4 .. 32), so the sum
+// order is fixed for a given launch shape.
+template <int M, int U>
+__global__ __launch_bounds__(1024) void k_dense_lanes(const float* __restrict__ x, const float* __restrict__ W,
+                                                      const float* __restrict__ bias, float* __restrict__ y,
+                                                      uint64_t n, uint32_t* counter, uint64_t* partials) {
+  static_assert(M == 4 || M == 8 || M == 16, "outputs must divide the 256 floats of a 1 KB load");
+  constexpr int kQ = M / 4;  // 1 KB loads per chunk
+  constexpr int kU = U;      // chunks in flight per lane
+  __shared__ double sh[1024];  // 16 waves x 16 outputs, then 64 ranges x 16 outputs
+  __shared__ int flag;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
+  const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * blockDim.x / kWave;
+  const uint64_t chunks = n / kWave;
+  const float4* W4 = reinterpret_cast<const float4*>(W);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto add = [&](const float4& v, float xf) {
+    const double xi = static_cast<double>(xf);
+    acc[0] = fma(static_cast<double>(v.x), xi, acc[0]);
+    acc[1] = fma(static_cast<double>(v.y), xi, acc[1]);
+    acc[2] = fma(static_cast<double>(v.z), xi, acc[2]);
+    acc[3] = fma(static_cast<double>(v.w), xi, acc[3]);
+  };
+  uint64_t c = wave;
+  for (; c + (kU - 1) * nwaves < chunks; c += kU * nwaves) {
+    float4 v[kU][kQ];
+    float xv[kU][kQ];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const uint64_t cc = c + u * nwaves;
+        v[u][q] = W4[cc * (kWave * kQ) + q * kWave + lane];
+        xv[u][q] = x[cc * kWave + (256u * q + 4u * lane) / M];
+      }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) add(v[u][q], xv[u][q]);
   }
-  if (arrive_last(counter, &flag)) {
-    // all threads fetch the partials (agent-scope loads, each a trip past the
-    // L2) 16 workgroups' worth at a time into LDS; M threads then add them in
-    // workgroup order
-    double t = 0.0;
-    for (uint32_t q0 = 0; q0 < gridDim.x; q0 += 16) {
-      const uint32_t cnt = min(16u, gridDim.x - q0);
-      for (uint32_t i = threadIdx.x; i < cnt * kDenseMaxOut; i += blockDim.x)
-        sh[i] = u2d(read_partial(partials, q0 * kDenseMaxOut + i));
-      __syncthreads();
-      if (threadIdx.x < M)
-        for (uint32_t q = 0; q < cnt; ++q) t += sh[q * kDenseMaxOut + threadIdx.x];
-      __syncthreads();
+  for (; c < chunks; c += nwaves) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) add(W4[c * (kWave * kQ) + q * kWave + lane], x[c * kWave + (256u * q + 4u * lane) / M]);
+  }
+  // the partial chunk of the last n % 64 inputs: the wave whose turn it is
+  if (c == chunks) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const uint64_t i = c * kWave + (256u * q + 4u * lane) / M;
+      if (i < n) add(W4[c * (kWave * kQ) + q * kWave + lane], x[i]);
     }
-    if (threadIdx.x < M) y[threadIdx.x] = static_cast<float>(t + static_cast<double>(bias[threadIdx.x]));
-    reset_counter(counter);
   }
+#pragma unroll
+  for (int mask = kQ; mask < kWave; mask <<= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += __shfl_xor(acc[k], mask, kWave);
+  if (lane < static_cast<uint32_t>(kQ)) {
+    const int wv_ = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[wv_ * kDenseMaxOut + 4 * lane + k] = acc[k];
+  }
+  dense_finish<M>(sh, &flag, bias, y, counter, partials);
 }
 
 // p = sigmoid(w . [e1; e2] + b), 2m <= 64: one wave, a fixed butterfly sum.
@@ -1956,7 +2178,9 @@ hipError_t l_ensemble(hipStream_t s, void* const* a, const void* p, const Launch
 // -- DL ---------------------------------------------------------------------------
 const char* cfg_conv(const LaunchCfg& c) {
   if (c.block != 256) return "this kernel runs 256-thread workgroups (16 x 16 pooled outputs)";
-  if (c.grid_cap != 0 || c.variant != 0) return "grid_cap and variant must be 0";
+  if (c.grid_cap != 0) return "grid_cap must be 0";
+  if (c.variant > 2)
+    return "variant must be 0 (one channel at a time), 1 (channels pipelined) or 2 (pipelined, scalar weights)";
   return nullptr;
 }
 const dag_p_conv* pconv(const void* p) { return static_cast<const dag_p_conv*>(p); }
@@ -1976,7 +2200,7 @@ const char* v_conv(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, 
   if (tiles > (1u << 30) || q->cout / conv_oc(q->cout) > 65535) return "grid too large";
   return nullptr;
 }
-hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
+hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
   const dag_p_conv* q = pconv(p);
   const uint32_t tiles_x = static_cast<uint32_t>(ceil_div(q->w / 2, kConvTile));
   const uint32_t tiles_y = static_cast<uint32_t>(ceil_div(q->h / 2, kConvTile));
@@ -1986,18 +2210,45 @@ hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   const auto* w = static_cast<const float*>(a[1]);
   const auto* bias = static_cast<const float*>(a[2]);
   auto* y = static_cast<float*>(a[3]);
-  if (oc == 8)
+  // variant 2 needs the fp64 weight copy in the stream's scratch (above the
+  // counters); where it does not fit, variant 1 runs instead
+  const uint64_t nw = static_cast<uint64_t>(q->cin) * q->cout * 9;
+  const bool sw = c.variant == 2 && nw <= reduction_capacity(sb);
+  double* w64 = sw ? reinterpret_cast<double*>(static_cast<char*>(scr) + kScratchPartialsOffset) : nullptr;
+  if (sw) {
+    const uint32_t gw = static_cast<uint32_t>(std::min<uint64_t>(ceil_div(nw, 256), 1024));
+    DAGRT_LAUNCH(k_conv_weights_f64, dim3(gw), dim3(256), 0, s, w, w64, q->cin, q->cout);
+  }
+  if (c.variant != 0) {
+#define DAGRT_CONV_PIPE(OC)                                                                                  \
+  if (sw)                                                                                                    \
+    DAGRT_LAUNCH((k_conv3x3_relu_pool_pipe<OC, true>), g, b, 0, s, x, w, w64, bias, y, q->cin, q->cout, q->h, \
+                 q->w, tiles_x);                                                                             \
+  else                                                                                                       \
+    DAGRT_LAUNCH((k_conv3x3_relu_pool_pipe<OC, false>), g, b, 0, s, x, w, w64, bias, y, q->cin, q->cout,     \
+                 q->h, q->w, tiles_x);
+    if (oc == 8) {
+      DAGRT_CONV_PIPE(8)
+    } else if (oc == 4) {
+      DAGRT_CONV_PIPE(4)
+    } else {
+      DAGRT_CONV_PIPE(1)
+    }
+#undef DAGRT_CONV_PIPE
+  } else if (oc == 8) {
     DAGRT_LAUNCH(k_conv3x3_relu_pool<8>, g, b, 0, s, x, w, bias, y, q->cin, q->h, q->w, tiles_x);
-  else if (oc == 4)
+  } else if (oc == 4) {
     DAGRT_LAUNCH(k_conv3x3_relu_pool<4>, g, b, 0, s, x, w, bias, y, q->cin, q->h, q->w, tiles_x);
-  else
+  } else {
     DAGRT_LAUNCH(k_conv3x3_relu_pool<1>, g, b, 0, s, x, w, bias, y, q->cin, q->h, q->w, tiles_x);
+  }
   return hipGetLastError();
 }
 
 const char* cfg_dense(const LaunchCfg& c) {
   if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
-  if (c.variant != 0) return "variant must be 0";
+  if (c.variant > 2)
+    return "variant must be 0 (one input per lane), 1 or 2 (contiguous 1 KB loads, 2 or 4 chunks in flight)";
   return nullptr;
 }
 const dag_p_dense* pdense(const void* p) { return static_cast<const dag_p_dense*>(p); }
@@ -2026,6 +2277,23 @@ hipError_t l_dense(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   const auto* W = static_cast<const float*>(a[1]);
   const auto* bias = static_cast<const float*>(a[2]);
   auto* y = static_cast<float*>(a[3]);
+  // variants 1 and 2 where their load pattern applies (M of 4, 8 or 16, aligned W)
+  if (c.variant != 0 && vec && (q->m == 4 || q->m == 8 || q->m == 16)) {
+#define DAGRT_DENSE_LANES(U)                                                                        \
+  if (q->m == 4)                                                                                    \
+    DAGRT_LAUNCH((k_dense_lanes<4, U>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);        \
+  else if (q->m == 8)                                                                               \
+    DAGRT_LAUNCH((k_dense_lanes<8, U>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);        \
+  else                                                                                              \
+    DAGRT_LAUNCH((k_dense_lanes<16, U>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);
+    if (c.variant == 1) {
+      DAGRT_DENSE_LANES(2)
+    } else {
+      DAGRT_DENSE_LANES(4)
+    }
+#undef DAGRT_DENSE_LANES
+    return hipGetLastError();
+  }
   switch (q->m) {
 #define DAGRT_DENSE_CASE(K) \
   case K: DAGRT_LAUNCH(k_dense<K>, g, b, 0, s, x, W, bias, y, q->n, vec, counter, partials); break;
@@ -2076,8 +2344,8 @@ const KernelDesc kTable[] = {
     /* 15 */ {"nb_proba", 4, 0x8, sizeof(dag_p_ml), {1024, 256, 0}, v_nb, l_nb, cfg_ml_one},
     /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ridge},
     /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml_one},
-    /* 18 */ {"conv3x3_relu_pool", 4, 0x8, sizeof(dag_p_conv), {256, 0, 0}, v_conv, l_conv, cfg_conv},
-    /* 19 */ {"dense", 4, 0x8, sizeof(dag_p_dense), {256, 1024, 0}, v_dense, l_dense, cfg_dense},
+    /* 18 */ {"conv3x3_relu_pool", 4, 0x8, sizeof(dag_p_conv), {256, 0, 1}, v_conv, l_conv, cfg_conv},
+    /* 19 */ {"dense", 4, 0x8, sizeof(dag_p_dense), {512, 256, 1}, v_dense, l_dense, cfg_dense},
     /* 20 */ {"siamese_combine", 5, 0x10, sizeof(dag_p_combine), {64, 0, 0}, v_combine2, l_combine2, cfg_combine},
 };
 

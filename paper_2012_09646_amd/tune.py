@@ -58,9 +58,13 @@ def candidates(kernel):
     if kernel == "ensemble":
         return [(b, c, 0) for b in BLOCKS for c in CAPS]
     if kernel == "dense":
-        return [(b, c, 0) for b in (256, 512, 1024) for c in (256, 512, 1024, 2048)]
+        # variant 0: one input per lane; 1, 2: whole 1 KB weight loads per wave,
+        # 2 or 4 chunks of 64 inputs in flight
+        return [(b, c, v) for b in (256, 512, 1024) for c in (256, 512, 1024, 2048) for v in (0, 1, 2)]
     if kernel == "conv3x3_relu_pool":
-        return [(256, 0, 0)]
+        # variant 0: one input channel per barrier pair; 1: channels pipelined;
+        # 2: pipelined with fp64 weights read as scalars
+        return [(256, 0, 0), (256, 0, 1), (256, 0, 2)]
     return []  # the delay kernel
 
 

@@ -30,21 +30,25 @@ def test_dl_pipeline(side, channels, embed):
     G.check_program(W.dl_program(side=side, seed=side, channels=channels, embed=embed))
 
 
-@pytest.mark.parametrize("m", [16, 7])
-@pytest.mark.parametrize("block,cap", [(256, 1024), (64, 3), (1024, 1), (512, 0)])
-def test_dense_reduction_launch_shapes(block, cap, m):
-    """Dense layer alone with several launch shapes, launched three times in
-    a row on one stream (the ticket counter must be back to zero each time)."""
-    banner("dense block=%d cap=%d m=%d" % (block, cap, m))
-    g = np.random.default_rng(block + cap + m)
-    n = 300007
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("m", [16, 7, 8, 4])
+@pytest.mark.parametrize("block,cap,n", [(256, 1024, 300007), (64, 3, 300007), (1024, 1, 300007), (512, 0, 300007),
+                                         (256, 256, 37), (128, 5, 64 * 13), (256, 7, 64 * 29 + 1)])
+def test_dense_reduction_launch_shapes(block, cap, n, m, variant):
+    """Dense layer alone with several launch shapes and variants (one input
+    per lane; whole 1 KB weight loads per wave with 2 or 4 chunks in flight,
+    which apply to 4, 8 or 16 outputs), inputs that leave a partial 64-input
+    chunk or none, launched three times in a row on one stream (the ticket
+    counter must be back to zero each time)."""
+    banner("dense block=%d cap=%d n=%d m=%d variant=%d" % (block, cap, n, m, variant))
+    g = np.random.default_rng(block + cap + m + n)
     x = g.random(n, dtype=np.float32) - 0.5
     w = g.random((n, m), dtype=np.float32) - 0.5      # stored input-major
     b = g.random(m, dtype=np.float32)
     ref = T.dense(x, w.T, b)
     ctx = D.Context(max_streams=1)
     try:
-        ctx.set_launch("dense", block, cap, 0)
+        ctx.set_launch("dense", block, cap, variant)
         hx, hw, hb, hy = ctx.alloc(x.nbytes), ctx.alloc(w.nbytes), ctx.alloc(b.nbytes), ctx.alloc(4 * m)
         ctx.host_write(hx, x)
         ctx.host_write(hw, w)
@@ -56,6 +60,46 @@ def test_dense_reduction_launch_shapes(block, cap, m):
             assert np.all(np.abs(y.astype(np.float64) - ref) <= 1e-5 * np.abs(ref.astype(np.float64))), (y, ref)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("variant,scratch", [(0, 0), (1, 0), (2, 0), (2, 4096)])
+@pytest.mark.parametrize("cin,cout,h,w", [(1, 16, 64, 64), (16, 32, 66, 98), (3, 8, 34, 36), (2, 4, 2, 2),
+                                          (5, 3, 40, 30), (17, 8, 50, 70), (4, 12, 96, 32)])
+def test_conv_launch_variants(variant, scratch, cin, cout, h, w):
+    """One convolution layer alone in each launch variant (one channel at a
+    time; channels pipelined through a double-buffered tile; pipelined with
+    fp64 weights read as scalars, which falls back to the second where the
+    stream scratch of 4096 bytes cannot hold the weight copy): ragged tiles,
+    odd and even channel counts, 8, 4 or 1 output channels per workgroup.
+    Every variant must agree with the others bit for bit (same FMA order)."""
+    banner("conv variant=%d scratch=%d cin=%d cout=%d h=%d w=%d" % (variant, scratch, cin, cout, h, w))
+    g = np.random.default_rng(cin * 1000 + cout + h + w)
+    x = (g.random((cin, h, w), dtype=np.float32) - 0.3).astype(np.float32)
+    wt = ((g.random((cout, cin, 3, 3), dtype=np.float32) - 0.5) / (3.0 * np.sqrt(cin))).astype(np.float32)
+    b = ((g.random(cout, dtype=np.float32) - 0.5) * 0.1).astype(np.float32)
+    ref = T.conv3x3_relu_pool(x, wt, b)
+    outs = {}
+    ctx = D.Context(max_streams=1, scratch_bytes=scratch)
+    try:
+        hx, hw_, hb = ctx.alloc(x.nbytes), ctx.alloc(wt.nbytes), ctx.alloc(b.nbytes)
+        hy = ctx.alloc(4 * cout * (h // 2) * (w // 2))
+        ctx.host_write(hx, x)
+        ctx.host_write(hw_, wt)
+        ctx.host_write(hb, b)
+        for v in [variant] + [u for u in (0, 1, 2) if u != variant]:
+            ctx.set_launch("conv3x3_relu_pool", 256, 0, v)
+            ctx.kernel("conv3x3_relu_pool", [(hx, "c"), (hw_, "c"), (hb, "c"), (hy, "m")],
+                       cin=cin, cout=cout, h=h, w=w)
+            y = np.zeros((cout, h // 2, w // 2), np.float32)
+            ctx.host_read(hy, y)
+            outs[v] = y
+    finally:
+        ctx.close()
+    y = outs[variant]
+    r = ref.astype(np.float64)
+    assert np.all(np.abs(y.astype(np.float64) - r) <= 1e-5 * np.abs(r)), np.max(np.abs(y - ref))
+    for v in (0, 1, 2):
+        assert np.array_equal(outs[v].view(np.uint32), y.view(np.uint32)), v
 
 
 def test_dl_full_size():
