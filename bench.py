@@ -36,11 +36,11 @@ FP64_PEAK_TFLOPS = 78.6   # vector fp64: 256 CUs x 128 flop/clk (4 SIMDs x 16 la
 # 83 + 44 + 23 + 3, variant 0, the library erfc, 127 + 61 + 22 + 7).  VALU wave-lane instructions per element
 # (all kinds) per variant:
 BS_FLOPS_PER_ELEMENT = 2 * 86 + 5 + 19 + 3
-BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25, 2: 153.625}
+BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25, 2: 144.125}
 # HBM bytes per bs_call launch (variant 2, 128 threads, grid cap 4096) from FETCH_SIZE / WRITE_SIZE, each divided
-# by what the counter reads for a 256 MiB copy kernel (FETCH_SIZE 0.500034x, WRITE_SIZE 1.000x of the true
+# by what the counter reads for a 256 MiB copy kernel (FETCH_SIZE 0.500027x, WRITE_SIZE 1.000x of the true
 # bytes): 16.14 MiB in + 16.00 MiB out
-TRAFFIC_BS_BYTES = int((8264.490625 / 0.5000344 + 16384.0 / 1.0) * 1024)
+TRAFFIC_BS_BYTES = int((8266.28125 / 0.5000268 + 16384.0 / 1.0) * 1024)
 CUS, CLOCK_GHZ = 256, 2.4
 SERVE_HW_QUEUES = 8
 

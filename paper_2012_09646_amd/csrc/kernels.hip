@@ -277,6 +277,17 @@ __device__ __forceinline__ double bs_price_fast(double s, const BsConst& k) {
   return s * n1 - k.disc_strike * n2;
 }
 
+// a * b + c as one three-address v_fma_f64.  For a Horner step whose
+// coefficient sits in a vector register (the kernel keeps more constants than
+// the scalar registers hold), the compiler otherwise picks the accumulating
+// form, which overwrites its addend, and copies the coefficient first: one
+// extra 64-bit move per step.
+__device__ __forceinline__ double fma_3addr(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 // ln 2 split so that k * kLn2Hi is exact for |k| < 2^21 (its low 21 mantissa
 // bits are zero); kLn2Lo is the rest.
 constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
@@ -296,7 +307,7 @@ __device__ __forceinline__ double exp_nonpos(double x) {
                             0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};  // 1/n!
   double p = c[13];
 #pragma unroll
-  for (int i = 12; i >= 0; --i) p = fma(p, r, c[i]);
+  for (int i = 12; i >= 0; --i) p = fma_3addr(p, r, c[i]);
   return ldexp(p, static_cast<int>(kd));
 }
 
@@ -322,7 +333,7 @@ __device__ __forceinline__ double log_pos(double y) {
                             0x1.1111111111111p-4, 0x1.e1e1e1e1e1e1ep-5, 0x1.af286bca1af28p-5};  // 1/(2n+1)
   double q = c[9];
 #pragma unroll
-  for (int i = 8; i >= 0; --i) q = fma(q, u2, c[i]);
+  for (int i = 8; i >= 0; --i) q = fma_3addr(q, u2, c[i]);
   const double ed = static_cast<double>(e);
   return fma(ed, kLn2Hi, fma(ed, kLn2Lo, 2.0 * u * q));
 }
