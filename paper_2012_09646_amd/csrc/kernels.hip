@@ -1501,7 +1501,12 @@ __global__ __launch_bounds__(1024) void k_dense(const float* __restrict__ x, con
 // 4) chunks are loaded before any is used.  At the end the lanes holding the
 // same outputs are added by a fixed butterfly (masks M/4 .. 32), so the sum
 // order is fixed for a given launch shape.
-template <int M, int U>
+//
+// SPLIT: the blocks only store their partials, and a second one-block kernel
+// on the same stream adds them (no ticket counter, no fences): each block's
+// agent-scope release fence and ticket atomic cost ~40 ns, serialised over
+// the blocks, which is ~11 us at 256 blocks.
+template <int M, int U, bool SPLIT>
 __global__ __launch_bounds__(1024) void k_dense_lanes(const float* __restrict__ x, const float* __restrict__ W,
                                                       const float* __restrict__ bias, float* __restrict__ y,
                                                       uint64_t n, uint32_t* counter, uint64_t* partials) {
@@ -1561,7 +1566,40 @@ __global__ __launch_bounds__(1024) void k_dense_lanes(const float* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 4; ++k) sh[wv_ * kDenseMaxOut + 4 * lane + k] = acc[k];
   }
-  dense_finish<M>(sh, &flag, bias, y, counter, partials);
+  if constexpr (SPLIT) {
+    __syncthreads();
+    if (threadIdx.x < M) {
+      const int nw = (blockDim.x + kWave - 1) / kWave;
+      double t = 0.0;
+      for (int q = 0; q < nw; ++q) t += sh[q * kDenseMaxOut + threadIdx.x];
+      partials[static_cast<uint64_t>(blockIdx.x) * kDenseMaxOut + threadIdx.x] = d2u(t);
+    }
+  } else {
+    dense_finish<M>(sh, &flag, bias, y, counter, partials);
+  }
+}
+
+// Final step of the split dense layer: one workgroup adds the partials of
+// nblocks blocks in the order of dense_finish (output j = t % 16 over one
+// range of blocks per thread, then the ranges in order), plus the bias.
+template <int M>
+__global__ __launch_bounds__(1024) void k_dense_final(const uint64_t* __restrict__ partials, uint32_t nblocks,
+                                                      const float* __restrict__ bias, float* __restrict__ y) {
+  __shared__ double sh[1024];
+  const uint32_t j = threadIdx.x % kDenseMaxOut, r = threadIdx.x / kDenseMaxOut;
+  const uint32_t nr = blockDim.x / kDenseMaxOut;
+  const uint32_t per = (nblocks + nr - 1) / nr;
+  const uint32_t q1 = min((r + 1) * per, nblocks);
+  double t = 0.0;
+  if (j < static_cast<uint32_t>(M))
+    for (uint32_t q = min(r * per, nblocks); q < q1; ++q) t += u2d(partials[q * kDenseMaxOut + j]);
+  sh[r * kDenseMaxOut + j] = t;
+  __syncthreads();
+  if (threadIdx.x < M) {
+    double sum = 0.0;
+    for (uint32_t k = 0; k < nr; ++k) sum += sh[k * kDenseMaxOut + threadIdx.x];
+    y[threadIdx.x] = static_cast<float>(sum + static_cast<double>(bias[threadIdx.x]));
+  }
 }
 
 // p = sigmoid(w . [e1; e2] + b), 2m <= 64: one wave, a fixed butterfly sum.
@@ -2258,8 +2296,9 @@ hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
 
 const char* cfg_dense(const LaunchCfg& c) {
   if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be a multiple of 64 in [64, 1024]";
-  if (c.variant > 2)
-    return "variant must be 0 (one input per lane), 1 or 2 (contiguous 1 KB loads, 2 or 4 chunks in flight)";
+  if (c.variant > 4)
+    return "variant must be 0 (one input per lane), 1 or 2 (contiguous 1 KB loads, 2 or 4 chunks in flight), "
+           "3 or 4 (the same with the final add in a second kernel)";
   return nullptr;
 }
 const dag_p_dense* pdense(const void* p) { return static_cast<const dag_p_dense*>(p); }
@@ -2288,21 +2327,37 @@ hipError_t l_dense(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   const auto* W = static_cast<const float*>(a[1]);
   const auto* bias = static_cast<const float*>(a[2]);
   auto* y = static_cast<float*>(a[3]);
-  // variants 1 and 2 where their load pattern applies (M of 4, 8 or 16, aligned W)
+  // variants 1 to 4 where their load pattern applies (M of 4, 8 or 16, aligned W):
+  // 1, 2: 2 or 4 chunks in flight, last block adds; 3, 4: the same, final add
+  // in a second kernel
   if (c.variant != 0 && vec && (q->m == 4 || q->m == 8 || q->m == 16)) {
-#define DAGRT_DENSE_LANES(U)                                                                        \
-  if (q->m == 4)                                                                                    \
-    DAGRT_LAUNCH((k_dense_lanes<4, U>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);        \
-  else if (q->m == 8)                                                                               \
-    DAGRT_LAUNCH((k_dense_lanes<8, U>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);        \
-  else                                                                                              \
-    DAGRT_LAUNCH((k_dense_lanes<16, U>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);
+#define DAGRT_DENSE_LANES(U, SPLIT)                                                                     \
+  if (q->m == 4)                                                                                        \
+    DAGRT_LAUNCH((k_dense_lanes<4, U, SPLIT>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);     \
+  else if (q->m == 8)                                                                                   \
+    DAGRT_LAUNCH((k_dense_lanes<8, U, SPLIT>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);     \
+  else                                                                                                  \
+    DAGRT_LAUNCH((k_dense_lanes<16, U, SPLIT>), g, b, 0, s, x, W, bias, y, q->n, counter, partials);
+    const bool split = c.variant >= 3;
     if (c.variant == 1) {
-      DAGRT_DENSE_LANES(2)
+      DAGRT_DENSE_LANES(2, false)
+    } else if (c.variant == 2) {
+      DAGRT_DENSE_LANES(4, false)
+    } else if (c.variant == 3) {
+      DAGRT_DENSE_LANES(2, true)
     } else {
-      DAGRT_DENSE_LANES(4)
+      DAGRT_DENSE_LANES(4, true)
     }
 #undef DAGRT_DENSE_LANES
+    if (split) {
+      const uint32_t nb = g.x;
+      if (q->m == 4)
+        DAGRT_LAUNCH(k_dense_final<4>, dim3(1), dim3(256), 0, s, partials, nb, bias, y);
+      else if (q->m == 8)
+        DAGRT_LAUNCH(k_dense_final<8>, dim3(1), dim3(256), 0, s, partials, nb, bias, y);
+      else
+        DAGRT_LAUNCH(k_dense_final<16>, dim3(1), dim3(256), 0, s, partials, nb, bias, y);
+    }
     return hipGetLastError();
   }
   switch (q->m) {
@@ -2356,7 +2411,7 @@ const KernelDesc kTable[] = {
     /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ridge},
     /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml_one},
     /* 18 */ {"conv3x3_relu_pool", 4, 0x8, sizeof(dag_p_conv), {256, 0, 1}, v_conv, l_conv, cfg_conv},
-    /* 19 */ {"dense", 4, 0x8, sizeof(dag_p_dense), {512, 256, 1}, v_dense, l_dense, cfg_dense},
+    /* 19 */ {"dense", 4, 0x8, sizeof(dag_p_dense), {512, 256, 3}, v_dense, l_dense, cfg_dense},
     /* 20 */ {"siamese_combine", 5, 0x10, sizeof(dag_p_combine), {64, 0, 0}, v_combine2, l_combine2, cfg_combine},
 };
 

@@ -59,8 +59,9 @@ def candidates(kernel):
         return [(b, c, 0) for b in BLOCKS for c in CAPS]
     if kernel == "dense":
         # variant 0: one input per lane; 1, 2: whole 1 KB weight loads per wave,
-        # 2 or 4 chunks of 64 inputs in flight
-        return [(b, c, v) for b in (256, 512, 1024) for c in (256, 512, 1024, 2048) for v in (0, 1, 2)]
+        # 2 or 4 chunks of 64 inputs in flight; 3, 4: the same with the final
+        # add in a second kernel
+        return [(b, c, v) for b in (256, 512, 1024) for c in (128, 256, 512, 1024, 2048) for v in (0, 1, 2, 3, 4)]
     if kernel == "conv3x3_relu_pool":
         # variant 0: one input channel per barrier pair; 1: channels pipelined;
         # 2: pipelined with fp64 weights read as scalars

@@ -30,16 +30,17 @@ def test_dl_pipeline(side, channels, embed):
     G.check_program(W.dl_program(side=side, seed=side, channels=channels, embed=embed))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("m", [16, 7, 8, 4])
 @pytest.mark.parametrize("block,cap,n", [(256, 1024, 300007), (64, 3, 300007), (1024, 1, 300007), (512, 0, 300007),
                                          (256, 256, 37), (128, 5, 64 * 13), (256, 7, 64 * 29 + 1)])
 def test_dense_reduction_launch_shapes(block, cap, n, m, variant):
     """Dense layer alone with several launch shapes and variants (one input
     per lane; whole 1 KB weight loads per wave with 2 or 4 chunks in flight,
-    which apply to 4, 8 or 16 outputs), inputs that leave a partial 64-input
-    chunk or none, launched three times in a row on one stream (the ticket
-    counter must be back to zero each time)."""
+    which apply to 4, 8 or 16 outputs, the last block adding the partials or
+    a second kernel), inputs that leave a partial 64-input chunk or none,
+    launched three times in a row on one stream (the ticket counter must be
+    back to zero each time)."""
     banner("dense block=%d cap=%d n=%d m=%d variant=%d" % (block, cap, n, m, variant))
     g = np.random.default_rng(block + cap + m + n)
     x = g.random(n, dtype=np.float32) - 0.5
