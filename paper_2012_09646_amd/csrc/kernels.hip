@@ -1591,8 +1591,18 @@ __global__ __launch_bounds__(1024) void k_dense_final(const uint64_t* __restrict
   const uint32_t per = (nblocks + nr - 1) / nr;
   const uint32_t q1 = min((r + 1) * per, nblocks);
   double t = 0.0;
-  if (j < static_cast<uint32_t>(M))
-    for (uint32_t q = min(r * per, nblocks); q < q1; ++q) t += u2d(partials[q * kDenseMaxOut + j]);
+  if (j < static_cast<uint32_t>(M)) {
+    // eight loads in flight, then added in block order
+    uint32_t q = min(r * per, nblocks);
+    for (; q + 8 <= q1; q += 8) {
+      uint64_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partials[(q + u) * kDenseMaxOut + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t += u2d(v[u]);
+    }
+    for (; q < q1; ++q) t += u2d(partials[q * kDenseMaxOut + j]);
+  }
   sh[r * kDenseMaxOut + j] = t;
   __syncthreads();
   if (threadIdx.x < M) {
@@ -2352,11 +2362,11 @@ hipError_t l_dense(hipStream_t s, void* const* a, const void* p, const LaunchCfg
     if (split) {
       const uint32_t nb = g.x;
       if (q->m == 4)
-        DAGRT_LAUNCH(k_dense_final<4>, dim3(1), dim3(256), 0, s, partials, nb, bias, y);
+        DAGRT_LAUNCH(k_dense_final<4>, dim3(1), dim3(1024), 0, s, partials, nb, bias, y);
       else if (q->m == 8)
-        DAGRT_LAUNCH(k_dense_final<8>, dim3(1), dim3(256), 0, s, partials, nb, bias, y);
+        DAGRT_LAUNCH(k_dense_final<8>, dim3(1), dim3(1024), 0, s, partials, nb, bias, y);
       else
-        DAGRT_LAUNCH(k_dense_final<16>, dim3(1), dim3(256), 0, s, partials, nb, bias, y);
+        DAGRT_LAUNCH(k_dense_final<16>, dim3(1), dim3(1024), 0, s, partials, nb, bias, y);
     }
     return hipGetLastError();
   }
@@ -2411,7 +2421,7 @@ const KernelDesc kTable[] = {
     /* 16 */ {"ridge_proba", 6, 0x20, sizeof(dag_p_ml), {256, 0, 0}, v_ridge, l_ridge, cfg_ridge},
     /* 17 */ {"ensemble", 4, 0xC, sizeof(dag_p_ml), {256, 0, 0}, v_ensemble, l_ensemble, cfg_ml_one},
     /* 18 */ {"conv3x3_relu_pool", 4, 0x8, sizeof(dag_p_conv), {256, 0, 1}, v_conv, l_conv, cfg_conv},
-    /* 19 */ {"dense", 4, 0x8, sizeof(dag_p_dense), {512, 256, 3}, v_dense, l_dense, cfg_dense},
+    /* 19 */ {"dense", 4, 0x8, sizeof(dag_p_dense), {512, 512, 4}, v_dense, l_dense, cfg_dense},
     /* 20 */ {"siamese_combine", 5, 0x10, sizeof(dag_p_combine), {64, 0, 0}, v_combine2, l_combine2, cfg_combine},
 };
 
