@@ -1116,19 +1116,15 @@ __global__ __launch_bounds__(256) void k_ridge_proba4(const float* __restrict__ 
     // the next kU4 features are loaded while the current ones are used
     constexpr int kU4 = kMlUnroll / 2;
     uint32_t f = 0;
+    // loads ahead clamped to the last feature, so the body has no branch
     float4 x[kU4];
-    if (F >= static_cast<uint32_t>(kU4)) {
 #pragma unroll
-      for (int u = 0; u < kU4; ++u) x[u] = col[static_cast<uint64_t>(u) * groups];
-    }
+    for (int u = 0; u < kU4; ++u) x[u] = col[static_cast<uint64_t>(min(static_cast<uint32_t>(u), F - 1)) * groups];
 #pragma unroll 1
     for (; f + kU4 <= F; f += kU4) {
       float4 xn[kU4];
-      const bool more = f + 2 * kU4 <= F;
-      if (more) {
 #pragma unroll
-        for (int u = 0; u < kU4; ++u) xn[u] = col[static_cast<uint64_t>(f + kU4 + u) * groups];
-      }
+      for (int u = 0; u < kU4; ++u) xn[u] = col[static_cast<uint64_t>(min(f + kU4 + u, F - 1)) * groups];
 #pragma unroll
       for (int u = 0; u < kU4; ++u) {
         const double mu = s_mu[f + u];
@@ -1138,10 +1134,8 @@ __global__ __launch_bounds__(256) void k_ridge_proba4(const float* __restrict__ 
         ridge_add<C>(acc[2], w, static_cast<double>(x[u].z) - mu);
         ridge_add<C>(acc[3], w, static_cast<double>(x[u].w) - mu);
       }
-      if (more) {
 #pragma unroll
-        for (int u = 0; u < kU4; ++u) x[u] = xn[u];
-      }
+      for (int u = 0; u < kU4; ++u) x[u] = xn[u];
     }
     for (; f < F; ++f) {
       const float4 x = col[static_cast<uint64_t>(f) * groups];
@@ -1154,6 +1148,66 @@ __global__ __launch_bounds__(256) void k_ridge_proba4(const float* __restrict__ 
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) softmax_store<C>(acc[j], P + (4 * g + j) * C);
+  }
+}
+
+// Two consecutive rows per thread with 8-byte loads (n even, X 8-byte
+// aligned) and eight features in flight: the four-row kernel needs about 250
+// registers (two waves per SIMD); two rows' accumulators and the loads in
+// flight fit in 128 (four waves).  Same sums in the same order as the
+// one-row kernel.
+template <int C>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ridge_proba2(
+    const float* __restrict__ X, const float* __restrict__ mean, const float* __restrict__ scale,
+    const float* __restrict__ W, const float* __restrict__ b, float* __restrict__ P, uint64_t n, uint32_t F) {
+  extern __shared__ __align__(16) double s_w[];  // [f][c] weights / scale, then F means
+  double* s_mu = s_w + F * C;
+  for (uint32_t i = threadIdx.x; i < C * F; i += blockDim.x) {
+    const uint32_t c = i / F, f = i - c * F;  // W is [c][f]
+    s_w[f * C + c] = static_cast<double>(W[i]) / static_cast<double>(scale[f]);
+  }
+  for (uint32_t f = threadIdx.x; f < F; f += blockDim.x) s_mu[f] = static_cast<double>(mean[f]);
+  __syncthreads();
+  const uint64_t pairs = n / 2;  // float2 columns per feature
+  const float2* X2 = reinterpret_cast<const float2*>(X);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  constexpr int kU = 8;
+  for (uint64_t g = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; g < pairs; g += stride) {
+    double acc[2][C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[0][c] = acc[1][c] = static_cast<double>(b[c]);
+    const float2* col = X2 + g;
+    uint32_t f = 0;
+    // the loads ahead are clamped to the last feature instead of skipped, so
+    // the loop body has no branch (a branch there split it, and the compiler
+    // then hoisted every feature's weight reads and spilled)
+    float2 x[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = col[static_cast<uint64_t>(min(static_cast<uint32_t>(u), F - 1)) * pairs];
+#pragma unroll 1
+    for (; f + kU <= F; f += kU) {
+      float2 xn[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) xn[u] = col[static_cast<uint64_t>(min(f + kU + u, F - 1)) * pairs];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const double mu = s_mu[f + u];
+        const double* w = s_w + (f + u) * C;
+        ridge_add<C>(acc[0], w, static_cast<double>(x[u].x) - mu);
+        ridge_add<C>(acc[1], w, static_cast<double>(x[u].y) - mu);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) x[u] = xn[u];
+    }
+    for (; f < F; ++f) {
+      const float2 xv = col[static_cast<uint64_t>(f) * pairs];
+      const double mu = s_mu[f];
+      const double* w = s_w + f * C;
+      ridge_add<C>(acc[0], w, static_cast<double>(xv.x) - mu);
+      ridge_add<C>(acc[1], w, static_cast<double>(xv.y) - mu);
+    }
+    softmax_store<C>(acc[0], P + (2 * g) * C);
+    softmax_store<C>(acc[1], P + (2 * g + 1) * C);
   }
 }
 
@@ -2123,8 +2177,8 @@ const char* ml_common(const dag_p_ml* q) {
 }
 
 const char* cfg_ridge(const LaunchCfg& c) {
-  if (c.variant != 0 && c.variant != 4) return "variant: rows per thread, 0 = one, 4 = four";
-  const uint32_t top = c.variant == 4 ? 256 : 512;
+  if (c.variant != 0 && c.variant != 2 && c.variant != 4) return "variant: rows per thread, 0 = one, 2 = two, 4 = four";
+  const uint32_t top = c.variant != 0 ? 256 : 512;
   if (c.block < 64 || c.block > top || c.block % 64)
     return "block must be a multiple of 64 in [64, 512] ([64, 256] for variant 4)";
   return nullptr;
@@ -2184,7 +2238,8 @@ hipError_t l_ridge(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   if (q->n == 0) return hipSuccess;
   // four rows per thread need 16-byte aligned float4 columns (n % 4 == 0), else one row
   const bool four = c.variant == 4 && q->n % 4 == 0 && aligned16(a[0]);
-  const dim3 g(stream_grid(four ? q->n / 4 : q->n, c)), b(c.block);
+  const bool two = c.variant == 2 && q->n % 2 == 0 && reinterpret_cast<uintptr_t>(a[0]) % 8 == 0;
+  const dim3 g(stream_grid(four ? q->n / 4 : (two ? q->n / 2 : q->n), c)), b(c.block);
   const size_t shm = ridge_lds_bytes(q);
   const auto* X = static_cast<const float*>(a[0]);
   const auto* mean = static_cast<const float*>(a[1]);
@@ -2197,6 +2252,8 @@ hipError_t l_ridge(hipStream_t s, void* const* a, const void* p, const LaunchCfg
   case K:                                                                                                  \
     if (four)                                                                                              \
       DAGRT_LAUNCH((k_ridge_proba4<K>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);      \
+    else if (two)                                                                                          \
+      DAGRT_LAUNCH((k_ridge_proba2<K>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);      \
     else                                                                                                   \
       DAGRT_LAUNCH((k_ridge_proba<K>), g, b, shm, s, X, mean, scale, W, bias, P, q->n, q->features);       \
     break;

@@ -53,8 +53,9 @@ def candidates(kernel):
         # one workgroup per CU fits beside the 128 KB table: its size sets the waves per CU
         return [(b, c, 0) for b in (256, 512, 1024) for c in (0, 256, 512, 1024)]
     if kernel == "ridge_proba":
-        # variant = rows per thread: 0 one, 4 four by 16-byte loads (workgroups up to 256)
-        return [(b, c, v) for b in (64, 128, 256, 512) for c in CAPS for v in (0, 4) if v != 4 or b <= 256]
+        # variant = rows per thread: 0 one, 2 two by 8-byte loads, 4 four by
+        # 16-byte loads (workgroups up to 256 for 2 and 4)
+        return [(b, c, v) for b in (64, 128, 256, 512) for c in CAPS for v in (0, 2, 4) if v == 0 or b <= 256]
     if kernel == "ensemble":
         return [(b, c, 0) for b in BLOCKS for c in CAPS]
     if kernel == "dense":

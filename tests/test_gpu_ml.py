@@ -71,14 +71,16 @@ def test_ml_pipeline(n, F, C, V):
     {"nb_proba": (512, 1, 0), "ridge_proba": (128, 1, 0), "ensemble": (128, 1, 0)},
     {"nb_proba": (1024, 256, 0), "ridge_proba": (256, 1024, 4), "ensemble": (256, 0, 0)},
     {"nb_proba": (1024, 256, 0), "ridge_proba": (64, 3, 4), "ensemble": (256, 0, 0)},
+    {"nb_proba": (1024, 256, 0), "ridge_proba": (256, 1024, 2), "ensemble": (256, 0, 0)},
+    {"nb_proba": (1024, 256, 0), "ridge_proba": (64, 5, 2), "ensemble": (256, 0, 0)},
 ])
 def test_ml_launch_configurations(launch, C):
     """Grid-stride loops that wrap several times, single workgroups, small
-    and large workgroups, one or four rows per thread: same results."""
+    and large workgroups, one, two or four rows per thread: same results."""
     banner("ml launch %s C=%d" % (launch, C))
     F = 200 if C == 10 else 127
-    # 5004 rows: a multiple of 4, so the four-row variant runs (5003 would fall back to one row)
-    prog = W.ml_program(n=5004 if launch["ridge_proba"][2] == 4 else 5003, seed=9, features=F, classes=C,
+    # 5004 rows: a multiple of 4, so the two- and four-row variants run (5003 would fall back to one row)
+    prog = W.ml_program(n=5004 if launch["ridge_proba"][2] in (2, 4) else 5003, seed=9, features=F, classes=C,
                         categories=16)
     ref = G.oracle_run(prog)
     outs, _ = run(prog, launch)
@@ -135,6 +137,36 @@ def test_ml_full_size_sampled():
     for g, o in ((g_nb, pnb), (g_rr, prr), (g_avg, avg)):
         assert np.all(np.abs(g.astype(np.float64) - o) <= 1e-5 * np.abs(o.astype(np.float64)))
     check_labels(np.ascontiguousarray(outs["label"].view(np.int32)[rows]), lab, avg, 10)
+
+
+@pytest.mark.parametrize("F", [1, 3, 8, 9, 17])
+@pytest.mark.parametrize("variant", [0, 2, 4])
+def test_ridge_few_features(variant, F):
+    """Ridge alone with fewer features than the loads kept in flight (and
+    just above): the loads ahead stop at the last feature."""
+    banner("ridge variant=%d F=%d" % (variant, F))
+    from oracle import tasks as T
+    n, C = 1004, 10
+    g = np.random.default_rng(F + 10 * variant)
+    X = (g.random((F, n), dtype=np.float32) * 4.0 - 2.0).astype(np.float32)    # feature-major
+    mean = (g.random(F, dtype=np.float32) - 0.5).astype(np.float32)
+    scale = (g.random(F, dtype=np.float32) + 0.5).astype(np.float32)
+    Wt = (g.random((C, F), dtype=np.float32) - 0.5).astype(np.float32)
+    b = (g.random(C, dtype=np.float32) - 0.5).astype(np.float32)
+    ref = T.ridge_predict_proba(np.ascontiguousarray(X.T), mean, scale, Wt, b)
+    ctx = D.Context(max_streams=1)
+    try:
+        ctx.set_launch("ridge_proba", 64, 3, variant)
+        hs = [ctx.alloc(a.nbytes) for a in (X, mean, scale, Wt, b)]
+        for h_, a in zip(hs, (X, mean, scale, Wt, b)):
+            ctx.host_write(h_, a)
+        hp = ctx.alloc(4 * n * C)
+        ctx.kernel("ridge_proba", [(h_, "c") for h_ in hs] + [(hp, "m")], n=n, features=F, classes=C)
+        P = np.zeros((n, C), np.float32)
+        ctx.host_read(hp, P)
+    finally:
+        ctx.close()
+    assert np.all(np.abs(P.astype(np.float64) - ref) <= 1e-5 * np.abs(ref.astype(np.float64)))
 
 
 def test_ml_zero_rows():
