@@ -418,6 +418,30 @@ __device__ __forceinline__ bool tile_of(int tiles_x, int ntiles, int xcd_map, in
   return true;
 }
 
+// Stage image rows [y0 - R, y0 - R + IH) x columns [x0 - R, x0 - R + 64 + 2R)
+// (clamped to the border) into s: a 256-thread workgroup's lane keeps one
+// column for the whole tile and each wave takes every fourth row, so the row
+// is uniform per wave and a load costs an add; the 2R halo columns are a
+// second load by the first 2R lanes.
+template <int R, int IH, int SW>
+__device__ __forceinline__ void stage_tile(const float* __restrict__ in, float (*s)[SW], int w, int h, int x0,
+                                           int y0) {
+  static_assert(2 * R <= 64 && SW >= kTW + 2 * R, "halo wider than a wave");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gx_main = min(max(x0 - R + lane, 0), w - 1);
+  const int gx_halo = min(max(x0 - R + kTW + lane, 0), w - 1);
+#pragma unroll
+  for (int k = 0; k < (IH + 3) / 4; ++k) {
+    const int r = wv + 4 * k;
+    if (r < IH) {
+      const int gy = min(max(y0 - R + r, 0), h - 1);
+      const float* row = in + static_cast<size_t>(gy) * w;
+      s[r][lane] = row[gx_main];
+      if (lane < 2 * R) s[r][kTW + lane] = row[gx_halo];
+    }
+  }
+}
+
 // Separable Gaussian: stage the input tile with its halo in LDS (fp32, as
 // stored), horizontal pass into an fp64 LDS tile, vertical pass to output.
 template <int R>
@@ -431,12 +455,7 @@ __global__ __launch_bounds__(256) void k_gauss_blur(const float* __restrict__ in
   __shared__ double s_h[IH][kTW];
   int x0, y0;
   if (!tile_of(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
-  for (int i = threadIdx.x; i < IH * IW; i += 256) {
-    const int r = i / IW, c = i - r * IW;
-    const int gy = min(max(y0 - R + r, 0), h - 1);
-    const int gx = min(max(x0 - R + c, 0), w - 1);
-    s_in[r][c] = in[static_cast<size_t>(gy) * w + gx];
-  }
+  stage_tile<R, IH, IW>(in, s_in, w, h, x0, y0);
   __syncthreads();
   // horizontal pass: each work item produces 4 adjacent outputs of one row
   // from one register window of 4 + 2R inputs (4x fewer LDS reads)
@@ -481,12 +500,7 @@ __global__ __launch_bounds__(256) void k_sobel(const float* __restrict__ in,
   __shared__ float s_in[IH][IW];
   int x0, y0;
   if (!tile_of(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
-  for (int i = threadIdx.x; i < IH * IW; i += 256) {
-    const int r = i / IW, c = i - r * IW;
-    const int gy = min(max(y0 - 1 + r, 0), h - 1);
-    const int gx = min(max(x0 - 1 + c, 0), w - 1);
-    s_in[r][c] = in[static_cast<size_t>(gy) * w + gx];
-  }
+  stage_tile<1, IH, IW>(in, s_in, w, h, x0, y0);
   __syncthreads();
   // each thread: 4 rows of one column from a 6 x 3 register window
   constexpr int G = 4;
