@@ -273,12 +273,17 @@ dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
 #define DAG_K_CONV3X3_RELU_POOL 18u /* x w b:c y:m   y[o] = maxpool2x2(relu(b[o] +
                                     sum_c corr3x3(x[c], w[o][c]))), zero
                                     padding; x: cin x h x w, w: cout x cin x
-                                    3 x 3, y: cout x h/2 x w/2 (h, w even) */
+                                    3 x 3, y: cout x h/2 x w/2 (h, w even);
+                                    launch variant 2 keeps an fp64 copy of w
+                                    in the stream's scratch (variant 1 runs
+                                    where it does not fit) */
 #define DAG_K_DENSE 19u          /* x W b:c y:m         y[j] = sum_i W[i][j] x[i] + b[j],
                                     W: n x m row-major (input-major: the m
                                     weights of input i adjacent), m <= 16
                                     (uses the stream's scratch for
-                                    per-workgroup partials) */
+                                    per-workgroup partials; launch variants
+                                    3 and 4 add them in a second kernel on
+                                    the same stream) */
 #define DAG_K_SIAMESE_COMBINE 20u /* e1 e2 w b:c p:m     p[0] = sigmoid(w . [e1; e2]
                                     + b[0]), e1, e2: m <= 32, w: 2m */
 #define DAG_K_USER_BASE 1000u    /* ids of dag_kernel_register */

@@ -1341,7 +1341,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_relu_pool(const float* __restri
 // [input channel][output channel][9] and are read with uniform (scalar)
 // loads straight into the FMAs' scalar operand, instead of being broadcast
 // from LDS: a 16-byte broadcast read still returns 1 KB per wave, and 72 of
-// them per channel nearly saturate the CU's LDS bandwidth.
+// them per channel nearly saturate the CU's LDS bandwidth.  (Measured slower
+// than the LDS form on every shape tried: the scalar loads' latency shows.)
 template <int OC, bool SW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_conv3x3_relu_pool_pipe(
     const float* __restrict__ x, const float* __restrict__ w, const double* __restrict__ w64,
