@@ -132,7 +132,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: the scheduler space-shares a single device; "
-              "multi-GPU runs are not part of this build (got --gpus %d)" % args.gpus, file=sys.stderr)
+              "runs on more than one GPU are not supported (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if not args.hw_queues and args.tuned and os.path.exists(args.tuned) and args.workload != "all":
         # the workload's tuned hardware queue count (the serving loop: 8, which
