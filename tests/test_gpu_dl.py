@@ -103,6 +103,35 @@ def test_conv_launch_variants(variant, scratch, cin, cout, h, w):
         assert np.array_equal(outs[v].view(np.uint32), y.view(np.uint32)), v
 
 
+@pytest.mark.parametrize("graph_mode", [0, 1])
+@pytest.mark.parametrize("conv_variant,dense_variant", [(2, 3), (2, 4), (1, 1)])
+def test_dl_region_replays_with_two_kernel_tasks(graph_mode, conv_variant, dense_variant):
+    """The DL DAG recorded as a region (hipGraph, or recorded multi-stream
+    replay) while its convolution and dense tasks launch two kernels each
+    (an fp64 weight copy, then the convolution; partial sums, then the final
+    add): three replays, the inputs uploaded again before each, every
+    replay's outputs checked against the oracle."""
+    from paper_2012_09646_amd import runner
+    banner("dl region graph_mode=%d conv=%d dense=%d" % (graph_mode, conv_variant, dense_variant))
+    prog = W.dl_program(side=96, seed=31, channels=(8, 16), embed=16)
+    ref = G.oracle_run(prog)
+    ctx = D.Context(graph_mode=graph_mode)
+    try:
+        ctx.set_launch("conv3x3_relu_pool", 256, 0, conv_variant)
+        ctx.set_launch("dense", 256, 64, dense_variant)
+        b = runner.Bound(ctx, prog)
+        b.record(1)
+        for _ in range(3):
+            for name in prog.outputs:
+                ctx.host_write(b.h[name], np.zeros(prog.bufs[name].nbytes, np.uint8))
+            b.upload([n for n in prog.bufs if prog.bufs[n].init is not None])
+            b.replay(1)
+            for name in prog.outputs:
+                G.assert_close(prog, name, b.read(name), ref[name])
+    finally:
+        ctx.close()
+
+
 def test_dl_full_size():
     """The benchmark's shape: two 1024 x 1024 images, 16 and 32 channels, 16-wide embeddings."""
     banner("dl full size")
