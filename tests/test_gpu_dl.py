@@ -132,8 +132,37 @@ def test_dl_region_replays_with_two_kernel_tasks(graph_mode, conv_variant, dense
         ctx.close()
 
 
+_FULL = {}
+
+
+def _full_size_reference():
+    if not _FULL:
+        prog = W.dl_program(side=1024, seed=6)
+        _FULL["prog"], _FULL["ref"] = prog, G.oracle_run(prog)
+    return _FULL["prog"], _FULL["ref"]
+
+
 def test_dl_full_size():
     """The benchmark's shape: two 1024 x 1024 images, 16 and 32 channels, 16-wide embeddings."""
     banner("dl full size")
     prog = W.dl_program(side=1024, seed=6)
     G.check_program(prog)
+
+
+@pytest.mark.parametrize("conv_variant,dense_variant,dense_block,dense_cap",
+                         [(0, 0, 256, 1024), (2, 3, 512, 256), (1, 4, 512, 512), (1, 2, 1024, 128)])
+def test_dl_full_size_launch_variants(conv_variant, dense_variant, dense_block, dense_cap):
+    """The benchmark's shape in other launch variants of the convolution and
+    dense kernels than the tuned ones: every output against the oracle."""
+    banner("dl full size conv=%d dense=%d (%d, %d)" % (conv_variant, dense_variant, dense_block, dense_cap))
+    prog, ref = _full_size_reference()
+    ctx = D.Context()
+    try:
+        ctx.set_launch("conv3x3_relu_pool", 256, 0, conv_variant)
+        ctx.set_launch("dense", dense_block, dense_cap, dense_variant)
+        b = runner.Bound(ctx, prog)
+        b.run()
+        for name in prog.outputs:
+            G.assert_close(prog, name, b.read(name), ref[name])
+    finally:
+        ctx.close()
