@@ -115,15 +115,17 @@ def test_ensemble_bit_exact_on_the_oracles_posteriors(n, C, tied):
         assert np.any(ref["label"].view(np.int32) > 0)
 
 
-def test_ml_full_size_sampled():
+@pytest.mark.parametrize("ridge_launch", [None, (256, 1024, 2), (256, 4096, 4)])
+def test_ml_full_size_sampled(ridge_launch):
     """The benchmark's shape (2^20 rows, 200 features, 10 classes, 16
-    categories) in the default launch configuration: 4096 sampled rows
-    against the oracle computed for those rows alone (rows are independent)."""
+    categories) in the default launch configuration and with the two- and
+    four-row ridge kernels: 4096 sampled rows against the oracle computed for
+    those rows alone (rows are independent)."""
     from oracle import tasks as T
     n = 1 << 20
-    banner("ml full size n=%d" % n)
+    banner("ml full size n=%d ridge %s" % (n, ridge_launch))
     prog = W.ml_program(n=n, seed=5)
-    outs, _ = run(prog)
+    outs, _ = run(prog, {"ridge_proba": ridge_launch} if ridge_launch else None)
     d = {k: prog.bufs[k].init for k in ("X", "log_theta", "log_prior", "mean", "scale", "W", "b")}
     rows = np.sort(np.random.default_rng(1).choice(n, 4096, replace=False))
     rows[0], rows[-1] = 0, n - 1
