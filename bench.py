@@ -433,21 +433,11 @@ def main():
         ctx = D.Context(spin_wait=args.spin_wait,
                         copy_engine=args.copy_engine if args.serve_copy_engine < 0 else args.serve_copy_engine)
         tune.apply_kernels(ctx, tuned)
-        kinds = ("vec", "bs", "img", "hits")
-        tmpls = []
-        key = 1000
-        for kind in kinds:
-            for k in W.SERVE_KS:
-                prog = W.serve_program(kind, k, seed=4, graphs=graphs)
-                tmpls.append(serving.ShapeTemplate(ctx, prog, key=key, result_bytes=64))
-                key += 1
-        budget = 64 << 30
-        srv = serving.Server(ctx, budget, host_arena_bytes=8 << 30, lanes=args.serve_lanes, bypass=32,
-                             copy_lanes=args.serve_copy_lanes, transfer_lanes=args.serve_transfer_lanes)
-        foot = []
-        for t in tmpls:
-            sid = srv.add(t)
-            foot.append(srv.footprint(sid))
+        tmpls = serving.mix_templates(ctx, graphs=graphs, result_bytes=64)
+        budget = serving.MIX_BUDGET
+        srv = serving.mix_server(ctx, tmpls, lanes=args.serve_lanes, copy_lanes=args.serve_copy_lanes,
+                                 transfer_lanes=args.serve_transfer_lanes)
+        foot = [srv.footprint(sid) for sid in range(len(tmpls))]
         def one_rate(rate, nreq, serial=True):
             arr, shp = W.poisson_trace(4, nreq, rate, len(tmpls))
             log("serving: %d requests at %g/s, %d shapes" % (len(arr), rate, len(tmpls)))

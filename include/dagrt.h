@@ -227,8 +227,12 @@ dag_status dag_buffer_register(dag_ctx ctx, void* ptr, size_t bytes, uint32_t lo
  * 256-byte aligned, not initialised). */
 dag_status dag_buffer_alloc(dag_ctx ctx, size_t bytes, uint32_t loc, dag_buf* out);
 /* Wait for every active task that uses the buffer (as a host write would),
- * then drop the handle; library-owned memory is freed. */
+ * then drop the handle; library-owned memory is freed.  Recorded regions
+ * that use the buffer can no longer be launched (dag_region_launch returns
+ * DAG_E_INVAL).  DAG_E_BUSY while a serving shape uses the buffer. */
 dag_status dag_buffer_release(dag_ctx ctx, dag_buf buf);
+/* Address and size of a registered buffer (the managed object behind a
+ * handle, Sec. IV-A), e.g. to hand it to code outside the scheduler. */
 dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
 
 /* ---- kernels --------------------------------------------------------------
@@ -418,7 +422,8 @@ dag_status dag_submit_batch(dag_ctx ctx, const dag_op* ops, uint32_t nops,
  * dag_region_launch(key) replays it as ONE task whose access set is the
  * union of the region's accesses (MUTABLE wins), with its dependencies on
  * earlier tasks inferred like any call.  Re-recording an existing key
- * replaces it. */
+ * replaces it; both are refused (DAG_E_BUSY) while a serving shape uses the
+ * key, as is dag_region_drop. */
 dag_status dag_region_begin(dag_ctx ctx, uint64_t key);
 dag_status dag_region_end(dag_ctx ctx);
 dag_status dag_region_launch(dag_ctx ctx, uint64_t key, dag_task* out);
@@ -434,8 +439,10 @@ dag_status dag_region_launch(dag_ctx ctx, uint64_t key, dag_task* out);
  * call that differs, or at the end when only a prefix matched, the calls so
  * far are submitted eagerly, the rest of the region runs eagerly, and the new
  * sequence replaces the recording at dag_region_run_end (*out = 0,
- * *replayed = 0).  Host accesses, sync and release are refused inside
- * (DAG_E_BUSY).  out and replayed may be NULL. */
+ * *replayed = 0); if a serving shape uses the recording, it is kept and the
+ * run is only eager.  A recording whose buffer was released is recorded
+ * anew.  Host accesses, sync and release are refused inside (DAG_E_BUSY).
+ * out and replayed may be NULL. */
 dag_status dag_region_run_begin(dag_ctx ctx, uint64_t key);
 dag_status dag_region_run_end(dag_ctx ctx, dag_task* out, uint32_t* replayed);
 /* Hand-written schedules (the paper compares its scheduler with
@@ -460,17 +467,28 @@ dag_status dag_region_info(dag_ctx ctx, uint64_t key, uint32_t* ntasks, uint32_t
 dag_status dag_region_drop(dag_ctx ctx, uint64_t key);
 
 /* ---- introspection ------------------------------------------------------- */
-/* Edge records in order of (dst, src, buf); *n = total count even when it
- * exceeds cap (then only cap records are written). */
+/* The computation DAG (Sec. IV-A: one edge per dependency, labelled with the
+ * argument that causes it).  Edge records in order of (dst, src, buf); *n =
+ * total count even when it exceeds cap (then only cap records are
+ * written). */
 dag_status dag_edges(dag_ctx ctx, dag_edge* out, size_t cap, size_t* n);
-/* Parents a task waited on through events (ascending ids). */
+/* Parents a task waited on through events (ascending ids): the
+ * synchronisation events of Sec. IV-B, placed only for parents on other
+ * streams (Sec. IV-C). */
 dag_status dag_task_waits(dag_ctx ctx, dag_task t, dag_task* out, uint32_t cap, uint32_t* n);
-/* Trace times need the task to have completed; this call waits for it. */
+/* A task's kind, stream (Sec. IV-C), activity (Sec. IV-B) and parent and
+ * wait counts; trace times (the per-computation timing the contention-free
+ * bound of Sec. V-E and the overlap figures of Sec. V-F use) need the task
+ * to have completed; this call waits for it. */
 dag_status dag_task_get_info(dag_ctx ctx, dag_task t, dag_task_info* out);
+/* Counters of the context (Sec. IV-B: tasks, vertices, edges, event waits,
+ * host waits, streams of the pool; host time spent scheduling). */
 dag_status dag_get_stats(dag_ctx ctx, dag_stats* out);
-/* Wait for all work, then restart the trace clock (trace mode only). */
+/* Wait for all work, then restart the trace clock (trace mode only): the
+ * time origin of the intervals the overlap figures of Sec. V-F use. */
 dag_status dag_trace_reset(dag_ctx ctx);
-/* HIP stream of pool stream index i (as void*), e.g. to time on it. */
+/* HIP stream of pool stream index i (as void*; the stream manager of
+ * Sec. IV-C), e.g. to time on it. */
 dag_status dag_stream_handle(dag_ctx ctx, uint32_t i, void** stream);
 
 /* ---- serving loop ------------------------------------------------------------
@@ -539,45 +557,93 @@ typedef struct {
   void* result;        /* host memory for result_bytes, or NULL */
 } dag_request;
 
+/* One completed request. */
 typedef struct {
-  uint64_t admit_ns; /* enqueued on the GPU (after the start of the run) */
-  uint64_t done_ns;  /* completion observed */
+  uint64_t id;         /* dag_serve_submit's id: 0, 1, ... in submission
+                          order within the session (dag_serve_run: the
+                          request's index) */
+  uint64_t arrival_ns; /* scheduled (or stamped) arrival, ns after the start
+                          of the session */
+  uint64_t admit_ns;   /* enqueued on the GPU */
+  uint64_t done_ns;    /* completion observed */
+  uint32_t shape;
   uint32_t lane;
-  uint32_t reserved;
-} dag_request_done;
+} dag_serve_done;
 
 typedef struct {
   double p50_ms, p99_ms, mean_ms, max_ms; /* latency = done - arrival
                                              (nearest-rank percentiles) */
-  double req_per_s;          /* n / (last completion - first arrival) */
-  double wall_ms;            /* run start to last completion */
+  double req_per_s;          /* completed / (last completion - first arrival) */
+  double wall_ms;            /* session start to last completion */
   uint64_t peak_device_bytes; /* max footprint in flight */
   uint32_t max_inflight;
   uint32_t max_queued;
-} dag_serve_stats;
+  uint64_t completed;        /* requests completed in the session */
+} dag_serve_summary;
 
 #define DAG_SERVE_CONCURRENT 0u /* continuous admission, lanes in parallel */
 #define DAG_SERVE_SERIAL 1u     /* one request at a time on one lane, the
                                    host waiting after every call (baseline) */
+#define DAG_SERVE_NOW UINT64_MAX /* dag_serve_submit: arrival = now */
 
 dag_status dag_serve_create(dag_ctx ctx, const dag_serve_config* cfg, dag_server* out);
-/* Waits for the lanes, frees the arenas. */
+/* Waits for the lanes, frees the arenas, unpins the shapes' regions and
+ * buffers.  Destroy every server before its context. */
 dag_status dag_serve_destroy(dag_server s);
 /* Register a shape: the region recorded under region_key, the role of every
  * buffer it uses (all must be listed), and the buffer whose first
  * result_bytes are returned per request (0 = none).  sim_ns is the service
  * time assumed by schedule-only contexts (dry_run), which simulate the loop
- * on a virtual clock instead of running it. */
+ * on a virtual clock instead of running it.  While the shape exists its
+ * region cannot be re-recorded or dropped and its buffers (and INIT sources)
+ * cannot be released (DAG_E_BUSY).  Not allowed while a session runs. */
 dag_status dag_serve_add_shape(dag_server s, uint64_t region_key, const dag_shape_buf* bufs,
                                uint32_t nbufs, dag_buf result_buf, size_t result_bytes,
                                uint64_t sim_ns, uint32_t* shape_id);
 /* Per-request footprint of a shape (device arena bytes, pinned arena bytes). */
 dag_status dag_serve_shape_info(dag_server s, uint32_t shape, uint64_t* device_bytes,
                                 uint64_t* host_bytes);
-/* Run the whole arrival trace (blocks until every request completed).
- * done[i] receives the timestamps of reqs[i]; stats may be NULL. */
+
+/* Online serving.  A session starts with dag_serve_start (its clock starts
+ * there) and accepts requests until dag_serve_close.  dag_serve_submit and
+ * dag_serve_close may be called from any thread, also while another thread
+ * is inside dag_serve_poll (they only hand the request over, without a HIP
+ * call, and return a status without setting the context's message); every
+ * other call on the server or its context must come from the one thread
+ * that polls.  dag_serve_poll runs the loop: it moves requests whose arrival
+ * time has come into the admission queue, retires requests whose completion
+ * event has fired (copying their results to the caller's memory), and admits
+ * queued requests while they fit, as described above.  It returns once at
+ * least one completion is ready to be reported, once every submitted
+ * request of a closed session has been reported, or after wait_us, and
+ * writes up to cap completions into done (in completion order; *n = count).
+ * *outstanding (optional) = requests submitted and not yet reported.
+ * Schedule-only contexts advance a virtual clock; it never passes the
+ * arrival of the latest submission until the session is closed, so a
+ * producer that submits in arrival order gets exactly the admissions and
+ * completions of a run that knew every request from the start. */
+dag_status dag_serve_start(dag_server s, uint32_t mode);
+/* arrival_ns: scheduled arrival in ns after dag_serve_start, non-decreasing
+ * over the submissions of a session (DAG_E_INVAL otherwise), or
+ * DAG_SERVE_NOW (not in schedule-only contexts).  result: host memory for
+ * the shape's result_bytes (or NULL), written before the completion is
+ * reported.  *id (optional) = the request's id.  DAG_E_BUSY: no session, or
+ * the session is closed. */
+dag_status dag_serve_submit(dag_server s, uint32_t shape, uint64_t arrival_ns, void* result,
+                            uint64_t* id);
+/* No more submissions in this session. */
+dag_status dag_serve_close(dag_server s);
+dag_status dag_serve_poll(dag_server s, uint64_t wait_us, dag_serve_done* done, uint32_t cap,
+                          uint32_t* n, uint64_t* outstanding);
+/* Latency percentiles, throughput and occupancy over the requests the
+ * session has completed so far. */
+dag_status dag_serve_stats(dag_server s, dag_serve_summary* out);
+/* A whole arrival trace as one session: starts it, submits every request
+ * with its scheduled arrival, closes it and polls until every request has
+ * completed (blocks).  done[i] receives request i's record; stats may be
+ * NULL. */
 dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint32_t mode,
-                         dag_request_done* done, dag_serve_stats* stats);
+                         dag_serve_done* done, dag_serve_summary* stats);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,7 @@ struct Buffer {
   uint64_t plan_nrows = 0, plan_nnz = 0;
   int32_t plan_stream = -1;  // pool stream the partition ran on
   hipEvent_t plan_ev = nullptr;
+  uint32_t pins = 0;  // serving shapes that use it (release is refused while > 0)
 };
 
 struct UserKernel {
@@ -77,6 +78,8 @@ struct Region {
   hipGraphExec_t exec = nullptr;
   void* scratch = nullptr;  // nstreams * scratch_bytes (graph mode)
   std::vector<hipEvent_t> evs;  // replay-mode events (per task)
+  bool dead = false;  // a buffer it uses was released: it can no longer be launched
+  uint32_t pins = 0;  // serving shapes built on it (re-recording and dropping are refused while > 0)
 };
 
 constexpr uint32_t kMaxArgs = 16;
@@ -119,7 +122,10 @@ struct dag_ctx_s {
   bool matching = false;
   uint64_t match_key = 0;
   size_t match_pos = 0;
-  bool in_region() const { return recording || matching; }
+  // the calls diverged from a recording that a serving shape uses: the rest
+  // of this run is eager and nothing is recorded
+  bool eager_run = false;
+  bool in_region() const { return recording || matching || eager_run; }
   std::unique_ptr<dagrt::Region> rec;
   std::vector<hipStream_t> aux;           // capture / replay streams
   std::vector<void*> aux_scratch;

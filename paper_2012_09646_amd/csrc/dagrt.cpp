@@ -471,9 +471,14 @@ dag_status diverge(dag_ctx c) {
   const Region* old = c->regions.at(c->match_key).get();
   const size_t n = c->match_pos;
   c->matching = false;
-  c->recording = true;
-  c->rec_key = c->match_key;
-  c->rec.reset(new Region());
+  if (old->pins) {
+    // a serving shape uses the recording: keep it, run this pass eagerly
+    c->eager_run = true;
+  } else {
+    c->recording = true;
+    c->rec_key = c->match_key;
+    c->rec.reset(new Region());
+  }
   for (size_t k = 0; k < n; ++k) {
     const RegionTask& t = old->tasks[k];
     dag_status st = t.kind == TK_KERNEL
@@ -918,6 +923,7 @@ dag_status dag_buffer_release(dag_ctx c, dag_buf h) {
   if (c->in_region()) return fail(c, DAG_E_BUSY, "release inside a region");
   Buffer* b = get_buf(c, h);
   if (!b) return fail(c, DAG_E_INVAL, "invalid buffer handle %u", h);
+  if (b->pins) return fail(c, DAG_E_BUSY, "buffer %u is used by %u serving shape(s)", h, b->pins);
   c->tr.add_host(TK_RELEASE, h - 1, ACC_W, c->serial, &c->tmp_wait);
   dag_status st = host_wait(c);
   if (st) return st;
@@ -925,6 +931,24 @@ dag_status dag_buffer_release(dag_ctx c, dag_buf h) {
   c->tr.retire(c->tr.last_id(), &c->tmp_retired);
   recycle_retired(c);
   if (!c->dry) free_plan(b);  // every SpMV that read it has completed
+  // Recorded regions hold the buffer's address (in their calls and in their
+  // graphs): they can no longer be launched.
+  bool any_dead = false;
+  for (auto& kv : c->regions) {
+    Region* r = kv.second.get();
+    if (r->dead) continue;
+    for (const Access& a : r->accs)
+      if (a.buf == h - 1) {
+        r->dead = true;
+        any_dead = true;
+        break;
+      }
+  }
+  if (any_dead && !c->dry) {
+    HIP_TRY(c, hipDeviceSynchronize());  // a replay may still be in flight
+    for (auto& kv : c->regions)
+      if (kv.second->dead) free_region(kv.second.get());
+  }
   if (b->owned && !c->dry) {
     hipError_t e = b->loc == DAG_PINNED_HOST ? hipHostFree(b->ptr) : hipFree(b->ptr);
     if (e != hipSuccess) return hip_fail(c, e, "free");
@@ -1111,9 +1135,9 @@ dag_status dag_submit_batch(dag_ctx c, const dag_op* ops, uint32_t nops, dag_tas
 dag_status dag_region_begin(dag_ctx c, uint64_t key) {
   CHECK_CTX(c);
   if (c->in_region()) return fail(c, DAG_E_BUSY, "a region is already being recorded");
-  if (c->dry && c->cfg.graph_mode == 0) {
-    // schedule-only contexts record the region but never build a graph
-  }
+  auto it = c->regions.find(key);
+  if (it != c->regions.end() && it->second->pins)
+    return fail(c, DAG_E_BUSY, "region key is used by a serving shape and cannot be re-recorded");
   c->recording = true;
   c->rec_key = key;
   c->rec.reset(new Region());
@@ -1164,6 +1188,7 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   auto it = c->regions.find(key);
   if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
   Region* r = it->second.get();
+  if (r->dead) return fail(c, DAG_E_INVAL, "region uses a released buffer");
   const auto t0 = Clock::now();
   int32_t s;
   bool created;
@@ -1197,6 +1222,7 @@ dag_status dag_region_set_schedule(dag_ctx c, uint64_t key, const dag_sched* sch
   auto it = c->regions.find(key);
   if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
   Region* r = it->second.get();
+  if (r->dead) return fail(c, DAG_E_INVAL, "region uses a released buffer");
   if (!sched || n != r->tasks.size())
     return fail(c, DAG_E_INVAL, "the schedule needs one entry per recorded call (%zu)", r->tasks.size());
   // vector clocks of the hand-written order: snap[k][s] = the last position
@@ -1253,7 +1279,8 @@ dag_status dag_region_info(dag_ctx c, uint64_t key, uint32_t* ntasks, uint32_t* 
 dag_status dag_region_run_begin(dag_ctx c, uint64_t key) {
   CHECK_CTX(c);
   if (c->in_region()) return fail(c, DAG_E_BUSY, "a region is already open");
-  if (c->regions.find(key) == c->regions.end()) return dag_region_begin(c, key);
+  auto it = c->regions.find(key);
+  if (it == c->regions.end() || it->second->dead) return dag_region_begin(c, key);
   c->matching = true;
   c->match_key = key;
   c->match_pos = 0;
@@ -1274,6 +1301,10 @@ dag_status dag_region_run_end(dag_ctx c, dag_task* out, uint32_t* replayed) {
     dag_status st = diverge(c);  // only a prefix matched: run it and record anew
     if (st) return st;
   }
+  if (c->eager_run) {
+    c->eager_run = false;
+    return DAG_OK;
+  }
   if (!c->recording) return fail(c, DAG_E_BUSY, "no region is open");
   return dag_region_end(c);
 }
@@ -1283,6 +1314,7 @@ dag_status dag_region_drop(dag_ctx c, uint64_t key) {
   if (c->in_region()) return fail(c, DAG_E_BUSY, "region drop inside a region");
   auto it = c->regions.find(key);
   if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
+  if (it->second->pins) return fail(c, DAG_E_BUSY, "region is used by a serving shape");
   if (!c->dry) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");

@@ -8,12 +8,16 @@
 // (Sec. IV); serving applies the same space-sharing across independent
 // requests, each of which is a DAG recorded like a recurring region.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
-#include <new>
 #include <deque>
 #include <map>
+#include <mutex>
+#include <new>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "context.hpp"
@@ -108,15 +112,24 @@ struct Shape {
   uint64_t dev_bytes = 0, host_bytes = 0;  // per-request block sizes
   uint64_t result_off = 0;                 // in the host block (device results)
   uint64_t sim_ns;
+  std::vector<uint32_t> pinned;  // buffer slots pinned while the shape exists
 };
 
 struct Flight {
-  uint32_t req;
+  uint64_t req;       // request id
   uint32_t lane;
   hipEvent_t ev;
   uint64_t dev_off, host_off;
   uint64_t sim_done;  // schedule-only contexts
   std::vector<hipEvent_t> evs;  // copy-lane mode: events of the request's calls
+};
+
+// A submitted request (the caller's view: shape, arrival, result memory).
+struct Req {
+  uint64_t id;
+  uint32_t shape;
+  uint64_t arrival_ns;
+  void* result;
 };
 
 }  // namespace
@@ -136,6 +149,30 @@ struct dag_server_s {
   std::vector<hipStream_t> copy_st[3];  // [kOnH2D], [kOnD2H]: copy lanes per direction
   uint64_t launched = 0;                // requests launched (rotates the copy lanes)
   std::vector<hipEvent_t> free_ev;
+
+  // ---- session (dag_serve_start .. end of the last request) ----
+  bool started = false;
+  bool serial = false;
+  Clock::time_point t0;
+  // shared with submitting threads (guarded by mu)
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Req> incoming;  // submitted, not yet taken by the polling thread
+  uint64_t next_id = 0;
+  uint64_t horizon = 0;      // arrival of the last submission (schedule-only clock bound)
+  bool closed = false;
+  // owned by the polling thread
+  std::deque<Req> pending;   // submitted, arrival still in the future
+  std::deque<Req> queue;     // arrived, waiting for admission (FIFO, bounded bypass)
+  std::vector<std::deque<Flight>> flights;  // per lane, in launch order
+  std::vector<uint64_t> lane_free;          // schedule-only: virtual time a lane drains
+  std::unordered_map<uint64_t, Req> live;   // admitted requests by id
+  std::unordered_map<uint64_t, dag_serve_done> admitted;  // admission records by id
+  std::deque<dag_serve_done> unreported;    // completions not yet returned by poll
+  std::vector<double> lat_ms;               // latencies of completed requests
+  uint64_t used = 0, peak = 0, vclock = 0, taken = 0, ndone = 0;
+  uint64_t first_arrival = UINT64_MAX, last_done = 0;
+  uint32_t inflight = 0, max_inflight = 0, max_queued = 0;
 };
 
 namespace {
@@ -282,6 +319,202 @@ void copy_result(const dag_server_s* s, const Shape& sh, uint64_t dev_off, uint6
   std::memcpy(out, src, sh.result_bytes);
 }
 
+// ---- the polling thread's loop ---------------------------------------------
+
+uint64_t now_ns(const dag_server_s* s) {
+  if (s->ctx->dry) return s->vclock;
+  return static_cast<uint64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - s->t0).count());
+}
+
+// Take what submitting threads have handed over; *closed and *horizon
+// receive the submission state seen at that moment.
+void take_incoming(dag_server s, bool* closed, uint64_t* horizon) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  while (!s->incoming.empty()) {
+    s->pending.push_back(s->incoming.front());
+    s->incoming.pop_front();
+  }
+  s->taken = s->next_id;
+  *closed = s->closed;
+  *horizon = s->horizon;
+}
+
+// Retire the request at the head of a lane.
+void complete(dag_server s, uint32_t lane, uint64_t when) {
+  Flight f = std::move(s->flights[lane].front());
+  s->flights[lane].pop_front();
+  auto it = s->live.find(f.req);
+  const Req rq = it->second;
+  s->live.erase(it);
+  const Shape& sh = s->shapes[rq.shape];
+  copy_result(s, sh, f.dev_off, f.host_off, rq.result);
+  dag_serve_done d = s->admitted[f.req];
+  s->admitted.erase(f.req);
+  d.done_ns = when;
+  s->unreported.push_back(d);
+  s->lat_ms.push_back((static_cast<double>(when) - static_cast<double>(rq.arrival_ns)) * 1e-6);
+  s->last_done = std::max(s->last_done, when);
+  if (sh.dev_bytes) s->dev.release(f.dev_off, sh.dev_bytes);
+  if (sh.host_bytes) s->host.release(f.host_off, sh.host_bytes);
+  s->used -= sh.dev_bytes;
+  if (f.ev) s->free_ev.push_back(f.ev);
+  for (hipEvent_t e : f.evs) s->free_ev.push_back(e);
+  --s->inflight;
+  ++s->ndone;
+}
+
+// One pass at the current time: arrivals into the queue, finished requests
+// retired (each lane completes in order), queued requests admitted while
+// their footprint fits (FIFO with a bounded bypass).  *progress = whether
+// anything changed.
+dag_status step(dag_server s, uint64_t now, bool* progress) {
+  dag_ctx c = s->ctx;
+  const bool dry = c->dry;
+  *progress = false;
+  while (!s->pending.empty() && s->pending.front().arrival_ns <= now) {
+    s->queue.push_back(s->pending.front());
+    s->pending.pop_front();
+  }
+  s->max_queued = std::max<uint32_t>(s->max_queued, static_cast<uint32_t>(s->queue.size()));
+  const uint32_t nl = static_cast<uint32_t>(s->flights.size());
+  for (uint32_t l = 0; l < nl; ++l) {
+    while (!s->flights[l].empty()) {
+      const Flight& f = s->flights[l].front();
+      bool fin;
+      if (dry) {
+        fin = f.sim_done <= now;
+      } else {
+        const hipError_t q = hipEventQuery(f.ev);
+        if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(c, q, "hipEventQuery");
+        if (q == hipErrorNotReady) (void)hipGetLastError();
+        fin = q == hipSuccess;
+      }
+      if (!fin) break;
+      complete(s, l, dry ? f.sim_done : now);
+      *progress = true;
+    }
+  }
+  uint32_t scanned = 0;
+  for (auto it = s->queue.begin(); it != s->queue.end() && scanned < std::max<uint32_t>(s->cfg.bypass, 1);) {
+    ++scanned;
+    if (s->serial && s->inflight) break;
+    const Req rq = *it;
+    const Shape& sh = s->shapes[rq.shape];
+    uint64_t doff = 0, hoff = 0;
+    bool ok = s->used + sh.dev_bytes <= s->cfg.budget_bytes;
+    if (ok && sh.dev_bytes) ok = s->dev.alloc(sh.dev_bytes, &doff);
+    if (ok && sh.host_bytes && !s->host.alloc(sh.host_bytes, &hoff)) {
+      if (sh.dev_bytes) s->dev.release(doff, sh.dev_bytes);
+      ok = false;
+    }
+    if (!ok) {
+      ++it;
+      continue;
+    }
+    // the lane with the fewest requests in flight (lowest index on ties)
+    // among the lanes of the request's class
+    uint32_t lo = 0, hi = nl;
+    if (!s->serial && s->cfg.transfer_lanes) {
+      if (sh.host_io)
+        hi = s->cfg.transfer_lanes;
+      else
+        lo = s->cfg.transfer_lanes;
+    }
+    uint32_t lane = lo;
+    for (uint32_t l = lo + 1; l < hi; ++l)
+      if (s->flights[l].size() < s->flights[lane].size()) lane = l;
+    Flight f{rq.id, lane, nullptr, doff, hoff, 0, {}};
+    if (dry) {
+      const uint64_t start = std::max(now, s->lane_free[lane]);
+      s->lane_free[lane] = f.sim_done = start + sh.sim_ns;
+    } else {
+      dag_status st = launch_request(s, sh, doff, hoff, s->lanes[lane], s->lane_scratch[lane], s->serial, &f.evs);
+      if (st) return st;
+      st = ev_get(s, &f.ev);
+      if (st) return st;
+      HIP_TRY(c, hipEventRecord(f.ev, s->lanes[lane]));
+    }
+    dag_serve_done d{};
+    d.id = rq.id;
+    d.arrival_ns = rq.arrival_ns;
+    d.admit_ns = now;
+    d.shape = rq.shape;
+    d.lane = lane;
+    s->admitted[rq.id] = d;
+    s->live[rq.id] = rq;
+    s->flights[lane].push_back(std::move(f));
+    s->used += sh.dev_bytes;
+    s->peak = std::max(s->peak, s->used);
+    ++s->inflight;
+    s->max_inflight = std::max(s->max_inflight, s->inflight);
+    it = s->queue.erase(it);
+    *progress = true;
+  }
+  return DAG_OK;
+}
+
+bool all_done(dag_server s, bool closed) {
+  return closed && s->pending.empty() && s->queue.empty() && s->inflight == 0 && s->ndone == s->taken;
+}
+
+// Advance the loop until a completion is available to report, everything is
+// done, or (GPU contexts) wait_us has passed.  Schedule-only contexts run on
+// a virtual clock that jumps to the next arrival or completion; it never
+// passes the arrival of the last submission until the session is closed, so
+// requests submitted later in arrival order are seen exactly as if they had
+// all been known from the start.
+dag_status advance(dag_server s, uint64_t wait_us) {
+  dag_ctx c = s->ctx;
+  const bool dry = c->dry;
+  const auto w0 = Clock::now();
+  for (;;) {
+    bool closed;
+    uint64_t horizon;
+    take_incoming(s, &closed, &horizon);
+    if (all_done(s, closed) || !s->unreported.empty()) return DAG_OK;
+    const uint64_t now = now_ns(s);
+    if (dry && !closed && now >= horizon) return DAG_OK;  // wait for the next submission
+    bool progress = false;
+    dag_status st = step(s, now, &progress);
+    if (st) return st;
+    if (progress) continue;
+    if (dry) {
+      uint64_t t = UINT64_MAX;
+      if (!s->pending.empty()) t = s->pending.front().arrival_ns;
+      for (const auto& fl : s->flights)
+        if (!fl.empty()) t = std::min(t, fl.front().sim_done);
+      if (t == UINT64_MAX) {
+        if (!s->queue.empty()) return fail(c, DAG_E_RANGE, "a queued request can never be admitted");
+        return DAG_OK;  // nothing to do until a submission
+      }
+      if (!closed && t >= horizon) return DAG_OK;
+      s->vclock = std::max(s->vclock, t);
+      continue;
+    }
+    if (s->inflight == 0 && !s->queue.empty())
+      return fail(c, DAG_E_RANGE, "a queued request can never be admitted (arena fragmentation)");
+    const double waited = us_since(w0);
+    if (waited >= static_cast<double>(wait_us)) return DAG_OK;
+    if (s->inflight == 0 && s->queue.empty()) {
+      // idle: sleep until shortly before the next known arrival, or up to
+      // 1 ms when none is known; a submission or the close wakes it
+      const double left_ns = (static_cast<double>(wait_us) - waited) * 1e3;
+      uint64_t sleep_ns = 0;
+      if (!s->pending.empty()) {
+        const uint64_t a = s->pending.front().arrival_ns;
+        sleep_ns = a > now + 200000 ? a - now - 100000 : 0;
+      } else if (!closed) {
+        sleep_ns = 1000000;
+      }
+      sleep_ns = std::min<uint64_t>(sleep_ns, static_cast<uint64_t>(std::max(left_ns, 0.0)));
+      if (sleep_ns) {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv.wait_for(lk, std::chrono::nanoseconds(sleep_ns), [&] { return !s->incoming.empty() || s->closed; });
+      }
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -342,6 +575,11 @@ dag_status dag_serve_destroy(dag_server s) {
       if (st) (void)hipStreamSynchronize(st);
     for (auto& v : s->copy_st)
       for (hipStream_t st : v) (void)hipStreamSynchronize(st);
+    for (const auto& fl : s->flights)
+      for (const Flight& f : fl) {
+        if (f.ev) (void)hipEventDestroy(f.ev);
+        for (hipEvent_t e : f.evs) (void)hipEventDestroy(e);
+      }
     for (hipStream_t st : s->lanes)
       if (st) (void)hipStreamDestroy(st);
     for (auto& v : s->copy_st)
@@ -352,6 +590,12 @@ dag_status dag_serve_destroy(dag_server s) {
     if (s->dev_base) (void)hipFree(s->dev_base);
     if (s->host_base) (void)hipHostFree(s->host_base);
   }
+  // unpin the regions and buffers the shapes use
+  for (Shape& sh : s->shapes) {
+    if (sh.region->pins) --sh.region->pins;
+    for (uint32_t slot : sh.pinned)
+      if (slot < s->ctx->bufs.size() && s->ctx->bufs[slot].pins) --s->ctx->bufs[slot].pins;
+  }
   delete s;
   return DAG_OK;
 }
@@ -361,8 +605,10 @@ dag_status dag_serve_add_shape(dag_server s, uint64_t key, const dag_shape_buf* 
   if (!s) return DAG_E_INVAL;
   dag_ctx c = s->ctx;
   CHECK_CTX(c);
+  if (s->started) return fail(c, DAG_E_BUSY, "shapes cannot be added while a session runs");
   auto it = c->regions.find(key);
   if (it == c->regions.end()) return fail(c, DAG_E_NOTFOUND, "unknown region key");
+  if (it->second->dead) return fail(c, DAG_E_INVAL, "region uses a released buffer");
   if (!bufs || nbufs == 0 || !shape_id) return fail(c, DAG_E_INVAL, "shape buffers required");
   Shape sh;
   sh.region = it->second.get();
@@ -377,11 +623,13 @@ dag_status dag_serve_add_shape(dag_server s, uint64_t key, const dag_shape_buf* 
     if (slot_to_buf[bufs[i].buf - 1] >= 0) return fail(c, DAG_E_INVAL, "shape buffer %u listed twice", i);
     slot_to_buf[bufs[i].buf - 1] = static_cast<int32_t>(i);
     ShapeBuf sb{bufs[i].role, b->ptr, b->bytes, b->loc, nullptr, 0, 0};
+    sh.pinned.push_back(bufs[i].buf - 1);
     if (bufs[i].role == DAG_ROLE_INIT) {
       Buffer* src = get_buf(c, bufs[i].init_src);
       if (!src || src->bytes < b->bytes) return fail(c, DAG_E_INVAL, "shape buffer %u: bad init source", i);
       sb.init_src = src->ptr;
       sb.init_loc = src->loc;
+      sh.pinned.push_back(bufs[i].init_src - 1);
     }
     if (bufs[i].role != DAG_ROLE_SHARED) {
       uint64_t& total = b->loc == DAG_PINNED_HOST ? sh.host_bytes : sh.dev_bytes;
@@ -427,6 +675,11 @@ dag_status dag_serve_add_shape(dag_server s, uint64_t key, const dag_shape_buf* 
   plan_copy_lanes(&sh);
   if (sh.dev_bytes > s->cfg.budget_bytes) return fail(c, DAG_E_RANGE, "shape needs more than the budget");
   if (sh.host_bytes > s->cfg.host_arena_bytes) return fail(c, DAG_E_RANGE, "shape needs more than the host arena");
+  // the region and the buffers stay as recorded while the shape exists
+  ++sh.region->pins;
+  std::sort(sh.pinned.begin(), sh.pinned.end());
+  sh.pinned.erase(std::unique(sh.pinned.begin(), sh.pinned.end()), sh.pinned.end());
+  for (uint32_t slot : sh.pinned) ++c->bufs[slot].pins;
   s->shapes.push_back(std::move(sh));
   *shape_id = static_cast<uint32_t>(s->shapes.size() - 1);
   return DAG_OK;
@@ -439,8 +692,124 @@ dag_status dag_serve_shape_info(dag_server s, uint32_t shape, uint64_t* device_b
   return DAG_OK;
 }
 
-dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint32_t mode, dag_request_done* done,
-                         dag_serve_stats* stats) {
+dag_status dag_serve_start(dag_server s, uint32_t mode) {
+  if (!s) return DAG_E_INVAL;
+  dag_ctx c = s->ctx;
+  CHECK_CTX(c);
+  if (mode > DAG_SERVE_SERIAL) return fail(c, DAG_E_INVAL, "bad mode");
+  if (s->started && !all_done(s, s->closed))
+    return fail(c, DAG_E_BUSY, "the previous session has requests outstanding");
+  s->started = true;
+  s->serial = mode == DAG_SERVE_SERIAL;
+  const uint32_t nl = s->serial ? 1u : static_cast<uint32_t>(s->lanes.size());
+  s->flights.assign(nl, {});
+  s->lane_free.assign(nl, 0);
+  s->pending.clear();
+  s->queue.clear();
+  s->live.clear();
+  s->admitted.clear();
+  s->unreported.clear();
+  s->lat_ms.clear();
+  s->used = s->peak = s->vclock = s->taken = s->ndone = 0;
+  s->first_arrival = UINT64_MAX;
+  s->last_done = 0;
+  s->inflight = s->max_inflight = s->max_queued = 0;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->incoming.clear();
+  s->next_id = 0;
+  s->horizon = 0;
+  s->closed = false;
+  s->t0 = Clock::now();
+  return DAG_OK;
+}
+
+dag_status dag_serve_submit(dag_server s, uint32_t shape, uint64_t arrival_ns, void* result, uint64_t* id) {
+  if (!s) return DAG_E_INVAL;
+  dag_ctx c = s->ctx;
+  if (c->poisoned) return DAG_E_POISONED;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!s->started || s->closed) return DAG_E_BUSY;
+  if (shape >= s->shapes.size()) return DAG_E_INVAL;
+  if (arrival_ns == DAG_SERVE_NOW) {
+    if (c->dry) return DAG_E_INVAL;  // a virtual clock has no "now" for other threads
+    arrival_ns =
+        static_cast<uint64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - s->t0).count());
+    arrival_ns = std::max(arrival_ns, s->horizon);
+  } else if (arrival_ns < s->horizon) {
+    return DAG_E_INVAL;  // arrivals are submitted in non-decreasing order
+  }
+  Req r{s->next_id++, shape, arrival_ns, result};
+  s->horizon = arrival_ns;
+  s->first_arrival = std::min(s->first_arrival, arrival_ns);
+  s->incoming.push_back(r);
+  if (id) *id = r.id;
+  s->cv.notify_all();
+  return DAG_OK;
+}
+
+dag_status dag_serve_close(dag_server s) {
+  if (!s) return DAG_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!s->started) return DAG_E_BUSY;
+  s->closed = true;
+  s->cv.notify_all();
+  return DAG_OK;
+}
+
+dag_status dag_serve_poll(dag_server s, uint64_t wait_us, dag_serve_done* done, uint32_t cap, uint32_t* n,
+                          uint64_t* outstanding) {
+  if (n) *n = 0;
+  if (!s) return DAG_E_INVAL;
+  dag_ctx c = s->ctx;
+  CHECK_CTX(c);
+  if (!s->started) return fail(c, DAG_E_BUSY, "no session: call dag_serve_start first");
+  if (cap && !done) return fail(c, DAG_E_INVAL, "done is NULL");
+  dag_status st = advance(s, wait_us);
+  if (st) return st;
+  uint32_t k = 0;
+  while (k < cap && !s->unreported.empty()) {
+    done[k++] = s->unreported.front();
+    s->unreported.pop_front();
+  }
+  if (n) *n = k;
+  if (outstanding) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    *outstanding = (s->next_id - s->ndone) + s->unreported.size();
+  }
+  return DAG_OK;
+}
+
+dag_status dag_serve_stats(dag_server s, dag_serve_summary* out) {
+  if (!s || !out) return DAG_E_INVAL;
+  std::vector<double> lat(s->lat_ms);
+  std::sort(lat.begin(), lat.end());
+  const size_t n = lat.size();
+  auto pct = [&](double q) {
+    if (lat.empty()) return 0.0;
+    size_t k = static_cast<size_t>(std::ceil(q / 100.0 * n));
+    k = std::max<size_t>(k, 1);
+    return lat[k - 1];
+  };
+  double sum = 0.0;
+  for (double v : lat) sum += v;
+  std::memset(out, 0, sizeof(*out));
+  out->p50_ms = pct(50);
+  out->p99_ms = pct(99);
+  out->mean_ms = n ? sum / n : 0.0;
+  out->max_ms = n ? lat.back() : 0.0;
+  const double span_s =
+      n ? (static_cast<double>(s->last_done) - static_cast<double>(s->first_arrival)) * 1e-9 : 0.0;
+  out->req_per_s = span_s > 0 ? n / span_s : 0.0;
+  out->wall_ms = static_cast<double>(s->last_done) * 1e-6;
+  out->peak_device_bytes = s->peak;
+  out->max_inflight = s->max_inflight;
+  out->max_queued = s->max_queued;
+  out->completed = n;
+  return DAG_OK;
+}
+
+dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint32_t mode, dag_serve_done* done,
+                         dag_serve_summary* stats) {
   if (!s) return DAG_E_INVAL;
   dag_ctx c = s->ctx;
   CHECK_CTX(c);
@@ -448,155 +817,30 @@ dag_status dag_serve_run(dag_server s, const dag_request* reqs, uint32_t n, uint
   if (n && (!reqs || !done)) return fail(c, DAG_E_INVAL, "reqs and done are required");
   for (uint32_t i = 0; i < n; ++i) {
     if (reqs[i].shape >= s->shapes.size()) return fail(c, DAG_E_INVAL, "request %u: unknown shape", i);
+    if (reqs[i].arrival_ns == DAG_SERVE_NOW) return fail(c, DAG_E_INVAL, "request %u: arrival must be a time", i);
     if (i && reqs[i].arrival_ns < reqs[i - 1].arrival_ns)
       return fail(c, DAG_E_INVAL, "requests must be sorted by arrival");
   }
-  const bool dry = c->dry;
-  const bool serial = mode == DAG_SERVE_SERIAL;
-  const uint32_t nl = serial ? 1u : static_cast<uint32_t>(s->lanes.size());
-  std::vector<std::deque<Flight>> flights(nl);
-  std::vector<uint64_t> lane_free(nl, 0);  // schedule-only: virtual time a lane drains
-  std::deque<uint32_t> queue;
-  uint32_t next = 0, ndone = 0, inflight = 0;
-  uint64_t used = 0, peak = 0, vclock = 0;
-  uint32_t max_inflight = 0, max_queued = 0;
-  const auto t0 = Clock::now();
-  auto now_ns = [&]() -> uint64_t {
-    if (dry) return vclock;
-    return static_cast<uint64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count());
-  };
-  auto complete = [&](uint32_t lane, uint64_t when) {
-    Flight f = flights[lane].front();
-    flights[lane].pop_front();
-    const Shape& sh = s->shapes[reqs[f.req].shape];
-    copy_result(s, sh, f.dev_off, f.host_off, reqs[f.req].result);
-    done[f.req].done_ns = when;
-    if (sh.dev_bytes) s->dev.release(f.dev_off, sh.dev_bytes);
-    if (sh.host_bytes) s->host.release(f.host_off, sh.host_bytes);
-    used -= sh.dev_bytes;
-    if (f.ev) s->free_ev.push_back(f.ev);
-    for (hipEvent_t e : f.evs) s->free_ev.push_back(e);
-    --inflight;
-    ++ndone;
-  };
-  while (ndone < n) {
-    uint64_t now = now_ns();
-    while (next < n && reqs[next].arrival_ns <= now) queue.push_back(next++);
-    max_queued = std::max<uint32_t>(max_queued, static_cast<uint32_t>(queue.size()));
-    bool progress = false;
-    // retire finished requests (lanes complete in order)
-    for (uint32_t l = 0; l < nl; ++l) {
-      while (!flights[l].empty()) {
-        const Flight& f = flights[l].front();
-        bool fin;
-        if (dry) {
-          fin = f.sim_done <= now;
-        } else {
-          const hipError_t q = hipEventQuery(f.ev);
-          if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(c, q, "hipEventQuery");
-          fin = q == hipSuccess;
-        }
-        if (!fin) break;
-        complete(l, dry ? f.sim_done : now);
-        progress = true;
-      }
-    }
-    // admit queued requests whose footprint fits (FIFO, bounded bypass)
-    uint32_t scanned = 0;
-    for (auto it = queue.begin(); it != queue.end() && scanned < std::max<uint32_t>(s->cfg.bypass, 1);) {
-      ++scanned;
-      if (serial && inflight) break;
-      const uint32_t r = *it;
-      const Shape& sh = s->shapes[reqs[r].shape];
-      uint64_t doff = 0, hoff = 0;
-      bool ok = used + sh.dev_bytes <= s->cfg.budget_bytes;
-      if (ok && sh.dev_bytes) ok = s->dev.alloc(sh.dev_bytes, &doff);
-      if (ok && sh.host_bytes && !s->host.alloc(sh.host_bytes, &hoff)) {
-        if (sh.dev_bytes) s->dev.release(doff, sh.dev_bytes);
-        ok = false;
-      }
-      if (!ok) {
-        ++it;
-        continue;
-      }
-      // the lane with the fewest requests in flight (lowest index on ties)
-      // among the lanes of the request's class
-      uint32_t lo = 0, hi = nl;
-      if (!serial && s->cfg.transfer_lanes) {
-        if (sh.host_io)
-          hi = s->cfg.transfer_lanes;
-        else
-          lo = s->cfg.transfer_lanes;
-      }
-      uint32_t lane = lo;
-      for (uint32_t l = lo + 1; l < hi; ++l)
-        if (flights[l].size() < flights[lane].size()) lane = l;
-      Flight f{r, lane, nullptr, doff, hoff, 0};
-      done[r].admit_ns = now;
-      done[r].lane = lane;
-      done[r].reserved = 0;
-      if (dry) {
-        const uint64_t start = std::max(now, lane_free[lane]);
-        lane_free[lane] = f.sim_done = start + sh.sim_ns;
-      } else {
-        dag_status st = launch_request(s, sh, doff, hoff, s->lanes[lane], s->lane_scratch[lane], serial, &f.evs);
-        if (st) return st;
-        st = ev_get(s, &f.ev);
-        if (st) return st;
-        HIP_TRY(c, hipEventRecord(f.ev, s->lanes[lane]));
-      }
-      flights[lane].push_back(std::move(f));
-      used += sh.dev_bytes;
-      peak = std::max(peak, used);
-      ++inflight;
-      max_inflight = std::max(max_inflight, inflight);
-      it = queue.erase(it);
-      progress = true;
-    }
-    if (!progress) {
-      if (dry) {
-        // advance the virtual clock to the next arrival or completion
-        uint64_t t = UINT64_MAX;
-        if (next < n) t = reqs[next].arrival_ns;
-        for (uint32_t l = 0; l < nl; ++l)
-          if (!flights[l].empty()) t = std::min(t, flights[l].front().sim_done);
-        if (t == UINT64_MAX) return fail(c, DAG_E_RANGE, "a queued request can never be admitted");
-        vclock = std::max(vclock, t);
-      } else if (inflight == 0 && next < n && queue.empty()) {
-        const uint64_t wait = reqs[next].arrival_ns > now ? reqs[next].arrival_ns - now : 0;
-        if (wait > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(wait - 100000));
-      } else if (inflight == 0 && !queue.empty()) {
-        return fail(c, DAG_E_RANGE, "a queued request can never be admitted (arena fragmentation)");
-      }
-    }
+  dag_status st = dag_serve_start(s, mode);
+  if (st) return st;
+  for (uint32_t i = 0; i < n; ++i) {
+    st = dag_serve_submit(s, reqs[i].shape, reqs[i].arrival_ns, reqs[i].result, nullptr);
+    if (st) return fail(c, st, "request %u: submission failed", i);
   }
-  if (stats) {
-    std::vector<double> lat(n);
-    double sum = 0.0;
-    uint64_t last = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-      lat[i] = (static_cast<double>(done[i].done_ns) - static_cast<double>(reqs[i].arrival_ns)) * 1e-6;
-      sum += lat[i];
-      last = std::max(last, done[i].done_ns);
-    }
-    std::sort(lat.begin(), lat.end());
-    auto pct = [&](double q) {
-      if (lat.empty()) return 0.0;
-      size_t k = static_cast<size_t>(std::ceil(q / 100.0 * lat.size()));
-      k = std::max<size_t>(k, 1);
-      return lat[k - 1];
-    };
-    stats->p50_ms = pct(50);
-    stats->p99_ms = pct(99);
-    stats->mean_ms = n ? sum / n : 0.0;
-    stats->max_ms = n ? lat.back() : 0.0;
-    const double span_s = n ? (static_cast<double>(last) - static_cast<double>(reqs[0].arrival_ns)) * 1e-9 : 0.0;
-    stats->req_per_s = span_s > 0 ? n / span_s : 0.0;
-    stats->wall_ms = static_cast<double>(last) * 1e-6;
-    stats->peak_device_bytes = peak;
-    stats->max_inflight = max_inflight;
-    stats->max_queued = max_queued;
+  dag_serve_close(s);
+  std::vector<dag_serve_done> buf(256);
+  uint64_t left = n;
+  while (left) {
+    uint32_t got = 0;
+    uint64_t outstanding = 0;
+    st = dag_serve_poll(s, 1000000, buf.data(), static_cast<uint32_t>(buf.size()), &got, &outstanding);
+    if (st) return st;
+    for (uint32_t k = 0; k < got; ++k) done[buf[k].id] = buf[k];
+    left -= got;
+    if (!got && !outstanding) break;
   }
+  if (left) return fail(c, DAG_E_RANGE, "%llu requests never completed", (unsigned long long)left);
+  if (stats) dag_serve_stats(s, stats);
   return DAG_OK;
 }
 

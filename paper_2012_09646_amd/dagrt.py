@@ -142,20 +142,21 @@ class dag_request(C.Structure):
                 ("result", C.c_void_p)]
 
 
-class dag_request_done(C.Structure):
-    _fields_ = [("admit_ns", C.c_uint64), ("done_ns", C.c_uint64), ("lane", C.c_uint32),
-                ("reserved", C.c_uint32)]
+class dag_serve_done(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("arrival_ns", C.c_uint64), ("admit_ns", C.c_uint64),
+                ("done_ns", C.c_uint64), ("shape", C.c_uint32), ("lane", C.c_uint32)]
 
 
-class dag_serve_stats(C.Structure):
+class dag_serve_summary(C.Structure):
     _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
                 ("max_ms", C.c_double), ("req_per_s", C.c_double), ("wall_ms", C.c_double),
                 ("peak_device_bytes", C.c_uint64), ("max_inflight", C.c_uint32),
-                ("max_queued", C.c_uint32)]
+                ("max_queued", C.c_uint32), ("completed", C.c_uint64)]
 
 
 DAG_ROLE_SHARED, DAG_ROLE_PRIVATE, DAG_ROLE_INIT = 0, 1, 2
 DAG_SERVE_CONCURRENT, DAG_SERVE_SERIAL = 0, 1
+DAG_SERVE_NOW = (1 << 64) - 1
 
 DAG_LAUNCH_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p,
                             C.c_void_p)
@@ -204,8 +205,14 @@ _SIGS = {
     "dag_serve_add_shape": (_st, [C.c_void_p, C.c_uint64, _P(dag_shape_buf), C.c_uint32, C.c_uint32,
                                   C.c_size_t, C.c_uint64, _P(C.c_uint32)]),
     "dag_serve_shape_info": (_st, [C.c_void_p, C.c_uint32, _P(C.c_uint64), _P(C.c_uint64)]),
-    "dag_serve_run": (_st, [C.c_void_p, _P(dag_request), C.c_uint32, C.c_uint32, _P(dag_request_done),
-                            _P(dag_serve_stats)]),
+    "dag_serve_start": (_st, [C.c_void_p, C.c_uint32]),
+    "dag_serve_submit": (_st, [C.c_void_p, C.c_uint32, C.c_uint64, C.c_void_p, _P(C.c_uint64)]),
+    "dag_serve_close": (_st, [C.c_void_p]),
+    "dag_serve_poll": (_st, [C.c_void_p, C.c_uint64, _P(dag_serve_done), C.c_uint32, _P(C.c_uint32),
+                             _P(C.c_uint64)]),
+    "dag_serve_stats": (_st, [C.c_void_p, _P(dag_serve_summary)]),
+    "dag_serve_run": (_st, [C.c_void_p, _P(dag_request), C.c_uint32, C.c_uint32, _P(dag_serve_done),
+                            _P(dag_serve_summary)]),
 }
 
 _lib = None
@@ -485,11 +492,49 @@ def dag_serve_shape_info(srv, shape):
     return a.value, b.value
 
 
+def dag_serve_start(ctx, srv, mode=DAG_SERVE_CONCURRENT):
+    _check(ctx, lib().dag_serve_start(srv, mode))
+
+
+def dag_serve_submit(srv, shape, arrival_ns=DAG_SERVE_NOW, result=None):
+    """Thread-safe (no context message on failure).  result: a C-contiguous
+    numpy array (kept alive by the caller until its completion is reported)
+    or None.  Returns the request id."""
+    rid = C.c_uint64()
+    st = lib().dag_serve_submit(srv, int(shape), int(arrival_ns), _host_ptr(result), C.byref(rid))
+    if st != DAG_OK:
+        raise DagError(st, "dag_serve_submit")
+    return rid.value
+
+
+def dag_serve_close(srv):
+    st = lib().dag_serve_close(srv)
+    if st != DAG_OK:
+        raise DagError(st, "dag_serve_close")
+
+
+def dag_serve_poll(ctx, srv, wait_us=0, cap=256):
+    """Returns (list of dag_serve_done, outstanding)."""
+    arr = (dag_serve_done * max(cap, 1))()
+    n = C.c_uint32()
+    left = C.c_uint64()
+    _check(ctx, lib().dag_serve_poll(srv, int(wait_us), arr, cap, C.byref(n), C.byref(left)))
+    return [arr[i] for i in range(n.value)], left.value
+
+
+def dag_serve_stats(srv):
+    out = dag_serve_summary()
+    st = lib().dag_serve_stats(srv, C.byref(out))
+    if st != DAG_OK:
+        raise DagError(st, "dag_serve_stats")
+    return out
+
+
 def dag_serve_run(ctx, srv, reqs, mode):
-    """reqs: ctypes array of dag_request.  Returns (done array, stats)."""
+    """reqs: ctypes array of dag_request.  Returns (done array, summary)."""
     n = len(reqs)
-    done = (dag_request_done * max(n, 1))()
-    stats = dag_serve_stats()
+    done = (dag_serve_done * max(n, 1))()
+    stats = dag_serve_summary()
     _check(ctx, lib().dag_serve_run(srv, reqs, n, mode, done, C.byref(stats)))
     return done, stats
 

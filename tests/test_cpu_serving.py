@@ -141,3 +141,120 @@ def test_transfer_lanes_separate_link_bound_requests():
         with pytest.raises(D.DagError):
             serving.Server(ctx, 1 << 30, host_arena_bytes=1 << 24, lanes=3, transfer_lanes=bad)
     ctx.close()
+
+
+def test_online_producer_gets_exactly_the_batch_schedule():
+    """Requests submitted one by one by a producer thread while the loop
+    polls (dag_serve_submit / dag_serve_poll) are admitted and completed on
+    the virtual clock exactly as when the whole trace is known at the start
+    (dag_serve_run), with the budget forcing queueing and bypass."""
+    ctx, srv, s0, s1 = make(1 << 30)
+    big, small = srv.footprint(s1)[0], srv.footprint(s0)[0]
+    srv.close()
+    ctx.close()
+    ctx, srv, s0, s1 = make(2 * big + 3 * small, lanes=3, bypass=4)
+    arr, shp = W.poisson_trace(11, 300, 40_000, 2)
+    out, st, _ = srv.run(arr, shp)
+    delays = W.rng(5).uniform(0, 2e-4, size=len(arr)) * (W.rng(6).random(len(arr)) < 0.2)
+    recs, st2, _ = srv.run_online(arr, shp, pace=False, delays=delays)
+    assert st.max_queued > 0
+    for i, (a, adm, done, sh, lane) in enumerate(recs):
+        assert (a, sh) == (arr[i], shp[i])
+        assert (adm, done, lane) == (out["admit_ns"][i], out["done_ns"][i], out["lane"][i]), i
+    for f in ("p50_ms", "p99_ms", "mean_ms", "req_per_s", "peak_device_bytes", "max_inflight", "max_queued"):
+        assert getattr(st, f) == getattr(st2, f), f
+    assert st2.completed == len(arr)
+    srv.close()
+    ctx.close()
+
+
+def test_online_submission_rules():
+    ctx, srv, s0, s1 = make(1 << 30)
+    with pytest.raises(D.DagError) as e:   # no session yet
+        srv.submit(s0, 0)
+    assert e.value.name == "DAG_E_BUSY"
+    srv.start()
+    srv.submit(s0, 100)
+    with pytest.raises(D.DagError) as e:   # arrivals must not go back in time
+        srv.submit(s0, 99)
+    assert e.value.name == "DAG_E_INVAL"
+    with pytest.raises(D.DagError) as e:   # a virtual clock has no "now"
+        srv.submit(s0)
+    assert e.value.name == "DAG_E_INVAL"
+    with pytest.raises(D.DagError):        # unknown shape
+        srv.submit(7, 200)
+    # the loop does not pass the latest arrival while more may come
+    got, left = srv.poll()
+    assert got == [] and left == 1
+    with pytest.raises(D.DagError) as e:   # a new session while requests are outstanding
+        srv.start()
+    assert e.value.name == "DAG_E_BUSY"
+    srv.close_session()
+    with pytest.raises(D.DagError) as e:   # closed
+        srv.submit(s0, 300)
+    assert e.value.name == "DAG_E_BUSY"
+    got, left = srv.poll()
+    assert len(got) == 1 and left == 0
+    d = got[0]
+    assert (d.id, d.arrival_ns, d.admit_ns, d.done_ns) == (0, 100, 100, 100 + 10_000)
+    assert srv.stats().completed == 1
+    srv.start()   # a fresh session
+    assert srv.stats().completed == 0
+    srv.close_session()
+    assert srv.poll() == ([], 0)
+    srv.close()
+    ctx.close()
+
+
+def test_released_buffer_kills_the_regions_that_use_it():
+    """A recorded region keeps its buffers' addresses: after one of them is
+    released the region can no longer be launched (DAG_E_INVAL), and a
+    recurring-region run records it anew instead of replaying it."""
+    ctx = D.Context(dry_run=True)
+    x, y = ctx.alloc(4096), ctx.alloc(4096)
+    D.dag_region_begin(ctx.h, 5)
+    ctx.kernel("vec_square", [(x, "m")], n=1024)
+    D.dag_region_end(ctx.h)
+    D.dag_region_begin(ctx.h, 6)
+    ctx.kernel("vec_square", [(y, "m")], n=1024)
+    D.dag_region_end(ctx.h)
+    D.dag_region_launch(ctx.h, 5)
+    ctx.release(x)
+    with pytest.raises(D.DagError) as e:
+        D.dag_region_launch(ctx.h, 5)
+    assert e.value.name == "DAG_E_INVAL"
+    D.dag_region_launch(ctx.h, 6)          # the other region is untouched
+    x2 = ctx.alloc(4096)
+    D.dag_region_run_begin(ctx.h, 5)       # the dead recording is replaced
+    ctx.kernel("vec_square", [(x2, "m")], n=1024)
+    assert D.dag_region_run_end(ctx.h) == (0, False)
+    D.dag_region_run_begin(ctx.h, 5)
+    ctx.kernel("vec_square", [(x2, "m")], n=1024)
+    tid, replayed = D.dag_region_run_end(ctx.h)
+    assert replayed and tid > 0
+    ctx.close()
+
+
+def test_serving_shape_pins_its_region_and_buffers():
+    ctx = D.Context(dry_run=True)
+    t = serving.ShapeTemplate(ctx, W.vec_program(n=256), key=3)
+    srv = serving.Server(ctx, 1 << 20, host_arena_bytes=1 << 16, lanes=2)
+    srv.add(t)
+    for call in (lambda: D.dag_region_drop(ctx.h, 3), lambda: D.dag_region_begin(ctx.h, 3),
+                 lambda: ctx.release(t.bound.h["x"]), lambda: ctx.release(t.pristine["x"])):
+        with pytest.raises(D.DagError) as e:
+            call()
+        assert e.value.name == "DAG_E_BUSY"
+    # a recurring run whose calls differ from the pinned recording runs
+    # eagerly and leaves the recording as it is
+    ntasks = D.dag_region_info(ctx.h, 3)[0]
+    D.dag_region_run_begin(ctx.h, 3)
+    tid = ctx.kernel("vec_square", [(t.bound.h["y"], "m")], n=7)
+    assert tid > 0
+    assert D.dag_region_run_end(ctx.h) == (0, False)
+    assert D.dag_region_info(ctx.h, 3)[0] == ntasks
+    srv.close()
+    ctx.release(t.pristine["x"])
+    ctx.release(t.bound.h["x"])
+    D.dag_region_drop(ctx.h, 3)
+    ctx.close()
