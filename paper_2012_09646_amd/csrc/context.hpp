@@ -115,7 +115,6 @@ struct dag_ctx_s {
   // regions
   std::unordered_map<uint64_t, std::unique_ptr<dagrt::Region>> regions;
   bool recording = false;
-  bool graph_pending = false;  // a hipGraph region was launched since the last host access
   uint64_t rec_key = 0;
   // dag_region_run_*: calls compared with the recording of match_key instead
   // of being run; match_pos calls have matched so far

@@ -502,15 +502,6 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
   if (out) *out = id;
   if (kind == TK_HOST_WRITE) b->plan_valid = false;
   char* p = static_cast<char*>(b->ptr) + off;
-  // After a hipGraph launch, waiting on the event recorded behind it on its
-  // stream was seen to return while part of a kernel node's output was not
-  // yet readable by the host copy (a multi-branch graph; a device-wide
-  // synchronisation before the access removed it), so the first host access
-  // after a graph launch synchronises the device.
-  if (!c->dry && c->graph_pending && !c->tmp_wait.empty()) {
-    HIP_TRY(c, hipDeviceSynchronize());
-    c->graph_pending = false;
-  }
   // A read of device memory that waits on its writer: copy on the writer's
   // stream into pinned staging and wait once (one host<->device round trip).
   if (!c->dry && kind == TK_HOST_READ && hdst && bytes && bytes <= kStagingBytes &&
@@ -558,10 +549,6 @@ dag_status do_sync(dag_ctx c) {
   if (c->in_region()) return fail(c, DAG_E_BUSY, "sync inside a region");
   c->tr.add_sync();
   if (!c->dry) {
-    if (c->graph_pending) {
-      HIP_TRY(c, hipDeviceSynchronize());
-      c->graph_pending = false;
-    }
     for (hipStream_t s : c->streams) HIP_TRY(c, hipStreamSynchronize(s));
     for (hipStream_t s : c->aux) HIP_TRY(c, hipStreamSynchronize(s));
     for (void* p : c->dead_plans) HIP_TRY(c, hipFree(p));
@@ -676,14 +663,17 @@ dag_status build_graph(dag_ctx c, Region* r) {
     HIP_TRY(c, hipEventRecord(forks[i], c->aux[i]));
     HIP_TRY(c, hipStreamWaitEvent(s0, forks[i], 0));
   }
-  // One sink node that depends on every branch (a zero-length delay kernel):
-  // graphs with several leaf nodes were seen to signal completion on the
-  // launch stream before all branches had finished (a host read then saw a
-  // device-to-host copy's destination unwritten).
-  if (r->nstreams > 1) {
-    const KernelDesc* spin = builtin_kernel(DAG_K_SPIN);
-    const dag_p_spin zero{0};
-    hipError_t e = spin->launch(s0, nullptr, &zero, spin->def, nullptr, 0);
+  // One sink node after every branch that writes back all eight L2s.  The
+  // kernel nodes of a graph were seen to leave results in L2 that a later
+  // kernel read correctly but a host copy (which reads memory) did not: in
+  // the ML graph the ensemble node produced correct labels from the naive
+  // Bayes posteriors, whose rows it reads on the same XCD that wrote them,
+  // while a host read of those posteriors after the graph's completion event
+  // still found part of them as last written by the host.  An eager launch
+  // makes its results visible to the host at completion; a graph node, as
+  // observed, need not.
+  {
+    hipError_t e = release_l2(s0);
     if (e != hipSuccess) return hip_fail(c, e, "region capture sink");
   }
   HIP_TRY(c, hipStreamEndCapture(s0, &r->graph));
@@ -1205,7 +1195,6 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   if (!c->dry) {
     if (r->exec) {
       HIP_TRY(c, hipGraphLaunch(r->exec, c->streams[s]));
-      c->graph_pending = true;
     } else {
       st = replay_region(c, r, c->streams[s], s);
       if (st) return st;

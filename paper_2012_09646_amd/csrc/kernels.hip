@@ -1702,6 +1702,13 @@ __global__ void k_spin(uint64_t ticks) {
   }
 }
 
+// Last node of a captured region graph: each workgroup makes a system-scope
+// release, which writes back every dirty line of its XCD's L2 to memory, so
+// what the graph's kernels stored is visible to the copy engines and to the
+// host once the graph's completion is signalled.  Workgroups are handed to
+// the eight XCDs round-robin by id, so 64 of them reach every L2.
+__global__ __launch_bounds__(64) void k_release_l2() { __threadfence_system(); }
+
 // Host<->device copy by the CUs (pinned host memory is read or written over
 // PCIe by the kernel itself): 16-byte words when both ends are 16-byte
 // aligned, then the tail bytes.
@@ -2532,6 +2539,12 @@ hipError_t copy_by_kernel(hipStream_t s, void* dst, const void* src, size_t byte
   constexpr uint32_t kCopyWorkgroups = 128;  // enough requests in flight to fill the link
   hipLaunchKernelGGL(k_copy_bytes, dim3(kCopyWorkgroups), dim3(256), 0, s, static_cast<const uint8_t*>(src),
                      static_cast<uint8_t*>(dst), static_cast<uint64_t>(bytes));
+  return hipGetLastError();
+}
+
+hipError_t release_l2(hipStream_t s) {
+  constexpr uint32_t kReleaseWorkgroups = 64;
+  hipLaunchKernelGGL(k_release_l2, dim3(kReleaseWorkgroups), dim3(64), 0, s);
   return hipGetLastError();
 }
 

@@ -50,6 +50,10 @@ hipError_t spmv_planned(hipStream_t s, void* const* ptrs, const void* params, co
 // pointers device-accessible; pinned host memory is).
 hipError_t copy_by_kernel(hipStream_t s, void* dst, const void* src, size_t bytes);
 
+// A kernel whose workgroups write back the dirty lines of every XCD's L2
+// (system-scope release on each XCD): the final node of region graphs.
+hipError_t release_l2(hipStream_t s);
+
 // Device wall-clock frequency in kHz (for the spin kernel); set once.
 void set_wall_clock_khz(uint64_t khz);
 
