@@ -210,7 +210,8 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out);
 /* Waits for all outstanding work, then frees everything the context owns
  * (library-allocated buffers included).  ctx may be NULL. */
 dag_status dag_destroy(dag_ctx ctx);
-/* Message of the last failing call on ctx (static string if ctx is NULL). */
+/* Message of the last failing call on ctx (ctx NULL: of the calling thread's
+ * last failing dag_launch_static call). */
 const char* dag_last_error(dag_ctx ctx);
 const char* dag_status_string(dag_status st);
 
@@ -391,6 +392,41 @@ dag_status dag_host_write(dag_ctx ctx, dag_buf buf, size_t off, const void* host
                           size_t bytes, dag_task* out);
 /* Wait for every submitted task and retire all of them. */
 dag_status dag_sync(dag_ctx ctx);
+
+/* ---- launch without allocating ----------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc.  The built-in
+ * kernel kernel_id runs directly on `stream` (a hipStream_t of the current
+ * device; NULL = its null stream) with the same parameters, arguments and
+ * results as dag_submit_kernel, but outside any context: no dependency
+ * tracking, no stream choice, no events, and no allocation on the call path
+ * (no hipMalloc, hipFree or other allocating routine).  The scratch that a
+ * context allocates per stream (reduction ticket and partials, SpMV tile
+ * partition and carries, dense-layer partials) is instead a fixed array of
+ * DAG_STATIC_SCRATCH_BYTES in device memory, one per GPU, held until the
+ * process ends; its 256-byte header is cleared by a small kernel on `stream`
+ * before each launch (no memset node under capture).
+ *   ptrs[i]: device-accessible address of argument i (the dag_submit_kernel
+ *     argument order of the kernel); bytes[i]: its size in bytes, checked
+ *     like a registered buffer's.  cfg: launch configuration (NULL = the
+ *     kernel's default; a context's tuned one comes from
+ *     dag_kernel_get_launch).  The call returns after enqueueing; the caller
+ *     owns every pointer and orders its own accesses on `stream`.
+ *   Every call on a GPU shares that GPU's array: calls that can overlap on
+ *   the device (other streams, other threads, other processes' contexts
+ *   do not share it) race and must be serialised by the caller, e.g. by
+ *   issuing them on one stream.
+ *   Errors: DAG_E_INVAL for a bad id, parameter block, argument count, NULL
+ *   pointer, size or configuration, or a stream of another device;
+ *   DAG_E_RANGE when the work needs more scratch than the array holds (e.g.
+ *   a merge-path SpMV of more than 149,787 tiles, i.e. nrows + nnz above
+ *   ~306 M at 8 items per thread); DAG_E_HIP if a launch fails.  Argument
+ *   and range errors enqueue nothing.  dag_last_error(NULL) returns
+ *   the calling thread's message for its last failing call. */
+#define DAG_STATIC_SCRATCH_BYTES (4u << 20)
+dag_status dag_launch_static(uint32_t kernel_id, const void* params, size_t params_bytes,
+                             void* const* ptrs, const size_t* bytes, uint32_t nargs,
+                             const dag_launch* cfg, void* stream);
 
 /* Batched submission: ops are processed in order exactly as the equivalent
  * sequence of single calls (same ids, edges, streams and waits).  Stops at

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libdagrt.so")
-SOURCES = ["dagrt.cpp", "serve.cpp", "kernels.hip"]
+SOURCES = ["dagrt.cpp", "serve.cpp", "kernels.hip", "static_launch.cpp"]
 
 ARCH = "gfx950"
 HIPFLAGS = [

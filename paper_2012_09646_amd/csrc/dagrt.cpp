@@ -751,7 +751,7 @@ const char* dag_status_string(dag_status st) {
   }
 }
 
-const char* dag_last_error(dag_ctx ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+const char* dag_last_error(dag_ctx ctx) { return ctx ? ctx->err.c_str() : static_launch_error(); }
 
 dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   if (!out) return DAG_E_INVAL;

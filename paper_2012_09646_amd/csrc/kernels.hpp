@@ -54,6 +54,9 @@ hipError_t copy_by_kernel(hipStream_t s, void* dst, const void* src, size_t byte
 // (system-scope release on each XCD): the final node of region graphs.
 hipError_t release_l2(hipStream_t s);
 
+// Message of the calling thread's last failing dag_launch_static call.
+const char* static_launch_error();
+
 // Device wall-clock frequency in kHz (for the spin kernel); set once.
 void set_wall_clock_khz(uint64_t khz);
 

@@ -21,6 +21,7 @@ DAG_OK = 0
 STATUS = {0: "DAG_OK", -1: "DAG_E_INVAL", -2: "DAG_E_ALIAS", -3: "DAG_E_NOMEM", -4: "DAG_E_HIP",
           -5: "DAG_E_POISONED", -6: "DAG_E_BUSY", -7: "DAG_E_UNSUPPORTED", -8: "DAG_E_NOTFOUND",
           -9: "DAG_E_RANGE"}
+DAG_E_INVAL, DAG_E_RANGE = -1, -9
 DAG_CONST, DAG_MUTABLE = 0, 1
 DAG_DEVICE, DAG_PINNED_HOST = 0, 1
 DAG_SERIAL_SYNC, DAG_PARALLEL_ASYNC = 0, 1
@@ -174,6 +175,8 @@ _SIGS = {
     "dag_buffer_release": (_st, [_ctx_t, C.c_uint32]),
     "dag_buffer_ptr": (_st, [_ctx_t, C.c_uint32, _P(C.c_void_p), _P(C.c_size_t)]),
     "dag_kernel_get_launch": (_st, [_ctx_t, C.c_uint32, _P(dag_launch)]),
+    "dag_launch_static": (_st, [C.c_uint32, C.c_void_p, C.c_size_t, _P(C.c_void_p), _P(C.c_size_t),
+                                C.c_uint32, _P(dag_launch), C.c_void_p]),
     "dag_kernel_set_launch": (_st, [_ctx_t, C.c_uint32, _P(dag_launch)]),
     "dag_tune_kernel": (_st, [_ctx_t, C.c_uint32, C.c_void_p, C.c_size_t, _P(dag_arg), C.c_uint32,
                               _P(dag_launch), C.c_uint32, C.c_uint32, _P(C.c_uint32), _P(C.c_double)]),
@@ -334,6 +337,23 @@ def dag_submit_kernel(ctx, kid, params, args):
     pb = C.sizeof(params) if params is not None else 0
     _check(ctx, lib().dag_submit_kernel(ctx, kid, pp, pb, arr, len(args), C.byref(out)))
     return out.value
+
+
+def dag_launch_static(kid, params, ptrs, sizes, cfg=None, stream=None):
+    """params: a ctypes parameter struct (or None); ptrs: device addresses
+    (ints) in the kernel's argument order; sizes: their sizes in bytes;
+    cfg: a dag_launch (None = the kernel's default); stream: a hipStream_t
+    as an int (None = the null stream)."""
+    n = len(ptrs)
+    if len(sizes) != n:
+        raise ValueError("one size per pointer")
+    pa = (C.c_void_p * max(n, 1))(*[C.c_void_p(int(p)) for p in ptrs])
+    sa = (C.c_size_t * max(n, 1))(*[int(v) for v in sizes])
+    pp = C.byref(params) if params is not None else None
+    pb = C.sizeof(params) if params is not None else 0
+    st = lib().dag_launch_static(kid, pp, pb, pa, sa, n, C.byref(cfg) if cfg is not None else None,
+                                 C.c_void_p(int(stream)) if stream else None)
+    _check(None, st)
 
 
 def dag_submit_copy(ctx, dst, dst_off, src, src_off, nbytes):
