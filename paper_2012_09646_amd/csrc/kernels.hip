@@ -390,11 +390,12 @@ __global__ __launch_bounds__(1024) void k_bs_call(const float* __restrict__ S, f
 }
 
 // ---------------------------------------------------------------------------
-// IMG: LDS-tiled stencils with clamp-to-edge borders.  A workgroup of 256
-// threads (64 x 4) produces a 64 x 16 output tile.
+// IMG: LDS-tiled stencils with clamp-to-edge borders.  A workgroup produces a
+// TW x TH output tile with TW * TH / 4 threads, each thread four rows of one
+// column.  Tile shapes (launch variant >> 1): 64 x 16 (256 threads, the
+// default), 64 x 8 (128), 64 x 4 (64) and 32 x 8 (64).
 // ---------------------------------------------------------------------------
-constexpr int kTW = 64;
-constexpr int kTH = 16;
+constexpr int kRowsPerThread = 4;
 
 struct GaussW {
   double w[31];
@@ -406,6 +407,7 @@ struct GaussW {
 // row-major tiles keeps a tile and its left, right, upper and lower
 // neighbours, whose halos overlap it, on one XCD and so in one L2.  Returns
 // false for the padding blocks of the last run (uniform per workgroup).
+template <int TW, int TH>
 __device__ __forceinline__ bool tile_of(int tiles_x, int ntiles, int xcd_map, int* x0, int* y0) {
   int t = blockIdx.x;
   if (xcd_map) {
@@ -413,55 +415,68 @@ __device__ __forceinline__ bool tile_of(int tiles_x, int ntiles, int xcd_map, in
     t = static_cast<int>(blockIdx.x % 8) * per + static_cast<int>(blockIdx.x / 8);
     if (t >= ntiles) return false;
   }
-  *x0 = (t % tiles_x) * kTW;
-  *y0 = (t / tiles_x) * kTH;
+  *x0 = (t % tiles_x) * TW;
+  *y0 = (t / tiles_x) * TH;
   return true;
 }
 
-// Stage image rows [y0 - R, y0 - R + IH) x columns [x0 - R, x0 - R + 64 + 2R)
-// (clamped to the border) into s: a 256-thread workgroup's lane keeps one
-// column for the whole tile and each wave takes every fourth row, so the row
-// is uniform per wave and a load costs an add; the 2R halo columns are a
-// second load by the first 2R lanes.
-template <int R, int IH, int SW>
+// Stage image rows [y0 - R, y0 - R + IH) x columns [x0 - R, x0 - R + TW + 2R)
+// (clamped to the border) into s.  64-wide tiles: a lane keeps one column for
+// the whole tile and each wave takes every NT/64-th row, so the row is uniform
+// per wave and a load costs an add; the 2R halo columns are a second load by
+// the first 2R lanes.  Other widths: the threads stride over the tile.
+template <int R, int TW, int IH, int SW, int NT>
 __device__ __forceinline__ void stage_tile(const float* __restrict__ in, float (*s)[SW], int w, int h, int x0,
                                            int y0) {
-  static_assert(2 * R <= 64 && SW >= kTW + 2 * R, "halo wider than a wave");
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gx_main = min(max(x0 - R + lane, 0), w - 1);
-  const int gx_halo = min(max(x0 - R + kTW + lane, 0), w - 1);
+  static_assert(SW >= TW + 2 * R, "LDS row too narrow");
+  if constexpr (TW == 64 && NT % 64 == 0 && 2 * R <= 64) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gx_main = min(max(x0 - R + lane, 0), w - 1);
+    const int gx_halo = min(max(x0 - R + TW + lane, 0), w - 1);
 #pragma unroll
-  for (int k = 0; k < (IH + 3) / 4; ++k) {
-    const int r = wv + 4 * k;
-    if (r < IH) {
+    for (int k = 0; k < (IH + NW - 1) / NW; ++k) {
+      const int r = wv + NW * k;
+      if (r < IH) {
+        const int gy = min(max(y0 - R + r, 0), h - 1);
+        const float* row = in + static_cast<size_t>(gy) * w;
+        s[r][lane] = row[gx_main];
+        if (lane < 2 * R) s[r][TW + lane] = row[gx_halo];
+      }
+    }
+  } else {
+    constexpr int IW = TW + 2 * R;
+    for (int idx = threadIdx.x; idx < IH * IW; idx += NT) {
+      const int r = idx / IW, c = idx - r * IW;
       const int gy = min(max(y0 - R + r, 0), h - 1);
-      const float* row = in + static_cast<size_t>(gy) * w;
-      s[r][lane] = row[gx_main];
-      if (lane < 2 * R) s[r][kTW + lane] = row[gx_halo];
+      const int gx = min(max(x0 - R + c, 0), w - 1);
+      s[r][c] = in[static_cast<size_t>(gy) * w + gx];
     }
   }
 }
 
 // Separable Gaussian: stage the input tile with its halo in LDS (fp32, as
 // stored), horizontal pass into an fp64 LDS tile, vertical pass to output.
-template <int R>
-__global__ __launch_bounds__(256) void k_gauss_blur(const float* __restrict__ in,
-                                                    float* __restrict__ out, int w, int h,
-                                                    GaussW wt, int tiles_x, int ntiles, int xcd_map) {
+template <int R, int TW, int TH>
+__global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_gauss_blur(const float* __restrict__ in,
+                                                                          float* __restrict__ out, int w, int h,
+                                                                          GaussW wt, int tiles_x, int ntiles,
+                                                                          int xcd_map) {
+  constexpr int G = kRowsPerThread;
+  constexpr int NT = TW * TH / G;
   constexpr int K = 2 * R + 1;
-  constexpr int IW = kTW + 2 * R;
-  constexpr int IH = kTH + 2 * R;
+  constexpr int IW = TW + 2 * R;
+  constexpr int IH = TH + 2 * R;
   __shared__ float s_in[IH][IW];
-  __shared__ double s_h[IH][kTW];
+  __shared__ double s_h[IH][TW];
   int x0, y0;
-  if (!tile_of(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
-  stage_tile<R, IH, IW>(in, s_in, w, h, x0, y0);
+  if (!tile_of<TW, TH>(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
+  stage_tile<R, TW, IH, IW, NT>(in, s_in, w, h, x0, y0);
   __syncthreads();
   // horizontal pass: each work item produces 4 adjacent outputs of one row
   // from one register window of 4 + 2R inputs (4x fewer LDS reads)
-  constexpr int G = 4;
-  for (int item = threadIdx.x; item < IH * (kTW / G); item += 256) {
-    const int r = item / (kTW / G), c0 = (item % (kTW / G)) * G;
+  for (int item = threadIdx.x; item < IH * (TW / G); item += NT) {
+    const int r = item / (TW / G), c0 = (item % (TW / G)) * G;
     float v[G + 2 * R];
 #pragma unroll
     for (int j = 0; j < G + 2 * R; ++j) v[j] = s_in[r][c0 + j];
@@ -475,8 +490,8 @@ __global__ __launch_bounds__(256) void k_gauss_blur(const float* __restrict__ in
   }
   __syncthreads();
   // vertical pass: each thread produces 4 rows of one column from one window
-  const int c = threadIdx.x & (kTW - 1);
-  const int r0 = (threadIdx.x / kTW) * G;
+  const int c = threadIdx.x % TW;
+  const int r0 = (threadIdx.x / TW) * G;
   const int gx = x0 + c;
   double v[G + 2 * R];
 #pragma unroll
@@ -493,19 +508,21 @@ __global__ __launch_bounds__(256) void k_gauss_blur(const float* __restrict__ in
 
 // Sobel gradient magnitude sqrt(gx^2 + gy^2), gx with [[-1,0,1],[-2,0,2],
 // [-1,0,1]] (correlation), gy with its transpose.
-__global__ __launch_bounds__(256) void k_sobel(const float* __restrict__ in,
-                                               float* __restrict__ out, int w, int h, int tiles_x,
-                                               int ntiles, int xcd_map) {
-  constexpr int IW = kTW + 2, IH = kTH + 2;
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_sobel(const float* __restrict__ in,
+                                                                     float* __restrict__ out, int w, int h,
+                                                                     int tiles_x, int ntiles, int xcd_map) {
+  constexpr int G = kRowsPerThread;
+  constexpr int NT = TW * TH / G;
+  constexpr int IW = TW + 2, IH = TH + 2;
   __shared__ float s_in[IH][IW];
   int x0, y0;
-  if (!tile_of(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
-  stage_tile<1, IH, IW>(in, s_in, w, h, x0, y0);
+  if (!tile_of<TW, TH>(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
+  stage_tile<1, TW, IH, IW, NT>(in, s_in, w, h, x0, y0);
   __syncthreads();
   // each thread: 4 rows of one column from a 6 x 3 register window
-  constexpr int G = 4;
-  const int c = threadIdx.x & (kTW - 1);
-  const int r0 = (threadIdx.x / kTW) * G;
+  const int c = threadIdx.x % TW;
+  const int r0 = (threadIdx.x / TW) * G;
   const int gx = x0 + c;
   double p[G + 2][3];
 #pragma unroll
@@ -1759,12 +1776,7 @@ const char* cfg_reduce(const LaunchCfg& c) {
   if (c.variant > 1) return "variant: 0 = two kernels, 1 = single pass";
   return nullptr;
 }
-const char* cfg_tile256(const LaunchCfg& c) {
-  if (c.block != 256) return "this kernel runs 256-thread workgroups";
-  if (c.grid_cap != 0) return "grid_cap must be 0";
-  if (c.variant > 1) return "variant: 0 = row-major tiles, 1 = one contiguous run of tiles per XCD";
-  return nullptr;
-}
+const char* cfg_tile(const LaunchCfg& c);
 const char* cfg_spmv(const LaunchCfg& c) {
   if (c.block != 256) return "SpMV runs 256-thread workgroups";
   if (c.grid_cap != 0) return "grid_cap must be 0";
@@ -1886,16 +1898,46 @@ const char* v_blur(const void* p, const size_t* sz, uint32_t na, const LaunchCfg
   return v_img2(p, sz, na, c, sb);
 }
 
-template <int R>
-void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt, int xcd_map) {
-  const int tx = static_cast<int>(ceil_div(w, kTW)), nt = tx * static_cast<int>(ceil_div(h, kTH));
+// Tile shapes of the stencils (launch variant >> 1) and their workgroup sizes.
+struct TileShape {
+  int tw, th;
+};
+constexpr TileShape kTileShapes[] = {{64, 16}, {64, 8}, {64, 4}, {32, 8}};
+constexpr uint32_t kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
+
+const char* cfg_tile(const LaunchCfg& c) {
+  if (c.grid_cap != 0) return "grid_cap must be 0";
+  if ((c.variant >> 1) >= kNumTileShapes)
+    return "variant: bit 0 = tile order (0 row-major, 1 one contiguous run of tiles per XCD), "
+           "variant >> 1 = tile shape (0: 64x16, 1: 64x8, 2: 64x4, 3: 32x8)";
+  const TileShape t = kTileShapes[c.variant >> 1];
+  if (c.block != static_cast<uint32_t>(t.tw * t.th / kRowsPerThread))
+    return "block must be the tile's threads: 256 for 64x16, 128 for 64x8, 64 for 64x4 and 32x8";
+  return nullptr;
+}
+
+template <int R, int TW, int TH>
+void launch_blur_shape(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt, int xcd_map) {
+  const int tx = static_cast<int>(ceil_div(w, TW)), nt = tx * static_cast<int>(ceil_div(h, TH));
   const int grid = xcd_map ? 8 * ((nt + 7) / 8) : nt;
-  DAGRT_LAUNCH(k_gauss_blur<R>, dim3(grid), dim3(256), 0, s, in, out, w, h, wt, tx, nt, xcd_map);
+  DAGRT_LAUNCH((k_gauss_blur<R, TW, TH>), dim3(grid), dim3(TW * TH / kRowsPerThread), 0, s, in, out, w, h, wt, tx,
+               nt, xcd_map);
+}
+
+template <int R>
+void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt, uint32_t variant) {
+  const int xm = static_cast<int>(variant & 1);
+  switch (variant >> 1) {
+    case 1: launch_blur_shape<R, 64, 8>(s, in, out, w, h, wt, xm); break;
+    case 2: launch_blur_shape<R, 64, 4>(s, in, out, w, h, wt, xm); break;
+    case 3: launch_blur_shape<R, 32, 8>(s, in, out, w, h, wt, xm); break;
+    default: launch_blur_shape<R, 64, 16>(s, in, out, w, h, wt, xm); break;
+  }
 }
 
 hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const auto* q = static_cast<const dag_p_img*>(p);
-  const int xm = static_cast<int>(c.variant);
+  const uint32_t vr = c.variant;
   const int k = static_cast<int>(q->ksize), rad = (k - 1) / 2;
   const double sigma = k / 6.0;
   GaussW wt{};
@@ -1909,33 +1951,45 @@ hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   auto* out = static_cast<float*>(a[1]);
   const int w = static_cast<int>(q->w), h = static_cast<int>(q->h);
   switch (rad) {
-    case 0: launch_blur_r<0>(s, in, out, w, h, wt, xm); break;
-    case 1: launch_blur_r<1>(s, in, out, w, h, wt, xm); break;
-    case 2: launch_blur_r<2>(s, in, out, w, h, wt, xm); break;
-    case 3: launch_blur_r<3>(s, in, out, w, h, wt, xm); break;
-    case 4: launch_blur_r<4>(s, in, out, w, h, wt, xm); break;
-    case 5: launch_blur_r<5>(s, in, out, w, h, wt, xm); break;
-    case 6: launch_blur_r<6>(s, in, out, w, h, wt, xm); break;
-    case 7: launch_blur_r<7>(s, in, out, w, h, wt, xm); break;
-    case 8: launch_blur_r<8>(s, in, out, w, h, wt, xm); break;
-    case 9: launch_blur_r<9>(s, in, out, w, h, wt, xm); break;
-    case 10: launch_blur_r<10>(s, in, out, w, h, wt, xm); break;
-    case 11: launch_blur_r<11>(s, in, out, w, h, wt, xm); break;
-    case 12: launch_blur_r<12>(s, in, out, w, h, wt, xm); break;
-    case 13: launch_blur_r<13>(s, in, out, w, h, wt, xm); break;
-    case 14: launch_blur_r<14>(s, in, out, w, h, wt, xm); break;
-    default: launch_blur_r<15>(s, in, out, w, h, wt, xm); break;
+    case 0: launch_blur_r<0>(s, in, out, w, h, wt, vr); break;
+    case 1: launch_blur_r<1>(s, in, out, w, h, wt, vr); break;
+    case 2: launch_blur_r<2>(s, in, out, w, h, wt, vr); break;
+    case 3: launch_blur_r<3>(s, in, out, w, h, wt, vr); break;
+    case 4: launch_blur_r<4>(s, in, out, w, h, wt, vr); break;
+    case 5: launch_blur_r<5>(s, in, out, w, h, wt, vr); break;
+    case 6: launch_blur_r<6>(s, in, out, w, h, wt, vr); break;
+    case 7: launch_blur_r<7>(s, in, out, w, h, wt, vr); break;
+    case 8: launch_blur_r<8>(s, in, out, w, h, wt, vr); break;
+    case 9: launch_blur_r<9>(s, in, out, w, h, wt, vr); break;
+    case 10: launch_blur_r<10>(s, in, out, w, h, wt, vr); break;
+    case 11: launch_blur_r<11>(s, in, out, w, h, wt, vr); break;
+    case 12: launch_blur_r<12>(s, in, out, w, h, wt, vr); break;
+    case 13: launch_blur_r<13>(s, in, out, w, h, wt, vr); break;
+    case 14: launch_blur_r<14>(s, in, out, w, h, wt, vr); break;
+    default: launch_blur_r<15>(s, in, out, w, h, wt, vr); break;
   }
   return hipGetLastError();
 }
 
+template <int TW, int TH>
+void launch_sobel_shape(hipStream_t s, const float* in, float* out, int w, int h, int xcd_map) {
+  const int tx = static_cast<int>(ceil_div(w, TW)), nt = tx * static_cast<int>(ceil_div(h, TH));
+  const int grid = xcd_map ? 8 * ((nt + 7) / 8) : nt;
+  DAGRT_LAUNCH((k_sobel<TW, TH>), dim3(grid), dim3(TW * TH / kRowsPerThread), 0, s, in, out, w, h, tx, nt,
+               xcd_map);
+}
+
 hipError_t l_sobel(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const auto* q = static_cast<const dag_p_img*>(p);
-  const int tx = static_cast<int>(ceil_div(q->w, kTW)), nt = tx * static_cast<int>(ceil_div(q->h, kTH));
-  const int xm = static_cast<int>(c.variant);
-  const int grid = xm ? 8 * ((nt + 7) / 8) : nt;
-  DAGRT_LAUNCH(k_sobel, dim3(grid), dim3(256), 0, s, static_cast<const float*>(a[0]), static_cast<float*>(a[1]),
-               static_cast<int>(q->w), static_cast<int>(q->h), tx, nt, xm);
+  const auto* in = static_cast<const float*>(a[0]);
+  auto* out = static_cast<float*>(a[1]);
+  const int w = static_cast<int>(q->w), h = static_cast<int>(q->h), xm = static_cast<int>(c.variant & 1);
+  switch (c.variant >> 1) {
+    case 1: launch_sobel_shape<64, 8>(s, in, out, w, h, xm); break;
+    case 2: launch_sobel_shape<64, 4>(s, in, out, w, h, xm); break;
+    case 3: launch_sobel_shape<32, 8>(s, in, out, w, h, xm); break;
+    default: launch_sobel_shape<64, 16>(s, in, out, w, h, xm); break;
+  }
   return hipGetLastError();
 }
 
@@ -2485,8 +2539,8 @@ const KernelDesc kTable[] = {
     /* 1 */ {"vec_square", 1, 0x1, sizeof(dag_p_n), {256, 0, 0}, v_vec_square, l_vec_square, cfg_block_any},
     /* 2 */ {"vec_sum_diff", 3, 0x4, sizeof(dag_p_n), {256, 1024, 0}, v_vec_sum_diff, l_vec_sum_diff, cfg_reduce},
     /* 3 */ {"bs_call", 2, 0x2, sizeof(dag_p_bs), {256, 0, 0}, v_bs, l_bs, cfg_bs},
-    /* 4 */ {"gauss_blur", 2, 0x2, sizeof(dag_p_img), {256, 0, 1}, v_blur, l_blur, cfg_tile256},
-    /* 5 */ {"sobel", 2, 0x2, sizeof(dag_p_img), {256, 0, 1}, v_img2, l_sobel, cfg_tile256},
+    /* 4 */ {"gauss_blur", 2, 0x2, sizeof(dag_p_img), {256, 0, 1}, v_blur, l_blur, cfg_tile},
+    /* 5 */ {"sobel", 2, 0x2, sizeof(dag_p_img), {256, 0, 1}, v_img2, l_sobel, cfg_tile},
     /* 6 */ {"minmax", 2, 0x2, sizeof(dag_p_n), {256, 1024, 0}, v_minmax, l_minmax, cfg_reduce},
     /* 7 */ {"normalise", 3, 0x4, sizeof(dag_p_n), {256, 0, 0}, v_normalise, l_normalise, cfg_block_any},
     /* 8 */ {"unsharp_combine", 8, 0x80, sizeof(dag_p_n), {256, 0, 0}, v_combine, l_combine, cfg_block_any},

@@ -13,8 +13,10 @@ retried inside the DAG, kept only when they shorten it by more than 3 % (the fas
 leave nothing for a kernel that could run beside it).  Each
 GPU_MAX_HW_QUEUES value is tried in a process of its own, since HIP fixes it
 at start-up (the orchestrating process never touches the GPU).  Results are
-stored as JSON keyed by GPU architecture, kernel and problem size, and loaded
-with ``apply``.
+stored as JSON keyed by GPU architecture (and marked with the ROCm release),
+kernel and problem size, and loaded with ``load``/``apply_kernels``.  Only
+configurations from ``candidates`` are installed; the GPU test suite checks
+every one of them against the oracle.
 
 Usage: python -m paper_2012_09646_amd.tune --workload img --out tuned.json
 """
@@ -33,6 +35,7 @@ ARCH = "gfx950"
 BLOCKS = (64, 128, 256, 512, 1024)
 CAPS = (0, 1024, 4096)
 NEAR_TIE = 0.03  # kernel configurations this close to the fastest alone are retried inside the DAG
+TILE_SHAPES = ((64, 16), (64, 8), (64, 4), (32, 8))  # stencil tiles, in the kernels' variant order
 
 
 def candidates(kernel):
@@ -48,7 +51,10 @@ def candidates(kernel):
     if kernel == "spmv_rows":
         return [(256, c, v) for v in (4, 8, 16, 32) for c in (0, 2048, 8192)]
     if kernel in ("gauss_blur", "sobel"):
-        return [(256, 0, v) for v in (0, 1)]  # tile order: row-major or one run per XCD
+        # variant bit 0: tile order (row-major, or one run per XCD); variant >> 1: tile shape 64x16, 64x8,
+        # 64x4 or 32x8, whose workgroup is the tile's threads (four rows of one column each)
+        return [(tw * th // 4, 0, order | (shape << 1))
+                for shape, (tw, th) in enumerate(TILE_SHAPES) for order in (0, 1)]
     if kernel == "nb_proba":
         # one workgroup per CU fits beside the 128 KB table: its size sets the waves per CU
         return [(b, c, 0) for b in (256, 512, 1024) for c in (0, 256, 512, 1024)]
@@ -98,7 +104,7 @@ def tune_kernels(ctx, prog, reps=20, log=None):
         valid = [i for i, t in enumerate(total) if t >= 0]
         best = min(valid, key=lambda i: total[i])
         di = cands.index(default) if default in cands else None
-        ctx.set_launch(k, *cands[best])
+        set_launch(ctx, k, cands[best])
         # near-ties (within NEAR_TIE of the best alone), fastest first: the DAG
         # tuning picks among them by makespan, since the configuration that
         # is fastest alone may leave no room for a concurrent kernel
@@ -148,7 +154,7 @@ def makespan(prog, kernels, overrides, ms, cm, lanes, restore=(), runs=15):
     ctx = D.Context(max_streams=ms, copy_streams=cm, copy_lanes=lanes)
     apply_kernels(ctx, kernels)
     for k, cfg in overrides.items():
-        ctx.set_launch(k, *cfg)
+        set_launch(ctx, k, cfg)
     b = runner.Bound(ctx, prog, read_bytes=4)
     pris = {}
     for dst in restore:
@@ -196,22 +202,57 @@ def break_ties(prog, kernels, best, restore=(), runs=15, rounds=3, log=None, mea
     return {k: list(v) for k, v in chosen.items()}, cur
 
 
+def check_candidate(kernel, cfg):
+    """Only configurations of candidates(kernel) are ever installed: that is
+    the set the GPU parity sweep checks against the oracle."""
+    cfg = tuple(int(v) for v in cfg)
+    if cfg not in candidates(kernel):
+        raise ValueError("%s: launch configuration %s is not one of the swept candidates" % (kernel, cfg))
+    return cfg
+
+
+def set_launch(ctx, kernel, cfg):
+    ctx.set_launch(kernel, *check_candidate(kernel, cfg))
+
+
 def apply_kernels(ctx, kernels):
     for k, e in (kernels or {}).items():
-        ctx.set_launch(k, e["block"], e["grid_cap"], e["variant"])
+        set_launch(ctx, k, (e["block"], e["grid_cap"], e["variant"]))
+
+
+def rocm_version():
+    """ROCm release of this machine (from /opt/rocm/.info/version), '' if unknown."""
+    for path in ("/opt/rocm/.info/version", "/opt/rocm/.info/version-dev"):
+        try:
+            with open(path) as f:
+                return f.read().strip().split("-")[0]
+        except OSError:
+            pass
+    return ""
 
 
 def load(path):
+    """The table for this architecture.  A table made under another ROCm
+    release still loads (its configurations are all valid candidates) but is
+    marked: data["rocm_matches"] is False and the caller reports it."""
     with open(path) as f:
         data = json.load(f)
     if data.get("arch") != ARCH:
         raise ValueError("tuning file is for %s, not %s" % (data.get("arch"), ARCH))
+    for k, e in data.get("kernels", {}).items():
+        check_candidate(k, (e["block"], e["grid_cap"], e["variant"]))
+    for name, e in data.get("dag", {}).items():
+        for k, cfg in e.get("kernels", {}).items():
+            check_candidate(k, cfg)
+    data["rocm_matches"] = data.get("rocm") == rocm_version()
     return data
 
 
 def save(path, data):
     data = dict(data)
     data["arch"] = ARCH
+    data["rocm"] = rocm_version()
+    data.pop("rocm_matches", None)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)

@@ -105,3 +105,40 @@ def test_near_ties_are_broken_by_makespan():
     assert over == {"nb_proba": [1024, 256, 0]} and ms == 0.40
     assert {"nb_proba": (512, 256, 0)} in seen                      # every near tie was tried
     assert {"nb_proba": (1024, 256, 0), "ridge_proba": (256, 0, 0)} in seen
+
+
+def test_shipped_table_holds_only_swept_candidates():
+    """tune.load refuses a table with a configuration outside candidates();
+    the shipped table loads and names its ROCm release."""
+    import os
+    path = os.path.join(os.path.dirname(tune.__file__), "tuning", "gfx950.json")
+    data = tune.load(path)
+    assert data["rocm"]
+    for k, e in data["kernels"].items():
+        assert (e["block"], e["grid_cap"], e["variant"]) in tune.candidates(k)
+
+
+def test_unswept_configuration_is_refused(tmp_path):
+    ctx = D.Context(dry_run=True)
+    # a valid library configuration that is not a candidate (grid cap 2048 for an elementwise kernel)
+    ctx.set_launch("vec_square", 256, 2048, 0)
+    with pytest.raises(ValueError):
+        tune.set_launch(ctx, "vec_square", (256, 2048, 0))
+    ctx.close()
+    p = str(tmp_path / "bad.json")
+    tune.save(p, {"kernels": {"sobel": {"block": 256, "grid_cap": 0, "variant": 2, "us": 1.0}}, "dag": {}})
+    with pytest.raises(ValueError):
+        tune.load(p)
+
+
+def test_stencil_tile_shapes_need_their_workgroup_size():
+    ctx = D.Context(dry_run=True)
+    for block, variant, ok in [(256, 0, True), (128, 2, True), (64, 4, True), (64, 6, True), (64, 7, True),
+                               (256, 2, False), (128, 4, False), (256, 8, False)]:
+        for k in ("gauss_blur", "sobel"):
+            try:
+                ctx.set_launch(k, block, 0, variant)
+                assert ok, (k, block, variant)
+            except D.DagError:
+                assert not ok, (k, block, variant)
+    ctx.close()
