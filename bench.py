@@ -90,7 +90,221 @@ def parse():
     ap.add_argument("--spin-wait", type=int, default=0, choices=[0, 1],
                     help="1: host waits spin (hipDeviceScheduleSpin)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-oracle", default="", help=argparse.SUPPRESS)  # internal: CPU baseline of one workload
     return ap.parse_args()
+
+
+# ---- CPU baseline: the oracle timed on the host's cores ----------------------------------------------
+# The oracle executes a DAG strictly in program order.  On one thread it runs unchanged (oracle.run.execute,
+# BLAS limited to one thread).  On all cores, each task whose outputs are independent per element, per image
+# row, per matrix row or per output channel is cut into ranges that forked worker processes compute with the
+# same oracle function (the program's buffers live in shared anonymous memory, so the workers write the
+# results in place); the reductions that return one correctly rounded sum (math.fsum), the dense layer and the
+# final combination run whole in the parent.  The arithmetic per output is the oracle's; the outputs must equal
+# the one-thread run's bit for bit (checked and reported).
+CPU_POOL_CAP = 16  # worker processes at most (the host share of one GPU)
+_CPU = {}          # the program being run: set before the pool forks, inherited by the workers
+
+PER_ELEMENT = ("vec_square", "bs_call", "unsharp_combine", "minmax")
+PER_ELEMENT_SCALAR2 = ("normalise", "scale_l2")  # argument 1 is a small whole buffer
+
+
+def _cpu_units(op, bufs):
+    k, p = op["kernel"], op.get("params", {})
+    if k in PER_ELEMENT or k in PER_ELEMENT_SCALAR2:
+        return int(p["n"])
+    if k in ("gauss_blur", "sobel"):
+        return int(p["h"])
+    if k in ("spmv", "spmv_rows"):
+        return int(p["nrows"])
+    if k in ("nb_proba", "ridge_proba", "ensemble"):
+        return int(p["n"])
+    if k == "conv3x3_relu_pool":
+        return int(p["cout"])
+    return 0
+
+
+def _cpu_ranges(op, bufs, units, pieces):
+    """Unit ranges of about equal work (SpMV: rows + nonzeros, as a merge path)."""
+    import numpy as np
+    if op["kernel"] in ("spmv", "spmv_rows"):
+        rp = bufs[op["args"][0][0]].view(np.int32)[:units + 1].astype(np.int64)
+        path = rp + np.arange(units + 1)
+        cuts = np.searchsorted(path, np.linspace(0, path[-1], pieces + 1)[1:-1])
+    else:
+        cuts = np.linspace(0, units, pieces + 1)[1:-1].round().astype(np.int64)
+    edges = [0] + sorted(set(int(c) for c in cuts if 0 < c < units)) + [units]
+    return list(zip(edges[:-1], edges[1:]))
+
+
+def _cpu_worker_init():
+    from threadpoolctl import threadpool_limits
+    _CPU["limits"] = threadpool_limits(1)
+
+
+def _cpu_chunk(task):
+    """Worker: one range of one task through the oracle's own function."""
+    import numpy as np
+    from oracle import run as orun
+    i, lo, hi = task
+    op = _CPU["ops"][i]
+    bufs = _CPU["bufs"]
+    k, p = op["kernel"], dict(op.get("params", {}))
+    a = [bufs[name] for name, _ in op["args"]]
+    fn = orun.KERNELS[k]
+
+    def f4(x, l, h):
+        return x[4 * l:4 * h]
+    if k == "minmax":
+        p["n"] = hi - lo
+        m = np.zeros(8, np.uint8)
+        fn(p, f4(a[0], lo, hi), m)
+        return m.view(np.float32).copy()
+    if k in PER_ELEMENT:
+        p["n"] = hi - lo
+        fn(p, *[f4(x, lo, hi) for x in a])
+    elif k in PER_ELEMENT_SCALAR2:
+        p["n"] = hi - lo
+        fn(p, f4(a[0], lo, hi), a[1], f4(a[2], lo, hi))
+    elif k in ("gauss_blur", "sobel"):
+        # rows lo..hi from the input rows they read (the stencil's halo; the image border stays the border)
+        w, h = p["w"], p["h"]
+        rad = (p["ksize"] - 1) // 2 if k == "gauss_blur" else 1
+        r0, r1 = max(lo - rad, 0), min(hi + rad, h)
+        p["h"] = r1 - r0
+        tmp = np.zeros(4 * w * (r1 - r0), np.uint8)
+        fn(p, a[0][4 * w * r0:4 * w * r1], tmp)
+        a[1][4 * w * lo:4 * w * hi] = tmp[4 * w * (lo - r0):4 * w * (hi - r0)]
+    elif k in ("spmv", "spmv_rows"):
+        rp = a[0].view(np.int32)
+        s0, s1 = int(rp[lo]), int(rp[hi])
+        sub = (rp[lo:hi + 1] - s0).astype(np.int32)
+        p.update(nrows=hi - lo, nnz=s1 - s0)
+        fn(p, sub.view(np.uint8), f4(a[1], s0, s1), f4(a[2], s0, s1), a[3], f4(a[4], lo, hi))
+    elif k in ("nb_proba", "ridge_proba"):
+        n, F, C = p["n"], p["features"], p["classes"]
+        X = np.ascontiguousarray(a[0].view(np.float32)[:n * F].reshape(F, n)[:, lo:hi])
+        p["n"] = hi - lo
+        fn(p, X.view(np.uint8).ravel(), *a[1:-1], a[-1][4 * C * lo:4 * C * hi])
+    elif k == "ensemble":
+        C = p["classes"]
+        p["n"] = hi - lo
+        fn(p, *[x[4 * C * lo:4 * C * hi] for x in a[:3]], f4(a[3], lo, hi))
+    elif k == "conv3x3_relu_pool":
+        cin, plane = p["cin"], (p["h"] // 2) * (p["w"] // 2)
+        p["cout"] = hi - lo
+        fn(p, a[0], a[1][36 * cin * lo:36 * cin * hi], f4(a[2], lo, hi), a[3][4 * plane * lo:4 * plane * hi])
+    return None
+
+
+def _cpu_execute(prog, bufs, pool, pieces):
+    """Program order, each splittable task spread over the pool."""
+    import numpy as np
+    from oracle import run as orun
+    for i, op in enumerate(prog.ops):
+        kind = op["kind"]
+        if kind == "kernel":
+            units = _cpu_units(op, bufs)
+            if pool is not None and units >= 2:
+                ranges = _cpu_ranges(op, bufs, units, pieces)
+                res = pool.map(_cpu_chunk, [(i, lo, hi) for lo, hi in ranges], chunksize=1)
+                if op["kernel"] == "minmax":
+                    m = bufs[op["args"][1][0]].view(np.float32)
+                    m[0] = max(r[0] for r in res)
+                    m[1] = min(r[1] for r in res)
+            else:
+                orun.KERNELS[op["kernel"]](op.get("params", {}), *[bufs[b] for b, _ in op["args"]])
+        elif kind == "copy":
+            nb, so, do = op["bytes"], op.get("src_off", 0), op.get("dst_off", 0)
+            bufs[op["dst"]][do:do + nb] = bufs[op["src"]][so:so + nb]
+        elif kind == "host_read":
+            bufs[op["buf"]].copy()
+        elif kind != "sync":
+            raise ValueError(kind)
+
+
+def cpu_workload_program(wl, quarter=False):
+    """The workload's program; quarter=True: the same DAG on a quarter of the elements (pixels, vertices,
+    rows), the one-thread sample of the heavy workloads."""
+    from paper_2012_09646_amd import workloads as W
+    q = 2 if quarter else 0
+    return {"vec": lambda: W.vec_program(n=1 << (20 - q), seed=0),
+            "bs": lambda: W.bs_program(n=1 << (22 - q), tasks=10, seed=1),
+            "img": lambda: W.img_program(side=2048 >> (q // 2), seed=2),
+            "hits": lambda: W.hits_program(n=1 << (20 - q), deg=20, iters=10, seed=3),
+            "ml": lambda: W.ml_program(n=1 << (20 - q), seed=5),
+            "dl": lambda: W.dl_program(side=1024 >> (q // 2), seed=6)}[wl]()
+
+
+# one-thread runs of these take 7-40 s each at full size: timed on a quarter of the elements, times 4
+CPU_ONE_THREAD_QUARTER = ("img", "hits", "ml", "dl")
+
+
+def cpu_baseline(wl, budget_s=4.0):
+    """The oracle on one thread and on all cores for one workload's DAG: ms per full DAG run (median of the
+    runs that fit in budget_s per mode, at least one).  The all-cores result must equal the one-thread one
+    bit for bit on the program the one-thread run executed."""
+    import mmap
+    import multiprocessing as mp
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import run as orun
+    from paper_2012_09646_amd import workloads as W
+    prog = cpu_workload_program(wl)
+    quarter = wl in CPU_ONE_THREAD_QUARTER
+    one = cpu_workload_program(wl, quarter=True) if quarter else prog
+    init = W.initial_arrays(prog)
+    init_one = W.initial_arrays(one) if quarter else init
+
+    def timed(prepare, run):
+        """Median ms of run(prepare()) over the runs that fit in budget_s (prepare is not timed)."""
+        times, t_start = [], time.perf_counter()
+        while not times or (time.perf_counter() - t_start < budget_s and len(times) < 5):
+            state = prepare()
+            t0 = time.perf_counter()
+            run(state)
+            times.append((time.perf_counter() - t0) * 1e3)
+        return statistics.median(times), len(times), state
+
+    def one_thread(arrays):
+        with threadpool_limits(1):
+            orun.execute(one.ops, arrays)
+    t1, n1, serial = timed(lambda: {k: v.copy() for k, v in init_one.items()}, one_thread)
+    cores = min(len(os.sched_getaffinity(0)), CPU_POOL_CAP)
+
+    def all_cores(p, ini, timed_runs):
+        bufs = {}
+        for name, arr in ini.items():
+            mm = mmap.mmap(-1, max(arr.nbytes, 1))
+            bufs[name] = np.frombuffer(mm, dtype=np.uint8, count=arr.nbytes)
+        _CPU.update(ops=p.ops, bufs=bufs)
+
+        def reset():
+            for name, arr in ini.items():
+                bufs[name][:] = arr
+            return bufs
+        with mp.get_context("fork").Pool(cores, initializer=_cpu_worker_init) as pool:
+            if timed_runs:
+                res = timed(reset, lambda b: _cpu_execute(p, b, pool, 4 * cores))
+            else:
+                _cpu_execute(p, reset(), pool, 4 * cores)
+                res = (None, 0, bufs)
+        _CPU.clear()
+        return res
+    tp, n_p, par = all_cores(prog, init, True)
+    if quarter:
+        par = all_cores(one, init_one, False)[2]
+    same = all(np.array_equal(par[o], serial[o]) for o in one.outputs)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"all_cores_ms": round(tp, 2), "one_thread_ms": round(t1 * (4 if quarter else 1), 2),
+            "cores": cores, "affinity_cores": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "runs": [n_p, n1], "one_thread_sample": "a quarter of the elements, x4" if quarter else "full DAG",
+            "matches_one_thread": bool(same)}
 
 
 def orchestrate(args):
@@ -112,9 +326,8 @@ def orchestrate(args):
         fwd += ["--hw-queues", str(args.hw_queues)]
     lines = {}
     for wl in ("bs", "vec", "img", "hits", "ml", "dl", "serve"):
-        extra = [] if wl == "bs" and not args.no_cpu_baseline else ["--no-cpu-baseline"]
         log("child process: --workload %s" % wl)
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", wl] + fwd + extra,
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", wl, "--no-cpu-baseline"] + fwd,
                            stdout=subprocess.PIPE, text=True)
         if r.returncode != 0:
             log("workload %s failed with status %d" % (wl, r.returncode))
@@ -125,7 +338,25 @@ def orchestrate(args):
         line["workloads"][wl] = lines[wl]["workloads"][wl]
     line["serving"] = lines["serve"]["serving"]
     line["config"]["processes"] = "one per workload"
+    if not args.no_cpu_baseline:
+        # this process never touched the GPU, so it may fork the oracle's workers
+        for wl in ("bs", "vec", "img", "hits", "ml", "dl"):
+            log("cpu baseline: %s (oracle, one thread and all cores)" % wl)
+            line["workloads"][wl]["cpu_oracle"] = cpu_baseline(wl)
+        add_cpu_line(line)
     print(json.dumps(line), flush=True)
+
+
+def add_cpu_line(line):
+    """The headline's cpu_baseline entry: the Black-Scholes DAG on the oracle."""
+    c = line["workloads"]["bs"]["cpu_oracle"]
+    line["cpu_baseline"] = {
+        "value": c["all_cores_ms"], "unit": "ms per DAG run", "cores": c["cores"], "kind": "oracle",
+        "sample": "full runs of the 10-task Black-Scholes DAG (10 x 2^22 options), median of %d; each pricing "
+                  "task cut into element ranges over %d worker processes, copies in the parent; outputs equal "
+                  "the one-thread run's: %s" % (c["runs"][0], c["cores"], c["matches_one_thread"]),
+        "value_one_thread": c["one_thread_ms"], "cpu_model": c["cpu_model"],
+        "affinity_cores": c["affinity_cores"]}
 
 
 def main():
@@ -145,6 +376,9 @@ def main():
                 args.hw_queues = int(json.load(f).get("dag", {}).get(args.workload, {}).get("hw_queues", 0))
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
+    if args.cpu_oracle:
+        print(json.dumps(cpu_baseline(args.cpu_oracle)), flush=True)
+        return
     if args.workload == "all":
         orchestrate(args)
         return
@@ -198,7 +432,7 @@ def main():
             tune.apply_kernels(ctx, tuned)
             # near-tie kernel configurations the tuner chose for this DAG's makespan
             for k, cfg in tuned_dag.get(name, {}).get("kernels", {}).items():
-                ctx.set_launch(k, *cfg)
+                tune.set_launch(ctx, k, cfg)
             b = runner.Bound(ctx, prog, read_bytes=4)
             for dst in restore:
                 if dst not in pris:
@@ -219,6 +453,8 @@ def main():
             ts = []
             for i in range(warm + n):
                 reset(ctx, b)
+                if i == warm:
+                    timed.stats0 = ctx.stats()  # host times of the timed runs only (no first-launch code loads)
                 t0 = time.perf_counter()
                 b.run()
                 t1 = time.perf_counter()
@@ -229,11 +465,12 @@ def main():
         ctxP, bP = make(D.DAG_PARALLEL_ASYNC, False)
         log(name, "parallel")
         par = timed(ctxP, bP, steps, warmup)
-        st = ctxP.stats()
+        st, st0 = ctxP.stats(), timed.stats0
         res["makespan_ms"] = statistics.median(par)
         res["makespan_min_ms"] = min(par)
-        res["host_us_per_task"] = st.submit_host_us / max(st.tasks, 1)
-        res["launch_us_per_task"] = st.launch_host_us / max(st.tasks, 1)
+        ntimed = max(st.tasks - st0.tasks, 1)
+        res["host_us_per_task"] = (st.submit_host_us - st0.submit_host_us) / ntimed
+        res["launch_us_per_task"] = (st.launch_host_us - st0.launch_host_us) / ntimed
         res["streams"] = st.streams
         edges = sorted({(s, d) for s, d, _, _ in bP.edges()})
         res["edges"] = len(edges)
@@ -346,6 +583,7 @@ def main():
         ctxT, bT = make(D.DAG_PARALLEL_ASYNC, 1)
         log(name, "traced parallel")
         tr = []
+        gap_us = {}
         for i in range(max(3, min(steps, 10))):
             reset(ctxT, bT)
             D.dag_trace_reset(ctxT.h)
@@ -353,8 +591,17 @@ def main():
             bT.run()
             tr.append((time.perf_counter() - t0) * 1e3)
             ivs = kernel_intervals(ctxT, bT, len(prog.ops))
+            gaps = M.dependency_gaps({(s, d) for s, d, _, _ in bT.edges()}, bT.streams(),
+                                     {pos: (a, bb) for pos, _, a, bb in ivs})
+            for kind in ("same", "cross"):
+                gap_us.setdefault(kind, []).extend(1e3 * g for g in gaps[kind])
         res["overlap"] = M.overlap([(k, a, bb) for _, k, a, bb in ivs])
         res["traced_makespan_ms"] = statistics.median(tr)
+        # device idle time per dependency edge (last parent's end to the task's start), over the traced runs
+        res["dependency_gap_us"] = {kind: {"edges": len(v), "median": statistics.median(v) if v else None,
+                                           "mean": statistics.fmean(v) if v else None,
+                                           "total_per_run": sum(v) / len(tr)}
+                                    for kind, v in ((k, gap_us.get(k, [])) for k in ("same", "cross"))}
         ctxT.close()
 
         # graph form: the DAG (or one HITS iteration) recorded once and replayed
@@ -575,21 +822,16 @@ def main():
     if "serve" in results:
         line["serving"] = results.pop("serve")
     line["workloads"] = results
-    if "bs" in results and not args.no_cpu_baseline:
-        from oracle import run as orun
-        log("cpu baseline (oracle, program order)")
-        times = []
-        t_start = time.perf_counter()
-        while True:
-            arrays = W.initial_arrays(bs_prog)
-            t0 = time.perf_counter()
-            orun.execute(bs_prog.ops, arrays)
-            times.append((time.perf_counter() - t0) * 1e3)
-            if time.perf_counter() - t_start > 10.0 or len(times) >= 5:
-                break
-        line["cpu_baseline"] = {"value": round(statistics.median(times), 2), "unit": "ms per DAG run",
-                                "cores": 1, "kind": "oracle",
-                                "sample": "%d full runs of the 10-task Black-Scholes DAG (numpy/scipy, one thread)" % len(times)}
+    if not args.no_cpu_baseline:
+        # in a child process that never touches the GPU (the oracle's workers are forked)
+        import subprocess
+        for wl in [w for w in results if w in ("bs", "vec", "img", "hits", "ml", "dl")]:
+            log("cpu baseline: %s (oracle, one thread and all cores)" % wl)
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle", wl],
+                               stdout=subprocess.PIPE, text=True, check=True)
+            results[wl]["cpu_oracle"] = json.loads(r.stdout.strip().splitlines()[-1])
+        if "bs" in results:
+            add_cpu_line(line)
     print(json.dumps(line), flush=True)
 
 

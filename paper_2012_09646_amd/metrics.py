@@ -88,6 +88,27 @@ def overlap(intervals):
     return {"CT": ct, "TC": tc, "CC": cc, "TOT": tot}
 
 
+def dependency_gaps(edges, streams, times):
+    """Idle time between a task's last-finishing parent and the task (the
+    latency an edge costs on the device).  edges: (src, dst) positions;
+    streams: {pos: stream}; times: {pos: (start, end)} for timed GPU tasks.
+    For every timed task with timed parents, the parent that ends last is the
+    one the task waited for; its gap start(task) - end(parent) goes to
+    'same' when both ran on one stream (stream order) and to 'cross' when
+    the parent ran on another stream (an event wait).  Returns
+    {'same': [...], 'cross': [...]}, in the units of `times`."""
+    parents = {}
+    for s, d in edges:
+        if s in times and d in times:
+            parents.setdefault(d, []).append(s)
+    out = {"same": [], "cross": []}
+    for d, ps in sorted(parents.items()):
+        p = max(ps, key=lambda q: times[q][1])
+        gap = times[d][0] - times[p][1]
+        out["same" if streams.get(p) == streams.get(d) else "cross"].append(gap)
+    return out
+
+
 def percentile(values, q):
     """Nearest-rank percentile (q in (0, 100])."""
     v = sorted(values)

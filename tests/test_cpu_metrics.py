@@ -57,3 +57,15 @@ def test_rocprof_intervals_and_runs(tmp_path):
     o = M.overlap([(x[0], x[1], x[2]) for x in runs[0]])
     # T [50,120) overlaps kernels on [100,120) = 20 of 70
     assert abs(o["TC"] - 20 / 70) < 1e-12
+
+
+def test_dependency_gaps_take_the_last_parent_and_split_by_stream():
+    # 1 and 2 on streams 0 and 1 end at 5 and 7; 3 (stream 0) starts at 9:
+    # its last parent is 2 (cross-stream), gap 2; 4 follows 3 on stream 0
+    edges = {(1, 3), (2, 3), (3, 4)}
+    streams = {1: 0, 2: 1, 3: 0, 4: 0}
+    times = {1: (0.0, 5.0), 2: (1.0, 7.0), 3: (9.0, 10.0), 4: (10.5, 11.0)}
+    g = M.dependency_gaps(edges, streams, times)
+    assert g == {"same": [0.5], "cross": [2.0]}
+    # untimed tasks (host reads) are ignored
+    assert M.dependency_gaps({(1, 5)}, streams, times) == {"same": [], "cross": []}
