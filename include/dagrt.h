@@ -244,7 +244,7 @@ dag_status dag_buffer_ptr(dag_ctx ctx, dag_buf buf, void** ptr, size_t* bytes);
  * host before launch).  fp32 data, fp64 arithmetic, one rounding to fp32. */
 #define DAG_K_VEC_SQUARE 1u      /* x:m                 x_i <- x_i*x_i (fp32) */
 #define DAG_K_VEC_SUM_DIFF 2u    /* x:c y:c r:m         r[0] = sum(x_i - y_i) */
-#define DAG_K_BS_CALL 3u         /* S:c C:m             Black-Scholes call */
+#define DAG_K_BS_CALL 3u         /* S:c C:m             Black-Scholes call (spots >= 0; S = 0 prices at 0) */
 #define DAG_K_GAUSS_BLUR 4u      /* in:c out:m          Gaussian blur, clamp */
 #define DAG_K_SOBEL 5u           /* in:c out:m          Sobel magnitude */
 #define DAG_K_MINMAX 6u          /* in:c M:m            M = [max, min] */

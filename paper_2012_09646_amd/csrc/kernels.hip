@@ -274,7 +274,10 @@ __device__ __forceinline__ double bs_price_fast(double s, const BsConst& k) {
   const double h2 = 0.5 * e2 * erfcx_pos(fabs(d2) * M_SQRT1_2);
   const double n1 = d1 < 0.0 ? h1 : 1.0 - h1;
   const double n2 = d2 < 0.0 ? h2 : 1.0 - h2;
-  return s * n1 - k.disc_strike * n2;
+  // a zero spot prices at 0 (ln 0 = -inf would reach erfcx_pos(inf) = NaN);
+  // spots must not be negative (the model's domain)
+  const double c = s * n1 - k.disc_strike * n2;
+  return s > 0.0 ? c : 0.0;
 }
 
 // a * b + c as one three-address v_fma_f64.  For a Horner step whose
@@ -339,7 +342,10 @@ __device__ __forceinline__ double log_pos(double y) {
 }
 
 // bs_price_fast with the exponential and logarithm above (inputs there are
-// finite: S > 0 is a normal float, the exponent is -d^2/2 <= 0).
+// finite: S * (1/K) is a normal double for every positive fp32 S, the
+// exponent is -d^2/2 <= 0).  A zero spot prices at 0 (the limit of the
+// formula); log_pos(0) is not -inf, so that is selected at the end, as in
+// bs_price_fast (one compare and select).  Spots must not be negative.
 __device__ __forceinline__ double bs_price_own(double s, const BsConst& k) {
   const double d1 = (log_pos(s * k.inv_strike) + k.mu_t) * k.inv_vol_t;
   const double d2 = d1 - k.vol_t;
@@ -350,7 +356,8 @@ __device__ __forceinline__ double bs_price_own(double s, const BsConst& k) {
   const double h2 = 0.5 * e2 * erfcx_pos(fabs(d2) * M_SQRT1_2);
   const double n1 = d1 < 0.0 ? h1 : 1.0 - h1;
   const double n2 = d2 < 0.0 ? h2 : 1.0 - h2;
-  return s * n1 - k.disc_strike * n2;
+  const double c = s * n1 - k.disc_strike * n2;
+  return s > 0.0 ? c : 0.0;
 }
 
 // variant 0: the library's erfc; 1: bs_price_fast; 2: bs_price_own.
@@ -1463,6 +1470,179 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// The same convolution as an implicit GEMM on the fp64 matrix cores
+// (v_mfma_f64_16x16x4f64: D[16x16] += A[16x4] * B[4x16], lane l supplying
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holding D[4 r + l / 16][l % 16]
+// in its r-th result, as an in-bounds probe of the instruction showed).  Rows of the product are convolution outputs, columns
+// output channels, and the reduction runs over (tap, input channel) pairs
+// k = tap * cin + c, so that a lane's four consecutive k of one MFMA are four
+// input channels of one tap and every operand address is the lane's base plus
+// a uniform offset.  A workgroup of four waves computes a 16 x 16 tile of
+// convolution outputs (8 x 8 pooled) for 16 * NJB output channels: each wave
+// four 4 x 4 pixel blocks (one MFMA row each: row i = pixel (i / 4, i % 4)),
+// so per reduction step it reads four A and NJB B values and issues 4 NJB
+// independent MFMAs.  The input tile (cin x 18 x 18, zero padded) and the
+// weights ([k][channel], fp32) are staged in LDS four input channels at a
+// time, the next four channels' loads in flight while the current ones'
+// products run.  Bias is
+// the accumulator's start; after the reduction a lane holds one pixel column
+// (px = l / 16, rows py = r) of a block for one channel, so the 2 x 2 pooling
+// is a max inside the lane (rows) and one across lanes l and l ^ 16
+// (columns), then ReLU (monotone, so it commutes with the max).  Needs cin % 4 == 0, cout % 16 == 0 and the staged tile and
+// weights within 64 KB of LDS (conv_mfma_lds).
+typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int kConvMfmaTile = 16;                      // convolution outputs per tile side
+constexpr int kConvMfmaIn = kConvMfmaTile + 2;         // 18 staged rows / columns
+constexpr size_t kConvMfmaMaxLds = 64 * 1024;
+
+template <int NJB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_conv3x3_relu_pool_mfma(
+    const float* __restrict__ x, const float* __restrict__ w, const float* __restrict__ bias, float* __restrict__ y,
+    uint32_t cin, uint32_t h, uint32_t wd, uint32_t tiles_x) {
+  constexpr int NC = 16 * NJB;                         // output channels of this workgroup
+  constexpr int kPlane = kConvMfmaIn * kConvMfmaIn;    // 324
+  constexpr int kOut = kConvMfmaTile / 2;              // 8 x 8 pooled outputs per channel
+  // One group = four input channels, the channels of one reduction step per
+  // tap: its input tile (4 x 324) and its weights (9 taps x 4 x NC) take
+  // kInSlots and kWSlots elements per thread.
+  constexpr int kInSlots = (4 * kPlane + 255) / 256;
+  constexpr int kWSlots = (9 * 4 * NC + 255) / 256;
+  extern __shared__ float s_dyn[];
+  float* s_in = s_dyn;                                 // [cin][18][18]
+  float* s_w = s_dyn + cin * kPlane;                   // [9 cin][NC], row k = tap * cin + c
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Y0 = static_cast<int>((blockIdx.x / tiles_x) * kConvMfmaTile);
+  const int X0 = static_cast<int>((blockIdx.x % tiles_x) * kConvMfmaTile);
+  const uint32_t o0 = blockIdx.y * NC;
+  const uint64_t plane = static_cast<uint64_t>(h) * wd;
+  // this thread's input elements of a group (fixed positions; zero padding
+  // outside the image)
+  uint32_t ioff[kInSlots];
+  uint32_t imask = 0;
+#pragma unroll
+  for (int j = 0; j < kInSlots; ++j) {
+    const uint32_t e = tid + 256 * j, cl = e / kPlane, rq = e % kPlane;
+    const int gy = Y0 - 1 + static_cast<int>(rq / kConvMfmaIn), gx = X0 - 1 + static_cast<int>(rq % kConvMfmaIn);
+    const bool in = e < 4 * kPlane && gy >= 0 && gy < static_cast<int>(h) && gx >= 0 && gx < static_cast<int>(wd);
+    ioff[j] = in ? cl * static_cast<uint32_t>(plane) + static_cast<uint32_t>(gy) * wd + static_cast<uint32_t>(gx) : 0u;
+    imask |= (in ? 1u : 0u) << j;
+  }
+  // Group g's loads go to registers (vi, vw) and from there to LDS, so the
+  // next group's loads are in flight while this group's products run.
+  // Weight element e of a group: channel jj = e % NC (lanes over output
+  // channels, so the LDS stores hit consecutive banks), then tap and channel.
+  float vi[kInSlots], vw[kWSlots];
+  auto fetch = [&](uint32_t g) {
+    const float* xg = x + static_cast<uint64_t>(4 * g) * plane;
+#pragma unroll
+    for (int j = 0; j < kInSlots; ++j) vi[j] = ((imask >> j) & 1u) ? xg[ioff[j]] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < kWSlots; ++j) {
+      const uint32_t e = tid + 256 * j, jj = e % NC, rem = e / NC, t = rem % 9, cl = rem / 9;
+      vw[j] = e < 9 * 4 * NC ? w[(static_cast<uint64_t>(o0 + jj) * cin + 4 * g + cl) * 9 + t] : 0.0f;
+    }
+  };
+  auto put = [&](uint32_t g) {
+#pragma unroll
+    for (int j = 0; j < kInSlots; ++j) {
+      const uint32_t e = tid + 256 * j;
+      if (e < 4 * kPlane) s_in[4 * g * kPlane + e] = vi[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kWSlots; ++j) {
+      const uint32_t e = tid + 256 * j, jj = e % NC, rem = e / NC, t = rem % 9, cl = rem / 9;
+      if (e < 9 * 4 * NC) s_w[(t * cin + 4 * g + cl) * NC + jj] = vw[j];
+    }
+  };
+  // lane roles: A row i = pixel (py, px) of a 4 x 4 block, reduction slot kq
+  const uint32_t i = lane & 15, kq = lane >> 4, py = i >> 2, px = i & 3;
+  // this wave's four blocks: block row `wave` of the tile, block columns 0..3
+  const float* a_base = s_in + kq * kPlane + (4 * wave + py) * kConvMfmaIn + px;
+  const float* b_base = s_w + kq * NC + i;
+  double4_t acc[4][NJB];
+#pragma unroll
+  for (int jb = 0; jb < NJB; ++jb) {
+    const double b0 = static_cast<double>(bias[o0 + 16 * jb + i]);
+#pragma unroll
+    for (int bx = 0; bx < 4; ++bx) acc[bx][jb] = double4_t{b0, b0, b0, b0};
+  }
+  const uint32_t ng = cin / 4;
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (uint32_t g = 0; g < ng; ++g) {
+    if (g + 1 < ng) fetch(g + 1);
+    const float* ag = a_base + 4 * g * kPlane;
+    const float* bg = b_base + 4 * g * NC;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t % 3;
+      const float* ap = ag + dy * kConvMfmaIn + dx;
+      const float* bp = bg + t * cin * NC;
+      double bv[NJB];
+#pragma unroll
+      for (int jb = 0; jb < NJB; ++jb) bv[jb] = static_cast<double>(bp[16 * jb]);
+#pragma unroll
+      for (int bx = 0; bx < 4; ++bx) {
+        const double av = static_cast<double>(ap[4 * bx]);
+#pragma unroll
+        for (int jb = 0; jb < NJB; ++jb)
+          acc[bx][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[jb], acc[bx][jb], 0, 0, 0);
+      }
+    }
+    if (g + 1 < ng) put(g + 1);
+    __syncthreads();
+  }
+  // Pooling: this lane holds pixel column px = kq of each block, rows 0..3
+  // in its four results; pooled row 0 from rows 0-1, row 1 from rows 2-3.
+  // The pooled tile [NC][8][8] goes through LDS (over the input tile, which
+  // every wave has finished reading at the last barrier) so that each of its
+  // rows is written as 32 contiguous bytes.
+  float* s_out = s_dyn;
+#pragma unroll
+  for (int jb = 0; jb < NJB; ++jb) {
+#pragma unroll
+    for (int bx = 0; bx < 4; ++bx) {
+      double m0 = fmax(acc[bx][jb][0], acc[bx][jb][1]);
+      double m1 = fmax(acc[bx][jb][2], acc[bx][jb][3]);
+      m0 = fmax(m0, __shfl_xor(m0, 16));
+      m1 = fmax(m1, __shfl_xor(m1, 16));
+      if ((kq & 1) == 0) {
+        float* o = s_out + ((16 * jb + i) * kOut + 2 * wave) * kOut + 2 * bx + (kq >> 1);
+        o[0] = static_cast<float>(fmax(m0, 0.0));
+        o[kOut] = static_cast<float>(fmax(m1, 0.0));
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t ph = h / 2, pw = wd / 2, PY0 = static_cast<uint32_t>(Y0 / 2), PX0 = static_cast<uint32_t>(X0 / 2);
+  for (uint32_t rrow = tid; rrow < NC * kOut; rrow += 256) {
+    const uint32_t ch = rrow / kOut, ry = rrow % kOut, PY = PY0 + ry;
+    if (PY >= ph) continue;
+    const float* src = s_out + rrow * kOut;
+    float* dst = y + (static_cast<uint64_t>(o0 + ch) * ph + PY) * pw + PX0;
+    if (PX0 + kOut <= pw && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+      reinterpret_cast<float4*>(dst)[0] = reinterpret_cast<const float4*>(src)[0];
+      reinterpret_cast<float4*>(dst)[1] = reinterpret_cast<const float4*>(src)[1];
+    } else {
+      for (uint32_t k = 0; k < kOut && PX0 + k < pw; ++k) dst[k] = src[k];
+    }
+  }
+}
+
+size_t conv_mfma_lds(uint32_t cin, uint32_t njb) {
+  // the staged input tile and weights; the pooled tile [16 njb][8][8] reuses it
+  const size_t staged = 4 * (static_cast<size_t>(cin) * kConvMfmaIn * kConvMfmaIn + 9ull * cin * 16 * njb);
+  return std::max<size_t>(staged, 4ull * 16 * njb * 64);
+}
+// Output-channel blocks of 16 per workgroup for the matrix-core form (2 where
+// cout allows and the LDS fits, else 1); 0 = the form does not apply.
+uint32_t conv_mfma_njb(uint32_t cin, uint32_t cout) {
+  if (cin % 4 != 0 || cout % 16 != 0) return 0;
+  if (cout % 32 == 0 && conv_mfma_lds(cin, 2) <= kConvMfmaMaxLds) return 2;
+  return conv_mfma_lds(cin, 1) <= kConvMfmaMaxLds ? 1 : 0;
+}
+
 // fp64 copy of convolution weights for the scalar-weight variant:
 // w64[(c * cout + o) * 9 + t] = w[(o * cin + c) * 9 + t] (exact conversion).
 __global__ __launch_bounds__(256) void k_conv_weights_f64(const float* __restrict__ w, double* __restrict__ w64,
@@ -2371,8 +2551,9 @@ hipError_t l_ensemble(hipStream_t s, void* const* a, const void* p, const Launch
 const char* cfg_conv(const LaunchCfg& c) {
   if (c.block != 256) return "this kernel runs 256-thread workgroups (16 x 16 pooled outputs)";
   if (c.grid_cap != 0) return "grid_cap must be 0";
-  if (c.variant > 2)
-    return "variant must be 0 (one channel at a time), 1 (channels pipelined) or 2 (pipelined, scalar weights)";
+  if (c.variant > 3)
+    return "variant must be 0 (one channel at a time), 1 (channels pipelined), 2 (pipelined, scalar weights) "
+           "or 3 (fp64 matrix cores)";
   return nullptr;
 }
 const dag_p_conv* pconv(const void* p) { return static_cast<const dag_p_conv*>(p); }
@@ -2390,6 +2571,8 @@ const char* v_conv(const void* p, const size_t* sz, uint32_t, const LaunchCfg&, 
   if (sz[3] < 4 * q->cout * (hw / 4)) return "y smaller than 4*cout*(h/2)*(w/2) bytes";
   const uint64_t tiles = ceil_div(q->h / 2, kConvTile) * ceil_div(q->w / 2, kConvTile);
   if (tiles > (1u << 30) || q->cout / conv_oc(q->cout) > 65535) return "grid too large";
+  const uint64_t mtiles = ceil_div(q->h, kConvMfmaTile) * ceil_div(q->w, kConvMfmaTile);
+  if (mtiles > (1u << 30)) return "grid too large";
   return nullptr;
 }
 hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void* scr, size_t sb) {
@@ -2402,6 +2585,20 @@ hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   const auto* w = static_cast<const float*>(a[1]);
   const auto* bias = static_cast<const float*>(a[2]);
   auto* y = static_cast<float*>(a[3]);
+  // variant 3: the matrix-core form where the channel counts allow it
+  // (conv_mfma_njb), else variant 1
+  const uint32_t njb = c.variant == 3 ? conv_mfma_njb(q->cin, q->cout) : 0;
+  if (njb) {
+    const uint32_t mtx = static_cast<uint32_t>(ceil_div(q->w, kConvMfmaTile));
+    const uint32_t mty = static_cast<uint32_t>(ceil_div(q->h, kConvMfmaTile));
+    const size_t lds = conv_mfma_lds(q->cin, njb);
+    const dim3 mg(mtx * mty, q->cout / (16 * njb));
+    if (njb == 2)
+      DAGRT_LAUNCH(k_conv3x3_relu_pool_mfma<2>, mg, dim3(256), lds, s, x, w, bias, y, q->cin, q->h, q->w, mtx);
+    else
+      DAGRT_LAUNCH(k_conv3x3_relu_pool_mfma<1>, mg, dim3(256), lds, s, x, w, bias, y, q->cin, q->h, q->w, mtx);
+    return hipGetLastError();
+  }
   // variant 2 needs the fp64 weight copy in the stream's scratch (above the
   // counters); where it does not fit, variant 1 runs instead
   const uint64_t nw = static_cast<uint64_t>(q->cin) * q->cout * 9;
@@ -2411,7 +2608,7 @@ hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
     const uint32_t gw = static_cast<uint32_t>(std::min<uint64_t>(ceil_div(nw, 256), 1024));
     DAGRT_LAUNCH(k_conv_weights_f64, dim3(gw), dim3(256), 0, s, w, w64, q->cin, q->cout);
   }
-  if (c.variant != 0) {
+  if (c.variant != 0) {  // 1, 2, and 3 where the matrix-core form does not apply
 #define DAGRT_CONV_PIPE(OC)                                                                                  \
   if (sw)                                                                                                    \
     DAGRT_LAUNCH((k_conv3x3_relu_pool_pipe<OC, true>), g, b, 0, s, x, w, w64, bias, y, q->cin, q->cout, q->h, \

@@ -71,8 +71,9 @@ def candidates(kernel):
         return [(b, c, v) for b in (256, 512, 1024) for c in (128, 256, 512, 1024, 2048) for v in (0, 1, 2, 3, 4)]
     if kernel == "conv3x3_relu_pool":
         # variant 0: one input channel per barrier pair; 1: channels pipelined;
-        # 2: pipelined with fp64 weights read as scalars
-        return [(256, 0, 0), (256, 0, 1), (256, 0, 2)]
+        # 2: pipelined with fp64 weights read as scalars; 3: implicit GEMM on
+        # the fp64 matrix cores (where cin % 4 == 0 and cout % 16 == 0)
+        return [(256, 0, v) for v in (0, 1, 2, 3)]
     return []  # the delay kernel
 
 

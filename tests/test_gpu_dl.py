@@ -63,14 +63,15 @@ def test_dense_reduction_launch_shapes(block, cap, n, m, variant):
         ctx.close()
 
 
-@pytest.mark.parametrize("variant,scratch", [(0, 0), (1, 0), (2, 0), (2, 4096)])
+@pytest.mark.parametrize("variant,scratch", [(0, 0), (1, 0), (2, 0), (2, 4096), (3, 4096)])
 @pytest.mark.parametrize("cin,cout,h,w", [(1, 16, 64, 64), (16, 32, 66, 98), (3, 8, 34, 36), (2, 4, 2, 2),
                                           (5, 3, 40, 30), (17, 8, 50, 70), (4, 12, 96, 32)])
 def test_conv_launch_variants(variant, scratch, cin, cout, h, w):
     """One convolution layer alone in each launch variant (one channel at a
     time; channels pipelined through a double-buffered tile; pipelined with
     fp64 weights read as scalars, which falls back to the second where the
-    stream scratch of 4096 bytes cannot hold the weight copy): ragged tiles,
+    stream scratch of 4096 bytes cannot hold the weight copy; the matrix-core
+    variant falls back to the second in that case too): ragged tiles,
     odd and even channel counts, 8, 4 or 1 output channels per workgroup.
     Every variant must agree with the others bit for bit (same FMA order)."""
     banner("conv variant=%d scratch=%d cin=%d cout=%d h=%d w=%d" % (variant, scratch, cin, cout, h, w))
@@ -103,8 +104,51 @@ def test_conv_launch_variants(variant, scratch, cin, cout, h, w):
         assert np.array_equal(outs[v].view(np.uint32), y.view(np.uint32)), v
 
 
+@pytest.mark.parametrize("cin,cout,h,w", [(16, 32, 66, 98), (4, 16, 34, 36), (8, 48, 50, 70), (16, 16, 2, 2),
+                                          (12, 32, 96, 32), (32, 16, 40, 30), (28, 32, 18, 46), (16, 32, 512, 512),
+                                          (3, 8, 34, 36), (16, 12, 20, 20)])
+def test_conv_matrix_core_variant(cin, cout, h, w):
+    """Variant 3, the implicit GEMM on the fp64 matrix cores (16 x 16 tiles
+    of convolution outputs, 16 or 32 output channels per workgroup, weights
+    rearranged into the stream scratch by a first kernel), against the
+    oracle at 1e-5: ragged tiles, several channel counts, one and two
+    channel blocks, launched twice in a row (equal bit for bit).  Where the channel counts do not
+    allow it (cin % 4 != 0 or cout % 16 != 0) variant 1 runs instead and the
+    result equals variant 1's bit for bit."""
+    banner("conv mfma cin=%d cout=%d h=%d w=%d" % (cin, cout, h, w))
+    g = np.random.default_rng(cin * 7919 + cout * 31 + h + w)
+    x = (g.random((cin, h, w), dtype=np.float32) - 0.3).astype(np.float32)
+    wt = ((g.random((cout, cin, 3, 3), dtype=np.float32) - 0.5) / (3.0 * np.sqrt(cin))).astype(np.float32)
+    b = ((g.random(cout, dtype=np.float32) - 0.5) * 0.1).astype(np.float32)
+    ref = T.conv3x3_relu_pool(x, wt, b)
+    outs = {}
+    ctx = D.Context(max_streams=1)
+    try:
+        hx, hw_, hb = ctx.alloc(x.nbytes), ctx.alloc(wt.nbytes), ctx.alloc(b.nbytes)
+        hy = ctx.alloc(4 * cout * (h // 2) * (w // 2))
+        ctx.host_write(hx, x)
+        ctx.host_write(hw_, wt)
+        ctx.host_write(hb, b)
+        for v in (3, 3, 1):
+            ctx.host_write(hy, np.zeros(cout * (h // 2) * (w // 2), np.float32))
+            ctx.set_launch("conv3x3_relu_pool", 256, 0, v)
+            ctx.kernel("conv3x3_relu_pool", [(hx, "c"), (hw_, "c"), (hb, "c"), (hy, "m")],
+                       cin=cin, cout=cout, h=h, w=w)
+            y = np.zeros((cout, h // 2, w // 2), np.float32)
+            ctx.host_read(hy, y)
+            r = ref.astype(np.float64)
+            assert np.all((y == ref) | (np.abs(y.astype(np.float64) - r) <= 1e-5 * np.abs(r))), \
+                (v, np.max(np.abs(y - ref)))
+            outs.setdefault(v, []).append(y)
+    finally:
+        ctx.close()
+    assert np.array_equal(outs[3][0].view(np.uint32), outs[3][1].view(np.uint32))
+    if cin % 4 or cout % 16:
+        assert np.array_equal(outs[3][0].view(np.uint32), outs[1][0].view(np.uint32))
+
+
 @pytest.mark.parametrize("graph_mode", [0, 1])
-@pytest.mark.parametrize("conv_variant,dense_variant", [(2, 3), (2, 4), (1, 1)])
+@pytest.mark.parametrize("conv_variant,dense_variant", [(2, 3), (2, 4), (1, 1), (3, 4)])
 def test_dl_region_replays_with_two_kernel_tasks(graph_mode, conv_variant, dense_variant):
     """The DL DAG recorded as a region (hipGraph, or recorded multi-stream
     replay) while its convolution and dense tasks launch two kernels each
@@ -150,7 +194,8 @@ def test_dl_full_size():
 
 
 @pytest.mark.parametrize("conv_variant,dense_variant,dense_block,dense_cap",
-                         [(0, 0, 256, 1024), (2, 3, 512, 256), (1, 4, 512, 512), (1, 2, 1024, 128)])
+                         [(0, 0, 256, 1024), (2, 3, 512, 256), (1, 4, 512, 512), (1, 2, 1024, 128),
+                          (3, 4, 512, 512)])
 def test_dl_full_size_launch_variants(conv_variant, dense_variant, dense_block, dense_cap):
     """The benchmark's shape in other launch variants of the convolution and
     dense kernels than the tuned ones: every output against the oracle."""

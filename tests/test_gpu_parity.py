@@ -94,13 +94,14 @@ def test_region_replays_copy_kernel(graph_mode):
 @pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("r,sigma,years", [(0.08, 0.3, 1.0), (0.0, 1.5, 4.0), (0.2, 0.05, 0.1), (0.03, 3.0, 30.0)])
 def test_bs_variants_wide_range(variant, r, sigma, years):
-    """Both call-price variants against the oracle over spot prices from deep
+    """Every call-price variant against the oracle over spot prices from deep
     out of the money to deep in the money (log-uniform over 1e-3 .. 1e4 with
-    strike 25), at several rates, volatilities and maturities."""
+    strike 25), at several rates, volatilities and maturities; also a zero
+    spot (price 0), the smallest subnormal and the smallest normal fp32 spot."""
     banner("bs variant=%d r=%g sigma=%g T=%g" % (variant, r, sigma, years))
     n = 300001
     spots = np.exp(np.linspace(np.log(1e-3), np.log(1e4), n)).astype(np.float32)
-    spots[:4] = [25.0, 24.999998, 25.000002, 1e-3]
+    spots[:7] = [25.0, 24.999998, 25.000002, 1e-3, 0.0, np.float32(1e-45), np.float32(1.1754944e-38)]
     prog = W.Program("bs1", {"S": W.Buf(4 * n, init=spots), "C": W.Buf(4 * n)},
                      [W.K("bs_call", [("S", "c"), ("C", "m")], n=n, K=25.0, r=r, sigma=sigma, T=years)], ["C"])
     ref = G.oracle_run(prog)["C"].view(np.float32).astype(np.float64)
@@ -117,6 +118,7 @@ def test_bs_variants_wide_range(variant, r, sigma, years):
     bad = np.abs(got - ref) > 1e-5 * np.abs(ref)
     assert not (bad & big).any(), (np.nonzero(bad & big)[0][:5], got[bad & big][:5], ref[bad & big][:5])
     assert np.all(np.abs(got[~big] - ref[~big]) <= 1e-30)
+    assert got[4] == 0.0 and ref[4] == 0.0
 
 
 @pytest.mark.parametrize("w,h", [(1, 1), (5, 3), (100, 77), (333, 130), (2048, 2048)])
