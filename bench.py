@@ -36,11 +36,11 @@ FP64_PEAK_TFLOPS = 78.6   # vector fp64: 256 CUs x 128 flop/clk (4 SIMDs x 16 la
 # 83 + 44 + 23 + 3, variant 0, the library erfc, 127 + 61 + 22 + 7).  VALU wave-lane instructions per element
 # (all kinds) per variant:
 BS_FLOPS_PER_ELEMENT = 2 * 86 + 5 + 19 + 3
-BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25, 2: 144.125}
+BS_VALU_PER_ELEMENT = {0: 285.75, 1: 206.25, 2: 146.125}  # 0, 1: measured before the zero-spot select (+2)
 # HBM bytes per bs_call launch (variant 2, 128 threads, grid cap 4096) from FETCH_SIZE / WRITE_SIZE, each divided
-# by what the counter reads for a 256 MiB copy kernel (FETCH_SIZE 0.500027x, WRITE_SIZE 1.000x of the true
-# bytes): 16.14 MiB in + 16.00 MiB out
-TRAFFIC_BS_BYTES = int((8266.28125 / 0.5000268 + 16384.0 / 1.0) * 1024)
+# by what the counter reads for a 256 MiB copy kernel (FETCH_SIZE 0.500054x, WRITE_SIZE 1.000x of the true
+# bytes): 16.14 MiB in + 16.00 MiB out (the kernel with the zero-spot select)
+TRAFFIC_BS_BYTES = int((8262.20625 / 0.5000536 + 16384.0 / 1.0) * 1024)
 CUS, CLOCK_GHZ = 256, 2.4
 SERVE_HW_QUEUES = 8
 
@@ -675,6 +675,56 @@ def main():
             ctxG.close()
         return res, ktimes
 
+    def edge_cost(calls=64, gate_ns=2_000_000, reps=15):
+        """Device cost of a dependency edge on this GPU.  A 2 ms delay kernel,
+        then a chain of `calls` tiny kernels that each square the same 4 KiB
+        vector (every call depends on the one before), recorded as a region
+        and replayed (recorded multi-stream replay) with two hand-written
+        schedules: all calls on one stream (edges through stream order), or
+        consecutive calls alternating between two streams, each waiting on
+        its predecessor's event.  The host enqueues the whole chain while the
+        delay runs, so a replay's time minus the delay is the device's time
+        for the chain; per call = that / calls."""
+        n = 1024
+        ones = np.ones(n, np.float32)
+        ops = [W.K("spin", [("x", "m")], ns=gate_ns)] + [W.K("vec_square", [("x", "m")], n=n)] * calls
+        prog = W.Program("chain", {"x": W.Buf(4 * n, init=ones)}, ops, ["x"])
+        ctx = D.Context(graph_mode=1, max_streams=2)
+        tune.apply_kernels(ctx, tuned)
+        b = runner.Bound(ctx, prog, read_bytes=4)
+        b.record(1)
+        ctx.sync()
+        out = {}
+        scheds = {"same_stream": [(0, [])] * (calls + 1),
+                  "cross_stream": [(0, [])] + [(k % 2, [k - 1]) for k in range(1, calls + 1)]}
+        for name, sched in scheds.items():
+            D.dag_region_set_schedule(ctx.h, 1, sched)
+            ts = []
+            for _ in range(reps + 2):
+                t0 = time.perf_counter()
+                D.dag_region_launch(ctx.h, 1)
+                ctx.sync()
+                ts.append((time.perf_counter() - t0) * 1e6)
+            out[name] = statistics.median(ts[2:])
+        # the delay alone (same context, one call)
+        ctx2 = D.Context(max_streams=1)
+        h = ctx2.alloc(4 * n)
+        ts = []
+        for _ in range(reps + 2):
+            t0 = time.perf_counter()
+            ctx2.kernel("spin", [(h, "m")], ns=gate_ns)
+            ctx2.sync()
+            ts.append((time.perf_counter() - t0) * 1e6)
+        gate = statistics.median(ts[2:])
+        ctx2.close()
+        ctx.close()
+        same = (out["same_stream"] - gate) / calls
+        cross = (out["cross_stream"] - gate) / calls
+        return {"calls": calls, "same_stream_us_per_call": round(same, 3),
+                "cross_stream_us_per_call": round(cross, 3), "cross_edge_extra_us": round(cross - same, 3),
+                "method": "2 ms delay kernel, then a %d-call dependent chain of 4 KiB squares replayed from a "
+                          "recorded region; (replay time - delay alone) / calls, median of %d" % (calls, reps)}
+
     def measure_serving(graphs):
         """Open-loop serving of the mixed trace, concurrent and serial."""
         ctx = D.Context(spin_wait=args.spin_wait,
@@ -728,6 +778,8 @@ def main():
         if wl == "vec":
             prog = W.vec_program(n=1 << 20, seed=0)
             results[wl], _ = measure(wl, prog, 5, args.warmup, restore=("x", "y"))
+            log("vec: cost of a dependency edge")
+            results[wl]["edge_cost"] = edge_cost()
         elif wl == "bs":
             prog = W.bs_program(n=1 << 22, tasks=10, seed=1)
             results[wl], kt_bs = measure(wl, prog, args.steps, args.warmup)

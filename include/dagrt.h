@@ -34,6 +34,11 @@
  *   - Testing hook: if the environment variable DAGRT_FAULT_LAUNCH=N is set
  *     when a context is created, its N-th kernel launch fails with DAG_E_HIP
  *     (without launching anything) and poisons the context.
+ *   - Profiling hook: with DAGRT_ROCTX=1 set when a context is created (and
+ *     the roctx library of the ROCm profiler present), the host-side
+ *     submission of every GPU task is a roctx range named
+ *     "dagrt task <id> <kernel|copy|region> stream <s> waits <n>", which
+ *     rocprofv3 --marker-trace records beside the kernel and copy traces.
  *   - Pointers are plain host or device addresses; sizes are in bytes unless
  *     stated.  Nothing in this header refers to a framework type.
  *   - Task ids are 1-based positions in program order (every submit, host

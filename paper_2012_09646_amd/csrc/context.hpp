@@ -103,7 +103,8 @@ struct dag_ctx_s {
   hipStream_t io = nullptr;
   void* staging = nullptr;                // pinned, for small host reads
   hipEvent_t read_ev = nullptr;
-  std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion
+  std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion; ev[id - ev_base]
+  uint64_t ev_base = 0;                   // first task id of ev (records before it were compacted)
   std::vector<hipEvent_t> ev0;            // per task, start (trace mode)
   std::vector<hipEvent_t> ev1;            // per task, kernel end (trace mode 2, built-in kernels)
   std::vector<hipEvent_t> free_ev;
@@ -131,6 +132,11 @@ struct dag_ctx_s {
   // failure injection (tests): the fault_at-th kernel launch reports an error
   // instead of launching; 0 = off
   uint64_t fault_at = 0, n_launches = 0;
+  // DAGRT_ROCTX=1: each GPU task's submission is a roctx range (profiler
+  // marker trace); the functions come from the roctx library, loaded at
+  // context creation
+  int (*roctx_push)(const char*) = nullptr;
+  int (*roctx_pop)() = nullptr;
   hipEvent_t gate_ev = nullptr;  // trace mode 3
   // stats
   uint64_t n_waits = 0, n_host_waits = 0, n_plans = 0;

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <dlfcn.h>
 #include <map>
 #include <memory>
 #include <new>
@@ -58,9 +59,10 @@ dag_status get_event(dag_ctx c, bool timing, hipEvent_t* out) {
 void recycle_retired(dag_ctx c) {
   if (c->cfg.trace || c->dry) return;
   for (uint64_t t : c->tmp_retired) {
-    if (t < c->ev.size() && c->ev[t]) {
-      c->free_ev.push_back(c->ev[t]);
-      c->ev[t] = nullptr;
+    const uint64_t k = t - c->ev_base;
+    if (k < c->ev.size() && c->ev[k]) {
+      c->free_ev.push_back(c->ev[k]);
+      c->ev[k] = nullptr;
     }
   }
 }
@@ -95,11 +97,12 @@ dag_status ensure_stream(dag_ctx c, int32_t s) {
 }
 
 void note_event_slot(dag_ctx c, uint64_t id) {
-  if (c->ev.size() <= id) {
-    c->ev.resize(id + 1, nullptr);
+  const uint64_t k = id - c->ev_base;
+  if (c->ev.size() <= k) {
+    c->ev.resize(k + 1, nullptr);
     if (c->cfg.trace) {
-      c->ev0.resize(id + 1, nullptr);
-      c->ev1.resize(id + 1, nullptr);
+      c->ev0.resize(k + 1, nullptr);
+      c->ev1.resize(k + 1, nullptr);
     }
   }
 }
@@ -133,9 +136,17 @@ dag_status gate_stream(dag_ctx c, int32_t s) {
 dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = false) {
   if (c->dry) return DAG_OK;
   const TaskRec& t = c->tr.task(id);
+  if (c->roctx_push) {
+    const KernelDesc* kd = t.kind == TK_KERNEL ? builtin_kernel(t.kernel_id) : nullptr;
+    const char* what = t.kind == TK_COPY ? "copy" : t.kind == TK_REGION ? "region" : kd ? kd->name : "user kernel";
+    char name[128];
+    std::snprintf(name, sizeof(name), "dagrt task %llu %s stream %d waits %u",
+                  static_cast<unsigned long long>(id), what, s, t.wait_n);
+    c->roctx_push(name);
+  }
   const uint64_t* w = c->tr.waits(id);
   for (uint32_t i = 0; i < t.wait_n; ++i) {
-    HIP_TRY(c, hipStreamWaitEvent(c->streams[s], c->ev[w[i]], 0));
+    HIP_TRY(c, hipStreamWaitEvent(c->streams[s], c->ev[w[i] - c->ev_base], 0));
   }
   c->n_waits += t.wait_n;
   note_event_slot(c, id);
@@ -147,12 +158,12 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
     hipEvent_t e0;
     dag_status st = get_event(c, true, &e0);
     if (st) return st;
-    c->ev0[id] = e0;
+    c->ev0[id - c->ev_base] = e0;
     if (dispatch_timed) {
       hipEvent_t e1;
       st = get_event(c, true, &e1);
       if (st) return st;
-      c->ev1[id] = e1;
+      c->ev1[id - c->ev_base] = e1;
       set_launch_events(e0, e1);
     } else {
       HIP_TRY(c, hipEventRecord(e0, c->streams[s]));
@@ -166,8 +177,9 @@ dag_status end_task(dag_ctx c, uint64_t id, int32_t s) {
   hipEvent_t e;
   dag_status st = get_event(c, traced(c, id), &e);
   if (st) return st;
-  c->ev[id] = e;
+  c->ev[id - c->ev_base] = e;
   HIP_TRY(c, hipEventRecord(e, c->streams[s]));
+  if (c->roctx_pop) c->roctx_pop();
   if (c->serial) HIP_TRY(c, hipStreamSynchronize(c->streams[s]));
   return DAG_OK;
 }
@@ -186,7 +198,7 @@ void add_access(std::vector<Access>* v, uint32_t slot, uint8_t acc) {
 dag_status host_wait(dag_ctx c) {
   if (c->dry) return DAG_OK;
   for (uint64_t w : c->tmp_wait) {
-    HIP_TRY(c, hipEventSynchronize(c->ev[w]));
+    HIP_TRY(c, hipEventSynchronize(c->ev[w - c->ev_base]));
     ++c->n_host_waits;
   }
   return DAG_OK;
@@ -490,6 +502,25 @@ dag_status diverge(dag_ctx c) {
   return DAG_OK;
 }
 
+// Once every task is retired, drop the tracker's per-task records (and the
+// event slots) if they have grown past kHistoryTasks, so a long-running
+// context keeps bounded host memory.  Not while tracing (the timing events
+// are the measurement) or inside a region (its recording refers to ids).
+constexpr uint64_t kHistoryTasks = 1u << 16;
+
+void maybe_compact(dag_ctx c) {
+  if (c->cfg.trace || c->in_region() || c->tr.num_active() != 0) return;
+  if (c->tr.last_id() + 1 - c->tr.first_kept() < kHistoryTasks) return;
+  for (hipEvent_t& e : c->ev)
+    if (e) {
+      c->free_ev.push_back(e);
+      e = nullptr;
+    }
+  c->tr.compact();
+  c->ev.clear();
+  c->ev_base = c->tr.base();
+}
+
 dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hdst, const void* hsrc,
                        size_t bytes, dag_task* out) {
   if (c->in_region()) return fail(c, DAG_E_BUSY, "host access inside a region");
@@ -515,6 +546,7 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
     c->tmp_retired.clear();
     c->tr.retire(id, &c->tmp_retired);
     recycle_retired(c);
+    maybe_compact(c);
     return DAG_OK;
   }
   dag_status st = host_wait(c);
@@ -522,6 +554,7 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
   c->tmp_retired.clear();
   c->tr.retire(id, &c->tmp_retired);
   recycle_retired(c);
+  maybe_compact(c);
   if (c->dry || bytes == 0) return DAG_OK;
   if (kind == TK_HOST_READ && hdst) {
     if (b->loc == DAG_PINNED_HOST) {
@@ -557,6 +590,7 @@ dag_status do_sync(dag_ctx c) {
   c->tmp_retired.clear();
   c->tr.retire_all(&c->tmp_retired);
   recycle_retired(c);
+  maybe_compact(c);
   return DAG_OK;
 }
 
@@ -776,6 +810,14 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   x->serial = c.policy == DAG_SERIAL_SYNC;
   x->dry = c.dry_run != 0;
   if (const char* f = std::getenv("DAGRT_FAULT_LAUNCH")) x->fault_at = std::strtoull(f, nullptr, 10);
+  if (const char* r = std::getenv("DAGRT_ROCTX"); r && std::atoi(r) > 0 && !x->dry) {
+    void* lib = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (lib) {
+      x->roctx_push = reinterpret_cast<int (*)(const char*)>(dlsym(lib, "roctxRangePushA"));
+      x->roctx_pop = reinterpret_cast<int (*)()>(dlsym(lib, "roctxRangePop"));
+      if (!x->roctx_push || !x->roctx_pop) x->roctx_push = nullptr, x->roctx_pop = nullptr;
+    }
+  }
   for (uint32_t k = 0; k < kNumBuiltin; ++k) {
     const KernelDesc* kd = builtin_kernel(k);
     if (kd) x->launch_cfg[k] = kd->def;
@@ -1331,7 +1373,7 @@ dag_status dag_edges(dag_ctx c, dag_edge* out, size_t cap, size_t* n) {
 
 dag_status dag_task_waits(dag_ctx c, dag_task t, dag_task* out, uint32_t cap, uint32_t* n) {
   if (!c || !n) return DAG_E_INVAL;
-  if (t == 0 || t > c->tr.last_id()) return fail(c, DAG_E_INVAL, "unknown task %llu", (unsigned long long)t);
+  if (!c->tr.known(t)) return fail(c, DAG_E_INVAL, "unknown task %llu (or its record was compacted)", (unsigned long long)t);
   const TaskRec& r = c->tr.task(t);
   *n = r.wait_n;
   const uint64_t* w = c->tr.waits(t);
@@ -1341,7 +1383,7 @@ dag_status dag_task_waits(dag_ctx c, dag_task t, dag_task* out, uint32_t cap, ui
 
 dag_status dag_task_get_info(dag_ctx c, dag_task t, dag_task_info* out) {
   if (!c || !out) return DAG_E_INVAL;
-  if (t == 0 || t > c->tr.last_id()) return fail(c, DAG_E_INVAL, "unknown task %llu", (unsigned long long)t);
+  if (!c->tr.known(t)) return fail(c, DAG_E_INVAL, "unknown task %llu (or its record was compacted)", (unsigned long long)t);
   const TaskRec& r = c->tr.task(t);
   out->kind = r.kind;
   out->stream = r.stream;
@@ -1353,11 +1395,12 @@ dag_status dag_task_get_info(dag_ctx c, dag_task t, dag_task_info* out) {
   out->reserved = 0;
   out->t_start_ms = -1.0;
   out->t_end_ms = -1.0;
-  if (c->cfg.trace && !c->dry && is_gpu_kind(r.kind) && t < c->ev.size() && c->ev[t] && c->ev0[t]) {
+  const uint64_t k = t - c->ev_base;  // trace contexts never compact: ev_base is 0
+  if (c->cfg.trace && !c->dry && is_gpu_kind(r.kind) && k < c->ev.size() && c->ev[k] && c->ev0[k]) {
     float a = 0.f, b = 0.f;
-    hipEvent_t end = (t < c->ev1.size() && c->ev1[t]) ? c->ev1[t] : c->ev[t];
-    hipError_t e = hipEventSynchronize(c->ev[t]);
-    if (e == hipSuccess) e = hipEventElapsedTime(&a, c->trace_ref, c->ev0[t]);
+    hipEvent_t end = (k < c->ev1.size() && c->ev1[k]) ? c->ev1[k] : c->ev[k];
+    hipError_t e = hipEventSynchronize(c->ev[k]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&a, c->trace_ref, c->ev0[k]);
     if (e == hipSuccess) e = hipEventElapsedTime(&b, c->trace_ref, end);
     if (e != hipSuccess) return hip_fail(c, e, "trace event query");
     out->t_start_ms = a;
@@ -1369,10 +1412,8 @@ dag_status dag_task_get_info(dag_ctx c, dag_task t, dag_task_info* out) {
 dag_status dag_get_stats(dag_ctx c, dag_stats* out) {
   if (!c || !out) return DAG_E_INVAL;
   out->tasks = c->tr.last_id();
-  uint64_t v = 0;
-  for (uint64_t t = 1; t <= c->tr.last_id(); ++t) v += c->tr.task(t).vertex ? 1 : 0;
-  out->vertices = v;
-  out->edges = c->tr.edges().size();
+  out->vertices = c->tr.vertices_total();
+  out->edges = c->tr.edges_total();
   out->waits = c->n_waits;
   out->host_waits = c->n_host_waits;
   out->streams = c->tr.num_streams();

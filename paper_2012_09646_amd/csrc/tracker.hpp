@@ -100,14 +100,43 @@ class Tracker {
     tasks_.emplace_back();  // id 0 = none
   }
 
-  uint64_t last_id() const { return tasks_.size() - 1; }
-  const TaskRec& task(uint64_t id) const { return tasks_[id]; }
+  // Ids below base_ were dropped by compact(); tasks_[k] is task base_ + k.
+  uint64_t last_id() const { return base_ + tasks_.size() - 1; }
+  uint64_t first_kept() const { return base_ == 0 ? 1 : base_; }
+  bool known(uint64_t id) const { return id >= first_kept() && id <= last_id(); }
+  uint64_t base() const { return base_; }
+  const TaskRec& task(uint64_t id) const { return tasks_[id - base_]; }
+  uint64_t vertices_total() const {
+    uint64_t v = dropped_vertices_;
+    for (const TaskRec& t : tasks_) v += t.vertex ? 1 : 0;
+    return v;
+  }
+  uint64_t edges_total() const { return dropped_edges_ + edges_.size(); }
   uint32_t num_streams() const { return static_cast<uint32_t>(streams_.size()); }
   bool is_lane(int32_t s) const { return s >= 0 && streams_[s].lane != 0; }
   uint64_t num_active() const { return nactive_total_; }
   const std::vector<EdgeRec>& edges() const { return edges_; }
-  const uint64_t* parents(uint64_t id) const { return par_pool_.data() + tasks_[id].par_off; }
-  const uint64_t* waits(uint64_t id) const { return wait_pool_.data() + tasks_[id].wait_off; }
+  const uint64_t* parents(uint64_t id) const { return par_pool_.data() + task(id).par_off; }
+  const uint64_t* waits(uint64_t id) const { return wait_pool_.data() + task(id).wait_off; }
+
+  // Drop the records of every task so far (ids stay monotonic): allowed only
+  // when no task is active, so none of them can produce an edge or a wait
+  // again.  The per-buffer W/R sets are cleared (their tasks are all
+  // retired, which yields the same future edges as an empty set).  Edges and
+  // task records queried later cover the tasks after this point only.
+  void compact() {
+    if (nactive_total_ != 0) return;
+    for (const TaskRec& t : tasks_) dropped_vertices_ += t.vertex ? 1 : 0;
+    dropped_edges_ += edges_.size();
+    base_ = last_id() + 1;
+    tasks_.clear();
+    par_pool_.clear();
+    wait_pool_.clear();
+    vc_pool_.clear();
+    edges_.clear();
+    active_list_.clear();
+    for (BufTrack& b : bufs_) b = BufTrack();
+  }
 
   void ensure_buffer(uint32_t slot) {
     if (slot >= bufs_.size()) bufs_.resize(slot + 1);
@@ -123,8 +152,8 @@ class Tracker {
     const BufTrack& b = bufs_[slot];
     if (acc == ACC_W && b.read_since_write) {
       for (uint64_t r : b.R)
-        if (tasks_[r].active) out->push_back(r);
-    } else if (b.W && tasks_[b.W].active) {
+        if (T(r).active) out->push_back(r);
+    } else if (b.W && T(b.W).active) {
       out->push_back(b.W);
     }
   }
@@ -138,7 +167,7 @@ class Tracker {
   // direction's lanes (FIFO streams outside the pool).
   uint64_t add_gpu(uint8_t kind, uint32_t kernel_id, const Access* accs, uint32_t n,
                    bool serial, int32_t* stream_out, bool* new_stream_out, uint8_t lane = 0) {
-    const uint64_t id = tasks_.size();
+    const uint64_t id = base_ + tasks_.size();
     tasks_.emplace_back();
     TaskRec& t = tasks_.back();
     t.kind = kind;
@@ -151,7 +180,7 @@ class Tracker {
     }
     std::sort(tmp_par_.begin(), tmp_par_.end());
     tmp_par_.erase(std::unique(tmp_par_.begin(), tmp_par_.end()), tmp_par_.end());
-    TaskRec& tt = tasks_[id];
+    TaskRec& tt = T(id);
     tt.par_off = static_cast<uint32_t>(par_pool_.size());
     tt.par_n = static_cast<uint32_t>(tmp_par_.size());
     par_pool_.insert(par_pool_.end(), tmp_par_.begin(), tmp_par_.end());
@@ -169,7 +198,7 @@ class Tracker {
   // (empty: not a vertex).  After waiting, the caller calls retire(id).
   uint64_t add_host(uint8_t kind, uint32_t slot, uint8_t acc, bool serial,
                     std::vector<uint64_t>* wait_on) {
-    const uint64_t id = tasks_.size();
+    const uint64_t id = base_ + tasks_.size();
     tasks_.emplace_back();
     tasks_.back().kind = kind;
     tmp_par_.clear();
@@ -187,7 +216,7 @@ class Tracker {
     }
     std::sort(tmp_par_.begin(), tmp_par_.end());
     tmp_par_.erase(std::unique(tmp_par_.begin(), tmp_par_.end()), tmp_par_.end());
-    TaskRec& t = tasks_[id];
+    TaskRec& t = T(id);
     t.vertex = !tmp_par_.empty();
     t.par_off = static_cast<uint32_t>(par_pool_.size());
     t.par_n = static_cast<uint32_t>(tmp_par_.size());
@@ -197,7 +226,7 @@ class Tracker {
   }
 
   uint64_t add_sync() {
-    const uint64_t id = tasks_.size();
+    const uint64_t id = base_ + tasks_.size();
     tasks_.emplace_back();
     tasks_.back().kind = TK_SYNC;
     return id;
@@ -206,7 +235,7 @@ class Tracker {
   // Retire the parents of host access `id` and all their ancestors.
   // Retired tasks are appended to *retired (may be null).
   void retire(uint64_t id, std::vector<uint64_t>* retired) {
-    stack_.assign(parents(id), parents(id) + tasks_[id].par_n);
+    stack_.assign(parents(id), parents(id) + task(id).par_n);
     retire_stack(retired);
   }
 
@@ -214,12 +243,15 @@ class Tracker {
   void retire_all(std::vector<uint64_t>* retired) {
     stack_.clear();
     for (uint64_t t : active_list_)
-      if (tasks_[t].active) stack_.push_back(t);
+      if (T(t).active) stack_.push_back(t);
     retire_stack(retired);
     active_list_.clear();
   }
 
  private:
+  TaskRec& T(uint64_t id) { return tasks_[id - base_]; }
+  const TaskRec& T(uint64_t id) const { return tasks_[id - base_]; }
+
   void add_edge(uint64_t src, uint64_t dst, uint32_t slot, uint32_t kind,
                 std::vector<uint64_t>* par) {
     edges_.push_back(EdgeRec{src, dst, slot, kind});
@@ -231,11 +263,11 @@ class Tracker {
     if (a.acc == ACC_W) {
       if (b.read_since_write) {
         for (uint64_t r : b.R)
-          if (tasks_[r].active) add_edge(r, id, a.buf, 1u, par);
-      } else if (b.W && tasks_[b.W].active) {
+          if (T(r).active) add_edge(r, id, a.buf, 1u, par);
+      } else if (b.W && T(b.W).active) {
         add_edge(b.W, id, a.buf, 2u, par);
       }
-    } else if (b.W && tasks_[b.W].active) {
+    } else if (b.W && T(b.W).active) {
       add_edge(b.W, id, a.buf, 0u, par);
     }
   }
@@ -250,7 +282,7 @@ class Tracker {
       if (b.R.size() >= 32) {
         size_t k = 0;
         for (uint64_t r : b.R)
-          if (tasks_[r].active) b.R[k++] = r;
+          if (T(r).active) b.R[k++] = r;
         b.R.resize(k);
       }
       b.R.push_back(id);
@@ -287,7 +319,7 @@ class Tracker {
     const uint64_t* par = par_pool_.data() + tasks_.back().par_off;
     const uint32_t np = tasks_.back().par_n;
     for (uint32_t i = 0; i < np; ++i) {
-      const int32_t s = tasks_[par[i]].stream;
+      const int32_t s = T(par[i]).stream;
       if (streams_[s].lane) continue;  // calls never join a copy lane
       if (streams_[s].tail == par[i]) {
         chosen = s;
@@ -318,15 +350,15 @@ class Tracker {
     if (st.vc.size() < ns) st.vc.resize(ns, 0);
     // event waits: newest parent per other stream, newest first, skipping
     // those already ordered before this point
-    TaskRec& t = tasks_[id];
+    TaskRec& t = T(id);
     const uint64_t* par = par_pool_.data() + t.par_off;
     cand_.clear();
     for (uint32_t i = 0; i < t.par_n; ++i) {
-      const TaskRec& p = tasks_[par[i]];
+      const TaskRec& p = T(par[i]);
       if (p.stream == s) continue;
       bool replaced = false;
       for (uint64_t& c : cand_) {
-        if (tasks_[c].stream == p.stream) {
+        if (T(c).stream == p.stream) {
           if (par[i] > c) c = par[i];
           replaced = true;
           break;
@@ -338,7 +370,7 @@ class Tracker {
     t.wait_off = static_cast<uint32_t>(wait_pool_.size());
     t.wait_n = 0;
     for (uint64_t c : cand_) {
-      const TaskRec& p = tasks_[c];
+      const TaskRec& p = T(c);
       if (st.vc[p.stream] >= p.pos) continue;
       wait_pool_.push_back(c);
       ++t.wait_n;
@@ -360,7 +392,7 @@ class Tracker {
     if (active_list_.size() > 64 && active_list_.size() > 2 * nactive_total_) {
       size_t k = 0;
       for (uint64_t a : active_list_)
-        if (tasks_[a].active) active_list_[k++] = a;
+        if (T(a).active) active_list_[k++] = a;
       active_list_.resize(k);
     }
   }
@@ -370,7 +402,7 @@ class Tracker {
     while (!stack_.empty()) {
       const uint64_t x = stack_.back();
       stack_.pop_back();
-      TaskRec& t = tasks_[x];
+      TaskRec& t = T(x);
       if (!t.active) continue;
       t.active = false;
       --nactive_total_;
@@ -403,6 +435,8 @@ class Tracker {
   std::vector<uint32_t> vc_pool_;
   std::vector<uint64_t> active_list_;
   uint64_t nactive_total_ = 0;
+  uint64_t base_ = 0;
+  uint64_t dropped_vertices_ = 0, dropped_edges_ = 0;
   std::vector<uint64_t> tmp_par_, cand_, stack_;
   std::vector<int32_t> empties_;
 };

@@ -12,6 +12,7 @@ import json
 import os
 
 from . import dagrt as D
+from . import metrics as M
 from . import runner
 from . import tune
 from . import workloads as W
@@ -29,17 +30,37 @@ def main():
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2012_09646_amd", "tuning", "gfx950.json"))
     ap.add_argument("--set", action="append", default=[], metavar="KERNEL=BLOCK,CAP,VARIANT",
                     help="launch configuration override after the tuning file (repeatable)")
+    ap.add_argument("--trace", type=int, default=0, choices=[0, 1],
+                    help="1: timing events on every task; the library's overlap figures of each run are printed "
+                         "(to compare with a profiler timeline of the same runs)")
+    ap.add_argument("--copy-engine", type=int, default=0, choices=[0, 1, 2, 3])
+    ap.add_argument("--max-streams", type=int, default=8)
     args = ap.parse_args()
     prog, _ = tune.workload_program(args.workload)
-    ctx = D.Context(policy=D.DAG_SERIAL_SYNC if args.serial else D.DAG_PARALLEL_ASYNC)
+    ctx = D.Context(policy=D.DAG_SERIAL_SYNC if args.serial else D.DAG_PARALLEL_ASYNC, trace=args.trace,
+                    copy_engine=args.copy_engine, max_streams=args.max_streams)
     if args.tuned and os.path.exists(args.tuned):
         tune.apply_kernels(ctx, tune.load(args.tuned).get("kernels", {}))
     for item in args.set:
         name, cfg = item.split("=")
         ctx.set_launch(name, *[int(v) for v in cfg.split(",")])
     b = runner.Bound(ctx, prog, read_bytes=4)
+    lib_overlap = []
     for _ in range(args.runs):
+        if args.trace:
+            D.dag_trace_reset(ctx.h)
         b.run()
+        if args.trace:
+            iv = []
+            for pos in range(1, len(prog.ops) + 1):
+                inf = ctx.info(b.base + pos)
+                if inf.stream < 0 or inf.t_start_ms < 0:
+                    continue
+                kind = "C" if inf.kind in (D.DAG_TASK_KERNEL, D.DAG_TASK_REGION) else "T"
+                iv.append((kind, inf.t_start_ms, inf.t_end_ms))
+            o = M.overlap(iv)
+            o["span_ms"] = max(e for _, _, e in iv) - min(s0 for _, s0, _ in iv)
+            lib_overlap.append(o)
     ctx.sync()
     n = args.copy_mib << 18  # fp32 elements
     src = ctx.alloc(4 * n)
@@ -49,7 +70,8 @@ def main():
     ctx.sync()
     ctx.close()
     print(json.dumps({"workload": args.workload, "runs": args.runs, "set": args.set, "copy_f32_bytes_read": 4 * n,
-                      "copy_f32_bytes_written": 4 * n, "copies": args.copies}), flush=True)
+                      "copy_f32_bytes_written": 4 * n, "copies": args.copies, "library_overlap": lib_overlap}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -69,3 +69,33 @@ def test_dependency_gaps_take_the_last_parent_and_split_by_stream():
     assert g == {"same": [0.5], "cross": [2.0]}
     # untimed tasks (host reads) are ignored
     assert M.dependency_gaps({(1, 5)}, streams, times) == {"same": [], "cross": []}
+
+
+def test_trace_overlap_reads_a_rocprofv3_timeline(tmp_path):
+    """The timeline reader behind the profile cross-check of the overlap
+    figures: kernels by name, copy kernels and memory copies as transfers,
+    runs split at the largest gaps between the library's task ranges."""
+    import csv
+    from paper_2012_09646_amd import trace_overlap as TO
+    k = [("k_bs_call<2>", 100, 200), ("k_copy_bytes", 150, 300), ("other", 0, 1000), ("k_bs_call<2>", 2100, 2200)]
+    with open(tmp_path / "p_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writerows(k)
+    with open(tmp_path / "p_memory_copy_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Start_Timestamp", "End_Timestamp"])
+        w.writerow([50, 120])
+        w.writerow([2000, 2150])
+    with open(tmp_path / "p_marker_api_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Function", "Start_Timestamp", "End_Timestamp"])
+        w.writerows([("dagrt task 1 copy stream 1 waits 0", 40, 45), ("dagrt task 2 bs_call stream 0 waits 1", 46, 50),
+                     ("dagrt task 7 copy stream 1 waits 0", 1990, 1995)])
+    ivs = TO.intervals(str(tmp_path), ["bs_call"], ["k_copy_bytes"])
+    assert ivs == [("T", 50, 120), ("C", 100, 200), ("T", 150, 300), ("T", 2000, 2150), ("C", 2100, 2200)]
+    runs = TO.split_runs(ivs, TO.task_ranges(str(tmp_path)), 2)
+    assert [len(r) for r in runs] == [3, 2]
+    o = M.overlap([(kind, a, b) for kind, a, b in runs[0]])
+    # the kernel [100, 200) is covered by transfers on [100, 120) and [150, 200)
+    assert abs(o["CT"] - 0.7) < 1e-12

@@ -483,3 +483,27 @@ def test_dl_kernel_argument_checks():
     assert _status(ctx.set_launch, "conv3x3_relu_pool", 256, 64, 1) == "DAG_E_INVAL"
     assert _status(ctx.set_launch, "siamese_combine", 128) == "DAG_E_INVAL"
     ctx.close()
+
+
+def test_history_is_compacted_once_everything_is_retired():
+    """A context that has run more than 65,536 tasks drops the per-task
+    records at the next point where every task is retired: ids stay
+    monotonic, the totals in the statistics keep counting, the dropped ids
+    are unknown to the introspection calls, and the DAG of a program run
+    afterwards is still the oracle's edge for edge."""
+    prog = W.vec_program(n=1024, seed=0)
+    ctx = D.Context(dry_run=True)
+    b = runner.Bound(ctx, prog)
+    st0 = ctx.stats()  # the uploads are host writes
+    runs = (1 << 16) // len(prog.ops) + 2
+    for _ in range(runs):
+        b.run()
+    st = ctx.stats()
+    assert st.tasks - st0.tasks == runs * len(prog.ops)
+    assert st.edges - st0.edges == runs * 3 and st.vertices - st0.vertices == runs * len(prog.ops)
+    assert _status(ctx.info, st0.tasks + 5) == "DAG_E_INVAL"  # compacted
+    b.run()
+    g = odag.build_dag(prog.ops)
+    assert b.edges() == g.edges
+    assert ctx.stats().tasks - st0.tasks == (runs + 1) * len(prog.ops)
+    ctx.close()
