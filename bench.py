@@ -720,10 +720,51 @@ def main():
         ctx.close()
         same = (out["same_stream"] - gate) / calls
         cross = (out["cross_stream"] - gate) / calls
-        return {"calls": calls, "same_stream_us_per_call": round(same, 3),
-                "cross_stream_us_per_call": round(cross, 3), "cross_edge_extra_us": round(cross - same, 3),
-                "method": "2 ms delay kernel, then a %d-call dependent chain of 4 KiB squares replayed from a "
-                          "recorded region; (replay time - delay alone) / calls, median of %d" % (calls, reps)}
+        res = {"calls": calls, "same_stream_us_per_call": round(same, 3),
+               "cross_stream_us_per_call": round(cross, 3), "cross_edge_extra_us": round(cross - same, 3),
+               "method": "2 ms delay kernel, then a %d-call dependent chain of 4 KiB squares replayed from a "
+                         "recorded region (event waits); (replay time - delay alone) / calls, median of %d"
+                         % (calls, reps)}
+        # The scheduler's own placement: after the delay, tiny kernels (zero
+        # delays) over four rotating buffers; calls 0 and 1 each write one,
+        # and from then on call k reads the outputs of calls k-1 and k-2 and
+        # overwrites that of k-4.  Its parents are
+        # k-3, k-2 and k-1; it joins the stream of k-2 (the oldest parent
+        # that is still the last call on its stream) and waits for k-1 on the
+        # other: every call is a cross-stream edge with max_streams=2, and
+        # with max_streams=1 the same calls run in stream order.
+        xs = {"o%d" % i: W.Buf(4 * n, init=ones) for i in range(4)}
+        eops = [W.K("spin", [("o%d" % i, "m") for i in range(4)], ns=gate_ns),
+                W.K("spin", [("o0", "m")], ns=0), W.K("spin", [("o1", "m")], ns=0)]
+        for k in range(2, calls):
+            eops.append(W.K("spin", [("o%d" % ((k - 1) % 4), "c"), ("o%d" % ((k - 2) % 4), "c"),
+                                     ("o%d" % (k % 4), "m")], ns=0))
+        eprog = W.Program("alternating", xs, eops, list(xs))
+        for mode, label in ((D.DAG_WAIT_SIGNALS, "signals"), (D.DAG_WAIT_EVENTS, "events")):
+            per = {}
+            for ms in (1, 2):
+                cx = D.Context(max_streams=ms, wait_mode=mode)
+                tune.apply_kernels(cx, tuned)
+                be = runner.Bound(cx, eprog, read_bytes=4)
+                ts = []
+                for _ in range(reps + 2):
+                    t0 = time.perf_counter()
+                    be.run()
+                    cx.sync()
+                    ts.append((time.perf_counter() - t0) * 1e6)
+                st = cx.stats()
+                cx.close()
+                per[ms] = (statistics.median(ts[2:]) - gate) / calls
+                if ms == 2:
+                    assert st.streams == 2 and st.waits >= calls - 1, (st.streams, st.waits)
+            res["eager_%s" % label] = {"same_stream_us_per_call": round(per[1], 3),
+                                       "cross_stream_us_per_call": round(per[2], 3),
+                                       "cross_edge_extra_us": round(per[2] - per[1], 3)}
+        res["eager_method"] = ("2 ms delay kernel, then %d zero-delay kernels submitted as one batch that "
+                               "alternate between two streams, each waiting for the previous one "
+                               "(max_streams=2), against the same calls on one stream (max_streams=1); "
+                               "(run time - delay alone) / calls, median of %d, per wait mode" % (calls, reps))
+        return res
 
     def measure_serving(graphs):
         """Open-loop serving of the mixed trace, concurrent and serial."""

@@ -156,8 +156,29 @@ typedef struct {
                              kernel; 3 = the reverse.  With 2 and 3 the two
                              directions never share an SDMA engine.
                              Device-to-device copies always use HIP. */
-  uint32_t reserved;
+  uint32_t wait_mode;     /* how a task on one stream waits for a parent on
+                             another (the event waits of Sec. IV-B):
+                             DAG_WAIT_SIGNALS (0) = the parent's stream raises
+                             a per-stream counter in device memory with a
+                             one-wave kernel queued after it, and the child's
+                             stream is held by a one-wave kernel that polls
+                             the counter (about 2 us per edge against about
+                             12 us for a HIP event wait; tasks on the CUs
+                             only, SDMA copies still end with an event; a
+                             poll that has not seen its value after 10 s
+                             gives up, and the next host wait or sync of the
+                             context then fails with DAG_E_HIP and poisons
+                             it); DAG_WAIT_EVENTS (1) = a HIP event recorded
+                             after every task and hipStreamWaitEvent.  The
+                             serial policy uses neither.  The environment
+                             variable DAGRT_SIGNAL_TIMEOUT_MS, read at
+                             dag_create, lowers the 10 s bound (tests of the
+                             failure path). */
 } dag_config;
+
+/* dag_config.wait_mode */
+#define DAG_WAIT_SIGNALS 0u
+#define DAG_WAIT_EVENTS 1u
 
 /* One argument of a call: a buffer and its access mode. */
 typedef struct {
@@ -194,7 +215,8 @@ typedef struct {
   uint64_t tasks;        /* ids handed out */
   uint64_t vertices;     /* tasks that are DAG vertices */
   uint64_t edges;        /* edge records (per buffer) */
-  uint64_t waits;        /* hipStreamWaitEvent calls placed */
+  uint64_t waits;        /* cross-stream waits placed (event waits and
+                            signal polls) */
   uint64_t host_waits;   /* host blocking waits */
   uint32_t streams;      /* streams created so far */
   uint32_t active;       /* currently active tasks */
@@ -205,6 +227,9 @@ typedef struct {
                             whose row-pointer buffer was not written since
                             its partition was computed (same sizes) reuses
                             it */
+  uint64_t signals;      /* completion signals raised (wait mode 0) */
+  uint64_t signal_waits; /* of `waits`, those placed as device-side polls of
+                            a signal rather than event waits */
 } dag_stats;
 
 /* ---- context ------------------------------------------------------------

@@ -83,6 +83,10 @@ struct Region {
 };
 
 constexpr uint32_t kMaxArgs = 16;
+// Wait mode 0: signal words (streams with a larger index end their tasks
+// with events) and the longest a device-side wait polls before giving up.
+constexpr uint32_t kSignalSlots = 128;
+constexpr uint64_t kSignalTimeoutMs = 10000;
 constexpr size_t kStagingBytes = 64 << 10;
 
 }  // namespace dagrt
@@ -105,6 +109,19 @@ struct dag_ctx_s {
   hipEvent_t read_ev = nullptr;
   std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion; ev[id - ev_base]
   uint64_t ev_base = 0;                   // first task id of ev (records before it were compacted)
+  // Wait mode 0: completion signals between streams (kernels.hpp).  sig_dev
+  // holds one word per stream; sig_next[s] is the last value raised on
+  // stream s; tsig[id - ev_base] is task id's value on its stream (0: the
+  // task has an event instead); mark_ev[s] is recorded on stream s when the
+  // host must wait for a signalled task of it.
+  bool signals = false;
+  uint64_t* sig_dev = nullptr;
+  uint32_t* sig_timed_out = nullptr;      // pinned host word raised by a wait that gave up
+  std::vector<uint64_t> sig_next;
+  std::vector<uint64_t> tsig;
+  std::vector<hipEvent_t> mark_ev;
+  uint64_t n_signals = 0, n_signal_waits = 0;
+  uint64_t sig_timeout_ms = dagrt::kSignalTimeoutMs;  // DAGRT_SIGNAL_TIMEOUT_MS overrides (tests)
   std::vector<hipEvent_t> ev0;            // per task, start (trace mode)
   std::vector<hipEvent_t> ev1;            // per task, kernel end (trace mode 2, built-in kernels)
   std::vector<hipEvent_t> free_ev;

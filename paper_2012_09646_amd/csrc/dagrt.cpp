@@ -71,11 +71,16 @@ void recycle_retired(dag_ctx c) {
 
 hipError_t new_stream(dag_ctx, hipStream_t* st) { return hipStreamCreateWithFlags(st, hipStreamNonBlocking); }
 
-hipError_t copy_async(dag_ctx c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+// Host<->device copies that the configured copy engine runs as a kernel on
+// the CUs rather than on an SDMA engine.
+bool copy_runs_as_kernel(dag_ctx c, hipMemcpyKind kind) {
   const uint32_t e = c->cfg.copy_engine;
-  const bool by_kernel = (kind == hipMemcpyHostToDevice && (e == 1 || e == 3)) ||
-                         (kind == hipMemcpyDeviceToHost && (e == 1 || e == 2));
-  if (by_kernel) return copy_by_kernel(s, dst, src, bytes);
+  return (kind == hipMemcpyHostToDevice && (e == 1 || e == 3)) ||
+         (kind == hipMemcpyDeviceToHost && (e == 1 || e == 2));
+}
+
+hipError_t copy_async(dag_ctx c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+  if (copy_runs_as_kernel(c, kind)) return copy_by_kernel(s, dst, src, bytes);
   return hipMemcpyAsync(dst, src, bytes, kind, s);
 }
 
@@ -92,6 +97,8 @@ dag_status ensure_stream(dag_ctx c, int32_t s) {
     HIP_TRY(c, hipStreamSynchronize(st));
     c->streams.push_back(st);
     c->scratch.push_back(scr);
+    c->sig_next.push_back(0);
+    c->mark_ev.push_back(nullptr);
   }
   return DAG_OK;
 }
@@ -100,6 +107,7 @@ void note_event_slot(dag_ctx c, uint64_t id) {
   const uint64_t k = id - c->ev_base;
   if (c->ev.size() <= k) {
     c->ev.resize(k + 1, nullptr);
+    c->tsig.resize(k + 1, 0);
     if (c->cfg.trace) {
       c->ev0.resize(k + 1, nullptr);
       c->ev1.resize(k + 1, nullptr);
@@ -145,9 +153,25 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
     c->roctx_push(name);
   }
   const uint64_t* w = c->tr.waits(id);
+  SignalWaits sw{};
+  sw.words = c->sig_dev;
+  sw.timed_out = c->sig_timed_out;
+  sw.max_ticks = c->sig_timeout_ms * wall_clock_ticks_per_ms();
   for (uint32_t i = 0; i < t.wait_n; ++i) {
-    HIP_TRY(c, hipStreamWaitEvent(c->streams[s], c->ev[w[i] - c->ev_base], 0));
+    const uint64_t k = w[i] - c->ev_base;
+    if (c->signals && c->tsig[k]) {
+      sw.slot[sw.n] = static_cast<uint32_t>(c->tr.task(w[i]).stream);
+      sw.value[sw.n] = c->tsig[k];
+      ++c->n_signal_waits;
+      if (++sw.n == kMaxSignalWaits) {
+        HIP_TRY(c, signal_wait(c->streams[s], sw));
+        sw.n = 0;
+      }
+    } else {
+      HIP_TRY(c, hipStreamWaitEvent(c->streams[s], c->ev[k], 0));
+    }
   }
+  HIP_TRY(c, signal_wait(c->streams[s], sw));
   c->n_waits += t.wait_n;
   note_event_slot(c, id);
   if (c->cfg.trace == 3) {
@@ -172,13 +196,26 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
   return DAG_OK;
 }
 
-dag_status end_task(dag_ctx c, uint64_t id, int32_t s) {
+// A task ends with a completion signal when signals are on and the task ran
+// on the CUs (kernels, region replays, copies by the copy kernel): the signal
+// kernel then follows it on the same engine.  SDMA copies end with an event.
+// Traced tasks also get their timing event.
+dag_status end_task(dag_ctx c, uint64_t id, int32_t s, bool on_cus) {
   if (c->dry) return DAG_OK;
-  hipEvent_t e;
-  dag_status st = get_event(c, traced(c, id), &e);
-  if (st) return st;
-  c->ev[id - c->ev_base] = e;
-  HIP_TRY(c, hipEventRecord(e, c->streams[s]));
+  const uint64_t k = id - c->ev_base;
+  const bool sig = c->signals && on_cus && static_cast<uint32_t>(s) < kSignalSlots;
+  if (sig) {
+    HIP_TRY(c, signal_raise(c->streams[s], c->sig_dev + static_cast<uint64_t>(s) * kSignalStride, ++c->sig_next[s]));
+    c->tsig[k] = c->sig_next[s];
+    ++c->n_signals;
+  }
+  if (!sig || traced(c, id)) {
+    hipEvent_t e;
+    dag_status st = get_event(c, traced(c, id), &e);
+    if (st) return st;
+    c->ev[k] = e;
+    HIP_TRY(c, hipEventRecord(e, c->streams[s]));
+  }
   if (c->roctx_pop) c->roctx_pop();
   if (c->serial) HIP_TRY(c, hipStreamSynchronize(c->streams[s]));
   return DAG_OK;
@@ -195,13 +232,37 @@ void add_access(std::vector<Access>* v, uint32_t slot, uint8_t acc) {
   v->push_back(Access{slot, acc});
 }
 
+// A wait of the device that gave up (wait mode 0) leaves its consumer run
+// without the dependency: the context is poisoned.
+dag_status check_signal_timeout(dag_ctx c) {
+  if (!c->sig_timed_out || __atomic_load_n(c->sig_timed_out, __ATOMIC_ACQUIRE) == 0) return DAG_OK;
+  c->poisoned = true;
+  return fail(c, DAG_E_HIP, "a cross-stream wait on the device gave up after %llu ms",
+              static_cast<unsigned long long>(c->sig_timeout_ms));
+}
+
+// The host waits for tmp_wait: a task with an event by that event; a
+// signalled task by a marker recorded now on its stream, once per stream
+// (which also waits for what was queued there after the task).
 dag_status host_wait(dag_ctx c) {
   if (c->dry) return DAG_OK;
+  uint64_t marked = 0;  // streams < 64 marked in this call
   for (uint64_t w : c->tmp_wait) {
-    HIP_TRY(c, hipEventSynchronize(c->ev[w - c->ev_base]));
+    const uint64_t k = w - c->ev_base;
+    if (c->ev[k]) {
+      HIP_TRY(c, hipEventSynchronize(c->ev[k]));
+      ++c->n_host_waits;
+      continue;
+    }
+    const int32_t s = c->tr.task(w).stream;
+    if (s < 64 && (marked >> s) & 1u) continue;
+    if (s < 64) marked |= uint64_t(1) << s;
+    if (!c->mark_ev[s]) HIP_TRY(c, hipEventCreateWithFlags(&c->mark_ev[s], hipEventDisableTiming));
+    HIP_TRY(c, hipEventRecord(c->mark_ev[s], c->streams[s]));
+    HIP_TRY(c, hipEventSynchronize(c->mark_ev[s]));
     ++c->n_host_waits;
   }
-  return DAG_OK;
+  return check_signal_timeout(c);
 }
 
 // A write to a buffer invalidates the SpMV partition derived from it.
@@ -384,7 +445,7 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
     }
   }
   note_written(c, c->tmp_acc);
-  st = end_task(c, id, s);
+  st = end_task(c, id, s, true);
   c->launch_us += us_since(t1);
   if (st) return st;
   if (c->recording) {
@@ -455,7 +516,7 @@ dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t 
   const void* sp = static_cast<const char*>(bs->ptr) + soff;
   if (!c->dry) HIP_TRY(c, copy_async(c, dp, sp, bytes, kind, c->streams[s]));
   note_written(c, c->tmp_acc);
-  st = end_task(c, id, s);
+  st = end_task(c, id, s, copy_runs_as_kernel(c, kind));
   c->launch_us += us_since(t1);
   if (st) return st;
   if (c->recording) {
@@ -518,6 +579,7 @@ void maybe_compact(dag_ctx c) {
     }
   c->tr.compact();
   c->ev.clear();
+  c->tsig.clear();
   c->ev_base = c->tr.base();
 }
 
@@ -542,6 +604,8 @@ dag_status host_access(dag_ctx c, uint8_t kind, dag_buf h, size_t off, void* hds
     HIP_TRY(c, hipEventRecord(c->read_ev, ws));
     HIP_TRY(c, hipEventSynchronize(c->read_ev));
     ++c->n_host_waits;
+    dag_status ts = check_signal_timeout(c);
+    if (ts) return ts;
     std::memcpy(hdst, c->staging, bytes);
     c->tmp_retired.clear();
     c->tr.retire(id, &c->tmp_retired);
@@ -586,6 +650,8 @@ dag_status do_sync(dag_ctx c) {
     for (hipStream_t s : c->aux) HIP_TRY(c, hipStreamSynchronize(s));
     for (void* p : c->dead_plans) HIP_TRY(c, hipFree(p));
     c->dead_plans.clear();
+    dag_status ts = check_signal_timeout(c);
+    if (ts) return ts;
   }
   c->tmp_retired.clear();
   c->tr.retire_all(&c->tmp_retired);
@@ -796,7 +862,8 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   if (cfg) c = *cfg;
   if (c.max_streams == 0) c.max_streams = 8;
   if (c.policy > DAG_PARALLEL_ASYNC || c.max_streams > DAG_MAX_STREAMS || c.graph_mode > 2 ||
-      c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1 || c.copy_engine > 3 || c.reserved)
+      c.trace > 3 || c.copy_streams > 1 || c.copy_lanes > 4 || c.own_queues > 1 || c.copy_engine > 3 ||
+      c.wait_mode > DAG_WAIT_EVENTS)
     return DAG_E_INVAL;
   // One hardware queue per stream (CU-masked streams) hung in testing with no
   // cause found in this library, so the mode is refused.
@@ -810,6 +877,8 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
   x->serial = c.policy == DAG_SERIAL_SYNC;
   x->dry = c.dry_run != 0;
   if (const char* f = std::getenv("DAGRT_FAULT_LAUNCH")) x->fault_at = std::strtoull(f, nullptr, 10);
+  if (const char* f = std::getenv("DAGRT_SIGNAL_TIMEOUT_MS"))
+    x->sig_timeout_ms = std::min<uint64_t>(std::strtoull(f, nullptr, 10), kSignalTimeoutMs);
   if (const char* r = std::getenv("DAGRT_ROCTX"); r && std::atoi(r) > 0 && !x->dry) {
     void* lib = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
     if (lib) {
@@ -835,6 +904,16 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device);
     if (e == hipSuccess) set_wall_clock_khz(static_cast<uint64_t>(khz));
     if (e == hipSuccess && c.trace == 3) e = hipEventCreateWithFlags(&x->gate_ev, hipEventDisableTiming);
+    if (e == hipSuccess && c.wait_mode == DAG_WAIT_SIGNALS && !x->serial) {
+      const size_t words = size_t(kSignalSlots) * kSignalStride;
+      e = hipMalloc(&x->sig_dev, words * sizeof(uint64_t));
+      if (e == hipSuccess) e = hipMemset(x->sig_dev, 0, words * sizeof(uint64_t));
+      if (e == hipSuccess) e = hipHostMalloc(&x->sig_timed_out, sizeof(uint32_t), hipHostMallocDefault);
+      if (e == hipSuccess) {
+        *x->sig_timed_out = 0;
+        x->signals = true;
+      }
+    }
     if (e == hipSuccess && c.trace) {
       e = hipEventCreate(&x->trace_ref);
       if (e == hipSuccess) e = hipEventRecord(x->trace_ref, x->io);
@@ -844,6 +923,8 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
       if (x->io) (void)hipStreamDestroy(x->io);
       if (x->staging) (void)hipHostFree(x->staging);
       if (x->read_ev) (void)hipEventDestroy(x->read_ev);
+      if (x->sig_dev) (void)hipFree(x->sig_dev);
+      if (x->sig_timed_out) (void)hipHostFree(x->sig_timed_out);
       delete x;
       return DAG_E_HIP;
     }
@@ -888,6 +969,10 @@ dag_status dag_destroy(dag_ctx c) {
     if (c->io) (void)hipStreamDestroy(c->io);
     if (c->staging) (void)hipHostFree(c->staging);
     if (c->read_ev) (void)hipEventDestroy(c->read_ev);
+    for (hipEvent_t e : c->mark_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (c->sig_dev) (void)hipFree(c->sig_dev);
+    if (c->sig_timed_out) (void)hipHostFree(c->sig_timed_out);
   }
   delete c;
   return DAG_OK;
@@ -1242,7 +1327,7 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
       if (st) return st;
     }
   }
-  st = end_task(c, id, s);
+  st = end_task(c, id, s, true);
   c->launch_us += us_since(t1);
   return st;
 }
@@ -1421,6 +1506,8 @@ dag_status dag_get_stats(dag_ctx c, dag_stats* out) {
   out->submit_host_us = c->submit_us;
   out->launch_host_us = c->launch_us;
   out->spmv_plans = c->n_plans;
+  out->signals = c->n_signals;
+  out->signal_waits = c->n_signal_waits;
   return DAG_OK;
 }
 

@@ -1906,6 +1906,36 @@ __global__ void k_spin(uint64_t ticks) {
 // the eight XCDs round-robin by id, so 64 of them reach every L2.
 __global__ __launch_bounds__(64) void k_release_l2() { __threadfence_system(); }
 
+// Completion signals between streams.  A task's signal is one word per
+// stream that a one-wave kernel, queued right after the task on its stream,
+// raises to the task's sequence number there: the task has finished (and its
+// end-of-kernel release has been made) before that kernel runs, because the
+// stream runs its work in order.  A consumer on another stream is queued
+// behind a one-wave kernel that polls the words it needs until each reaches
+// its value; the consumer's own dispatch, ordered after that kernel, makes the
+// acquire that makes the producer's stores visible to it.  Polls use
+// device-coherent atomic loads and sleep between tries; past max_ticks of the
+// constant-rate clock the poller gives up, raises the flag in host memory and
+// exits, so every wave ends.
+__global__ __launch_bounds__(64) void k_dag_signal(uint64_t* word, uint64_t value) {
+  if (threadIdx.x == 0) __hip_atomic_store(word, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(64) void k_dag_wait(SignalWaits w) {
+  if (threadIdx.x != 0) return;
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t i = 0; i < w.n; ++i) {
+    const uint64_t* word = w.words + static_cast<uint64_t>(w.slot[i]) * kSignalStride;
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < w.value[i]) {
+      if (wall_clock64() - t0 > w.max_ticks) {
+        __hip_atomic_store(w.timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
 // Host<->device copy by the CUs (pinned host memory is read or written over
 // PCIe by the kernel itself): 16-byte words when both ends are 16-byte
 // aligned, then the tail bytes.
@@ -2798,6 +2828,20 @@ hipError_t release_l2(hipStream_t s) {
   hipLaunchKernelGGL(k_release_l2, dim3(kReleaseWorkgroups), dim3(64), 0, s);
   return hipGetLastError();
 }
+
+hipError_t signal_raise(hipStream_t s, uint64_t* word, uint64_t value) {
+  hipLaunchKernelGGL(k_dag_signal, dim3(1), dim3(64), 0, s, word, value);
+  return hipGetLastError();
+}
+
+hipError_t signal_wait(hipStream_t s, const SignalWaits& w) {
+  if (w.n == 0) return hipSuccess;
+  if (w.n > kMaxSignalWaits) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dag_wait, dim3(1), dim3(64), 0, s, w);
+  return hipGetLastError();
+}
+
+uint64_t wall_clock_ticks_per_ms() { return g_wall_khz; }
 
 void set_launch_events(hipEvent_t start, hipEvent_t stop) {
   tl_start = start;

@@ -54,6 +54,26 @@ hipError_t copy_by_kernel(hipStream_t s, void* dst, const void* src, size_t byte
 // (system-scope release on each XCD): the final node of region graphs.
 hipError_t release_l2(hipStream_t s);
 
+// Completion signals between streams: one 64-bit word per stream, kSignalStride
+// words apart.  signal_raise queues a one-wave kernel that stores value into
+// word once the work queued before it on s has finished; signal_wait queues a
+// one-wave kernel that returns once every listed word has reached its value
+// (or, after max_ticks of the device's constant-rate clock, stores 1 into
+// *timed_out, host memory, and returns).
+constexpr uint32_t kMaxSignalWaits = 8;
+constexpr uint32_t kSignalStride = 16;  // words: one 128-byte line per stream
+struct SignalWaits {
+  const uint64_t* words;
+  uint32_t* timed_out;
+  uint64_t max_ticks;
+  uint32_t n;
+  uint32_t slot[kMaxSignalWaits];
+  uint64_t value[kMaxSignalWaits];
+};
+hipError_t signal_raise(hipStream_t s, uint64_t* word, uint64_t value);
+hipError_t signal_wait(hipStream_t s, const SignalWaits& w);
+uint64_t wall_clock_ticks_per_ms();
+
 // Message of the calling thread's last failing dag_launch_static call.
 const char* static_launch_error();
 

@@ -25,6 +25,7 @@ DAG_E_INVAL, DAG_E_RANGE = -1, -9
 DAG_CONST, DAG_MUTABLE = 0, 1
 DAG_DEVICE, DAG_PINNED_HOST = 0, 1
 DAG_SERIAL_SYNC, DAG_PARALLEL_ASYNC = 0, 1
+DAG_WAIT_SIGNALS, DAG_WAIT_EVENTS = 0, 1
 DAG_EDGE_RAW, DAG_EDGE_WAR, DAG_EDGE_WAW = 0, 1, 2
 (DAG_TASK_KERNEL, DAG_TASK_COPY, DAG_TASK_HOST_READ, DAG_TASK_HOST_WRITE, DAG_TASK_SYNC,
  DAG_TASK_REGION, DAG_TASK_RELEASE) = range(7)
@@ -46,7 +47,7 @@ class dag_config(C.Structure):
                 ("dry_run", C.c_uint32), ("device", C.c_int32), ("graph_mode", C.c_uint32),
                 ("scratch_bytes", C.c_uint64), ("copy_streams", C.c_uint32),
                 ("spin_wait", C.c_uint32), ("copy_lanes", C.c_uint32), ("own_queues", C.c_uint32),
-                ("copy_engine", C.c_uint32), ("reserved", C.c_uint32)]
+                ("copy_engine", C.c_uint32), ("wait_mode", C.c_uint32)]
 
 
 class dag_arg(C.Structure):
@@ -68,7 +69,8 @@ class dag_stats(C.Structure):
     _fields_ = [("tasks", C.c_uint64), ("vertices", C.c_uint64), ("edges", C.c_uint64),
                 ("waits", C.c_uint64), ("host_waits", C.c_uint64), ("streams", C.c_uint32),
                 ("active", C.c_uint32), ("submit_host_us", C.c_double),
-                ("launch_host_us", C.c_double), ("spmv_plans", C.c_uint64)]
+                ("launch_host_us", C.c_double), ("spmv_plans", C.c_uint64), ("signals", C.c_uint64),
+                ("signal_waits", C.c_uint64)]
 
 
 class dag_launch(C.Structure):
@@ -589,10 +591,10 @@ class Context:
 
     def __init__(self, policy=DAG_PARALLEL_ASYNC, max_streams=8, trace=0, dry_run=False,
                  device=0, graph_mode=0, scratch_bytes=0, copy_streams=0, spin_wait=0, copy_lanes=1,
-                 own_queues=0, copy_engine=0):
+                 own_queues=0, copy_engine=0, wait_mode=0):
         self.cfg = dag_config(policy, max_streams, int(trace), int(bool(dry_run)), device,
                               graph_mode, scratch_bytes, copy_streams, int(spin_wait), int(copy_lanes),
-                              int(own_queues), int(copy_engine), 0)
+                              int(own_queues), int(copy_engine), int(wait_mode))
         self.h = dag_create(self.cfg)
 
     def close(self):

@@ -19,9 +19,10 @@ def oracle_run(prog):
 
 
 def gpu_run(prog, policy=D.DAG_PARALLEL_ASYNC, max_streams=8, batch=True, trace=0,
-            graph_mode=0, outputs=None, copy_streams=1, own_queues=0, copy_engine=0):
+            graph_mode=0, outputs=None, copy_streams=1, own_queues=0, copy_engine=0, wait_mode=0):
     ctx = D.Context(policy=policy, max_streams=max_streams, trace=trace, graph_mode=graph_mode,
-                    copy_streams=copy_streams, own_queues=own_queues, copy_engine=copy_engine)
+                    copy_streams=copy_streams, own_queues=own_queues, copy_engine=copy_engine,
+                    wait_mode=wait_mode)
     b = runner.Bound(ctx, prog)
     if batch:
         b.run()

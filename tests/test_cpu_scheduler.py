@@ -257,6 +257,12 @@ def test_bad_config_rejected():
     assert e.value.name == "DAG_E_UNSUPPORTED"
     with pytest.raises(D.DagError):
         D.Context(dry_run=True, copy_lanes=5)
+    with pytest.raises(D.DagError) as e:
+        D.Context(dry_run=True, wait_mode=2)
+    assert e.value.name == "DAG_E_INVAL"
+    for mode in (D.DAG_WAIT_SIGNALS, D.DAG_WAIT_EVENTS):  # both accepted; dry runs place no wait of either kind
+        with D.Context(dry_run=True, wait_mode=mode) as ctx:
+            assert ctx.stats().signals == 0
 
 
 def test_serial_policy_computes_no_dependencies():

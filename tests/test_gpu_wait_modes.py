@@ -1,0 +1,114 @@
+"""Waits between streams in both wait modes: device-side polls of completion
+signals (DAG_WAIT_SIGNALS, the default) and HIP events (DAG_WAIT_EVENTS).
+The same programs give the oracle's outputs and edges in both modes; in
+signal mode the waits on tasks that ran on the CUs are polls, in event mode
+none are; a slow producer holds back its consumer on another stream; and a
+poll that gives up (its bound lowered from the host) poisons the context at
+the next host wait instead of letting a wrong result through."""
+
+import pytest
+
+import gpu_util as G
+from oracle import dag as odag
+from paper_2012_09646_amd import dagrt as D
+from paper_2012_09646_amd import runner
+from paper_2012_09646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MODES = [D.DAG_WAIT_SIGNALS, D.DAG_WAIT_EVENTS]
+
+# Small ragged programs; the Black-Scholes one runs its copies on the copy
+# lanes, host->device by SDMA (events) and device->host by the copy kernel
+# (signals), so both kinds of wait meet in one DAG.
+PROGRAMS = {
+    "vec": (lambda: W.vec_program(n=(1 << 20) + 3, seed=21), {}),
+    "bs": (lambda: W.bs_program(n=(1 << 18) + 5, tasks=4, seed=22), dict(copy_streams=0, copy_engine=2)),
+    "img": (lambda: W.img_program(side=257, height=131, seed=23), {}),
+    "hits": (lambda: W.hits_program(n=(1 << 13) + 7, iters=4, seed=24), {}),
+    "ml": (lambda: W.ml_program(n=3001, seed=25), {}),
+    "dl": (lambda: W.dl_program(side=64, seed=26), {}),
+}
+
+
+def banner(s):
+    print("[wait] " + s, flush=True)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("name", sorted(PROGRAMS))
+def test_programs_in_both_modes(name, mode):
+    banner("%s mode %d" % (name, mode))
+    make, kw = PROGRAMS[name]
+    prog = make()
+    ref = G.oracle_run(prog)
+    g = odag.build_dag(prog.ops)
+    ctx, b, outs = G.gpu_run(prog, max_streams=8, wait_mode=mode, **kw)
+    try:
+        assert b.edges() == g.edges
+        for out in prog.outputs:
+            G.assert_close(prog, out, outs[out], ref[out])
+        st = ctx.stats()
+        if mode == D.DAG_WAIT_EVENTS:
+            assert st.signals == 0 and st.signal_waits == 0
+        else:
+            gpu_tasks = sum(1 for o in prog.ops if o["kind"] in ("kernel", "copy"))
+            sdma = sum(1 for o in prog.ops if o["kind"] == "copy" and
+                       prog.bufs[o["src"]].loc == "host")  # host->device copies by SDMA
+            assert st.signals == gpu_tasks - sdma
+            assert st.signal_waits <= st.waits
+            if name in ("img", "hits"):  # every cross-stream parent is a kernel
+                assert st.waits > 0 and st.signal_waits == st.waits
+            if name == "bs":  # copies by SDMA (events) and by the copy kernel (signals)
+                assert 0 < st.signal_waits < st.waits
+    finally:
+        ctx.close()
+
+
+def _chain_program(spin_ns, n=(1 << 16) + 9, seed=27):
+    """y <- y^2 on one stream; a delay then x <- x^2 on a second; r = sum(x - y)
+    joins them on the first stream (its lowest parent's), behind a wait for
+    the second."""
+    base = W.vec_program(n=n, seed=seed)
+    ops = [W.K("vec_square", [("y", "m")], n=n),
+           W.K("spin", [("x", "m")], ns=spin_ns),
+           W.K("vec_square", [("x", "m")], n=n),
+           W.K("vec_sum_diff", [("x", "c"), ("y", "c"), ("r", "m")], n=n),
+           W.HR("r")]
+    return W.Program("chain", base.bufs, ops, base.outputs, "r")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_slow_producer_holds_its_consumer(mode):
+    banner("slow producer mode %d" % mode)
+    prog = _chain_program(20_000_000)
+    ref = G.oracle_run(prog)
+    with D.Context(max_streams=4, wait_mode=mode) as ctx:
+        b = runner.Bound(ctx, prog)
+        b.run()
+        st = b.streams()
+        assert st[1] == st[4] != st[2] == st[3]
+        for out in prog.outputs:
+            G.assert_close(prog, out, b.read(out), ref[out])
+        s = ctx.stats()
+        assert s.waits == 1 and s.signal_waits == (1 if mode == D.DAG_WAIT_SIGNALS else 0)
+
+
+def test_a_wait_that_gives_up_poisons_the_context(monkeypatch):
+    """The poll's bound is lowered to 1 ms from the host while its producer
+    runs 100 ms: the poll exits, and the host read that follows reports the
+    failure (every kernel still ends normally)."""
+    banner("poll bound 1 ms")
+    monkeypatch.setenv("DAGRT_SIGNAL_TIMEOUT_MS", "1")
+    prog = _chain_program(100_000_000)
+    ctx = D.Context(max_streams=4)
+    monkeypatch.delenv("DAGRT_SIGNAL_TIMEOUT_MS")
+    try:
+        b = runner.Bound(ctx, prog, upload=True)
+        with pytest.raises(D.DagError) as ei:
+            b.run()
+        assert "gave up" in str(ei.value)
+        with pytest.raises(D.DagError):
+            ctx.sync()
+    finally:
+        ctx.close()
