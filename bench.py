@@ -89,6 +89,8 @@ def parse():
                          "and the fan-out at serial speed), 3 = H2D kernel + D2H SDMA")
     ap.add_argument("--spin-wait", type=int, default=0, choices=[0, 1],
                     help="1: host waits spin (hipDeviceScheduleSpin)")
+    ap.add_argument("--wait-mode", type=int, default=0, choices=[0, 1],
+                    help="cross-stream waits: 0 = device-side signal polls, 1 = HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-oracle", default="", help=argparse.SUPPRESS)  # internal: CPU baseline of one workload
     return ap.parse_args()
@@ -317,7 +319,8 @@ def orchestrate(args):
     fwd = ["--steps", str(args.steps), "--warmup", str(args.warmup), "--tuned", args.tuned,
            "--max-streams", str(args.max_streams), "--copy-streams", str(args.copy_streams),
            "--copy-lanes", str(args.copy_lanes), "--copy-engine", str(args.copy_engine),
-           "--spin-wait", str(args.spin_wait), "--requests", str(args.requests), "--rate", str(args.rate),
+           "--spin-wait", str(args.spin_wait), "--wait-mode", str(args.wait_mode), "--requests", str(args.requests),
+           "--rate", str(args.rate),
            "--low-rate", str(args.low_rate), "--capacity-rate", str(args.capacity_rate),
            "--serve-lanes", str(args.serve_lanes),
            "--serve-copy-lanes", str(args.serve_copy_lanes), "--serve-copy-engine", str(args.serve_copy_engine),
@@ -428,7 +431,7 @@ def main():
         def make(policy, trace):
             ctx = D.Context(policy=policy, max_streams=args.max_streams, trace=trace,
                             copy_streams=args.copy_streams, spin_wait=args.spin_wait,
-                            copy_lanes=args.copy_lanes, copy_engine=args.copy_engine)
+                            copy_lanes=args.copy_lanes, copy_engine=args.copy_engine, wait_mode=args.wait_mode)
             tune.apply_kernels(ctx, tuned)
             # near-tie kernel configurations the tuner chose for this DAG's makespan
             for k, cfg in tuned_dag.get(name, {}).get("kernels", {}).items():
@@ -622,7 +625,7 @@ def main():
         for gm, tag, engine in forms:
             ctxG = D.Context(policy=D.DAG_PARALLEL_ASYNC, max_streams=args.max_streams, graph_mode=gm,
                              copy_streams=args.copy_streams, spin_wait=args.spin_wait,
-                             copy_lanes=args.copy_lanes, copy_engine=engine)
+                             copy_lanes=args.copy_lanes, copy_engine=engine, wait_mode=args.wait_mode)
             tune.apply_kernels(ctxG, tuned)
             bG = runner.Bound(ctxG, prog, read_bytes=4)
             for dst in restore:

@@ -158,13 +158,17 @@ typedef struct {
                              Device-to-device copies always use HIP. */
   uint32_t wait_mode;     /* how a task on one stream waits for a parent on
                              another (the event waits of Sec. IV-B):
-                             DAG_WAIT_SIGNALS (0) = the parent's stream raises
-                             a per-stream counter in device memory with a
-                             one-wave kernel queued after it, and the child's
-                             stream is held by a one-wave kernel that polls
-                             the counter (about 2 us per edge against about
-                             12 us for a HIP event wait; tasks on the CUs
-                             only, SDMA copies still end with an event; a
+                             DAG_WAIT_SIGNALS (0) = a task on the CUs takes
+                             the next value of a per-stream counter in device
+                             memory, which a one-wave kernel queued behind it
+                             raises (lazily: before the next task on that
+                             stream when the pool has several streams, else
+                             when a task elsewhere first waits for it), and
+                             the child's stream is held by a one-wave kernel
+                             that polls the counter (about 2 us per edge
+                             against about 12 us for a HIP event wait; SDMA
+                             copies and region replays still end with an
+                             event; a
                              poll that has not seen its value after 10 s
                              gives up, and the next host wait or sync of the
                              context then fails with DAG_E_HIP and poisons
@@ -227,7 +231,9 @@ typedef struct {
                             whose row-pointer buffer was not written since
                             its partition was computed (same sizes) reuses
                             it */
-  uint64_t signals;      /* completion signals raised (wait mode 0) */
+  uint64_t signals;      /* signal kernels queued (wait mode 0); one raise
+                            covers every task queued before it on its
+                            stream */
   uint64_t signal_waits; /* of `waits`, those placed as device-side polls of
                             a signal rather than event waits */
 } dag_stats;

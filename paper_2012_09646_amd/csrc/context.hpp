@@ -110,14 +110,16 @@ struct dag_ctx_s {
   std::vector<hipEvent_t> ev;             // per task (GPU tasks), completion; ev[id - ev_base]
   uint64_t ev_base = 0;                   // first task id of ev (records before it were compacted)
   // Wait mode 0: completion signals between streams (kernels.hpp).  sig_dev
-  // holds one word per stream; sig_next[s] is the last value raised on
-  // stream s; tsig[id - ev_base] is task id's value on its stream (0: the
-  // task has an event instead); mark_ev[s] is recorded on stream s when the
-  // host must wait for a signalled task of it.
+  // holds one word per stream.  A task that ends with a signal takes the
+  // next value of its stream, sig_next[s]; tsig[id - ev_base] keeps it (0:
+  // the task has an event instead).  The value is raised on the device
+  // lazily: sig_raised[s] is the last value queued for raising on stream s.
+  // mark_ev[s] is recorded on stream s when the host must wait for a
+  // signalled task of it.
   bool signals = false;
   uint64_t* sig_dev = nullptr;
   uint32_t* sig_timed_out = nullptr;      // pinned host word raised by a wait that gave up
-  std::vector<uint64_t> sig_next;
+  std::vector<uint64_t> sig_next, sig_raised;
   std::vector<uint64_t> tsig;
   std::vector<hipEvent_t> mark_ev;
   uint64_t n_signals = 0, n_signal_waits = 0;

@@ -98,6 +98,7 @@ dag_status ensure_stream(dag_ctx c, int32_t s) {
     c->streams.push_back(st);
     c->scratch.push_back(scr);
     c->sig_next.push_back(0);
+    c->sig_raised.push_back(0);
     c->mark_ev.push_back(nullptr);
   }
   return DAG_OK;
@@ -138,7 +139,23 @@ dag_status gate_stream(dag_ctx c, int32_t s) {
   return DAG_OK;
 }
 
+// Queue on stream s the raising of its newest signal value, unless already
+// queued.  Stream order makes it cover every task of s queued before it.
+dag_status raise_signal(dag_ctx c, int32_t s) {
+  if (c->sig_raised[s] >= c->sig_next[s]) return DAG_OK;
+  HIP_TRY(c, signal_raise(c->streams[s], c->sig_dev + static_cast<uint64_t>(s) * kSignalStride, c->sig_next[s]));
+  c->sig_raised[s] = c->sig_next[s];
+  ++c->n_signals;
+  return DAG_OK;
+}
+
 // Enqueue the waits of task id on its stream and (trace) its start event.
+// Signals are raised late: the one of the task before on this stream just
+// before this task when the pool has several streams (a consumer elsewhere
+// may need that task without this one), and any other when a consumer on
+// another stream first waits for it (at once if it is still the last task of
+// its stream; otherwise the raise also covers the tasks queued after it).
+// A one-stream pool thus raises signals only for its copy lanes.
 // With dispatch_timed, the start (and kernel-end) events are attached to the
 // task's kernel dispatches instead of being recorded as separate markers.
 dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = false) {
@@ -152,6 +169,10 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
                   static_cast<unsigned long long>(id), what, s, t.wait_n);
     c->roctx_push(name);
   }
+  if (c->signals && c->cfg.max_streams > 1 && static_cast<uint32_t>(s) < kSignalSlots) {
+    dag_status st = raise_signal(c, s);
+    if (st) return st;
+  }
   const uint64_t* w = c->tr.waits(id);
   SignalWaits sw{};
   sw.words = c->sig_dev;
@@ -160,7 +181,12 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
   for (uint32_t i = 0; i < t.wait_n; ++i) {
     const uint64_t k = w[i] - c->ev_base;
     if (c->signals && c->tsig[k]) {
-      sw.slot[sw.n] = static_cast<uint32_t>(c->tr.task(w[i]).stream);
+      const int32_t ws = c->tr.task(w[i]).stream;
+      if (c->sig_raised[ws] < c->tsig[k]) {
+        dag_status st = raise_signal(c, ws);
+        if (st) return st;
+      }
+      sw.slot[sw.n] = static_cast<uint32_t>(ws);
       sw.value[sw.n] = c->tsig[k];
       ++c->n_signal_waits;
       if (++sw.n == kMaxSignalWaits) {
@@ -197,18 +223,15 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
 }
 
 // A task ends with a completion signal when signals are on and the task ran
-// on the CUs (kernels, region replays, copies by the copy kernel): the signal
-// kernel then follows it on the same engine.  SDMA copies end with an event.
+// on the CUs (kernels, copies by the copy kernel): the signal kernel that
+// raises its value follows it on the same engine.  SDMA copies and region
+// replays end with an event.
 // Traced tasks also get their timing event.
 dag_status end_task(dag_ctx c, uint64_t id, int32_t s, bool on_cus) {
   if (c->dry) return DAG_OK;
   const uint64_t k = id - c->ev_base;
   const bool sig = c->signals && on_cus && static_cast<uint32_t>(s) < kSignalSlots;
-  if (sig) {
-    HIP_TRY(c, signal_raise(c->streams[s], c->sig_dev + static_cast<uint64_t>(s) * kSignalStride, ++c->sig_next[s]));
-    c->tsig[k] = c->sig_next[s];
-    ++c->n_signals;
-  }
+  if (sig) c->tsig[k] = ++c->sig_next[s];  // raised when first needed
   if (!sig || traced(c, id)) {
     hipEvent_t e;
     dag_status st = get_event(c, traced(c, id), &e);
@@ -740,7 +763,10 @@ dag_status build_graph(dag_ctx c, Region* r) {
   dag_status st = ensure_aux(c, r->nstreams);
   if (st) return st;
   HIP_TRY(c, hipMalloc(&r->scratch, c->cfg.scratch_bytes * r->nstreams));
-  HIP_TRY(c, hipMemset(r->scratch, 0, c->cfg.scratch_bytes * r->nstreams));
+  // (on a stream of the context: a first use of the null stream changes how
+  // the runtime spreads the process's streams over the hardware queues, and
+  // with 8 queues that made the region graphs' replays twice as slow)
+  HIP_TRY(c, hipMemsetAsync(r->scratch, 0, c->cfg.scratch_bytes * r->nstreams, c->aux[0]));
   HIP_TRY(c, hipDeviceSynchronize());
   std::vector<hipEvent_t> evs(r->tasks.size(), nullptr);
   std::vector<hipEvent_t> forks(r->nstreams, nullptr);
@@ -907,7 +933,9 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
     if (e == hipSuccess && c.wait_mode == DAG_WAIT_SIGNALS && !x->serial) {
       const size_t words = size_t(kSignalSlots) * kSignalStride;
       e = hipMalloc(&x->sig_dev, words * sizeof(uint64_t));
-      if (e == hipSuccess) e = hipMemset(x->sig_dev, 0, words * sizeof(uint64_t));
+      // cleared on the context's own stream: the null stream stays unused
+      if (e == hipSuccess) e = hipMemsetAsync(x->sig_dev, 0, words * sizeof(uint64_t), x->io);
+      if (e == hipSuccess) e = hipStreamSynchronize(x->io);
       if (e == hipSuccess) e = hipHostMalloc(&x->sig_timed_out, sizeof(uint32_t), hipHostMallocDefault);
       if (e == hipSuccess) {
         *x->sig_timed_out = 0;
@@ -1327,7 +1355,10 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
       if (st) return st;
     }
   }
-  st = end_task(c, id, s, true);
+  // A region replay ends with an event: a signal kernel queued right behind
+  // hipGraphLaunch slowed the replays of the next launches on that stream
+  // (HITS iteration graphs: 4.3 ms against 2.2 ms per ten launches).
+  st = end_task(c, id, s, false);
   c->launch_us += us_since(t1);
   return st;
 }

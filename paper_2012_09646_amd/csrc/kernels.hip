@@ -892,6 +892,171 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ row_
   if (lane == 0) y[r] = static_cast<float>(sc.head_val[b] + acc);
 }
 
+// Row-window SpMV (the launch variants 0x100 | IPT; 0x200 added: the column
+// indices and values are read with non-temporal loads).  Tile b covers the
+// nonzeros [b*W, min((b+1)*W, nnz)), W = 256 * IPT, and owns the rows that
+// start in that window (own[b] <= r < own[b+1]; the last tile also owns the
+// rows that start at nnz).  The tile's products are formed coalesced (IPT
+// column indices and values per thread, their gathers of x, fp64 products in
+// LDS); then each owned row is summed from LDS, by one thread when its part
+// in the tile has at most kShortRow nonzeros and by a whole wave (strided
+// lanes, butterfly) otherwise.  The only owned row that can run past the
+// tile is the last one: its in-tile sum is the tile's tail part.  Nonzeros at
+// the start of the tile that belong to a row started in an earlier tile are
+// summed by wave 0 into the tile's head part; the fix-up adds the parts of
+// such a row in tile order, in the tile where the row ends.  Every sum is
+// taken in a fixed order, so results do not depend on timing.
+constexpr int kShortRow = 32;
+
+struct SpmvWindowScratch {
+  double* head_val;  // per tile: sum of the nonzeros before its first owned row
+  double* tail_val;  // per tile: in-tile sum of its last owned row when that row runs past the tile
+  int* head_row;     // per tile: the row its head part ends (fix-up writes it), else -1
+};
+
+// Smallest r in [0, nrows] with row_ptr[r] >= target (r = nrows when no row
+// starts at or after target), by one wave: 64 probes per round shrink the
+// interval 65-fold.
+__device__ int wave_lower_bound(const int* __restrict__ row_ptr, int nrows, int nnz, long long target) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int lo = 0, hi = nrows;  // the answer lies in [lo, hi]
+  while (hi - lo > kWave) {
+    const long long span = hi - lo;
+    const int xq = lo + static_cast<int>(((lane + 1) * span) / (kWave + 1));  // lo < xq < hi
+    const bool below = clamp_nnz(row_ptr[xq], nnz) < target;
+    const int c = __popcll(__ballot(below));  // probes 0 .. c-1 lie below the target
+    const int lo0 = lo;
+    if (c > 0) lo = lo0 + static_cast<int>((c * span) / (kWave + 1)) + 1;
+    if (c < kWave) hi = lo0 + static_cast<int>(((c + 1) * span) / (kWave + 1));
+  }
+  const int xq = lo + lane;
+  const bool below = xq < hi && clamp_nnz(row_ptr[xq], nnz) < target;
+  return lo + __popcll(__ballot(below));
+}
+
+// own[b] for b = 0 .. ntiles (own[ntiles] = nrows), one wave per boundary.
+__global__ __launch_bounds__(256) void k_spmv_window_partition(const int* __restrict__ row_ptr, int nrows,
+                                                               int nnz, int window, int ntiles,
+                                                               int* __restrict__ own) {
+  const int b = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (b > ntiles) return;
+  const int r = b == ntiles ? nrows : wave_lower_bound(row_ptr, nrows, nnz, static_cast<long long>(b) * window);
+  if ((threadIdx.x & (kWave - 1)) == 0) own[b] = r;
+}
+
+template <int IPT, bool kStream>
+__global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                                     const float* __restrict__ val, const float* __restrict__ x,
+                                                     float* __restrict__ y, int nrows, int ncols, int nnz,
+                                                     const int* __restrict__ own, SpmvWindowScratch sc) {
+  constexpr int W = 256 * IPT;
+  __shared__ double s_prod[W];
+  __shared__ int s_long[256];
+  __shared__ int s_nlong;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int b = blockIdx.x;
+  const int k0 = static_cast<int>(min(static_cast<long long>(b) * W, static_cast<long long>(nnz)));
+  const int k1 = static_cast<int>(min(static_cast<long long>(k0) + W, static_cast<long long>(nnz)));
+  const int cnt = k1 - k0;
+  int cidx[IPT];
+  float v[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int i = tid + j * 256;
+    if (kStream) {  // read once: hint the caches to keep x's lines rather than these
+      cidx[j] = i < cnt ? __builtin_nontemporal_load(col + k0 + i) : 0;
+      v[j] = i < cnt ? __builtin_nontemporal_load(val + k0 + i) : 0.0f;
+    } else {
+      cidx[j] = i < cnt ? col[k0 + i] : 0;
+      v[j] = i < cnt ? val[k0 + i] : 0.0f;
+    }
+  }
+  float xv[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) xv[j] = x[min(max(cidx[j], 0), ncols - 1)];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int i = tid + j * 256;
+    if (i < cnt) s_prod[i] = static_cast<double>(v[j]) * static_cast<double>(xv[j]);
+  }
+  const int r0 = own[b], r1 = own[b + 1];
+  if (tid == 0) s_nlong = 0;
+  __syncthreads();
+  // local [start, end) of row r's nonzeros inside the tile; e = global end
+  auto local_range = [&](int r, int* ls, int* le, int* e) {
+    const int s0 = clamp_nnz(row_ptr[r], nnz);
+    *e = clamp_nnz(row_ptr[r + 1], nnz);
+    *ls = min(max(s0, k0), k1) - k0;
+    *le = max(min(max(*e, k0), k1) - k0, *ls);
+  };
+  if (wv == 0) {
+    const int hend = min(max(r0 < nrows ? clamp_nnz(row_ptr[r0], nnz) : nnz, k0), k1);
+    double h = 0.0;
+    for (int i = lane; i < hend - k0; i += kWave) h += s_prod[i];
+    h = wave_sum(h);
+    if (lane == 0) {
+      sc.head_val[b] = h;
+      // the head part ends its row here unless the row runs on past the tile
+      const bool has_head = b > 0 && r0 > 0 && hend > k0;
+      const bool ends_here = r0 < nrows ? clamp_nnz(row_ptr[r0], nnz) <= k1 : nnz <= k1;
+      sc.head_row[b] = has_head && ends_here ? r0 - 1 : -1;
+    }
+  }
+  for (int c = r0; c < r1; c += 256) {
+    const int r = c + tid;
+    if (r < r1) {
+      int ls, le, e;
+      local_range(r, &ls, &le, &e);
+      if (le - ls <= kShortRow) {
+        double acc = 0.0;
+        for (int i = ls; i < le; ++i) acc += s_prod[i];
+        if (e <= k1)
+          y[r] = static_cast<float>(acc);
+        else
+          sc.tail_val[b] = acc;
+      } else {
+        s_long[atomicAdd(&s_nlong, 1)] = r;
+      }
+    }
+    __syncthreads();
+    const int nl = s_nlong;
+    for (int q = wv; q < nl; q += 256 / kWave) {
+      const int r2 = s_long[q];
+      int ls, le, e;
+      local_range(r2, &ls, &le, &e);
+      double acc = 0.0;
+      for (int i = ls + lane; i < le; i += kWave) acc += s_prod[i];
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        if (e <= k1)
+          y[r2] = static_cast<float>(acc);
+        else
+          sc.tail_val[b] = acc;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s_nlong = 0;
+    __syncthreads();
+  }
+}
+
+// Rows that run across tiles: one wave per tile whose head part ends a row
+// adds, in tile order, the row's tail part in the tile that owns it and the
+// head parts of the tiles after that one up to this tile.
+__global__ __launch_bounds__(256) void k_spmv_window_fixup(const int* __restrict__ row_ptr, float* __restrict__ y,
+                                                           SpmvWindowScratch sc, int ntiles, int nnz, int window) {
+  const int b = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (b >= ntiles) return;
+  const int r = sc.head_row[b];
+  if (r < 0) return;
+  const int owner = min(clamp_nnz(row_ptr[r], nnz) / window, ntiles - 1);
+  double acc = 0.0;
+  for (int k = owner + 1 + lane; k <= b; k += kWave) acc += sc.head_val[k];
+  acc = wave_sum(acc);
+  if (lane == 0) y[r] = static_cast<float>(sc.tail_val[owner] + acc);
+}
+
 // CSR SpMV for matrices with short rows: L lanes per row stride over the row
 // (the matrix read once, coalesced within the row), fp64 partial sums
 // combined by an xor butterfly inside each group of L lanes.  No search and
@@ -1990,8 +2155,16 @@ const char* cfg_tile(const LaunchCfg& c);
 const char* cfg_spmv(const LaunchCfg& c) {
   if (c.block != 256) return "SpMV runs 256-thread workgroups";
   if (c.grid_cap != 0) return "grid_cap must be 0";
+  const uint32_t ipt = c.variant & 0xffu;
+  if (c.variant & 0x100u) {
+    if (c.variant > 0x3ffu || (ipt != 4 && ipt != 8 && ipt != 16))
+      return "row-window SpMV variant must be 0x100 | 4, 8 or 16 (nonzeros per thread), plus 0x200 for "
+             "streaming loads of the matrix";
+    return nullptr;
+  }
   if (c.variant != 4 && c.variant != 8 && c.variant != 12 && c.variant != 16)
-    return "SpMV variant (items per thread) must be 4, 8, 12 or 16";
+    return "SpMV variant must be 4, 8, 12 or 16 (merge-path items per thread) or 0x100 | 4, 8 or 16 "
+           "(row windows)";
   return nullptr;
 }
 const char* cfg_spin(const LaunchCfg& c) {
@@ -2266,11 +2439,19 @@ hipError_t l_combine(hipStream_t s, void* const* a, const void* p, const LaunchC
 }
 
 // -- HITS -------------------------------------------------------------------
-uint64_t spmv_tiles(const dag_p_csr* q, uint32_t ipt) {
-  return ceil_div(static_cast<uint64_t>(q->nrows) + q->nnz, 256ull * ipt);
+// Variants 4..16: merge-path tiles of 256 * variant rows and nonzeros;
+// 0x100 | IPT: row windows of 256 * IPT nonzeros (at least one tile, which
+// owns every row when there is no nonzero).
+bool spmv_is_window(uint32_t variant) { return (variant & 0x100u) != 0; }
+uint64_t spmv_tiles(const dag_p_csr* q, uint32_t variant) {
+  const uint64_t items = 256ull * (variant & 0xffu);
+  if (spmv_is_window(variant)) return std::max<uint64_t>(1, ceil_div(static_cast<uint64_t>(q->nnz), items));
+  return ceil_div(static_cast<uint64_t>(q->nrows) + q->nnz, items);
 }
 // Carries live after the reduction ticket counter (which must stay zero):
 // head_val, tail_val (fp64), head_row, tail_row, coord (int32, tiles + 1).
+// The row-window form uses the first three and keeps its row boundaries
+// where coord is.
 size_t spmv_scratch_need(uint64_t tiles) { return kScratchPartialsOffset + tiles * (8 + 8 + 4 + 4) + 4 * (tiles + 1); }
 
 const char* v_spmv(const void* p, const size_t* sz, uint32_t, const LaunchCfg& c, size_t sb) {
@@ -2305,13 +2486,57 @@ SpmvScratch spmv_carries(void* scr, int tiles) {
   return sc;
 }
 
-hipError_t spmv_partition_into(hipStream_t s, const int* row_ptr, const dag_p_csr* q, uint32_t ipt, int tiles,
+hipError_t spmv_partition_into(hipStream_t s, const int* row_ptr, const dag_p_csr* q, uint32_t variant, int tiles,
                                int* coord) {
+  const int waves_per_wg = 256 / kWave;
+  const int items = static_cast<int>(256 * (variant & 0xffu));
+  if (spmv_is_window(variant)) {
+    DAGRT_LAUNCH(k_spmv_window_partition, dim3(ceil_div(tiles + 1, waves_per_wg)), dim3(256), 0, s, row_ptr,
+                 static_cast<int>(q->nrows), static_cast<int>(q->nnz), items, tiles, coord);
+    return hipGetLastError();
+  }
   SpmvScratch sc{};
   sc.coord = coord;
-  const int waves_per_wg = 256 / kWave;
   DAGRT_LAUNCH(k_spmv_partition, dim3(ceil_div(tiles + 1, waves_per_wg)), dim3(256), 0, s, row_ptr,
-               static_cast<int>(q->nrows), static_cast<int>(q->nnz), static_cast<int>(256 * ipt), tiles, sc);
+               static_cast<int>(q->nrows), static_cast<int>(q->nnz), items, tiles, sc);
+  return hipGetLastError();
+}
+
+template <int IPT, bool kStream>
+void launch_spmv_window(hipStream_t s, void* const* a, const dag_p_csr* q, const int* own,
+                        const SpmvWindowScratch& sc, int tiles) {
+  DAGRT_LAUNCH((k_spmv_window<IPT, kStream>), dim3(tiles), dim3(256), 0, s, static_cast<const int*>(a[0]),
+               static_cast<const int*>(a[1]), static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
+               static_cast<float*>(a[4]), static_cast<int>(q->nrows), static_cast<int>(q->ncols),
+               static_cast<int>(q->nnz), own, sc);
+}
+
+// Row-window products and fix-up over the row boundaries in own.
+hipError_t spmv_window_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, uint32_t variant, int tiles,
+                             const int* own, void* scr) {
+  const SpmvScratch c = spmv_carries(scr, tiles);
+  SpmvWindowScratch sc;
+  sc.head_val = c.head_val;
+  sc.tail_val = c.tail_val;
+  sc.head_row = c.head_row;
+  const bool stream = (variant & 0x200u) != 0;
+  switch (variant & 0xffu) {
+    case 4:
+      stream ? launch_spmv_window<4, true>(s, a, q, own, sc, tiles) : launch_spmv_window<4, false>(s, a, q, own, sc, tiles);
+      break;
+    case 16:
+      stream ? launch_spmv_window<16, true>(s, a, q, own, sc, tiles) : launch_spmv_window<16, false>(s, a, q, own, sc, tiles);
+      break;
+    default:
+      stream ? launch_spmv_window<8, true>(s, a, q, own, sc, tiles) : launch_spmv_window<8, false>(s, a, q, own, sc, tiles);
+      break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int waves_per_wg = 256 / kWave;
+  DAGRT_LAUNCH(k_spmv_window_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s,
+               static_cast<const int*>(a[0]), static_cast<float*>(a[4]), sc, tiles, static_cast<int>(q->nnz),
+               static_cast<int>(256 * (variant & 0xffu)));
   return hipGetLastError();
 }
 
@@ -2339,6 +2564,7 @@ hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   const SpmvScratch sc = spmv_carries(scr, tiles);
   hipError_t e = spmv_partition_into(s, static_cast<const int*>(a[0]), q, c.variant, tiles, sc.coord);
   if (e != hipSuccess) return e;
+  if (spmv_is_window(c.variant)) return spmv_window_fixup(s, a, q, c.variant, tiles, sc.coord, scr);
   return spmv_merge_fixup(s, a, q, c.variant, tiles, sc);
 }
 
@@ -2810,6 +3036,7 @@ hipError_t spmv_planned(hipStream_t s, void* const* ptrs, const void* params, co
   const auto* q = static_cast<const dag_p_csr*>(params);
   if (q->nrows == 0) return hipSuccess;
   const int tiles = static_cast<int>(spmv_tiles(q, cfg.variant));
+  if (spmv_is_window(cfg.variant)) return spmv_window_fixup(s, ptrs, q, cfg.variant, tiles, coord, scratch);
   SpmvScratch sc = spmv_carries(scratch, tiles);
   sc.coord = const_cast<int*>(coord);
   return spmv_merge_fixup(s, ptrs, q, cfg.variant, tiles, sc);

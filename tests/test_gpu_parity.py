@@ -164,7 +164,7 @@ def _spmv_program(rp, ci, va, x):
     return W.Program("spmv", bufs, ops, ["y"])
 
 
-@pytest.mark.parametrize("variant", [4, 8, 12, 16])
+@pytest.mark.parametrize("variant", [4, 8, 12, 16, 0x104, 0x108, 0x110])
 def test_spmv_long_rows_and_empty_rows(variant):
     banner("spmv variant=%d" % variant)
     n = 50000
@@ -204,7 +204,7 @@ def _random_csr(seed, n, long_row):
     return rp, ci, W.uniform_f32(seed + 100, ci.size)
 
 
-@pytest.mark.parametrize("variant", [4, 16])
+@pytest.mark.parametrize("variant", [4, 16, 0x108])
 def test_spmv_partition_reuse(variant):
     """The merge-path partition kept with the row-pointer buffer: reused by an
     SpMV on another stream, recomputed after the row pointers are rewritten
@@ -255,6 +255,45 @@ def test_spmv_no_nonzeros():
     prog = _spmv_program(rp, np.zeros(0, np.int32), np.zeros(0, np.float32), W.uniform_f32(1, n))
     out = G.check_program(prog)
     assert np.all(out["y"].view(np.float32) == 0)
+    for variant in (0x104, 0x110):
+        with D.Context() as ctx:
+            ctx.set_launch("spmv", 256, 0, variant)
+            from paper_2012_09646_amd import runner
+            b = runner.Bound(ctx, prog)
+            b.run()
+            assert np.all(b.read("y").view(np.float32) == 0)
+
+
+@pytest.mark.parametrize("variant", [0x104, 0x108, 0x110])
+def test_spmv_rows_on_window_edges(variant):
+    """Row-window SpMV with rows that end exactly where a window ends, rows of
+    exactly one and several windows, runs of empty rows between them and at
+    the end, and a row that starts at the last nonzero."""
+    banner("spmv window edges variant=%#x" % variant)
+    wnd = 256 * (variant & 0xff)
+    rng = np.random.default_rng(variant)
+    pieces = [wnd, 0, 0, wnd - 3, 3, 2 * wnd, 1, wnd - 1, 0, 5 * wnd + 7, 33, 31, 32, 64, 65, 0] + \
+             list(rng.integers(0, 70, 500)) + [1, 0, 0, 0]
+    lengths = np.array(pieces, dtype=np.int64)
+    rp = np.zeros(lengths.size + 1, np.int32)
+    np.cumsum(lengths, out=rp[1:])
+    n = lengths.size
+    ci = rng.integers(0, n, int(rp[-1])).astype(np.int32)
+    va = W.uniform_f32(variant + 1, ci.size)
+    x = W.uniform_f32(variant + 2, n)
+    prog = _spmv_program(rp, ci, va, x)
+    ref = T.spmv(rp, ci, va, x)
+    with D.Context() as ctx:
+        ctx.set_launch("spmv", 256, 0, variant)
+        from paper_2012_09646_amd import runner
+        b = runner.Bound(ctx, prog)
+        for _ in range(2):  # the second run reuses the row boundaries kept with rp
+            b.run()
+            y = b.read("y").view(np.float32)
+            assert np.all(y[lengths == 0] == 0.0)
+            bad = np.abs(y.astype(np.float64) - ref) > 1e-5 * np.abs(ref)
+            assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:5])
+        assert ctx.stats().spmv_plans == 1
 
 
 @pytest.mark.parametrize("policy,pool,batch", [
