@@ -958,6 +958,13 @@ __global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row
   const int k0 = static_cast<int>(min(static_cast<long long>(b) * W, static_cast<long long>(nnz)));
   const int k1 = static_cast<int>(min(static_cast<long long>(k0) + W, static_cast<long long>(nnz)));
   const int cnt = k1 - k0;
+  // the first 256 owned rows' bounds are loaded while the matrix is
+  const int r0 = own[b], r1 = own[b + 1];
+  int pre_s = 0, pre_e = 0;
+  if (r0 + tid < r1) {
+    pre_s = clamp_nnz(row_ptr[r0 + tid], nnz);
+    pre_e = clamp_nnz(row_ptr[r0 + tid + 1], nnz);
+  }
   int cidx[IPT];
   float v[IPT];
 #pragma unroll
@@ -979,15 +986,16 @@ __global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row
     const int i = tid + j * 256;
     if (i < cnt) s_prod[i] = static_cast<double>(v[j]) * static_cast<double>(xv[j]);
   }
-  const int r0 = own[b], r1 = own[b + 1];
   if (tid == 0) s_nlong = 0;
   __syncthreads();
-  // local [start, end) of row r's nonzeros inside the tile; e = global end
-  auto local_range = [&](int r, int* ls, int* le, int* e) {
-    const int s0 = clamp_nnz(row_ptr[r], nnz);
-    *e = clamp_nnz(row_ptr[r + 1], nnz);
+  // local [start, end) of a row's nonzeros [s0, e) inside the tile
+  auto clip = [&](int s0, int e, int* ls, int* le) {
     *ls = min(max(s0, k0), k1) - k0;
-    *le = max(min(max(*e, k0), k1) - k0, *ls);
+    *le = max(min(max(e, k0), k1) - k0, *ls);
+  };
+  auto local_range = [&](int r, int* ls, int* le, int* e) {
+    *e = clamp_nnz(row_ptr[r + 1], nnz);
+    clip(clamp_nnz(row_ptr[r], nnz), *e, ls, le);
   };
   if (wv == 0) {
     const int hend = min(max(r0 < nrows ? clamp_nnz(row_ptr[r0], nnz) : nnz, k0), k1);
@@ -1006,7 +1014,12 @@ __global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row
     const int r = c + tid;
     if (r < r1) {
       int ls, le, e;
-      local_range(r, &ls, &le, &e);
+      if (c == r0) {
+        e = pre_e;
+        clip(pre_s, pre_e, &ls, &le);
+      } else {
+        local_range(r, &ls, &le, &e);
+      }
       if (le - ls <= kShortRow) {
         double acc = 0.0;
         for (int i = ls; i < le; ++i) acc += s_prod[i];
