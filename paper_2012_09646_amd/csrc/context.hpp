@@ -120,6 +120,7 @@ struct dag_ctx_s {
   uint64_t* sig_dev = nullptr;
   uint32_t* sig_timed_out = nullptr;      // pinned host word raised by a wait that gave up
   std::vector<uint64_t> sig_next, sig_raised;
+  std::vector<std::vector<uint32_t>> tail_writes;  // per stream: buffers its last signalled task wrote
   std::vector<uint64_t> tsig;
   std::vector<hipEvent_t> mark_ev;
   uint64_t n_signals = 0, n_signal_waits = 0;

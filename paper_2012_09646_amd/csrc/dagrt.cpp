@@ -99,6 +99,7 @@ dag_status ensure_stream(dag_ctx c, int32_t s) {
     c->scratch.push_back(scr);
     c->sig_next.push_back(0);
     c->sig_raised.push_back(0);
+    c->tail_writes.emplace_back();
     c->mark_ev.push_back(nullptr);
   }
   return DAG_OK;
@@ -149,16 +150,32 @@ dag_status raise_signal(dag_ctx c, int32_t s) {
   return DAG_OK;
 }
 
+// Does the task with accesses accs touch every buffer the last signalled task
+// of stream s wrote?  Then a later reader of those buffers either reads this
+// task's result or runs alongside it, and waiting for this task as well
+// costs little.
+bool covers_tail(dag_ctx c, int32_t s, const std::vector<Access>& accs) {
+  for (uint32_t b : c->tail_writes[s]) {
+    bool hit = false;
+    for (const Access& a : accs) hit = hit || a.buf == b;
+    if (!hit) return false;
+  }
+  return true;
+}
+
 // Enqueue the waits of task id on its stream and (trace) its start event.
-// Signals are raised late: the one of the task before on this stream just
-// before this task when the pool has several streams (a consumer elsewhere
-// may need that task without this one), and any other when a consumer on
-// another stream first waits for it (at once if it is still the last task of
-// its stream; otherwise the raise also covers the tasks queued after it).
-// A one-stream pool thus raises signals only for its copy lanes.
+// Signals are raised late.  The one of the task before on this stream is
+// raised just before this task when the pool has several streams and this
+// task leaves some buffer that one wrote untouched (a consumer elsewhere may
+// need that buffer without this task); any other when a consumer on another
+// stream first waits for it (at once if it is still the last task of its
+// stream; otherwise the raise also covers the tasks queued after it).  A
+// chain whose tasks consume their predecessors' outputs, and a one-stream
+// pool, thus raise signals only where another stream waits.
 // With dispatch_timed, the start (and kernel-end) events are attached to the
 // task's kernel dispatches instead of being recorded as separate markers.
-dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = false) {
+dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, const std::vector<Access>& accs,
+                      bool dispatch_timed = false) {
   if (c->dry) return DAG_OK;
   const TaskRec& t = c->tr.task(id);
   if (c->roctx_push) {
@@ -169,7 +186,8 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, bool dispatch_timed = f
                   static_cast<unsigned long long>(id), what, s, t.wait_n);
     c->roctx_push(name);
   }
-  if (c->signals && c->cfg.max_streams > 1 && static_cast<uint32_t>(s) < kSignalSlots) {
+  if (c->signals && c->cfg.max_streams > 1 && static_cast<uint32_t>(s) < kSignalSlots &&
+      c->sig_raised[s] < c->sig_next[s] && !covers_tail(c, s, accs)) {
     dag_status st = raise_signal(c, s);
     if (st) return st;
   }
@@ -231,7 +249,13 @@ dag_status end_task(dag_ctx c, uint64_t id, int32_t s, bool on_cus) {
   if (c->dry) return DAG_OK;
   const uint64_t k = id - c->ev_base;
   const bool sig = c->signals && on_cus && static_cast<uint32_t>(s) < kSignalSlots;
-  if (sig) c->tsig[k] = ++c->sig_next[s];  // raised when first needed
+  if (sig) {
+    c->tsig[k] = ++c->sig_next[s];  // raised when first needed
+    std::vector<uint32_t>& tw = c->tail_writes[s];
+    tw.clear();
+    for (const Access& a : c->tmp_acc)
+      if (a.acc == ACC_W) tw.push_back(a.buf);
+  }
   if (!sig || traced(c, id)) {
     hipEvent_t e;
     dag_status st = get_event(c, traced(c, id), &e);
@@ -446,7 +470,7 @@ dag_status submit_kernel(dag_ctx c, uint32_t kid, const void* params, size_t pby
   if (st) return st;
   const auto t1 = Clock::now();
   const bool dispatch_timed = kd && (c->cfg.trace == 1 || c->cfg.trace == 2);
-  st = begin_task(c, id, s, dispatch_timed);
+  st = begin_task(c, id, s, c->tmp_acc, dispatch_timed);
   if (st) return st;
   if (c->fault_at && ++c->n_launches == c->fault_at) {
     set_launch_events(nullptr, nullptr);
@@ -533,7 +557,7 @@ dag_status submit_copy(dag_ctx c, dag_buf dst, size_t doff, dag_buf src, size_t 
   dag_status st = ensure_stream(c, s);
   if (st) return st;
   const auto t1 = Clock::now();
-  st = begin_task(c, id, s);
+  st = begin_task(c, id, s, c->tmp_acc);
   if (st) return st;
   void* dp = static_cast<char*>(bd->ptr) + doff;
   const void* sp = static_cast<const char*>(bs->ptr) + soff;
@@ -1345,7 +1369,7 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
   dag_status st = ensure_stream(c, s);
   if (st) return st;
   const auto t1 = Clock::now();
-  st = begin_task(c, id, s);
+  st = begin_task(c, id, s, r->accs);
   if (st) return st;
   if (!c->dry) {
     if (r->exec) {
