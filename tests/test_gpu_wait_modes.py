@@ -130,3 +130,37 @@ def test_one_stream_pool_raises_no_signal():
             assert st.signals == 0 and st.waits == 0 and st.streams == 1
         finally:
             ctx.close()
+
+
+def test_wide_join_waits_for_ten_streams():
+    """A task that joins ten branches, each on its own stream, places nine
+    waits: more than one poll kernel holds (eight), so two are queued.  The
+    timing events show it starting after every branch ended (each branch is
+    a delay of a different length, then x_i <- x_i^2), and the outputs equal
+    the oracle's."""
+    banner("ten-way join")
+    n = (1 << 16) + 3
+    bufs = {"x%d" % i: W.Buf(4 * n, init=W.uniform_f32(40 + i, n)) for i in range(10)}
+    bufs.update(z=W.Buf(4), r=W.Buf(4))
+    ops = []
+    for i in range(10):
+        ops += [W.K("spin", [("x%d" % i, "m")], ns=100_000 + 40_000 * ((7 * i) % 10)),
+                W.K("vec_square", [("x%d" % i, "m")], n=n)]
+    ops.append(W.K("spin", [("x%d" % i, "c") for i in range(10)] + [("z", "m")], ns=0))
+    ops.append(W.K("vec_sum_diff", [("x0", "c"), ("x9", "c"), ("r", "m")], n=n))
+    ops.append(W.HR("r"))
+    prog = W.Program("join10", bufs, ops, ["x%d" % i for i in range(10)] + ["r"], "r")
+    ref = G.oracle_run(prog)
+    with D.Context(max_streams=16, trace=1) as ctx:
+        b = runner.Bound(ctx, prog)
+        D.dag_trace_reset(ctx.h)
+        b.run()
+        join = 21  # position of the joining task
+        info = {p: ctx.info(b.base + p) for p in range(1, len(ops) + 1)}
+        assert info[join].nwaits == 9
+        assert len({info[2 * i + 2].stream for i in range(10)}) == 10
+        last_branch_end = max(info[2 * i + 2].t_end_ms for i in range(10))
+        assert info[join].t_start_ms >= last_branch_end - 1e-6
+        assert ctx.stats().signal_waits >= 9
+        for out in prog.outputs:
+            G.assert_close(prog, out, b.read(out), ref[out])
