@@ -83,6 +83,9 @@ def size_key(op):
     return ",".join("%s=%s" % (k, p[k]) for k in sorted(p) if k in ("n", "w", "h", "nrows", "nnz", "ksize"))
 
 
+ONE_LAUNCH_VARIANT = ("vec_sum_diff", "minmax", "sumsq")  # variant 0: two kernels, 1: one
+
+
 def tune_kernels(ctx, prog, reps=20, log=None):
     """Tune every tunable kernel of `prog` in context `ctx`; installs the
     winners in ctx and returns {kernel: entry}."""
@@ -112,6 +115,14 @@ def tune_kernels(ctx, prog, reps=20, log=None):
         # is fastest alone may leave no room for a concurrent kernel
         near = sorted((i for i in valid if i != best and total[i] <= total[best] * (1 + NEAR_TIE)),
                       key=lambda i: total[i])[:3]
+        # a reduction finished by its last workgroup (variant 1) saves a launch, which in a DAG of short
+        # kernels can matter more than its time alone: its fastest form is always tried in the DAG
+        if k in ONE_LAUNCH_VARIANT and cands[best][2] != 1:
+            ones = [i for i in valid if cands[i][2] == 1]
+            if ones:
+                f = min(ones, key=lambda i: total[i])
+                if f not in near:
+                    near.append(f)
         out[k] = {"block": cands[best][0], "grid_cap": cands[best][1], "variant": cands[best][2],
                   "us": total[best] / len(ops), "size": size_key(ops[0]), "launches": len(ops),
                   "default_us": (total[di] / len(ops)) if di is not None and total[di] >= 0 else None,
