@@ -893,7 +893,8 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ row_
 }
 
 // Row-window SpMV (the launch variants 0x100 | IPT; 0x200 added: the column
-// indices and values are read with non-temporal loads).  Tile b covers the
+// indices and values are read with non-temporal loads; 0x400: the resident
+// grid form below).  Tile b covers the
 // nonzeros [b*W, min((b+1)*W, nnz)), W = 256 * IPT, and owns the rows that
 // start in that window (own[b] <= r < own[b+1]; the last tile also owns the
 // rows that start at nnz).  The tile's products are formed coalesced (IPT
@@ -944,6 +945,86 @@ __global__ __launch_bounds__(256) void k_spmv_window_partition(const int* __rest
   if ((threadIdx.x & (kWave - 1)) == 0) own[b] = r;
 }
 
+// The row phase of a row-window tile whose products are in s_prod: the
+// tile's head part (wave 0), then its owned rows r0 .. r1 - 1.  The values
+// it needs first come in with the matrix: pre_s, pre_e are the bounds of row
+// r0 + tid and head_end the start of row r0 (nnz if r0 = nrows), so the
+// usual tile makes no global load here (rows past the first 256 load their
+// bounds).  Long rows are handed to the waves through LDS with their bounds
+// (s_long: 4 ints each).  Every thread takes part (the barriers inside are
+// reached by all).
+__device__ __forceinline__ void spmv_window_rows(const int* __restrict__ row_ptr, float* __restrict__ y, int nrows,
+                                                 int nnz, int b, int k0, int k1, int r0, int r1, int pre_s,
+                                                 int pre_e, int head_end, const double* s_prod, int* s_long,
+                                                 int* s_nlong, SpmvWindowScratch sc) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  // local [start, end) of a row's nonzeros [s0, e) inside the tile
+  auto clip = [&](int s0, int e, int* ls, int* le) {
+    *ls = min(max(s0, k0), k1) - k0;
+    *le = max(min(max(e, k0), k1) - k0, *ls);
+  };
+  auto local_range = [&](int r, int* ls, int* le, int* e) {
+    *e = clamp_nnz(row_ptr[r + 1], nnz);
+    clip(clamp_nnz(row_ptr[r], nnz), *e, ls, le);
+  };
+  if (wv == 0) {
+    const int hend = min(max(head_end, k0), k1);
+    double h = 0.0;
+    for (int i = lane; i < hend - k0; i += kWave) h += s_prod[i];
+    h = wave_sum(h);
+    if (lane == 0) {
+      sc.head_val[b] = h;
+      // the head part ends its row here unless the row runs on past the tile
+      const bool has_head = b > 0 && r0 > 0 && hend > k0;
+      const bool ends_here = head_end <= k1;
+      sc.head_row[b] = has_head && ends_here ? r0 - 1 : -1;
+    }
+  }
+  for (int c = r0; c < r1; c += 256) {
+    const int r = c + tid;
+    if (r < r1) {
+      int ls, le, e;
+      if (c == r0) {
+        e = pre_e;
+        clip(pre_s, pre_e, &ls, &le);
+      } else {
+        local_range(r, &ls, &le, &e);
+      }
+      if (le - ls <= kShortRow) {
+        double acc = 0.0;
+        for (int i = ls; i < le; ++i) acc += s_prod[i];
+        if (e <= k1)
+          y[r] = static_cast<float>(acc);
+        else
+          sc.tail_val[b] = acc;
+      } else {
+        int* slot = s_long + 4 * atomicAdd(s_nlong, 1);
+        slot[0] = r;
+        slot[1] = ls;
+        slot[2] = le;
+        slot[3] = e;
+      }
+    }
+    __syncthreads();
+    const int nl = *s_nlong;
+    for (int q = wv; q < nl; q += 256 / kWave) {
+      const int r2 = s_long[4 * q], ls = s_long[4 * q + 1], le = s_long[4 * q + 2], e = s_long[4 * q + 3];
+      double acc = 0.0;
+      for (int i = ls + lane; i < le; i += kWave) acc += s_prod[i];
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        if (e <= k1)
+          y[r2] = static_cast<float>(acc);
+        else
+          sc.tail_val[b] = acc;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) *s_nlong = 0;
+    __syncthreads();
+  }
+}
+
 template <int IPT, bool kStream>
 __global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row_ptr, const int* __restrict__ col,
                                                      const float* __restrict__ val, const float* __restrict__ x,
@@ -951,9 +1032,9 @@ __global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row
                                                      const int* __restrict__ own, SpmvWindowScratch sc) {
   constexpr int W = 256 * IPT;
   __shared__ double s_prod[W];
-  __shared__ int s_long[256];
+  __shared__ int s_long[4 * 256];
   __shared__ int s_nlong;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int tid = threadIdx.x;
   const int b = blockIdx.x;
   const int k0 = static_cast<int>(min(static_cast<long long>(b) * W, static_cast<long long>(nnz)));
   const int k1 = static_cast<int>(min(static_cast<long long>(k0) + W, static_cast<long long>(nnz)));
@@ -965,6 +1046,7 @@ __global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row
     pre_s = clamp_nnz(row_ptr[r0 + tid], nnz);
     pre_e = clamp_nnz(row_ptr[r0 + tid + 1], nnz);
   }
+  const int head_end = r0 < nrows ? clamp_nnz(row_ptr[r0], nnz) : nnz;
   int cidx[IPT];
   float v[IPT];
 #pragma unroll
@@ -988,68 +1070,89 @@ __global__ __launch_bounds__(256) void k_spmv_window(const int* __restrict__ row
   }
   if (tid == 0) s_nlong = 0;
   __syncthreads();
-  // local [start, end) of a row's nonzeros [s0, e) inside the tile
-  auto clip = [&](int s0, int e, int* ls, int* le) {
-    *ls = min(max(s0, k0), k1) - k0;
-    *le = max(min(max(e, k0), k1) - k0, *ls);
+  spmv_window_rows(row_ptr, y, nrows, nnz, b, k0, k1, r0, r1, pre_s, pre_e, head_end, s_prod, s_long, &s_nlong, sc);
+}
+
+// The same tiles, a resident grid looping over them: while one tile's rows
+// are summed from LDS, the matrix, row bounds and owned-row range of the
+// workgroup's next tile are already being loaded (variant bit 0x400).
+template <int IPT>
+__global__ __launch_bounds__(256) void k_spmv_window_pf(const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                                        const float* __restrict__ val, const float* __restrict__ x,
+                                                        float* __restrict__ y, int nrows, int ncols, int nnz,
+                                                        const int* __restrict__ own, int ntiles,
+                                                        SpmvWindowScratch sc) {
+  constexpr int W = 256 * IPT;
+  __shared__ double s_prod[W];
+  __shared__ int s_long[4 * 256];
+  __shared__ int s_nlong;
+  const int tid = threadIdx.x;
+  auto window = [&](int t, int* k0, int* k1) {
+    *k0 = static_cast<int>(min(static_cast<long long>(t) * W, static_cast<long long>(nnz)));
+    *k1 = static_cast<int>(min(static_cast<long long>(*k0) + W, static_cast<long long>(nnz)));
   };
-  auto local_range = [&](int r, int* ls, int* le, int* e) {
-    *e = clamp_nnz(row_ptr[r + 1], nnz);
-    clip(clamp_nnz(row_ptr[r], nnz), *e, ls, le);
+  // tile t's matrix slice, owned rows and the bounds the row phase starts with
+  auto load = [&](int t, int (&ci)[IPT], float (&vv)[IPT], int* r0, int* r1, int* ps, int* pe, int* he) {
+    int k0, k1;
+    window(t, &k0, &k1);
+    const int cnt = k1 - k0;
+    *r0 = own[t];
+    *r1 = own[t + 1];
+    *ps = 0;
+    *pe = 0;
+    if (*r0 + tid < *r1) {
+      *ps = clamp_nnz(row_ptr[*r0 + tid], nnz);
+      *pe = clamp_nnz(row_ptr[*r0 + tid + 1], nnz);
+    }
+    *he = *r0 < nrows ? clamp_nnz(row_ptr[*r0], nnz) : nnz;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int i = tid + j * 256;
+      ci[j] = i < cnt ? col[k0 + i] : 0;
+      vv[j] = i < cnt ? val[k0 + i] : 0.0f;
+    }
   };
-  if (wv == 0) {
-    const int hend = min(max(r0 < nrows ? clamp_nnz(row_ptr[r0], nnz) : nnz, k0), k1);
-    double h = 0.0;
-    for (int i = lane; i < hend - k0; i += kWave) h += s_prod[i];
-    h = wave_sum(h);
-    if (lane == 0) {
-      sc.head_val[b] = h;
-      // the head part ends its row here unless the row runs on past the tile
-      const bool has_head = b > 0 && r0 > 0 && hend > k0;
-      const bool ends_here = r0 < nrows ? clamp_nnz(row_ptr[r0], nnz) <= k1 : nnz <= k1;
-      sc.head_row[b] = has_head && ends_here ? r0 - 1 : -1;
+  int cidx[IPT];
+  float v[IPT];
+  int r0 = 0, r1 = 0, ps = 0, pe = 0, he = 0;
+  int b = blockIdx.x;
+  if (b < ntiles) load(b, cidx, v, &r0, &r1, &ps, &pe, &he);
+  if (tid == 0) s_nlong = 0;
+  for (; b < ntiles; b += gridDim.x) {
+    int k0, k1;
+    window(b, &k0, &k1);
+    const int cnt = k1 - k0;
+    float xv[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) xv[j] = x[min(max(cidx[j], 0), ncols - 1)];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int i = tid + j * 256;
+      if (i < cnt) s_prod[i] = static_cast<double>(v[j]) * static_cast<double>(xv[j]);
     }
-  }
-  for (int c = r0; c < r1; c += 256) {
-    const int r = c + tid;
-    if (r < r1) {
-      int ls, le, e;
-      if (c == r0) {
-        e = pre_e;
-        clip(pre_s, pre_e, &ls, &le);
-      } else {
-        local_range(r, &ls, &le, &e);
-      }
-      if (le - ls <= kShortRow) {
-        double acc = 0.0;
-        for (int i = ls; i < le; ++i) acc += s_prod[i];
-        if (e <= k1)
-          y[r] = static_cast<float>(acc);
-        else
-          sc.tail_val[b] = acc;
-      } else {
-        s_long[atomicAdd(&s_nlong, 1)] = r;
-      }
+    const int nb = b + static_cast<int>(gridDim.x);
+    int ncidx[IPT];
+    float nv[IPT];
+    int nr0 = 0, nr1 = 0, nps = 0, npe = 0, nhe = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      ncidx[j] = 0;
+      nv[j] = 0.0f;
     }
+    if (nb < ntiles) load(nb, ncidx, nv, &nr0, &nr1, &nps, &npe, &nhe);
     __syncthreads();
-    const int nl = s_nlong;
-    for (int q = wv; q < nl; q += 256 / kWave) {
-      const int r2 = s_long[q];
-      int ls, le, e;
-      local_range(r2, &ls, &le, &e);
-      double acc = 0.0;
-      for (int i = ls + lane; i < le; i += kWave) acc += s_prod[i];
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        if (e <= k1)
-          y[r2] = static_cast<float>(acc);
-        else
-          sc.tail_val[b] = acc;
-      }
+    spmv_window_rows(row_ptr, y, nrows, nnz, b, k0, k1, r0, r1, ps, pe, he, s_prod, s_long, &s_nlong, sc);
+    __syncthreads();  // s_prod is rewritten by the next tile
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      cidx[j] = ncidx[j];
+      v[j] = nv[j];
     }
-    __syncthreads();
-    if (tid == 0) s_nlong = 0;
-    __syncthreads();
+    r0 = nr0;
+    r1 = nr1;
+    ps = nps;
+    pe = npe;
+    he = nhe;
   }
 }
 
@@ -2170,9 +2273,11 @@ const char* cfg_spmv(const LaunchCfg& c) {
   if (c.grid_cap != 0) return "grid_cap must be 0";
   const uint32_t ipt = c.variant & 0xffu;
   if (c.variant & 0x100u) {
-    if (c.variant > 0x3ffu || (ipt != 4 && ipt != 8 && ipt != 16))
+    const uint32_t mode = c.variant & 0x600u;
+    if (c.variant > 0x7ffu || (ipt != 4 && ipt != 8 && ipt != 16) || mode == 0x600u || (mode == 0x400u && ipt == 16))
       return "row-window SpMV variant must be 0x100 | 4, 8 or 16 (nonzeros per thread), plus 0x200 for "
-             "streaming loads of the matrix";
+             "streaming loads of the matrix or 0x400 (4 or 8 per thread) for a resident grid that loads each "
+             "workgroup's next tile early";
     return nullptr;
   }
   if (c.variant != 4 && c.variant != 8 && c.variant != 12 && c.variant != 16)
@@ -2524,6 +2629,19 @@ void launch_spmv_window(hipStream_t s, void* const* a, const dag_p_csr* q, const
                static_cast<int>(q->nnz), own, sc);
 }
 
+// Compute units of the current device (cached per device ordinal).
+int device_cus() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 // Row-window products and fix-up over the row boundaries in own.
 hipError_t spmv_window_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, uint32_t variant, int tiles,
                              const int* own, void* scr) {
@@ -2533,6 +2651,30 @@ hipError_t spmv_window_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, 
   sc.tail_val = c.tail_val;
   sc.head_row = c.head_row;
   const bool stream = (variant & 0x200u) != 0;
+  if (variant & 0x400u) {
+    // resident grid: as many workgroups as fit on the GPU at once, never more than the tiles
+    // resident workgroups per CU, from the occupancy calculator (once per kernel)
+    static int per_cu[2] = {0, 0};
+    const int which = (variant & 0xffu) == 8 ? 1 : 0;
+    if (per_cu[which] == 0) {
+      const void* kf[2] = {reinterpret_cast<const void*>(&k_spmv_window_pf<4>),
+                           reinterpret_cast<const void*>(&k_spmv_window_pf<8>)};
+      int n = 0;
+      const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kf[which], 256, 0);
+      per_cu[which] = (oe == hipSuccess && n > 0) ? n : 4;
+    }
+    const int grid = std::max(1, std::min(tiles, per_cu[which] * device_cus()));
+    if ((variant & 0xffu) == 8)
+      DAGRT_LAUNCH(k_spmv_window_pf<8>, dim3(grid), dim3(256), 0, s, static_cast<const int*>(a[0]),
+                   static_cast<const int*>(a[1]), static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
+                   static_cast<float*>(a[4]), static_cast<int>(q->nrows), static_cast<int>(q->ncols),
+                   static_cast<int>(q->nnz), own, tiles, sc);
+    else
+      DAGRT_LAUNCH(k_spmv_window_pf<4>, dim3(grid), dim3(256), 0, s, static_cast<const int*>(a[0]),
+                   static_cast<const int*>(a[1]), static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
+                   static_cast<float*>(a[4]), static_cast<int>(q->nrows), static_cast<int>(q->ncols),
+                   static_cast<int>(q->nnz), own, tiles, sc);
+  } else
   switch (variant & 0xffu) {
     case 4:
       stream ? launch_spmv_window<4, true>(s, a, q, own, sc, tiles) : launch_spmv_window<4, false>(s, a, q, own, sc, tiles);

@@ -25,7 +25,7 @@ def spmv_bounds(args, n=1 << 20, deg=20):
     same shape and nonzero count as HITS' but different column patterns:
     sequential columns (every gather of x coalesced: the streaming floor),
     uniformly random columns (every gather a separate cache line: the random
-    gather bound), and A^T itself.  Each matrix gets its own context; its
+    gather bound), and A^T and A themselves.  Each matrix gets its own context; its
     SpMVs run back to back after one partition."""
     import numpy as np
     nnz = n * deg
@@ -35,6 +35,7 @@ def spmv_bounds(args, n=1 << 20, deg=20):
             ("uniform", rp, g.integers(0, n, nnz).astype(np.int32))]
     gr = W.hits_graph(n, deg, 3)
     mats.append(("hits_at", gr["at_ptr"], gr["at_col"]))
+    mats.append(("hits_a", gr["a_ptr"], gr["a_col"]))
     val = np.ones(nnz, np.float32)
     x = W.uniform_f32(18, n)
     order = []
@@ -66,8 +67,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="bs", choices=["vec", "bs", "img", "hits", "ml", "dl", "spmv_bounds"],
                     help="spmv_bounds: the SpMV kernel alone on three matrices of 2^20 rows x 20 nonzeros "
-                         "(sequential columns, uniformly random columns, HITS' A^T), runs times each in that "
-                         "order")
+                         "(sequential columns, uniformly random columns, HITS' A^T and A), runs times each in "
+                         "that order")
     ap.add_argument("--runs", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--copies", type=int, default=3)

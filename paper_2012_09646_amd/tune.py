@@ -47,8 +47,9 @@ def candidates(kernel):
     if kernel in ("vec_sum_diff", "minmax", "sumsq"):
         return [(b, c, v) for b in (256, 512, 1024) for c in (64, 128, 256, 512, 1024, 2048) for v in (0, 1)]
     if kernel == "spmv":
-        # merge-path items per thread, or 0x100 | nonzeros per thread of the row-window form
-        return [(256, 0, v) for v in (4, 8, 12, 16, 0x104, 0x108, 0x110)]
+        # merge-path items per thread, or 0x100 | nonzeros per thread of the row-window form (0x400: resident
+        # grid loading each workgroup's next tile early)
+        return [(256, 0, v) for v in (4, 8, 12, 16, 0x104, 0x108, 0x110, 0x504, 0x508)]
     if kernel == "spmv_rows":
         return [(256, c, v) for v in (4, 8, 16, 32) for c in (0, 2048, 8192)]
     if kernel in ("gauss_blur", "sobel"):

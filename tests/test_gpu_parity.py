@@ -164,7 +164,7 @@ def _spmv_program(rp, ci, va, x):
     return W.Program("spmv", bufs, ops, ["y"])
 
 
-@pytest.mark.parametrize("variant", [4, 8, 12, 16, 0x104, 0x108, 0x110])
+@pytest.mark.parametrize("variant", [4, 8, 12, 16, 0x104, 0x108, 0x110, 0x504, 0x508])
 def test_spmv_long_rows_and_empty_rows(variant):
     banner("spmv variant=%d" % variant)
     n = 50000
@@ -255,7 +255,7 @@ def test_spmv_no_nonzeros():
     prog = _spmv_program(rp, np.zeros(0, np.int32), np.zeros(0, np.float32), W.uniform_f32(1, n))
     out = G.check_program(prog)
     assert np.all(out["y"].view(np.float32) == 0)
-    for variant in (0x104, 0x110):
+    for variant in (0x104, 0x110, 0x504):
         with D.Context() as ctx:
             ctx.set_launch("spmv", 256, 0, variant)
             from paper_2012_09646_amd import runner
@@ -264,7 +264,7 @@ def test_spmv_no_nonzeros():
             assert np.all(b.read("y").view(np.float32) == 0)
 
 
-@pytest.mark.parametrize("variant", [0x104, 0x108, 0x110])
+@pytest.mark.parametrize("variant", [0x104, 0x108, 0x110, 0x504, 0x508])
 def test_spmv_rows_on_window_edges(variant):
     """Row-window SpMV with rows that end exactly where a window ends, rows of
     exactly one and several windows, runs of empty rows between them and at
