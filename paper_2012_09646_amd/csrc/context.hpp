@@ -86,6 +86,7 @@ constexpr uint32_t kMaxArgs = 16;
 // Wait mode 0: signal words (streams with a larger index end their tasks
 // with events) and the longest a device-side wait polls before giving up.
 constexpr uint32_t kSignalSlots = 128;
+constexpr uint32_t kAuxSlotBase = 96;  // words of the capture / replay streams (pool streams and lanes stay below)
 constexpr uint64_t kSignalTimeoutMs = 10000;
 constexpr size_t kStagingBytes = 64 << 10;
 
@@ -121,6 +122,7 @@ struct dag_ctx_s {
   uint32_t* sig_timed_out = nullptr;      // pinned host word raised by a wait that gave up
   std::vector<uint64_t> sig_next, sig_raised;
   std::vector<std::vector<uint32_t>> tail_writes;  // per stream: buffers its last signalled task wrote
+  std::vector<std::pair<uint32_t, uint64_t>> tmp_sig;  // replay: (word, value) raised after each waited-on task
   std::vector<uint64_t> tsig;
   std::vector<hipEvent_t> mark_ev;
   uint64_t n_signals = 0, n_signal_waits = 0;

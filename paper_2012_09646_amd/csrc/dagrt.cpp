@@ -97,8 +97,6 @@ dag_status ensure_stream(dag_ctx c, int32_t s) {
     HIP_TRY(c, hipStreamSynchronize(st));
     c->streams.push_back(st);
     c->scratch.push_back(scr);
-    c->sig_next.push_back(0);
-    c->sig_raised.push_back(0);
     c->tail_writes.emplace_back();
     c->mark_ev.push_back(nullptr);
   }
@@ -186,7 +184,7 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, const std::vector<Acces
                   static_cast<unsigned long long>(id), what, s, t.wait_n);
     c->roctx_push(name);
   }
-  if (c->signals && c->cfg.max_streams > 1 && static_cast<uint32_t>(s) < kSignalSlots &&
+  if (c->signals && c->cfg.max_streams > 1 && static_cast<uint32_t>(s) < kAuxSlotBase &&
       c->sig_raised[s] < c->sig_next[s] && !covers_tail(c, s, accs)) {
     dag_status st = raise_signal(c, s);
     if (st) return st;
@@ -248,7 +246,7 @@ dag_status begin_task(dag_ctx c, uint64_t id, int32_t s, const std::vector<Acces
 dag_status end_task(dag_ctx c, uint64_t id, int32_t s, bool on_cus) {
   if (c->dry) return DAG_OK;
   const uint64_t k = id - c->ev_base;
-  const bool sig = c->signals && on_cus && static_cast<uint32_t>(s) < kSignalSlots;
+  const bool sig = c->signals && on_cus && static_cast<uint32_t>(s) < kAuxSlotBase;
   if (sig) {
     c->tsig[k] = ++c->sig_next[s];  // raised when first needed
     std::vector<uint32_t>& tw = c->tail_writes[s];
@@ -848,9 +846,84 @@ void free_region(Region* r) {
 
 // Replay without a graph: fork from the macro task's stream onto auxiliary
 // streams, run the recorded calls with their intra-region waits, join back.
+static_assert(DAG_MAX_STREAMS + 2 * kMaxLanesPerDir <= kAuxSlotBase, "signal words of pool streams and lanes");
+
+// Recorded replay with completion signals (wait mode 0): the launch stream
+// keeps its own signal word, the capture/replay streams use words from
+// kAuxSlotBase on; every raise is queued at once (the replay knows which
+// tasks are waited on), and the fork, the waits on recorded dependencies and
+// the join are polls.
+dag_status replay_region_signals(dag_ctx c, Region* r, hipStream_t s, int32_t ps) {
+  auto word = [&](uint32_t slot) { return c->sig_dev + static_cast<uint64_t>(slot) * kSignalStride; };
+  auto raise_now = [&](hipStream_t st, uint32_t slot, uint64_t* v) -> hipError_t {
+    *v = ++c->sig_next[slot];
+    c->sig_raised[slot] = *v;
+    ++c->n_signals;
+    return signal_raise(st, word(slot), *v);
+  };
+  SignalWaits sw{};
+  sw.words = c->sig_dev;
+  sw.timed_out = c->sig_timed_out;
+  sw.max_ticks = c->sig_timeout_ms * wall_clock_ticks_per_ms();
+  auto add_wait = [&](hipStream_t st, uint32_t slot, uint64_t v) -> hipError_t {
+    sw.slot[sw.n] = slot;
+    sw.value[sw.n] = v;
+    ++c->n_signal_waits;
+    if (++sw.n < kMaxSignalWaits) return hipSuccess;
+    const hipError_t e = signal_wait(st, sw);
+    sw.n = 0;
+    return e;
+  };
+  auto flush = [&](hipStream_t st) {
+    const hipError_t e = signal_wait(st, sw);
+    sw.n = 0;
+    return e;
+  };
+  const uint32_t sslot = static_cast<uint32_t>(ps);
+  uint64_t fork_v = 0;
+  HIP_TRY(c, raise_now(s, sslot, &fork_v));
+  for (uint32_t i = 1; i < r->nstreams; ++i) {
+    HIP_TRY(c, add_wait(c->aux[i], sslot, fork_v));
+    HIP_TRY(c, flush(c->aux[i]));
+  }
+  std::vector<std::pair<uint32_t, uint64_t>>& tv = c->tmp_sig;
+  tv.assign(r->tasks.size(), {0u, 0u});
+  for (uint32_t k = 0; k < r->tasks.size(); ++k) {
+    const RegionTask& t = r->tasks[k];
+    hipStream_t ts = t.rstream == 0 ? s : c->aux[t.rstream];
+    const uint32_t slot = t.rstream == 0 ? sslot : kAuxSlotBase + t.rstream;
+    void* scr = t.rstream == 0 ? c->scratch[ps] : c->aux_scratch[t.rstream];
+    for (uint32_t w : t.rwaits) HIP_TRY(c, add_wait(ts, tv[w].first, tv[w].second));
+    HIP_TRY(c, flush(ts));
+    hipError_t e = launch_region_task(c, t, ts, scr);
+    if (e != hipSuccess) return hip_fail(c, e, "region replay launch");
+    if (t.waited_on) {
+      uint64_t v = 0;
+      HIP_TRY(c, raise_now(ts, slot, &v));
+      tv[k] = {slot, v};
+    }
+  }
+  for (uint32_t i = 1; i < r->nstreams; ++i) {
+    uint64_t v = 0;
+    HIP_TRY(c, raise_now(c->aux[i], kAuxSlotBase + i, &v));
+    HIP_TRY(c, add_wait(s, kAuxSlotBase + i, v));
+  }
+  HIP_TRY(c, flush(s));
+  return DAG_OK;
+}
+
 dag_status replay_region(dag_ctx c, Region* r, hipStream_t s, int32_t pool_stream) {
   dag_status st = ensure_aux(c, r->nstreams);
   if (st) return st;
+  // signals when every recorded task runs on the CUs: with SDMA copies in the
+  // region (host<->device copies of the Black-Scholes fan-out) a signal
+  // kernel behind each copy on its stream slowed the replay to the serial
+  // time, so such regions keep their events
+  bool on_cus = c->signals && static_cast<uint32_t>(pool_stream) < kAuxSlotBase &&
+                r->nstreams <= kSignalSlots - kAuxSlotBase;
+  for (const RegionTask& t : r->tasks)
+    if (t.kind == TK_COPY && !copy_runs_as_kernel(c, t.ckind)) on_cus = false;
+  if (on_cus) return replay_region_signals(c, r, s, pool_stream);
   if (r->evs.empty()) {
     r->evs.assign(r->tasks.size() + 2 * r->nstreams, nullptr);
     for (auto& e : r->evs) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -964,6 +1037,8 @@ dag_status dag_create(const dag_config* cfg, dag_ctx* out) {
       if (e == hipSuccess) {
         *x->sig_timed_out = 0;
         x->signals = true;
+        x->sig_next.assign(kSignalSlots, 0);
+        x->sig_raised.assign(kSignalSlots, 0);
       }
     }
     if (e == hipSuccess && c.trace) {
