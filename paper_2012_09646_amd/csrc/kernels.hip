@@ -2962,9 +2962,9 @@ hipError_t l_ensemble(hipStream_t s, void* const* a, const void* p, const Launch
 const char* cfg_conv(const LaunchCfg& c) {
   if (c.block != 256) return "this kernel runs 256-thread workgroups (16 x 16 pooled outputs)";
   if (c.grid_cap != 0) return "grid_cap must be 0";
-  if (c.variant > 3)
-    return "variant must be 0 (one channel at a time), 1 (channels pipelined), 2 (pipelined, scalar weights) "
-           "or 3 (fp64 matrix cores)";
+  if (c.variant > 4)
+    return "variant must be 0 (one channel at a time), 1 (channels pipelined), 2 (pipelined, scalar weights), "
+           "3 (fp64 matrix cores) or 4 (matrix cores, 16 output channels per workgroup)";
   return nullptr;
 }
 const dag_p_conv* pconv(const void* p) { return static_cast<const dag_p_conv*>(p); }
@@ -2996,9 +2996,11 @@ hipError_t l_conv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   const auto* w = static_cast<const float*>(a[1]);
   const auto* bias = static_cast<const float*>(a[2]);
   auto* y = static_cast<float*>(a[3]);
-  // variant 3: the matrix-core form where the channel counts allow it
-  // (conv_mfma_njb), else variant 1
-  const uint32_t njb = c.variant == 3 ? conv_mfma_njb(q->cin, q->cout) : 0;
+  // variants 3 and 4: the matrix-core form where the channel counts allow it
+  // (conv_mfma_njb; 4 with one block of 16 output channels per workgroup),
+  // else variant 1
+  uint32_t njb = c.variant >= 3 ? conv_mfma_njb(q->cin, q->cout) : 0;
+  if (c.variant == 4 && njb == 2) njb = 1;  // 16 output channels per workgroup: twice the workgroups
   if (njb) {
     const uint32_t mtx = static_cast<uint32_t>(ceil_div(q->w, kConvMfmaTile));
     const uint32_t mty = static_cast<uint32_t>(ceil_div(q->h, kConvMfmaTile));

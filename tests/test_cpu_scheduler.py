@@ -482,7 +482,8 @@ def test_dl_kernel_argument_checks():
     assert _status(ctx.set_launch, "conv3x3_relu_pool", 256, 0, 1) == "DAG_OK"
     assert _status(ctx.set_launch, "conv3x3_relu_pool", 256, 0, 2) == "DAG_OK"
     assert _status(ctx.set_launch, "conv3x3_relu_pool", 256, 0, 3) == "DAG_OK"
-    assert _status(ctx.set_launch, "conv3x3_relu_pool", 256, 0, 4) == "DAG_E_INVAL"
+    assert _status(ctx.set_launch, "conv3x3_relu_pool", 256, 0, 4) == "DAG_OK"
+    assert _status(ctx.set_launch, "conv3x3_relu_pool", 256, 0, 5) == "DAG_E_INVAL"
     assert _status(ctx.set_launch, "dense", 256, 1024, 2) == "DAG_OK"
     assert _status(ctx.set_launch, "dense", 256, 1024, 4) == "DAG_OK"
     assert _status(ctx.set_launch, "dense", 256, 1024, 5) == "DAG_E_INVAL"

@@ -109,10 +109,10 @@ def test_conv_launch_variants(variant, scratch, cin, cout, h, w):
                                           (3, 8, 34, 36), (16, 12, 20, 20)])
 def test_conv_matrix_core_variant(cin, cout, h, w):
     """Variant 3, the implicit GEMM on the fp64 matrix cores (16 x 16 tiles
-    of convolution outputs, 16 or 32 output channels per workgroup, weights
-    rearranged into the stream scratch by a first kernel), against the
-    oracle at 1e-5: ragged tiles, several channel counts, one and two
-    channel blocks, launched twice in a row (equal bit for bit).  Where the channel counts do not
+    of convolution outputs, 16 or 32 output channels per workgroup), against
+    the oracle at 1e-5: ragged tiles, several channel counts, one and two
+    channel blocks, launched twice in a row (equal bit for bit); variant 4
+    (always one block of 16 channels) equal to it bit for bit.  Where the channel counts do not
     allow it (cin % 4 != 0 or cout % 16 != 0) variant 1 runs instead and the
     result equals variant 1's bit for bit."""
     banner("conv mfma cin=%d cout=%d h=%d w=%d" % (cin, cout, h, w))
@@ -129,7 +129,7 @@ def test_conv_matrix_core_variant(cin, cout, h, w):
         ctx.host_write(hx, x)
         ctx.host_write(hw_, wt)
         ctx.host_write(hb, b)
-        for v in (3, 3, 1):
+        for v in (3, 3, 4, 1):
             ctx.host_write(hy, np.zeros(cout * (h // 2) * (w // 2), np.float32))
             ctx.set_launch("conv3x3_relu_pool", 256, 0, v)
             ctx.kernel("conv3x3_relu_pool", [(hx, "c"), (hw_, "c"), (hb, "c"), (hy, "m")],
@@ -143,6 +143,8 @@ def test_conv_matrix_core_variant(cin, cout, h, w):
     finally:
         ctx.close()
     assert np.array_equal(outs[3][0].view(np.uint32), outs[3][1].view(np.uint32))
+    # variant 4 (one block of 16 channels per workgroup) sums every output in variant 3's order
+    assert np.array_equal(outs[4][0].view(np.uint32), outs[3][0].view(np.uint32))
     if cin % 4 or cout % 16:
         assert np.array_equal(outs[3][0].view(np.uint32), outs[1][0].view(np.uint32))
 
