@@ -462,24 +462,70 @@ __device__ __forceinline__ void stage_tile(const float* __restrict__ in, float (
   }
 }
 
-// Separable Gaussian: stage the input tile with its halo in LDS (fp32, as
-// stored), horizontal pass into an fp64 LDS tile, vertical pass to output.
+// A 64-wide tile's rows with their halo held in registers: the same lane and
+// row assignment as stage_tile's 64-wide path (lane = column, wave = every
+// NW-th row), so that the loads of the next tile can be in flight while the
+// current one is computed from LDS.
+template <int R, int TH, int NT>
+struct TileRows {
+  static constexpr int NW = NT / 64;
+  static constexpr int IH = TH + 2 * R;
+  static constexpr int RPW = (IH + NW - 1) / NW;
+  static_assert(NT % 64 == 0 && 2 * R <= 64, "64-wide tiles with at most 64 halo columns");
+  float m[RPW];
+  float hl[RPW];
+  __device__ __forceinline__ void load(const float* __restrict__ in, int w, int h, int x0, int y0) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gx_main = min(max(x0 - R + lane, 0), w - 1);
+    const int gx_halo = min(max(x0 - R + 64 + lane, 0), w - 1);
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int r = wv + NW * k;
+      if (r < IH) {
+        const float* row = in + static_cast<size_t>(min(max(y0 - R + r, 0), h - 1)) * w;
+        m[k] = row[gx_main];
+        if (lane < 2 * R) hl[k] = row[gx_halo];
+      }
+    }
+  }
+  template <int SW>
+  __device__ __forceinline__ void store(float (*s)[SW]) const {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int r = wv + NW * k;
+      if (r < IH) {
+        s[r][lane] = m[k];
+        if (lane < 2 * R) s[r][64 + lane] = hl[k];
+      }
+    }
+  }
+};
+
+// Resident grid over 64-wide tiles: gridDim.x is a multiple of 8 and block b
+// runs on XCD b % 8, which walks its contiguous run of row-major tiles (as in
+// tile_of's xcd_map = 1) with gridDim.x / 8 workgroups side by side.
+struct ResidentTiles {
+  int t, end, step;
+  __device__ __forceinline__ explicit ResidentTiles(int ntiles) {
+    const int per = (ntiles + 7) / 8;
+    const int xcd = static_cast<int>(blockIdx.x % 8);
+    t = xcd * per + static_cast<int>(blockIdx.x / 8);
+    end = min(ntiles, (xcd + 1) * per);
+    step = static_cast<int>(gridDim.x / 8);
+  }
+};
+
+// The blur's two passes over a staged tile: horizontal into the fp64 tile
+// s_h, barrier, vertical to the output.
 template <int R, int TW, int TH>
-__global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_gauss_blur(const float* __restrict__ in,
-                                                                          float* __restrict__ out, int w, int h,
-                                                                          GaussW wt, int tiles_x, int ntiles,
-                                                                          int xcd_map) {
+__device__ __forceinline__ void blur_passes(const float (*s_in)[TW + 2 * R], double (*s_h)[TW],
+                                            float* __restrict__ out, int w, int h, const GaussW& wt, int x0,
+                                            int y0) {
   constexpr int G = kRowsPerThread;
   constexpr int NT = TW * TH / G;
   constexpr int K = 2 * R + 1;
-  constexpr int IW = TW + 2 * R;
   constexpr int IH = TH + 2 * R;
-  __shared__ float s_in[IH][IW];
-  __shared__ double s_h[IH][TW];
-  int x0, y0;
-  if (!tile_of<TW, TH>(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
-  stage_tile<R, TW, IH, IW, NT>(in, s_in, w, h, x0, y0);
-  __syncthreads();
   // horizontal pass: each work item produces 4 adjacent outputs of one row
   // from one register window of 4 + 2R inputs (4x fewer LDS reads)
   for (int item = threadIdx.x; item < IH * (TW / G); item += NT) {
@@ -513,20 +559,59 @@ __global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_gauss_blur(const f
   }
 }
 
-// Sobel gradient magnitude sqrt(gx^2 + gy^2), gx with [[-1,0,1],[-2,0,2],
-// [-1,0,1]] (correlation), gy with its transpose.
-template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_sobel(const float* __restrict__ in,
-                                                                     float* __restrict__ out, int w, int h,
-                                                                     int tiles_x, int ntiles, int xcd_map) {
-  constexpr int G = kRowsPerThread;
-  constexpr int NT = TW * TH / G;
-  constexpr int IW = TW + 2, IH = TH + 2;
+// Separable Gaussian: stage the input tile with its halo in LDS (fp32, as
+// stored), horizontal pass into an fp64 LDS tile, vertical pass to output.
+template <int R, int TW, int TH>
+__global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_gauss_blur(const float* __restrict__ in,
+                                                                          float* __restrict__ out, int w, int h,
+                                                                          GaussW wt, int tiles_x, int ntiles,
+                                                                          int xcd_map) {
+  constexpr int NT = TW * TH / kRowsPerThread;
+  constexpr int IW = TW + 2 * R;
+  constexpr int IH = TH + 2 * R;
   __shared__ float s_in[IH][IW];
+  __shared__ double s_h[IH][TW];
   int x0, y0;
   if (!tile_of<TW, TH>(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
-  stage_tile<1, TW, IH, IW, NT>(in, s_in, w, h, x0, y0);
+  stage_tile<R, TW, IH, IW, NT>(in, s_in, w, h, x0, y0);
   __syncthreads();
+  blur_passes<R, TW, TH>(s_in, s_h, out, w, h, wt, x0, y0);
+}
+
+// The same blur on a resident grid (64-wide tiles): each workgroup walks its
+// XCD's tiles, holding the next tile's rows in registers while it computes
+// the current one, so that the loads overlap the arithmetic.
+template <int R, int TH>
+__global__ __launch_bounds__(64 * TH / kRowsPerThread) void k_gauss_blur_rt(const float* __restrict__ in,
+                                                                             float* __restrict__ out, int w, int h,
+                                                                             GaussW wt, int tiles_x, int ntiles) {
+  constexpr int TW = 64;
+  constexpr int NT = TW * TH / kRowsPerThread;
+  constexpr int IH = TH + 2 * R;
+  __shared__ float s_in[IH][TW + 2 * R];
+  __shared__ double s_h[IH][TW];
+  ResidentTiles it(ntiles);
+  TileRows<R, TH, NT> next;
+  if (it.t < it.end) next.load(in, w, h, (it.t % tiles_x) * TW, (it.t / tiles_x) * TH);
+  for (; it.t < it.end; it.t += it.step) {  // uniform per workgroup
+    const int x0 = (it.t % tiles_x) * TW, y0 = (it.t / tiles_x) * TH;
+    // every thread left the previous tile's horizontal pass (the barrier in
+    // blur_passes) before any writes s_in, and its vertical pass before the
+    // barrier below, after which s_h is written again
+    next.store(s_in);
+    __syncthreads();
+    const int tn = it.t + it.step;
+    if (tn < it.end) next.load(in, w, h, (tn % tiles_x) * TW, (tn / tiles_x) * TH);
+    blur_passes<R, TW, TH>(s_in, s_h, out, w, h, wt, x0, y0);
+  }
+}
+
+// Sobel gradient magnitude sqrt(gx^2 + gy^2), gx with [[-1,0,1],[-2,0,2],
+// [-1,0,1]] (correlation), gy with its transpose, over a staged tile.
+template <int TW, int TH>
+__device__ __forceinline__ void sobel_tile(const float (*s_in)[TW + 2], float* __restrict__ out, int w, int h,
+                                           int x0, int y0) {
+  constexpr int G = kRowsPerThread;
   // each thread: 4 rows of one column from a 6 x 3 register window
   const int c = threadIdx.x % TW;
   const int r0 = (threadIdx.x / TW) * G;
@@ -544,6 +629,43 @@ __global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_sobel(const float*
     const double sx = (p[o][2] - p[o][0]) + 2.0 * (p[o + 1][2] - p[o + 1][0]) + (p[o + 2][2] - p[o + 2][0]);
     const double sy = (p[o + 2][0] - p[o][0]) + 2.0 * (p[o + 2][1] - p[o][1]) + (p[o + 2][2] - p[o][2]);
     if (gx < w && gy < h) out[static_cast<size_t>(gy) * w + gx] = static_cast<float>(sqrt(sx * sx + sy * sy));
+  }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH / kRowsPerThread) void k_sobel(const float* __restrict__ in,
+                                                                     float* __restrict__ out, int w, int h,
+                                                                     int tiles_x, int ntiles, int xcd_map) {
+  constexpr int NT = TW * TH / kRowsPerThread;
+  constexpr int IW = TW + 2, IH = TH + 2;
+  __shared__ float s_in[IH][IW];
+  int x0, y0;
+  if (!tile_of<TW, TH>(tiles_x, ntiles, xcd_map, &x0, &y0)) return;
+  stage_tile<1, TW, IH, IW, NT>(in, s_in, w, h, x0, y0);
+  __syncthreads();
+  sobel_tile<TW, TH>(s_in, out, w, h, x0, y0);
+}
+
+// Sobel on a resident grid of 64-wide tiles, the next tile's rows loaded
+// into registers during the current tile's arithmetic (as k_gauss_blur_rt).
+template <int TH>
+__global__ __launch_bounds__(64 * TH / kRowsPerThread) void k_sobel_rt(const float* __restrict__ in,
+                                                                        float* __restrict__ out, int w, int h,
+                                                                        int tiles_x, int ntiles) {
+  constexpr int TW = 64;
+  constexpr int NT = TW * TH / kRowsPerThread;
+  __shared__ float s_in[TH + 2][TW + 2];
+  ResidentTiles it(ntiles);
+  TileRows<1, TH, NT> next;
+  if (it.t < it.end) next.load(in, w, h, (it.t % tiles_x) * TW, (it.t / tiles_x) * TH);
+  for (; it.t < it.end; it.t += it.step) {  // uniform per workgroup
+    const int x0 = (it.t % tiles_x) * TW, y0 = (it.t / tiles_x) * TH;
+    next.store(s_in);
+    __syncthreads();
+    const int tn = it.t + it.step;
+    if (tn < it.end) next.load(in, w, h, (tn % tiles_x) * TW, (tn / tiles_x) * TH);
+    sobel_tile<TW, TH>(s_in, out, w, h, x0, y0);
+    __syncthreads();  // every read of s_in done before the next tile's rows overwrite it
   }
 }
 
@@ -2406,12 +2528,19 @@ struct TileShape {
 constexpr TileShape kTileShapes[] = {{64, 16}, {64, 8}, {64, 4}, {32, 8}};
 constexpr uint32_t kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
 
+// Variant bit 3: resident grid with the next tile's loads in flight, for the
+// 64-wide shapes with the per-XCD tile order (variants 9 and 11).
+constexpr uint32_t kTileResident = 8;
+
 const char* cfg_tile(const LaunchCfg& c) {
-  if (c.grid_cap != 0) return "grid_cap must be 0";
-  if ((c.variant >> 1) >= kNumTileShapes)
+  if (c.grid_cap != 0 && !(c.variant & kTileResident))
+    return "grid_cap must be 0 (it caps the workgroups of the resident variants only)";
+  const uint32_t shape = (c.variant & ~kTileResident) >> 1;
+  if (shape >= kNumTileShapes || ((c.variant & kTileResident) && c.variant != 9 && c.variant != 11))
     return "variant: bit 0 = tile order (0 row-major, 1 one contiguous run of tiles per XCD), "
-           "variant >> 1 = tile shape (0: 64x16, 1: 64x8, 2: 64x4, 3: 32x8)";
-  const TileShape t = kTileShapes[c.variant >> 1];
+           "bits 1-2 = tile shape (0: 64x16, 1: 64x8, 2: 64x4, 3: 32x8), bit 3 = resident grid loading each "
+           "workgroup's next tile early (9: 64x16, 11: 64x8)";
+  const TileShape t = kTileShapes[shape];
   if (c.block != static_cast<uint32_t>(t.tw * t.th / kRowsPerThread))
     return "block must be the tile's threads: 256 for 64x16, 128 for 64x8, 64 for 64x4 and 32x8";
   return nullptr;
@@ -2425,9 +2554,50 @@ void launch_blur_shape(hipStream_t s, const float* in, float* out, int w, int h,
                nt, xcd_map);
 }
 
+// Compute units of the current device (cached per device ordinal).
+int device_cus() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+// Workgroups of a resident tile grid: as many as fit on the GPU at once
+// (occupancy of the kernel, asked once per instantiation through *per_cu)
+// or cap if that is smaller (0: no cap), a multiple of 8 so that every XCD
+// gets the same count, at most one per tile.
+int resident_tile_grid(const void* kern, int threads, int ntiles, int* per_cu, uint32_t cap) {
+  if (*per_cu == 0) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, 0);
+    *per_cu = (e == hipSuccess && n > 0) ? n : 2;
+  }
+  int per_xcd = std::min((ntiles + 7) / 8, *per_cu * device_cus() / 8);
+  if (cap) per_xcd = std::min<int64_t>(per_xcd, cap / 8);
+  return 8 * std::max(1, per_xcd);
+}
+
+template <int R, int TH>
+void launch_blur_rt(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt, uint32_t cap) {
+  static int per_cu = 0;
+  const int tx = static_cast<int>(ceil_div(w, 64)), nt = tx * static_cast<int>(ceil_div(h, TH));
+  const int grid = resident_tile_grid(reinterpret_cast<const void*>(&k_gauss_blur_rt<R, TH>),
+                                      64 * TH / kRowsPerThread, nt, &per_cu, cap);
+  DAGRT_LAUNCH((k_gauss_blur_rt<R, TH>), dim3(grid), dim3(64 * TH / kRowsPerThread), 0, s, in, out, w, h, wt,
+               tx, nt);
+}
+
 template <int R>
-void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt, uint32_t variant) {
+void launch_blur_r(hipStream_t s, const float* in, float* out, int w, int h, const GaussW& wt, uint32_t variant,
+                   uint32_t cap) {
   const int xm = static_cast<int>(variant & 1);
+  if (variant == 9) return launch_blur_rt<R, 16>(s, in, out, w, h, wt, cap);
+  if (variant == 11) return launch_blur_rt<R, 8>(s, in, out, w, h, wt, cap);
   switch (variant >> 1) {
     case 1: launch_blur_shape<R, 64, 8>(s, in, out, w, h, wt, xm); break;
     case 2: launch_blur_shape<R, 64, 4>(s, in, out, w, h, wt, xm); break;
@@ -2452,22 +2622,22 @@ hipError_t l_blur(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   auto* out = static_cast<float*>(a[1]);
   const int w = static_cast<int>(q->w), h = static_cast<int>(q->h);
   switch (rad) {
-    case 0: launch_blur_r<0>(s, in, out, w, h, wt, vr); break;
-    case 1: launch_blur_r<1>(s, in, out, w, h, wt, vr); break;
-    case 2: launch_blur_r<2>(s, in, out, w, h, wt, vr); break;
-    case 3: launch_blur_r<3>(s, in, out, w, h, wt, vr); break;
-    case 4: launch_blur_r<4>(s, in, out, w, h, wt, vr); break;
-    case 5: launch_blur_r<5>(s, in, out, w, h, wt, vr); break;
-    case 6: launch_blur_r<6>(s, in, out, w, h, wt, vr); break;
-    case 7: launch_blur_r<7>(s, in, out, w, h, wt, vr); break;
-    case 8: launch_blur_r<8>(s, in, out, w, h, wt, vr); break;
-    case 9: launch_blur_r<9>(s, in, out, w, h, wt, vr); break;
-    case 10: launch_blur_r<10>(s, in, out, w, h, wt, vr); break;
-    case 11: launch_blur_r<11>(s, in, out, w, h, wt, vr); break;
-    case 12: launch_blur_r<12>(s, in, out, w, h, wt, vr); break;
-    case 13: launch_blur_r<13>(s, in, out, w, h, wt, vr); break;
-    case 14: launch_blur_r<14>(s, in, out, w, h, wt, vr); break;
-    default: launch_blur_r<15>(s, in, out, w, h, wt, vr); break;
+    case 0: launch_blur_r<0>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 1: launch_blur_r<1>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 2: launch_blur_r<2>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 3: launch_blur_r<3>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 4: launch_blur_r<4>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 5: launch_blur_r<5>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 6: launch_blur_r<6>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 7: launch_blur_r<7>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 8: launch_blur_r<8>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 9: launch_blur_r<9>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 10: launch_blur_r<10>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 11: launch_blur_r<11>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 12: launch_blur_r<12>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 13: launch_blur_r<13>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    case 14: launch_blur_r<14>(s, in, out, w, h, wt, vr, c.grid_cap); break;
+    default: launch_blur_r<15>(s, in, out, w, h, wt, vr, c.grid_cap); break;
   }
   return hipGetLastError();
 }
@@ -2480,11 +2650,28 @@ void launch_sobel_shape(hipStream_t s, const float* in, float* out, int w, int h
                xcd_map);
 }
 
+template <int TH>
+void launch_sobel_rt(hipStream_t s, const float* in, float* out, int w, int h, uint32_t cap) {
+  static int per_cu = 0;
+  const int tx = static_cast<int>(ceil_div(w, 64)), nt = tx * static_cast<int>(ceil_div(h, TH));
+  const int grid = resident_tile_grid(reinterpret_cast<const void*>(&k_sobel_rt<TH>), 64 * TH / kRowsPerThread,
+                                      nt, &per_cu, cap);
+  DAGRT_LAUNCH((k_sobel_rt<TH>), dim3(grid), dim3(64 * TH / kRowsPerThread), 0, s, in, out, w, h, tx, nt);
+}
+
 hipError_t l_sobel(hipStream_t s, void* const* a, const void* p, const LaunchCfg& c, void*, size_t) {
   const auto* q = static_cast<const dag_p_img*>(p);
   const auto* in = static_cast<const float*>(a[0]);
   auto* out = static_cast<float*>(a[1]);
   const int w = static_cast<int>(q->w), h = static_cast<int>(q->h), xm = static_cast<int>(c.variant & 1);
+  if (c.variant == 9) {
+    launch_sobel_rt<16>(s, in, out, w, h, c.grid_cap);
+    return hipGetLastError();
+  }
+  if (c.variant == 11) {
+    launch_sobel_rt<8>(s, in, out, w, h, c.grid_cap);
+    return hipGetLastError();
+  }
   switch (c.variant >> 1) {
     case 1: launch_sobel_shape<64, 8>(s, in, out, w, h, xm); break;
     case 2: launch_sobel_shape<64, 4>(s, in, out, w, h, xm); break;
@@ -2627,19 +2814,6 @@ void launch_spmv_window(hipStream_t s, void* const* a, const dag_p_csr* q, const
                static_cast<const int*>(a[1]), static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
                static_cast<float*>(a[4]), static_cast<int>(q->nrows), static_cast<int>(q->ncols),
                static_cast<int>(q->nnz), own, sc);
-}
-
-// Compute units of the current device (cached per device ordinal).
-int device_cus() {
-  static int cached[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cached[dev] = n;
-  }
-  return cached[dev];
 }
 
 // Row-window products and fix-up over the row boundaries in own.

@@ -53,10 +53,13 @@ def candidates(kernel):
     if kernel == "spmv_rows":
         return [(256, c, v) for v in (4, 8, 16, 32) for c in (0, 2048, 8192)]
     if kernel in ("gauss_blur", "sobel"):
-        # variant bit 0: tile order (row-major, or one run per XCD); variant >> 1: tile shape 64x16, 64x8,
-        # 64x4 or 32x8, whose workgroup is the tile's threads (four rows of one column each)
-        return [(tw * th // 4, 0, order | (shape << 1))
-                for shape, (tw, th) in enumerate(TILE_SHAPES) for order in (0, 1)]
+        # variant bit 0: tile order (row-major, or one run per XCD); bits 1-2: tile shape 64x16, 64x8,
+        # 64x4 or 32x8, whose workgroup is the tile's threads (four rows of one column each); 9 and 11:
+        # 64x16 and 64x8 on a resident grid (grid cap: workgroups, 0 = as many as fit) that loads each
+        # workgroup's next tile while it computes the current one
+        return ([(tw * th // 4, 0, order | (shape << 1))
+                 for shape, (tw, th) in enumerate(TILE_SHAPES) for order in (0, 1)] +
+                [(256, c, 9) for c in (0, 1024, 512)] + [(128, c, 11) for c in (0, 2048, 1024)])
     if kernel == "nb_proba":
         # one workgroup per CU fits beside the 128 KB table: its size sets the waves per CU
         return [(b, c, 0) for b in (256, 512, 1024) for c in (0, 256, 512, 1024)]

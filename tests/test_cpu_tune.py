@@ -133,12 +133,17 @@ def test_unswept_configuration_is_refused(tmp_path):
 
 def test_stencil_tile_shapes_need_their_workgroup_size():
     ctx = D.Context(dry_run=True)
-    for block, variant, ok in [(256, 0, True), (128, 2, True), (64, 4, True), (64, 6, True), (64, 7, True),
-                               (256, 2, False), (128, 4, False), (256, 8, False)]:
+    # 9 and 11: the resident grids of 64x16 and 64x8 tiles, the only ones that take a grid cap
+    for block, cap, variant, ok in [(256, 0, 0, True), (128, 0, 2, True), (64, 0, 4, True), (64, 0, 6, True),
+                                    (64, 0, 7, True), (256, 0, 2, False), (128, 0, 4, False), (256, 0, 8, False),
+                                    (256, 0, 9, True), (256, 1024, 9, True), (128, 0, 11, True),
+                                    (128, 8, 11, True), (128, 0, 9, False), (256, 0, 11, False),
+                                    (64, 0, 13, False), (64, 0, 15, False), (256, 1024, 1, False),
+                                    (256, 0, 16, False)]:
         for k in ("gauss_blur", "sobel"):
             try:
-                ctx.set_launch(k, block, 0, variant)
-                assert ok, (k, block, variant)
+                ctx.set_launch(k, block, cap, variant)
+                assert ok, (k, block, cap, variant)
             except D.DagError:
-                assert not ok, (k, block, variant)
+                assert not ok, (k, block, cap, variant)
     ctx.close()

@@ -127,19 +127,22 @@ def test_img(w, h):
     G.check_program(W.img_program(side=w, height=h, seed=2))
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("launch", [(256, 0, 0), (256, 0, 1), (256, 0, 9), (256, 8, 9), (256, 24, 9),
+                                    (128, 0, 11), (128, 16, 11)])
 @pytest.mark.parametrize("w,h", [(1, 1), (70, 19), (333, 130), (2048, 2048), (2000, 1000)])
-def test_img_tile_orders(w, h, variant):
-    """Blur and Sobel with row-major tiles (0) and with one contiguous run of
-    tiles per XCD (1): tile counts below 8, not a multiple of 8, full image."""
-    banner("img tile order %d %dx%d" % (variant, w, h))
+def test_img_tile_orders(w, h, launch):
+    """Blur and Sobel with row-major tiles (variant 0), with one contiguous
+    run of tiles per XCD (1), and on a resident grid that walks each XCD's run
+    (9: 64x16 tiles, 11: 64x8; a cap of 8 workgroups leaves one per XCD to
+    walk the whole run): tile counts below 8, not a multiple of 8, full image."""
+    banner("img tiles %s %dx%d" % (launch, w, h))
     from paper_2012_09646_amd import runner
     prog = W.img_program(side=w, height=h, seed=21)
     ref = G.oracle_run(prog)
     ctx = D.Context()
     try:
-        ctx.set_launch("gauss_blur", 256, 0, variant)
-        ctx.set_launch("sobel", 256, 0, variant)
+        ctx.set_launch("gauss_blur", *launch)
+        ctx.set_launch("sobel", *launch)
         b = runner.Bound(ctx, prog)
         b.run()
         for name in prog.outputs:
