@@ -167,7 +167,8 @@ typedef struct {
                              the child's stream is held by a one-wave kernel
                              that polls the counter (about 2 us per edge
                              against about 12 us for a HIP event wait; SDMA
-                             copies and region replays still end with an
+                             copies, hipGraph launches and recorded replays
+                             that contain SDMA copies still end with an
                              event; a
                              poll that has not seen its value after 10 s
                              gives up, and the next host wait or sync of the

@@ -880,11 +880,13 @@ dag_status replay_region_signals(dag_ctx c, Region* r, hipStream_t s, int32_t ps
     return e;
   };
   const uint32_t sslot = static_cast<uint32_t>(ps);
-  uint64_t fork_v = 0;
-  HIP_TRY(c, raise_now(s, sslot, &fork_v));
-  for (uint32_t i = 1; i < r->nstreams; ++i) {
-    HIP_TRY(c, add_wait(c->aux[i], sslot, fork_v));
-    HIP_TRY(c, flush(c->aux[i]));
+  if (r->nstreams > 1) {  // a one-stream region runs in the launch stream's order: no fork
+    uint64_t fork_v = 0;
+    HIP_TRY(c, raise_now(s, sslot, &fork_v));
+    for (uint32_t i = 1; i < r->nstreams; ++i) {
+      HIP_TRY(c, add_wait(c->aux[i], sslot, fork_v));
+      HIP_TRY(c, flush(c->aux[i]));
+    }
   }
   std::vector<std::pair<uint32_t, uint64_t>>& tv = c->tmp_sig;
   tv.assign(r->tasks.size(), {0u, 0u});
@@ -912,25 +914,30 @@ dag_status replay_region_signals(dag_ctx c, Region* r, hipStream_t s, int32_t ps
   return DAG_OK;
 }
 
+// A recorded replay uses signals when every recorded task runs on the CUs:
+// with SDMA copies in the region (host<->device copies of the Black-Scholes
+// fan-out) a signal kernel behind each copy on its stream slowed the replay
+// to the serial time, so such regions keep their events.
+bool replay_on_cus(dag_ctx c, const Region* r, int32_t pool_stream) {
+  if (!c->signals || static_cast<uint32_t>(pool_stream) >= kAuxSlotBase ||
+      r->nstreams > kSignalSlots - kAuxSlotBase)
+    return false;
+  for (const RegionTask& t : r->tasks)
+    if (t.kind == TK_COPY && !copy_runs_as_kernel(c, t.ckind)) return false;
+  return true;
+}
+
 dag_status replay_region(dag_ctx c, Region* r, hipStream_t s, int32_t pool_stream) {
   dag_status st = ensure_aux(c, r->nstreams);
   if (st) return st;
-  // signals when every recorded task runs on the CUs: with SDMA copies in the
-  // region (host<->device copies of the Black-Scholes fan-out) a signal
-  // kernel behind each copy on its stream slowed the replay to the serial
-  // time, so such regions keep their events
-  bool on_cus = c->signals && static_cast<uint32_t>(pool_stream) < kAuxSlotBase &&
-                r->nstreams <= kSignalSlots - kAuxSlotBase;
-  for (const RegionTask& t : r->tasks)
-    if (t.kind == TK_COPY && !copy_runs_as_kernel(c, t.ckind)) on_cus = false;
-  if (on_cus) return replay_region_signals(c, r, s, pool_stream);
+  if (replay_on_cus(c, r, pool_stream)) return replay_region_signals(c, r, s, pool_stream);
   if (r->evs.empty()) {
     r->evs.assign(r->tasks.size() + 2 * r->nstreams, nullptr);
     for (auto& e : r->evs) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   hipEvent_t* fork = &r->evs[r->tasks.size()];
   hipEvent_t* join = fork + r->nstreams;
-  HIP_TRY(c, hipEventRecord(fork[0], s));
+  if (r->nstreams > 1) HIP_TRY(c, hipEventRecord(fork[0], s));
   for (uint32_t i = 1; i < r->nstreams; ++i) HIP_TRY(c, hipStreamWaitEvent(c->aux[i], fork[0], 0));
   for (uint32_t k = 0; k < r->tasks.size(); ++k) {
     const RegionTask& t = r->tasks[k];
@@ -1454,10 +1461,14 @@ dag_status dag_region_launch(dag_ctx c, uint64_t key, dag_task* out) {
       if (st) return st;
     }
   }
-  // A region replay ends with an event: a signal kernel queued right behind
-  // hipGraphLaunch slowed the replays of the next launches on that stream
-  // (HITS iteration graphs: 4.3 ms against 2.2 ms per ten launches).
-  st = end_task(c, id, s, false);
+  // A hipGraph launch ends with an event: a signal kernel queued right
+  // behind hipGraphLaunch slowed the replays of the next launches on that
+  // stream (HITS iteration graphs: 4.3 ms against 2.2 ms per ten launches).
+  // A recorded replay on the CUs, joined on this stream by polls, ends with
+  // a signal like a kernel (its outputs are the region's written buffers).
+  const bool sig_end = !r->exec && replay_on_cus(c, r, s);
+  if (sig_end) c->tmp_acc = r->accs;
+  st = end_task(c, id, s, sig_end);
   c->launch_us += us_since(t1);
   return st;
 }

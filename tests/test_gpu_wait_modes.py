@@ -164,3 +164,41 @@ def test_wide_join_waits_for_ten_streams():
         assert ctx.stats().signal_waits >= 9
         for out in prog.outputs:
             G.assert_close(prog, out, b.read(out), ref[out])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_a_consumer_on_another_stream_waits_for_a_replay(mode):
+    """A recorded multi-stream replay (graph mode 1) of the vector diamond,
+    then y <- y^2 (on the replay's stream: the replay is its tail) and x <-
+    x^2, which joins another stream and must wait for the replay there. A
+    replay whose tasks all ran on the CUs ends with a completion signal, so
+    in signal mode that wait is a poll; the results equal the oracle's after
+    every one of three rounds."""
+    banner("consumer of a replay mode %d" % mode)
+    n = (1 << 18) + 5
+    base = W.vec_program(n=n, seed=31)
+    # inputs in [0.9, 1): six squarings keep them normal
+    base.bufs["x"] = W.Buf(4 * n, init=W.uniform_f32(31, n, 0.9, 1.0, stream=0))
+    base.bufs["y"] = W.Buf(4 * n, init=W.uniform_f32(31, n, 0.9, 1.0, stream=1))
+    region = [o for o in base.ops if o["kind"] == "kernel"]
+    after = [W.K("vec_square", [("y", "m")], n=n), W.K("vec_square", [("x", "m")], n=n)]
+    rounds = 3
+    ref = G.oracle_run(W.Program("vec_rounds", base.bufs, (region + after) * rounds, base.outputs))
+    prog = W.Program("vec_region", base.bufs, region + after, base.outputs)
+    with D.Context(max_streams=4, graph_mode=1, wait_mode=mode) as ctx:
+        b = runner.Bound(ctx, prog)
+        b.record(1, 0, len(region))  # the region runs once while it is recorded
+        tail = b._sub(list(range(len(region), len(region) + 2)))
+        for k in range(rounds):
+            ids = D.dag_submit_batch(ctx.h, tail)
+            if k + 1 < rounds:
+                D.dag_region_launch(ctx.h, 1)
+        info = {t: ctx.info(t) for t in ids}
+        assert info[ids[1]].stream != info[ids[0]].stream and info[ids[1]].nwaits >= 1
+        for out in prog.outputs:
+            G.assert_close(prog, out, b.read(out), ref[out])
+        st = ctx.stats()
+        if mode == D.DAG_WAIT_SIGNALS:
+            assert st.signal_waits >= 1
+        else:
+            assert st.signals == 0 and st.signal_waits == 0
