@@ -77,5 +77,9 @@ def test_ml_in_the_bench_configuration():
         assert np.all(np.abs(g - o) <= 1e-5 * np.abs(o.astype(np.float64))), name
     got = outs["label"].view(np.int32)[rows]
     a64 = avg.astype(np.float64)
-    for r in np.nonzero(got != lab)[0]:
+    flips = np.nonzero(got != lab)[0]
+    print("[gpu] sampled labels differing from the oracle's at near-ties: %d of %d" % (flips.size, rows.size),
+          flush=True)
+    assert flips.size <= rows.size // 100
+    for r in flips:
         assert a64[r, got[r]] >= a64[r].max() * (1 - 2e-5)

@@ -61,7 +61,9 @@ def test_ml_pipeline(n, F, C, V):
     assert edges == odag.build_dag(prog.ops).edges
     for name in ("Pnb", "Prr", "Pavg"):
         G.assert_close(prog, name, outs[name], ref[name])
-    check_labels(outs["label"], ref["label"], ref["Pavg"], C)
+    flips = check_labels(outs["label"], ref["label"], ref["Pavg"], C)
+    print("[gpu] labels differing from the oracle's at near-ties: %d of %d rows" % (flips, n), flush=True)
+    assert flips <= max(1, n // 100)  # near-ties are rare on these inputs
 
 
 @pytest.mark.parametrize("C", [10, 16])
