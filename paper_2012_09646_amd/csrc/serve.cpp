@@ -697,7 +697,12 @@ dag_status dag_serve_start(dag_server s, uint32_t mode) {
   dag_ctx c = s->ctx;
   CHECK_CTX(c);
   if (mode > DAG_SERVE_SERIAL) return fail(c, DAG_E_INVAL, "bad mode");
-  if (s->started && !all_done(s, s->closed))
+  bool closed;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);  // dag_serve_close may run on another thread
+    closed = s->closed;
+  }
+  if (s->started && !all_done(s, closed))
     return fail(c, DAG_E_BUSY, "the previous session has requests outstanding");
   s->started = true;
   s->serial = mode == DAG_SERVE_SERIAL;
@@ -711,10 +716,10 @@ dag_status dag_serve_start(dag_server s, uint32_t mode) {
   s->unreported.clear();
   s->lat_ms.clear();
   s->used = s->peak = s->vclock = s->taken = s->ndone = 0;
-  s->first_arrival = UINT64_MAX;
   s->last_done = 0;
   s->inflight = s->max_inflight = s->max_queued = 0;
   std::lock_guard<std::mutex> lk(s->mu);
+  s->first_arrival = UINT64_MAX;
   s->incoming.clear();
   s->next_id = 0;
   s->horizon = 0;
@@ -797,8 +802,13 @@ dag_status dag_serve_stats(dag_server s, dag_serve_summary* out) {
   out->p99_ms = pct(99);
   out->mean_ms = n ? sum / n : 0.0;
   out->max_ms = n ? lat.back() : 0.0;
+  uint64_t first_arrival;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);  // dag_serve_submit updates it from producer threads
+    first_arrival = s->first_arrival;
+  }
   const double span_s =
-      n ? (static_cast<double>(s->last_done) - static_cast<double>(s->first_arrival)) * 1e-9 : 0.0;
+      n ? (static_cast<double>(s->last_done) - static_cast<double>(first_arrival)) * 1e-9 : 0.0;
   out->req_per_s = span_s > 0 ? n / span_s : 0.0;
   out->wall_ms = static_cast<double>(s->last_done) * 1e-6;
   out->peak_device_bytes = s->peak;
