@@ -1278,21 +1278,41 @@ __global__ __launch_bounds__(256) void k_spmv_window_pf(const int* __restrict__ 
   }
 }
 
-// Rows that run across tiles: one wave per tile whose head part ends a row
-// adds, in tile order, the row's tail part in the tile that owns it and the
-// head parts of the tiles after that one up to this tile.
+// Rows that run across tiles: for each tile b whose head part ends a row,
+// y[row] = (the row's tail part in the tile that owns it) + (the head parts
+// of tiles owner + 1 .. b).  One thread per tile: a row spanning at most
+// kFixupSerial tiles (nearly all: a tile holds 1024 or 2048 nonzeros) is
+// summed by its thread in tile order; longer ones go to the whole wave, one
+// at a time, with a fixed lane-strided order and butterfly.  Few, short
+// workgroups, so that the kernel is not held back when another kernel fills
+// the GPU beside it.
+constexpr int kFixupSerial = 8;
+
 __global__ __launch_bounds__(256) void k_spmv_window_fixup(const int* __restrict__ row_ptr, float* __restrict__ y,
                                                            SpmvWindowScratch sc, int ntiles, int nnz, int window) {
-  const int b = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (b >= ntiles) return;
-  const int r = sc.head_row[b];
-  if (r < 0) return;
-  const int owner = min(clamp_nnz(row_ptr[r], nnz) / window, ntiles - 1);
-  double acc = 0.0;
-  for (int k = owner + 1 + lane; k <= b; k += kWave) acc += sc.head_val[k];
-  acc = wave_sum(acc);
-  if (lane == 0) y[r] = static_cast<float>(sc.tail_val[owner] + acc);
+  const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  const int lane = static_cast<int>(threadIdx.x & (kWave - 1));
+  int r = -1, owner = 0;
+  if (b < ntiles) {
+    r = sc.head_row[b];
+    if (r >= 0) owner = min(clamp_nnz(row_ptr[r], nnz) / window, ntiles - 1);
+  }
+  const bool alone = r >= 0 && b - owner <= kFixupSerial;
+  if (alone) {
+    double acc = 0.0;
+    for (int k = owner + 1; k <= b; ++k) acc += sc.head_val[k];
+    y[r] = static_cast<float>(sc.tail_val[owner] + acc);
+  }
+  uint64_t rest = __ballot(r >= 0 && !alone);  // every lane of the wave takes part from here on
+  while (rest) {
+    const int l = __ffsll(static_cast<unsigned long long>(rest)) - 1;
+    rest &= rest - 1;
+    const int bl = __shfl(b, l, kWave), rl = __shfl(r, l, kWave), ol = __shfl(owner, l, kWave);
+    double acc = 0.0;
+    for (int k = ol + 1 + lane; k <= bl; k += kWave) acc += sc.head_val[k];
+    acc = wave_sum(acc);
+    if (lane == 0) y[rl] = static_cast<float>(sc.tail_val[ol] + acc);
+  }
 }
 
 // CSR SpMV for matrices with short rows: L lanes per row stride over the row
@@ -2392,7 +2412,8 @@ const char* cfg_reduce(const LaunchCfg& c) {
 const char* cfg_tile(const LaunchCfg& c);
 const char* cfg_spmv(const LaunchCfg& c) {
   if (c.block != 256) return "SpMV runs 256-thread workgroups";
-  if (c.grid_cap != 0) return "grid_cap must be 0";
+  if (c.grid_cap != 0 && (c.variant & 0x500u) != 0x500u)
+    return "grid_cap must be 0 (it caps the workgroups of the resident row-window variants 0x504 and 0x508)";
   const uint32_t ipt = c.variant & 0xffu;
   if (c.variant & 0x100u) {
     const uint32_t mode = c.variant & 0x600u;
@@ -2818,7 +2839,7 @@ void launch_spmv_window(hipStream_t s, void* const* a, const dag_p_csr* q, const
 
 // Row-window products and fix-up over the row boundaries in own.
 hipError_t spmv_window_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, uint32_t variant, int tiles,
-                             const int* own, void* scr) {
+                             const int* own, void* scr, uint32_t cap) {
   const SpmvScratch c = spmv_carries(scr, tiles);
   SpmvWindowScratch sc;
   sc.head_val = c.head_val;
@@ -2837,7 +2858,10 @@ hipError_t spmv_window_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, 
       const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kf[which], 256, 0);
       per_cu[which] = (oe == hipSuccess && n > 0) ? n : 4;
     }
-    const int grid = std::max(1, std::min(tiles, per_cu[which] * device_cus()));
+    // (grid_cap, if set, leaves the rest of the CUs' slots to kernels on other streams)
+    int grid = std::min(tiles, per_cu[which] * device_cus());
+    if (cap) grid = std::min<int64_t>(grid, cap);
+    grid = std::max(1, grid);
     if ((variant & 0xffu) == 8)
       DAGRT_LAUNCH(k_spmv_window_pf<8>, dim3(grid), dim3(256), 0, s, static_cast<const int*>(a[0]),
                    static_cast<const int*>(a[1]), static_cast<const float*>(a[2]), static_cast<const float*>(a[3]),
@@ -2862,9 +2886,8 @@ hipError_t spmv_window_fixup(hipStream_t s, void* const* a, const dag_p_csr* q, 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int waves_per_wg = 256 / kWave;
-  DAGRT_LAUNCH(k_spmv_window_fixup, dim3(ceil_div(tiles, waves_per_wg)), dim3(256), 0, s,
-               static_cast<const int*>(a[0]), static_cast<float*>(a[4]), sc, tiles, static_cast<int>(q->nnz),
+  DAGRT_LAUNCH(k_spmv_window_fixup, dim3(ceil_div(tiles, 256)), dim3(256), 0, s, static_cast<const int*>(a[0]),
+               static_cast<float*>(a[4]), sc, tiles, static_cast<int>(q->nnz),
                static_cast<int>(256 * (variant & 0xffu)));
   return hipGetLastError();
 }
@@ -2893,7 +2916,7 @@ hipError_t l_spmv(hipStream_t s, void* const* a, const void* p, const LaunchCfg&
   const SpmvScratch sc = spmv_carries(scr, tiles);
   hipError_t e = spmv_partition_into(s, static_cast<const int*>(a[0]), q, c.variant, tiles, sc.coord);
   if (e != hipSuccess) return e;
-  if (spmv_is_window(c.variant)) return spmv_window_fixup(s, a, q, c.variant, tiles, sc.coord, scr);
+  if (spmv_is_window(c.variant)) return spmv_window_fixup(s, a, q, c.variant, tiles, sc.coord, scr, c.grid_cap);
   return spmv_merge_fixup(s, a, q, c.variant, tiles, sc);
 }
 
@@ -3367,7 +3390,8 @@ hipError_t spmv_planned(hipStream_t s, void* const* ptrs, const void* params, co
   const auto* q = static_cast<const dag_p_csr*>(params);
   if (q->nrows == 0) return hipSuccess;
   const int tiles = static_cast<int>(spmv_tiles(q, cfg.variant));
-  if (spmv_is_window(cfg.variant)) return spmv_window_fixup(s, ptrs, q, cfg.variant, tiles, coord, scratch);
+  if (spmv_is_window(cfg.variant))
+    return spmv_window_fixup(s, ptrs, q, cfg.variant, tiles, coord, scratch, cfg.grid_cap);
   SpmvScratch sc = spmv_carries(scratch, tiles);
   sc.coord = const_cast<int*>(coord);
   return spmv_merge_fixup(s, ptrs, q, cfg.variant, tiles, sc);

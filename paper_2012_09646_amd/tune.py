@@ -35,6 +35,11 @@ ARCH = "gfx950"
 BLOCKS = (64, 128, 256, 512, 1024)
 CAPS = (0, 1024, 4096)
 NEAR_TIE = 0.03  # kernel configurations this close to the fastest alone are retried inside the DAG
+# Grid caps of the resident SpMV (workgroups; uncapped it fills every wave slot of the GPU, eight workgroups
+# per CU), and the kernels whose fastest capped form is always retried inside the DAG: a kernel that holds
+# every CU slot for its whole run keeps a kernel on another stream from starting.
+RESIDENT_CAPS = (1792, 1536, 1024)
+LEAVES_ROOM = {"spmv": lambda cfg: cfg[2] & 0x500 == 0x500 and cfg[1] != 0}
 TILE_SHAPES = ((64, 16), (64, 8), (64, 4), (32, 8))  # stencil tiles, in the kernels' variant order
 
 
@@ -48,8 +53,9 @@ def candidates(kernel):
         return [(b, c, v) for b in (256, 512, 1024) for c in (64, 128, 256, 512, 1024, 2048) for v in (0, 1)]
     if kernel == "spmv":
         # merge-path items per thread, or 0x100 | nonzeros per thread of the row-window form (0x400: resident
-        # grid loading each workgroup's next tile early)
-        return [(256, 0, v) for v in (4, 8, 12, 16, 0x104, 0x108, 0x110, 0x504, 0x508)]
+        # grid loading each workgroup's next tile early; a grid cap leaves CU slots to other streams)
+        return ([(256, 0, v) for v in (4, 8, 12, 16, 0x104, 0x108, 0x110, 0x504, 0x508)] +
+                [(256, c, 0x504) for c in RESIDENT_CAPS])
     if kernel == "spmv_rows":
         return [(256, c, v) for v in (4, 8, 16, 32) for c in (0, 2048, 8192)]
     if kernel in ("gauss_blur", "sobel"):
@@ -126,6 +132,13 @@ def tune_kernels(ctx, prog, reps=20, log=None):
             ones = [i for i in valid if cands[i][2] == 1]
             if ones:
                 f = min(ones, key=lambda i: total[i])
+                if f not in near:
+                    near.append(f)
+        # likewise the fastest form that leaves CU slots free for kernels on other streams
+        if k in LEAVES_ROOM and not LEAVES_ROOM[k](cands[best]):
+            room = [i for i in valid if LEAVES_ROOM[k](cands[i])]
+            if room:
+                f = min(room, key=lambda i: total[i])
                 if f not in near:
                     near.append(f)
         out[k] = {"block": cands[best][0], "grid_cap": cands[best][1], "variant": cands[best][2],

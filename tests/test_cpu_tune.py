@@ -147,3 +147,22 @@ def test_stencil_tile_shapes_need_their_workgroup_size():
             except D.DagError:
                 assert not ok, (k, block, cap, variant)
     ctx.close()
+
+
+def test_spmv_grid_cap_only_for_the_resident_grid():
+    ctx = D.Context(dry_run=True)
+    for cap, variant, ok in [(0, 0x504, True), (1024, 0x504, True), (1, 0x508, True), (1024, 0x104, False),
+                             (1024, 8, False), (1024, 0x304, False)]:
+        try:
+            ctx.set_launch("spmv", 256, cap, variant)
+            assert ok, (cap, variant)
+        except D.DagError:
+            assert not ok, (cap, variant)
+    ctx.close()
+
+
+def test_resident_spmv_caps_are_candidates_and_tried_in_the_dag():
+    cands = tune.candidates("spmv")
+    for c in tune.RESIDENT_CAPS:
+        assert (256, c, 0x504) in cands
+    assert tune.LEAVES_ROOM["spmv"]((256, 1024, 0x504)) and not tune.LEAVES_ROOM["spmv"]((256, 0, 0x504))

@@ -167,9 +167,12 @@ def _spmv_program(rp, ci, va, x):
     return W.Program("spmv", bufs, ops, ["y"])
 
 
-@pytest.mark.parametrize("variant", [4, 8, 12, 16, 0x104, 0x108, 0x110, 0x504, 0x508])
-def test_spmv_long_rows_and_empty_rows(variant):
-    banner("spmv variant=%d" % variant)
+@pytest.mark.parametrize("variant,cap", [(4, 0), (8, 0), (12, 0), (16, 0), (0x104, 0), (0x108, 0), (0x110, 0),
+                                         (0x504, 0), (0x508, 0), (0x504, 1024), (0x504, 8), (0x508, 1)])
+def test_spmv_long_rows_and_empty_rows(variant, cap):
+    """Rows spanning many tiles, a long last row, empty rows; the resident
+    grids also capped (down to one workgroup walking every tile)."""
+    banner("spmv variant=%d cap=%d" % (variant, cap))
     n = 50000
     rng = np.random.default_rng(5)
     lengths = np.zeros(n, dtype=np.int64)
@@ -186,7 +189,7 @@ def test_spmv_long_rows_and_empty_rows(variant):
     prog = _spmv_program(rp, ci, va, x)
     ref = T.spmv(rp, ci, va, x)
     ctx = D.Context()
-    ctx.set_launch("spmv", 256, 0, variant)
+    ctx.set_launch("spmv", 256, cap, variant)
     from paper_2012_09646_amd import runner
     b = runner.Bound(ctx, prog)
     b.run()
