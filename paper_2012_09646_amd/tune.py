@@ -39,7 +39,9 @@ NEAR_TIE = 0.03  # kernel configurations this close to the fastest alone are ret
 # per CU), and the kernels whose fastest capped form is always retried inside the DAG: a kernel that holds
 # every CU slot for its whole run keeps a kernel on another stream from starting.
 RESIDENT_CAPS = (1792, 1536, 1024)
-LEAVES_ROOM = {"spmv": lambda cfg: cfg[2] & 0x500 == 0x500 and cfg[1] != 0}
+LEAVES_ROOM = {"spmv": lambda cfg: cfg[2] & 0x500 == 0x500 and cfg[1] != 0,
+               "gauss_blur": lambda cfg: cfg[2] in (9, 11) and cfg[1] != 0,
+               "sobel": lambda cfg: cfg[2] in (9, 11) and cfg[1] != 0}
 TILE_SHAPES = ((64, 16), (64, 8), (64, 4), (32, 8))  # stencil tiles, in the kernels' variant order
 
 

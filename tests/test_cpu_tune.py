@@ -166,3 +166,9 @@ def test_resident_spmv_caps_are_candidates_and_tried_in_the_dag():
     for c in tune.RESIDENT_CAPS:
         assert (256, c, 0x504) in cands
     assert tune.LEAVES_ROOM["spmv"]((256, 1024, 0x504)) and not tune.LEAVES_ROOM["spmv"]((256, 0, 0x504))
+
+
+def test_capped_resident_tiles_are_candidates():
+    for k in ("gauss_blur", "sobel"):
+        room = [c for c in tune.candidates(k) if tune.LEAVES_ROOM[k](c)]
+        assert room and all(c[2] in (9, 11) and c[1] for c in room)
