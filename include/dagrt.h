@@ -368,8 +368,13 @@ typedef struct { uint32_t m, reserved; } dag_p_combine;        /* SIAMESE_COMBIN
 /* Launch configuration of a built-in kernel (used by the autotuner). */
 typedef struct {
   uint32_t block;    /* threads per workgroup (multiple of 64, <= 1024) */
-  uint32_t grid_cap; /* max workgroups for grid-stride kernels; 0 = none */
-  uint32_t variant;  /* kernel-specific (SpMV items per thread, ...) */
+  uint32_t grid_cap; /* max workgroups for grid-stride kernels and for the
+                        resident grids (row-window SpMV 0x504/0x508, blur
+                        and Sobel 9/11), which otherwise take as many as fit
+                        on the GPU at once; 0 = none */
+  uint32_t variant;  /* kernel-specific (SpMV items per thread, ...); the
+                        library's error message for a refused one lists the
+                        kernel's accepted values */
   uint32_t reserved;
 } dag_launch;
 dag_status dag_kernel_get_launch(dag_ctx ctx, uint32_t kernel_id, dag_launch* out);
