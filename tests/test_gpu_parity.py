@@ -151,6 +151,30 @@ def test_img_tile_orders(w, h, launch):
         ctx.close()
 
 
+@pytest.mark.parametrize("launch", [(256, 0, 1), (256, 0, 9), (128, 0, 11), (128, 16, 11), (64, 0, 4),
+                                    (64, 0, 6)])
+@pytest.mark.parametrize("ksize", [1, 5, 9, 31])
+def test_blur_kernel_sizes(ksize, launch):
+    """Blur radii outside the IMG workload's three (0, 2, 4 and the largest,
+    15) in the one-tile-per-workgroup shapes and on the resident grids, on an
+    image whose sides are not multiples of any tile."""
+    banner("blur ksize=%d %s" % (ksize, launch))
+    from paper_2012_09646_amd import runner
+    w, h = 197, 131
+    prog = W.Program("blur", {"img": W.Buf(4 * w * h, init=W.uniform_f32(40 + ksize, w * h)),
+                              "out": W.Buf(4 * w * h)},
+                     [W.K("gauss_blur", [("img", "c"), ("out", "m")], w=w, h=h, ksize=ksize)], ["out"])
+    ref = G.oracle_run(prog)
+    ctx = D.Context()
+    try:
+        ctx.set_launch("gauss_blur", *launch)
+        b = runner.Bound(ctx, prog)
+        b.run()
+        G.assert_close(prog, "out", b.read("out"), ref["out"])
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("n,deg,iters", [(64, 4, 3), (3000, 20, 10), (1 << 20, 20, 10)])
 def test_hits(n, deg, iters):
     banner("hits n=%d deg=%d iters=%d" % (n, deg, iters))
