@@ -172,3 +172,26 @@ def test_capped_resident_tiles_are_candidates():
     for k in ("gauss_blur", "sobel"):
         room = [c for c in tune.candidates(k) if tune.LEAVES_ROOM[k](c)]
         assert room and all(c[2] in (9, 11) and c[1] for c in room)
+
+
+def test_the_fastest_capped_resident_form_is_retried_in_the_dag(monkeypatch):
+    """tune_kernels (timings faked; schedule-only context): the uncapped
+    resident SpMV wins alone, and the fastest capped form joins the
+    configurations retried inside the DAG although it is not a near-tie; a
+    reduction's one-launch form likewise."""
+    def fake_tune(h, kid, prm, args, cands, reps=20):
+        us = [200.0 + i for i in range(len(cands))]
+        if kid == D.KERNEL_IDS["spmv"]:
+            us[cands.index((256, 0, 0x504))] = 50.0
+            for c, t in zip(tune.RESIDENT_CAPS, (61.0, 60.0, 70.0)):
+                us[cands.index((256, c, 0x504))] = t
+        return 0, us
+
+    monkeypatch.setattr(tune.D, "dag_tune_kernel", fake_tune)
+    ctx = D.Context(dry_run=True)
+    out = tune.tune_kernels(ctx, W.hits_program(n=1000, iters=2, seed=3))
+    ctx.close()
+    e = out["spmv"]
+    assert (e["block"], e["grid_cap"], e["variant"]) == (256, 0, 0x504)
+    assert [256, tune.RESIDENT_CAPS[1], 0x504] in [n[:3] for n in e["near"]]
+    assert any(n[2] == 1 for n in out["sumsq"]["near"])
