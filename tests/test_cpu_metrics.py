@@ -99,3 +99,25 @@ def test_trace_overlap_reads_a_rocprofv3_timeline(tmp_path):
     o = M.overlap([(kind, a, b) for kind, a, b in runs[0]])
     # the kernel [100, 200) is covered by transfers on [100, 120) and [150, 200)
     assert abs(o["CT"] - 0.7) < 1e-12
+
+
+def test_algorithmic_bytes_equal_the_argument_buffers():
+    """The roofline's compulsory bytes of every kernel of every workload DAG
+    equal what its arguments hold in the program: each buffer once, except a
+    buffer the kernel both reads and writes (vec_square updates x in place),
+    which moves twice."""
+    from paper_2012_09646_amd import workloads as W
+    in_place = {"vec_square"}
+    progs = [W.vec_program(n=1000, seed=0), W.bs_program(n=1000, tasks=2, seed=1), W.img_program(side=64, seed=2),
+             W.hits_program(n=500, iters=2, seed=3), W.ml_program(n=300, seed=5), W.dl_program(side=64, seed=6)]
+    seen = set()
+    for prog in progs:
+        for o in prog.ops:
+            if o["kind"] != "kernel":
+                continue
+            k = o["kernel"]
+            held = sum(prog.bufs[b].nbytes * (2 if m == "m" and k in in_place else 1)
+                       for b, m in dict(o["args"]).items())
+            assert M.algorithmic_bytes(k, o["params"]) == held, (k, o["params"])
+            seen.add(k)
+    assert len(seen) == 18
